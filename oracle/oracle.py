@@ -1,0 +1,288 @@
+"""ctypes wrapper of the FP64 CPU oracle (``qmc_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the HIP library or its binding imports
+this module.  Functions follow the paper's Alg. 1 (VMC: lines 4-11; DMC: the
+whole generation loop including reweight/branch and the trial-energy update);
+the wavefunction pieces are textbook definitions named in the C source.
+"""
+import ctypes
+import os
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+
+from . import build_oracle
+
+_lib = None
+
+
+def lib():
+    """Load (building first if needed) the oracle shared library."""
+    global _lib
+    if _lib is None:
+        path = build_oracle.build(force=False)
+        L = ctypes.CDLL(path)
+        u32p = ctypes.POINTER(ctypes.c_uint32)
+        dp = ctypes.c_void_p
+        L.or_philox4x32_10.argtypes = [u32p, u32p, u32p]
+        L.or_uniform53.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
+        L.or_uniform53.restype = ctypes.c_double
+        L.or_gauss3.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, dp]
+        L.or_accept_uniform.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32]
+        L.or_accept_uniform.restype = ctypes.c_double
+        L.or_branch_uniform.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32]
+        L.or_branch_uniform.restype = ctypes.c_double
+        L.or_child_uid.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32]
+        L.or_child_uid.restype = ctypes.c_uint32
+        L.or_coef.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+        L.or_coef.restype = ctypes.c_double
+        L.or_orbital_vgl.argtypes = [ctypes.POINTER(OrSystem), dp, ctypes.c_int, dp, dp, dp]
+        L.or_lnj.argtypes = [ctypes.POINTER(OrSystem), dp]
+        L.or_lnj.restype = ctypes.c_double
+        L.or_lu_inverse.argtypes = [ctypes.c_int, dp, dp, dp, dp]
+        L.or_lu_inverse.restype = ctypes.c_int
+        L.or_local_energy.argtypes = [ctypes.POINTER(OrSystem), dp, dp, dp, dp, dp, dp, dp]
+        L.or_local_energy.restype = ctypes.c_double
+        L.or_vmc.argtypes = [ctypes.POINTER(OrSystem), ctypes.c_int, dp, dp, ctypes.c_int,
+                             ctypes.c_uint32, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                             dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp]
+        L.or_vmc.restype = ctypes.c_int
+        L.or_setup.argtypes = [ctypes.POINTER(OrSystem), ctypes.c_int, dp, ctypes.c_int, dp, dp, dp, dp]
+        L.or_setup.restype = ctypes.c_int
+        L.or_dmc.argtypes = [ctypes.POINTER(OrSystem), ctypes.c_int, dp, dp, ctypes.c_int,
+                             ctypes.c_uint32, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                             ctypes.c_int, ctypes.c_int, dp, dp, dp, dp, dp, dp, dp, dp]
+        L.or_dmc.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+class OrSystem(ctypes.Structure):
+    _fields_ = [
+        ("n_up", ctypes.c_int), ("n_dn", ctypes.c_int),
+        ("L", ctypes.c_double),
+        ("G", ctypes.c_int), ("n_orb", ctypes.c_int),
+        ("orb_kind", ctypes.c_int),
+        ("table", ctypes.c_void_p),
+        ("coef_seed", ctypes.c_uint64),
+        ("coef_fp32", ctypes.c_int),
+        ("use_j2", ctypes.c_int),
+        ("j2_a_par", ctypes.c_double), ("j2_a_anti", ctypes.c_double), ("j2_b", ctypes.c_double),
+        ("seed", ctypes.c_uint64),
+    ]
+
+
+ORB_TABLE, ORB_SEEDED, ORB_PLANEWAVE = 0, 1, 2
+
+
+@dataclass
+class System:
+    """One electronic system: box, orbitals, Jastrow and the move-RNG key."""
+    n_up: int
+    n_dn: int
+    L: float
+    G: int = 0
+    n_orb: int = 0
+    orb_kind: int = ORB_SEEDED
+    table: Optional[np.ndarray] = None
+    coef_seed: int = 0
+    coef_fp32: bool = False
+    use_j2: bool = False
+    j2_a_par: float = 0.25
+    j2_a_anti: float = 0.5
+    j2_b: float = 1.0
+    seed: int = 0
+    _c: OrSystem = field(default=None, repr=False)
+
+    @property
+    def n_e(self) -> int:
+        return self.n_up + self.n_dn
+
+    def c(self) -> OrSystem:
+        if self.table is not None:
+            self.table = np.ascontiguousarray(self.table, dtype=np.float64)
+        self._c = OrSystem(self.n_up, self.n_dn, float(self.L), int(self.G), int(self.n_orb),
+                           int(self.orb_kind),
+                           self.table.ctypes.data if self.table is not None else None,
+                           int(self.coef_seed), int(self.coef_fp32), int(self.use_j2),
+                           float(self.j2_a_par), float(self.j2_a_anti), float(self.j2_b),
+                           int(self.seed))
+        return self._c
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data
+
+
+def philox4x32_10(ctr, key):
+    """Philox4x32-10 of one 128-bit counter under a 64-bit key."""
+    c = (ctypes.c_uint32 * 4)(*[int(x) & 0xFFFFFFFF for x in ctr])
+    k = (ctypes.c_uint32 * 2)(*[int(x) & 0xFFFFFFFF for x in key])
+    o = (ctypes.c_uint32 * 4)()
+    lib().or_philox4x32_10(c, k, o)
+    return [o[i] for i in range(4)]
+
+
+def uniform53(lo, hi):
+    return lib().or_uniform53(lo, hi)
+
+
+def gauss3(seed, uid, step, e):
+    z = np.zeros(3)
+    lib().or_gauss3(seed, uid, step, e, z.ctypes.data)
+    return z
+
+
+def accept_uniform(seed, uid, step, e):
+    return lib().or_accept_uniform(seed, uid, step, e)
+
+
+def branch_uniform(seed, uid, step):
+    return lib().or_branch_uniform(seed, uid, step)
+
+
+def child_uid(seed, uid, step, copy):
+    return lib().or_child_uid(seed, uid, step, copy)
+
+
+def coef(seed, idx):
+    return lib().or_coef(seed, idx)
+
+
+def orbital_vgl(sys: System, r, norb=None):
+    """(v[n], g[n,3], lap[n]) of orbitals 0..norb-1 at r."""
+    norb = sys.n_orb if norb is None else norb
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    v = np.zeros(norb)
+    g = np.zeros((norb, 3))
+    l = np.zeros(norb)
+    cs = sys.c()
+    lib().or_orbital_vgl(ctypes.byref(cs), r.ctypes.data, norb, v.ctypes.data, g.ctypes.data, l.ctypes.data)
+    return v, g, l
+
+
+def lnj(sys: System, R):
+    R = np.ascontiguousarray(R, dtype=np.float64)
+    cs = sys.c()
+    return lib().or_lnj(ctypes.byref(cs), R.ctypes.data)
+
+
+def lu_inverse(A):
+    """(A^-1, log|det A|, sign det A) by LU with partial pivoting."""
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    n = A.shape[0]
+    inv = np.zeros_like(A)
+    ld = ctypes.c_double()
+    sg = ctypes.c_int()
+    st = lib().or_lu_inverse(n, A.ctypes.data, inv.ctypes.data, ctypes.addressof(ld), ctypes.addressof(sg))
+    if st != 0:
+        raise ZeroDivisionError("singular matrix")
+    return inv, ld.value, sg.value
+
+
+def local_energy(sys: System, R, Ainv_up, Ainv_dn, G_up, G_dn, L_up, L_dn):
+    """Kinetic local energy from inverses, gradient rows ([n][n][3]) and Laplacian rows."""
+    arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (R, Ainv_up, Ainv_dn, G_up, G_dn, L_up, L_dn)]
+    cs = sys.c()
+    return lib().or_local_energy(ctypes.byref(cs), *[a.ctypes.data for a in arrs])
+
+
+@dataclass
+class VmcResult:
+    rho: np.ndarray      # [S][Ne][W]
+    dlnj: np.ndarray
+    prob: np.ndarray
+    u: np.ndarray
+    acc: np.ndarray      # uint8
+    logdet: np.ndarray   # [S][W][2]
+    sign: np.ndarray     # [S][W][2]
+    eloc: np.ndarray     # [S][W]
+    R: np.ndarray        # [W][Ne][3]
+    n_acc: np.ndarray    # [W]
+    ainv: Optional[np.ndarray]  # [W][2][n][n] (A^-1 per spin, row j orbital / col i electron)
+
+
+def vmc(sys: System, R0, n_sweeps, sigma=0.5, uids=None, first_step=0, max_moves=0,
+        n_threads=0, want_ainv=False) -> VmcResult:
+    """Run VMC sweeps (Alg. 1 L4-L11) for every walker of R0 ([W][Ne][3])."""
+    R0 = np.ascontiguousarray(R0, dtype=np.float64)
+    W, ne = R0.shape[0], R0.shape[1]
+    assert ne == sys.n_e
+    uids = np.arange(W, dtype=np.uint32) if uids is None else np.ascontiguousarray(uids, dtype=np.uint32)
+    shp = (n_sweeps, ne, W)
+    res = VmcResult(np.full(shp, np.nan), np.full(shp, np.nan), np.full(shp, np.nan), np.full(shp, np.nan),
+                    np.zeros(shp, np.uint8), np.full((n_sweeps, W, 2), np.nan),
+                    np.zeros((n_sweeps, W, 2), np.int32), np.full((n_sweeps, W), np.nan),
+                    np.zeros_like(R0), np.zeros(W, np.int64),
+                    np.zeros((W, sys.n_up * sys.n_up + sys.n_dn * sys.n_dn)) if want_ainv else None)
+    cs = sys.c()
+    st = lib().or_vmc(ctypes.byref(cs), W, uids.ctypes.data, R0.ctypes.data, n_sweeps, first_step,
+                      sigma, max_moves, n_threads,
+                      res.rho.ctypes.data, res.dlnj.ctypes.data, res.prob.ctypes.data, res.u.ctypes.data,
+                      res.acc.ctypes.data, res.logdet.ctypes.data, res.sign.ctypes.data,
+                      res.eloc.ctypes.data, res.R.ctypes.data, res.n_acc.ctypes.data, _p(res.ainv))
+    if st != 0:
+        raise ZeroDivisionError("singular starting configuration")
+    if want_ainv:
+        n = sys.n_up
+        assert sys.n_up == sys.n_dn
+        res.ainv = res.ainv.reshape(W, 2, n, n)
+    return res
+
+
+def setup(sys: System, R0, n_threads=0):
+    """Initial (log|det| [W][2], sign [W][2], E_L [W], A^-1 [W][2][n][n])."""
+    R0 = np.ascontiguousarray(R0, dtype=np.float64)
+    W = R0.shape[0]
+    ld = np.zeros((W, 2))
+    sg = np.zeros((W, 2), np.int32)
+    el = np.zeros(W)
+    n = sys.n_up
+    ai = np.zeros((W, 2, n, n))
+    cs = sys.c()
+    st = lib().or_setup(ctypes.byref(cs), W, R0.ctypes.data, n_threads, ld.ctypes.data, sg.ctypes.data,
+                        el.ctypes.data, ai.ctypes.data)
+    if st != 0:
+        raise ZeroDivisionError("singular starting configuration")
+    return ld, sg, el, ai
+
+
+@dataclass
+class DmcResult:
+    pop: np.ndarray       # [gen]
+    wsum: np.ndarray      # [gen] sum of branching weights
+    e_est: np.ndarray     # [gen] weighted mean local energy
+    e_t: np.ndarray       # [gen] trial energy after the update
+    n_acc: int
+    n_prop: int
+    uids: np.ndarray      # final population
+    R: np.ndarray
+    eloc: np.ndarray
+
+
+def dmc(sys: System, R0, n_gen, tau, e_trial, n_target=None, max_pop=None, uids=None,
+        first_step=0, n_threads=0) -> DmcResult:
+    """Run DMC generations (Alg. 1 including L12-L13) on one system's population."""
+    R0 = np.ascontiguousarray(R0, dtype=np.float64)
+    W, ne = R0.shape[0], R0.shape[1]
+    n_target = W if n_target is None else n_target
+    max_pop = 4 * W + 16 if max_pop is None else max_pop
+    uids = np.arange(W, dtype=np.uint32) if uids is None else np.ascontiguousarray(uids, dtype=np.uint32)
+    pop = np.zeros(n_gen, np.int32)
+    wsum = np.zeros(n_gen)
+    eest = np.zeros(n_gen)
+    et = np.zeros(n_gen)
+    counts = np.zeros(2, np.int64)
+    uo = np.zeros(max_pop, np.uint32)
+    Ro = np.zeros((max_pop, ne, 3))
+    eo = np.zeros(max_pop)
+    cs = sys.c()
+    n = lib().or_dmc(ctypes.byref(cs), W, uids.ctypes.data, R0.ctypes.data, n_gen, first_step, tau,
+                     e_trial, n_target, max_pop, n_threads, pop.ctypes.data, wsum.ctypes.data,
+                     eest.ctypes.data, et.ctypes.data, counts.ctypes.data, uo.ctypes.data, Ro.ctypes.data,
+                     eo.ctypes.data)
+    if n < 0:
+        raise RuntimeError("oracle DMC failed with status %d" % n)
+    return DmcResult(pop, wsum, eest, et, int(counts[0]), int(counts[1]), uo[:n].copy(), Ro[:n].copy(),
+                     eo[:n].copy())

@@ -1,0 +1,401 @@
+"""Pins of the FP64 CPU oracle against what the mathematics fixes (CPU only).
+
+Each test checks the oracle against something other than itself: published
+known-answer vectors, closed forms, invariants, a textbook library routine, or
+the brute-force second reference in ``oracle/direct.py``.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle as orc
+from oracle.direct import Direct, spline_vgl
+from synth import planewave_table, start_positions
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden_numbers(name):
+    vals = []
+    for line in open(os.path.join(GOLD, name)):
+        line = line.strip()
+        if line and not line.startswith("#"):
+            vals.append(line.split())
+    return vals
+
+
+# ---------------------------------------------------------------- Philox / RNG
+
+def test_philox_known_answers():
+    """Philox4x32-10 reproduces the published Random123 known-answer vectors."""
+    rows = _golden_numbers("philox4x32_10_kat.txt")
+    assert len(rows) == 3
+    for r in rows:
+        v = [int(x, 16) for x in r]
+        assert orc.philox4x32_10(v[0:4], v[4:6]) == v[6:10]
+
+
+def test_uniform53_endpoints():
+    assert orc.uniform53(0, 0) == 0.0
+    assert orc.uniform53(0xFFFFFFFF, 0xFFFFFFFF) == 1.0 - 2.0 ** -53
+    # only the top 53 bits count: the low 11 bits of the low word are dropped
+    assert orc.uniform53(0x7FF, 0) == 0.0
+    assert orc.uniform53(0x800, 0) == 2.0 ** -53
+
+
+def test_gaussian_moments():
+    z = np.array([orc.gauss3(7, uid, 3, e) for uid in range(40) for e in range(100)])
+    assert abs(z.mean()) < 0.04
+    assert abs(z.var() - 1.0) < 0.05
+    # components are independent
+    assert abs(np.corrcoef(z.T)[0, 1]) < 0.05 and abs(np.corrcoef(z.T)[0, 2]) < 0.05
+
+
+def test_coefficients_in_range_and_fp32_rounding():
+    c = np.array([orc.coef(1002, i) for i in range(5000)])
+    assert c.min() >= -1.0 and c.max() < 1.0
+    assert abs(c.mean()) < 0.05
+    # the FP32 table holds the round-to-nearest value of the FP64 coefficient
+    sys64 = orc.System(1, 1, 10.0, G=4, n_orb=2, orb_kind=orc.ORB_SEEDED, coef_seed=1002)
+    sys32 = orc.System(1, 1, 10.0, G=4, n_orb=2, orb_kind=orc.ORB_SEEDED, coef_seed=1002, coef_fp32=True)
+    # at a grid node the value is (c_{i-1} + 4 c_i + c_{i+1}) / 6 per axis; compare both paths
+    r = np.array([2.5, 5.0, 7.5])
+    v64, _, _ = orc.orbital_vgl(sys64, r)
+    v32, _, _ = orc.orbital_vgl(sys32, r)
+    assert np.all(np.abs(v64 - v32) < 1e-7) and np.any(v64 != v32)
+
+
+# ------------------------------------------------------------------- splines
+
+def _cubic_reproduction_table(G, L, coeffs):
+    """Per-axis control values c_j = p(x_j) - (h^2/6) p''(x_j) reproduce a cubic p exactly
+    (Marsden identity); the 3-D table is the tensor product for p = px(x) py(y) pz(z)."""
+    h = L / G
+    x = np.arange(G) * h
+    tab = np.zeros((G, G, G, len(coeffs)))
+    for n, (cx, cy, cz) in enumerate(coeffs):
+        ax = []
+        for c in (cx, cy, cz):
+            p = np.polynomial.Polynomial(c)
+            ax.append(p(x) - h * h / 6.0 * p.deriv(2)(x))
+        tab[..., n] = ax[0][:, None, None] * ax[1][None, :, None] * ax[2][None, None, :]
+    return tab
+
+
+def _poly_vgl(coeffs, r):
+    v, g, l = [], [], []
+    for cx, cy, cz in coeffs:
+        P = [np.polynomial.Polynomial(c) for c in (cx, cy, cz)]
+        f = [P[a](r[a]) for a in range(3)]
+        d1 = [P[a].deriv(1)(r[a]) for a in range(3)]
+        d2 = [P[a].deriv(2)(r[a]) for a in range(3)]
+        v.append(f[0] * f[1] * f[2])
+        g.append([d1[0] * f[1] * f[2], f[0] * d1[1] * f[2], f[0] * f[1] * d1[2]])
+        l.append(d2[0] * f[1] * f[2] + f[0] * d2[1] * f[2] + f[0] * f[1] * d2[2])
+    return np.array(v), np.array(g), np.array(l)
+
+
+def test_spline_cubic_reproduction():
+    """P1: cubic polynomials are reproduced exactly (value, gradient, Laplacian)."""
+    G, L = 12, 6.0
+    h = L / G
+    rng = np.random.default_rng(1)
+    coeffs = [tuple(rng.uniform(-1, 1, 4) for _ in range(3)) for _ in range(5)]
+    tab = _cubic_reproduction_table(G, L, coeffs)
+    s = orc.System(1, 1, L, G=G, n_orb=5, orb_kind=orc.ORB_TABLE, table=tab)
+    for _ in range(30):
+        # keep the 4-point stencil (i-1 .. i+2) inside the grid: no wrap
+        r = rng.uniform(h, (G - 2) * h - 1e-9, 3)
+        v, g, l = orc.orbital_vgl(s, r)
+        ve, ge, le = _poly_vgl(coeffs, r)
+        scale = 1.0 + np.abs(ve).max()
+        assert np.allclose(v, ve, atol=1e-12 * scale, rtol=0)
+        assert np.allclose(g, ge, atol=1e-11 * scale, rtol=0)
+        assert np.allclose(l, le, atol=1e-10 * scale, rtol=0)
+
+
+def test_spline_partition_of_unity():
+    """P2: constant coefficients give a constant orbital, zero gradient and Laplacian."""
+    G, L = 8, 4.0
+    tab = np.full((G, G, G, 3), 0.0)
+    tab[..., 0] = 1.0
+    tab[..., 1] = -2.5
+    tab[..., 2] = 0.125
+    s = orc.System(1, 1, L, G=G, n_orb=3, orb_kind=orc.ORB_TABLE, table=tab)
+    rng = np.random.default_rng(2)
+    for r in list(rng.uniform(-3 * L, 3 * L, (20, 3))) + [np.array([L, 0.0, L - 1e-15]), np.zeros(3)]:
+        v, g, l = orc.orbital_vgl(s, r)
+        assert np.allclose(v, [1.0, -2.5, 0.125], atol=1e-14)
+        assert np.abs(g).max() < 1e-13 and np.abs(l).max() < 1e-12
+
+
+def test_spline_prefilter_interpolates_nodes():
+    """P3: the closed-form prefilter makes the spline interpolate the plane waves at nodes,
+    and the per-orbital -S''/S at nodes exceeds k^2 by the printed closed-form excess."""
+    L = 5.0
+    excess = [float(x) for x in _golden_numbers("planewave_c1_energy.txt")[1]]
+    for G, exc in zip((16, 32, 64), excess):
+        tab = planewave_table(G, L)
+        s = orc.System(1, 1, L, G=G, n_orb=4, orb_kind=orc.ORB_TABLE, table=tab)
+        h = L / G
+        k = 2 * np.pi / L
+        for (i, j, m) in [(0, 0, 0), (3, 5, 7), (G - 1, 1, G // 2)]:
+            r = np.array([i * h, j * h, m * h])
+            v, g, l = orc.orbital_vgl(s, r)
+            f = np.array([1.0, np.cos(k * r[0]), np.sin(k * r[0]), np.cos(k * r[1])])
+            assert np.allclose(v, f, atol=1e-13)
+            # -S''/S = k^2 (1 + excess) wherever S != 0
+            for n in (1, 2, 3):
+                if abs(v[n]) > 0.1:
+                    assert abs(-l[n] / v[n] / k ** 2 - 1.0 - exc) < 2e-6
+        # gradient and Laplacian are consistent with finite differences of the value
+        r = np.array([0.3, 1.7, 4.1])
+        d = 1e-5
+        v0, g0, l0 = orc.orbital_vgl(s, r)
+        lap_fd = np.zeros(4)
+        for c in range(3):
+            e = np.zeros(3); e[c] = d
+            vp, _, _ = orc.orbital_vgl(s, r + e)
+            vm, _, _ = orc.orbital_vgl(s, r - e)
+            assert np.allclose((vp - vm) / (2 * d), g0[:, c], atol=1e-7)
+            lap_fd += (vp - 2 * v0 + vm) / d ** 2
+        assert np.allclose(lap_fd, l0, atol=2e-4)
+
+
+def test_spline_matches_basis_matrix_form():
+    """The oracle's expanded polynomial weights agree with the basis-matrix form on random,
+    wrapping inputs (two independent codings of the same definition)."""
+    G, L = 7, 3.5
+    rng = np.random.default_rng(3)
+    tab = rng.uniform(-1, 1, (G, G, G, 6))
+    s = orc.System(1, 1, L, G=G, n_orb=6, orb_kind=orc.ORB_TABLE, table=tab)
+    pts = list(rng.uniform(-L, 2 * L, (40, 3))) + [np.array([L, L, L]), np.array([0.0, L - 1e-14, 1e-300])]
+    for r in pts:
+        v, g, l = orc.orbital_vgl(s, r)
+        v2, g2, l2 = spline_vgl(tab, L, r)
+        assert np.allclose(v, v2, atol=1e-13) and np.allclose(g, g2, atol=1e-12)
+        assert np.allclose(l, l2, atol=1e-10)
+
+
+def test_seeded_table_matches_materialised_table():
+    """orb_kind=seeded evaluates coefficient idx = ((ix G + iy) G + iz) n_orb + n on the fly."""
+    G, L, n = 5, 2.0, 3
+    tab = np.array([orc.coef(99, i) for i in range(G ** 3 * n)]).reshape(G, G, G, n)
+    s1 = orc.System(1, 1, L, G=G, n_orb=n, orb_kind=orc.ORB_SEEDED, coef_seed=99)
+    s2 = orc.System(1, 1, L, G=G, n_orb=n, orb_kind=orc.ORB_TABLE, table=tab)
+    for r in np.random.default_rng(4).uniform(0, L, (10, 3)):
+        a = orc.orbital_vgl(s1, r)
+        b = orc.orbital_vgl(s2, r)
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+
+
+# ------------------------------------------------------------------------ LU
+
+def test_lu_inverse_logdet_sign():
+    rng = np.random.default_rng(5)
+    for n in (1, 2, 5, 20, 64):
+        A = rng.standard_normal((n, n))
+        inv, ld, sg = orc.lu_inverse(A)
+        s_np, ld_np = np.linalg.slogdet(A)
+        assert abs(ld - ld_np) < 1e-11 * max(1, abs(ld_np))
+        assert sg == int(s_np)
+        assert np.abs(A @ inv - np.eye(n)).max() < 1e-10
+    # permutation matrix: |det| = 1, sign = parity
+    P = np.eye(4)[[1, 0, 3, 2]]
+    inv, ld, sg = orc.lu_inverse(P)
+    assert ld == 0.0 and sg == 1 and np.array_equal(inv, P.T)
+    P = np.eye(3)[[1, 2, 0]]
+    assert orc.lu_inverse(P)[2] == 1
+    P = np.eye(3)[[1, 0, 2]]
+    assert orc.lu_inverse(P)[2] == -1
+    with pytest.raises(ZeroDivisionError):
+        orc.lu_inverse(np.array([[1.0, 2.0], [2.0, 4.0]]))
+
+
+# ------------------------------------------------------- chain vs brute force
+
+def _tiny_system(n, G=8, L=4.0, j2=True, seed=11):
+    tab = np.random.default_rng(seed).uniform(-1, 1, (G, G, G, n))
+    s = orc.System(n, n, L, G=G, n_orb=n, orb_kind=orc.ORB_TABLE, table=tab, use_j2=j2, seed=seed)
+    d = Direct(n, n, L, table=tab, use_j2=j2, seed=seed)
+    return s, d
+
+
+@pytest.mark.parametrize("n,j2", [(1, True), (2, False), (3, True)])
+def test_vmc_chain_matches_direct_determinants(n, j2):
+    """P4 / P7 / P10: Sherman-Morrison ratios equal det(A')/det(A) from two LUs, the Jastrow
+    ratio equals the brute-force difference of full pair sums, the accept sequence is the same,
+    and the accumulated log|det| equals slogdet of the final matrices."""
+    s, d = _tiny_system(n, j2=j2)
+    R0 = start_positions(77, 3, 2 * n, s.L)
+    sweeps = 6
+    res = orc.vmc(s, R0, sweeps, sigma=0.6)
+    for w in range(3):
+        ref = d.vmc(R0[w], sweeps, sigma=0.6, uid=w)
+        assert np.array_equal(res.acc[:, :, w], ref["acc"])
+        assert np.allclose(res.rho[:, :, w], ref["rho"], rtol=1e-10, atol=1e-13)
+        assert np.allclose(res.dlnj[:, :, w], ref["dlnj"], rtol=1e-12, atol=1e-13)
+        assert np.allclose(res.logdet[:, w, :], ref["logdet"], rtol=1e-10, atol=1e-10)
+        assert np.allclose(res.R[w], ref["R"], atol=1e-14)
+    assert 0.2 < res.acc.mean() < 0.95
+
+
+def test_inverse_after_sweeps_matches_direct_inverse():
+    """P5: after several sweeps of Sherman-Morrison updates the kept inverse equals inv(A)."""
+    n = 6
+    s, d = _tiny_system(n, G=10, L=5.0, j2=True, seed=12)
+    R0 = start_positions(78, 2, 2 * n, s.L)
+    res = orc.vmc(s, R0, 4, sigma=0.5, want_ainv=True)
+    assert res.acc.sum() > 10
+    for w in range(2):
+        mats = d.matrices(res.R[w])
+        for sp in range(2):
+            ref = np.linalg.inv(mats[sp])
+            err = np.abs(res.ainv[w, sp] - ref).max() / np.abs(ref).max()
+            assert err < 1e-11
+
+
+def test_local_energy_matches_finite_differences():
+    """L11: the kinetic local energy formula agrees with -1/2 sum lap Psi / Psi by finite
+    differences of the directly evaluated wavefunction (splines + J2)."""
+    n = 2
+    s, d = _tiny_system(n, G=8, L=4.0, j2=True, seed=13)
+    R0 = start_positions(79, 3, 2 * n, s.L)
+    res = orc.vmc(s, R0, 2, sigma=0.5)
+    for w in range(3):
+        e_fd = d.eloc_fd(res.R[w])
+        assert abs(res.eloc[-1, w] - e_fd) < 2e-5 * max(1.0, abs(e_fd))
+
+
+def test_planewave_local_energy_is_exact_constant():
+    """P8: with analytic plane-wave orbitals E_L = sum k_j^2 / 2 = 12 pi^2 / 25 for every walker
+    and every sweep."""
+    e0 = float(_golden_numbers("planewave_c1_energy.txt")[0][0])
+    s = orc.System(4, 4, 5.0, n_orb=4, orb_kind=orc.ORB_PLANEWAVE, seed=1001)
+    R0 = start_positions(1001, 8, 8, 5.0)
+    res = orc.vmc(s, R0, 5, sigma=0.5)
+    assert np.all(np.abs(res.eloc - e0) < 1e-11 * e0)
+    ld, sg, el, _ = orc.setup(s, R0)
+    assert np.all(np.abs(el - e0) < 1e-11 * e0)
+    # and the brute-force finite-difference energy agrees with it
+    d = Direct(4, 4, 5.0, planewave=True)
+    assert abs(d.eloc_fd(res.R[0]) - e0) < 1e-5
+
+
+def test_spline_local_energy_converges_as_h2():
+    """P9: with the prefiltered spline the local energy approaches 12 pi^2 / 25 as O(h^2):
+    about 1 % off at G=16 and about 4x closer at G=32."""
+    e0 = float(_golden_numbers("planewave_c1_energy.txt")[0][0])
+    R0 = start_positions(1001, 16, 8, 5.0)
+    errs = []
+    for G in (16, 32):
+        s = orc.System(4, 4, 5.0, G=G, n_orb=4, orb_kind=orc.ORB_TABLE, table=planewave_table(G, 5.0),
+                       seed=1001)
+        res = orc.vmc(s, R0, 3, sigma=0.5)
+        errs.append(np.median(np.abs(res.eloc / e0 - 1.0)))
+    assert 1e-3 < errs[0] < 5e-2
+    assert 2.5 < errs[0] / errs[1] < 6.5
+
+
+def test_two_electron_jastrow_closed_form():
+    """P10: one up and one down electron, constant orbital: E_L = -(u'' + 2u'/r + u'^2) with
+    u' = a/(1+br)^2, u'' = -2ab/(1+br)^3 (a = 0.5, b = 1) for r < L/2."""
+    G, L = 4, 10.0
+    tab = np.ones((G, G, G, 1))
+    s = orc.System(1, 1, L, G=G, n_orb=1, orb_kind=orc.ORB_TABLE, table=tab, use_j2=True, seed=5)
+    a, b = 0.5, 1.0
+    for r in (0.3, 1.0, 2.2, 4.9):
+        R = np.array([[[1.0, 2.0, 3.0], [1.0 + r, 2.0, 3.0]]])
+        _, _, el, _ = orc.setup(s, R)
+        up = a / (1 + b * r) ** 2
+        upp = -2 * a * b / (1 + b * r) ** 3
+        assert abs(el[0] - (-(upp + 2 * up / r + up * up))) < 1e-13
+        # ln J of the pair is u(r) = a r / (1 + b r)
+        assert abs(orc.lnj(s, R[0]) - a * r / (1 + b * r)) < 1e-15
+    # minimum image: a separation of L - r is the same pair at distance r
+    R1 = np.array([[0.5, 0.5, 0.5], [0.5 + L - 1.5, 0.5, 0.5]])
+    assert abs(orc.lnj(s, R1) - a * 1.5 / 2.5) < 1e-14
+
+
+def test_metropolis_always_accepts_when_ratio_is_one():
+    """P11: constant orbital, no Jastrow: P = 1 so every move is accepted and the trajectory is
+    the wrapped Gaussian walk r <- wrap(r + sigma z) of the generator alone."""
+    G, L = 4, 3.0
+    s = orc.System(1, 1, L, G=G, n_orb=1, orb_kind=orc.ORB_TABLE, table=np.full((G, G, G, 1), 0.7),
+                   seed=31)
+    R0 = start_positions(5, 2, 2, L)
+    res = orc.vmc(s, R0, 25, sigma=0.9, uids=[10, 11], first_step=100)
+    assert res.acc.all()
+    assert np.allclose(res.prob, 1.0, atol=1e-15)
+    for w, uid in enumerate((10, 11)):
+        R = R0[w].copy()
+        for sw in range(25):
+            for e in range(2):
+                R[e] = R[e] + 0.9 * orc.gauss3(31, uid, 100 + sw, e)
+                R[e] -= L * np.floor(R[e] / L)
+        assert np.allclose(res.R[w], R, atol=1e-12)
+
+
+def test_walker_subsets_and_partial_sweeps_are_consistent():
+    """Walkers are independent: a subset run (by uid) reproduces the full run's records, and a
+    partial first sweep reproduces its prefix."""
+    s, _ = _tiny_system(3, j2=True, seed=14)
+    R0 = start_positions(80, 5, 6, s.L)
+    full = orc.vmc(s, R0, 2)
+    sub = orc.vmc(s, R0[[1, 3]], 2, uids=[1, 3])
+    assert np.array_equal(sub.acc, full.acc[:, :, [1, 3]])
+    assert np.array_equal(sub.rho, full.rho[:, :, [1, 3]])
+    part = orc.vmc(s, R0, 1, max_moves=4)
+    assert np.array_equal(part.rho[0, :4], full.rho[0, :4])
+    assert np.isnan(part.rho[0, 4:]).all()
+
+
+# ----------------------------------------------------------------------- DMC
+
+def test_dmc_eigenstate_population_is_constant():
+    """P13: for the analytic plane-wave eigenstate with E_T = E0 every branching weight is 1,
+    the population never changes and the energy estimate is E0."""
+    e0 = float(_golden_numbers("planewave_c1_energy.txt")[0][0])
+    s = orc.System(4, 4, 5.0, n_orb=4, orb_kind=orc.ORB_PLANEWAVE, seed=9)
+    R0 = start_positions(9, 12, 8, 5.0)
+    res = orc.dmc(s, R0, 6, tau=0.01, e_trial=e0, n_target=12)
+    assert np.all(res.pop == 12)
+    assert np.allclose(res.wsum, 12.0, atol=1e-10)
+    assert np.allclose(res.e_est, e0, atol=1e-10)
+    assert np.allclose(res.e_t, e0, atol=1e-10)
+    assert np.array_equal(res.uids, np.arange(12))
+    assert res.n_acc > 0.9 * res.n_prop
+
+
+def test_dmc_without_drift_is_a_gaussian_walk():
+    """With a constant orbital and no Jastrow the drift is zero and P = 1: the DMC move is the
+    wrapped Gaussian walk with standard deviation sqrt(tau)."""
+    G, L, tau = 4, 3.0, 0.04
+    s = orc.System(1, 1, L, G=G, n_orb=1, orb_kind=orc.ORB_TABLE, table=np.full((G, G, G, 1), 1.3),
+                   seed=41)
+    R0 = start_positions(6, 3, 2, L)
+    res = orc.dmc(s, R0, 5, tau=tau, e_trial=0.0, n_target=3)
+    assert res.n_acc == res.n_prop == 5 * 3 * 2
+    assert np.all(res.pop == 3)
+    for w in range(3):
+        R = R0[w].copy()
+        for g in range(5):
+            for e in range(2):
+                R[e] = R[e] + np.sqrt(tau) * orc.gauss3(41, w, g, e)
+                R[e] -= L * np.floor(R[e] / L)
+        assert np.allclose(res.R[w], R, atol=1e-12)
+
+
+def test_dmc_branching_bookkeeping():
+    """Branching multiplicities follow floor(w + u_b) capped at 3, children inherit the parent's
+    configuration in population order, copy 0 keeps the parent's uid."""
+    s, _ = _tiny_system(2, j2=True, seed=15)
+    R0 = start_positions(81, 20, 4, s.L)
+    res = orc.dmc(s, R0, 3, tau=0.05, e_trial=0.0, n_target=20)
+    assert res.pop[-1] == len(res.uids) > 0
+    # every final walker descends from an original uid or is a hashed child uid
+    assert len(set(res.uids.tolist())) == len(res.uids)
+    # the trial energy update: E_T = E_est - ln(N/N_target)/(10 tau)
+    assert np.allclose(res.e_t, res.e_est - np.log(res.pop / 20.0) / (10 * 0.05), atol=1e-12)
