@@ -141,6 +141,7 @@ class Direct:
         rho = np.zeros((n_sweeps, ne)); dl = np.zeros((n_sweeps, ne)); pr = np.zeros((n_sweeps, ne))
         acc = np.zeros((n_sweeps, ne), np.uint8)
         logdet = np.zeros((n_sweeps, 2))
+        sign = np.zeros((n_sweeps, 2))
         for s in range(n_sweeps):
             step = first_step + s
             for e in range(ne):
@@ -160,4 +161,14 @@ class Direct:
                 if a:
                     R = Rn
             logdet[s] = [d[1] for d in self.slogdets(R)]
-        return dict(rho=rho, dlnj=dl, prob=pr, acc=acc, logdet=logdet, R=R)
+            sign[s] = [d[0] for d in self.slogdets(R)]
+        return dict(rho=rho, dlnj=dl, prob=pr, acc=acc, logdet=logdet, sign=sign, R=R)
+
+    def drift_fd(self, R, e, h=1e-6):
+        """grad_e ln|Psi| by central first differences."""
+        g = np.zeros(3)
+        for c in range(3):
+            Rp = R.copy(); Rp[e, c] += h
+            Rm = R.copy(); Rm[e, c] -= h
+            g[c] = (self.log_psi(Rp)[1] - self.log_psi(Rm)[1]) / (2 * h)
+        return g

@@ -54,6 +54,10 @@ def lib():
                              ctypes.c_uint32, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                              ctypes.c_int, ctypes.c_int, dp, dp, dp, dp, dp, dp, dp, dp]
         L.or_dmc.restype = ctypes.c_int
+        L.or_drift.argtypes = [ctypes.POINTER(OrSystem), dp, ctypes.c_int, dp]
+        L.or_drift.restype = ctypes.c_int
+        L.or_dmc_move_prob.argtypes = [ctypes.POINTER(OrSystem), dp, ctypes.c_int, dp, ctypes.c_double, dp, dp]
+        L.or_dmc_move_prob.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -246,6 +250,29 @@ def setup(sys: System, R0, n_threads=0):
     if st != 0:
         raise ZeroDivisionError("singular starting configuration")
     return ld, sg, el, ai
+
+
+def drift(sys: System, R, e):
+    """grad ln|Psi_T| with respect to electron e at configuration R ([Ne][3])."""
+    R = np.ascontiguousarray(R, dtype=np.float64)
+    v = np.zeros(3)
+    cs = sys.c()
+    if lib().or_drift(ctypes.byref(cs), R.ctypes.data, e, v.ctypes.data) != 0:
+        raise ZeroDivisionError("singular configuration")
+    return v
+
+
+def dmc_move_prob(sys: System, R, e, delta, tau):
+    """(P, rho_D) of the DMC move of electron e by the displacement delta from configuration R."""
+    R = np.ascontiguousarray(R, dtype=np.float64)
+    d = np.ascontiguousarray(delta, dtype=np.float64)
+    p = ctypes.c_double()
+    r = ctypes.c_double()
+    cs = sys.c()
+    if lib().or_dmc_move_prob(ctypes.byref(cs), R.ctypes.data, e, d.ctypes.data, tau,
+                              ctypes.addressof(p), ctypes.addressof(r)) != 0:
+        raise ZeroDivisionError("singular configuration")
+    return p.value, r.value
 
 
 @dataclass

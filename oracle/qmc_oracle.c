@@ -727,6 +727,66 @@ int or_setup(const or_system* s, int n_walkers, const double* R0, int n_threads,
     return status;
 }
 
+
+/* DMC acceptance probability of moving electron e by the displacement delta
+   (r' = wrap(r_e + delta)); v = drift at r_e, v' = drift at r':
+   P = rho_D^2 exp(2 dlnJ) exp(-(|delta + tau v'|^2 - |delta - tau v|^2) / (2 tau)).
+   Leaves the orbital row at r' in t and r', rho_D in rnew, *rho_out. */
+static double dmc_move_prob(const or_system* s, const walker* w, int e, const double delta[3],
+                            double tau, scratch* t, double rnew[3], double* rho_out)
+{
+    int sp = spin_of(s, e);
+    int n = sp == 0 ? s->n_up : s->n_dn;
+    double v[3], gd[3], gj[3], lj, vnew[3];
+    drift_current(s, w, e, v);
+    for (int c = 0; c < 3; ++c) rnew[c] = wrap(w->R[3 * e + c] + delta[c], s->L);
+    or_orbital_vgl(s, rnew, n, t->v, t->g, t->l);
+    double rho = det_ratio(s, w, e, t, gd);
+    double dlnj = j2_delta(s, w->R, e, rnew);
+    j2_grad_lap(s, w->R, e, rnew, gj, &lj);
+    double fwd = 0, bwd = 0;
+    for (int c = 0; c < 3; ++c) {
+        vnew[c] = gd[c] + gj[c];
+        double f = delta[c] - tau * v[c];
+        double b = delta[c] + tau * vnew[c];
+        fwd += f * f;
+        bwd += b * b;
+    }
+    *rho_out = rho;
+    return rho * rho * exp(2.0 * dlnj) * exp(-(bwd - fwd) / (2.0 * tau));
+}
+
+/* Test entry points for one configuration R of one walker: the drift
+   grad ln|Psi| of electron e, and the DMC acceptance probability of moving it
+   by delta (rho_D returned through rho_out).  Return -1 if R is singular. */
+int or_drift(const or_system* s, const double* R, int e, double v[3])
+{
+    walker w;
+    walker_alloc(s, &w);
+    memcpy(w.R, R, sizeof(double) * 3 * (s->n_up + s->n_dn));
+    int st = walker_setup(s, &w);
+    if (st == 0) drift_current(s, &w, e, v);
+    walker_free(&w);
+    return st;
+}
+
+int or_dmc_move_prob(const or_system* s, const double* R, int e, const double delta[3], double tau,
+                     double* prob, double* rho_out)
+{
+    int nmax = s->n_up > s->n_dn ? s->n_up : s->n_dn;
+    walker w;
+    scratch t;
+    double rnew[3];
+    walker_alloc(s, &w);
+    scratch_alloc(&t, nmax);
+    memcpy(w.R, R, sizeof(double) * 3 * (s->n_up + s->n_dn));
+    int st = walker_setup(s, &w);
+    if (st == 0) *prob = dmc_move_prob(s, &w, e, delta, tau, &t, rnew, rho_out);
+    scratch_free(&t);
+    walker_free(&w);
+    return st;
+}
+
 /* ------------------------------------------------------------------------ */
 /* DMC: Alg. 1 with drift-diffusion proposals and branching (L12-L13).       */
 /* Per move (electron e, current drift v = grad ln|Psi| at r_e):             */
@@ -780,28 +840,11 @@ int or_dmc(const or_system* s, int n_walkers, const uint32_t* uids, const double
             scratch t;
             scratch_alloc(&t, nmax);
             for (int e = 0; e < ne; ++e) {
-                int sp = spin_of(s, e);
-                int n = sp == 0 ? s->n_up : s->n_dn;
-                double v[3], z[3], delta[3], rnew[3], gd[3], gj[3], lj, vnew[3];
+                double v[3], z[3], delta[3], rnew[3], rho;
                 drift_current(s, w, e, v);
                 or_gauss3(s->seed, w->uid, step, (uint32_t)e, z);
-                for (int c = 0; c < 3; ++c) {
-                    delta[c] = tau * v[c] + sqrt_tau * z[c];
-                    rnew[c] = wrap(w->R[3 * e + c] + delta[c], s->L);
-                }
-                or_orbital_vgl(s, rnew, n, t.v, t.g, t.l);
-                double rho = det_ratio(s, w, e, &t, gd);
-                double dlnj = j2_delta(s, w->R, e, rnew);
-                j2_grad_lap(s, w->R, e, rnew, gj, &lj);
-                double fwd = 0, bwd = 0;
-                for (int c = 0; c < 3; ++c) {
-                    vnew[c] = gd[c] + gj[c];
-                    double f = delta[c] - tau * v[c];
-                    double b = delta[c] + tau * vnew[c];
-                    fwd += f * f;
-                    bwd += b * b;
-                }
-                double prob = rho * rho * exp(2.0 * dlnj) * exp(-(bwd - fwd) / (2.0 * tau));
+                for (int c = 0; c < 3; ++c) delta[c] = tau * v[c] + sqrt_tau * z[c];
+                double prob = dmc_move_prob(s, w, e, delta, tau, &t, rnew, &rho);
                 double u = or_accept_uniform(s->seed, w->uid, step, (uint32_t)e);
                 int acc = (rho > 0.0) && (u < prob);
                 n_prop++;

@@ -238,8 +238,12 @@ def test_vmc_chain_matches_direct_determinants(n, j2):
         assert np.allclose(res.rho[:, :, w], ref["rho"], rtol=1e-10, atol=1e-13)
         assert np.allclose(res.dlnj[:, :, w], ref["dlnj"], rtol=1e-12, atol=1e-13)
         assert np.allclose(res.logdet[:, w, :], ref["logdet"], rtol=1e-10, atol=1e-10)
+        assert np.array_equal(res.sign[:, w, :], ref["sign"].astype(np.int32))
         assert np.allclose(res.R[w], ref["R"], atol=1e-14)
     assert 0.2 < res.acc.mean() < 0.95
+    if n > 1:
+        # the chains cross nodes, so both determinant signs occur
+        assert (res.sign == -1).any() and (res.sign == 1).any()
 
 
 def test_inverse_after_sweeps_matches_direct_inverse():
@@ -399,3 +403,54 @@ def test_dmc_branching_bookkeeping():
     assert len(set(res.uids.tolist())) == len(res.uids)
     # the trial energy update: E_T = E_est - ln(N/N_target)/(10 tau)
     assert np.allclose(res.e_t, res.e_est - np.log(res.pop / 20.0) / (10 * 0.05), atol=1e-12)
+
+
+def test_dmc_drift_matches_finite_differences():
+    """The DMC drift grad ln|Psi_T| (determinant part from the inverse column and gradient row,
+    plus the Jastrow gradient) agrees with central differences of the direct ln|Psi|."""
+    n = 3
+    s, d = _tiny_system(n, G=8, L=4.0, j2=True, seed=16)
+    R = start_positions(82, 1, 2 * n, s.L)[0]
+    for e in range(2 * n):
+        v = orc.drift(s, R, e)
+        assert np.allclose(v, d.drift_fd(R, e), atol=2e-6 * (1 + np.abs(v).max()))
+
+
+def test_dmc_acceptance_detailed_balance():
+    """Importance-sampled Metropolis-Hastings obeys detailed balance with respect to |Psi_T|^2:
+    the acceptance of a move and of its exact reverse multiply to one,
+    P(r -> r') P(r' -> r) = 1, for any displacement (Reynolds et al. 1982)."""
+    n = 3
+    s, _ = _tiny_system(n, G=8, L=4.0, j2=True, seed=17)
+    R = start_positions(83, 1, 2 * n, s.L)[0]
+    rng = np.random.default_rng(7)
+    for tau in (0.01, 0.1):
+        for e in range(2 * n):
+            delta = rng.normal(0, np.sqrt(tau), 3) + tau * orc.drift(s, R, e)
+            p_f, rho_f = orc.dmc_move_prob(s, R, e, delta, tau)
+            R2 = R.copy()
+            R2[e] = R[e] + delta
+            R2[e] -= s.L * np.floor(R2[e] / s.L)
+            p_b, rho_b = orc.dmc_move_prob(s, R2, e, -delta, tau)
+            assert abs(p_f * p_b - 1.0) < 1e-9
+            assert abs(rho_f * rho_b - 1.0) < 1e-9
+            # and it is not trivially 1 in each direction
+            assert abs(p_f - 1.0) > 1e-6
+
+
+def test_dmc_branching_multiplicity_cap():
+    """With the weight forced above 3 (E_T far above a constant E_L, large tau) every walker
+    branches into exactly 3 copies: m = min(3, floor(w + u)), w = exp(tau ecut)."""
+    e0 = float(_golden_numbers("planewave_c1_energy.txt")[0][0])
+    s = orc.System(4, 4, 5.0, n_orb=4, orb_kind=orc.ORB_PLANEWAVE, seed=19)
+    R0 = start_positions(19, 12, 8, 5.0)
+    tau = 4.0
+    ecut = 0.2 * np.sqrt(8 / tau)
+    assert np.exp(tau * ecut) > 3.0
+    res = orc.dmc(s, R0, 1, tau=tau, e_trial=e0 + 100.0, n_target=12, max_pop=64)
+    assert res.pop[0] == 36
+    assert np.allclose(res.wsum[0], 12 * np.exp(tau * ecut), rtol=1e-12)
+    # children follow their parent: copies 0, 1, 2 of walker w sit at 3w, 3w+1, 3w+2
+    assert np.array_equal(res.uids[::3], np.arange(12))
+    assert np.array_equal(res.R[1::3], res.R[::3])
+    assert res.uids[1] == orc.child_uid(19, 0, 0, 1)
