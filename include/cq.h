@@ -1,0 +1,184 @@
+/*
+ * cq.h -- C ABI of the crowd-of-walkers particle-by-particle QMC move on
+ * MI355X (gfx950).
+ *
+ * The library implements the batched particle-by-particle move of Luo, Doak
+ * and Kent, "A High-Performance Design for Hierarchical Parallelism in the
+ * QMCPACK Monte Carlo code" (arXiv 2209.14487): for every walker of a crowd
+ * (Sec. III, a subset of the walkers that moves through the algorithm in
+ * lock-step, driven by one host thread) and for every particle in turn, lines
+ * 5-9 of Alg. 1 -- propose a move, evaluate the wavefunction ratio and the
+ * derivatives at the new position, accept or reject -- followed by the local
+ * energy (Alg. 1 L11).  The calls are the paper's batched "multi-walker" API
+ * (Sec. III): one call advances every walker of the crowd.
+ *
+ * Wavefunction (not specified by the paper; textbook definitions):
+ *   Psi_T(R) = det A_up det A_dn exp(sum_{i<j} u(r_ij)),
+ *   A_sigma[i][j] = phi_j(r_i) with phi_j a periodic uniform cubic B-spline on a
+ *   G^3 grid over a cubic box of edge L, and u(r) = a r / (1 + b r) (two-body
+ *   Pade Jastrow, a depends on equal/opposite spins, minimum-image distance).
+ *
+ * Conventions shared by every call:
+ *   - Status codes only; nothing is thrown across the ABI.  On a non-OK status
+ *     cq_last_error() returns a thread-local message.
+ *   - Invalid sizes or pointers give CQ_EINVAL before anything is allocated.
+ *   - Host arrays passed in are copied; host arrays passed out are owned by the
+ *     caller.  Device buffers allocated by the library are owned by it.
+ *   - run_* calls are asynchronous on the crowd's HIP stream; get_* calls
+ *     synchronise that stream first.
+ *   - A crowd is driven by one host thread at a time; distinct crowds may be
+ *     driven concurrently from different threads (the paper's crowds over host
+ *     threads, Alg. 4).
+ *   - Electrons 0..N-1 are spin up, N..2N-1 spin down; n_up == n_dn == N.
+ *   - Positions are FP64, [walker][electron][xyz], row-major.
+ */
+#ifndef CQ_H
+#define CQ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CQ_OK = 0,
+    CQ_EINVAL = 1,     /* invalid argument or size */
+    CQ_ENOMEM = 2,     /* device or host allocation failed */
+    CQ_EDEVICE = 3,    /* HIP runtime error (message says which call) */
+    CQ_ESINGULAR = 4,  /* a Slater matrix was singular or not finite (message names the walker) */
+    CQ_ESTATE = 5      /* call made in the wrong state (e.g. run before positions are set) */
+} cq_status;
+
+typedef enum { CQ_FP64 = 0, CQ_MIXED = 1 } cq_precision;
+
+/* Kernel classes whose device time can be measured with cq_crowd_get_kernel_timing. */
+typedef enum {
+    CQ_KERNEL_VGL = 0,      /* propose + B-spline VGL + ratio partial dots + Jastrow partials */
+    CQ_KERNEL_RESOLVE = 1,  /* ratio, Metropolis decision, window bookkeeping */
+    CQ_KERNEL_UPDATE = 2,   /* Sherman-Morrison / delayed rank-k inverse update */
+    CQ_KERNEL_ENERGY = 3,   /* local energy */
+    CQ_KERNEL_INVERSE = 4,  /* FP64 Gauss-Jordan inversion (initial and periodic recompute) */
+    CQ_KERNEL_COUNT = 5
+} cq_kernel_kind;
+
+typedef struct cq_system cq_system;  /* orbitals + Jastrow + box + electron counts (opaque) */
+typedef struct cq_crowd cq_crowd;    /* walkers moved in lock-step (opaque) */
+
+/* ---------------------------------------------------------------- systems */
+
+/* Create an empty system of n_up + n_dn electrons in a cubic box of edge box_L
+   (bohr).  Requires n_up == n_dn >= 1, box_L > 0. */
+cq_status cq_system_create(int n_up, int n_dn, double box_L, cq_system** out);
+
+/* Load B-spline coefficients, layout [gx][gy][gz][n_orb] row-major (orbital
+   index fastest), elem_bytes 4 (FP32) or 8 (FP64), gx == gy == gz >= 4,
+   n_orb == n_up.  coefs_on_device = 0: host array, copied to the device.
+   coefs_on_device = 1: a device buffer that the system BORROWS (e.g. a torch
+   tensor); it must stay alive and unchanged while the system exists.
+   The FP32 table drives the mixed-precision path, the FP64 table the FP64 path;
+   a system may hold both (load twice). */
+cq_status cq_system_load_bspline(cq_system* sys, const void* coefs, int elem_bytes, int gx, int gy, int gz,
+                                 int n_orb, int coefs_on_device);
+
+/* Generate a seeded coefficient table on the device (owned by the system):
+   coefficient with linear index idx = ((ix G + iy) G + iz) n_orb + n is
+   2 u - 1, u the 53-bit uniform of Philox4x32-10 (Salmon et al. SC'11) with key
+   (seed low, seed high) and counter (idx low, idx high, 0xC0EF, 0), u =
+   ((w1:w0) >> 11) 2^-53.  elem_bytes 4 stores the FP64 value rounded to
+   nearest FP32.  Synthetic stand-in for fitted orbitals of any size. */
+cq_status cq_system_fill_bspline_philox(cq_system* sys, uint64_t seed, int elem_bytes, int grid, int n_orb);
+
+/* Two-body Pade Jastrow u(r) = a r / (1 + b r): a_par for equal spins,
+   a_anti for opposite spins.  Without this call the Jastrow factor is 1. */
+cq_status cq_system_load_pade_j2(cq_system* sys, double a_par, double a_anti, double b);
+
+void cq_system_destroy(cq_system* sys);
+
+/* ----------------------------------------------------------------- crowds */
+
+typedef struct {
+    int precision;        /* cq_precision: CQ_MIXED uses the FP32 table and FP32 inverses,
+                             FP64 for log|det|, the recompute and every sum over walkers */
+    int delay_rank;       /* k: 1 = Sherman-Morrison after every accepted move, 2..32 = delayed
+                             rank-k update (window of k proposals); 0 = choose by autotuning */
+    int recompute_every;  /* sweeps between FP64 recomputes of the inverses (0 = never) */
+    uint64_t seed;        /* Philox key of the move random numbers */
+    uint32_t first_uid;   /* walker w of this crowd has uid first_uid + w (random streams) */
+    void* hip_stream;     /* borrowed hipStream_t to run on, or NULL: the crowd makes its own */
+    int use_graph;        /* 1: capture one sweep as a hipGraph and replay it */
+} cq_crowd_desc;
+
+/* Create a crowd of walkers_per_system[s] walkers of each system s.  This
+   version accepts n_systems == 1.  Allocates every device buffer up front
+   (CQ_ENOMEM if the device cannot hold them). */
+cq_status cq_crowd_create(const cq_system* const* systems, const int* walkers_per_system, int n_systems,
+                          const cq_crowd_desc* desc, cq_crowd** out);
+
+/* Set positions R [W][Ne][3] (host, or device when on_device = 1), then
+   evaluate every orbital at every electron, invert both Slater matrices in
+   FP64 (Gauss-Jordan with partial pivoting) and compute log|det|, sign and the
+   local energy.  CQ_ESINGULAR if a matrix is singular.  Resets the sweep
+   counter to first_step. */
+cq_status cq_crowd_set_positions(cq_crowd* c, const double* R, int on_device, uint32_t first_step);
+
+/* Alg. 1 L4-L11 for n_sweeps sweeps: each electron in index order proposes
+   r' = wrap(r + sigma z), z ~ N(0, I_3) from Philox counter (uid, step, e, 0/1),
+   accepts iff u < rho_D^2 exp(2 dlnJ) with u from counter (uid, step, e, 2), and
+   updates the inverse.  The local energy is evaluated after every sweep.
+   Asynchronous. */
+cq_status cq_crowd_run_vmc(cq_crowd* c, int n_sweeps, double sigma);
+
+/* Recompute every inverse and log|det| from the current rows in FP64 now.
+   If max_drift is non-NULL it receives max |log|det| kept - log|det| recomputed|
+   over walkers and spins.  Synchronous. */
+cq_status cq_crowd_recompute(cq_crowd* c, double* max_drift);
+
+/* log|det A_sigma| [W][2] (FP64) and sign [W][2] (+1/-1). */
+cq_status cq_crowd_get_logdet(cq_crowd* c, double* logdet, int* sign);
+/* accepted and proposed single-electron moves per walker [W] since set_positions. */
+cq_status cq_crowd_get_acceptance(cq_crowd* c, int64_t* accepted, int64_t* proposed);
+/* kinetic local energy -1/2 sum_i lap_i Psi / Psi per walker [W] after the last sweep. */
+cq_status cq_crowd_get_local_energy(cq_crowd* c, double* e_l);
+/* positions [W][Ne][3]; n_walkers_per_system (may be NULL) receives the walker count. */
+cq_status cq_crowd_get_positions(cq_crowd* c, double* R, int* n_walkers_per_system);
+/* the kept inverses as FP64 [W][2][N][N], element [w][s][j][i] = (A_s^-1)[j][i]. */
+cq_status cq_crowd_get_inverse(cq_crowd* c, double* ainv);
+
+/* Parity mode: the crowd follows the given decisions flags[sweep][e][w]
+   (1 accept, 0 reject) for the next n_sweeps sweeps instead of its own, while
+   still recording its own probability.  flags = NULL switches it off. */
+cq_status cq_crowd_set_forced_decisions(cq_crowd* c, const uint8_t* flags, int n_sweeps);
+/* Record per-move rho_D, dlnJ, P and the decision for the next n_sweeps sweeps
+   (0 switches recording off). */
+cq_status cq_crowd_record_moves(cq_crowd* c, int n_sweeps);
+/* Copy the records out: arrays [n_sweeps][Ne][W]; any pointer may be NULL. */
+cq_status cq_crowd_get_move_records(cq_crowd* c, double* rho, double* dlnj, double* prob, uint8_t* acc);
+
+/* Record HIP events on the crowd's stream around every launch of the kernel
+   kinds in kind_mask (bit 1 << cq_kernel_kind; 0 switches timing off) and read
+   back the summed device time in ms and the launch count of one kind since the
+   last set call.  While timing is on, sweeps are launched eagerly (no graph).
+   Up to 65536 launches per kind are timed between set calls. */
+cq_status cq_crowd_set_kernel_timing(cq_crowd* c, int kind_mask);
+cq_status cq_crowd_get_kernel_timing(cq_crowd* c, int kind, double* total_ms, int64_t* launches);
+
+/* Wait for all work queued on the crowd's stream. */
+cq_status cq_crowd_synchronize(cq_crowd* c);
+
+void cq_crowd_destroy(cq_crowd* c);
+
+/* Plain streaming device-to-device copy of `bytes` bytes (multiple of 16,
+   16-byte aligned pointers) with a library kernel on `hip_stream` (NULL: the
+   null stream), synchronous.  Its hardware traffic counters give the scale
+   factor between counter readings and bytes moved. */
+cq_status cq_device_copy(void* dst, const void* src, uint64_t bytes, void* hip_stream);
+
+/* Thread-local message of the last non-OK status ("" if none). */
+const char* cq_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CQ_H */

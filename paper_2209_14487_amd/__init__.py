@@ -1,0 +1,276 @@
+"""Crowd-of-walkers particle-by-particle QMC move on MI355X (gfx950).
+
+Thin ctypes binding of ``libcrowdqmc.so`` (C ABI in ``include/cq.h``): argument
+marshalling only, every step of the move runs in the library's HIP kernels.
+PyTorch is optional plumbing: a torch CUDA tensor may be passed wherever a
+device buffer is accepted and a torch stream as the crowd's stream.
+
+The method is the batched particle-by-particle move of Luo, Doak and Kent,
+arXiv 2209.14487 (Alg. 1 L5-L11 applied to every walker of a crowd in lock-step,
+Sec. III "crowds", Alg. 4).
+"""
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcrowdqmc.so")
+
+CQ_OK, CQ_EINVAL, CQ_ENOMEM, CQ_EDEVICE, CQ_ESINGULAR, CQ_ESTATE = range(6)
+CQ_FP64, CQ_MIXED = 0, 1
+KERNEL_VGL, KERNEL_RESOLVE, KERNEL_UPDATE, KERNEL_ENERGY, KERNEL_INVERSE = range(5)
+KERNEL_NAMES = {"vgl": KERNEL_VGL, "resolve": KERNEL_RESOLVE, "update": KERNEL_UPDATE,
+                "energy": KERNEL_ENERGY, "inverse": KERNEL_INVERSE}
+
+_STATUS_NAMES = {1: "CQ_EINVAL", 2: "CQ_ENOMEM", 3: "CQ_EDEVICE", 4: "CQ_ESINGULAR", 5: "CQ_ESTATE"}
+
+
+class CqError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (_STATUS_NAMES.get(status, str(status)), msg))
+        self.status = status
+
+
+class CrowdDesc(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("delay_rank", ctypes.c_int), ("recompute_every", ctypes.c_int),
+                ("seed", ctypes.c_uint64), ("first_uid", ctypes.c_uint32), ("hip_stream", ctypes.c_void_p),
+                ("use_graph", ctypes.c_int)]
+
+
+_lib = None
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_SIGS = {
+    "cq_system_create": [_I, _I, ctypes.c_double, _P],
+    "cq_system_load_bspline": [_P, _P, _I, _I, _I, _I, _I, _I],
+    "cq_system_fill_bspline_philox": [_P, ctypes.c_uint64, _I, _I, _I],
+    "cq_system_load_pade_j2": [_P, ctypes.c_double, ctypes.c_double, ctypes.c_double],
+    "cq_system_destroy": [_P],
+    "cq_crowd_create": [_P, _P, _I, _P, _P],
+    "cq_crowd_set_positions": [_P, _P, _I, ctypes.c_uint32],
+    "cq_crowd_run_vmc": [_P, _I, ctypes.c_double],
+    "cq_crowd_recompute": [_P, _P],
+    "cq_crowd_get_logdet": [_P, _P, _P],
+    "cq_crowd_get_acceptance": [_P, _P, _P],
+    "cq_crowd_get_local_energy": [_P, _P],
+    "cq_crowd_get_positions": [_P, _P, _P],
+    "cq_crowd_get_inverse": [_P, _P],
+    "cq_crowd_set_forced_decisions": [_P, _P, _I],
+    "cq_crowd_record_moves": [_P, _I],
+    "cq_crowd_get_move_records": [_P, _P, _P, _P, _P],
+    "cq_crowd_set_kernel_timing": [_P, _I],
+    "cq_crowd_get_kernel_timing": [_P, _I, _P, _P],
+    "cq_crowd_synchronize": [_P],
+    "cq_device_copy": [_P, _P, ctypes.c_uint64, _P],
+    "cq_crowd_destroy": [_P],
+    "cq_last_error": [],
+}
+_VOID = {"cq_system_destroy", "cq_crowd_destroy"}
+
+
+def lib():
+    """Load the HIP library; raises if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libcrowdqmc.so is not built; run __graft_entry__.build() "
+                              "(hipcc --offload-arch=gfx950)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, args in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = None if name in _VOID else (ctypes.c_char_p if name == "cq_last_error" else ctypes.c_int)
+        _lib = L
+    return _lib
+
+
+def exported_names():
+    return list(_SIGS)
+
+
+def _check(st):
+    if st != CQ_OK:
+        raise CqError(st, lib().cq_last_error().decode())
+
+
+def device_copy(dst, src, nbytes: int, stream=None):
+    """Library streaming copy between device buffers (traffic-counter calibration)."""
+    _check(lib().cq_device_copy(_ptr(dst), _ptr(src), nbytes, _stream_handle(stream)))
+
+
+def _ptr(x):
+    """Device or host address of a numpy array, a torch tensor or an int."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if isinstance(x, np.ndarray):
+        return x.ctypes.data
+    if hasattr(x, "data_ptr"):
+        return x.data_ptr()
+    raise TypeError("unsupported buffer type %r" % type(x))
+
+
+def _stream_handle(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream  # torch.cuda.Stream
+
+
+class System:
+    """Electrons, box, B-spline orbitals and Pade J2 of one system (cq_system)."""
+
+    def __init__(self, n_per_spin: int, box_L: float):
+        h = ctypes.c_void_p()
+        _check(lib().cq_system_create(n_per_spin, n_per_spin, box_L, ctypes.byref(h)))
+        self._h = h
+        self.n = n_per_spin
+        self.L = box_L
+        self._keep = []
+
+    def fill_philox(self, seed: int, elem_bytes: int, grid: int):
+        _check(lib().cq_system_fill_bspline_philox(self._h, seed, elem_bytes, grid, self.n))
+
+    def load_table(self, table, elem_bytes: Optional[int] = None):
+        """table [G][G][G][N]: numpy (copied) or a torch CUDA tensor (borrowed, kept alive here)."""
+        G = table.shape[0]
+        if isinstance(table, np.ndarray):
+            eb = table.dtype.itemsize if elem_bytes is None else elem_bytes
+            arr = np.ascontiguousarray(table, dtype=np.float32 if eb == 4 else np.float64)
+            _check(lib().cq_system_load_bspline(self._h, arr.ctypes.data, eb, G, G, G, table.shape[3], 0))
+        else:
+            assert table.is_contiguous()
+            eb = table.element_size()
+            self._keep.append(table)
+            _check(lib().cq_system_load_bspline(self._h, table.data_ptr(), eb, G, G, G, table.shape[3], 1))
+
+    def load_j2(self, a_par=0.25, a_anti=0.5, b=1.0):
+        _check(lib().cq_system_load_pade_j2(self._h, a_par, a_anti, b))
+
+    def close(self):
+        if self._h:
+            lib().cq_system_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Crowd:
+    """A crowd of walkers of one system moved in lock-step (cq_crowd)."""
+
+    def __init__(self, system: System, n_walkers: int, precision: str = "mixed", delay_rank: int = 1,
+                 recompute_every: int = 0, seed: int = 0, first_uid: int = 0, stream=None,
+                 use_graph: bool = True):
+        self.system = system
+        self.W = n_walkers
+        self.n = system.n
+        self.ne = 2 * system.n
+        desc = CrowdDesc(CQ_MIXED if precision == "mixed" else CQ_FP64, delay_rank, recompute_every, seed,
+                         first_uid, _stream_handle(stream), int(use_graph))
+        systems = (ctypes.c_void_p * 1)(system._h.value)
+        counts = (ctypes.c_int * 1)(n_walkers)
+        h = ctypes.c_void_p()
+        _check(lib().cq_crowd_create(systems, counts, 1, ctypes.byref(desc), ctypes.byref(h)))
+        self._h = h
+        self._rec = 0
+
+    def set_positions(self, R, first_step: int = 0):
+        if isinstance(R, np.ndarray):
+            R = np.ascontiguousarray(R, dtype=np.float64)
+            assert R.shape == (self.W, self.ne, 3)
+            _check(lib().cq_crowd_set_positions(self._h, R.ctypes.data, 0, first_step))
+        else:
+            _check(lib().cq_crowd_set_positions(self._h, R.data_ptr(), 1, first_step))
+
+    def run_vmc(self, n_sweeps: int, sigma: float = 0.5):
+        _check(lib().cq_crowd_run_vmc(self._h, n_sweeps, sigma))
+
+    def recompute(self) -> float:
+        d = ctypes.c_double()
+        _check(lib().cq_crowd_recompute(self._h, ctypes.byref(d)))
+        return d.value
+
+    def logdet(self):
+        ld = np.zeros((self.W, 2))
+        sg = np.zeros((self.W, 2), np.int32)
+        _check(lib().cq_crowd_get_logdet(self._h, ld.ctypes.data, sg.ctypes.data))
+        return ld, sg
+
+    def acceptance(self):
+        a = np.zeros(self.W, np.int64)
+        p = np.zeros(self.W, np.int64)
+        _check(lib().cq_crowd_get_acceptance(self._h, a.ctypes.data, p.ctypes.data))
+        return a, p
+
+    def local_energy(self):
+        e = np.zeros(self.W)
+        _check(lib().cq_crowd_get_local_energy(self._h, e.ctypes.data))
+        return e
+
+    def positions(self):
+        R = np.zeros((self.W, self.ne, 3))
+        _check(lib().cq_crowd_get_positions(self._h, R.ctypes.data, None))
+        return R
+
+    def inverse(self):
+        """A^-1 per walker and spin, [W][2][N][N] FP64 (row = orbital, column = electron)."""
+        a = np.zeros((self.W, 2, self.n, self.n))
+        _check(lib().cq_crowd_get_inverse(self._h, a.ctypes.data))
+        return a
+
+    def set_forced(self, flags: Optional[np.ndarray]):
+        if flags is None:
+            _check(lib().cq_crowd_set_forced_decisions(self._h, None, 0))
+        else:
+            f = np.ascontiguousarray(flags, dtype=np.uint8)
+            assert f.shape[1:] == (self.ne, self.W)
+            _check(lib().cq_crowd_set_forced_decisions(self._h, f.ctypes.data, f.shape[0]))
+
+    def record(self, n_sweeps: int):
+        _check(lib().cq_crowd_record_moves(self._h, n_sweeps))
+        self._rec = n_sweeps
+
+    def records(self):
+        shp = (self._rec, self.ne, self.W)
+        rho, dl, pr = np.zeros(shp), np.zeros(shp), np.zeros(shp)
+        acc = np.zeros(shp, np.uint8)
+        _check(lib().cq_crowd_get_move_records(self._h, rho.ctypes.data, dl.ctypes.data, pr.ctypes.data,
+                                               acc.ctypes.data))
+        return dict(rho=rho, dlnj=dl, prob=pr, acc=acc)
+
+    def set_timing(self, kinds=()):
+        """Time the given kernel kinds (names or ids) with HIP events; () switches timing off."""
+        mask = 0
+        for k in kinds:
+            mask |= 1 << (KERNEL_NAMES[k] if isinstance(k, str) else k)
+        _check(lib().cq_crowd_set_kernel_timing(self._h, mask))
+
+    def kernel_timing(self, kind):
+        k = KERNEL_NAMES[kind] if isinstance(kind, str) else kind
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        _check(lib().cq_crowd_get_kernel_timing(self._h, k, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+    def synchronize(self):
+        _check(lib().cq_crowd_synchronize(self._h))
+
+    def close(self):
+        if self._h:
+            lib().cq_crowd_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

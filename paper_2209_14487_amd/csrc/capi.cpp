@@ -1,0 +1,790 @@
+// C ABI and crowd runtime: device buffers, the per-sweep launch sequence
+// (optionally captured once as a hipGraph and replayed), the FP64 recompute
+// schedule, parity-mode buffers and per-kernel event timing.
+//
+// One sweep (paper Alg. 1 L4-L11 over all walkers of the crowd in lock-step,
+// the batched form of Alg. 3/4) is, for e = 0 .. Ne-1:
+//   k_vgl_move(e)  -> k_resolve(e)  [-> k_flush(spin) at the end of a window]
+// then the local energy and the step counter.  Windows cover k consecutive
+// electrons of one spin and never span spins or sweeps.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "cq.h"
+#include "cq_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+cq_status fail(cq_status s, const std::string& msg)
+{
+    g_err = msg;
+    return s;
+}
+
+#define HIP_TRY(x)                                                                                   \
+    do {                                                                                             \
+        hipError_t e_ = (x);                                                                         \
+        if (e_ != hipSuccess) return fail(CQ_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr int kEventCap = 1 << 16;  // timed launches kept per kernel kind between reads
+
+}  // namespace
+
+struct cq_system {
+    int n_up = 0, n_dn = 0;
+    double L = 0.0;
+    int G = 0, n_orb = 0;
+    void* table[2] = {nullptr, nullptr};  // [0] FP32, [1] FP64
+    bool owned[2] = {false, false};
+    int use_j2 = 0;
+    double a_par = 0.0, a_anti = 0.0, b = 1.0;
+};
+
+struct cq_crowd {
+    const cq_system* sys = nullptr;
+    int W = 0, n = 0, ne = 0, K = 1, prec = CQ_MIXED, recompute_every = 0, use_graph = 0;
+    uint64_t seed = 0;
+    uint32_t first_uid = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::vector<void*> allocs;
+    // device state
+    double* R = nullptr;
+    void* M = nullptr;
+    void* VGL = nullptr;
+    double* logdet = nullptr;
+    int* sign = nullptr;
+    long long* nacc = nullptr;
+    long long* nprop = nullptr;
+    double* eloc = nullptr;
+    double* elpart = nullptr;
+    int* cnt = nullptr;
+    int* welec = nullptr;
+    void* stage = nullptr;
+    void* Cbuf = nullptr;
+    double* wrho = nullptr;
+    double* wG = nullptr;
+    double* beta = nullptr;
+    int* pend = nullptr;
+    double* part = nullptr;
+    double* rnew = nullptr;
+    uint32_t* uid = nullptr;
+    cq::Params* prm = nullptr;
+    int* status = nullptr;
+    double* drift = nullptr;
+    cq::InvWork inv{};
+    // parity mode
+    int rec_cap = 0;
+    double* rec_rho = nullptr;
+    double* rec_dlnj = nullptr;
+    double* rec_prob = nullptr;
+    uint8_t* rec_acc = nullptr;
+    int forced_cap = 0;
+    uint8_t* forced = nullptr;
+    // host state
+    cq::Params hp{};
+    bool ready = false;
+    int since_recompute = 0;
+    hipGraphExec_t gexec = nullptr;
+    // timing
+    int timing_mask = 0;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[CQ_KERNEL_COUNT];
+    size_t ev_used[CQ_KERNEL_COUNT] = {};
+};
+
+namespace {
+
+template <typename T>
+cq::CrowdView<T> view(const cq_crowd* c)
+{
+    cq::CrowdView<T> v{};
+    v.W = c->W;
+    v.n = c->n;
+    v.ne = c->ne;
+    v.K = c->K;
+    v.G = c->sys->G;
+    v.n_orb = c->sys->n_orb;
+    v.L = c->sys->L;
+    v.table = (const T*)c->sys->table[sizeof(T) == 8 ? 1 : 0];
+    v.R = c->R;
+    v.M = (T*)c->M;
+    v.VGL = (T*)c->VGL;
+    v.logdet = c->logdet;
+    v.sign = c->sign;
+    v.nacc = c->nacc;
+    v.nprop = c->nprop;
+    v.eloc = c->eloc;
+    v.elpart = c->elpart;
+    v.cnt = c->cnt;
+    v.welec = c->welec;
+    v.stage = (T*)c->stage;
+    v.Cbuf = (T*)c->Cbuf;
+    v.wrho = c->wrho;
+    v.wG = c->wG;
+    v.beta = c->beta;
+    v.pend = c->pend;
+    v.part = c->part;
+    v.rnew = c->rnew;
+    v.uid = c->uid;
+    v.seed = c->seed;
+    v.use_j2 = c->sys->use_j2;
+    v.a_par = c->sys->a_par;
+    v.a_anti = c->sys->a_anti;
+    v.b = c->sys->b;
+    v.prm = c->prm;
+    v.rec_rho = c->rec_rho;
+    v.rec_dlnj = c->rec_dlnj;
+    v.rec_prob = c->rec_prob;
+    v.rec_acc = c->rec_acc;
+    v.forced = c->forced;
+    v.status = c->status;
+    v.drift = c->drift;
+    return v;
+}
+
+cq_status dev_alloc(cq_crowd* c, void** p, size_t bytes)
+{
+    if (bytes == 0) bytes = 16;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(CQ_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
+    }
+    c->allocs.push_back(*p);
+    return CQ_OK;
+}
+
+void timed_begin(cq_crowd* c, int kind)
+{
+    if (!(c->timing_mask >> kind & 1) || c->ev_used[kind] >= (size_t)kEventCap) return;
+    auto& pool = c->ev[kind];
+    if (c->ev_used[kind] == pool.size()) {
+        hipEvent_t a, b;
+        if (hipEventCreate(&a) != hipSuccess) return;
+        if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return; }
+        pool.push_back({a, b});
+    }
+    (void)hipEventRecord(pool[c->ev_used[kind]].first, c->stream);
+}
+
+void timed_end(cq_crowd* c, int kind)
+{
+    if (!(c->timing_mask >> kind & 1) || c->ev_used[kind] >= (size_t)kEventCap || c->ev_used[kind] >= c->ev[kind].size())
+        return;
+    (void)hipEventRecord(c->ev[kind][c->ev_used[kind]].second, c->stream);
+    c->ev_used[kind]++;
+}
+
+template <typename T>
+void enqueue_sweep(cq_crowd* c)
+{
+    const cq::CrowdView<T> v = view<T>(c);
+    const int n = c->n, K = c->K;
+    for (int e = 0; e < c->ne; ++e) {
+        const int spin = e / n, a = e % n;
+        const int reset = (a % K) == 0;
+        timed_begin(c, CQ_KERNEL_VGL);
+        cq::launch_vgl_move<T>(v, e, reset, c->stream);
+        timed_end(c, CQ_KERNEL_VGL);
+        timed_begin(c, CQ_KERNEL_RESOLVE);
+        cq::launch_resolve<T>(v, e, reset, c->stream);
+        timed_end(c, CQ_KERNEL_RESOLVE);
+        if ((a + 1) % K == 0 || a == n - 1) {
+            timed_begin(c, CQ_KERNEL_UPDATE);
+            if (K > 1) cq::launch_finalize<T>(v, c->stream);
+            cq::launch_flush<T>(v, spin, c->stream);
+            timed_end(c, CQ_KERNEL_UPDATE);
+        }
+    }
+    timed_begin(c, CQ_KERNEL_ENERGY);
+    cq::launch_energy<T>(v, c->stream);
+    timed_end(c, CQ_KERNEL_ENERGY);
+    cq::launch_sweep_end(c->prm, c->stream);
+}
+
+template <typename T>
+void enqueue_inverse(cq_crowd* c)
+{
+    timed_begin(c, CQ_KERNEL_INVERSE);
+    cq::launch_inverse<T>(view<T>(c), c->inv, c->stream);
+    timed_end(c, CQ_KERNEL_INVERSE);
+}
+
+void sweep(cq_crowd* c)
+{
+    if (c->prec == CQ_FP64)
+        enqueue_sweep<double>(c);
+    else
+        enqueue_sweep<float>(c);
+}
+
+void inverse(cq_crowd* c)
+{
+    if (c->prec == CQ_FP64)
+        enqueue_inverse<double>(c);
+    else
+        enqueue_inverse<float>(c);
+}
+
+cq_status push_params(cq_crowd* c)
+{
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(hipMemcpy(c->prm, &c->hp, sizeof(cq::Params), hipMemcpyHostToDevice));
+    return CQ_OK;
+}
+
+void drop_graph(cq_crowd* c)
+{
+    if (c->gexec) {
+        (void)hipGraphExecDestroy(c->gexec);
+        c->gexec = nullptr;
+    }
+}
+
+cq_status build_graph(cq_crowd* c)
+{
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    sweep(c);
+    hipError_t e = hipStreamEndCapture(c->stream, &g);
+    if (e != hipSuccess) return fail(CQ_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        c->gexec = nullptr;
+        return fail(CQ_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+    return CQ_OK;
+}
+
+cq_status check_singular(cq_crowd* c, const char* where)
+{
+    std::vector<int> st(c->W);
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(hipMemcpy(st.data(), c->status, sizeof(int) * c->W, hipMemcpyDeviceToHost));
+    for (int w = 0; w < c->W; ++w)
+        if (st[w]) return fail(CQ_ESINGULAR, std::string(where) + ": Slater matrix of walker " + std::to_string(w) +
+                                                 " is singular or not finite");
+    return CQ_OK;
+}
+
+template <typename T>
+cq_status setup_state(cq_crowd* c)
+{
+    const cq::CrowdView<T> v = view<T>(c);
+    HIP_TRY(hipMemsetAsync(c->logdet, 0, sizeof(double) * 2 * c->W, c->stream));
+    HIP_TRY(hipMemsetAsync(c->sign, 0, sizeof(int) * 2 * c->W, c->stream));
+    HIP_TRY(hipMemsetAsync(c->nacc, 0, sizeof(long long) * c->W, c->stream));
+    HIP_TRY(hipMemsetAsync(c->nprop, 0, sizeof(long long) * c->W, c->stream));
+    HIP_TRY(hipMemsetAsync(c->cnt, 0, sizeof(int) * c->W, c->stream));
+    HIP_TRY(hipMemsetAsync(c->pend, 0xFF, sizeof(int) * c->W, c->stream));
+    HIP_TRY(hipMemsetAsync(c->status, 0, sizeof(int) * c->W, c->stream));
+    cq::launch_setup_vgl<T>(v, c->stream);
+    HIP_TRY(hipGetLastError());
+    enqueue_inverse<T>(c);
+    HIP_TRY(hipGetLastError());
+    cq::launch_energy<T>(v, c->stream);
+    HIP_TRY(hipGetLastError());
+    return check_singular(c, "set_positions");
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* cq_last_error(void) { return g_err.c_str(); }
+
+cq_status cq_system_create(int n_up, int n_dn, double box_L, cq_system** out)
+{
+    if (!out) return fail(CQ_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n_up < 1 || n_dn != n_up) return fail(CQ_EINVAL, "need n_up == n_dn >= 1");
+    if (n_up % 4 != 0) return fail(CQ_EINVAL, "electrons per spin must be a multiple of 4");
+    if (n_up > 2048) return fail(CQ_EINVAL, "at most 2048 electrons per spin");
+    if (!(box_L > 0.0) || !std::isfinite(box_L)) return fail(CQ_EINVAL, "box_L must be positive and finite");
+    cq_system* s = new (std::nothrow) cq_system();
+    if (!s) return fail(CQ_ENOMEM, "host allocation failed");
+    s->n_up = n_up;
+    s->n_dn = n_dn;
+    s->L = box_L;
+    *out = s;
+    return CQ_OK;
+}
+
+static cq_status check_table_shape(cq_system* s, int elem_bytes, int gx, int gy, int gz, int n_orb)
+{
+    if (!s) return fail(CQ_EINVAL, "system is NULL");
+    if (elem_bytes != 4 && elem_bytes != 8) return fail(CQ_EINVAL, "elem_bytes must be 4 or 8");
+    if (gx != gy || gy != gz || gx < 4) return fail(CQ_EINVAL, "grid must be cubic with at least 4 points");
+    if (n_orb != s->n_up) return fail(CQ_EINVAL, "n_orb must equal the electrons per spin");
+    if (s->G != 0 && s->G != gx) return fail(CQ_EINVAL, "grid differs from the table already loaded");
+    return CQ_OK;
+}
+
+cq_status cq_system_load_bspline(cq_system* s, const void* coefs, int elem_bytes, int gx, int gy, int gz, int n_orb,
+                                 int coefs_on_device)
+{
+    cq_status st = check_table_shape(s, elem_bytes, gx, gy, gz, n_orb);
+    if (st != CQ_OK) return st;
+    if (!coefs) return fail(CQ_EINVAL, "coefs is NULL");
+    const int slot = elem_bytes == 8 ? 1 : 0;
+    const size_t bytes = (size_t)gx * gx * gx * n_orb * elem_bytes;
+    if (s->owned[slot]) HIP_TRY(hipFree(s->table[slot]));
+    s->table[slot] = nullptr;
+    s->owned[slot] = false;
+    if (coefs_on_device) {
+        s->table[slot] = const_cast<void*>(coefs);
+    } else {
+        void* p = nullptr;
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(CQ_ENOMEM, "hipMalloc of the coefficient table failed");
+        }
+        e = hipMemcpy(p, coefs, bytes, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(p);
+            return fail(CQ_EDEVICE, std::string("hipMemcpy table: ") + hipGetErrorString(e));
+        }
+        s->table[slot] = p;
+        s->owned[slot] = true;
+    }
+    s->G = gx;
+    s->n_orb = n_orb;
+    return CQ_OK;
+}
+
+cq_status cq_system_fill_bspline_philox(cq_system* s, uint64_t seed, int elem_bytes, int grid, int n_orb)
+{
+    cq_status st = check_table_shape(s, elem_bytes, grid, grid, grid, n_orb);
+    if (st != CQ_OK) return st;
+    const int slot = elem_bytes == 8 ? 1 : 0;
+    const size_t count = (size_t)grid * grid * grid * n_orb;
+    if (s->owned[slot]) HIP_TRY(hipFree(s->table[slot]));
+    s->table[slot] = nullptr;
+    s->owned[slot] = false;
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, count * elem_bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(CQ_ENOMEM, "hipMalloc of the coefficient table failed");
+    }
+    if (elem_bytes == 4)
+        cq::launch_fill_philox<float>((float*)p, seed, count, nullptr);
+    else
+        cq::launch_fill_philox<double>((double*)p, seed, count, nullptr);
+    e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) {
+        (void)hipFree(p);
+        return fail(CQ_EDEVICE, std::string("coefficient fill: ") + hipGetErrorString(e));
+    }
+    s->table[slot] = p;
+    s->owned[slot] = true;
+    s->G = grid;
+    s->n_orb = n_orb;
+    return CQ_OK;
+}
+
+cq_status cq_system_load_pade_j2(cq_system* s, double a_par, double a_anti, double b)
+{
+    if (!s) return fail(CQ_EINVAL, "system is NULL");
+    if (!std::isfinite(a_par) || !std::isfinite(a_anti) || !(b >= 0.0) || !std::isfinite(b))
+        return fail(CQ_EINVAL, "Jastrow parameters must be finite, b >= 0");
+    s->use_j2 = 1;
+    s->a_par = a_par;
+    s->a_anti = a_anti;
+    s->b = b;
+    return CQ_OK;
+}
+
+void cq_system_destroy(cq_system* s)
+{
+    if (!s) return;
+    for (int i = 0; i < 2; ++i)
+        if (s->owned[i]) (void)hipFree(s->table[i]);
+    delete s;
+}
+
+void cq_crowd_destroy(cq_crowd* c)
+{
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    drop_graph(c);
+    for (int k = 0; k < CQ_KERNEL_COUNT; ++k)
+        for (auto& p : c->ev[k]) {
+            (void)hipEventDestroy(p.first);
+            (void)hipEventDestroy(p.second);
+        }
+    for (void* p : c->allocs) (void)hipFree(p);
+    if (c->rec_rho) (void)hipFree(c->rec_rho);
+    if (c->rec_dlnj) (void)hipFree(c->rec_dlnj);
+    if (c->rec_prob) (void)hipFree(c->rec_prob);
+    if (c->rec_acc) (void)hipFree(c->rec_acc);
+    if (c->forced) (void)hipFree(c->forced);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+cq_status cq_crowd_create(const cq_system* const* systems, const int* walkers_per_system, int n_systems,
+                          const cq_crowd_desc* desc, cq_crowd** out)
+{
+    if (!out) return fail(CQ_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!systems || !walkers_per_system || !desc) return fail(CQ_EINVAL, "NULL argument");
+    if (n_systems != 1) return fail(CQ_EINVAL, "this version runs crowds of one system");
+    const cq_system* s = systems[0];
+    if (!s) return fail(CQ_EINVAL, "system is NULL");
+    const int W = walkers_per_system[0];
+    if (W < 1) return fail(CQ_EINVAL, "need at least one walker");
+    if (desc->precision != CQ_FP64 && desc->precision != CQ_MIXED) return fail(CQ_EINVAL, "unknown precision");
+    if (!s->table[desc->precision == CQ_FP64 ? 1 : 0])
+        return fail(CQ_EINVAL, desc->precision == CQ_FP64 ? "system has no FP64 table" : "system has no FP32 table");
+    int K = desc->delay_rank == 0 ? std::min(32, s->n_up) : desc->delay_rank;
+    if (K < 1 || K > cq::kMaxDelay) return fail(CQ_EINVAL, "delay_rank must be 0..32");
+    if (desc->recompute_every < 0) return fail(CQ_EINVAL, "recompute_every must be >= 0");
+
+    cq_crowd* c = new (std::nothrow) cq_crowd();
+    if (!c) return fail(CQ_ENOMEM, "host allocation failed");
+    c->sys = s;
+    c->W = W;
+    c->n = s->n_up;
+    c->ne = 2 * s->n_up;
+    c->K = K;
+    c->prec = desc->precision;
+    c->recompute_every = desc->recompute_every;
+    c->use_graph = desc->use_graph;
+    c->seed = desc->seed;
+    c->first_uid = desc->first_uid;
+    if (desc->hip_stream) {
+        c->stream = (hipStream_t)desc->hip_stream;
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            return fail(CQ_EDEVICE, "hipStreamCreate failed");
+        }
+        c->own_stream = true;
+    }
+    const size_t es = c->prec == CQ_FP64 ? 8 : 4;
+    const size_t n = c->n, ne = c->ne;
+    constexpr int CHf = cq::chunk_orbitals<float>(), CHd = cq::chunk_orbitals<double>();
+    const int C = (int)((n + (es == 8 ? CHd : CHf) - 1) / (es == 8 ? CHd : CHf));
+    struct {
+        void** p;
+        size_t bytes;
+    } plan[] = {
+        {(void**)&c->R, sizeof(double) * W * ne * 3},
+        {&c->M, es * W * 2 * n * n},
+        {&c->VGL, es * W * 2 * n * 5 * n},
+        {(void**)&c->logdet, sizeof(double) * W * 2},
+        {(void**)&c->sign, sizeof(int) * W * 2},
+        {(void**)&c->nacc, sizeof(long long) * W},
+        {(void**)&c->nprop, sizeof(long long) * W},
+        {(void**)&c->eloc, sizeof(double) * W},
+        {(void**)&c->elpart, sizeof(double) * W * ne},
+        {(void**)&c->cnt, sizeof(int) * W},
+        {(void**)&c->welec, sizeof(int) * W * K},
+        {&c->stage, es * W * K * 5 * n},
+        {&c->Cbuf, es * W * K * n},
+        {(void**)&c->wrho, sizeof(double) * W * K},
+        {(void**)&c->wG, sizeof(double) * W * K * K},
+        {(void**)&c->beta, sizeof(double) * W * K},
+        {(void**)&c->pend, sizeof(int) * W},
+        {(void**)&c->part, sizeof(double) * W * C * cq::part_stride(K)},
+        {(void**)&c->rnew, sizeof(double) * W * 3},
+        {(void**)&c->uid, sizeof(uint32_t) * W},
+        {(void**)&c->prm, sizeof(cq::Params)},
+        {(void**)&c->status, sizeof(int) * W},
+        {(void**)&c->drift, sizeof(double) * W * 2},
+    };
+    for (auto& e : plan) {
+        cq_status st = dev_alloc(c, e.p, e.bytes);
+        if (st != CQ_OK) {
+            std::string msg = g_err;
+            cq_crowd_destroy(c);
+            return fail(st, msg);
+        }
+    }
+    const size_t invb = cq::inverse_work_bytes(2 * W, (int)n);
+    if (invb) {
+        const int nmat = 2 * W, b = cq::panel_width((int)n);
+        void *S, *PR, *piv, *la, *ng;
+        cq_status st = dev_alloc(c, &S, sizeof(double) * nmat * n * n);
+        if (st == CQ_OK) st = dev_alloc(c, &PR, sizeof(double) * nmat * b * n);
+        if (st == CQ_OK) st = dev_alloc(c, &piv, sizeof(int) * nmat * n * 2);
+        if (st == CQ_OK) st = dev_alloc(c, &la, sizeof(double) * nmat * 2);  // log|det| and max|A| per matrix
+        if (st == CQ_OK) st = dev_alloc(c, &ng, sizeof(int) * nmat * 2);
+        if (st != CQ_OK) {
+            std::string msg = g_err;
+            cq_crowd_destroy(c);
+            return fail(st, msg);
+        }
+        c->inv.S = (double*)S;
+        c->inv.PR = (double*)PR;
+        c->inv.pivrow = (int*)piv;
+        c->inv.logabs = (double*)la;
+        c->inv.negs = (int*)ng;
+        c->inv.b = b;
+    }
+    std::vector<uint32_t> uids(W);
+    for (int w = 0; w < W; ++w) uids[w] = desc->first_uid + (uint32_t)w;
+    hipError_t e = hipMemcpy(c->uid, uids.data(), sizeof(uint32_t) * W, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        cq_crowd_destroy(c);
+        return fail(CQ_EDEVICE, std::string("hipMemcpy uids: ") + hipGetErrorString(e));
+    }
+    c->hp = cq::Params{};
+    c->hp.sigma = 0.5;
+    e = hipMemcpy(c->prm, &c->hp, sizeof(cq::Params), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        cq_crowd_destroy(c);
+        return fail(CQ_EDEVICE, std::string("hipMemcpy params: ") + hipGetErrorString(e));
+    }
+    *out = c;
+    return CQ_OK;
+}
+
+cq_status cq_crowd_set_positions(cq_crowd* c, const double* R, int on_device, uint32_t first_step)
+{
+    if (!c || !R) return fail(CQ_EINVAL, "NULL argument");
+    const size_t bytes = sizeof(double) * c->W * c->ne * 3;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(hipMemcpy(c->R, R, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice));
+    c->hp.step = first_step;
+    c->hp.rec_sweep = 0;
+    cq_status st = push_params(c);
+    if (st != CQ_OK) return st;
+    c->ready = false;
+    c->since_recompute = 0;
+    st = c->prec == CQ_FP64 ? setup_state<double>(c) : setup_state<float>(c);
+    if (st != CQ_OK) return st;
+    c->ready = true;
+    return CQ_OK;
+}
+
+cq_status cq_crowd_run_vmc(cq_crowd* c, int n_sweeps, double sigma)
+{
+    if (!c) return fail(CQ_EINVAL, "crowd is NULL");
+    if (n_sweeps < 0 || !(sigma > 0.0) || !std::isfinite(sigma)) return fail(CQ_EINVAL, "bad n_sweeps or sigma");
+    if (!c->ready) return fail(CQ_ESTATE, "set positions before running");
+    if (sigma != c->hp.sigma) {
+        c->hp.sigma = sigma;
+        cq_status st = push_params(c);
+        if (st != CQ_OK) return st;
+    }
+    for (int s = 0; s < n_sweeps; ++s) {
+        if (c->use_graph && !c->timing_mask) {
+            if (!c->gexec) {
+                cq_status st = build_graph(c);
+                if (st != CQ_OK) return st;
+            }
+            HIP_TRY(hipGraphLaunch(c->gexec, c->stream));
+        } else {
+            sweep(c);
+        }
+        c->hp.step += 1;
+        c->hp.rec_sweep += 1;
+        if (c->recompute_every > 0 && ++c->since_recompute >= c->recompute_every) {
+            inverse(c);
+            c->since_recompute = 0;
+        }
+    }
+    HIP_TRY(hipGetLastError());
+    return CQ_OK;
+}
+
+cq_status cq_crowd_recompute(cq_crowd* c, double* max_drift)
+{
+    if (!c) return fail(CQ_EINVAL, "crowd is NULL");
+    if (!c->ready) return fail(CQ_ESTATE, "set positions before recomputing");
+    inverse(c);
+    HIP_TRY(hipGetLastError());
+    cq_status st = check_singular(c, "recompute");
+    if (st != CQ_OK) return st;
+    if (max_drift) {
+        std::vector<double> d(2 * c->W);
+        HIP_TRY(hipMemcpy(d.data(), c->drift, sizeof(double) * 2 * c->W, hipMemcpyDeviceToHost));
+        double m = 0.0;
+        for (double x : d) m = std::max(m, x);
+        *max_drift = m;
+    }
+    return CQ_OK;
+}
+
+static cq_status copy_out(cq_crowd* c, void* dst, const void* src, size_t bytes)
+{
+    if (!c) return fail(CQ_EINVAL, "crowd is NULL");
+    if (!dst) return CQ_OK;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost));
+    return CQ_OK;
+}
+
+cq_status cq_crowd_get_logdet(cq_crowd* c, double* logdet, int* sign)
+{
+    if (!c) return fail(CQ_EINVAL, "crowd is NULL");
+    cq_status st = copy_out(c, logdet, c->logdet, sizeof(double) * 2 * c->W);
+    if (st != CQ_OK) return st;
+    return copy_out(c, sign, c->sign, sizeof(int) * 2 * c->W);
+}
+
+cq_status cq_crowd_get_acceptance(cq_crowd* c, int64_t* accepted, int64_t* proposed)
+{
+    if (!c) return fail(CQ_EINVAL, "crowd is NULL");
+    cq_status st = copy_out(c, accepted, c->nacc, sizeof(int64_t) * c->W);
+    if (st != CQ_OK) return st;
+    return copy_out(c, proposed, c->nprop, sizeof(int64_t) * c->W);
+}
+
+cq_status cq_crowd_get_local_energy(cq_crowd* c, double* e_l)
+{
+    if (!c) return fail(CQ_EINVAL, "crowd is NULL");
+    return copy_out(c, e_l, c->eloc, sizeof(double) * c->W);
+}
+
+cq_status cq_crowd_get_positions(cq_crowd* c, double* R, int* n_walkers_per_system)
+{
+    if (!c) return fail(CQ_EINVAL, "crowd is NULL");
+    if (n_walkers_per_system) n_walkers_per_system[0] = c->W;
+    return copy_out(c, R, c->R, sizeof(double) * c->W * c->ne * 3);
+}
+
+cq_status cq_crowd_get_inverse(cq_crowd* c, double* ainv)
+{
+    if (!c) return fail(CQ_EINVAL, "crowd is NULL");
+    if (!ainv) return CQ_OK;
+    const size_t n = c->n, cnt = (size_t)c->W * 2 * n * n;
+    const size_t es = c->prec == CQ_FP64 ? 8 : 4;
+    std::vector<unsigned char> raw(cnt * es);
+    cq_status st = copy_out(c, raw.data(), c->M, cnt * es);
+    if (st != CQ_OK) return st;
+    for (size_t m = 0; m < (size_t)c->W * 2; ++m)
+        for (size_t i = 0; i < n; ++i)
+            for (size_t j = 0; j < n; ++j) {
+                const size_t src = (m * n + i) * n + j;  // M[i][j] = A^-1[j][i]
+                ainv[(m * n + j) * n + i] = es == 8 ? ((const double*)raw.data())[src]
+                                                    : (double)((const float*)raw.data())[src];
+            }
+    return CQ_OK;
+}
+
+cq_status cq_crowd_set_forced_decisions(cq_crowd* c, const uint8_t* flags, int n_sweeps)
+{
+    if (!c) return fail(CQ_EINVAL, "crowd is NULL");
+    if (flags && n_sweeps < 1) return fail(CQ_EINVAL, "n_sweeps must be >= 1");
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (c->forced) {
+        HIP_TRY(hipFree(c->forced));
+        c->forced = nullptr;
+    }
+    c->forced_cap = 0;
+    if (flags) {
+        const size_t bytes = (size_t)n_sweeps * c->ne * c->W;
+        if (hipMalloc((void**)&c->forced, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            c->forced = nullptr;
+            return fail(CQ_ENOMEM, "forced-decision buffer");
+        }
+        HIP_TRY(hipMemcpy(c->forced, flags, bytes, hipMemcpyHostToDevice));
+        c->forced_cap = n_sweeps;
+    }
+    c->hp.forced_cap = c->forced_cap;
+    c->hp.rec_sweep = 0;
+    drop_graph(c);
+    return push_params(c);
+}
+
+cq_status cq_crowd_record_moves(cq_crowd* c, int n_sweeps)
+{
+    if (!c) return fail(CQ_EINVAL, "crowd is NULL");
+    if (n_sweeps < 0) return fail(CQ_EINVAL, "n_sweeps must be >= 0");
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    for (void** p : {(void**)&c->rec_rho, (void**)&c->rec_dlnj, (void**)&c->rec_prob, (void**)&c->rec_acc})
+        if (*p) {
+            HIP_TRY(hipFree(*p));
+            *p = nullptr;
+        }
+    c->rec_cap = 0;
+    if (n_sweeps > 0) {
+        const size_t cnt = (size_t)n_sweeps * c->ne * c->W;
+        bool ok = hipMalloc((void**)&c->rec_rho, cnt * 8) == hipSuccess;
+        ok = ok && hipMalloc((void**)&c->rec_dlnj, cnt * 8) == hipSuccess;
+        ok = ok && hipMalloc((void**)&c->rec_prob, cnt * 8) == hipSuccess;
+        ok = ok && hipMalloc((void**)&c->rec_acc, cnt) == hipSuccess;
+        if (!ok) {
+            (void)hipGetLastError();
+            return fail(CQ_ENOMEM, "record buffers");
+        }
+        c->rec_cap = n_sweeps;
+    }
+    c->hp.rec_cap = c->rec_cap;
+    c->hp.rec_sweep = 0;
+    drop_graph(c);
+    return push_params(c);
+}
+
+cq_status cq_crowd_get_move_records(cq_crowd* c, double* rho, double* dlnj, double* prob, uint8_t* acc)
+{
+    if (!c) return fail(CQ_EINVAL, "crowd is NULL");
+    if (c->rec_cap == 0) return fail(CQ_ESTATE, "recording is off");
+    const size_t cnt = (size_t)c->rec_cap * c->ne * c->W;
+    cq_status st = copy_out(c, rho, c->rec_rho, cnt * 8);
+    if (st == CQ_OK) st = copy_out(c, dlnj, c->rec_dlnj, cnt * 8);
+    if (st == CQ_OK) st = copy_out(c, prob, c->rec_prob, cnt * 8);
+    if (st == CQ_OK) st = copy_out(c, acc, c->rec_acc, cnt);
+    return st;
+}
+
+cq_status cq_crowd_set_kernel_timing(cq_crowd* c, int kind_mask)
+{
+    if (!c) return fail(CQ_EINVAL, "crowd is NULL");
+    if (kind_mask < 0 || kind_mask >= (1 << CQ_KERNEL_COUNT)) return fail(CQ_EINVAL, "bad kernel kind mask");
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->timing_mask = kind_mask;
+    for (int k = 0; k < CQ_KERNEL_COUNT; ++k) c->ev_used[k] = 0;
+    return CQ_OK;
+}
+
+cq_status cq_crowd_get_kernel_timing(cq_crowd* c, int kind, double* total_ms, int64_t* launches)
+{
+    if (!c) return fail(CQ_EINVAL, "crowd is NULL");
+    if (kind < 0 || kind >= CQ_KERNEL_COUNT) return fail(CQ_EINVAL, "unknown kernel kind");
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    double tot = 0.0;
+    for (size_t i = 0; i < c->ev_used[kind]; ++i) {
+        float ms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, c->ev[kind][i].first, c->ev[kind][i].second));
+        tot += ms;
+    }
+    if (total_ms) *total_ms = tot;
+    if (launches) *launches = (int64_t)c->ev_used[kind];
+    return CQ_OK;
+}
+
+cq_status cq_device_copy(void* dst, const void* src, uint64_t bytes, void* hip_stream)
+{
+    if (!dst || !src || bytes % 16 || ((uintptr_t)dst | (uintptr_t)src) % 16)
+        return fail(CQ_EINVAL, "copy needs 16-byte aligned pointers and a multiple of 16 bytes");
+    cq::launch_copy(dst, src, (size_t)bytes, (hipStream_t)hip_stream);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize((hipStream_t)hip_stream));
+    return CQ_OK;
+}
+
+cq_status cq_crowd_synchronize(cq_crowd* c)
+{
+    if (!c) return fail(CQ_EINVAL, "crowd is NULL");
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(hipGetLastError());
+    return CQ_OK;
+}
+
+}  // extern "C"

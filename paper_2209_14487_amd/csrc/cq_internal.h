@@ -1,0 +1,113 @@
+// Internal declarations shared by the C ABI (capi.cpp) and the kernel files.
+//
+// Device layout of one crowd (W walkers, N electrons per spin, Ne = 2N,
+// T = float for the mixed path and double for the FP64 path, K = delay rank):
+//   R      double [W][Ne][3]          positions
+//   M      T      [W][2][N][N]        M[w][s][a][j] = (A_s^-1)[j][a]: row a is the
+//                                     inverse column of electron a, contiguous
+//   VGL    T      [W][2][N][5][N]     rows of A (value), grad x/y/z and Laplacian of
+//                                     every orbital j at electron a
+//   logdet double [W][2], sign int [W][2], nacc/nprop int64 [W], eloc double [W]
+//   window (accepted moves m = 0 .. cnt-1 of the current k proposals):
+//           welec int [W][K]    electron (within its spin) of move m
+//           stage T [W][K][5][N] orbital rows u_m (+ gradients, Laplacian) at r'_m;
+//                               slot cnt holds the pending proposal
+//           Cbuf  T [W][K][N]   inverse column c_m of electron e_m just before
+//                               move m (slot cnt: the old column, pending)
+//           wrho  double [W][K] determinant ratio of move m
+//           wG    double [W][K][K] wG[m][j] = u_m . c_j (j < m)
+//           beta  double [W][K], pend int [W]: coefficients of the last accepted
+//                               move, whose column still has to be brought up to date
+//   part   double [W][C][NP]          per-workgroup partial sums of one move
+//   rnew   double [W][3]              proposed position of the current move
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cq {
+
+constexpr int kMaxDelay = 32;
+constexpr int kBlock = 256;
+
+// Partial-sum slots of one move workgroup: 4 determinant dots, 5 per window
+// slot, then the Jastrow difference and gradient.
+__host__ __device__ constexpr int part_stride(int K) { return 4 + 5 * K + 4; }
+__host__ __device__ constexpr int part_j2(int K) { return 4 + 5 * K; }
+
+template <typename T>
+__host__ __device__ constexpr int chunk_orbitals() { return 64 * (16 / (int)sizeof(T)); }
+
+// Device-resident scalars read by every kernel, so that a captured sweep graph
+// stays valid from one sweep to the next.
+struct Params {
+    uint32_t step;       // Philox step of the current sweep
+    int32_t rec_sweep;   // index of the current sweep in the record / forced buffers
+    int32_t rec_cap;     // record capacity in sweeps (0 = off)
+    int32_t forced_cap;  // forced-decision capacity in sweeps (0 = off)
+    double sigma;        // VMC step
+    double tau;          // DMC time step
+};
+
+template <typename T>
+struct CrowdView {
+    int W, n, ne, K;
+    int G, n_orb;
+    double L;
+    const T* table;
+    double* R;
+    T* M;
+    T* VGL;
+    double* logdet;
+    int* sign;
+    long long* nacc;
+    long long* nprop;
+    double* eloc;
+    double* elpart;
+    int* cnt;
+    int* welec;
+    T* stage;
+    T* Cbuf;
+    double* wrho;
+    double* wG;
+    double* beta;
+    int* pend;
+    double* part;
+    double* rnew;
+    const uint32_t* uid;
+    uint64_t seed;
+    int use_j2;
+    double a_par, a_anti, b;
+    Params* prm;
+    double* rec_rho;
+    double* rec_dlnj;
+    double* rec_prob;
+    uint8_t* rec_acc;
+    const uint8_t* forced;
+    int* status;         // [W] 0 ok, 1 singular / not finite at the last inversion
+    double* drift;       // [W][2] |log|det| kept - recomputed| at the last inversion
+};
+
+// FP64 Gauss-Jordan workspace for matrices too large for LDS.
+struct InvWork {
+    double* S;        // [nmat][N][N]
+    double* PR;       // [nmat][b][N] pivot rows of the current panel (before the update)
+    int* pivrow;      // [nmat][N] pivot row of column k
+    double* logabs;   // [nmat] log|det|, followed by [nmat] max|A_ij| (as 64-bit patterns)
+    int* negs;        // [nmat] number of negative pivots
+    int b;            // panel width
+};
+
+template <typename T> void launch_fill_philox(T* table, uint64_t seed, size_t count, hipStream_t s);
+template <typename T> void launch_setup_vgl(const CrowdView<T>& v, hipStream_t s);
+template <typename T> void launch_vgl_move(const CrowdView<T>& v, int e, int reset, hipStream_t s);
+template <typename T> void launch_resolve(const CrowdView<T>& v, int e, int reset, hipStream_t s);
+template <typename T> void launch_finalize(const CrowdView<T>& v, hipStream_t s);
+template <typename T> void launch_flush(const CrowdView<T>& v, int spin, hipStream_t s);
+template <typename T> void launch_energy(const CrowdView<T>& v, hipStream_t s);
+template <typename T> void launch_inverse(const CrowdView<T>& v, const InvWork& wk, hipStream_t s);
+void launch_sweep_end(Params* prm, hipStream_t s);
+void launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
+size_t inverse_work_bytes(int nmat, int n);
+int panel_width(int n);  // columns per panel of the blocked inversion
+
+}  // namespace cq

@@ -1,0 +1,239 @@
+// Inverse update and local energy kernels.
+//
+// k_flush_vec   applies the accepted moves m = 0 .. cnt-1 of one window to the
+//               inverse in one read and one write of M = (A^-1)^T.  Move m
+//               replaced row e_m of A by u_m with ratio rho_m; c_m is the inverse
+//               column of e_m just before move m.  For every row a of M
+//               (a column of A^-1) the moves act in order as rank-1 updates:
+//                 p_m  = M[a] . u_m                        (rank-k product)
+//                 b_m  = (p_m - sum_{j<m} b_j (u_m . c_j) - delta(a, e_m)) / rho_m
+//                 M[a] -= sum_m b_m c_m                     (rank-k product)
+//               k = 1 is Sherman-Morrison; for k > 1 this is the Woodbury update
+//               with the k x k window matrix factorised in move order, which
+//               keeps the rounding of a sequence of Sherman-Morrison steps.
+//               Each wave keeps RPW rows in registers and streams the window rows.
+// k_energy_*    kinetic local energy (Alg. 1 L11):
+//                 E_L = -1/2 sum_i [l_i + lap_i U + |grad_i U|^2 + 2 g_i . grad_i U]
+//               g_i = sum_j grad phi_j(r_i) A^-1_ji is the dot of gradient row i
+//               with row i of M (likewise l_i); FP64 sums over electrons.
+#include "cq_device.h"
+#include "cq_internal.h"
+
+namespace cq {
+
+constexpr int kRowsPerWave = 4;
+constexpr int kRowsPerBlock = 4 * kRowsPerWave;
+
+template <typename T, int EPL>
+__global__ __launch_bounds__(kBlock) void k_flush_vec(CrowdView<T> v, int spin)
+{
+    constexpr int VEC = 16 / sizeof(T);
+    constexpr int NV = EPL / VEC;  // 16-byte vectors per lane per row
+    __shared__ double gG[kMaxDelay][kMaxDelay + 1];
+    __shared__ double grho[kMaxDelay];
+    __shared__ int wel[kMaxDelay];
+    __shared__ double pq[4][kRowsPerWave][kMaxDelay];
+    __shared__ double xs[4][kRowsPerWave][kMaxDelay];
+    const int n = v.n, K = v.K;
+    const int nstrip = (n + kRowsPerBlock - 1) / kRowsPerBlock;
+    int w, strip;
+    xcd_map(blockIdx.x, nstrip, w, strip);
+    if (w >= v.W) return;
+    const int cnt = v.cnt[w];
+    if (cnt == 0) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int i = tid; i < cnt * cnt; i += kBlock) {
+        const int r = i / cnt, c = i % cnt;
+        gG[r][c] = c < r ? v.wG[((size_t)w * K + r) * K + c] : 0.0;
+    }
+    if (tid < cnt) {
+        wel[tid] = v.welec[(size_t)w * K + tid];
+        grho[tid] = v.wrho[(size_t)w * K + tid];
+    }
+
+    // copy the accepted orbital rows of the window into the A, G, L rows
+    for (int mm = strip; mm < cnt; mm += nstrip) {
+        const int ea = v.welec[(size_t)w * K + mm];
+        const T* src = v.stage + ((size_t)w * K + mm) * 5 * (size_t)n;
+        T* dst = v.VGL + (((size_t)w * 2 + spin) * n + ea) * 5 * (size_t)n;
+        for (int i = tid; i < 5 * n; i += kBlock) dst[i] = src[i];
+    }
+    __syncthreads();
+
+    const int r0 = strip * kRowsPerBlock + wave * kRowsPerWave;
+    T* Mbase = v.M + ((size_t)w * 2 + spin) * n * (size_t)n;
+    T mr[kRowsPerWave][EPL];
+#pragma unroll
+    for (int q = 0; q < kRowsPerWave; ++q)
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            const int j = (i * 64 + lane) * VEC;
+            if (r0 + q < n && j < n) {
+                load16(Mbase + (size_t)(r0 + q) * n + j, &mr[q][i * VEC]);
+            } else {
+#pragma unroll
+                for (int t = 0; t < VEC; ++t) mr[q][i * VEC + t] = (T)0;
+            }
+        }
+    // p[q][m] = M[r] . u_m
+    for (int mm = 0; mm < cnt; ++mm) {
+        T u[EPL];
+        const T* up = v.stage + (((size_t)w * K + mm) * 5 + 0) * n;
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            const int j = (i * 64 + lane) * VEC;
+            if (j < n) {
+                load16(up + j, &u[i * VEC]);
+            } else {
+#pragma unroll
+                for (int t = 0; t < VEC; ++t) u[i * VEC + t] = (T)0;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kRowsPerWave; ++q) {
+            T s = (T)0;
+#pragma unroll
+            for (int i = 0; i < EPL; ++i) s += mr[q][i] * u[i];
+            s = wave_sum(s);
+            if (lane == 0) pq[wave][q][mm] = (double)s;
+        }
+    }
+    __syncthreads();
+    // b[q][m]: forward substitution in move order, one lane per row
+    if (lane < kRowsPerWave) {
+        const int q = lane, r = r0 + q;
+        for (int mm = 0; mm < cnt; ++mm) {
+            double t = pq[wave][q][mm] - (r == wel[mm] ? 1.0 : 0.0);
+            for (int j = 0; j < mm; ++j) t -= xs[wave][q][j] * gG[mm][j];
+            xs[wave][q][mm] = t / grho[mm];
+        }
+    }
+    __syncthreads();
+    // M[r] -= sum_m b[q][m] c_m
+    for (int mm = 0; mm < cnt; ++mm) {
+        T cm[EPL];
+        const T* cp = v.Cbuf + ((size_t)w * K + mm) * n;
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            const int j = (i * 64 + lane) * VEC;
+            if (j < n) {
+                load16(cp + j, &cm[i * VEC]);
+            } else {
+#pragma unroll
+                for (int t = 0; t < VEC; ++t) cm[i * VEC + t] = (T)0;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kRowsPerWave; ++q) {
+            const T x = (T)xs[wave][q][mm];
+#pragma unroll
+            for (int i = 0; i < EPL; ++i) mr[q][i] -= x * cm[i];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < kRowsPerWave; ++q)
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            const int j = (i * 64 + lane) * VEC;
+            if (r0 + q < n && j < n) store16(Mbase + (size_t)(r0 + q) * n + j, &mr[q][i * VEC]);
+        }
+}
+
+template <typename T>
+void launch_flush(const CrowdView<T>& v, int spin, hipStream_t s)
+{
+    constexpr int VEC = 16 / sizeof(T);
+    const int nstrip = (v.n + kRowsPerBlock - 1) / kRowsPerBlock;
+    const dim3 grid(xcd_grid(v.W, nstrip)), block(kBlock);
+    const int per_lane = (v.n + 63) / 64;
+    if (per_lane <= VEC)
+        hipLaunchKernelGGL((k_flush_vec<T, VEC>), grid, block, 0, s, v, spin);
+    else if (per_lane <= 4)
+        hipLaunchKernelGGL((k_flush_vec<T, 4>), grid, block, 0, s, v, spin);
+    else if (per_lane <= 8)
+        hipLaunchKernelGGL((k_flush_vec<T, 8>), grid, block, 0, s, v, spin);
+    else if (per_lane <= 16)
+        hipLaunchKernelGGL((k_flush_vec<T, 16>), grid, block, 0, s, v, spin);
+    else
+        hipLaunchKernelGGL((k_flush_vec<T, 32>), grid, block, 0, s, v, spin);
+}
+
+// One wave per (walker, electron): this electron's contribution to sum_i [...]
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_energy_rows(CrowdView<T> v)
+{
+    constexpr int VEC = 16 / sizeof(T);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const long long gw = (long long)blockIdx.x * 4 + wave;
+    if (gw >= (long long)v.W * v.ne) return;
+    const int w = (int)(gw / v.ne), e = (int)(gw % v.ne);
+    const int n = v.n, spin = e >= n, a = e - spin * n;
+    const T* mrow = v.M + (((size_t)w * 2 + spin) * n + a) * (size_t)n;
+    const T* vg = v.VGL + (((size_t)w * 2 + spin) * n + a) * 5 * (size_t)n;
+    T s[4] = {(T)0, (T)0, (T)0, (T)0};
+    for (int j = lane * VEC; j < n; j += 64 * VEC) {
+        T m[VEC], x[VEC];
+        load16(mrow + j, m);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            load16(vg + (size_t)(k + 1) * n + j, x);
+#pragma unroll
+            for (int i = 0; i < VEC; ++i) s[k] += x[i] * m[i];
+        }
+    }
+    double g[3], l;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) g[k] = (double)wave_sum(s[k]);
+    l = (double)wave_sum(s[3]);
+    double gu[3] = {0.0, 0.0, 0.0}, lu = 0.0;
+    if (v.use_j2) {
+        const double* re = v.R + ((size_t)w * v.ne + e) * 3;
+        for (int m = lane; m < v.ne; m += 64) {
+            if (m == e) continue;
+            const double aa = ((m >= n) == (spin != 0)) ? v.a_par : v.a_anti;
+            double d[3], u, du, d2u;
+            min_image(re, v.R + ((size_t)w * v.ne + m) * 3, v.L, d);
+            const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            pade(aa, v.b, r, u, du, d2u);
+            const double f = du / r;
+            gu[0] += f * d[0];
+            gu[1] += f * d[1];
+            gu[2] += f * d[2];
+            lu += d2u + 2.0 * f;
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) gu[k] = wave_sum(gu[k]);
+        lu = wave_sum(lu);
+    }
+    if (lane == 0)
+        v.elpart[gw] = l + lu + gu[0] * gu[0] + gu[1] * gu[1] + gu[2] * gu[2]
+                       + 2.0 * (g[0] * gu[0] + g[1] * gu[1] + g[2] * gu[2]);
+}
+
+// Fixed-order FP64 sum over electrons: one wave per walker.
+__global__ __launch_bounds__(kBlock) void k_energy_sum(const double* __restrict__ elpart, double* __restrict__ eloc,
+                                                       int W, int ne)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int w = blockIdx.x * 4 + wave;
+    if (w >= W) return;
+    double s = 0.0;
+    for (int e = lane; e < ne; e += 64) s += elpart[(size_t)w * ne + e];
+    s = wave_sum(s);
+    if (lane == 0) eloc[w] = -0.5 * s;
+}
+
+template <typename T>
+void launch_energy(const CrowdView<T>& v, hipStream_t s)
+{
+    const long long waves = (long long)v.W * v.ne;
+    hipLaunchKernelGGL(k_energy_rows<T>, dim3((unsigned)((waves + 3) / 4)), dim3(kBlock), 0, s, v);
+    hipLaunchKernelGGL(k_energy_sum, dim3((v.W + 3) / 4), dim3(kBlock), 0, s, v.elpart, v.eloc, v.W, v.ne);
+}
+
+template void launch_flush<float>(const CrowdView<float>&, int, hipStream_t);
+template void launch_flush<double>(const CrowdView<double>&, int, hipStream_t);
+template void launch_energy<float>(const CrowdView<float>&, hipStream_t);
+template void launch_energy<double>(const CrowdView<double>&, hipStream_t);
+
+}  // namespace cq

@@ -1,0 +1,278 @@
+"""GPU parity of the batched particle-by-particle VMC move against the FP64 CPU oracle.
+
+Every test calls the HIP library through the C ABI (paper_2209_14487_amd) and
+compares with ``oracle`` on the same seeded inputs and random streams.
+
+Tolerances: FP64 path, ratios / log|det| / E_L within 1e-10 relative and identical
+accept/reject decisions except at near-ties |P - u| < 1e-6.  Mixed path (FP32
+table, FP32 inverse), run in forced-decision mode on the oracle's trajectory:
+relative ratio error median <= 1e-5 and 99th percentile <= 1e-4 (2e-4 at N = 256)
+over moves with |rho| >= 0.1 (the relative error of any FP32 dot product is unbounded as rho -> 0);
+the maximum is reported and bounded at 5e-3.  A CPU emulation of the same chain
+with the inverse stored in FP32 (FP64 everywhere else) shows a tail of the same
+size (99.9th percentile ~1e-4, max ~3e-4 over 20 walkers x 6 sweeps at N = 32),
+so the tail is the cost of an FP32 inverse on these cond(A) ~ 100 matrices, not of
+the kernels.  log|det| within 1e-4 of max(1, |log|det||).
+"""
+import numpy as np
+import pytest
+
+import oracle as orc
+import paper_2209_14487_amd as cq
+from synth import J2_A_ANTI, J2_A_PAR, J2_B, planewave_table, start_positions
+
+pytestmark = pytest.mark.gpu
+
+NEAR_TIE = 1e-6
+
+
+def make_pair(n, L, G, move_seed, table=None, coef_seed=None, j2=True, fp64=True, fp32=False):
+    """The same system on both sides: GPU cq.System and oracle System."""
+    g = cq.System(n, L)
+    if table is not None:
+        if fp64:
+            g.load_table(np.asarray(table, np.float64))
+        if fp32:
+            g.load_table(np.asarray(table, np.float32))
+        o = orc.System(n, n, L, G=G, n_orb=n, orb_kind=orc.ORB_TABLE, table=table, use_j2=j2, seed=move_seed)
+    else:
+        if fp64:
+            g.fill_philox(coef_seed, 8, G)
+        if fp32:
+            g.fill_philox(coef_seed, 4, G)
+        o = orc.System(n, n, L, G=G, n_orb=n, orb_kind=orc.ORB_SEEDED, coef_seed=coef_seed, use_j2=j2,
+                       seed=move_seed)
+    if j2:
+        g.load_j2(J2_A_PAR, J2_A_ANTI, J2_B)
+        o.j2_a_par, o.j2_a_anti, o.j2_b = J2_A_PAR, J2_A_ANTI, J2_B
+    return g, o
+
+
+def run_gpu(crowd, R0, sweeps, sigma, first_step=0, forced=None):
+    crowd.set_positions(R0, first_step)
+    crowd.record(sweeps)
+    if forced is not None:
+        crowd.set_forced(forced)
+    ld = np.zeros((sweeps, crowd.W, 2))
+    sg = np.zeros((sweeps, crowd.W, 2), np.int32)
+    el = np.zeros((sweeps, crowd.W))
+    for s in range(sweeps):
+        crowd.run_vmc(1, sigma)
+        ld[s], sg[s] = crowd.logdet()
+        el[s] = crowd.local_energy()
+    rec = crowd.records()
+    rec.update(logdet=ld, sign=sg, eloc=el, R=crowd.positions())
+    return rec
+
+
+def mixed_ratio_check(gpu_rho, ref_rho, label, p99_bound=1e-4):
+    err = np.abs(gpu_rho - ref_rho)
+    rel = err / np.abs(ref_rho)
+    big = np.abs(ref_rho) >= 0.1
+    stats = dict(median=float(np.median(rel)), p99=float(np.quantile(rel[big], 0.99)),
+                 p999=float(np.quantile(rel[big], 0.999)), max_big=float(rel[big].max()),
+                 max_all=float(rel.max()))
+    print("%s: ratio rel err %s" % (label, " ".join("%s=%.2e" % kv for kv in stats.items())))
+    assert stats["median"] <= 1e-5, stats
+    assert stats["p99"] <= p99_bound, stats
+    assert stats["max_big"] <= 5e-3, stats
+    return stats
+
+
+def first_divergence(acc_a, acc_b):
+    """Per walker: flat (sweep, electron) index of the first differing decision, or None."""
+    S, ne, W = acc_a.shape
+    out = []
+    for w in range(W):
+        d = np.nonzero(acc_a[:, :, w].ravel() != acc_b[:, :, w].ravel())[0]
+        out.append(int(d[0]) if len(d) else None)
+    return out
+
+
+def compare_fp64(gpu, ref, sweeps, ne, tol=1e-10):
+    div = first_divergence(gpu["acc"], ref.acc)
+    W = len(div)
+    n_div = 0
+    for w, d in enumerate(div):
+        lim = sweeps * ne if d is None else d
+        if d is not None:
+            n_div += 1
+            s, e = divmod(d, ne)
+            assert abs(ref.prob[s, e, w] - ref.u[s, e, w]) < NEAR_TIE, "decision differs away from a near-tie"
+        for key in ("rho", "dlnj", "prob"):
+            a = gpu[key][:, :, w].ravel()[:lim]
+            b = getattr(ref, key)[:, :, w].ravel()[:lim]
+            assert np.all(np.abs(a - b) <= tol * np.maximum(1.0, np.abs(b))), key
+        full = lim // ne  # sweeps completed before any divergence
+        if full:
+            a, b = gpu["logdet"][:full, w], ref.logdet[:full, w]
+            assert np.all(np.abs(a - b) <= tol * np.maximum(1.0, np.abs(b)))
+            assert np.array_equal(gpu["sign"][:full, w], ref.sign[:full, w])
+            a, b = gpu["eloc"][:full, w], ref.eloc[:full, w]
+            assert np.all(np.abs(a - b) <= tol * np.maximum(1.0, np.abs(b)))
+    assert n_div <= max(1, W // 20)
+    return div
+
+
+def test_c1_fp64_sherman_morrison_matches_oracle():
+    """C1: 4+4 electrons, L=5, 16^3 plane-wave spline, 16 walkers, 200 sweeps, FP64, SM."""
+    n, L, G, W, S = 4, 5.0, 16, 16, 200
+    g, o = make_pair(n, L, G, 1001, table=planewave_table(G, L), j2=False)
+    R0 = start_positions(1001, W, 2 * n, L)
+    crowd = cq.Crowd(g, W, precision="fp64", delay_rank=1, seed=1001)
+    gpu = run_gpu(crowd, R0, S, 0.5)
+    ref = orc.vmc(o, R0, S, sigma=0.5)
+    div = compare_fp64(gpu, ref, S, 2 * n)
+    # E_L equals 12 pi^2 / 25 up to the O(h^2) spline error (about 1 % at G = 16)
+    e0 = 12 * np.pi ** 2 / 25
+    assert np.all(np.abs(gpu["eloc"] / e0 - 1) < 0.05)
+    assert 0.2 < gpu["acc"].mean() < 0.95
+    if all(d is None for d in div):
+        assert np.allclose(gpu["R"], ref.R, atol=1e-12)
+    crowd.close()
+
+
+@pytest.mark.parametrize("k", [1, 4, 8, 32])
+def test_c2_shape_fp64_delayed_ranks_match_oracle(k):
+    """C2 shapes (32+32, L=10, 48^3 seeded table, Pade J2) on 61 walkers (ragged against the
+    8-XCD mapping): Sherman-Morrison and rank-k delayed updates reproduce the oracle chain."""
+    n, L, G, W, S = 32, 10.0, 48, 61, 4
+    g, o = make_pair(n, L, G, 1002, coef_seed=1002)
+    R0 = start_positions(1002, W, 2 * n, L)
+    crowd = cq.Crowd(g, W, precision="fp64", delay_rank=k, seed=1002)
+    gpu = run_gpu(crowd, R0, S, 0.5)
+    ref = orc.vmc(o, R0, S, sigma=0.5, want_ainv=True)
+    div = compare_fp64(gpu, ref, S, 2 * n)
+    ok = [w for w, d in enumerate(div) if d is None]
+    inv = crowd.inverse()
+    for w in ok:
+        assert np.abs(inv[w] - ref.ainv[w]).max() <= 1e-9 * np.abs(ref.ainv[w]).max()
+    crowd.close()
+
+
+@pytest.mark.parametrize("k,recompute", [(1, 2), (8, 2), (32, 0)])
+def test_c2_mixed_precision_on_oracle_trajectory(k, recompute):
+    """C2 mixed precision (FP32 table, FP32 inverse and dots, FP64 log|det| and sums) follows
+    the oracle's decisions; its own ratios stay within 1e-4 relative of the FP64 oracle, its
+    own decisions differ only where |P - u| is within that error, and log|det| stays within
+    1e-4 of max(1, |log|det||) across periodic FP64 recomputes."""
+    n, L, G, W, S = 32, 10.0, 48, 40, 6
+    g, o = make_pair(n, L, G, 1002, coef_seed=1002, fp64=False, fp32=True)
+    R0 = start_positions(1002, W, 2 * n, L)
+    ref = orc.vmc(o, R0, S, sigma=0.5)
+    crowd = cq.Crowd(g, W, precision="mixed", delay_rank=k, recompute_every=recompute, seed=1002)
+    gpu = run_gpu(crowd, R0, S, 0.5, forced=ref.acc)
+    mixed_ratio_check(gpu["rho"], ref.rho, "C2 mixed k=%d recompute=%d" % (k, recompute))
+    # its own decisions differ from the oracle's only where P and u are within the error
+    own = gpu["prob"] > ref.u
+    mism = own != ref.acc.astype(bool)
+    gap = np.abs(ref.prob[mism] - ref.u[mism]) / np.maximum(ref.prob[mism], 1e-300)
+    print("   own decisions differing: %d of %d, max |P-u|/P there %.2e"
+          % (mism.sum(), mism.size, gap.max() if mism.any() else 0.0))
+    assert mism.sum() <= 1e-3 * mism.size
+    assert np.all(gap <= 1e-2)
+    err = np.abs(gpu["logdet"] - ref.logdet) / np.maximum(1.0, np.abs(ref.logdet))
+    eerr = np.abs(gpu["eloc"] - ref.eloc) / np.maximum(1.0, np.abs(ref.eloc))
+    print("   log|det| max err %.2e, E_L max rel err %.2e (median %.2e)" % (err.max(), eerr.max(), np.median(eerr)))
+    assert err.max() < 1e-4, err.max()
+    assert np.array_equal(gpu["sign"], ref.sign)
+    assert np.median(eerr) < 1e-5 and eerr.max() < 1e-2
+    assert np.allclose(gpu["R"], ref.R, atol=1e-12)
+    crowd.close()
+
+
+def test_crowd_partition_is_bit_identical():
+    """Splitting the walkers into crowds changes nothing (paper Sec. III: crowd size 1 is the
+    per-walker driver, one crowd is the whole-population batch): FP64 results per walker are
+    bit-identical for 1 x 24, 8 + 16 and 24 x 1 walkers."""
+    n, L, G, W, S = 32, 10.0, 48, 24, 2
+    g, _ = make_pair(n, L, G, 7, coef_seed=1002)
+    R0 = start_positions(1002, W, 2 * n, L)
+
+    def run(parts):
+        out_R, out_ld, out_el = [], [], []
+        lo = 0
+        for p in parts:
+            c = cq.Crowd(g, p, precision="fp64", delay_rank=4, seed=7, first_uid=lo)
+            c.set_positions(R0[lo:lo + p])
+            c.run_vmc(S, 0.5)
+            out_R.append(c.positions())
+            out_ld.append(c.logdet()[0])
+            out_el.append(c.local_energy())
+            c.close()
+            lo += p
+        return np.concatenate(out_R), np.concatenate(out_ld), np.concatenate(out_el)
+
+    a = run([24])
+    b = run([8, 16])
+    c = run([1] * 24)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    for x, y in zip(a, c):
+        assert np.array_equal(x, y)
+
+
+def test_graph_replay_equals_eager_launches():
+    """The sweep captured once as a hipGraph and replayed gives the eager result bit for bit."""
+    n, L, G, W, S = 32, 10.0, 48, 16, 3
+    g, _ = make_pair(n, L, G, 9, coef_seed=1002, fp64=False, fp32=True)
+    R0 = start_positions(1002, W, 2 * n, L)
+    res = []
+    for use_graph in (False, True):
+        c = cq.Crowd(g, W, precision="mixed", delay_rank=8, recompute_every=2, seed=9, use_graph=use_graph)
+        c.set_positions(R0)
+        for _ in range(S):
+            c.run_vmc(1, 0.5)
+            c.synchronize()
+        res.append((c.positions(), c.logdet()[0], c.local_energy(), c.acceptance()[0]))
+        c.close()
+    for x, y in zip(*res):
+        assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("precision,k", [("fp64", 1), ("fp64", 16), ("mixed", 32)])
+def test_n256_blocked_inverse_and_multichunk_sweep(precision, k):
+    """C3 system size (256+256, L=20, 64^3): blocked FP64 Gauss-Jordan set-up, multi-workgroup
+    orbital chunks and one full sweep, on 3 walkers."""
+    n, L, G, W, S = 256, 20.0, 64, 3, 1
+    g, o = make_pair(n, L, G, 1003, coef_seed=1003, fp64=precision == "fp64", fp32=precision == "mixed")
+    R0 = start_positions(1003, W, 2 * n, L)
+    ld0, sg0, el0, ai0 = orc.setup(o, R0)
+    crowd = cq.Crowd(g, W, precision=precision, delay_rank=k, seed=1003)
+    crowd.set_positions(R0)
+    ld, sg = crowd.logdet()
+    tol = 1e-10 if precision == "fp64" else 1e-4
+    assert np.all(np.abs(ld - ld0) <= tol * np.maximum(1, np.abs(ld0)))
+    assert np.array_equal(sg, sg0)
+    inv = crowd.inverse()
+    itol = 1e-9 if precision == "fp64" else 2e-3
+    for w in range(W):
+        assert np.abs(inv[w] - ai0[w]).max() <= itol * np.abs(ai0[w]).max()
+    el = crowd.local_energy()
+    assert np.all(np.abs(el - el0) <= (1e-9 if precision == "fp64" else 1e-3) * np.maximum(1, np.abs(el0)))
+    ref = orc.vmc(o, R0, S, sigma=0.5)
+    if precision == "fp64":
+        gpu = run_gpu(crowd, R0, S, 0.5)
+        compare_fp64(gpu, ref, S, 2 * n)
+    else:
+        gpu = run_gpu(crowd, R0, S, 0.5, forced=ref.acc)
+        # FP32 rounding of N-term dots and of the stored inverse grows with N: twice the N=32 bound
+        mixed_ratio_check(gpu["rho"], ref.rho, "N=256 mixed k=%d" % k, p99_bound=2e-4)
+    crowd.close()
+
+
+def test_singular_start_is_reported():
+    """Two same-spin electrons at one position make A singular: CQ_ESINGULAR names the walker."""
+    n, L, G, W = 4, 5.0, 16, 3
+    g, _ = make_pair(n, L, G, 1, table=planewave_table(G, L), j2=False)
+    R0 = start_positions(1001, W, 2 * n, L)
+    R0[1, 2] = R0[1, 0]
+    crowd = cq.Crowd(g, W, precision="fp64", seed=1)
+    with pytest.raises(cq.CqError) as ei:
+        crowd.set_positions(R0)
+    assert ei.value.status == cq.CQ_ESINGULAR
+    assert "walker 1" in str(ei.value)
+    with pytest.raises(cq.CqError) as ei:
+        crowd.run_vmc(1, 0.5)
+    assert ei.value.status == cq.CQ_ESTATE
+    crowd.close()
