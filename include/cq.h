@@ -54,13 +54,27 @@ typedef enum { CQ_FP64 = 0, CQ_MIXED = 1 } cq_precision;
 
 /* Kernel classes whose device time can be measured with cq_crowd_get_kernel_timing. */
 typedef enum {
-    CQ_KERNEL_VGL = 0,      /* propose + B-spline VGL + ratio partial dots + Jastrow partials */
-    CQ_KERNEL_RESOLVE = 1,  /* ratio, Metropolis decision, window bookkeeping */
+    CQ_KERNEL_VGL = 0,      /* per move: B-spline VGL at the proposal, ratio and Jastrow partial sums,
+                               fused with the previous move's decision */
+    CQ_KERNEL_RESOLVE = 1,  /* end of a window: decision of its last move */
     CQ_KERNEL_UPDATE = 2,   /* Sherman-Morrison / delayed rank-k inverse update */
     CQ_KERNEL_ENERGY = 3,   /* local energy */
     CQ_KERNEL_INVERSE = 4,  /* FP64 Gauss-Jordan inversion (initial and periodic recompute) */
     CQ_KERNEL_COUNT = 5
 } cq_kernel_kind;
+
+/* Mapping of the moves to the GPU.  Both compute the same Markov chain; their
+   sums are grouped differently, so results agree to rounding, and each path is
+   bit-reproducible on its own (independent of how walkers form crowds).
+   CQ_PATH_MULTI:   one kernel launch per move, several workgroups per walker (one
+                    per chunk of orbitals), the previous move decided inside the
+                    next launch; uses every CU even for few walkers.
+   CQ_PATH_WINDOW:  one workgroup per walker runs all k moves of an update window
+                    in one launch (decisions and window bookkeeping stay in the
+                    workgroup); far fewer launches, one CU per walker.
+   CQ_PATH_AUTO:    CQ_PATH_WINDOW when the crowd has at least 64 walkers, else
+                    CQ_PATH_MULTI. */
+typedef enum { CQ_PATH_AUTO = 0, CQ_PATH_MULTI = 1, CQ_PATH_WINDOW = 2 } cq_kernel_path;
 
 typedef struct cq_system cq_system;  /* orbitals + Jastrow + box + electron counts (opaque) */
 typedef struct cq_crowd cq_crowd;    /* walkers moved in lock-step (opaque) */
@@ -107,6 +121,7 @@ typedef struct {
     uint32_t first_uid;   /* walker w of this crowd has uid first_uid + w (random streams) */
     void* hip_stream;     /* borrowed hipStream_t to run on, or NULL: the crowd makes its own */
     int use_graph;        /* 1: capture one sweep as a hipGraph and replay it */
+    int kernel_path;      /* how the moves are mapped to the GPU (cq_kernel_path) */
 } cq_crowd_desc;
 
 /* Create a crowd of walkers_per_system[s] walkers of each system s.  This

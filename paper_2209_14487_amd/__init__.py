@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libcrowdqmc.so")
 
 CQ_OK, CQ_EINVAL, CQ_ENOMEM, CQ_EDEVICE, CQ_ESINGULAR, CQ_ESTATE = range(6)
 CQ_FP64, CQ_MIXED = 0, 1
+PATHS = {"auto": 0, "multi": 1, "window": 2}
 KERNEL_VGL, KERNEL_RESOLVE, KERNEL_UPDATE, KERNEL_ENERGY, KERNEL_INVERSE = range(5)
 KERNEL_NAMES = {"vgl": KERNEL_VGL, "resolve": KERNEL_RESOLVE, "update": KERNEL_UPDATE,
                 "energy": KERNEL_ENERGY, "inverse": KERNEL_INVERSE}
@@ -36,7 +37,7 @@ class CqError(RuntimeError):
 class CrowdDesc(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("delay_rank", ctypes.c_int), ("recompute_every", ctypes.c_int),
                 ("seed", ctypes.c_uint64), ("first_uid", ctypes.c_uint32), ("hip_stream", ctypes.c_void_p),
-                ("use_graph", ctypes.c_int)]
+                ("use_graph", ctypes.c_int), ("kernel_path", ctypes.c_int)]
 
 
 _lib = None
@@ -169,13 +170,13 @@ class Crowd:
 
     def __init__(self, system: System, n_walkers: int, precision: str = "mixed", delay_rank: int = 1,
                  recompute_every: int = 0, seed: int = 0, first_uid: int = 0, stream=None,
-                 use_graph: bool = True):
+                 use_graph: bool = True, path: str = "auto"):
         self.system = system
         self.W = n_walkers
         self.n = system.n
         self.ne = 2 * system.n
         desc = CrowdDesc(CQ_MIXED if precision == "mixed" else CQ_FP64, delay_rank, recompute_every, seed,
-                         first_uid, _stream_handle(stream), int(use_graph))
+                         first_uid, _stream_handle(stream), int(use_graph), PATHS[path])
         systems = (ctypes.c_void_p * 1)(system._h.value)
         counts = (ctypes.c_int * 1)(n_walkers)
         h = ctypes.c_void_p()

@@ -4,7 +4,8 @@
 //
 // One sweep (paper Alg. 1 L4-L11 over all walkers of the crowd in lock-step,
 // the batched form of Alg. 3/4) is, for e = 0 .. Ne-1:
-//   k_vgl_move(e)  -> k_resolve(e)  [-> k_flush(spin) at the end of a window]
+//   k_move(e, resolving e-1)  [-> k_move(resolve e only) -> k_flush(spin) at the
+//   end of a window]
 // then the local energy and the step counter.  Windows cover k consecutive
 // electrons of one spin and never span spins or sweeps.
 #include <hip/hip_runtime.h>
@@ -51,6 +52,7 @@ struct cq_system {
 struct cq_crowd {
     const cq_system* sys = nullptr;
     int W = 0, n = 0, ne = 0, K = 1, prec = CQ_MIXED, recompute_every = 0, use_graph = 0;
+    int path = CQ_PATH_WINDOW;
     uint64_t seed = 0;
     uint32_t first_uid = 0;
     hipStream_t stream = nullptr;
@@ -188,18 +190,34 @@ void enqueue_sweep(cq_crowd* c)
 {
     const cq::CrowdView<T> v = view<T>(c);
     const int n = c->n, K = c->K;
+    if (c->path == CQ_PATH_WINDOW) {
+        for (int spin = 0; spin < 2; ++spin)
+            for (int a0 = 0; a0 < n; a0 += K) {
+                timed_begin(c, CQ_KERNEL_VGL);
+                cq::launch_window<T>(v, spin * n + a0, std::min(K, n - a0), c->stream);
+                timed_end(c, CQ_KERNEL_VGL);
+                timed_begin(c, CQ_KERNEL_UPDATE);
+                cq::launch_flush<T>(v, spin, c->stream);
+                timed_end(c, CQ_KERNEL_UPDATE);
+            }
+        timed_begin(c, CQ_KERNEL_ENERGY);
+        cq::launch_energy<T>(v, c->stream);
+        timed_end(c, CQ_KERNEL_ENERGY);
+        cq::launch_sweep_end(c->prm, c->stream);
+        return;
+    }
     for (int e = 0; e < c->ne; ++e) {
         const int spin = e / n, a = e % n;
         const int reset = (a % K) == 0;
         timed_begin(c, CQ_KERNEL_VGL);
-        cq::launch_vgl_move<T>(v, e, reset, c->stream);
+        cq::launch_move<T>(v, e, reset ? -1 : e - 1, reset, c->stream);
         timed_end(c, CQ_KERNEL_VGL);
-        timed_begin(c, CQ_KERNEL_RESOLVE);
-        cq::launch_resolve<T>(v, e, reset, c->stream);
-        timed_end(c, CQ_KERNEL_RESOLVE);
         if ((a + 1) % K == 0 || a == n - 1) {
+            // end of the window: decide its last move, then apply the window
+            timed_begin(c, CQ_KERNEL_RESOLVE);
+            cq::launch_move<T>(v, -1, e, 0, c->stream);
+            timed_end(c, CQ_KERNEL_RESOLVE);
             timed_begin(c, CQ_KERNEL_UPDATE);
-            if (K > 1) cq::launch_finalize<T>(v, c->stream);
             cq::launch_flush<T>(v, spin, c->stream);
             timed_end(c, CQ_KERNEL_UPDATE);
         }
@@ -270,9 +288,14 @@ cq_status check_singular(cq_crowd* c, const char* where)
     std::vector<int> st(c->W);
     HIP_TRY(hipStreamSynchronize(c->stream));
     HIP_TRY(hipMemcpy(st.data(), c->status, sizeof(int) * c->W, hipMemcpyDeviceToHost));
-    for (int w = 0; w < c->W; ++w)
-        if (st[w]) return fail(CQ_ESINGULAR, std::string(where) + ": Slater matrix of walker " + std::to_string(w) +
-                                                 " is singular or not finite");
+    for (int w = 0; w < c->W; ++w) {
+        if (st[w] & 2)
+            return fail(CQ_ESTATE, std::string(where) + ": update-window bookkeeping out of range for walker " +
+                                       std::to_string(w) + " (internal error)");
+        if (st[w] & 1)
+            return fail(CQ_ESINGULAR, std::string(where) + ": Slater matrix of walker " + std::to_string(w) +
+                                          " is singular or not finite");
+    }
     return CQ_OK;
 }
 
@@ -284,8 +307,12 @@ cq_status setup_state(cq_crowd* c)
     HIP_TRY(hipMemsetAsync(c->sign, 0, sizeof(int) * 2 * c->W, c->stream));
     HIP_TRY(hipMemsetAsync(c->nacc, 0, sizeof(long long) * c->W, c->stream));
     HIP_TRY(hipMemsetAsync(c->nprop, 0, sizeof(long long) * c->W, c->stream));
-    HIP_TRY(hipMemsetAsync(c->cnt, 0, sizeof(int) * c->W, c->stream));
-    HIP_TRY(hipMemsetAsync(c->pend, 0xFF, sizeof(int) * c->W, c->stream));
+    HIP_TRY(hipMemsetAsync(c->cnt, 0, sizeof(int) * 3 * c->W, c->stream));
+    HIP_TRY(hipMemsetAsync(c->welec, 0, sizeof(int) * c->W * c->K, c->stream));
+    // window slots are read (masked) before they are first written: start them at 0
+    const size_t es = c->prec == CQ_FP64 ? 8 : 4;
+    HIP_TRY(hipMemsetAsync(c->stage, 0, es * c->W * c->K * 5 * c->n, c->stream));
+    HIP_TRY(hipMemsetAsync(c->Cbuf, 0, es * c->W * c->K * c->n, c->stream));
     HIP_TRY(hipMemsetAsync(c->status, 0, sizeof(int) * c->W, c->stream));
     cq::launch_setup_vgl<T>(v, c->stream);
     HIP_TRY(hipGetLastError());
@@ -451,6 +478,8 @@ cq_status cq_crowd_create(const cq_system* const* systems, const int* walkers_pe
     int K = desc->delay_rank == 0 ? std::min(32, s->n_up) : desc->delay_rank;
     if (K < 1 || K > cq::kMaxDelay) return fail(CQ_EINVAL, "delay_rank must be 0..32");
     if (desc->recompute_every < 0) return fail(CQ_EINVAL, "recompute_every must be >= 0");
+    if (desc->kernel_path < CQ_PATH_AUTO || desc->kernel_path > CQ_PATH_WINDOW)
+        return fail(CQ_EINVAL, "unknown kernel_path");
 
     cq_crowd* c = new (std::nothrow) cq_crowd();
     if (!c) return fail(CQ_ENOMEM, "host allocation failed");
@@ -462,6 +491,7 @@ cq_status cq_crowd_create(const cq_system* const* systems, const int* walkers_pe
     c->prec = desc->precision;
     c->recompute_every = desc->recompute_every;
     c->use_graph = desc->use_graph;
+    c->path = desc->kernel_path != CQ_PATH_AUTO ? desc->kernel_path : (W >= 64 ? CQ_PATH_WINDOW : CQ_PATH_MULTI);
     c->seed = desc->seed;
     c->first_uid = desc->first_uid;
     if (desc->hip_stream) {
@@ -490,7 +520,7 @@ cq_status cq_crowd_create(const cq_system* const* systems, const int* walkers_pe
         {(void**)&c->nprop, sizeof(long long) * W},
         {(void**)&c->eloc, sizeof(double) * W},
         {(void**)&c->elpart, sizeof(double) * W * ne},
-        {(void**)&c->cnt, sizeof(int) * W},
+        {(void**)&c->cnt, sizeof(int) * 3 * W},
         {(void**)&c->welec, sizeof(int) * W * K},
         {&c->stage, es * W * K * 5 * n},
         {&c->Cbuf, es * W * K * n},
@@ -498,8 +528,8 @@ cq_status cq_crowd_create(const cq_system* const* systems, const int* walkers_pe
         {(void**)&c->wG, sizeof(double) * W * K * K},
         {(void**)&c->beta, sizeof(double) * W * K},
         {(void**)&c->pend, sizeof(int) * W},
-        {(void**)&c->part, sizeof(double) * W * C * cq::part_stride(K)},
-        {(void**)&c->rnew, sizeof(double) * W * 3},
+        {(void**)&c->part, sizeof(double) * 2 * W * C * cq::part_stride(K)},
+        {(void**)&c->rnew, sizeof(double) * 4 * W * 3},
         {(void**)&c->uid, sizeof(uint32_t) * W},
         {(void**)&c->prm, sizeof(cq::Params)},
         {(void**)&c->status, sizeof(int) * W},
@@ -579,6 +609,13 @@ cq_status cq_crowd_run_vmc(cq_crowd* c, int n_sweeps, double sigma)
         c->hp.sigma = sigma;
         cq_status st = push_params(c);
         if (st != CQ_OK) return st;
+    }
+    // proposal of the first move (each move kernel makes the next one's)
+    if (c->path == CQ_PATH_MULTI) {
+        if (c->prec == CQ_FP64)
+            cq::launch_first_proposal<double>(view<double>(c), c->stream);
+        else
+            cq::launch_first_proposal<float>(view<float>(c), c->stream);
     }
     for (int s = 0; s < n_sweeps; ++s) {
         if (c->use_graph && !c->timing_mask) {
@@ -784,7 +821,7 @@ cq_status cq_crowd_synchronize(cq_crowd* c)
     if (!c) return fail(CQ_EINVAL, "crowd is NULL");
     HIP_TRY(hipStreamSynchronize(c->stream));
     HIP_TRY(hipGetLastError());
-    return CQ_OK;
+    return check_singular(c, "synchronize");
 }
 
 }  // extern "C"

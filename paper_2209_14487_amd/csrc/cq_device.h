@@ -133,13 +133,47 @@ __device__ __forceinline__ void min_image(const double* ri, const double* rj, do
     }
 }
 
-// Butterfly sum over the 64 lanes of a wave (every lane gets the total).
+// Sum over the 64 lanes of a wave; every lane gets the same total.  Within each
+// row of 16 lanes the partner values come from DPP lane swizzles (quad
+// permutations for distances 1 and 2, half-row and row mirrors for 4 and 8), so
+// no LDS traffic is needed; the four row sums are then read as scalars and added
+// in a fixed order, (row0 + row1) + (row2 + row3).
+namespace dpp {
+constexpr int kQuadXor1 = 0xB1;      // quad_perm [1,0,3,2]
+constexpr int kQuadXor2 = 0x4E;      // quad_perm [2,3,0,1]
+constexpr int kHalfMirror = 0x141;   // row_half_mirror
+constexpr int kMirror = 0x140;       // row_mirror
+template <int CTRL>
+__device__ __forceinline__ float mov(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double mov(double x)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float lane(float x, int l)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+__device__ __forceinline__ double lane(double x, int l)
+{
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), l),
+                            __builtin_amdgcn_readlane(__double2loint(x), l));
+}
+}  // namespace dpp
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v)
 {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    v += dpp::mov<dpp::kQuadXor1>(v);
+    v += dpp::mov<dpp::kQuadXor2>(v);
+    v += dpp::mov<dpp::kHalfMirror>(v);
+    v += dpp::mov<dpp::kMirror>(v);
+    return (dpp::lane(v, 0) + dpp::lane(v, 16)) + (dpp::lane(v, 32) + dpp::lane(v, 48));
 }
 
 // Block-to-(walker, part) mapping that keeps all workgroups of one walker on the

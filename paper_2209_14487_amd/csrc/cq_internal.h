@@ -18,8 +18,8 @@
 //           wG    double [W][K][K] wG[m][j] = u_m . c_j (j < m)
 //           beta  double [W][K], pend int [W]: coefficients of the last accepted
 //                               move, whose column still has to be brought up to date
-//   part   double [W][C][NP]          per-workgroup partial sums of one move
-//   rnew   double [W][3]              proposed position of the current move
+//   part   double [2][W][C][NP]       per-workgroup partial sums of a move (by move parity)
+//   rnew   double [4][W][3]           proposals, slot e % 4 holds move e's
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -63,7 +63,7 @@ struct CrowdView {
     long long* nprop;
     double* eloc;
     double* elpart;
-    int* cnt;
+    int* cnt;            // [3][W] window count seen by the last move of each parity; [2]: final
     int* welec;
     T* stage;
     T* Cbuf;
@@ -83,7 +83,8 @@ struct CrowdView {
     double* rec_prob;
     uint8_t* rec_acc;
     const uint8_t* forced;
-    int* status;         // [W] 0 ok, 1 singular / not finite at the last inversion
+    int* status;         // [W] bit 0: singular / not finite at the last inversion; bit 1: window
+                         // bookkeeping out of range (internal error)
     double* drift;       // [W][2] |log|det| kept - recomputed| at the last inversion
 };
 
@@ -99,9 +100,10 @@ struct InvWork {
 
 template <typename T> void launch_fill_philox(T* table, uint64_t seed, size_t count, hipStream_t s);
 template <typename T> void launch_setup_vgl(const CrowdView<T>& v, hipStream_t s);
-template <typename T> void launch_vgl_move(const CrowdView<T>& v, int e, int reset, hipStream_t s);
-template <typename T> void launch_resolve(const CrowdView<T>& v, int e, int reset, hipStream_t s);
-template <typename T> void launch_finalize(const CrowdView<T>& v, hipStream_t s);
+template <typename T> void launch_move(const CrowdView<T>& v, int e, int prev, int reset, hipStream_t s);
+template <typename T> void launch_first_proposal(const CrowdView<T>& v, hipStream_t s);
+template <typename T> void launch_window(const CrowdView<T>& v, int e0, int nmoves, hipStream_t s);
+int window_threads(int n, int elem_bytes);
 template <typename T> void launch_flush(const CrowdView<T>& v, int spin, hipStream_t s);
 template <typename T> void launch_energy(const CrowdView<T>& v, hipStream_t s);
 template <typename T> void launch_inverse(const CrowdView<T>& v, const InvWork& wk, hipStream_t s);

@@ -39,8 +39,9 @@ __global__ __launch_bounds__(kBlock) void k_flush_vec(CrowdView<T> v, int spin)
     int w, strip;
     xcd_map(blockIdx.x, nstrip, w, strip);
     if (w >= v.W) return;
-    const int cnt = v.cnt[w];
-    if (cnt == 0) return;
+    int cnt = v.cnt[(size_t)2 * v.W + w];  // final size of the window
+    if (cnt > K) cnt = K;
+    if (cnt <= 0) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     for (int i = tid; i < cnt * cnt; i += kBlock) {
         const int r = i / cnt, c = i % cnt;
@@ -54,6 +55,10 @@ __global__ __launch_bounds__(kBlock) void k_flush_vec(CrowdView<T> v, int spin)
     // copy the accepted orbital rows of the window into the A, G, L rows
     for (int mm = strip; mm < cnt; mm += nstrip) {
         const int ea = v.welec[(size_t)w * K + mm];
+        if (ea < 0 || ea >= n) {  // never written: bookkeeping error, flagged, row left alone
+            if (tid == 0) atomicOr(&v.status[w], 2);
+            continue;
+        }
         const T* src = v.stage + ((size_t)w * K + mm) * 5 * (size_t)n;
         T* dst = v.VGL + (((size_t)w * 2 + spin) * n + ea) * 5 * (size_t)n;
         for (int i = tid; i < 5 * n; i += kBlock) dst[i] = src[i];

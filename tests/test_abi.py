@@ -47,7 +47,7 @@ def test_invalid_arguments_are_rejected_before_any_device_work():
     assert L.cq_system_load_pade_j2(h, float("nan"), 0.5, 1.0) == cq.CQ_EINVAL
     assert L.cq_system_load_pade_j2(h, 0.25, 0.5, 1.0) == cq.CQ_OK
     # a crowd needs a table of its precision
-    desc = cq.CrowdDesc(cq.CQ_FP64, 1, 0, 1, 0, None, 0)
+    desc = cq.CrowdDesc(cq.CQ_FP64, 1, 0, 1, 0, None, 0, 0)
     systems = (ctypes.c_void_p * 1)(h.value)
     counts = (ctypes.c_int * 1)(16)
     c = ctypes.c_void_p()

@@ -114,12 +114,16 @@ def compare_fp64(gpu, ref, sweeps, ne, tol=1e-10):
     return div
 
 
-def test_c1_fp64_sherman_morrison_matches_oracle():
+PATHS = ["multi", "window"]
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_c1_fp64_sherman_morrison_matches_oracle(path):
     """C1: 4+4 electrons, L=5, 16^3 plane-wave spline, 16 walkers, 200 sweeps, FP64, SM."""
     n, L, G, W, S = 4, 5.0, 16, 16, 200
     g, o = make_pair(n, L, G, 1001, table=planewave_table(G, L), j2=False)
     R0 = start_positions(1001, W, 2 * n, L)
-    crowd = cq.Crowd(g, W, precision="fp64", delay_rank=1, seed=1001)
+    crowd = cq.Crowd(g, W, precision="fp64", delay_rank=1, seed=1001, path=path)
     gpu = run_gpu(crowd, R0, S, 0.5)
     ref = orc.vmc(o, R0, S, sigma=0.5)
     div = compare_fp64(gpu, ref, S, 2 * n)
@@ -132,14 +136,15 @@ def test_c1_fp64_sherman_morrison_matches_oracle():
     crowd.close()
 
 
+@pytest.mark.parametrize("path", PATHS)
 @pytest.mark.parametrize("k", [1, 4, 8, 32])
-def test_c2_shape_fp64_delayed_ranks_match_oracle(k):
+def test_c2_shape_fp64_delayed_ranks_match_oracle(k, path):
     """C2 shapes (32+32, L=10, 48^3 seeded table, Pade J2) on 61 walkers (ragged against the
     8-XCD mapping): Sherman-Morrison and rank-k delayed updates reproduce the oracle chain."""
     n, L, G, W, S = 32, 10.0, 48, 61, 4
     g, o = make_pair(n, L, G, 1002, coef_seed=1002)
     R0 = start_positions(1002, W, 2 * n, L)
-    crowd = cq.Crowd(g, W, precision="fp64", delay_rank=k, seed=1002)
+    crowd = cq.Crowd(g, W, precision="fp64", delay_rank=k, seed=1002, path=path)
     gpu = run_gpu(crowd, R0, S, 0.5)
     ref = orc.vmc(o, R0, S, sigma=0.5, want_ainv=True)
     div = compare_fp64(gpu, ref, S, 2 * n)
@@ -150,8 +155,9 @@ def test_c2_shape_fp64_delayed_ranks_match_oracle(k):
     crowd.close()
 
 
-@pytest.mark.parametrize("k,recompute", [(1, 2), (8, 2), (32, 0)])
-def test_c2_mixed_precision_on_oracle_trajectory(k, recompute):
+@pytest.mark.parametrize("k,recompute,path", [(1, 2, "window"), (8, 2, "window"), (32, 0, "window"),
+                                              (8, 2, "multi")])
+def test_c2_mixed_precision_on_oracle_trajectory(k, recompute, path):
     """C2 mixed precision (FP32 table, FP32 inverse and dots, FP64 log|det| and sums) follows
     the oracle's decisions; its own ratios stay within 1e-4 relative of the FP64 oracle, its
     own decisions differ only where |P - u| is within that error, and log|det| stays within
@@ -160,9 +166,9 @@ def test_c2_mixed_precision_on_oracle_trajectory(k, recompute):
     g, o = make_pair(n, L, G, 1002, coef_seed=1002, fp64=False, fp32=True)
     R0 = start_positions(1002, W, 2 * n, L)
     ref = orc.vmc(o, R0, S, sigma=0.5)
-    crowd = cq.Crowd(g, W, precision="mixed", delay_rank=k, recompute_every=recompute, seed=1002)
+    crowd = cq.Crowd(g, W, precision="mixed", delay_rank=k, recompute_every=recompute, seed=1002, path=path)
     gpu = run_gpu(crowd, R0, S, 0.5, forced=ref.acc)
-    mixed_ratio_check(gpu["rho"], ref.rho, "C2 mixed k=%d recompute=%d" % (k, recompute))
+    mixed_ratio_check(gpu["rho"], ref.rho, "C2 mixed k=%d recompute=%d %s" % (k, recompute, path))
     # its own decisions differ from the oracle's only where P and u are within the error
     own = gpu["prob"] > ref.u
     mism = own != ref.acc.astype(bool)
@@ -181,7 +187,8 @@ def test_c2_mixed_precision_on_oracle_trajectory(k, recompute):
     crowd.close()
 
 
-def test_crowd_partition_is_bit_identical():
+@pytest.mark.parametrize("path", PATHS)
+def test_crowd_partition_is_bit_identical(path):
     """Splitting the walkers into crowds changes nothing (paper Sec. III: crowd size 1 is the
     per-walker driver, one crowd is the whole-population batch): FP64 results per walker are
     bit-identical for 1 x 24, 8 + 16 and 24 x 1 walkers."""
@@ -193,7 +200,7 @@ def test_crowd_partition_is_bit_identical():
         out_R, out_ld, out_el = [], [], []
         lo = 0
         for p in parts:
-            c = cq.Crowd(g, p, precision="fp64", delay_rank=4, seed=7, first_uid=lo)
+            c = cq.Crowd(g, p, precision="fp64", delay_rank=4, seed=7, first_uid=lo, path=path)
             c.set_positions(R0[lo:lo + p])
             c.run_vmc(S, 0.5)
             out_R.append(c.positions())
@@ -212,14 +219,16 @@ def test_crowd_partition_is_bit_identical():
         assert np.array_equal(x, y)
 
 
-def test_graph_replay_equals_eager_launches():
+@pytest.mark.parametrize("path", PATHS)
+def test_graph_replay_equals_eager_launches(path):
     """The sweep captured once as a hipGraph and replayed gives the eager result bit for bit."""
     n, L, G, W, S = 32, 10.0, 48, 16, 3
     g, _ = make_pair(n, L, G, 9, coef_seed=1002, fp64=False, fp32=True)
     R0 = start_positions(1002, W, 2 * n, L)
     res = []
     for use_graph in (False, True):
-        c = cq.Crowd(g, W, precision="mixed", delay_rank=8, recompute_every=2, seed=9, use_graph=use_graph)
+        c = cq.Crowd(g, W, precision="mixed", delay_rank=8, recompute_every=2, seed=9, use_graph=use_graph,
+                     path=path)
         c.set_positions(R0)
         for _ in range(S):
             c.run_vmc(1, 0.5)
@@ -230,15 +239,16 @@ def test_graph_replay_equals_eager_launches():
         assert np.array_equal(x, y)
 
 
-@pytest.mark.parametrize("precision,k", [("fp64", 1), ("fp64", 16), ("mixed", 32)])
-def test_n256_blocked_inverse_and_multichunk_sweep(precision, k):
+@pytest.mark.parametrize("precision,k,path", [("fp64", 1, "multi"), ("fp64", 16, "multi"), ("mixed", 32, "multi"),
+                                              ("fp64", 16, "window"), ("mixed", 32, "window")])
+def test_n256_blocked_inverse_and_multichunk_sweep(precision, k, path):
     """C3 system size (256+256, L=20, 64^3): blocked FP64 Gauss-Jordan set-up, multi-workgroup
     orbital chunks and one full sweep, on 3 walkers."""
     n, L, G, W, S = 256, 20.0, 64, 3, 1
     g, o = make_pair(n, L, G, 1003, coef_seed=1003, fp64=precision == "fp64", fp32=precision == "mixed")
     R0 = start_positions(1003, W, 2 * n, L)
     ld0, sg0, el0, ai0 = orc.setup(o, R0)
-    crowd = cq.Crowd(g, W, precision=precision, delay_rank=k, seed=1003)
+    crowd = cq.Crowd(g, W, precision=precision, delay_rank=k, seed=1003, path=path)
     crowd.set_positions(R0)
     ld, sg = crowd.logdet()
     tol = 1e-10 if precision == "fp64" else 1e-4
@@ -257,7 +267,7 @@ def test_n256_blocked_inverse_and_multichunk_sweep(precision, k):
     else:
         gpu = run_gpu(crowd, R0, S, 0.5, forced=ref.acc)
         # FP32 rounding of N-term dots and of the stored inverse grows with N: twice the N=32 bound
-        mixed_ratio_check(gpu["rho"], ref.rho, "N=256 mixed k=%d" % k, p99_bound=2e-4)
+        mixed_ratio_check(gpu["rho"], ref.rho, "N=256 mixed k=%d %s" % (k, path), p99_bound=2e-4)
     crowd.close()
 
 
@@ -276,3 +286,22 @@ def test_singular_start_is_reported():
         crowd.run_vmc(1, 0.5)
     assert ei.value.status == cq.CQ_ESTATE
     crowd.close()
+
+
+def test_paths_agree():
+    """The per-move multi-workgroup path and the walker-resident window path compute the same
+    chain: identical decisions, and ratios, log|det| and energies within the FP64 parity bar
+    (their sums are grouped differently, so they agree to rounding, not bit for bit)."""
+    n, L, G, W, S = 32, 10.0, 48, 20, 3
+    g, _ = make_pair(n, L, G, 1002, coef_seed=1002)
+    R0 = start_positions(1002, W, 2 * n, L)
+    out = []
+    for path in PATHS:
+        c = cq.Crowd(g, W, precision="fp64", delay_rank=8, seed=1002, path=path)
+        out.append(run_gpu(c, R0, S, 0.5))
+        c.close()
+    a, b = out
+    assert np.array_equal(a["acc"], b["acc"])
+    assert np.all(np.abs(a["rho"] - b["rho"]) <= 1e-10 * np.maximum(1.0, np.abs(b["rho"])))
+    assert np.all(np.abs(a["logdet"] - b["logdet"]) <= 1e-10 * np.maximum(1.0, np.abs(b["logdet"])))
+    assert np.all(np.abs(a["eloc"] - b["eloc"]) <= 1e-10 * np.maximum(1.0, np.abs(b["eloc"])))
