@@ -42,7 +42,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-moves", type=int, default=512, help="moves per walker in the CPU baseline sample")
     ap.add_argument("--delay", type=int, default=None, help="override the delay rank")
-    ap.add_argument("--eager", action="store_true", help="launch kernels eagerly instead of replaying a graph")
+    ap.add_argument("--eager", action="store_true", help="skip the extra hipGraph replay run")
+    ap.add_argument("--path", default="auto", choices=["auto", "multi", "window", "batch"],
+                    help="mapping of the moves to the GPU")
     return ap.parse_args()
 
 
@@ -55,14 +57,19 @@ def make_system(cq, wl, elem_bytes):
     return s
 
 
-def run_gpu(cq, wl, precision, delay, recompute, steps, warmup, timing_kinds, use_graph):
-    """Time `steps` sweeps over `wl.crowds` crowds (one stream each); returns a result dict."""
+def run_gpu(cq, wl, precision, delay, recompute, steps, warmup, timing_kinds, use_graph, path="auto",
+            graph_steps=0):
+    """Time `steps` sweeps over `wl.crowds` crowds (one stream each); returns a result dict.
+
+    With timing_kinds, HIP events bracket every launch of those kernel kinds on each crowd's
+    stream during the timed sweeps (launches are then eager).  graph_steps > 0 adds a second
+    timed run of that many sweeps replaying the captured sweep graph, no events."""
     from synth import start_positions
     system = make_system(cq, wl, 4 if precision == "mixed" else 8)
     crowds = []
     for ci in range(wl.crowds):
         c = cq.Crowd(system, wl.walkers, precision=precision, delay_rank=delay, recompute_every=recompute,
-                     seed=wl.seed, first_uid=ci * wl.walkers, use_graph=use_graph)
+                     seed=wl.seed, first_uid=ci * wl.walkers, use_graph=use_graph, path=path)
         c.set_positions(start_positions(wl.seed, wl.walkers, wl.n_e, wl.L, first_walker=ci * wl.walkers))
         crowds.append(c)
     log("  %s: %d crowd(s) x %d walkers set up" % (precision, wl.crowds, wl.walkers))
@@ -70,6 +77,7 @@ def run_gpu(cq, wl, precision, delay, recompute, steps, warmup, timing_kinds, us
         c.run_vmc(warmup, wl.sigma)
     for c in crowds:
         c.synchronize()
+    acc0 = sum(int(c.acceptance()[0].sum()) for c in crowds)
     for c in crowds:
         c.set_timing(timing_kinds)
     t0 = time.perf_counter()
@@ -91,11 +99,28 @@ def run_gpu(cq, wl, precision, delay, recompute, steps, warmup, timing_kinds, us
     el = np.concatenate([c.local_energy() for c in crowds])
     for c in crowds:
         c.set_timing(())
+    graph_s = None
+    if graph_steps > 0:
+        for c in crowds:
+            c.run_vmc(1, wl.sigma)  # captures the graph
+        for c in crowds:
+            c.synchronize()
+        g0 = time.perf_counter()
+        for c in crowds:
+            c.run_vmc(graph_steps, wl.sigma)
+        for c in crowds:
+            c.synchronize()
+        graph_s = time.perf_counter() - g0
+    for c in crowds:
         c.close()
     system.close()
     moves = wl.crowds * wl.walkers * wl.n_e * steps
-    return dict(seconds=t1 - t0, moves=moves, moves_per_s=moves / (t1 - t0), kernels=kt,
-                acceptance=acc / max(prop, 1), e_mean=float(el.mean()), finite=bool(np.isfinite(el).all()))
+    out = dict(seconds=t1 - t0, moves=moves, moves_per_s=moves / (t1 - t0), kernels=kt,
+               accepted_timed=acc - acc0, acceptance=acc / max(prop, 1), e_mean=float(el.mean()),
+               finite=bool(np.isfinite(el).all()))
+    if graph_s is not None:
+        out["graph_moves_per_s"] = wl.crowds * wl.walkers * wl.n_e * graph_steps / graph_s
+    return out
 
 
 def cpu_baseline(wl, moves_per_walker):
@@ -135,38 +160,41 @@ def main():
     log("workload %s: N=%d per spin, W=%d x %d crowd(s), G=%d, k=%d, recompute every %d"
         % (wl.name, wl.n, wl.walkers, wl.crowds, wl.G, delay, wl.recompute_every))
 
-    kinds = ["vgl", "update"]
-    mixed = run_gpu(cq, wl, "mixed", delay, wl.recompute_every, args.steps, args.warmup, kinds, not args.eager)
+    kinds = ["vgl", "resolve", "update", "energy", "inverse"]
+    mixed = run_gpu(cq, wl, "mixed", delay, wl.recompute_every, args.steps, args.warmup, kinds, not args.eager,
+                    path=args.path, graph_steps=0 if args.eager else max(2, args.steps // 4))
     log("  mixed: %.3f s for %d sweeps, %.3e moves/s, acceptance %.3f"
         % (mixed["seconds"], args.steps, mixed["moves_per_s"], mixed["acceptance"]))
-    # eager-launch pass with events on every kernel class: device time per kernel class
-    ev = run_gpu(cq, wl, "mixed", delay, wl.recompute_every, max(2, args.steps // 4), 1,
-                 ["vgl", "resolve", "update", "energy", "inverse"], False)
 
     n, W, s_c, s = wl.n, wl.walkers * wl.crowds, 4, 4
     kinfo = {}
-    for k, (ms, cnt) in ev["kernels"].items():
+    for k, (ms, cnt) in mixed["kernels"].items():
         kinfo[k] = dict(ms_total=round(ms, 3), launches=cnt, us_per_launch=round(1e3 * ms / max(cnt, 1), 3),
-                        share=round(ms / (1e3 * ev["seconds"]), 4))
-    # B-spline VGL kernel (per launch: every walker gathers 64 stencil points x N orbitals,
-    # reads its inverse column and writes the proposal's 5 orbital rows and the column)
+                        share=round(ms / (1e3 * mixed["seconds"]), 4))
+    windows_per_sweep = 2 * ((n + delay - 1) // delay)
+    # B-spline VGL of the window's proposals (k_prop_vgl): per proposal 64 stencil points x N
+    # orbitals read from the table and the 5 rows written; one launch = W x k proposals
     vgl_ms, vgl_n = mixed["kernels"]["vgl"]
-    vgl_bytes = W * (64 * n * s_c + n * s + 6 * n * s)
-    vgl_gbs = vgl_bytes / (vgl_ms / vgl_n * 1e-3) / 1e9
-    # update kernel (per launch: every walker reads and writes its N x N inverse once and streams
-    # the window's k rows and k columns; 4 N^2 k flops executed)
+    props_per_launch = W * n * 2 * args.steps / max(vgl_n, 1)
+    vgl_bytes = props_per_launch * (64 * n * s_c + 5 * n * s)
+    vgl_t = vgl_ms / max(vgl_n, 1) * 1e-3
+    vgl_gbs = vgl_bytes / vgl_t / 1e9
+    # rank-k inverse update (k_flush): per walker-spin window with r accepted moves it reads and
+    # writes the N x N inverse once and does 4 N^2 r flops; r summed over the timed region
     up_ms, up_n = mixed["kernels"]["update"]
-    up_bytes = W * (2 * n * n * s + 2 * delay * n * s)
-    up_flops = W * 4.0 * n * n * delay
     up_t = up_ms / max(up_n, 1) * 1e-3
+    r_per_launch = mixed["accepted_timed"] / max(up_n, 1)
+    up_flops = 4.0 * n * n * r_per_launch
+    up_bytes = W * 2 * n * n * s + 2 * r_per_launch * n * s
     roof_vgl = dict(bound="hbm", achieved=round(vgl_gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(vgl_gbs / HBM_PEAK_GBS, 4), traffic=None, kernel="k_vgl_move",
-                    us_per_launch=round(vgl_ms / vgl_n * 1e3, 3), bytes_per_launch=vgl_bytes)
+                    frac=round(vgl_gbs / HBM_PEAK_GBS, 4), traffic=None, kernel="k_prop_vgl",
+                    us_per_launch=round(vgl_t * 1e6, 3), bytes_per_launch=int(vgl_bytes),
+                    proposals_per_launch=int(props_per_launch))
     roof_up = dict(bound="mfma", achieved=round(up_flops / up_t / 1e12, 2), peak=FP32_PEAK_TFLOPS,
                    unit="TFLOP/s", frac=round(up_flops / up_t / 1e12 / FP32_PEAK_TFLOPS, 4),
-                   hbm_gbs=round(up_bytes / up_t / 1e9, 1), kernel="k_flush (+k_finalize)",
-                   us_per_launch=round(up_t * 1e6, 3))
-
+                   hbm_gbs=round(up_bytes / up_t / 1e9, 1), kernel="k_flush_vec",
+                   us_per_launch=round(up_t * 1e6, 3), accepted_per_launch=round(r_per_launch, 2))
+    dominant = roof_vgl if vgl_ms >= up_ms else roof_up
     out = dict(metric=METRIC, value=round(mixed["moves_per_s"], 1), unit="moves/s", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=round(1e3 * mixed["seconds"] / args.steps, 3),
                higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32",
@@ -175,12 +203,15 @@ def main():
                                     "%d crowd(s) x %d walkers, delayed rank %d, FP64 recompute every %d sweeps"
                                     % (wl.name, n, n, wl.L, wl.G, wl.table_bytes(4) / 1e9, wl.crowds, wl.walkers,
                                        delay, wl.recompute_every),
-                           precision="mixed", launch="eager" if args.eager else "hipGraph per sweep"),
-               roofline=roof_vgl if vgl_ms >= up_ms else roof_up,
-               roofline_spline=roof_vgl, roofline_update=roof_up, kernels=kinfo,
+                           precision="mixed", path=args.path,
+                           launch="eager launches with HIP events around every kernel (timed region)"),
+               roofline=dominant, roofline_spline=roof_vgl, roofline_update=roof_up, kernels=kinfo,
+               windows_per_sweep=windows_per_sweep,
                acceptance=round(mixed["acceptance"], 4), e_mean=mixed["e_mean"])
+    if "graph_moves_per_s" in mixed:
+        out["graph_moves_per_s"] = round(mixed["graph_moves_per_s"], 1)
     if args.fp64_steps > 0:
-        f64 = run_gpu(cq, wl, "fp64", delay, 0, args.fp64_steps, 1, [], not args.eager)
+        f64 = run_gpu(cq, wl, "fp64", delay, 0, args.fp64_steps, 1, [], not args.eager, path=args.path)
         log("  fp64: %.3e moves/s" % f64["moves_per_s"])
         out["fp64_moves_per_s"] = round(f64["moves_per_s"], 1)
         out["mixed_over_fp64"] = round(mixed["moves_per_s"] / f64["moves_per_s"], 3)

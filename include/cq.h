@@ -54,27 +54,33 @@ typedef enum { CQ_FP64 = 0, CQ_MIXED = 1 } cq_precision;
 
 /* Kernel classes whose device time can be measured with cq_crowd_get_kernel_timing. */
 typedef enum {
-    CQ_KERNEL_VGL = 0,      /* per move: B-spline VGL at the proposal, ratio and Jastrow partial sums,
-                               fused with the previous move's decision */
-    CQ_KERNEL_RESOLVE = 1,  /* end of a window: decision of its last move */
+    CQ_KERNEL_VGL = 0,      /* B-spline VGL at the proposals: per move fused with the ratio, Jastrow
+                               and the previous decision (MULTI), per window with all its moves
+                               (WINDOW), or per window for all its proposals at once (BATCH) */
+    CQ_KERNEL_RESOLVE = 1,  /* decisions: of a window's last move (MULTI), of all its moves (BATCH) */
     CQ_KERNEL_UPDATE = 2,   /* Sherman-Morrison / delayed rank-k inverse update */
     CQ_KERNEL_ENERGY = 3,   /* local energy */
     CQ_KERNEL_INVERSE = 4,  /* FP64 Gauss-Jordan inversion (initial and periodic recompute) */
     CQ_KERNEL_COUNT = 5
 } cq_kernel_kind;
 
-/* Mapping of the moves to the GPU.  Both compute the same Markov chain; their
-   sums are grouped differently, so results agree to rounding, and each path is
-   bit-reproducible on its own (independent of how walkers form crowds).
+/* Mapping of the moves to the GPU.  All paths compute the same Markov chain
+   (same proposals, uniforms and decisions); their sums are grouped differently,
+   so results agree to rounding, and each path is bit-reproducible on its own
+   (independent of how walkers form crowds).
    CQ_PATH_MULTI:   one kernel launch per move, several workgroups per walker (one
                     per chunk of orbitals), the previous move decided inside the
                     next launch; uses every CU even for few walkers.
    CQ_PATH_WINDOW:  one workgroup per walker runs all k moves of an update window
                     in one launch (decisions and window bookkeeping stay in the
                     workgroup); far fewer launches, one CU per walker.
-   CQ_PATH_AUTO:    CQ_PATH_WINDOW when the crowd has at least 64 walkers, else
-                    CQ_PATH_MULTI. */
-typedef enum { CQ_PATH_AUTO = 0, CQ_PATH_MULTI = 1, CQ_PATH_WINDOW = 2 } cq_kernel_path;
+   CQ_PATH_BATCH:   the k proposals of a window are evaluated in one launch over
+                    all walkers (a VMC proposal depends only on its own electron,
+                    which has not moved yet), then one workgroup per walker
+                    decides the window's moves in order from the k x k products of
+                    proposal rows and inverse columns.
+   CQ_PATH_AUTO:    CQ_PATH_BATCH. */
+typedef enum { CQ_PATH_AUTO = 0, CQ_PATH_MULTI = 1, CQ_PATH_WINDOW = 2, CQ_PATH_BATCH = 3 } cq_kernel_path;
 
 typedef struct cq_system cq_system;  /* orbitals + Jastrow + box + electron counts (opaque) */
 typedef struct cq_crowd cq_crowd;    /* walkers moved in lock-step (opaque) */

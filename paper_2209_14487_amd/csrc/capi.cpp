@@ -51,7 +51,7 @@ struct cq_system {
 
 struct cq_crowd {
     const cq_system* sys = nullptr;
-    int W = 0, n = 0, ne = 0, K = 1, prec = CQ_MIXED, recompute_every = 0, use_graph = 0;
+    int W = 0, n = 0, ne = 0, K = 1, Q = 1, prec = CQ_MIXED, recompute_every = 0, use_graph = 0;
     int path = CQ_PATH_WINDOW;
     uint64_t seed = 0;
     uint32_t first_uid = 0;
@@ -70,6 +70,7 @@ struct cq_crowd {
     double* elpart = nullptr;
     int* cnt = nullptr;
     int* welec = nullptr;
+    int* wslot = nullptr;
     void* stage = nullptr;
     void* Cbuf = nullptr;
     double* wrho = nullptr;
@@ -78,6 +79,11 @@ struct cq_crowd {
     int* pend = nullptr;
     double* part = nullptr;
     double* rnew = nullptr;
+    double* jd = nullptr;
+    double* rprop = nullptr;
+    double* pmat = nullptr;
+    double* tmat = nullptr;
+    int* cur = nullptr;
     uint32_t* uid = nullptr;
     cq::Params* prm = nullptr;
     int* status = nullptr;
@@ -112,6 +118,7 @@ cq::CrowdView<T> view(const cq_crowd* c)
     v.n = c->n;
     v.ne = c->ne;
     v.K = c->K;
+    v.Q = c->Q;
     v.G = c->sys->G;
     v.n_orb = c->sys->n_orb;
     v.L = c->sys->L;
@@ -127,6 +134,7 @@ cq::CrowdView<T> view(const cq_crowd* c)
     v.elpart = c->elpart;
     v.cnt = c->cnt;
     v.welec = c->welec;
+    v.wslot = c->wslot;
     v.stage = (T*)c->stage;
     v.Cbuf = (T*)c->Cbuf;
     v.wrho = c->wrho;
@@ -135,6 +143,11 @@ cq::CrowdView<T> view(const cq_crowd* c)
     v.pend = c->pend;
     v.part = c->part;
     v.rnew = c->rnew;
+    v.jd = c->jd;
+    v.rprop = c->rprop;
+    v.pmat = c->pmat;
+    v.tmat = c->tmat;
+    v.cur = c->cur;
     v.uid = c->uid;
     v.seed = c->seed;
     v.use_j2 = c->sys->use_j2;
@@ -190,6 +203,26 @@ void enqueue_sweep(cq_crowd* c)
 {
     const cq::CrowdView<T> v = view<T>(c);
     const int n = c->n, K = c->K;
+    if (c->path == CQ_PATH_BATCH) {
+        const int rounds = cq::batch_rounds(n, K);
+        for (int spin = 0; spin < 2; ++spin)
+            for (int r = 0; r < rounds; ++r) {
+                timed_begin(c, CQ_KERNEL_VGL);
+                cq::launch_batch_vgl<T>(v, spin, r == 0, c->stream);
+                timed_end(c, CQ_KERNEL_VGL);
+                timed_begin(c, CQ_KERNEL_RESOLVE);
+                cq::launch_batch_decide<T>(v, spin, c->stream);
+                timed_end(c, CQ_KERNEL_RESOLVE);
+                timed_begin(c, CQ_KERNEL_UPDATE);
+                cq::launch_flush<T>(v, spin, c->stream);
+                timed_end(c, CQ_KERNEL_UPDATE);
+            }
+        timed_begin(c, CQ_KERNEL_ENERGY);
+        cq::launch_energy<T>(v, c->stream);
+        timed_end(c, CQ_KERNEL_ENERGY);
+        cq::launch_sweep_end(c->prm, c->stream);
+        return;
+    }
     if (c->path == CQ_PATH_WINDOW) {
         for (int spin = 0; spin < 2; ++spin)
             for (int a0 = 0; a0 < n; a0 += K) {
@@ -309,9 +342,11 @@ cq_status setup_state(cq_crowd* c)
     HIP_TRY(hipMemsetAsync(c->nprop, 0, sizeof(long long) * c->W, c->stream));
     HIP_TRY(hipMemsetAsync(c->cnt, 0, sizeof(int) * 3 * c->W, c->stream));
     HIP_TRY(hipMemsetAsync(c->welec, 0, sizeof(int) * c->W * c->K, c->stream));
+    HIP_TRY(hipMemsetAsync(c->wslot, 0, sizeof(int) * c->W * c->K, c->stream));
     // window slots are read (masked) before they are first written: start them at 0
     const size_t es = c->prec == CQ_FP64 ? 8 : 4;
-    HIP_TRY(hipMemsetAsync(c->stage, 0, es * c->W * c->K * 5 * c->n, c->stream));
+    HIP_TRY(hipMemsetAsync(c->stage, 0, es * c->W * c->Q * 5 * c->n, c->stream));
+    HIP_TRY(hipMemsetAsync(c->cur, 0, sizeof(int) * 3 * c->W, c->stream));
     HIP_TRY(hipMemsetAsync(c->Cbuf, 0, es * c->W * c->K * c->n, c->stream));
     HIP_TRY(hipMemsetAsync(c->status, 0, sizeof(int) * c->W, c->stream));
     cq::launch_setup_vgl<T>(v, c->stream);
@@ -478,7 +513,7 @@ cq_status cq_crowd_create(const cq_system* const* systems, const int* walkers_pe
     int K = desc->delay_rank == 0 ? std::min(32, s->n_up) : desc->delay_rank;
     if (K < 1 || K > cq::kMaxDelay) return fail(CQ_EINVAL, "delay_rank must be 0..32");
     if (desc->recompute_every < 0) return fail(CQ_EINVAL, "recompute_every must be >= 0");
-    if (desc->kernel_path < CQ_PATH_AUTO || desc->kernel_path > CQ_PATH_WINDOW)
+    if (desc->kernel_path < CQ_PATH_AUTO || desc->kernel_path > CQ_PATH_BATCH)
         return fail(CQ_EINVAL, "unknown kernel_path");
 
     cq_crowd* c = new (std::nothrow) cq_crowd();
@@ -491,7 +526,8 @@ cq_status cq_crowd_create(const cq_system* const* systems, const int* walkers_pe
     c->prec = desc->precision;
     c->recompute_every = desc->recompute_every;
     c->use_graph = desc->use_graph;
-    c->path = desc->kernel_path != CQ_PATH_AUTO ? desc->kernel_path : (W >= 64 ? CQ_PATH_WINDOW : CQ_PATH_MULTI);
+    c->path = desc->kernel_path != CQ_PATH_AUTO ? desc->kernel_path : CQ_PATH_BATCH;
+    c->Q = c->path == CQ_PATH_BATCH ? cq::batch_candidates(c->n, K) : K;
     c->seed = desc->seed;
     c->first_uid = desc->first_uid;
     if (desc->hip_stream) {
@@ -522,7 +558,13 @@ cq_status cq_crowd_create(const cq_system* const* systems, const int* walkers_pe
         {(void**)&c->elpart, sizeof(double) * W * ne},
         {(void**)&c->cnt, sizeof(int) * 3 * W},
         {(void**)&c->welec, sizeof(int) * W * K},
-        {&c->stage, es * W * K * 5 * n},
+        {(void**)&c->wslot, sizeof(int) * W * K},
+        {(void**)&c->jd, sizeof(double) * W * c->Q},
+        {(void**)&c->rprop, sizeof(double) * W * c->Q * 3},
+        {(void**)&c->pmat, sizeof(double) * W * c->Q * c->Q},
+        {(void**)&c->tmat, sizeof(double) * W * K * c->Q},
+        {(void**)&c->cur, sizeof(int) * W * 3},
+        {&c->stage, es * W * c->Q * 5 * n},
         {&c->Cbuf, es * W * K * n},
         {(void**)&c->wrho, sizeof(double) * W * K},
         {(void**)&c->wG, sizeof(double) * W * K * K},

@@ -10,8 +10,11 @@
 //   logdet double [W][2], sign int [W][2], nacc/nprop int64 [W], eloc double [W]
 //   window (accepted moves m = 0 .. cnt-1 of the current k proposals):
 //           welec int [W][K]    electron (within its spin) of move m
-//           stage T [W][K][5][N] orbital rows u_m (+ gradients, Laplacian) at r'_m;
-//                               slot cnt holds the pending proposal
+//           wslot int [W][K]    stage slot holding the rows of move m
+//           stage T [W][Q][5][N] orbital rows (+ gradients, Laplacian) of proposals:
+//                               per-move paths (Q = K): slot m = accepted move m,
+//                               slot cnt the pending proposal; batched path: ring
+//                               of Q candidates, slot = electron mod Q
 //           Cbuf  T [W][K][N]   inverse column c_m of electron e_m just before
 //                               move m (slot cnt: the old column, pending)
 //           wrho  double [W][K] determinant ratio of move m
@@ -27,6 +30,7 @@
 namespace cq {
 
 constexpr int kMaxDelay = 32;
+constexpr int kMaxCand = 64;   // candidates per round of the batched path
 constexpr int kBlock = 256;
 
 // Partial-sum slots of one move workgroup: 4 determinant dots, 5 per window
@@ -51,6 +55,7 @@ struct Params {
 template <typename T>
 struct CrowdView {
     int W, n, ne, K;
+    int Q;               // stage slots per walker: K, or the candidate ring of the batched path
     int G, n_orb;
     double L;
     const T* table;
@@ -65,6 +70,7 @@ struct CrowdView {
     double* elpart;
     int* cnt;            // [3][W] window count seen by the last move of each parity; [2]: final
     int* welec;
+    int* wslot;          // [W][K] stage slot of accepted move m
     T* stage;
     T* Cbuf;
     double* wrho;
@@ -73,6 +79,12 @@ struct CrowdView {
     int* pend;
     double* part;
     double* rnew;
+    double* jd;          // [W][Q] Jastrow difference of the candidate in ring slot q
+    double* rprop;       // [W][Q][3] its proposed position
+    double* pmat;        // [W][Q][Q] P of the current round's candidates
+    double* tmat;        // [W][K][Q] T: accepted columns in the basis of the round's c0 columns
+    int* cur;            // [W][2] next electron to decide, end of the evaluated candidates;
+                         // then [W] first candidate of the last round
     const uint32_t* uid;
     uint64_t seed;
     int use_j2;
@@ -104,6 +116,10 @@ template <typename T> void launch_move(const CrowdView<T>& v, int e, int prev, i
 template <typename T> void launch_first_proposal(const CrowdView<T>& v, hipStream_t s);
 template <typename T> void launch_window(const CrowdView<T>& v, int e0, int nmoves, hipStream_t s);
 int window_threads(int n, int elem_bytes);
+template <typename T> void launch_batch_vgl(const CrowdView<T>& v, int spin, bool block_start, hipStream_t s);
+template <typename T> void launch_batch_decide(const CrowdView<T>& v, int spin, hipStream_t s);
+int batch_rounds(int n, int K);      // rounds per spin block (enough when every move is accepted)
+int batch_candidates(int n, int K);  // candidates per round, Q
 template <typename T> void launch_flush(const CrowdView<T>& v, int spin, hipStream_t s);
 template <typename T> void launch_energy(const CrowdView<T>& v, hipStream_t s);
 template <typename T> void launch_inverse(const CrowdView<T>& v, const InvWork& wk, hipStream_t s);

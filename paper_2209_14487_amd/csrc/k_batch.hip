@@ -1,0 +1,500 @@
+// Batched VMC moves with delayed updates of k accepted moves.
+//
+// A VMC proposal r'_e = r_e + sigma z (Sec. II, Metropolis sampling with
+// Gaussian moves, no drift) depends only on electron e's own position, and e has
+// not moved yet in the sweep when its turn comes.  So the proposals of many
+// upcoming moves are known before any of them is decided, and their orbital rows
+// (paper Alg. 1 L7: B-spline value, gradient, Laplacian) can be evaluated in one
+// wide, fully parallel gather launch over all walkers.  The sequential part
+// (Alg. 1 L8-L9: ratios, Jastrow, Metropolis, in electron order) then works on
+// small matrices only.
+//
+// Per walker and spin block, electrons are taken in order.  A round looks at the
+// next Q candidates [dec, dec + Q) (evaluated ones are kept in a ring of Q stage
+// slots, slot = electron mod Q) and decides them in order until k moves have been
+// accepted or the candidates run out; the k (or fewer) accepted moves are then
+// applied to the inverse in one rank-k update (delayed update).  With
+//     P[i][j] = u_i . c0_j      (u_i: value row of candidate i, c0_j: inverse
+//                                column of candidate j's electron, round start)
+// the determinant ratio of candidate m after the accepted set S of the round is
+// the Schur complement det(P[S+m, S+m]) / det(P[S, S]), evaluated in move order:
+//     c_a     column of the a-th accepted electron just before its move
+//             = sum_i T[a][i] c0_i
+//     x_a     = u_m . c_a      = sum_i T[a][i] P[m][i]
+//     beta_a  = (P[s_a][m] - sum_{j<a} beta_j G[a][j]) / rho_a
+//     rho_m   = P[m][m] - sum_a beta_a x_a
+//     accepted: T[cnt] = e_m - sum_a beta_a T[a], G[cnt][a] = x_a, rho_cnt = rho_m.
+// The Jastrow difference of a candidate is summed over all electrons when it is
+// evaluated; every later accepted move adds the change of its pair term.
+//
+// k_prop_vgl    gather + VGL of the new candidates, their Jastrow sums
+// k_pmat        P of every walker's candidates (FP64 sums of exact products)
+// k_decide      one workgroup per walker: the decisions, the window for the
+//               update kernel (accepted rows by slot, rho, G, and T with
+//               c_a = sum_i T[a][i] c0_i), the cursors and the Jastrow sums of the
+//               candidates left for later
+// k_cols        the columns c_a of the accepted moves
+#include "cq_device.h"
+#include "cq_internal.h"
+
+namespace cq {
+
+// Stencil of one proposal (table offsets and the five weights of the 64 points,
+// index 16 x + 4 y + z); lane l of a wave fills entry l.
+template <typename T>
+__device__ __forceinline__ void stencil_entry(const CrowdView<T>& v, const double rp[3], int l, size_t* sidx,
+                                              T* sw)
+{
+    const int G = v.G;
+    const AxisW<T> ax = axis_weights<T>(rp[0], v.L, G);
+    const AxisW<T> ay = axis_weights<T>(rp[1], v.L, G);
+    const AxisW<T> az = axis_weights<T>(rp[2], v.L, G);
+    const int p = l >> 4, yy = (l >> 2) & 3, zz = l & 3;
+    T bx = ax.b[0], dx = ax.d1[0], d2x = ax.d2[0];
+    if (p == 1) { bx = ax.b[1]; dx = ax.d1[1]; d2x = ax.d2[1]; }
+    if (p == 2) { bx = ax.b[2]; dx = ax.d1[2]; d2x = ax.d2[2]; }
+    if (p == 3) { bx = ax.b[3]; dx = ax.d1[3]; d2x = ax.d2[3]; }
+    T by = ay.b[0], dy = ay.d1[0], d2y = ay.d2[0];
+    if (yy == 1) { by = ay.b[1]; dy = ay.d1[1]; d2y = ay.d2[1]; }
+    if (yy == 2) { by = ay.b[2]; dy = ay.d1[2]; d2y = ay.d2[2]; }
+    if (yy == 3) { by = ay.b[3]; dy = ay.d1[3]; d2y = ay.d2[3]; }
+    T bz = az.b[0], dz = az.d1[0], d2z = az.d2[0];
+    if (zz == 1) { bz = az.b[1]; dz = az.d1[1]; d2z = az.d2[1]; }
+    if (zz == 2) { bz = az.b[2]; dz = az.d1[2]; d2z = az.d2[2]; }
+    if (zz == 3) { bz = az.b[3]; dz = az.d1[3]; d2z = az.d2[3]; }
+    const int jx = (ax.i0 + p + G - 1) % G, jy = (ay.i0 + yy + G - 1) % G, jz = (az.i0 + zz + G - 1) % G;
+    sidx[l] = (((size_t)jx * G + jy) * G + jz) * (size_t)v.n_orb;
+    sw[l * 5 + 0] = bx * by * bz;
+    sw[l * 5 + 1] = dx * by * bz;
+    sw[l * 5 + 2] = bx * dy * bz;
+    sw[l * 5 + 3] = bx * by * dz;
+    sw[l * 5 + 4] = d2x * by * bz + bx * d2y * bz + bx * by * d2z;
+}
+
+template <typename T>
+__device__ __forceinline__ double pair_j2(const CrowdView<T>& v, double a, const double* x, const double* y)
+{
+    double d[3];
+    min_image(x, y, v.L, d);
+    double u, du, d2u;
+    pade(a, v.b, sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]), u, du, d2u);
+    return u;
+}
+
+// Proposals per workgroup: one when a proposal's orbital groups fill the
+// workgroup, else up to 4 (a proposal then takes `groups` consecutive threads).
+inline int batch_pp(int n, int elem_bytes)
+{
+    const int groups = n / (16 / elem_bytes);
+    if (groups >= kBlock) return 1;
+    const int pp = kBlock / groups;
+    return pp > 4 ? 4 : pp;
+}
+
+inline int batch_threads(int n, int elem_bytes)
+{
+    const int groups = n / (16 / elem_bytes);
+    const int pp = batch_pp(n, elem_bytes);
+    if (pp == 1) return kBlock;
+    const int t = ((pp * groups + 63) / 64) * 64;
+    return t > kBlock ? kBlock : t;
+}
+
+// Candidate t of walker w in the current round: electron a = ev + t (within the
+// spin), evaluated when a < min(dec + Q, n).
+__device__ __forceinline__ bool new_candidate(const int* cur, int w, int t, int Q, int n, int& a)
+{
+    const int dec = cur[2 * w], ev = cur[2 * w + 1];
+    const int end = dec + Q < n ? dec + Q : n;
+    a = ev + t;
+    return a < end;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_prop_vgl(CrowdView<T> v, int spin, int pp)
+{
+    constexpr int VEC = 16 / sizeof(T);
+    __shared__ size_t s_idx[4][64];
+    __shared__ T s_w[4][64 * 5];
+    __shared__ double s_rp[4][3];
+    __shared__ double s_part[kBlock];
+    __shared__ int s_ok[4];
+    const int n = v.n, Q = v.Q, groups = n / VEC;
+    const int nprop = v.W * Q;
+    const int nt = blockDim.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
+    const int first = blockIdx.x * pp;
+    const uint32_t step = v.prm->step;
+    const double sigma = v.prm->sigma;
+
+    // proposals and stencils: wave p fills proposal p (a single wave fills all)
+    for (int p = wave; p < pp; p += nw) {
+        const int pi = first + p;
+        int a = 0;
+        const bool ok = pi < nprop && new_candidate(v.cur, pi / Q, pi % Q, Q, n, a);
+        if (lane == 0) s_ok[p] = ok;
+        if (!ok) continue;
+        const int w = pi / Q, e = spin * n + a, slot = a % Q;
+        double z[3], rp[3];
+        gauss3(v.seed, v.uid[w], step, (uint32_t)e, z);
+        for (int k = 0; k < 3; ++k) rp[k] = wrap_box(v.R[((size_t)w * v.ne + e) * 3 + k] + sigma * z[k], v.L);
+        stencil_entry<T>(v, rp, lane, s_idx[p], s_w[p]);
+        if (lane == 0) {
+            for (int k = 0; k < 3; ++k) {
+                s_rp[p][k] = rp[k];
+                v.rprop[((size_t)w * Q + slot) * 3 + k] = rp[k];
+            }
+        }
+    }
+    __syncthreads();
+
+    const int tpp = pp == 1 ? nt : groups;  // threads per proposal
+    const int p = tid / tpp, t0 = tid % tpp;
+    const int pi = first + p;
+    const bool live = p < pp && pi < nprop && s_ok[p];
+    int a = 0;
+    if (live) new_candidate(v.cur, pi / Q, pi % Q, Q, n, a);
+    const int w = live ? pi / Q : 0, e = spin * n + a, slot = a % Q;
+    if (live) {
+        T* dst = v.stage + ((size_t)w * Q + slot) * 5 * (size_t)n;
+        const size_t* sidx = s_idx[p];
+        const T* sw = s_w[p];
+        for (int g = t0; g < groups; g += tpp) {
+            const int j0 = g * VEC;
+            T acc[5][VEC];
+#pragma unroll
+            for (int k = 0; k < 5; ++k)
+#pragma unroll
+                for (int i = 0; i < VEC; ++i) acc[k][i] = (T)0;
+#pragma unroll 1
+            for (int x = 0; x < 4; ++x) {
+                T vals[16][VEC];
+#pragma unroll
+                for (int q = 0; q < 16; ++q) load16(v.table + sidx[x * 16 + q] + j0, vals[q]);
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    const T* wq = sw + (x * 16 + q) * 5;
+                    const T wv = wq[0], wgx = wq[1], wgy = wq[2], wgz = wq[3], wl = wq[4];
+#pragma unroll
+                    for (int i = 0; i < VEC; ++i) {
+                        acc[0][i] += wv * vals[q][i];
+                        acc[1][i] += wgx * vals[q][i];
+                        acc[2][i] += wgy * vals[q][i];
+                        acc[3][i] += wgz * vals[q][i];
+                        acc[4][i] += wl * vals[q][i];
+                    }
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 5; ++k) store16(dst + (size_t)k * n + j0, acc[k]);
+        }
+    }
+
+    // Jastrow difference of each proposal against the current positions
+    if (!v.use_j2) {
+        if (live && t0 == 0) v.jd[(size_t)w * Q + slot] = 0.0;
+        return;
+    }
+    double dj = 0.0;
+    if (live) {
+        const double* Rw = v.R + (size_t)w * v.ne * 3;
+        double re[3], rp[3];
+        for (int k = 0; k < 3; ++k) {
+            re[k] = Rw[(size_t)e * 3 + k];
+            rp[k] = s_rp[p][k];
+        }
+        for (int i = t0; i < v.ne; i += tpp) {
+            if (i == e) continue;
+            const double aa = ((i >= v.n) == (spin != 0)) ? v.a_par : v.a_anti;
+            dj += pair_j2(v, aa, rp, Rw + (size_t)i * 3) - pair_j2(v, aa, re, Rw + (size_t)i * 3);
+        }
+    }
+    if (tpp % 64 == 0) {
+        dj = wave_sum(dj);
+        if (lane == 0) s_part[wave] = dj;
+        __syncthreads();
+        if (live && t0 == 0) {
+            double sum = 0.0;
+            for (int q = 0; q < tpp / 64; ++q) sum += s_part[p * (tpp / 64) + q];
+            v.jd[(size_t)w * Q + slot] = sum;
+        }
+    } else {
+        s_part[tid] = dj;
+        __syncthreads();
+        if (live && t0 == 0) {
+            double sum = 0.0;
+            for (int q = 0; q < tpp; ++q) sum += s_part[tid + q];
+            v.jd[(size_t)w * Q + slot] = sum;
+        }
+    }
+}
+
+// P of one walker's candidates, in 16 x 16 blocks (one wave each; lane = 2 x 2
+// outputs).  Products of the stored values are formed exactly in FP64 and summed
+// in orbital order.
+constexpr int kPB = 16;   // block edge
+constexpr int kPT = 64;   // orbitals per LDS tile
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_pmat(CrowdView<T> v, int spin)
+{
+    __shared__ T sU[kPB][kPT + 1];
+    __shared__ T sC[kPB][kPT + 1];
+    const int Q = v.Q, n = v.n;
+    const int nb = (Q + kPB - 1) / kPB;
+    const int w = blockIdx.x / (nb * nb), blk = blockIdx.x % (nb * nb);
+    const int bi = blk / nb, bj = blk % nb;
+    const int dec = v.cur[2 * w];
+    const int nc = (dec + Q < n ? dec + Q : n) - dec;
+    if (bi * kPB >= nc || bj * kPB >= nc) return;
+    const int lane = threadIdx.x;
+    const int li = (lane >> 3) * 2, lj = (lane & 7) * 2;
+    const T* Mw = v.M + ((size_t)w * 2 + spin) * n * (size_t)n;
+    double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+    for (int l0 = 0; l0 < n; l0 += kPT) {
+        for (int idx = lane; idx < kPB * kPT; idx += 64) {
+            const int r = idx / kPT, c = idx % kPT, l = l0 + c;
+            const int ci = bi * kPB + r, cj = bj * kPB + r;
+            const bool okl = l < n;
+            sU[r][c] = (okl && ci < nc) ? v.stage[((size_t)w * Q + (dec + ci) % Q) * 5 * n + l] : (T)0;
+            sC[r][c] = (okl && cj < nc) ? Mw[(size_t)(dec + cj) * n + l] : (T)0;
+        }
+        __syncthreads();
+        const int lim = n - l0 < kPT ? n - l0 : kPT;
+        for (int c = 0; c < lim; ++c) {
+            const double u0 = (double)sU[li][c], u1 = (double)sU[li + 1][c];
+            const double c0 = (double)sC[lj][c], c1 = (double)sC[lj + 1][c];
+            acc[0][0] = fma(u0, c0, acc[0][0]);
+            acc[0][1] = fma(u0, c1, acc[0][1]);
+            acc[1][0] = fma(u1, c0, acc[1][0]);
+            acc[1][1] = fma(u1, c1, acc[1][1]);
+        }
+        __syncthreads();
+    }
+    double* P = v.pmat + (size_t)w * Q * Q;
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int i = bi * kPB + li + r, j = bj * kPB + lj + c;
+            if (i < nc && j < nc) P[(size_t)i * Q + j] = acc[r][c];
+        }
+}
+
+// Jastrow pair-term change for candidate (r_old -> r_new) when another electron
+// moved from o to q.
+template <typename T>
+__device__ __forceinline__ double pair_change(const CrowdView<T>& v, const double* rn, const double* ro,
+                                              const double* q, const double* o)
+{
+    return (pair_j2(v, v.a_par, rn, q) - pair_j2(v, v.a_par, rn, o)) -
+           (pair_j2(v, v.a_par, ro, q) - pair_j2(v, v.a_par, ro, o));
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_decide(CrowdView<T> v, int spin)
+{
+    constexpr int D = kMaxDelay, QM = kMaxCand;
+    __shared__ double s_P[QM][QM + 1];
+    __shared__ double s_T[D][QM + 1];
+    __shared__ double s_G[D][D + 1];
+    __shared__ double s_rinv[D];
+    __shared__ double s_u[QM], s_jd[QM];
+    __shared__ double s_rold[QM][3], s_rnew[QM][3];
+    __shared__ int s_slot[D];
+    __shared__ int s_cnt, s_ndec;
+
+    const int w = blockIdx.x;
+    const int n = v.n, K = v.K, Q = v.Q;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int dec = v.cur[2 * w];
+    const int nc = (dec + Q < n ? dec + Q : n) - dec;
+    const int e0 = spin * n + dec;
+    const int rs = v.prm->rec_sweep;
+    const uint32_t step = v.prm->step;
+    if (nc <= 0) {  // this walker's spin block is done
+        if (tid == 0) v.cnt[(size_t)2 * v.W + w] = 0;
+        return;
+    }
+    // candidates: P, uniforms, Jastrow sums, positions
+    const double* Pw = v.pmat + (size_t)w * Q * Q;
+    for (int idx = tid; idx < nc * nc; idx += kBlock) s_P[idx / nc][idx % nc] = Pw[(size_t)(idx / nc) * Q + idx % nc];
+    if (tid < nc) {
+        const int slot = (dec + tid) % Q;
+        s_u[tid] = accept_uniform(v.seed, v.uid[w], step, (uint32_t)(e0 + tid));
+        s_jd[tid] = v.jd[(size_t)w * Q + slot];
+        for (int k = 0; k < 3; ++k) {
+            s_rold[tid][k] = v.R[((size_t)w * v.ne + e0 + tid) * 3 + k];
+            s_rnew[tid][k] = v.rprop[((size_t)w * Q + slot) * 3 + k];
+        }
+    }
+    __syncthreads();
+
+    // decisions in electron order (wave 0; lane a <-> accepted move a for the
+    // recurrences, lane i <-> candidate i for the rows of T)
+    if (wave == 0) {
+        double ld = v.logdet[w * 2 + spin];
+        int sg = v.sign[w * 2 + spin];
+        int cnt = 0, m = 0;
+        for (; m < nc && cnt < K; ++m) {
+            const bool mine = lane < cnt;
+            const int sa = mine ? s_slot[lane] : 0;
+            // x_a = u_m . c_a = sum_i T[a][i] P[m][i]  (T[a][i] = 0 for i > s_a)
+            double x = 0.0;
+            if (mine)
+                for (int i = 0; i <= sa; ++i) x += s_T[lane][i] * s_P[m][i];
+            // beta_a by forward substitution over the accepted moves
+            double t = mine ? s_P[sa][m] : 0.0, my_beta = 0.0;
+            for (int j = 0; j < cnt; ++j) {
+                const double bj = dpp::lane(t, j) * s_rinv[j];
+                if (lane == j) my_beta = bj;
+                if (lane > j && mine) t -= bj * s_G[lane][j];
+            }
+            const double rho = s_P[m][m] - wave_sum(mine ? my_beta * x : 0.0);
+            double cj = 0.0;
+            if (v.use_j2 && mine) cj = pair_change(v, s_rnew[m], s_rold[m], s_rnew[sa], s_rold[sa]);
+            const double dlnj = s_jd[m] + wave_sum(cj);
+            const double prob = rho * rho * exp(2.0 * dlnj);
+            int acc = s_u[m] < prob;
+            const size_t ri = ((size_t)rs * v.ne + e0 + m) * v.W + w;
+            if (v.forced && rs < v.prm->forced_cap) acc = v.forced[ri] != 0;
+            if (lane == 0 && rs < v.prm->rec_cap) {
+                v.rec_rho[ri] = rho;
+                v.rec_dlnj[ri] = dlnj;
+                v.rec_prob[ri] = prob;
+                v.rec_acc[ri] = (uint8_t)acc;
+            }
+            if (acc) {
+                if (mine) s_G[cnt][lane] = x;
+                // T[cnt][i] = delta(i, m) - sum_a beta_a T[a][i]   (lane i)
+                for (int i = lane; i < nc; i += 64) {
+                    double tc = i == m ? 1.0 : 0.0;
+                    for (int aa = 0; aa < cnt; ++aa) tc -= dpp::lane(my_beta, aa) * s_T[aa][i];
+                    s_T[cnt][i] = tc;
+                }
+                if (lane == 0) {
+                    s_rinv[cnt] = 1.0 / rho;
+                    s_slot[cnt] = m;
+                    v.wrho[(size_t)w * K + cnt] = rho;
+                }
+                ld += log(fabs(rho));
+                if (rho < 0.0) sg = -sg;
+                ++cnt;
+            }
+        }
+        if (lane == 0) {
+            v.logdet[w * 2 + spin] = ld;
+            v.sign[w * 2 + spin] = sg;
+            v.nacc[w] += cnt;
+            v.nprop[w] += m;
+            s_cnt = cnt;
+            s_ndec = m;
+        }
+    }
+    __syncthreads();
+    const int cnt = s_cnt, ndec = s_ndec;
+
+    // the window for the update kernels, the accepted positions, the cursors
+    if (tid < cnt) {
+        const int a = dec + s_slot[tid];
+        v.welec[(size_t)w * K + tid] = a;
+        v.wslot[(size_t)w * K + tid] = a % Q;
+        for (int k = 0; k < 3; ++k) v.R[((size_t)w * v.ne + spin * n + a) * 3 + k] = s_rnew[s_slot[tid]][k];
+    }
+    for (int idx = tid; idx < cnt * cnt; idx += kBlock) {
+        const int i = idx / cnt, j = idx % cnt;
+        if (j < i) v.wG[((size_t)w * K + i) * K + j] = s_G[i][j];
+    }
+    for (int idx = tid; idx < cnt * nc; idx += kBlock) {
+        const int i = idx / nc, j = idx % nc;
+        v.tmat[((size_t)w * K + i) * Q + j] = s_T[i][j];
+    }
+    if (tid == 0) {
+        v.cnt[(size_t)2 * v.W + w] = cnt;
+        v.cur[2 * w] = dec + ndec;
+        v.cur[2 * w + 1] = dec + nc;
+        v.cur[2 * v.W + w] = dec;  // start of this round's candidates, for the column kernel
+    }
+    // Jastrow sums of the candidates left for later rounds: add this round's moves
+    if (v.use_j2 && tid >= ndec && tid < nc) {
+        double d = 0.0;
+        for (int j = 0; j < cnt; ++j) {
+            const int sj = s_slot[j];
+            d += pair_change(v, s_rnew[tid], s_rold[tid], s_rnew[sj], s_rold[sj]);
+        }
+        v.jd[(size_t)w * Q + (dec + tid) % Q] = s_jd[tid] + d;
+    }
+}
+
+// Columns of the accepted moves: c_a = sum_i T[a][i] c0_i for a < cnt (FP64 sums
+// of exact products, rounded to T).  One wave per walker and 64 orbitals.
+template <typename T>
+__global__ __launch_bounds__(64) void k_cols(CrowdView<T> v, int spin)
+{
+    constexpr int D = kMaxDelay, QM = kMaxCand;
+    __shared__ double s_T[D][QM + 1];
+    const int n = v.n, K = v.K, Q = v.Q;
+    const int nlb = (n + 63) / 64;
+    const int w = blockIdx.x / nlb, l = (blockIdx.x % nlb) * 64 + threadIdx.x;
+    const int cnt = v.cnt[(size_t)2 * v.W + w];
+    if (cnt <= 0 || cnt > K) return;
+    const int dec = v.cur[2 * v.W + w];
+    const int nc = (dec + Q < n ? dec + Q : n) - dec;
+    for (int idx = threadIdx.x; idx < cnt * nc; idx += 64)
+        s_T[idx / nc][idx % nc] = v.tmat[((size_t)w * K + idx / nc) * Q + idx % nc];
+    __syncthreads();
+    if (l >= n) return;
+    const T* Mw = v.M + ((size_t)w * 2 + spin) * n * (size_t)n;
+    double acc[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) acc[a] = 0.0;
+    for (int i = 0; i < nc; ++i) {
+        const double c = (double)Mw[(size_t)(dec + i) * n + l];
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+            if (a < cnt) acc[a] = fma(s_T[a][i], c, acc[a]);
+    }
+    T* Cw = v.Cbuf + (size_t)w * K * n;
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+        if (a < cnt) Cw[(size_t)a * n + l] = (T)acc[a];
+}
+
+__global__ void k_cursor_reset(int* cur, int W)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < 2 * W) cur[i] = 0;
+}
+
+int batch_rounds(int n, int K) { return (n + K - 1) / K; }
+
+int batch_candidates(int n, int K)
+{
+    int q = 2 * K + 8;
+    if (q > kMaxCand) q = kMaxCand;
+    return q < n ? q : n;
+}
+
+template <typename T>
+void launch_batch_vgl(const CrowdView<T>& v, int spin, bool block_start, hipStream_t s)
+{
+    if (block_start) hipLaunchKernelGGL(k_cursor_reset, dim3((2 * v.W + 255) / 256), dim3(256), 0, s, v.cur, v.W);
+    const int pp = batch_pp(v.n, sizeof(T));
+    const int nb = (v.W * v.Q + pp - 1) / pp;
+    hipLaunchKernelGGL(k_prop_vgl<T>, dim3(nb), dim3(batch_threads(v.n, sizeof(T))), 0, s, v, spin, pp);
+}
+
+template <typename T>
+void launch_batch_decide(const CrowdView<T>& v, int spin, hipStream_t s)
+{
+    const int pb = (v.Q + kPB - 1) / kPB;
+    hipLaunchKernelGGL(k_pmat<T>, dim3(v.W * pb * pb), dim3(64), 0, s, v, spin);
+    hipLaunchKernelGGL(k_decide<T>, dim3(v.W), dim3(kBlock), 0, s, v, spin);
+    hipLaunchKernelGGL(k_cols<T>, dim3(v.W * ((v.n + 63) / 64)), dim3(64), 0, s, v, spin);
+}
+
+template void launch_batch_vgl<float>(const CrowdView<float>&, int, bool, hipStream_t);
+template void launch_batch_vgl<double>(const CrowdView<double>&, int, bool, hipStream_t);
+template void launch_batch_decide<float>(const CrowdView<float>&, int, hipStream_t);
+template void launch_batch_decide<double>(const CrowdView<double>&, int, hipStream_t);
+
+}  // namespace cq

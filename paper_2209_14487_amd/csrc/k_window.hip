@@ -85,7 +85,7 @@ __global__ __launch_bounds__(512) void k_window(CrowdView<T> v, int e0, int nmov
     const int rs = v.prm->rec_sweep;
     const double sigma = v.prm->sigma;
     const T* Mspin = v.M + ((size_t)w * 2 + spin) * n * (size_t)n;
-    T* stage = v.stage + (size_t)w * K * 5 * n;
+    T* stage = v.stage + (size_t)w * v.Q * 5 * n;
     T* Cb = v.Cbuf + (size_t)w * K * n;
     const int prop_wave = nw > 1 ? 1 : 0;  // the wave that prepares the next move's stencil
 
@@ -328,6 +328,7 @@ __global__ __launch_bounds__(512) void k_window(CrowdView<T> v, int e0, int nmov
     // hand the window to the update kernel
     if (tid < cnt) {
         v.welec[(size_t)w * K + tid] = s_wel[tid];
+        v.wslot[(size_t)w * K + tid] = tid;
         v.wrho[(size_t)w * K + tid] = s_rho[tid];
     }
     for (int idx = tid; idx < cnt * cnt; idx += nt) {

@@ -114,7 +114,7 @@ def compare_fp64(gpu, ref, sweeps, ne, tol=1e-10):
     return div
 
 
-PATHS = ["multi", "window"]
+PATHS = ["multi", "window", "batch"]
 
 
 @pytest.mark.parametrize("path", PATHS)
@@ -156,7 +156,8 @@ def test_c2_shape_fp64_delayed_ranks_match_oracle(k, path):
 
 
 @pytest.mark.parametrize("k,recompute,path", [(1, 2, "window"), (8, 2, "window"), (32, 0, "window"),
-                                              (8, 2, "multi")])
+                                              (8, 2, "multi"), (1, 2, "batch"), (8, 2, "batch"),
+                                              (32, 0, "batch")])
 def test_c2_mixed_precision_on_oracle_trajectory(k, recompute, path):
     """C2 mixed precision (FP32 table, FP32 inverse and dots, FP64 log|det| and sums) follows
     the oracle's decisions; its own ratios stay within 1e-4 relative of the FP64 oracle, its
@@ -240,7 +241,8 @@ def test_graph_replay_equals_eager_launches(path):
 
 
 @pytest.mark.parametrize("precision,k,path", [("fp64", 1, "multi"), ("fp64", 16, "multi"), ("mixed", 32, "multi"),
-                                              ("fp64", 16, "window"), ("mixed", 32, "window")])
+                                              ("fp64", 16, "window"), ("mixed", 32, "window"),
+                                              ("fp64", 1, "batch"), ("fp64", 32, "batch"), ("mixed", 32, "batch")])
 def test_n256_blocked_inverse_and_multichunk_sweep(precision, k, path):
     """C3 system size (256+256, L=20, 64^3): blocked FP64 Gauss-Jordan set-up, multi-workgroup
     orbital chunks and one full sweep, on 3 walkers."""
@@ -271,6 +273,25 @@ def test_n256_blocked_inverse_and_multichunk_sweep(precision, k, path):
     crowd.close()
 
 
+@pytest.mark.parametrize("sigma,k", [(0.01, 8), (0.01, 32), (0.5, 16)])
+def test_batch_rounds_at_extreme_acceptance(sigma, k):
+    """Batched path at high acceptance (0.9 at sigma = 0.01: every round closes its window after
+    exactly k accepted moves, so a spin block needs nearly all of its N / k rounds) and with
+    windows cut short (k = 16 at 0.43 acceptance: the 32 candidates of a spin block run out
+    before 16 are accepted): FP64 against the oracle, all decisions, ratios and energies."""
+    n, L, G, W, S = 32, 10.0, 48, 24, 2
+    g, o = make_pair(n, L, G, 1002, coef_seed=1002)
+    R0 = start_positions(1002, W, 2 * n, L)
+    crowd = cq.Crowd(g, W, precision="fp64", delay_rank=k, seed=1002, path="batch")
+    gpu = run_gpu(crowd, R0, S, sigma)
+    ref = orc.vmc(o, R0, S, sigma=sigma)
+    compare_fp64(gpu, ref, S, 2 * n)
+    acc = gpu["acc"].mean()
+    print("   sigma %.2f k %d: acceptance %.3f" % (sigma, k, acc))
+    assert (acc > 0.85) if sigma < 0.1 else (acc < 0.6)
+    crowd.close()
+
+
 def test_singular_start_is_reported():
     """Two same-spin electrons at one position make A singular: CQ_ESINGULAR names the walker."""
     n, L, G, W = 4, 5.0, 16, 3
@@ -289,9 +310,10 @@ def test_singular_start_is_reported():
 
 
 def test_paths_agree():
-    """The per-move multi-workgroup path and the walker-resident window path compute the same
-    chain: identical decisions, and ratios, log|det| and energies within the FP64 parity bar
-    (their sums are grouped differently, so they agree to rounding, not bit for bit)."""
+    """The per-move multi-workgroup path, the walker-resident window path and the batched-window
+    path compute the same chain: identical decisions, and ratios, log|det| and energies within
+    the FP64 parity bar (their sums are grouped differently, so they agree to rounding, not bit
+    for bit)."""
     n, L, G, W, S = 32, 10.0, 48, 20, 3
     g, _ = make_pair(n, L, G, 1002, coef_seed=1002)
     R0 = start_positions(1002, W, 2 * n, L)
@@ -300,8 +322,9 @@ def test_paths_agree():
         c = cq.Crowd(g, W, precision="fp64", delay_rank=8, seed=1002, path=path)
         out.append(run_gpu(c, R0, S, 0.5))
         c.close()
-    a, b = out
-    assert np.array_equal(a["acc"], b["acc"])
-    assert np.all(np.abs(a["rho"] - b["rho"]) <= 1e-10 * np.maximum(1.0, np.abs(b["rho"])))
-    assert np.all(np.abs(a["logdet"] - b["logdet"]) <= 1e-10 * np.maximum(1.0, np.abs(b["logdet"])))
-    assert np.all(np.abs(a["eloc"] - b["eloc"]) <= 1e-10 * np.maximum(1.0, np.abs(b["eloc"])))
+    b = out[0]
+    for a in out[1:]:
+        assert np.array_equal(a["acc"], b["acc"])
+        assert np.all(np.abs(a["rho"] - b["rho"]) <= 1e-10 * np.maximum(1.0, np.abs(b["rho"])))
+        assert np.all(np.abs(a["logdet"] - b["logdet"]) <= 1e-10 * np.maximum(1.0, np.abs(b["logdet"])))
+        assert np.all(np.abs(a["eloc"] - b["eloc"]) <= 1e-10 * np.maximum(1.0, np.abs(b["eloc"])))
