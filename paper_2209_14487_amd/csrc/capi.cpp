@@ -73,8 +73,10 @@ struct cq_crowd {
     int* wslot = nullptr;
     void* stage = nullptr;
     void* Cbuf = nullptr;
+    float* ct = nullptr;
     double* wrho = nullptr;
     double* wG = nullptr;
+    double* wlinv = nullptr;
     double* beta = nullptr;
     int* pend = nullptr;
     double* part = nullptr;
@@ -137,8 +139,11 @@ cq::CrowdView<T> view(const cq_crowd* c)
     v.wslot = c->wslot;
     v.stage = (T*)c->stage;
     v.Cbuf = (T*)c->Cbuf;
+    // the batched path hands the matrix-core update its columns transposed
+    v.ct = (sizeof(T) == 4 && c->path == CQ_PATH_BATCH && cq::flush_mfma_fits(c->n)) ? c->ct : nullptr;
     v.wrho = c->wrho;
     v.wG = c->wG;
+    v.wlinv = c->wlinv;
     v.beta = c->beta;
     v.pend = c->pend;
     v.part = c->part;
@@ -214,7 +219,7 @@ void enqueue_sweep(cq_crowd* c)
                 cq::launch_batch_decide<T>(v, spin, c->stream);
                 timed_end(c, CQ_KERNEL_RESOLVE);
                 timed_begin(c, CQ_KERNEL_UPDATE);
-                cq::launch_flush<T>(v, spin, c->stream);
+                cq::launch_flush<T>(v, spin, c->stream, true);
                 timed_end(c, CQ_KERNEL_UPDATE);
             }
         timed_begin(c, CQ_KERNEL_ENERGY);
@@ -566,8 +571,10 @@ cq_status cq_crowd_create(const cq_system* const* systems, const int* walkers_pe
         {(void**)&c->cur, sizeof(int) * W * 3},
         {&c->stage, es * W * c->Q * 5 * n},
         {&c->Cbuf, es * W * K * n},
+        {(void**)&c->ct, sizeof(float) * W * n * cq::kMaxDelay},
         {(void**)&c->wrho, sizeof(double) * W * K},
         {(void**)&c->wG, sizeof(double) * W * K * K},
+        {(void**)&c->wlinv, sizeof(double) * W * K * K},
         {(void**)&c->beta, sizeof(double) * W * K},
         {(void**)&c->pend, sizeof(int) * W},
         {(void**)&c->part, sizeof(double) * 2 * W * C * cq::part_stride(K)},

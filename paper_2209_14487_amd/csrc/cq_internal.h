@@ -73,8 +73,10 @@ struct CrowdView {
     int* wslot;          // [W][K] stage slot of accepted move m
     T* stage;
     T* Cbuf;
+    float* ct;           // [W][N][32] columns transposed (Ct[k][m]) for the matrix-core update, or null
     double* wrho;
     double* wG;
+    double* wlinv;       // [W][K][K] inverse of the window's triangle (G below, rho on the diagonal)
     double* beta;
     int* pend;
     double* part;
@@ -120,7 +122,10 @@ template <typename T> void launch_batch_vgl(const CrowdView<T>& v, int spin, boo
 template <typename T> void launch_batch_decide(const CrowdView<T>& v, int spin, hipStream_t s);
 int batch_rounds(int n, int K);      // rounds per spin block (enough when every move is accepted)
 int batch_candidates(int n, int K);  // candidates per round, Q
-template <typename T> void launch_flush(const CrowdView<T>& v, int spin, hipStream_t s);
+// linv_ready: the window's L^-1 is already in wlinv (the batched path forms it)
+template <typename T> void launch_flush(const CrowdView<T>& v, int spin, hipStream_t s, bool linv_ready = false);
+bool flush_mfma_fits(int n);  // the FP32 matrix-core update handles this N
+void launch_flush_mfma(const CrowdView<float>& v, int spin, hipStream_t s, bool linv_ready);
 template <typename T> void launch_energy(const CrowdView<T>& v, hipStream_t s);
 template <typename T> void launch_inverse(const CrowdView<T>& v, const InvWork& wk, hipStream_t s);
 void launch_sweep_end(Params* prm, hipStream_t s);

@@ -228,17 +228,22 @@ __global__ __launch_bounds__(kBlock) void k_prop_vgl(CrowdView<T> v, int spin, i
     }
 }
 
-// P of one walker's candidates, in 16 x 16 blocks (one wave each; lane = 2 x 2
-// outputs).  Products of the stored values are formed exactly in FP64 and summed
-// in orbital order.
-constexpr int kPB = 16;   // block edge
-constexpr int kPT = 64;   // orbitals per LDS tile
+// P of one walker's candidates in 16 x 16 blocks on the FP64 matrix cores
+// (v_mfma_f64_16x16x4f64): the stored T values are widened to FP64, so every
+// product is exact and the sums are FP64.  Operand layout: lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16]; the result is D[l / 16 + 4 v][l % 16].
+// The 4 k values of a step are taken as k0 + VEC q + s (q = l / 16, s = step
+// within a 16-byte load), the same on both operands.  The 4 waves of a
+// workgroup take alternate k chunks; their partial blocks are added in order.
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+constexpr int kPB = 16;  // block edge
 
 template <typename T>
-__global__ __launch_bounds__(64) void k_pmat(CrowdView<T> v, int spin)
+__global__ __launch_bounds__(kBlock) void k_pmat(CrowdView<T> v, int spin)
 {
-    __shared__ T sU[kPB][kPT + 1];
-    __shared__ T sC[kPB][kPT + 1];
+    constexpr int VEC = 16 / sizeof(T);
+    constexpr int KC = 4 * VEC;  // k values per chunk
+    __shared__ double sP[4][kPB][kPB + 1];
     const int Q = v.Q, n = v.n;
     const int nb = (Q + kPB - 1) / kPB;
     const int w = blockIdx.x / (nb * nb), blk = blockIdx.x % (nb * nb);
@@ -246,38 +251,41 @@ __global__ __launch_bounds__(64) void k_pmat(CrowdView<T> v, int spin)
     const int dec = v.cur[2 * w];
     const int nc = (dec + Q < n ? dec + Q : n) - dec;
     if (bi * kPB >= nc || bj * kPB >= nc) return;
-    const int lane = threadIdx.x;
-    const int li = (lane >> 3) * 2, lj = (lane & 7) * 2;
-    const T* Mw = v.M + ((size_t)w * 2 + spin) * n * (size_t)n;
-    double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
-    for (int l0 = 0; l0 < n; l0 += kPT) {
-        for (int idx = lane; idx < kPB * kPT; idx += 64) {
-            const int r = idx / kPT, c = idx % kPT, l = l0 + c;
-            const int ci = bi * kPB + r, cj = bj * kPB + r;
-            const bool okl = l < n;
-            sU[r][c] = (okl && ci < nc) ? v.stage[((size_t)w * Q + (dec + ci) % Q) * 5 * n + l] : (T)0;
-            sC[r][c] = (okl && cj < nc) ? Mw[(size_t)(dec + cj) * n + l] : (T)0;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r = lane & 15, q = lane >> 4;
+    const int ci = bi * kPB + r, cj = bj * kPB + r;
+    const T* urow = v.stage + ((size_t)w * Q + (dec + (ci < nc ? ci : 0)) % Q) * 5 * (size_t)n;
+    const T* crow = v.M + (((size_t)w * 2 + spin) * n + dec + (cj < nc ? cj : 0)) * (size_t)n;
+    f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int k0 = wave * KC; k0 < n; k0 += 4 * KC) {
+        T u[VEC], c[VEC];
+        const int kk = k0 + VEC * q;
+        if (kk < n && ci < nc) {
+            load16(urow + kk, u);
+        } else {
+#pragma unroll
+            for (int s = 0; s < VEC; ++s) u[s] = (T)0;
         }
-        __syncthreads();
-        const int lim = n - l0 < kPT ? n - l0 : kPT;
-        for (int c = 0; c < lim; ++c) {
-            const double u0 = (double)sU[li][c], u1 = (double)sU[li + 1][c];
-            const double c0 = (double)sC[lj][c], c1 = (double)sC[lj + 1][c];
-            acc[0][0] = fma(u0, c0, acc[0][0]);
-            acc[0][1] = fma(u0, c1, acc[0][1]);
-            acc[1][0] = fma(u1, c0, acc[1][0]);
-            acc[1][1] = fma(u1, c1, acc[1][1]);
+        if (kk < n && cj < nc) {
+            load16(crow + kk, c);
+        } else {
+#pragma unroll
+            for (int s = 0; s < VEC; ++s) c[s] = (T)0;
         }
-        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < VEC; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64((double)u[s], (double)c[s], acc, 0, 0, 0);
     }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) sP[wave][q + 4 * t][r] = acc[t];
+    __syncthreads();
     double* P = v.pmat + (size_t)w * Q * Q;
-#pragma unroll
-    for (int r = 0; r < 2; ++r)
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            const int i = bi * kPB + li + r, j = bj * kPB + lj + c;
-            if (i < nc && j < nc) P[(size_t)i * Q + j] = acc[r][c];
-        }
+    {
+        const int i = tid >> 4, j = tid & 15;
+        const double sum = ((sP[0][i][j] + sP[1][i][j]) + sP[2][i][j]) + sP[3][i][j];
+        const int gi = bi * kPB + i, gj = bj * kPB + j;
+        if (gi < nc && gj < nc) P[(size_t)gi * Q + gj] = sum;
+    }
 }
 
 // Jastrow pair-term change for candidate (r_old -> r_new) when another electron
@@ -290,19 +298,30 @@ __device__ __forceinline__ double pair_change(const CrowdView<T>& v, const doubl
            (pair_j2(v, v.a_par, ro, q) - pair_j2(v, v.a_par, ro, o));
 }
 
+// Decision kernel.  Everything the sequential loop reads sits in LDS (dynamic,
+// about 113 KB at Q = 64): P, the Jastrow pair changes of every candidate pair,
+// T, X[a][i] = u_i . c_a (the accepted columns against every candidate), and
+// L^-1 of the window's triangle (G below the diagonal, rho on it), so that
+//     beta = L^-1 y,  y_a = P[s_a][m]        (a product, not a substitution)
+// and every per-candidate quantity is a lookup or an independent sum.
+struct DecideLds {
+    static constexpr int QM = kMaxCand, D = kMaxDelay;
+    double P[QM][QM + 1];
+    double PC[QM][QM + 1];   // PC[m][s]: Jastrow change of candidate m when s (< m) moves
+    double T[D][QM + 1];
+    double X[D][QM + 1];
+    double Li[D][D + 1];
+    double u[QM], jd[QM];
+    double rold[QM][3], rnew[QM][3];
+    int slot[D];
+    int cnt, ndec;
+};
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_decide(CrowdView<T> v, int spin)
 {
-    constexpr int D = kMaxDelay, QM = kMaxCand;
-    __shared__ double s_P[QM][QM + 1];
-    __shared__ double s_T[D][QM + 1];
-    __shared__ double s_G[D][D + 1];
-    __shared__ double s_rinv[D];
-    __shared__ double s_u[QM], s_jd[QM];
-    __shared__ double s_rold[QM][3], s_rnew[QM][3];
-    __shared__ int s_slot[D];
-    __shared__ int s_cnt, s_ndec;
-
+    extern __shared__ unsigned char dsm[];
+    DecideLds& S = *reinterpret_cast<DecideLds*>(dsm);
     const int w = blockIdx.x;
     const int n = v.n, K = v.K, Q = v.Q;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -317,44 +336,47 @@ __global__ __launch_bounds__(kBlock) void k_decide(CrowdView<T> v, int spin)
     }
     // candidates: P, uniforms, Jastrow sums, positions
     const double* Pw = v.pmat + (size_t)w * Q * Q;
-    for (int idx = tid; idx < nc * nc; idx += kBlock) s_P[idx / nc][idx % nc] = Pw[(size_t)(idx / nc) * Q + idx % nc];
+    for (int idx = tid; idx < nc * nc; idx += kBlock) S.P[idx / nc][idx % nc] = Pw[(size_t)(idx / nc) * Q + idx % nc];
     if (tid < nc) {
         const int slot = (dec + tid) % Q;
-        s_u[tid] = accept_uniform(v.seed, v.uid[w], step, (uint32_t)(e0 + tid));
-        s_jd[tid] = v.jd[(size_t)w * Q + slot];
+        S.u[tid] = accept_uniform(v.seed, v.uid[w], step, (uint32_t)(e0 + tid));
+        S.jd[tid] = v.jd[(size_t)w * Q + slot];
         for (int k = 0; k < 3; ++k) {
-            s_rold[tid][k] = v.R[((size_t)w * v.ne + e0 + tid) * 3 + k];
-            s_rnew[tid][k] = v.rprop[((size_t)w * Q + slot) * 3 + k];
+            S.rold[tid][k] = v.R[((size_t)w * v.ne + e0 + tid) * 3 + k];
+            S.rnew[tid][k] = v.rprop[((size_t)w * Q + slot) * 3 + k];
         }
     }
     __syncthreads();
+    for (int idx = tid; idx < kMaxDelay * (kMaxDelay + 1); idx += kBlock) (&S.Li[0][0])[idx] = 0.0;
+    // Jastrow pair changes of all candidate pairs (s < m)
+    for (int idx = tid; idx < nc * nc; idx += kBlock) {
+        const int m = idx / nc, sx = idx % nc;
+        if (sx < m) S.PC[m][sx] = v.use_j2 ? pair_change(v, S.rnew[m], S.rold[m], S.rnew[sx], S.rold[sx]) : 0.0;
+    }
+    __syncthreads();
 
-    // decisions in electron order (wave 0; lane a <-> accepted move a for the
-    // recurrences, lane i <-> candidate i for the rows of T)
+    // decisions in electron order (wave 0; lane a <-> accepted move a for beta and
+    // x, lane i <-> candidate i for the new rows of T and X)
     if (wave == 0) {
         double ld = v.logdet[w * 2 + spin];
         int sg = v.sign[w * 2 + spin];
         int cnt = 0, m = 0;
         for (; m < nc && cnt < K; ++m) {
             const bool mine = lane < cnt;
-            const int sa = mine ? s_slot[lane] : 0;
-            // x_a = u_m . c_a = sum_i T[a][i] P[m][i]  (T[a][i] = 0 for i > s_a)
-            double x = 0.0;
-            if (mine)
-                for (int i = 0; i <= sa; ++i) x += s_T[lane][i] * s_P[m][i];
-            // beta_a by forward substitution over the accepted moves
-            double t = mine ? s_P[sa][m] : 0.0, my_beta = 0.0;
-            for (int j = 0; j < cnt; ++j) {
-                const double bj = dpp::lane(t, j) * s_rinv[j];
-                if (lane == j) my_beta = bj;
-                if (lane > j && mine) t -= bj * s_G[lane][j];
-            }
-            const double rho = s_P[m][m] - wave_sum(mine ? my_beta * x : 0.0);
-            double cj = 0.0;
-            if (v.use_j2 && mine) cj = pair_change(v, s_rnew[m], s_rold[m], s_rnew[sa], s_rold[sa]);
-            const double dlnj = s_jd[m] + wave_sum(cj);
+            const int sa = mine ? S.slot[lane] : 0;
+            const double y = mine ? S.P[sa][m] : 0.0;
+            const double x = mine ? S.X[lane][m] : 0.0;
+            const double pc = mine ? S.PC[m][sa] : 0.0;
+            // beta_a = sum_{j<=a} Li[a][j] y_j  (Li is zero above the diagonal)
+            const int arow = mine ? lane : 0;
+            double beta = 0.0;
+#pragma unroll 8
+            for (int j = 0; j < cnt; ++j) beta += S.Li[arow][j] * dpp::lane(y, j);
+            if (!mine) beta = 0.0;
+            const double rho = S.P[m][m] - wave_sum(beta * x);
+            const double dlnj = S.jd[m] + wave_sum(pc);
             const double prob = rho * rho * exp(2.0 * dlnj);
-            int acc = s_u[m] < prob;
+            int acc = S.u[m] < prob;
             const size_t ri = ((size_t)rs * v.ne + e0 + m) * v.W + w;
             if (v.forced && rs < v.prm->forced_cap) acc = v.forced[ri] != 0;
             if (lane == 0 && rs < v.prm->rec_cap) {
@@ -364,16 +386,27 @@ __global__ __launch_bounds__(kBlock) void k_decide(CrowdView<T> v, int spin)
                 v.rec_acc[ri] = (uint8_t)acc;
             }
             if (acc) {
-                if (mine) s_G[cnt][lane] = x;
-                // T[cnt][i] = delta(i, m) - sum_a beta_a T[a][i]   (lane i)
-                for (int i = lane; i < nc; i += 64) {
-                    double tc = i == m ? 1.0 : 0.0;
-                    for (int aa = 0; aa < cnt; ++aa) tc -= dpp::lane(my_beta, aa) * s_T[aa][i];
-                    s_T[cnt][i] = tc;
-                }
+                const double rinv = 1.0 / rho;
+                if (mine) v.wG[((size_t)w * K + cnt) * K + lane] = x;  // G[cnt][a] = u_m . c_a
+                // new row of L^-1: Li[cnt][j] = -sum_{t=j}^{cnt-1} x_t Li[t][j] / rho  (lane j)
+                const int lcol = lane < kMaxDelay ? lane : 0;
+                double li = 0.0;
+#pragma unroll 8
+                for (int t = 0; t < cnt; ++t) li += dpp::lane(x, t) * S.Li[t][lcol];
+                if (mine) S.Li[cnt][lane] = -li * rinv;
+                if (lane == cnt) S.Li[cnt][cnt] = rinv;
+                // new row of T: T[cnt][i] = delta(i, m) - sum_a beta_a T[a][i]   (lane i)
+                double tc = lane == m ? 1.0 : 0.0;
+#pragma unroll 8
+                for (int aa = 0; aa < cnt; ++aa) tc -= dpp::lane(beta, aa) * S.T[aa][lane];
+                S.T[cnt][lane] = lane < nc ? tc : 0.0;
+                // new row of X: X[cnt][i] = sum_{q<=m} T[cnt][q] P[i][q]   (lane i)
+                double xc = 0.0;
+#pragma unroll 8
+                for (int q = 0; q <= m; ++q) xc += S.T[cnt][q] * S.P[lane][q];
+                S.X[cnt][lane] = xc;
                 if (lane == 0) {
-                    s_rinv[cnt] = 1.0 / rho;
-                    s_slot[cnt] = m;
+                    S.slot[cnt] = m;
                     v.wrho[(size_t)w * K + cnt] = rho;
                 }
                 ld += log(fabs(rho));
@@ -386,27 +419,27 @@ __global__ __launch_bounds__(kBlock) void k_decide(CrowdView<T> v, int spin)
             v.sign[w * 2 + spin] = sg;
             v.nacc[w] += cnt;
             v.nprop[w] += m;
-            s_cnt = cnt;
-            s_ndec = m;
+            S.cnt = cnt;
+            S.ndec = m;
         }
     }
     __syncthreads();
-    const int cnt = s_cnt, ndec = s_ndec;
+    const int cnt = S.cnt, ndec = S.ndec;
 
     // the window for the update kernels, the accepted positions, the cursors
     if (tid < cnt) {
-        const int a = dec + s_slot[tid];
+        const int a = dec + S.slot[tid];
         v.welec[(size_t)w * K + tid] = a;
         v.wslot[(size_t)w * K + tid] = a % Q;
-        for (int k = 0; k < 3; ++k) v.R[((size_t)w * v.ne + spin * n + a) * 3 + k] = s_rnew[s_slot[tid]][k];
-    }
-    for (int idx = tid; idx < cnt * cnt; idx += kBlock) {
-        const int i = idx / cnt, j = idx % cnt;
-        if (j < i) v.wG[((size_t)w * K + i) * K + j] = s_G[i][j];
+        for (int k = 0; k < 3; ++k) v.R[((size_t)w * v.ne + spin * n + a) * 3 + k] = S.rnew[S.slot[tid]][k];
     }
     for (int idx = tid; idx < cnt * nc; idx += kBlock) {
         const int i = idx / nc, j = idx % nc;
-        v.tmat[((size_t)w * K + i) * Q + j] = s_T[i][j];
+        v.tmat[((size_t)w * K + i) * Q + j] = S.T[i][j];
+    }
+    for (int idx = tid; idx < cnt * cnt; idx += kBlock) {
+        const int i = idx / cnt, j = idx % cnt;
+        v.wlinv[((size_t)w * K + i) * K + j] = S.Li[i][j];
     }
     if (tid == 0) {
         v.cnt[(size_t)2 * v.W + w] = cnt;
@@ -417,41 +450,58 @@ __global__ __launch_bounds__(kBlock) void k_decide(CrowdView<T> v, int spin)
     // Jastrow sums of the candidates left for later rounds: add this round's moves
     if (v.use_j2 && tid >= ndec && tid < nc) {
         double d = 0.0;
-        for (int j = 0; j < cnt; ++j) {
-            const int sj = s_slot[j];
-            d += pair_change(v, s_rnew[tid], s_rold[tid], s_rnew[sj], s_rold[sj]);
-        }
-        v.jd[(size_t)w * Q + (dec + tid) % Q] = s_jd[tid] + d;
+        for (int j = 0; j < cnt; ++j) d += S.PC[tid][S.slot[j]];
+        v.jd[(size_t)w * Q + (dec + tid) % Q] = S.jd[tid] + d;
     }
 }
 
 // Columns of the accepted moves: c_a = sum_i T[a][i] c0_i for a < cnt (FP64 sums
-// of exact products, rounded to T).  One wave per walker and 64 orbitals.
+// of exact products, rounded to T).  One thread per orbital; the loads of 8
+// candidate columns are issued together.
 template <typename T>
-__global__ __launch_bounds__(64) void k_cols(CrowdView<T> v, int spin)
+__global__ __launch_bounds__(kBlock) void k_cols(CrowdView<T> v, int spin)
 {
     constexpr int D = kMaxDelay, QM = kMaxCand;
-    __shared__ double s_T[D][QM + 1];
+    __shared__ double s_T[D][QM + 8];
     const int n = v.n, K = v.K, Q = v.Q;
-    const int nlb = (n + 63) / 64;
-    const int w = blockIdx.x / nlb, l = (blockIdx.x % nlb) * 64 + threadIdx.x;
+    const int nlb = (n + kBlock - 1) / kBlock;
+    const int w = blockIdx.x / nlb, l = (blockIdx.x % nlb) * kBlock + threadIdx.x;
     const int cnt = v.cnt[(size_t)2 * v.W + w];
     if (cnt <= 0 || cnt > K) return;
     const int dec = v.cur[2 * v.W + w];
     const int nc = (dec + Q < n ? dec + Q : n) - dec;
-    for (int idx = threadIdx.x; idx < cnt * nc; idx += 64)
-        s_T[idx / nc][idx % nc] = v.tmat[((size_t)w * K + idx / nc) * Q + idx % nc];
+    // T padded with zeros (rows a >= cnt, columns i >= nc): no branches in the sums
+    for (int idx = threadIdx.x; idx < D * QM; idx += kBlock) {
+        const int a = idx / QM, i = idx % QM;
+        s_T[a][i] = (a < cnt && i < nc) ? v.tmat[((size_t)w * K + a) * Q + i] : 0.0;
+    }
     __syncthreads();
     if (l >= n) return;
-    const T* Mw = v.M + ((size_t)w * 2 + spin) * n * (size_t)n;
+    const T* Mw = v.M + (((size_t)w * 2 + spin) * n + dec) * (size_t)n + l;
     double acc[D];
 #pragma unroll
     for (int a = 0; a < D; ++a) acc[a] = 0.0;
-    for (int i = 0; i < nc; ++i) {
-        const double c = (double)Mw[(size_t)(dec + i) * n + l];
+    for (int i0 = 0; i0 < nc; i0 += 8) {
+        double c[8];
 #pragma unroll
-        for (int a = 0; a < D; ++a)
-            if (a < cnt) acc[a] = fma(s_T[a][i], c, acc[a]);
+        for (int q = 0; q < 8; ++q) c[q] = (double)Mw[(size_t)(i0 + q < nc ? i0 + q : 0) * n];
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+#pragma unroll
+            for (int a = 0; a < D; ++a) acc[a] = fma(s_T[a][i0 + q], c[q], acc[a]);
+    }
+    if constexpr (sizeof(T) == 4) {
+        if (v.ct) {  // transposed for the matrix-core update: 32 per row, zeros past cnt
+            float* dst = v.ct + ((size_t)w * n + l) * D;
+#pragma unroll
+            for (int g = 0; g < D / 4; ++g) {
+                float x[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) x[q] = 4 * g + q < cnt ? (float)acc[4 * g + q] : 0.0f;
+                store16(dst + 4 * g, x);
+            }
+            return;
+        }
     }
     T* Cw = v.Cbuf + (size_t)w * K * n;
 #pragma unroll
@@ -487,9 +537,15 @@ template <typename T>
 void launch_batch_decide(const CrowdView<T>& v, int spin, hipStream_t s)
 {
     const int pb = (v.Q + kPB - 1) / kPB;
-    hipLaunchKernelGGL(k_pmat<T>, dim3(v.W * pb * pb), dim3(64), 0, s, v, spin);
-    hipLaunchKernelGGL(k_decide<T>, dim3(v.W), dim3(kBlock), 0, s, v, spin);
-    hipLaunchKernelGGL(k_cols<T>, dim3(v.W * ((v.n + 63) / 64)), dim3(64), 0, s, v, spin);
+    hipLaunchKernelGGL(k_pmat<T>, dim3(v.W * pb * pb), dim3(kBlock), 0, s, v, spin);
+    static bool lds_set = false;  // opt in to more than 64 KB of LDS, once per type
+    if (!lds_set) {
+        (void)hipFuncSetAttribute((const void*)k_decide<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)sizeof(DecideLds));
+        lds_set = true;
+    }
+    hipLaunchKernelGGL(k_decide<T>, dim3(v.W), dim3(kBlock), sizeof(DecideLds), s, v, spin);
+    hipLaunchKernelGGL(k_cols<T>, dim3(v.W * ((v.n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, v, spin);
 }
 
 template void launch_batch_vgl<float>(const CrowdView<float>&, int, bool, hipStream_t);

@@ -1,0 +1,231 @@
+// Rank-k inverse update on the FP32 matrix cores (mixed precision, N % 32 == 0,
+// N <= 1024).
+//
+// Same update as k_flush_vec: with u_m the accepted rows, c_m the columns just
+// before move m, rho_m the ratios and G[m][j] = u_m . c_j, every row a of
+// M = (A^-1)^T gets
+//     x_m = M[a] . u_m                                   (GEMM 1, X = M U^T)
+//     b_m = (x_m - sum_{j<m} b_j G[m][j] - delta(a, e_m)) / rho_m
+//     M[a] -= sum_m b_m c_m                              (GEMM 2, M -= B C)
+// The forward substitution is the same for every row: with L lower triangular,
+// L[m][j] = G[m][j] (j < m), L[m][m] = rho_m, it is b = L^-1 y, y_m = x_m -
+// delta(a, e_m).  k_window_linv forms L^-1 once per walker (FP64, one lane per
+// column), so the strip's 32 rows are solved in parallel.
+// One workgroup owns a strip of 32 rows of M for the whole update, so M is read
+// and written once.  The strip stays in registers as 32 x 32 tiles of M^T in the
+// accumulator layout of v_mfma_f32_32x32x2f32 (lane l holds strip row l % 32 and
+// the 16 columns 8 (v / 4) + 4 (l / 32) + v % 4 of the tile).  That layout is at
+// the same time the B operand of GEMM 1 (the two k values of step v are the
+// columns of half 0 and half 1) and the accumulator of GEMM 2, so neither product
+// moves the strip.  Each of the 4 waves holds every 4th tile; GEMM 1 partial
+// sums of the waves are added in a fixed order in LDS.
+#include "cq_device.h"
+#include "cq_internal.h"
+
+namespace cq {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int kStripTiles = 8;  // 32-column tiles per wave (N <= 4 * 8 * 32)
+
+__global__ __launch_bounds__(kBlock, 2) void k_flush_mfma(CrowdView<float> v, int spin)
+{
+    __shared__ float sX[4][32][33];   // per wave: partial X^T[m][i]
+    __shared__ float sB[32][33];      // b[i][m] (FP32 operand of GEMM 2)
+    __shared__ double sY[32][33];     // x[i][j] - delta(row0 + i, e_j)
+    __shared__ double sL[32][33];     // L^-1
+    __shared__ int wel[32], wsl[32];
+    const int n = v.n, K = v.K;
+    const int ntile = n / 32, nstrip = n / 32;
+    int w, strip;
+    xcd_map(blockIdx.x, nstrip, w, strip);
+    if (w >= v.W) return;
+    int cnt = v.cnt[(size_t)2 * v.W + w];
+    if (cnt > K) cnt = K;
+    if (cnt <= 0) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int h = lane >> 5, l32 = lane & 31;
+    if (tid < cnt) {
+        wel[tid] = v.welec[(size_t)w * K + tid];
+        const int sl = v.wslot[(size_t)w * K + tid];
+        if (sl < 0 || sl >= v.Q) atomicOr(&v.status[w], 2);
+        wsl[tid] = sl < 0 || sl >= v.Q ? 0 : sl;
+    }
+    __syncthreads();
+
+    // the accepted orbital rows of the window go to the A, G, L rows
+    for (int mm = strip; mm < cnt; mm += nstrip) {
+        const int ea = wel[mm];
+        if (ea < 0 || ea >= n) {
+            if (tid == 0) atomicOr(&v.status[w], 2);
+            continue;
+        }
+        const float* src = v.stage + ((size_t)w * v.Q + wsl[mm]) * 5 * (size_t)n;
+        float* dst = v.VGL + (((size_t)w * 2 + spin) * n + ea) * 5 * (size_t)n;
+        for (int i = tid * 4; i < 5 * n; i += kBlock * 4) {
+            float x[4];
+            load16(src + i, x);
+            store16(dst + i, x);
+        }
+    }
+
+    const int row0 = strip * 32;
+    float* Mb = v.M + (((size_t)w * 2 + spin) * n + row0) * (size_t)n;
+    f32x16 mt[kStripTiles];
+#pragma unroll
+    for (int tt = 0; tt < kStripTiles; ++tt) {
+        const int t = wave + 4 * tt;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) mt[tt][q] = 0.0f;
+        if (t < ntile) {
+            const float* src = Mb + (size_t)l32 * n + t * 32 + 4 * h;
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                float x[4];
+                load16(src + 8 * g, x);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) mt[tt][4 * g + q] = x[q];
+            }
+        }
+    }
+
+    // GEMM 1: X^T[m][i] = sum_k u_m[k] M[row0 + i][k] over this wave's tiles
+    f32x16 xacc;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) xacc[q] = 0.0f;
+    const float* urow = v.stage + ((size_t)w * v.Q + wsl[l32 < cnt ? l32 : 0]) * 5 * (size_t)n;
+#pragma unroll
+    for (int tt = 0; tt < kStripTiles; ++tt) {
+        const int t = wave + 4 * tt;
+        if (t < ntile) {
+            float u[16];
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                if (l32 < cnt) {
+                    load16(urow + t * 32 + 8 * g + 4 * h, &u[4 * g]);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) u[4 * g + q] = 0.0f;
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 16; ++q) xacc = __builtin_amdgcn_mfma_f32_32x32x2f32(u[q], mt[tt][q], xacc, 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) sX[wave][8 * (q >> 2) + 4 * h + (q & 3)][l32] = xacc[q];
+    __syncthreads();
+
+    // y[i][j] = x[i][j] - delta(row0 + i, e_j) in FP64, then
+    // b[i][m] = sum_{j<=m} Linv[m][j] y[i][j]
+    for (int idx = tid; idx < 32 * 32; idx += kBlock) {
+        const int i = idx >> 5, j = idx & 31;
+        if (j < cnt) {
+            const double x = (((double)sX[0][j][i] + (double)sX[1][j][i]) + (double)sX[2][j][i]) +
+                             (double)sX[3][j][i];
+            sY[i][j] = x - (row0 + i == wel[j] ? 1.0 : 0.0);
+            sL[i][j] = i < cnt ? v.wlinv[((size_t)w * K + i) * K + j] : 0.0;
+        }
+    }
+    __syncthreads();
+    for (int idx = tid; idx < 32 * 32; idx += kBlock) {
+        const int i = idx >> 5, m = idx & 31;
+        double b = 0.0;
+        if (m < cnt)
+            for (int j = 0; j <= m; ++j) b += sL[m][j] * sY[i][j];
+        sB[i][m] = (float)b;
+    }
+    __syncthreads();
+
+    // GEMM 2: M^T[k][i] -= sum_m c_m[k] b[i][m], moves m = 16 h + s.  With the
+    // columns stored transposed (Ct[k][m], 32 per row) a lane fetches the 16
+    // operands of a tile with 4 vector loads; otherwise one load per step.
+    const float* Ct = v.ct ? v.ct + ((size_t)w * n) * kMaxDelay : nullptr;
+    const float* Cw = v.Cbuf + (size_t)w * K * n;
+    auto fetch = [&](int t, float (&a)[16]) {
+        if (Ct) {
+            const float* src = Ct + (size_t)(t * 32 + l32) * kMaxDelay + 16 * h;
+#pragma unroll
+            for (int g = 0; g < 4; ++g) load16(src + 4 * g, &a[4 * g]);
+        } else {
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int m = 16 * h + q;
+                const float c = Cw[(size_t)(m < cnt ? m : 0) * n + t * 32 + l32];
+                a[q] = m < cnt ? c : 0.0f;
+            }
+        }
+    };
+    // software pipeline: the operands of the next tile load during this tile's MFMAs
+    float a[16], an[16];
+    if (wave < ntile) fetch(wave, a);
+#pragma unroll
+    for (int tt = 0; tt < kStripTiles; ++tt) {
+        const int t = wave + 4 * tt;
+        if (t < ntile) {
+            if (tt + 1 < kStripTiles && t + 4 < ntile) fetch(t + 4, an);
+            // operands past cnt are zero (Ct and b are zero-padded), so all 16 steps run
+#pragma unroll
+            for (int q = 0; q < 16; ++q)
+                mt[tt] = __builtin_amdgcn_mfma_f32_32x32x2f32(-a[q], sB[l32][16 * h + q], mt[tt], 0, 0, 0);
+#pragma unroll
+            for (int q = 0; q < 16; ++q) a[q] = an[q];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int tt = 0; tt < kStripTiles; ++tt) {
+        const int t = wave + 4 * tt;
+        if (t < ntile) {
+            float* dst = Mb + (size_t)l32 * n + t * 32 + 4 * h;
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                float x[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) x[q] = mt[tt][4 * g + q];
+                store16(dst + 8 * g, x);
+            }
+        }
+    }
+}
+
+// L^-1 of each walker's window (lower triangular, FP64): lane j forms column j
+// by forward substitution down the rows.
+__global__ __launch_bounds__(64) void k_window_linv(CrowdView<float> v)
+{
+    __shared__ double sL[32][33];
+    __shared__ double sX[32][33];
+    const int w = blockIdx.x, K = v.K, lane = threadIdx.x;
+    int cnt = v.cnt[(size_t)2 * v.W + w];
+    if (cnt > K) cnt = K;
+    if (cnt <= 0) return;
+    for (int idx = lane; idx < cnt * cnt; idx += 64) {
+        const int r = idx / cnt, c = idx % cnt;
+        sL[r][c] = c < r ? v.wG[((size_t)w * K + r) * K + c] : (c == r ? v.wrho[(size_t)w * K + r] : 0.0);
+    }
+    __syncthreads();
+    if (lane < cnt) {
+        const int j = lane;
+        for (int m = 0; m < cnt; ++m) {
+            double t = m == j ? 1.0 : 0.0;
+            for (int q = j; q < m; ++q) t -= sL[m][q] * sX[q][j];
+            sX[m][j] = m < j ? 0.0 : t / sL[m][m];
+        }
+    }
+    __syncthreads();
+    for (int idx = lane; idx < cnt * cnt; idx += 64) {
+        const int r = idx / cnt, c = idx % cnt;
+        v.wlinv[((size_t)w * K + r) * K + c] = sX[r][c];
+    }
+}
+
+bool flush_mfma_fits(int n) { return n % 32 == 0 && n <= 4 * kStripTiles * 32; }
+
+void launch_flush_mfma(const CrowdView<float>& v, int spin, hipStream_t s, bool linv_ready)
+{
+    const int nstrip = v.n / 32;
+    if (!linv_ready) hipLaunchKernelGGL(k_window_linv, dim3(v.W), dim3(64), 0, s, v);
+    hipLaunchKernelGGL(k_flush_mfma, dim3(xcd_grid(v.W, nstrip)), dim3(kBlock), 0, s, v, spin);
+}
+
+}  // namespace cq

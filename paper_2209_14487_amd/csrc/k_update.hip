@@ -150,8 +150,14 @@ __global__ __launch_bounds__(kBlock) void k_flush_vec(CrowdView<T> v, int spin)
 }
 
 template <typename T>
-void launch_flush(const CrowdView<T>& v, int spin, hipStream_t s)
+void launch_flush(const CrowdView<T>& v, int spin, hipStream_t s, bool linv_ready)
 {
+    if constexpr (sizeof(T) == 4) {
+        if (flush_mfma_fits(v.n)) {
+            launch_flush_mfma(v, spin, s, linv_ready);
+            return;
+        }
+    }
     constexpr int VEC = 16 / sizeof(T);
     const int nstrip = (v.n + kRowsPerBlock - 1) / kRowsPerBlock;
     const dim3 grid(xcd_grid(v.W, nstrip)), block(kBlock);
@@ -241,8 +247,8 @@ void launch_energy(const CrowdView<T>& v, hipStream_t s)
     hipLaunchKernelGGL(k_energy_sum, dim3((v.W + 3) / 4), dim3(kBlock), 0, s, v.elpart, v.eloc, v.W, v.ne);
 }
 
-template void launch_flush<float>(const CrowdView<float>&, int, hipStream_t);
-template void launch_flush<double>(const CrowdView<double>&, int, hipStream_t);
+template void launch_flush<float>(const CrowdView<float>&, int, hipStream_t, bool);
+template void launch_flush<double>(const CrowdView<double>&, int, hipStream_t, bool);
 template void launch_energy<float>(const CrowdView<float>&, hipStream_t);
 template void launch_energy<double>(const CrowdView<double>&, hipStream_t);
 
