@@ -83,6 +83,8 @@ struct cq_crowd {
     double* rnew = nullptr;
     double* jd = nullptr;
     double* rprop = nullptr;
+    size_t* sidx = nullptr;
+    void* swt = nullptr;
     double* pmat = nullptr;
     double* tmat = nullptr;
     int* cur = nullptr;
@@ -150,6 +152,8 @@ cq::CrowdView<T> view(const cq_crowd* c)
     v.rnew = c->rnew;
     v.jd = c->jd;
     v.rprop = c->rprop;
+    v.sidx = c->sidx;
+    v.swt = c->swt;
     v.pmat = c->pmat;
     v.tmat = c->tmat;
     v.cur = c->cur;
@@ -566,6 +570,8 @@ cq_status cq_crowd_create(const cq_system* const* systems, const int* walkers_pe
         {(void**)&c->wslot, sizeof(int) * W * K},
         {(void**)&c->jd, sizeof(double) * W * c->Q},
         {(void**)&c->rprop, sizeof(double) * W * c->Q * 3},
+        {(void**)&c->sidx, sizeof(size_t) * W * c->Q * 64},
+        {&c->swt, es * W * c->Q * 64 * 5},
         {(void**)&c->pmat, sizeof(double) * W * c->Q * c->Q},
         {(void**)&c->tmat, sizeof(double) * W * K * c->Q},
         {(void**)&c->cur, sizeof(int) * W * 3},

@@ -83,6 +83,8 @@ struct CrowdView {
     double* rnew;
     double* jd;          // [W][Q] Jastrow difference of the candidate in ring slot q
     double* rprop;       // [W][Q][3] its proposed position
+    size_t* sidx;        // [W][Q][64] table offsets of its stencil points
+    void* swt;           // [W][Q][64][5] T: their value, gradient and Laplacian weights
     double* pmat;        // [W][Q][Q] P of the current round's candidates
     double* tmat;        // [W][K][Q] T: accepted columns in the basis of the round's c0 columns
     int* cur;            // [W][2] next electron to decide, end of the evaluated candidates;

@@ -27,6 +27,7 @@
 // The Jastrow difference of a candidate is summed over all electrons when it is
 // evaluated; every later accepted move adds the change of its pair term.
 //
+// k_stencils    proposals and stencils of the new candidates
 // k_prop_vgl    gather + VGL of the new candidates, their Jastrow sums
 // k_pmat        P of every walker's candidates (FP64 sums of exact products)
 // k_decide      one workgroup per walker: the decisions, the window for the
@@ -110,6 +111,31 @@ __device__ __forceinline__ bool new_candidate(const int* cur, int w, int t, int 
     return a < end;
 }
 
+// Proposals and stencils of the round's new candidates, one wave per candidate
+// (lane = stencil entry), so that the gather workgroups start loading at once.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_stencils(CrowdView<T> v, int spin)
+{
+    const int n = v.n, Q = v.Q;
+    const int pi = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (pi >= v.W * Q) return;
+    int a = 0;
+    if (!new_candidate(v.cur, pi / Q, pi % Q, Q, n, a)) return;
+    const int w = pi / Q, e = spin * n + a, slot = a % Q;
+    const size_t ps = (size_t)w * Q + slot;
+    double z[3], rp[3];
+    gauss3(v.seed, v.uid[w], v.prm->step, (uint32_t)e, z);
+    const double sigma = v.prm->sigma;
+    for (int k = 0; k < 3; ++k) rp[k] = wrap_box(v.R[((size_t)w * v.ne + e) * 3 + k] + sigma * z[k], v.L);
+    stencil_entry<T>(v, rp, lane, v.sidx + ps * 64, (T*)v.swt + ps * 64 * 5);
+    if (lane < 3) v.rprop[ps * 3 + lane] = rp[lane];
+}
+
+// Gather + value/gradient/Laplacian of the round's new candidates.  Each thread
+// owns one 16-byte group of orbitals and runs the 64 stencil points as 4 planes
+// of 16 loads; between issuing a plane's loads and using them it works through
+// its share of the candidate's Jastrow pair sums, which then costs no time of
+// its own.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_prop_vgl(CrowdView<T> v, int spin, int pp)
 {
@@ -121,29 +147,27 @@ __global__ __launch_bounds__(kBlock) void k_prop_vgl(CrowdView<T> v, int spin, i
     __shared__ int s_ok[4];
     const int n = v.n, Q = v.Q, groups = n / VEC;
     const int nprop = v.W * Q;
-    const int nt = blockDim.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
+    const int nt = blockDim.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int first = blockIdx.x * pp;
-    const uint32_t step = v.prm->step;
-    const double sigma = v.prm->sigma;
 
-    // proposals and stencils: wave p fills proposal p (a single wave fills all)
-    for (int p = wave; p < pp; p += nw) {
-        const int pi = first + p;
+    // stencils of this workgroup's proposals into LDS
+    if (tid < pp) {
+        const int pi = first + tid;
         int a = 0;
-        const bool ok = pi < nprop && new_candidate(v.cur, pi / Q, pi % Q, Q, n, a);
-        if (lane == 0) s_ok[p] = ok;
-        if (!ok) continue;
-        const int w = pi / Q, e = spin * n + a, slot = a % Q;
-        double z[3], rp[3];
-        gauss3(v.seed, v.uid[w], step, (uint32_t)e, z);
-        for (int k = 0; k < 3; ++k) rp[k] = wrap_box(v.R[((size_t)w * v.ne + e) * 3 + k] + sigma * z[k], v.L);
-        stencil_entry<T>(v, rp, lane, s_idx[p], s_w[p]);
-        if (lane == 0) {
-            for (int k = 0; k < 3; ++k) {
-                s_rp[p][k] = rp[k];
-                v.rprop[((size_t)w * Q + slot) * 3 + k] = rp[k];
-            }
-        }
+        s_ok[tid] = pi < nprop && new_candidate(v.cur, pi / Q, pi % Q, Q, n, a);
+    }
+    __syncthreads();
+    for (int idx = tid; idx < pp * 64; idx += nt) {
+        const int p = idx >> 6, l = idx & 63, pi = first + p;
+        if (!s_ok[p]) continue;
+        int a = 0;
+        new_candidate(v.cur, pi / Q, pi % Q, Q, n, a);
+        const size_t ps = (size_t)(pi / Q) * Q + a % Q;
+        s_idx[p][l] = v.sidx[ps * 64 + l];
+        const T* sw = (const T*)v.swt + (ps * 64 + l) * 5;
+#pragma unroll
+        for (int k = 0; k < 5; ++k) s_w[p][l * 5 + k] = sw[k];
+        if (l < 3) s_rp[p][l] = v.rprop[ps * 3 + l];
     }
     __syncthreads();
 
@@ -154,6 +178,29 @@ __global__ __launch_bounds__(kBlock) void k_prop_vgl(CrowdView<T> v, int spin, i
     int a = 0;
     if (live) new_candidate(v.cur, pi / Q, pi % Q, Q, n, a);
     const int w = live ? pi / Q : 0, e = spin * n + a, slot = a % Q;
+    const bool j2 = v.use_j2 && live;
+    const double* Rw = v.R + (size_t)w * v.ne * 3;
+    double re[3], rpp[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        re[k] = j2 ? Rw[(size_t)e * 3 + k] : 0.0;
+        rpp[k] = j2 ? s_rp[p][k] : 0.0;
+    }
+    // this thread's Jastrow pairs: electrons i = t0, t0 + tpp, ... (skipping e)
+    const int jn = j2 ? (v.ne - t0 + tpp - 1) / tpp : 0;
+    int jnext = 0;
+    double dj = 0.0;
+    auto j2_pairs = [&](int count) {
+        for (int c = 0; c < count && jnext < jn; ++c, ++jnext) {
+            const int i = t0 + jnext * tpp;
+            if (i == e) continue;
+            const double aa = ((i >= v.n) == (spin != 0)) ? v.a_par : v.a_anti;
+            const double* ri = Rw + (size_t)i * 3;
+            dj += pair_j2(v, aa, rpp, ri) - pair_j2(v, aa, re, ri);
+        }
+    };
+    const int gsteps = live ? 4 * ((groups - t0 + tpp - 1) / tpp) : 0;  // plane iterations
+    const int jper = gsteps ? (jn + gsteps - 1) / gsteps : 0;
     if (live) {
         T* dst = v.stage + ((size_t)w * Q + slot) * 5 * (size_t)n;
         const size_t* sidx = s_idx[p];
@@ -170,6 +217,7 @@ __global__ __launch_bounds__(kBlock) void k_prop_vgl(CrowdView<T> v, int spin, i
                 T vals[16][VEC];
 #pragma unroll
                 for (int q = 0; q < 16; ++q) load16(v.table + sidx[x * 16 + q] + j0, vals[q]);
+                j2_pairs(jper);  // overlaps the loads in flight
 #pragma unroll
                 for (int q = 0; q < 16; ++q) {
                     const T* wq = sw + (x * 16 + q) * 5;
@@ -188,25 +236,12 @@ __global__ __launch_bounds__(kBlock) void k_prop_vgl(CrowdView<T> v, int spin, i
             for (int k = 0; k < 5; ++k) store16(dst + (size_t)k * n + j0, acc[k]);
         }
     }
+    j2_pairs(jn);  // whatever is left (threads without a group of their own)
 
     // Jastrow difference of each proposal against the current positions
     if (!v.use_j2) {
         if (live && t0 == 0) v.jd[(size_t)w * Q + slot] = 0.0;
         return;
-    }
-    double dj = 0.0;
-    if (live) {
-        const double* Rw = v.R + (size_t)w * v.ne * 3;
-        double re[3], rp[3];
-        for (int k = 0; k < 3; ++k) {
-            re[k] = Rw[(size_t)e * 3 + k];
-            rp[k] = s_rp[p][k];
-        }
-        for (int i = t0; i < v.ne; i += tpp) {
-            if (i == e) continue;
-            const double aa = ((i >= v.n) == (spin != 0)) ? v.a_par : v.a_anti;
-            dj += pair_j2(v, aa, rp, Rw + (size_t)i * 3) - pair_j2(v, aa, re, Rw + (size_t)i * 3);
-        }
     }
     if (tpp % 64 == 0) {
         dj = wave_sum(dj);
@@ -528,6 +563,7 @@ template <typename T>
 void launch_batch_vgl(const CrowdView<T>& v, int spin, bool block_start, hipStream_t s)
 {
     if (block_start) hipLaunchKernelGGL(k_cursor_reset, dim3((2 * v.W + 255) / 256), dim3(256), 0, s, v.cur, v.W);
+    hipLaunchKernelGGL(k_stencils<T>, dim3((v.W * v.Q + kBlock / 64 - 1) / (kBlock / 64)), dim3(kBlock), 0, s, v, spin);
     const int pp = batch_pp(v.n, sizeof(T));
     const int nb = (v.W * v.Q + pp - 1) / pp;
     hipLaunchKernelGGL(k_prop_vgl<T>, dim3(nb), dim3(batch_threads(v.n, sizeof(T))), 0, s, v, spin, pp);

@@ -17,7 +17,7 @@
 // the 16 columns 8 (v / 4) + 4 (l / 32) + v % 4 of the tile).  That layout is at
 // the same time the B operand of GEMM 1 (the two k values of step v are the
 // columns of half 0 and half 1) and the accumulator of GEMM 2, so neither product
-// moves the strip.  Each of the 4 waves holds every 4th tile; GEMM 1 partial
+// moves the strip.  Each of the 16 waves holds every 16th tile; GEMM 1 partial
 // sums of the waves are added in a fixed order in LDS.
 #include "cq_device.h"
 #include "cq_internal.h"
@@ -26,11 +26,13 @@ namespace cq {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-constexpr int kStripTiles = 8;  // 32-column tiles per wave (N <= 4 * 8 * 32)
+constexpr int kFlushWaves = 16;                   // waves per workgroup
+constexpr int kFlushThreads = 64 * kFlushWaves;
+constexpr int kStripTiles = 2;                    // 32-column tiles per wave (N <= 16 * 2 * 32)
 
-__global__ __launch_bounds__(kBlock, 2) void k_flush_mfma(CrowdView<float> v, int spin)
+__global__ __launch_bounds__(kFlushThreads) void k_flush_mfma(CrowdView<float> v, int spin)
 {
-    __shared__ float sX[4][32][33];   // per wave: partial X^T[m][i]
+    __shared__ float sX[kFlushWaves][32][33];  // per wave: partial X^T[m][i]
     __shared__ float sB[32][33];      // b[i][m] (FP32 operand of GEMM 2)
     __shared__ double sY[32][33];     // x[i][j] - delta(row0 + i, e_j)
     __shared__ double sL[32][33];     // L^-1
@@ -62,7 +64,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_flush_mfma(CrowdView<float> v, in
         }
         const float* src = v.stage + ((size_t)w * v.Q + wsl[mm]) * 5 * (size_t)n;
         float* dst = v.VGL + (((size_t)w * 2 + spin) * n + ea) * 5 * (size_t)n;
-        for (int i = tid * 4; i < 5 * n; i += kBlock * 4) {
+        for (int i = tid * 4; i < 5 * n; i += kFlushThreads * 4) {
             float x[4];
             load16(src + i, x);
             store16(dst + i, x);
@@ -74,7 +76,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_flush_mfma(CrowdView<float> v, in
     f32x16 mt[kStripTiles];
 #pragma unroll
     for (int tt = 0; tt < kStripTiles; ++tt) {
-        const int t = wave + 4 * tt;
+        const int t = wave + kFlushWaves * tt;
 #pragma unroll
         for (int q = 0; q < 16; ++q) mt[tt][q] = 0.0f;
         if (t < ntile) {
@@ -89,27 +91,36 @@ __global__ __launch_bounds__(kBlock, 2) void k_flush_mfma(CrowdView<float> v, in
         }
     }
 
-    // GEMM 1: X^T[m][i] = sum_k u_m[k] M[row0 + i][k] over this wave's tiles
+    // GEMM 1: X^T[m][i] = sum_k u_m[k] M[row0 + i][k] over this wave's tiles; the
+    // u operands of the next tile load during this tile's MFMAs
     f32x16 xacc;
 #pragma unroll
     for (int q = 0; q < 16; ++q) xacc[q] = 0.0f;
     const float* urow = v.stage + ((size_t)w * v.Q + wsl[l32 < cnt ? l32 : 0]) * 5 * (size_t)n;
+    const bool urow_live = l32 < cnt;
+    auto fetch_u = [&](int t, float (&u)[16]) {
 #pragma unroll
-    for (int tt = 0; tt < kStripTiles; ++tt) {
-        const int t = wave + 4 * tt;
-        if (t < ntile) {
-            float u[16];
+        for (int g = 0; g < 4; ++g) {
+            float x[4];
+            load16(urow + t * 32 + 8 * g + 4 * h, x);
 #pragma unroll
-            for (int g = 0; g < 4; ++g) {
-                if (l32 < cnt) {
-                    load16(urow + t * 32 + 8 * g + 4 * h, &u[4 * g]);
-                } else {
+            for (int q = 0; q < 4; ++q) u[4 * g + q] = urow_live ? x[q] : 0.0f;
+        }
+    };
+    {
+        float u[16], un[16];
+        if (wave < ntile) fetch_u(wave, u);
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) u[4 * g + q] = 0.0f;
-                }
+        for (int tt = 0; tt < kStripTiles; ++tt) {
+            const int t = wave + kFlushWaves * tt;
+            if (t < ntile) {
+                if (tt + 1 < kStripTiles && t + kFlushWaves < ntile) fetch_u(t + kFlushWaves, un);
+#pragma unroll
+                for (int q = 0; q < 16; ++q) xacc = __builtin_amdgcn_mfma_f32_32x32x2f32(u[q], mt[tt][q], xacc, 0, 0, 0);
+#pragma unroll
+                for (int q = 0; q < 16; ++q) u[q] = un[q];
             }
-#pragma unroll
-            for (int q = 0; q < 16; ++q) xacc = __builtin_amdgcn_mfma_f32_32x32x2f32(u[q], mt[tt][q], xacc, 0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);
         }
     }
 #pragma unroll
@@ -117,23 +128,30 @@ __global__ __launch_bounds__(kBlock, 2) void k_flush_mfma(CrowdView<float> v, in
     __syncthreads();
 
     // y[i][j] = x[i][j] - delta(row0 + i, e_j) in FP64, then
-    // b[i][m] = sum_{j<=m} Linv[m][j] y[i][j]
-    for (int idx = tid; idx < 32 * 32; idx += kBlock) {
+    // b[i][m] = sum_j Linv[m][j] y[i][j] (Linv and y zero-padded to 32 x 32)
+    for (int idx = tid; idx < 32 * 32; idx += kFlushThreads) {
         const int i = idx >> 5, j = idx & 31;
-        if (j < cnt) {
-            const double x = (((double)sX[0][j][i] + (double)sX[1][j][i]) + (double)sX[2][j][i]) +
-                             (double)sX[3][j][i];
-            sY[i][j] = x - (row0 + i == wel[j] ? 1.0 : 0.0);
-            sL[i][j] = i < cnt ? v.wlinv[((size_t)w * K + i) * K + j] : 0.0;
-        }
+        double x = 0.0;
+#pragma unroll
+        for (int q = 0; q < kFlushWaves; ++q) x += (double)sX[q][j][i];
+        sY[i][j] = j < cnt ? x - (row0 + i == wel[j] ? 1.0 : 0.0) : 0.0;
+        sL[i][j] = (i < cnt && j <= i) ? v.wlinv[((size_t)w * K + i) * K + j] : 0.0;
     }
     __syncthreads();
-    for (int idx = tid; idx < 32 * 32; idx += kBlock) {
-        const int i = idx >> 5, m = idx & 31;
-        double b = 0.0;
-        if (m < cnt)
-            for (int j = 0; j <= m; ++j) b += sL[m][j] * sY[i][j];
-        sB[i][m] = (float)b;
+    {
+        constexpr int MPT = 32 * 32 / kFlushThreads;  // moves of one row per thread
+        const int i = tid / (32 / MPT), m0 = (tid % (32 / MPT)) * MPT;
+        double b[MPT];
+#pragma unroll
+        for (int r = 0; r < MPT; ++r) b[r] = 0.0;
+#pragma unroll
+        for (int j = 0; j < 32; ++j) {
+            const double y = sY[i][j];
+#pragma unroll
+            for (int r = 0; r < MPT; ++r) b[r] = fma(sL[m0 + r][j], y, b[r]);
+        }
+#pragma unroll
+        for (int r = 0; r < MPT; ++r) sB[i][m0 + r] = (float)b[r];
     }
     __syncthreads();
 
@@ -161,9 +179,9 @@ __global__ __launch_bounds__(kBlock, 2) void k_flush_mfma(CrowdView<float> v, in
     if (wave < ntile) fetch(wave, a);
 #pragma unroll
     for (int tt = 0; tt < kStripTiles; ++tt) {
-        const int t = wave + 4 * tt;
+        const int t = wave + kFlushWaves * tt;
         if (t < ntile) {
-            if (tt + 1 < kStripTiles && t + 4 < ntile) fetch(t + 4, an);
+            if (tt + 1 < kStripTiles && t + kFlushWaves < ntile) fetch(t + kFlushWaves, an);
             // operands past cnt are zero (Ct and b are zero-padded), so all 16 steps run
 #pragma unroll
             for (int q = 0; q < 16; ++q)
@@ -175,7 +193,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_flush_mfma(CrowdView<float> v, in
     }
 #pragma unroll
     for (int tt = 0; tt < kStripTiles; ++tt) {
-        const int t = wave + 4 * tt;
+        const int t = wave + kFlushWaves * tt;
         if (t < ntile) {
             float* dst = Mb + (size_t)l32 * n + t * 32 + 4 * h;
 #pragma unroll
@@ -219,13 +237,13 @@ __global__ __launch_bounds__(64) void k_window_linv(CrowdView<float> v)
     }
 }
 
-bool flush_mfma_fits(int n) { return n % 32 == 0 && n <= 4 * kStripTiles * 32; }
+bool flush_mfma_fits(int n) { return n % 32 == 0 && n <= kFlushWaves * kStripTiles * 32; }
 
 void launch_flush_mfma(const CrowdView<float>& v, int spin, hipStream_t s, bool linv_ready)
 {
     const int nstrip = v.n / 32;
     if (!linv_ready) hipLaunchKernelGGL(k_window_linv, dim3(v.W), dim3(64), 0, s, v);
-    hipLaunchKernelGGL(k_flush_mfma, dim3(xcd_grid(v.W, nstrip)), dim3(kBlock), 0, s, v, spin);
+    hipLaunchKernelGGL(k_flush_mfma, dim3(xcd_grid(v.W, nstrip)), dim3(kFlushThreads), 0, s, v, spin);
 }
 
 }  // namespace cq
