@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--eager", action="store_true", help="skip the extra hipGraph replay run")
     ap.add_argument("--path", default="auto", choices=["auto", "multi", "window", "batch"],
                     help="mapping of the moves to the GPU")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first copy 1 GiB with the library's plain copy kernel (counter calibration runs)")
     return ap.parse_args()
 
 
@@ -123,6 +125,29 @@ def run_gpu(cq, wl, precision, delay, recompute, steps, warmup, timing_kinds, us
     return out
 
 
+def kernel_source_hash():
+    """SHA-256 of the sources the gather kernel is built from."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("k_batch.hip", "cq_device.h", "cq_internal.h"):
+        with open(os.path.join(ROOT, "paper_2209_14487_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload):
+    """HBM bytes per k_prop_vgl launch from the committed counter summary, or None when the
+    summary is missing or was taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", "k_prop_vgl_%s_traffic.json" % workload)
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_sha256") != kernel_source_hash():
+        return None
+    return rec.get("traffic_bytes_per_launch")
+
+
 def cpu_baseline(wl, moves_per_walker):
     """The FP64 oracle (OpenMP over walkers) on a bounded sample of the same workload."""
     import oracle as orc
@@ -160,7 +185,15 @@ def main():
     log("workload %s: N=%d per spin, W=%d x %d crowd(s), G=%d, k=%d, recompute every %d"
         % (wl.name, wl.n, wl.walkers, wl.crowds, wl.G, delay, wl.recompute_every))
 
-    kinds = ["vgl", "resolve", "update", "energy", "inverse"]
+    if args.calibrate_copy:
+        import torch
+        src = torch.ones(1 << 30, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        cq.device_copy(dst.data_ptr(), src.data_ptr(), 1 << 30)
+        del src, dst
+        log("  copied 1 GiB with cq_device_copy (calibration)")
+    kinds = ["propose", "vgl", "resolve", "update", "energy", "inverse"]
     mixed = run_gpu(cq, wl, "mixed", delay, wl.recompute_every, args.steps, args.warmup, kinds, not args.eager,
                     path=args.path, graph_steps=0 if args.eager else max(2, args.steps // 4))
     log("  mixed: %.3f s for %d sweeps, %.3e moves/s, acceptance %.3f"
@@ -186,13 +219,14 @@ def main():
     r_per_launch = mixed["accepted_timed"] / max(up_n, 1)
     up_flops = 4.0 * n * n * r_per_launch
     up_bytes = W * 2 * n * n * s + 2 * r_per_launch * n * s
+    traffic = measured_traffic(wl.name)
     roof_vgl = dict(bound="hbm", achieved=round(vgl_gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(vgl_gbs / HBM_PEAK_GBS, 4), traffic=None, kernel="k_prop_vgl",
+                    frac=round(vgl_gbs / HBM_PEAK_GBS, 4), traffic=traffic, kernel="k_prop_vgl",
                     us_per_launch=round(vgl_t * 1e6, 3), bytes_per_launch=int(vgl_bytes),
                     proposals_per_launch=int(props_per_launch))
     roof_up = dict(bound="mfma", achieved=round(up_flops / up_t / 1e12, 2), peak=FP32_PEAK_TFLOPS,
                    unit="TFLOP/s", frac=round(up_flops / up_t / 1e12 / FP32_PEAK_TFLOPS, 4),
-                   hbm_gbs=round(up_bytes / up_t / 1e9, 1), kernel="k_flush_vec",
+                   hbm_gbs=round(up_bytes / up_t / 1e9, 1), kernel="k_flush_mfma",
                    us_per_launch=round(up_t * 1e6, 3), accepted_per_launch=round(r_per_launch, 2))
     dominant = roof_vgl if vgl_ms >= up_ms else roof_up
     out = dict(metric=METRIC, value=round(mixed["moves_per_s"], 1), unit="moves/s", n_gpus=1, steps=args.steps,

@@ -57,11 +57,13 @@ typedef enum {
     CQ_KERNEL_VGL = 0,      /* B-spline VGL at the proposals: per move fused with the ratio, Jastrow
                                and the previous decision (MULTI), per window with all its moves
                                (WINDOW), or per window for all its proposals at once (BATCH) */
-    CQ_KERNEL_RESOLVE = 1,  /* decisions: of a window's last move (MULTI), of all its moves (BATCH) */
+    CQ_KERNEL_RESOLVE = 1,  /* decisions: of a window's last move (MULTI), of a round's moves with
+                               the products they need (BATCH) */
     CQ_KERNEL_UPDATE = 2,   /* Sherman-Morrison / delayed rank-k inverse update */
     CQ_KERNEL_ENERGY = 3,   /* local energy */
     CQ_KERNEL_INVERSE = 4,  /* FP64 Gauss-Jordan inversion (initial and periodic recompute) */
-    CQ_KERNEL_COUNT = 5
+    CQ_KERNEL_PROPOSE = 5,  /* proposals and stencils of a round's new candidates (BATCH) */
+    CQ_KERNEL_COUNT = 6
 } cq_kernel_kind;
 
 /* Mapping of the moves to the GPU.  All paths compute the same Markov chain

@@ -21,9 +21,9 @@ LIB_PATH = os.path.join(_HERE, "libcrowdqmc.so")
 CQ_OK, CQ_EINVAL, CQ_ENOMEM, CQ_EDEVICE, CQ_ESINGULAR, CQ_ESTATE = range(6)
 CQ_FP64, CQ_MIXED = 0, 1
 PATHS = {"auto": 0, "multi": 1, "window": 2, "batch": 3}
-KERNEL_VGL, KERNEL_RESOLVE, KERNEL_UPDATE, KERNEL_ENERGY, KERNEL_INVERSE = range(5)
+KERNEL_VGL, KERNEL_RESOLVE, KERNEL_UPDATE, KERNEL_ENERGY, KERNEL_INVERSE, KERNEL_PROPOSE = range(6)
 KERNEL_NAMES = {"vgl": KERNEL_VGL, "resolve": KERNEL_RESOLVE, "update": KERNEL_UPDATE,
-                "energy": KERNEL_ENERGY, "inverse": KERNEL_INVERSE}
+                "energy": KERNEL_ENERGY, "inverse": KERNEL_INVERSE, "propose": KERNEL_PROPOSE}
 
 _STATUS_NAMES = {1: "CQ_EINVAL", 2: "CQ_ENOMEM", 3: "CQ_EDEVICE", 4: "CQ_ESINGULAR", 5: "CQ_ESTATE"}
 

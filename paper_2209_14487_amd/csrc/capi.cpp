@@ -216,8 +216,11 @@ void enqueue_sweep(cq_crowd* c)
         const int rounds = cq::batch_rounds(n, K);
         for (int spin = 0; spin < 2; ++spin)
             for (int r = 0; r < rounds; ++r) {
+                timed_begin(c, CQ_KERNEL_PROPOSE);
+                cq::launch_batch_stencils<T>(v, spin, r == 0, c->stream);
+                timed_end(c, CQ_KERNEL_PROPOSE);
                 timed_begin(c, CQ_KERNEL_VGL);
-                cq::launch_batch_vgl<T>(v, spin, r == 0, c->stream);
+                cq::launch_batch_vgl<T>(v, spin, c->stream);
                 timed_end(c, CQ_KERNEL_VGL);
                 timed_begin(c, CQ_KERNEL_RESOLVE);
                 cq::launch_batch_decide<T>(v, spin, c->stream);

@@ -120,7 +120,8 @@ template <typename T> void launch_move(const CrowdView<T>& v, int e, int prev, i
 template <typename T> void launch_first_proposal(const CrowdView<T>& v, hipStream_t s);
 template <typename T> void launch_window(const CrowdView<T>& v, int e0, int nmoves, hipStream_t s);
 int window_threads(int n, int elem_bytes);
-template <typename T> void launch_batch_vgl(const CrowdView<T>& v, int spin, bool block_start, hipStream_t s);
+template <typename T> void launch_batch_stencils(const CrowdView<T>& v, int spin, bool block_start, hipStream_t s);
+template <typename T> void launch_batch_vgl(const CrowdView<T>& v, int spin, hipStream_t s);
 template <typename T> void launch_batch_decide(const CrowdView<T>& v, int spin, hipStream_t s);
 int batch_rounds(int n, int K);      // rounds per spin block (enough when every move is accepted)
 int batch_candidates(int n, int K);  // candidates per round, Q

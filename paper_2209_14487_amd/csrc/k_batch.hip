@@ -560,10 +560,15 @@ int batch_candidates(int n, int K)
 }
 
 template <typename T>
-void launch_batch_vgl(const CrowdView<T>& v, int spin, bool block_start, hipStream_t s)
+void launch_batch_stencils(const CrowdView<T>& v, int spin, bool block_start, hipStream_t s)
 {
     if (block_start) hipLaunchKernelGGL(k_cursor_reset, dim3((2 * v.W + 255) / 256), dim3(256), 0, s, v.cur, v.W);
     hipLaunchKernelGGL(k_stencils<T>, dim3((v.W * v.Q + kBlock / 64 - 1) / (kBlock / 64)), dim3(kBlock), 0, s, v, spin);
+}
+
+template <typename T>
+void launch_batch_vgl(const CrowdView<T>& v, int spin, hipStream_t s)
+{
     const int pp = batch_pp(v.n, sizeof(T));
     const int nb = (v.W * v.Q + pp - 1) / pp;
     hipLaunchKernelGGL(k_prop_vgl<T>, dim3(nb), dim3(batch_threads(v.n, sizeof(T))), 0, s, v, spin, pp);
@@ -584,8 +589,10 @@ void launch_batch_decide(const CrowdView<T>& v, int spin, hipStream_t s)
     hipLaunchKernelGGL(k_cols<T>, dim3(v.W * ((v.n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, v, spin);
 }
 
-template void launch_batch_vgl<float>(const CrowdView<float>&, int, bool, hipStream_t);
-template void launch_batch_vgl<double>(const CrowdView<double>&, int, bool, hipStream_t);
+template void launch_batch_stencils<float>(const CrowdView<float>&, int, bool, hipStream_t);
+template void launch_batch_stencils<double>(const CrowdView<double>&, int, bool, hipStream_t);
+template void launch_batch_vgl<float>(const CrowdView<float>&, int, hipStream_t);
+template void launch_batch_vgl<double>(const CrowdView<double>&, int, hipStream_t);
 template void launch_batch_decide<float>(const CrowdView<float>&, int, hipStream_t);
 template void launch_batch_decide<double>(const CrowdView<double>&, int, hipStream_t);
 
