@@ -130,6 +130,8 @@ typedef struct {
     void* hip_stream;     /* borrowed hipStream_t to run on, or NULL: the crowd makes its own */
     int use_graph;        /* 1: capture one sweep as a hipGraph and replay it */
     int kernel_path;      /* how the moves are mapped to the GPU (cq_kernel_path) */
+    int max_walkers;      /* capacity for a DMC population (0: the initial walker count); the
+                             per-walker buffers are sized for it */
 } cq_crowd_desc;
 
 /* Create a crowd of walkers_per_system[s] walkers of each system s.  This
@@ -177,6 +179,33 @@ cq_status cq_crowd_set_forced_decisions(cq_crowd* c, const uint8_t* flags, int n
 cq_status cq_crowd_record_moves(cq_crowd* c, int n_sweeps);
 /* Copy the records out: arrays [n_sweeps][Ne][W]; any pointer may be NULL. */
 cq_status cq_crowd_get_move_records(cq_crowd* c, double* rho, double* dlnj, double* prob, uint8_t* acc);
+
+/* Diffusion Monte Carlo (paper Alg. 1 with a drift-diffusion move at L5 and
+   reweighting / branching at L12-L13; Sec. II-A).  Runs n_generations
+   generations of the crowd's population at time step tau: per generation one
+   sweep of drift-diffusion moves (Metropolis-Hastings with the drifted Gaussian
+   Green's function; moves that cross a node are rejected), the local energy,
+   then branching:
+     E_c = E_L clipped to E_T +- 0.2 sqrt(Ne / tau),
+     w = exp(-tau ((E_c,old + E_c,new) / 2 - E_T)),  m = min(3, floor(w + u_b)),
+     E_est = sum w E_L / sum w,  E_T <- E_est - ln(N / n_target) / (10 tau).
+   Children follow their parent in population order; copy 0 keeps the parent's
+   uid, copy c >= 1 gets a new one from the counter generator.  e_trial: the
+   starting E_T (NaN: continue with the current one).  history (may be NULL):
+   host array [n_generations][4] of population, sum of weights, E_est and E_T
+   after each generation.  Moves use the walker-resident per-move kernel
+   whatever the crowd's kernel path.  Synchronous: the population size is read
+   back after every generation.  Errors: CQ_EINVAL (bad arguments), CQ_ESTATE
+   (positions not set, or the population died out or outgrew max_walkers; the
+   crowd then keeps the last complete generation). */
+cq_status cq_crowd_run_dmc(cq_crowd* c, int n_generations, double tau, double e_trial, int n_target,
+                           double* history);
+
+/* Current number of walkers (changes under DMC branching). */
+cq_status cq_crowd_get_population(cq_crowd* c, int* n_walkers);
+
+/* uids of the current walkers, [n_walkers]. */
+cq_status cq_crowd_get_uids(cq_crowd* c, uint32_t* uids);
 
 /* Record HIP events on the crowd's stream around every launch of the kernel
    kinds in kind_mask (bit 1 << cq_kernel_kind; 0 switches timing off) and read

@@ -37,7 +37,7 @@ class CqError(RuntimeError):
 class CrowdDesc(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("delay_rank", ctypes.c_int), ("recompute_every", ctypes.c_int),
                 ("seed", ctypes.c_uint64), ("first_uid", ctypes.c_uint32), ("hip_stream", ctypes.c_void_p),
-                ("use_graph", ctypes.c_int), ("kernel_path", ctypes.c_int)]
+                ("use_graph", ctypes.c_int), ("kernel_path", ctypes.c_int), ("max_walkers", ctypes.c_int)]
 
 
 _lib = None
@@ -53,6 +53,9 @@ _SIGS = {
     "cq_crowd_create": [_P, _P, _I, _P, _P],
     "cq_crowd_set_positions": [_P, _P, _I, ctypes.c_uint32],
     "cq_crowd_run_vmc": [_P, _I, ctypes.c_double],
+    "cq_crowd_run_dmc": [_P, _I, ctypes.c_double, ctypes.c_double, _I, _P],
+    "cq_crowd_get_population": [_P, _P],
+    "cq_crowd_get_uids": [_P, _P],
     "cq_crowd_recompute": [_P, _P],
     "cq_crowd_get_logdet": [_P, _P, _P],
     "cq_crowd_get_acceptance": [_P, _P, _P],
@@ -170,13 +173,14 @@ class Crowd:
 
     def __init__(self, system: System, n_walkers: int, precision: str = "mixed", delay_rank: int = 1,
                  recompute_every: int = 0, seed: int = 0, first_uid: int = 0, stream=None,
-                 use_graph: bool = True, path: str = "auto"):
+                 use_graph: bool = True, path: str = "auto", max_walkers: int = 0):
         self.system = system
         self.W = n_walkers
+        self._w0 = n_walkers
         self.n = system.n
         self.ne = 2 * system.n
         desc = CrowdDesc(CQ_MIXED if precision == "mixed" else CQ_FP64, delay_rank, recompute_every, seed,
-                         first_uid, _stream_handle(stream), int(use_graph), PATHS[path])
+                         first_uid, _stream_handle(stream), int(use_graph), PATHS[path], max_walkers)
         systems = (ctypes.c_void_p * 1)(system._h.value)
         counts = (ctypes.c_int * 1)(n_walkers)
         h = ctypes.c_void_p()
@@ -194,6 +198,28 @@ class Crowd:
 
     def run_vmc(self, n_sweeps: int, sigma: float = 0.5):
         _check(lib().cq_crowd_run_vmc(self._h, n_sweeps, sigma))
+
+    def run_dmc(self, n_generations: int, tau: float, e_trial: float = float("nan"), n_target: int = 0):
+        """DMC generations; returns the history [n_generations][4] (population, sum of
+        weights, E_est, E_T).  n_target 0: the initial walker count."""
+        h = np.zeros((n_generations, 4))
+        if n_target <= 0:
+            n_target = self._w0
+        try:
+            _check(lib().cq_crowd_run_dmc(self._h, n_generations, tau, e_trial, n_target, h.ctypes.data))
+        finally:
+            self.W = self.population()
+        return h
+
+    def population(self) -> int:
+        n = ctypes.c_int()
+        _check(lib().cq_crowd_get_population(self._h, ctypes.byref(n)))
+        return n.value
+
+    def uids(self):
+        u = np.zeros(self.W, np.uint32)
+        _check(lib().cq_crowd_get_uids(self._h, u.ctypes.data))
+        return u
 
     def recompute(self) -> float:
         d = ctypes.c_double()

@@ -52,6 +52,7 @@ struct cq_system {
 struct cq_crowd {
     const cq_system* sys = nullptr;
     int W = 0, n = 0, ne = 0, K = 1, Q = 1, prec = CQ_MIXED, recompute_every = 0, use_graph = 0;
+    int Wcap = 0;  // capacity of the per-walker buffers (DMC populations)
     int path = CQ_PATH_WINDOW;
     uint64_t seed = 0;
     uint32_t first_uid = 0;
@@ -67,6 +68,27 @@ struct cq_crowd {
     long long* nacc = nullptr;
     long long* nprop = nullptr;
     double* eloc = nullptr;
+    double* eold = nullptr;
+    // DMC: the second set of per-walker buffers (allocated on first use) and branching state
+    struct {
+        double* R = nullptr;
+        void* M = nullptr;
+        void* VGL = nullptr;
+        double* logdet = nullptr;
+        int* sign = nullptr;
+        double* eloc = nullptr;
+        double* eold = nullptr;
+        uint32_t* uid = nullptr;
+        long long* nacc = nullptr;
+        long long* nprop = nullptr;
+    } alt;
+    bool have_alt = false;
+    cq::DmcState* dmc_state = nullptr;
+    double* dmc_wt = nullptr;
+    int* dmc_mult = nullptr;
+    int* dmc_off = nullptr;
+    double* dmc_hist = nullptr;
+    int dmc_hist_cap = 0;
     double* elpart = nullptr;
     int* cnt = nullptr;
     int* welec = nullptr;
@@ -352,15 +374,16 @@ cq_status setup_state(cq_crowd* c)
     HIP_TRY(hipMemsetAsync(c->sign, 0, sizeof(int) * 2 * c->W, c->stream));
     HIP_TRY(hipMemsetAsync(c->nacc, 0, sizeof(long long) * c->W, c->stream));
     HIP_TRY(hipMemsetAsync(c->nprop, 0, sizeof(long long) * c->W, c->stream));
-    HIP_TRY(hipMemsetAsync(c->cnt, 0, sizeof(int) * 3 * c->W, c->stream));
-    HIP_TRY(hipMemsetAsync(c->welec, 0, sizeof(int) * c->W * c->K, c->stream));
-    HIP_TRY(hipMemsetAsync(c->wslot, 0, sizeof(int) * c->W * c->K, c->stream));
-    // window slots are read (masked) before they are first written: start them at 0
+    HIP_TRY(hipMemsetAsync(c->cnt, 0, sizeof(int) * 3 * c->Wcap, c->stream));
+    HIP_TRY(hipMemsetAsync(c->welec, 0, sizeof(int) * c->Wcap * c->K, c->stream));
+    HIP_TRY(hipMemsetAsync(c->wslot, 0, sizeof(int) * c->Wcap * c->K, c->stream));
+    // window slots are read (masked) before they are first written: start them at 0; every
+    // walker slot up to the capacity, since DMC branching fills slots past the initial count
     const size_t es = c->prec == CQ_FP64 ? 8 : 4;
-    HIP_TRY(hipMemsetAsync(c->stage, 0, es * c->W * c->Q * 5 * c->n, c->stream));
-    HIP_TRY(hipMemsetAsync(c->cur, 0, sizeof(int) * 3 * c->W, c->stream));
-    HIP_TRY(hipMemsetAsync(c->Cbuf, 0, es * c->W * c->K * c->n, c->stream));
-    HIP_TRY(hipMemsetAsync(c->status, 0, sizeof(int) * c->W, c->stream));
+    HIP_TRY(hipMemsetAsync(c->stage, 0, es * c->Wcap * c->Q * 5 * c->n, c->stream));
+    HIP_TRY(hipMemsetAsync(c->cur, 0, sizeof(int) * 3 * c->Wcap, c->stream));
+    HIP_TRY(hipMemsetAsync(c->Cbuf, 0, es * c->Wcap * c->K * c->n, c->stream));
+    HIP_TRY(hipMemsetAsync(c->status, 0, sizeof(int) * c->Wcap, c->stream));
     cq::launch_setup_vgl<T>(v, c->stream);
     HIP_TRY(hipGetLastError());
     enqueue_inverse<T>(c);
@@ -368,6 +391,107 @@ cq_status setup_state(cq_crowd* c)
     cq::launch_energy<T>(v, c->stream);
     HIP_TRY(hipGetLastError());
     return check_singular(c, "set_positions");
+}
+
+template <typename T>
+cq::WalkerArrays<T> walker_arrays(cq_crowd* c, bool alt)
+{
+    if (alt)
+        return {c->alt.R, (T*)c->alt.M, (T*)c->alt.VGL, c->alt.logdet, c->alt.sign, c->alt.eloc, c->alt.eold,
+                c->alt.uid, c->alt.nacc, c->alt.nprop};
+    return {c->R, (T*)c->M, (T*)c->VGL, c->logdet, c->sign, c->eloc, c->eold, c->uid, c->nacc, c->nprop};
+}
+
+cq_status ensure_dmc(cq_crowd* c, int n_gen)
+{
+    if (!c->have_alt) {
+        const size_t Wc = (size_t)c->Wcap, n = c->n, ne = c->ne;
+        const size_t es = c->prec == CQ_FP64 ? 8 : 4;
+        struct {
+            void** p;
+            size_t bytes;
+        } plan[] = {
+            {(void**)&c->alt.R, sizeof(double) * Wc * ne * 3},
+            {&c->alt.M, es * Wc * 2 * n * n},
+            {&c->alt.VGL, es * Wc * 2 * n * 5 * n},
+            {(void**)&c->alt.logdet, sizeof(double) * Wc * 2},
+            {(void**)&c->alt.sign, sizeof(int) * Wc * 2},
+            {(void**)&c->alt.eloc, sizeof(double) * Wc},
+            {(void**)&c->alt.eold, sizeof(double) * Wc},
+            {(void**)&c->alt.uid, sizeof(uint32_t) * Wc},
+            {(void**)&c->alt.nacc, sizeof(long long) * Wc},
+            {(void**)&c->alt.nprop, sizeof(long long) * Wc},
+            {(void**)&c->dmc_state, sizeof(cq::DmcState)},
+            {(void**)&c->dmc_wt, sizeof(double) * Wc},
+            {(void**)&c->dmc_mult, sizeof(int) * Wc},
+            {(void**)&c->dmc_off, sizeof(int) * Wc},
+        };
+        for (auto& e : plan) {
+            cq_status st = dev_alloc(c, e.p, e.bytes);
+            if (st != CQ_OK) return st;
+        }
+        cq::DmcState st0{};
+        HIP_TRY(hipMemcpy(c->dmc_state, &st0, sizeof(st0), hipMemcpyHostToDevice));
+        c->have_alt = true;
+    }
+    if (n_gen > c->dmc_hist_cap) {
+        if (c->dmc_hist) (void)hipFree(c->dmc_hist);
+        c->dmc_hist = nullptr;
+        c->dmc_hist_cap = 0;
+        HIP_TRY(hipMalloc(&c->dmc_hist, sizeof(double) * 4 * (size_t)n_gen));
+        c->dmc_hist_cap = n_gen;
+    }
+    return CQ_OK;
+}
+
+template <typename T>
+void dmc_generation(cq_crowd* c, int gen, int n_target, double tau)
+{
+    cq::CrowdView<T> v = view<T>(c);
+    v.ct = nullptr;  // the per-move kernel leaves the window's columns in row layout
+    const int n = c->n, K = c->K;
+    for (int spin = 0; spin < 2; ++spin)
+        for (int a0 = 0; a0 < n; a0 += K) {
+            timed_begin(c, CQ_KERNEL_VGL);
+            cq::launch_window_dmc<T>(v, spin * n + a0, std::min(K, n - a0), c->stream);
+            timed_end(c, CQ_KERNEL_VGL);
+            timed_begin(c, CQ_KERNEL_UPDATE);
+            cq::launch_flush<T>(v, spin, c->stream, false);
+            timed_end(c, CQ_KERNEL_UPDATE);
+        }
+    timed_begin(c, CQ_KERNEL_ENERGY);
+    cq::launch_energy<T>(v, c->stream);
+    timed_end(c, CQ_KERNEL_ENERGY);
+    cq::DmcView d{};
+    d.state = c->dmc_state;
+    d.wt = c->dmc_wt;
+    d.mult = c->dmc_mult;
+    d.off = c->dmc_off;
+    d.history = c->dmc_hist;
+    d.pop = c->W;
+    d.cap = c->Wcap;
+    d.n_target = n_target;
+    const size_t nV = 2 * (size_t)n * 5 * n;
+    d.chunks = (int)std::min<size_t>(256, std::max<size_t>(1, nV / (256 * 256)));
+    d.ecut = 0.2 * std::sqrt((double)c->ne / tau);
+    d.seed = c->seed;
+    cq::launch_dmc_branch<T>(d, walker_arrays<T>(c, false), walker_arrays<T>(c, true), n, c->ne, c->prm, gen,
+                             c->stream);
+    cq::launch_sweep_end(c->prm, c->stream);
+}
+
+void swap_walker_sets(cq_crowd* c)
+{
+    std::swap(c->R, c->alt.R);
+    std::swap(c->M, c->alt.M);
+    std::swap(c->VGL, c->alt.VGL);
+    std::swap(c->logdet, c->alt.logdet);
+    std::swap(c->sign, c->alt.sign);
+    std::swap(c->eloc, c->alt.eloc);
+    std::swap(c->eold, c->alt.eold);
+    std::swap(c->uid, c->alt.uid);
+    std::swap(c->nacc, c->alt.nacc);
+    std::swap(c->nprop, c->alt.nprop);
 }
 
 }  // namespace
@@ -499,6 +623,7 @@ void cq_crowd_destroy(cq_crowd* c)
             (void)hipEventDestroy(p.second);
         }
     for (void* p : c->allocs) (void)hipFree(p);
+    if (c->dmc_hist) (void)hipFree(c->dmc_hist);
     if (c->rec_rho) (void)hipFree(c->rec_rho);
     if (c->rec_dlnj) (void)hipFree(c->rec_dlnj);
     if (c->rec_prob) (void)hipFree(c->rec_prob);
@@ -528,10 +653,12 @@ cq_status cq_crowd_create(const cq_system* const* systems, const int* walkers_pe
     if (desc->kernel_path < CQ_PATH_AUTO || desc->kernel_path > CQ_PATH_BATCH)
         return fail(CQ_EINVAL, "unknown kernel_path");
 
+    if (desc->max_walkers < 0) return fail(CQ_EINVAL, "max_walkers must be >= 0");
     cq_crowd* c = new (std::nothrow) cq_crowd();
     if (!c) return fail(CQ_ENOMEM, "host allocation failed");
     c->sys = s;
     c->W = W;
+    c->Wcap = std::max(W, desc->max_walkers);
     c->n = s->n_up;
     c->ne = 2 * s->n_up;
     c->K = K;
@@ -555,43 +682,45 @@ cq_status cq_crowd_create(const cq_system* const* systems, const int* walkers_pe
     const size_t n = c->n, ne = c->ne;
     constexpr int CHf = cq::chunk_orbitals<float>(), CHd = cq::chunk_orbitals<double>();
     const int C = (int)((n + (es == 8 ? CHd : CHf) - 1) / (es == 8 ? CHd : CHf));
+    const size_t Wc = (size_t)c->Wcap;
     struct {
         void** p;
         size_t bytes;
     } plan[] = {
-        {(void**)&c->R, sizeof(double) * W * ne * 3},
-        {&c->M, es * W * 2 * n * n},
-        {&c->VGL, es * W * 2 * n * 5 * n},
-        {(void**)&c->logdet, sizeof(double) * W * 2},
-        {(void**)&c->sign, sizeof(int) * W * 2},
-        {(void**)&c->nacc, sizeof(long long) * W},
-        {(void**)&c->nprop, sizeof(long long) * W},
-        {(void**)&c->eloc, sizeof(double) * W},
-        {(void**)&c->elpart, sizeof(double) * W * ne},
-        {(void**)&c->cnt, sizeof(int) * 3 * W},
-        {(void**)&c->welec, sizeof(int) * W * K},
-        {(void**)&c->wslot, sizeof(int) * W * K},
-        {(void**)&c->jd, sizeof(double) * W * c->Q},
-        {(void**)&c->rprop, sizeof(double) * W * c->Q * 3},
-        {(void**)&c->sidx, sizeof(size_t) * W * c->Q * 64},
-        {&c->swt, es * W * c->Q * 64 * 5},
-        {(void**)&c->pmat, sizeof(double) * W * c->Q * c->Q},
-        {(void**)&c->tmat, sizeof(double) * W * K * c->Q},
-        {(void**)&c->cur, sizeof(int) * W * 3},
-        {&c->stage, es * W * c->Q * 5 * n},
-        {&c->Cbuf, es * W * K * n},
-        {(void**)&c->ct, sizeof(float) * W * n * cq::kMaxDelay},
-        {(void**)&c->wrho, sizeof(double) * W * K},
-        {(void**)&c->wG, sizeof(double) * W * K * K},
-        {(void**)&c->wlinv, sizeof(double) * W * K * K},
-        {(void**)&c->beta, sizeof(double) * W * K},
-        {(void**)&c->pend, sizeof(int) * W},
-        {(void**)&c->part, sizeof(double) * 2 * W * C * cq::part_stride(K)},
-        {(void**)&c->rnew, sizeof(double) * 4 * W * 3},
-        {(void**)&c->uid, sizeof(uint32_t) * W},
+        {(void**)&c->R, sizeof(double) * Wc * ne * 3},
+        {&c->M, es * Wc * 2 * n * n},
+        {&c->VGL, es * Wc * 2 * n * 5 * n},
+        {(void**)&c->logdet, sizeof(double) * Wc * 2},
+        {(void**)&c->sign, sizeof(int) * Wc * 2},
+        {(void**)&c->nacc, sizeof(long long) * Wc},
+        {(void**)&c->nprop, sizeof(long long) * Wc},
+        {(void**)&c->eloc, sizeof(double) * Wc},
+        {(void**)&c->eold, sizeof(double) * Wc},
+        {(void**)&c->elpart, sizeof(double) * Wc * ne},
+        {(void**)&c->cnt, sizeof(int) * 3 * Wc},
+        {(void**)&c->welec, sizeof(int) * Wc * K},
+        {(void**)&c->wslot, sizeof(int) * Wc * K},
+        {(void**)&c->jd, sizeof(double) * Wc * c->Q},
+        {(void**)&c->rprop, sizeof(double) * Wc * c->Q * 3},
+        {(void**)&c->sidx, sizeof(size_t) * Wc * c->Q * 64},
+        {&c->swt, es * Wc * c->Q * 64 * 5},
+        {(void**)&c->pmat, sizeof(double) * Wc * c->Q * c->Q},
+        {(void**)&c->tmat, sizeof(double) * Wc * K * c->Q},
+        {(void**)&c->cur, sizeof(int) * Wc * 3},
+        {&c->stage, es * Wc * c->Q * 5 * n},
+        {&c->Cbuf, es * Wc * K * n},
+        {(void**)&c->ct, sizeof(float) * Wc * n * cq::kMaxDelay},
+        {(void**)&c->wrho, sizeof(double) * Wc * K},
+        {(void**)&c->wG, sizeof(double) * Wc * K * K},
+        {(void**)&c->wlinv, sizeof(double) * Wc * K * K},
+        {(void**)&c->beta, sizeof(double) * Wc * K},
+        {(void**)&c->pend, sizeof(int) * Wc},
+        {(void**)&c->part, sizeof(double) * 2 * Wc * C * cq::part_stride(K)},
+        {(void**)&c->rnew, sizeof(double) * 4 * Wc * 3},
+        {(void**)&c->uid, sizeof(uint32_t) * Wc},
         {(void**)&c->prm, sizeof(cq::Params)},
-        {(void**)&c->status, sizeof(int) * W},
-        {(void**)&c->drift, sizeof(double) * W * 2},
+        {(void**)&c->status, sizeof(int) * Wc},
+        {(void**)&c->drift, sizeof(double) * Wc * 2},
     };
     for (auto& e : plan) {
         cq_status st = dev_alloc(c, e.p, e.bytes);
@@ -601,9 +730,9 @@ cq_status cq_crowd_create(const cq_system* const* systems, const int* walkers_pe
             return fail(st, msg);
         }
     }
-    const size_t invb = cq::inverse_work_bytes(2 * W, (int)n);
+    const size_t invb = cq::inverse_work_bytes(2 * c->Wcap, (int)n);
     if (invb) {
-        const int nmat = 2 * W, b = cq::panel_width((int)n);
+        const int nmat = 2 * c->Wcap, b = cq::panel_width((int)n);
         void *S, *PR, *piv, *la, *ng;
         cq_status st = dev_alloc(c, &S, sizeof(double) * nmat * n * n);
         if (st == CQ_OK) st = dev_alloc(c, &PR, sizeof(double) * nmat * b * n);
@@ -654,6 +783,8 @@ cq_status cq_crowd_set_positions(cq_crowd* c, const double* R, int on_device, ui
     c->since_recompute = 0;
     st = c->prec == CQ_FP64 ? setup_state<double>(c) : setup_state<float>(c);
     if (st != CQ_OK) return st;
+    HIP_TRY(hipMemcpyAsync(c->eold, c->eloc, sizeof(double) * c->W, hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
     c->ready = true;
     return CQ_OK;
 }
@@ -693,6 +824,58 @@ cq_status cq_crowd_run_vmc(cq_crowd* c, int n_sweeps, double sigma)
         }
     }
     HIP_TRY(hipGetLastError());
+    return CQ_OK;
+}
+
+cq_status cq_crowd_run_dmc(cq_crowd* c, int n_generations, double tau, double e_trial, int n_target,
+                           double* history)
+{
+    if (!c) return fail(CQ_EINVAL, "crowd is NULL");
+    if (n_generations < 0 || !(tau > 0.0) || !std::isfinite(tau) || n_target < 1)
+        return fail(CQ_EINVAL, "bad n_generations, tau or n_target");
+    if (!c->ready) return fail(CQ_ESTATE, "set positions before running");
+    if (n_generations == 0) return CQ_OK;
+    cq_status st = ensure_dmc(c, n_generations);
+    if (st != CQ_OK) return st;
+    c->hp.tau = tau;
+    st = push_params(c);
+    if (st != CQ_OK) return st;
+    cq::DmcState ds{};
+    HIP_TRY(hipMemcpy(&ds, c->dmc_state, sizeof(ds), hipMemcpyDeviceToHost));
+    if (std::isfinite(e_trial)) ds.e_t = e_trial;
+    ds.status = 0;
+    HIP_TRY(hipMemcpy(c->dmc_state, &ds, sizeof(ds), hipMemcpyHostToDevice));
+    drop_graph(c);  // walker buffers and the population change from here on
+    for (int gen = 0; gen < n_generations; ++gen) {
+        if (c->prec == CQ_FP64)
+            dmc_generation<double>(c, gen, n_target, tau);
+        else
+            dmc_generation<float>(c, gen, n_target, tau);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        HIP_TRY(hipMemcpy(&ds, c->dmc_state, sizeof(ds), hipMemcpyDeviceToHost));
+        c->hp.step += 1;
+        c->hp.rec_sweep += 1;
+        if (ds.status) {
+            if (history) HIP_TRY(hipMemcpy(history, c->dmc_hist, sizeof(double) * 4 * gen, hipMemcpyDeviceToHost));
+            return fail(CQ_ESTATE, "DMC population " + std::to_string(ds.new_pop) +
+                                       (ds.new_pop == 0 ? " died out" : " exceeds max_walkers") + " at generation " +
+                                       std::to_string(gen));
+        }
+        cq_status cs = check_singular(c, "run_dmc");
+        if (cs != CQ_OK) return cs;
+        swap_walker_sets(c);
+        c->W = ds.new_pop;
+    }
+    if (history)
+        HIP_TRY(hipMemcpy(history, c->dmc_hist, sizeof(double) * 4 * (size_t)n_generations, hipMemcpyDeviceToHost));
+    return CQ_OK;
+}
+
+cq_status cq_crowd_get_population(cq_crowd* c, int* n_walkers)
+{
+    if (!c || !n_walkers) return fail(CQ_EINVAL, "NULL argument");
+    *n_walkers = c->W;
     return CQ_OK;
 }
 
@@ -750,6 +933,12 @@ cq_status cq_crowd_get_positions(cq_crowd* c, double* R, int* n_walkers_per_syst
     if (!c) return fail(CQ_EINVAL, "crowd is NULL");
     if (n_walkers_per_system) n_walkers_per_system[0] = c->W;
     return copy_out(c, R, c->R, sizeof(double) * c->W * c->ne * 3);
+}
+
+cq_status cq_crowd_get_uids(cq_crowd* c, uint32_t* uids)
+{
+    if (!c) return fail(CQ_EINVAL, "crowd is NULL");
+    return copy_out(c, uids, c->uid, sizeof(uint32_t) * c->W);
 }
 
 cq_status cq_crowd_get_inverse(cq_crowd* c, double* ainv)

@@ -104,6 +104,42 @@ struct CrowdView {
     double* drift;       // [W][2] |log|det| kept - recomputed| at the last inversion
 };
 
+// DMC population state on the device.
+struct DmcState {
+    double e_t;       // trial energy
+    int new_pop;      // population after the last branching
+    int status;       // 1: population died out or exceeded the capacity
+    long long nacc;   // accepted / proposed moves over all generations
+    long long nprop;
+};
+
+// Branching buffers of one crowd.
+struct DmcView {
+    DmcState* state;
+    double* wt;       // [cap] weights of the generation
+    int* mult;        // [cap] multiplicities
+    int* off;         // [cap] first child index
+    double* history;  // [n_gen][4] population, sum of weights, E_est, E_T
+    int pop, cap, n_target, chunks;
+    double ecut;
+    uint64_t seed;
+};
+
+// The per-walker arrays that branching copies (one of two buffer sets).
+template <typename T>
+struct WalkerArrays {
+    double* R;
+    T* M;
+    T* VGL;
+    double* logdet;
+    int* sign;
+    double* eloc;
+    double* eold;     // E_L at the start of the generation
+    uint32_t* uid;
+    long long* nacc;
+    long long* nprop;
+};
+
 // FP64 Gauss-Jordan workspace for matrices too large for LDS.
 struct InvWork {
     double* S;        // [nmat][N][N]
@@ -132,6 +168,10 @@ void launch_flush_mfma(const CrowdView<float>& v, int spin, hipStream_t s, bool 
 template <typename T> void launch_energy(const CrowdView<T>& v, hipStream_t s);
 template <typename T> void launch_inverse(const CrowdView<T>& v, const InvWork& wk, hipStream_t s);
 void launch_sweep_end(Params* prm, hipStream_t s);
+template <typename T> void launch_window_dmc(const CrowdView<T>& v, int e0, int nmoves, hipStream_t s);
+template <typename T>
+void launch_dmc_branch(const DmcView& d, const WalkerArrays<T>& src, const WalkerArrays<T>& dst, int n, int ne,
+                       const Params* prm, int gen, hipStream_t s);
 void launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 size_t inverse_work_bytes(int nmat, int n);
 int panel_width(int n);  // columns per panel of the blocked inversion
