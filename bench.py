@@ -170,6 +170,69 @@ def cpu_baseline(wl, moves_per_walker):
                 seconds=round(t2 - t0, 1))
 
 
+def run_c5(cq, args):
+    """C5: DMC (tau = 0.01) on three systems at once (S1/S2/S3: 32, 256, 1024 electrons per spin;
+    target populations 2000, 500, 64), mixed precision, one crowd per system on its own stream,
+    driven by its own host thread; against the same generations in FP64 run one system after
+    another.  Moves per second over all systems (accepted + rejected drift-diffusion moves)."""
+    import threading
+    from synth import WORKLOADS, start_positions
+    systems = [WORKLOADS[k] for k in ("c5s1", "c5s2", "c5s3")]
+    tau, warm, gens = 0.01, args.warmup, args.steps
+
+    def one(wl, precision, out):
+        s = make_system(cq, wl, 4 if precision == "mixed" else 8)
+        cap = 4 * wl.walkers + 64
+        c = cq.Crowd(s, wl.walkers, precision=precision, delay_rank=wl.delay_rank, seed=wl.seed,
+                     max_walkers=cap, path="window")
+        c.set_positions(start_positions(wl.seed, wl.walkers, wl.n_e, wl.L))
+        c.run_vmc(4, wl.sigma)  # equilibrate in VMC before the first DMC generation
+        e0 = float(np.mean(c.local_energy()))
+        c.run_dmc(warm, tau, e0, n_target=wl.dmc_target)
+        out["ready"].wait()
+        t0 = time.perf_counter()
+        h = c.run_dmc(gens, tau, float("nan"), n_target=wl.dmc_target)
+        t1 = time.perf_counter()
+        out[wl.name] = dict(seconds=t1 - t0, moves=float(h[:, 0].sum()) * wl.n_e if gens else 0.0,
+                            pop=[int(x) for x in h[:, 0]], e_t=float(h[-1, 3]) if gens else None, t0=t0, t1=t1)
+        c.close()
+        s.close()
+
+    res = {}
+    # mixed: three systems concurrently
+    out = {"ready": threading.Barrier(len(systems))}
+    ths = [threading.Thread(target=one, args=(wl, "mixed", out)) for wl in systems]
+    for t in ths:
+        t.start()
+    for t in ths:
+        t.join()
+    mixed = {wl.name: out[wl.name] for wl in systems}
+    span = max(v["t1"] for v in mixed.values()) - min(v["t0"] for v in mixed.values())
+    moves = sum(v["moves"] for v in mixed.values())
+    log("  c5 mixed, concurrent: %.3e moves/s over %.2f s" % (moves / span, span))
+    # FP64: one system after another
+    f64 = {}
+    for wl in systems:
+        o = {"ready": threading.Barrier(1)}
+        one(wl, "fp64", o)
+        f64[wl.name] = o[wl.name]
+    f64_s = sum(v["seconds"] for v in f64.values())
+    f64_moves = sum(v["moves"] for v in f64.values())
+    log("  c5 fp64, per system: %.3e moves/s over %.2f s" % (f64_moves / f64_s, f64_s))
+    res = dict(metric="DMC electron moves/sec at 1 GPU, three systems at once (mixed) vs per-system FP64",
+               value=round(moves / span, 1), unit="moves/s", n_gpus=1, steps=gens, warmup=warm,
+               ms_per_step=round(1e3 * span / max(gens, 1), 3), higher_is_better=True, scaling="weak",
+               vs_baseline=None, dtype="f32", data="synthetic (seeded Philox B-spline coefficients, uniform starts)",
+               config=dict(workload="c5: DMC tau=0.01, S1 32+32 e L=10 G=48 target 2000, S2 256+256 e L=20 G=64 "
+                                    "target 500, S3 1024+1024 e L=32 G=96 target 64; mixed; one crowd per "
+                                    "system on its own stream"),
+               per_system={k: dict(moves_per_s=round(v["moves"] / v["seconds"], 1), pop=v["pop"], e_t=v["e_t"])
+                           for k, v in mixed.items()},
+               fp64_per_system_moves_per_s=round(f64_moves / f64_s, 1),
+               mixed_concurrent_over_fp64_sequential=round((moves / span) / (f64_moves / f64_s), 3))
+    print(json.dumps(res), flush=True)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -180,6 +243,9 @@ def main():
         sys.exit(2)
     import paper_2209_14487_amd as cq
     from synth import WORKLOADS
+    if args.workload == "c5":
+        run_c5(cq, args)
+        return
     wl = WORKLOADS[args.workload]
     delay = args.delay if args.delay is not None else wl.delay_rank
     log("workload %s: N=%d per spin, W=%d x %d crowd(s), G=%d, k=%d, recompute every %d"

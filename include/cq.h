@@ -123,7 +123,10 @@ typedef struct {
     int precision;        /* cq_precision: CQ_MIXED uses the FP32 table and FP32 inverses,
                              FP64 for log|det|, the recompute and every sum over walkers */
     int delay_rank;       /* k: 1 = Sherman-Morrison after every accepted move, 2..32 = delayed
-                             rank-k update (window of k proposals); 0 = choose by autotuning */
+                             rank-k update (the batched path closes a window after k accepted
+                             moves, the per-move paths after k proposals); 0 = autotune: the
+                             first run_vmc (or cq_crowd_autotune) times sweeps at k = 1, 2, 4,
+                             ..., min(32, n_up) and keeps the fastest */
     int recompute_every;  /* sweeps between FP64 recomputes of the inverses (0 = never) */
     uint64_t seed;        /* Philox key of the move random numbers */
     uint32_t first_uid;   /* walker w of this crowd has uid first_uid + w (random streams) */
@@ -180,6 +183,18 @@ cq_status cq_crowd_record_moves(cq_crowd* c, int n_sweeps);
 /* Copy the records out: arrays [n_sweeps][Ne][W]; any pointer may be NULL. */
 cq_status cq_crowd_get_move_records(cq_crowd* c, double* rho, double* dlnj, double* prob, uint8_t* acc);
 
+/* Delay-rank autotuning for a crowd created with delay_rank = 0: time
+   sweeps_per_candidate sweeps (eager launches, HIP events) at every candidate
+   k = 1, 2, 4, ..., min(32, n_up) and keep the fastest; *chosen_k (may be NULL)
+   receives it.  The timed sweeps are ordinary sweeps of the chain (they advance
+   the positions and the random-number step).  run_vmc calls it with one sweep
+   per candidate when the crowd has not been tuned.  Errors: CQ_EINVAL,
+   CQ_ESTATE (positions not set). */
+cq_status cq_crowd_autotune(cq_crowd* c, int sweeps_per_candidate, int* chosen_k);
+
+/* The delay rank in use (after autotuning, the chosen one). */
+cq_status cq_crowd_get_delay_rank(cq_crowd* c, int* k);
+
 /* Diffusion Monte Carlo (paper Alg. 1 with a drift-diffusion move at L5 and
    reweighting / branching at L12-L13; Sec. II-A).  Runs n_generations
    generations of the crowd's population at time step tau: per generation one
@@ -188,7 +203,7 @@ cq_status cq_crowd_get_move_records(cq_crowd* c, double* rho, double* dlnj, doub
    then branching:
      E_c = E_L clipped to E_T +- 0.2 sqrt(Ne / tau),
      w = exp(-tau ((E_c,old + E_c,new) / 2 - E_T)),  m = min(3, floor(w + u_b)),
-     E_est = sum w E_L / sum w,  E_T <- E_est - ln(N / n_target) / (10 tau).
+     E_est = sum w E_L / sum w,  E_T <- E_est - ln(N / n_target) / tau.
    Children follow their parent in population order; copy 0 keeps the parent's
    uid, copy c >= 1 gets a new one from the counter generator.  e_trial: the
    starting E_T (NaN: continue with the current one).  history (may be NULL):

@@ -797,7 +797,7 @@ int or_dmc_move_prob(const or_system* s, const double* R, int e, const double de
 /* Per generation, for the whole population of this system:                 */
 /*   E_c = E_L clipped to [E_T - ecut, E_T + ecut], ecut = 0.2 sqrt(Ne/tau)   */
 /*   w = exp(-tau ((E_c(old) + E_c(new))/2 - E_T)), m = min(3, floor(w + u_b))*/
-/*   E_est = sum w E_L(new) / sum w,  E_T <- E_est - ln(N_w / N_target)/(10 tau) */
+/*   E_est = sum w E_L(new) / sum w,  E_T <- E_est - ln(N_w / N_target) / tau   */
 /* Children follow their parent in population order; copy 0 keeps the       */
 /* parent's uid.  Returns the final population size, -1 on a singular start, */
 /* -2 if the population dies out or exceeds max_pop.                         */
@@ -897,7 +897,7 @@ int or_dmc(const or_system* s, int n_walkers, const uint32_t* uids, const double
         free(mult);
         /* L13: trial energy */
         double e_est = wesum / wsum;
-        e_t = e_est - log((double)new_pop / (double)n_target) / (10.0 * tau);
+        e_t = e_est - log((double)new_pop / (double)n_target) / tau;
         pop = new_pop;
         if (pop_out) pop_out[gen] = pop;
         if (wsum_out) wsum_out[gen] = wsum;

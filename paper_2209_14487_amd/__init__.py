@@ -55,6 +55,8 @@ _SIGS = {
     "cq_crowd_run_vmc": [_P, _I, ctypes.c_double],
     "cq_crowd_run_dmc": [_P, _I, ctypes.c_double, ctypes.c_double, _I, _P],
     "cq_crowd_get_population": [_P, _P],
+    "cq_crowd_autotune": [_P, _I, _P],
+    "cq_crowd_get_delay_rank": [_P, _P],
     "cq_crowd_get_uids": [_P, _P],
     "cq_crowd_recompute": [_P, _P],
     "cq_crowd_get_logdet": [_P, _P, _P],
@@ -210,6 +212,16 @@ class Crowd:
         finally:
             self.W = self.population()
         return h
+
+    def autotune(self, sweeps_per_candidate: int = 1) -> int:
+        k = ctypes.c_int()
+        _check(lib().cq_crowd_autotune(self._h, sweeps_per_candidate, ctypes.byref(k)))
+        return k.value
+
+    def delay_rank(self) -> int:
+        k = ctypes.c_int()
+        _check(lib().cq_crowd_get_delay_rank(self._h, ctypes.byref(k)))
+        return k.value
 
     def population(self) -> int:
         n = ctypes.c_int()

@@ -53,6 +53,8 @@ struct cq_crowd {
     const cq_system* sys = nullptr;
     int W = 0, n = 0, ne = 0, K = 1, Q = 1, prec = CQ_MIXED, recompute_every = 0, use_graph = 0;
     int Wcap = 0;  // capacity of the per-walker buffers (DMC populations)
+    int Kcap = 1;  // largest delay rank the window buffers hold
+    bool autotune = false, tuned = false;
     int path = CQ_PATH_WINDOW;
     uint64_t seed = 0;
     uint32_t first_uid = 0;
@@ -662,6 +664,8 @@ cq_status cq_crowd_create(const cq_system* const* systems, const int* walkers_pe
     c->n = s->n_up;
     c->ne = 2 * s->n_up;
     c->K = K;
+    c->Kcap = K;
+    c->autotune = desc->delay_rank == 0;
     c->prec = desc->precision;
     c->recompute_every = desc->recompute_every;
     c->use_graph = desc->use_graph;
@@ -789,6 +793,66 @@ cq_status cq_crowd_set_positions(cq_crowd* c, const double* R, int on_device, ui
     return CQ_OK;
 }
 
+// Delay-rank autotuning: time `sweeps` eager sweeps at every k in {1, 2, 4, ..., Kcap}
+// (powers of two below Kcap, then Kcap itself)
+// (the window buffers are sized for Kcap) and keep the fastest.  The timed sweeps are
+// ordinary sweeps of the chain.
+static cq_status autotune_k(cq_crowd* c, int sweeps, int* chosen)
+{
+    hipEvent_t a, b;
+    HIP_TRY(hipEventCreate(&a));
+    if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return fail(CQ_EDEVICE, "hipEventCreate failed");
+    }
+    int best_k = c->K;
+    float best_ms = 0.0f;
+    std::vector<int> cands;
+    for (int k = 1; k < c->Kcap; k *= 2) cands.push_back(k);
+    cands.push_back(c->Kcap);
+    for (int k : cands) {
+        c->K = k;
+        c->Q = c->path == CQ_PATH_BATCH ? cq::batch_candidates(c->n, k) : k;
+        drop_graph(c);
+        if (c->path == CQ_PATH_MULTI) {
+            if (c->prec == CQ_FP64)
+                cq::launch_first_proposal<double>(view<double>(c), c->stream);
+            else
+                cq::launch_first_proposal<float>(view<float>(c), c->stream);
+        }
+        (void)hipEventRecord(a, c->stream);
+        for (int s = 0; s < sweeps; ++s) {
+            sweep(c);
+            c->hp.step += 1;
+            c->hp.rec_sweep += 1;
+        }
+        (void)hipEventRecord(b, c->stream);
+        HIP_TRY(hipEventSynchronize(b));
+        float ms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, a, b));
+        if (best_ms == 0.0f || ms < best_ms) {
+            best_ms = ms;
+            best_k = k;
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    c->K = best_k;
+    c->Q = c->path == CQ_PATH_BATCH ? cq::batch_candidates(c->n, best_k) : best_k;
+    drop_graph(c);
+    c->tuned = true;
+    if (chosen) *chosen = best_k;
+    return check_singular(c, "autotune");
+}
+
+cq_status cq_crowd_autotune(cq_crowd* c, int sweeps_per_candidate, int* chosen_k)
+{
+    if (!c) return fail(CQ_EINVAL, "crowd is NULL");
+    if (sweeps_per_candidate < 1) return fail(CQ_EINVAL, "sweeps_per_candidate must be >= 1");
+    if (!c->ready) return fail(CQ_ESTATE, "set positions before autotuning");
+    return autotune_k(c, sweeps_per_candidate, chosen_k);
+}
+
 cq_status cq_crowd_run_vmc(cq_crowd* c, int n_sweeps, double sigma)
 {
     if (!c) return fail(CQ_EINVAL, "crowd is NULL");
@@ -797,6 +861,10 @@ cq_status cq_crowd_run_vmc(cq_crowd* c, int n_sweeps, double sigma)
     if (sigma != c->hp.sigma) {
         c->hp.sigma = sigma;
         cq_status st = push_params(c);
+        if (st != CQ_OK) return st;
+    }
+    if (c->autotune && !c->tuned && n_sweeps > 0) {
+        cq_status st = autotune_k(c, 1, nullptr);
         if (st != CQ_OK) return st;
     }
     // proposal of the first move (each move kernel makes the next one's)
@@ -869,6 +937,13 @@ cq_status cq_crowd_run_dmc(cq_crowd* c, int n_generations, double tau, double e_
     }
     if (history)
         HIP_TRY(hipMemcpy(history, c->dmc_hist, sizeof(double) * 4 * (size_t)n_generations, hipMemcpyDeviceToHost));
+    return CQ_OK;
+}
+
+cq_status cq_crowd_get_delay_rank(cq_crowd* c, int* k)
+{
+    if (!c || !k) return fail(CQ_EINVAL, "NULL argument");
+    *k = c->K;
     return CQ_OK;
 }
 

@@ -23,7 +23,7 @@
 // Branching after every generation (all walkers of the crowd's population):
 //   E_c = E_L clipped to [E_T - ecut, E_T + ecut], ecut = 0.2 sqrt(Ne / tau)
 //   w = exp(-tau ((E_c(old) + E_c(new)) / 2 - E_T)),  m = min(3, floor(w + u_b))
-//   E_est = sum w E_L / sum w,  E_T <- E_est - ln(N_new / N_target) / (10 tau)
+//   E_est = sum w E_L / sum w,  E_T <- E_est - ln(N_new / N_target) / tau
 // Children follow their parent in population order; copy 0 keeps the parent's
 // uid, copy c >= 1 gets Philox(uid, step, c, block 4) word 0.  The sums and the
 // prefix sum run in population order (one thread), as the definition reads.
@@ -476,7 +476,7 @@ __global__ void k_dmc_sums(DmcView d, const double* eloc, long long* nacc, long 
         return;
     }
     const double e_est = wesum / wsum;
-    const double et = e_est - log((double)off / (double)d.n_target) / (10.0 * prm->tau);
+    const double et = e_est - log((double)off / (double)d.n_target) / prm->tau;
     st->e_t = et;
     double* h = d.history + (size_t)gen * 4;
     h[0] = (double)off;

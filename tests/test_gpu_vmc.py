@@ -328,3 +328,23 @@ def test_paths_agree():
         assert np.all(np.abs(a["rho"] - b["rho"]) <= 1e-10 * np.maximum(1.0, np.abs(b["rho"])))
         assert np.all(np.abs(a["logdet"] - b["logdet"]) <= 1e-10 * np.maximum(1.0, np.abs(b["logdet"])))
         assert np.all(np.abs(a["eloc"] - b["eloc"]) <= 1e-10 * np.maximum(1.0, np.abs(b["eloc"])))
+
+
+def test_autotuned_delay_rank_keeps_the_chain():
+    """delay_rank = 0: the first run times sweeps at k = 1, 2, 4, ..., 32 and keeps the fastest;
+    the tuning sweeps are ordinary sweeps, so the chain still matches the FP64 oracle."""
+    n, L, G, W, S = 32, 10.0, 48, 16, 1
+    g, o = make_pair(n, L, G, 1002, coef_seed=1002)
+    R0 = start_positions(1002, W, 2 * n, L)
+    crowd = cq.Crowd(g, W, precision="fp64", delay_rank=0, seed=1002)
+    crowd.set_positions(R0)
+    k = crowd.autotune(1)
+    assert k in (1, 2, 4, 8, 16, 32) and crowd.delay_rank() == k
+    tuned_sweeps = 6  # one per candidate
+    crowd.record(S)
+    crowd.run_vmc(S, 0.5)
+    ref = orc.vmc(o, R0, tuned_sweeps + S, sigma=0.5)
+    rec = crowd.records()
+    assert np.array_equal(rec["acc"][0], ref.acc[tuned_sweeps])
+    assert np.all(np.abs(rec["rho"][0] - ref.rho[tuned_sweeps]) <= 1e-10 * np.maximum(1.0, np.abs(ref.rho[tuned_sweeps])))
+    crowd.close()

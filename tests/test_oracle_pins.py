@@ -401,8 +401,8 @@ def test_dmc_branching_bookkeeping():
     assert res.pop[-1] == len(res.uids) > 0
     # every final walker descends from an original uid or is a hashed child uid
     assert len(set(res.uids.tolist())) == len(res.uids)
-    # the trial energy update: E_T = E_est - ln(N/N_target)/(10 tau)
-    assert np.allclose(res.e_t, res.e_est - np.log(res.pop / 20.0) / (10 * 0.05), atol=1e-12)
+    # the trial energy update: E_T = E_est - ln(N/N_target)/tau
+    assert np.allclose(res.e_t, res.e_est - np.log(res.pop / 20.0) / 0.05, atol=1e-12)
 
 
 def test_dmc_drift_matches_finite_differences():
