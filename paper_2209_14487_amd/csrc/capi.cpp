@@ -51,7 +51,7 @@ struct cq_system {
 
 struct cq_crowd {
     const cq_system* sys = nullptr;
-    int W = 0, n = 0, ne = 0, K = 1, Q = 1, prec = CQ_MIXED, recompute_every = 0, use_graph = 0;
+    int W = 0, n = 0, ne = 0, K = 1, Q = 1, QR = 1, prec = CQ_MIXED, recompute_every = 0, use_graph = 0;
     int Wcap = 0;  // capacity of the per-walker buffers (DMC populations)
     int Kcap = 1;  // largest delay rank the window buffers hold
     bool autotune = false, tuned = false;
@@ -60,6 +60,10 @@ struct cq_crowd {
     uint32_t first_uid = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    // second stream of the batched path: the next round's proposals and gather run on it
+    // while the current round's update runs on `stream`; fork / join events per round
+    hipStream_t stream2 = nullptr;
+    std::vector<hipEvent_t> fork_ev, join_ev;
     std::vector<void*> allocs;
     // device state
     double* R = nullptr;
@@ -147,6 +151,7 @@ cq::CrowdView<T> view(const cq_crowd* c)
     v.ne = c->ne;
     v.K = c->K;
     v.Q = c->Q;
+    v.QR = c->QR;
     v.G = c->sys->G;
     v.n_orb = c->sys->n_orb;
     v.L = c->sys->L;
@@ -210,7 +215,7 @@ cq_status dev_alloc(cq_crowd* c, void** p, size_t bytes)
     return CQ_OK;
 }
 
-void timed_begin(cq_crowd* c, int kind)
+void timed_begin(cq_crowd* c, int kind, hipStream_t st = nullptr)
 {
     if (!(c->timing_mask >> kind & 1) || c->ev_used[kind] >= (size_t)kEventCap) return;
     auto& pool = c->ev[kind];
@@ -220,14 +225,14 @@ void timed_begin(cq_crowd* c, int kind)
         if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return; }
         pool.push_back({a, b});
     }
-    (void)hipEventRecord(pool[c->ev_used[kind]].first, c->stream);
+    (void)hipEventRecord(pool[c->ev_used[kind]].first, st ? st : c->stream);
 }
 
-void timed_end(cq_crowd* c, int kind)
+void timed_end(cq_crowd* c, int kind, hipStream_t st = nullptr)
 {
     if (!(c->timing_mask >> kind & 1) || c->ev_used[kind] >= (size_t)kEventCap || c->ev_used[kind] >= c->ev[kind].size())
         return;
-    (void)hipEventRecord(c->ev[kind][c->ev_used[kind]].second, c->stream);
+    (void)hipEventRecord(c->ev[kind][c->ev_used[kind]].second, st ? st : c->stream);
     c->ev_used[kind]++;
 }
 
@@ -237,22 +242,44 @@ void enqueue_sweep(cq_crowd* c)
     const cq::CrowdView<T> v = view<T>(c);
     const int n = c->n, K = c->K;
     if (c->path == CQ_PATH_BATCH) {
-        const int rounds = cq::batch_rounds(n, K);
-        for (int spin = 0; spin < 2; ++spin)
-            for (int r = 0; r < rounds; ++r) {
-                timed_begin(c, CQ_KERNEL_PROPOSE);
-                cq::launch_batch_stencils<T>(v, spin, r == 0, c->stream);
-                timed_end(c, CQ_KERNEL_PROPOSE);
-                timed_begin(c, CQ_KERNEL_VGL);
-                cq::launch_batch_vgl<T>(v, spin, c->stream);
-                timed_end(c, CQ_KERNEL_VGL);
-                timed_begin(c, CQ_KERNEL_RESOLVE);
-                cq::launch_batch_decide<T>(v, spin, c->stream);
-                timed_end(c, CQ_KERNEL_RESOLVE);
-                timed_begin(c, CQ_KERNEL_UPDATE);
-                cq::launch_flush<T>(v, spin, c->stream, true);
-                timed_end(c, CQ_KERNEL_UPDATE);
+        // Rounds of both spin blocks in order.  Round r+1's proposals and gather run on
+        // stream2 while round r's update runs on stream (they touch disjoint data: the
+        // gather reads positions and cursors that round r's decisions already wrote, the
+        // update reads and writes the inverse); the next decisions wait for both.
+        const int rounds = cq::batch_rounds(n, K), total = 2 * rounds;
+        auto gather = [&](int q, hipStream_t st) {
+            const int spin = q / rounds, r = q % rounds;
+            timed_begin(c, CQ_KERNEL_PROPOSE, st);
+            cq::launch_batch_stencils<T>(v, spin, r == 0, st);
+            timed_end(c, CQ_KERNEL_PROPOSE, st);
+            timed_begin(c, CQ_KERNEL_VGL, st);
+            cq::launch_batch_vgl<T>(v, spin, st);
+            timed_end(c, CQ_KERNEL_VGL, st);
+        };
+        const bool overlap = c->stream2 != nullptr && (int)c->fork_ev.size() >= total;
+        gather(0, c->stream);
+        for (int q = 0; q < total; ++q) {
+            const int spin = q / rounds;
+            timed_begin(c, CQ_KERNEL_RESOLVE);
+            cq::launch_batch_decide<T>(v, spin, c->stream);
+            timed_end(c, CQ_KERNEL_RESOLVE);
+            // no overlap into a new spin block: its candidates' ring slots are not disjoint from
+            // the slots of the rows the last update of the previous block still reads
+            const bool fork = overlap && q + 1 < total && (q + 1) % rounds != 0;
+            if (fork) {
+                (void)hipEventRecord(c->fork_ev[q], c->stream);
+                (void)hipStreamWaitEvent(c->stream2, c->fork_ev[q], 0);
+                gather(q + 1, c->stream2);
+                (void)hipEventRecord(c->join_ev[q], c->stream2);
             }
+            timed_begin(c, CQ_KERNEL_UPDATE);
+            cq::launch_flush<T>(v, spin, c->stream, true);
+            timed_end(c, CQ_KERNEL_UPDATE);
+            if (fork)
+                (void)hipStreamWaitEvent(c->stream, c->join_ev[q], 0);
+            else if (q + 1 < total)
+                gather(q + 1, c->stream);  // after the update, in stream order
+        }
         timed_begin(c, CQ_KERNEL_ENERGY);
         cq::launch_energy<T>(v, c->stream);
         timed_end(c, CQ_KERNEL_ENERGY);
@@ -382,7 +409,7 @@ cq_status setup_state(cq_crowd* c)
     // window slots are read (masked) before they are first written: start them at 0; every
     // walker slot up to the capacity, since DMC branching fills slots past the initial count
     const size_t es = c->prec == CQ_FP64 ? 8 : 4;
-    HIP_TRY(hipMemsetAsync(c->stage, 0, es * c->Wcap * c->Q * 5 * c->n, c->stream));
+    HIP_TRY(hipMemsetAsync(c->stage, 0, es * c->Wcap * c->QR * 5 * c->n, c->stream));
     HIP_TRY(hipMemsetAsync(c->cur, 0, sizeof(int) * 3 * c->Wcap, c->stream));
     HIP_TRY(hipMemsetAsync(c->Cbuf, 0, es * c->Wcap * c->K * c->n, c->stream));
     HIP_TRY(hipMemsetAsync(c->status, 0, sizeof(int) * c->Wcap, c->stream));
@@ -631,6 +658,9 @@ void cq_crowd_destroy(cq_crowd* c)
     if (c->rec_prob) (void)hipFree(c->rec_prob);
     if (c->rec_acc) (void)hipFree(c->rec_acc);
     if (c->forced) (void)hipFree(c->forced);
+    for (hipEvent_t e : c->fork_ev) (void)hipEventDestroy(e);
+    for (hipEvent_t e : c->join_ev) (void)hipEventDestroy(e);
+    if (c->stream2) (void)hipStreamDestroy(c->stream2);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
@@ -671,6 +701,7 @@ cq_status cq_crowd_create(const cq_system* const* systems, const int* walkers_pe
     c->use_graph = desc->use_graph;
     c->path = desc->kernel_path != CQ_PATH_AUTO ? desc->kernel_path : CQ_PATH_BATCH;
     c->Q = c->path == CQ_PATH_BATCH ? cq::batch_candidates(c->n, K) : K;
+    c->QR = c->path == CQ_PATH_BATCH ? 2 * c->Q : c->Q;
     c->seed = desc->seed;
     c->first_uid = desc->first_uid;
     if (desc->hip_stream) {
@@ -681,6 +712,25 @@ cq_status cq_crowd_create(const cq_system* const* systems, const int* walkers_pe
             return fail(CQ_EDEVICE, "hipStreamCreate failed");
         }
         c->own_stream = true;
+    }
+    if (c->path == CQ_PATH_BATCH) {
+        // default priority, like the crowd's own stream
+        if (hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking) == hipSuccess) {
+            const int total = 2 * cq::batch_rounds(c->n, 1);  // enough for any delay rank
+            for (int i = 0; i < total; ++i) {
+                hipEvent_t f, j;
+                if (hipEventCreateWithFlags(&f, hipEventDisableTiming) != hipSuccess) break;
+                if (hipEventCreateWithFlags(&j, hipEventDisableTiming) != hipSuccess) {
+                    (void)hipEventDestroy(f);
+                    break;
+                }
+                c->fork_ev.push_back(f);
+                c->join_ev.push_back(j);
+            }
+        } else {
+            (void)hipGetLastError();
+            c->stream2 = nullptr;
+        }
     }
     const size_t es = c->prec == CQ_FP64 ? 8 : 4;
     const size_t n = c->n, ne = c->ne;
@@ -704,14 +754,14 @@ cq_status cq_crowd_create(const cq_system* const* systems, const int* walkers_pe
         {(void**)&c->cnt, sizeof(int) * 3 * Wc},
         {(void**)&c->welec, sizeof(int) * Wc * K},
         {(void**)&c->wslot, sizeof(int) * Wc * K},
-        {(void**)&c->jd, sizeof(double) * Wc * c->Q},
-        {(void**)&c->rprop, sizeof(double) * Wc * c->Q * 3},
-        {(void**)&c->sidx, sizeof(size_t) * Wc * c->Q * 64},
-        {&c->swt, es * Wc * c->Q * 64 * 5},
+        {(void**)&c->jd, sizeof(double) * Wc * c->QR},
+        {(void**)&c->rprop, sizeof(double) * Wc * c->QR * 3},
+        {(void**)&c->sidx, sizeof(size_t) * Wc * c->QR * 64},
+        {&c->swt, es * Wc * c->QR * 64 * 5},
         {(void**)&c->pmat, sizeof(double) * Wc * c->Q * c->Q},
         {(void**)&c->tmat, sizeof(double) * Wc * K * c->Q},
         {(void**)&c->cur, sizeof(int) * Wc * 3},
-        {&c->stage, es * Wc * c->Q * 5 * n},
+        {&c->stage, es * Wc * c->QR * 5 * n},
         {&c->Cbuf, es * Wc * K * n},
         {(void**)&c->ct, sizeof(float) * Wc * n * cq::kMaxDelay},
         {(void**)&c->wrho, sizeof(double) * Wc * K},
@@ -813,6 +863,7 @@ static cq_status autotune_k(cq_crowd* c, int sweeps, int* chosen)
     for (int k : cands) {
         c->K = k;
         c->Q = c->path == CQ_PATH_BATCH ? cq::batch_candidates(c->n, k) : k;
+        c->QR = c->path == CQ_PATH_BATCH ? 2 * c->Q : c->Q;
         drop_graph(c);
         if (c->path == CQ_PATH_MULTI) {
             if (c->prec == CQ_FP64)
@@ -839,6 +890,7 @@ static cq_status autotune_k(cq_crowd* c, int sweeps, int* chosen)
     (void)hipEventDestroy(b);
     c->K = best_k;
     c->Q = c->path == CQ_PATH_BATCH ? cq::batch_candidates(c->n, best_k) : best_k;
+    c->QR = c->path == CQ_PATH_BATCH ? 2 * c->Q : c->Q;
     drop_graph(c);
     c->tuned = true;
     if (chosen) *chosen = best_k;

@@ -55,7 +55,10 @@ struct Params {
 template <typename T>
 struct CrowdView {
     int W, n, ne, K;
-    int Q;               // stage slots per walker: K, or the candidate ring of the batched path
+    int Q;               // candidates per round (batched path), else K
+    int QR;              // stage slots per walker: K, or the candidate ring of the batched path (2 Q,
+                         // so a round's new candidates never reuse a slot the previous window's
+                         // update still reads)
     int G, n_orb;
     double L;
     const T* table;

@@ -116,13 +116,13 @@ __device__ __forceinline__ bool new_candidate(const int* cur, int w, int t, int 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_stencils(CrowdView<T> v, int spin)
 {
-    const int n = v.n, Q = v.Q;
+    const int n = v.n, Q = v.Q, QR = v.QR;
     const int pi = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (pi >= v.W * Q) return;
     int a = 0;
     if (!new_candidate(v.cur, pi / Q, pi % Q, Q, n, a)) return;
-    const int w = pi / Q, e = spin * n + a, slot = a % Q;
-    const size_t ps = (size_t)w * Q + slot;
+    const int w = pi / Q, e = spin * n + a, slot = a % QR;
+    const size_t ps = (size_t)w * QR + slot;
     double z[3], rp[3];
     gauss3(v.seed, v.uid[w], v.prm->step, (uint32_t)e, z);
     const double sigma = v.prm->sigma;
@@ -145,7 +145,7 @@ __global__ __launch_bounds__(kBlock) void k_prop_vgl(CrowdView<T> v, int spin, i
     __shared__ double s_rp[4][3];
     __shared__ double s_part[kBlock];
     __shared__ int s_ok[4];
-    const int n = v.n, Q = v.Q, groups = n / VEC;
+    const int n = v.n, Q = v.Q, QR = v.QR, groups = n / VEC;
     const int nprop = v.W * Q;
     const int nt = blockDim.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int first = blockIdx.x * pp;
@@ -162,7 +162,7 @@ __global__ __launch_bounds__(kBlock) void k_prop_vgl(CrowdView<T> v, int spin, i
         if (!s_ok[p]) continue;
         int a = 0;
         new_candidate(v.cur, pi / Q, pi % Q, Q, n, a);
-        const size_t ps = (size_t)(pi / Q) * Q + a % Q;
+        const size_t ps = (size_t)(pi / Q) * QR + a % QR;
         s_idx[p][l] = v.sidx[ps * 64 + l];
         const T* sw = (const T*)v.swt + (ps * 64 + l) * 5;
 #pragma unroll
@@ -177,7 +177,7 @@ __global__ __launch_bounds__(kBlock) void k_prop_vgl(CrowdView<T> v, int spin, i
     const bool live = p < pp && pi < nprop && s_ok[p];
     int a = 0;
     if (live) new_candidate(v.cur, pi / Q, pi % Q, Q, n, a);
-    const int w = live ? pi / Q : 0, e = spin * n + a, slot = a % Q;
+    const int w = live ? pi / Q : 0, e = spin * n + a, slot = a % QR;
     const bool j2 = v.use_j2 && live;
     const double* Rw = v.R + (size_t)w * v.ne * 3;
     double re[3], rpp[3];
@@ -202,7 +202,7 @@ __global__ __launch_bounds__(kBlock) void k_prop_vgl(CrowdView<T> v, int spin, i
     const int gsteps = live ? 4 * ((groups - t0 + tpp - 1) / tpp) : 0;  // plane iterations
     const int jper = gsteps ? (jn + gsteps - 1) / gsteps : 0;
     if (live) {
-        T* dst = v.stage + ((size_t)w * Q + slot) * 5 * (size_t)n;
+        T* dst = v.stage + ((size_t)w * QR + slot) * 5 * (size_t)n;
         const size_t* sidx = s_idx[p];
         const T* sw = s_w[p];
         for (int g = t0; g < groups; g += tpp) {
@@ -240,7 +240,7 @@ __global__ __launch_bounds__(kBlock) void k_prop_vgl(CrowdView<T> v, int spin, i
 
     // Jastrow difference of each proposal against the current positions
     if (!v.use_j2) {
-        if (live && t0 == 0) v.jd[(size_t)w * Q + slot] = 0.0;
+        if (live && t0 == 0) v.jd[(size_t)w * QR + slot] = 0.0;
         return;
     }
     if (tpp % 64 == 0) {
@@ -250,7 +250,7 @@ __global__ __launch_bounds__(kBlock) void k_prop_vgl(CrowdView<T> v, int spin, i
         if (live && t0 == 0) {
             double sum = 0.0;
             for (int q = 0; q < tpp / 64; ++q) sum += s_part[p * (tpp / 64) + q];
-            v.jd[(size_t)w * Q + slot] = sum;
+            v.jd[(size_t)w * QR + slot] = sum;
         }
     } else {
         s_part[tid] = dj;
@@ -258,7 +258,7 @@ __global__ __launch_bounds__(kBlock) void k_prop_vgl(CrowdView<T> v, int spin, i
         if (live && t0 == 0) {
             double sum = 0.0;
             for (int q = 0; q < tpp; ++q) sum += s_part[tid + q];
-            v.jd[(size_t)w * Q + slot] = sum;
+            v.jd[(size_t)w * QR + slot] = sum;
         }
     }
 }
@@ -289,7 +289,7 @@ __global__ __launch_bounds__(kBlock) void k_pmat(CrowdView<T> v, int spin)
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r = lane & 15, q = lane >> 4;
     const int ci = bi * kPB + r, cj = bj * kPB + r;
-    const T* urow = v.stage + ((size_t)w * Q + (dec + (ci < nc ? ci : 0)) % Q) * 5 * (size_t)n;
+    const T* urow = v.stage + ((size_t)w * v.QR + (dec + (ci < nc ? ci : 0)) % v.QR) * 5 * (size_t)n;
     const T* crow = v.M + (((size_t)w * 2 + spin) * n + dec + (cj < nc ? cj : 0)) * (size_t)n;
     f64x4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll 4
@@ -373,12 +373,12 @@ __global__ __launch_bounds__(kBlock) void k_decide(CrowdView<T> v, int spin)
     const double* Pw = v.pmat + (size_t)w * Q * Q;
     for (int idx = tid; idx < nc * nc; idx += kBlock) S.P[idx / nc][idx % nc] = Pw[(size_t)(idx / nc) * Q + idx % nc];
     if (tid < nc) {
-        const int slot = (dec + tid) % Q;
+        const int slot = (dec + tid) % v.QR;
         S.u[tid] = accept_uniform(v.seed, v.uid[w], step, (uint32_t)(e0 + tid));
-        S.jd[tid] = v.jd[(size_t)w * Q + slot];
+        S.jd[tid] = v.jd[(size_t)w * v.QR + slot];
         for (int k = 0; k < 3; ++k) {
             S.rold[tid][k] = v.R[((size_t)w * v.ne + e0 + tid) * 3 + k];
-            S.rnew[tid][k] = v.rprop[((size_t)w * Q + slot) * 3 + k];
+            S.rnew[tid][k] = v.rprop[((size_t)w * v.QR + slot) * 3 + k];
         }
     }
     __syncthreads();
@@ -465,7 +465,7 @@ __global__ __launch_bounds__(kBlock) void k_decide(CrowdView<T> v, int spin)
     if (tid < cnt) {
         const int a = dec + S.slot[tid];
         v.welec[(size_t)w * K + tid] = a;
-        v.wslot[(size_t)w * K + tid] = a % Q;
+        v.wslot[(size_t)w * K + tid] = a % v.QR;
         for (int k = 0; k < 3; ++k) v.R[((size_t)w * v.ne + spin * n + a) * 3 + k] = S.rnew[S.slot[tid]][k];
     }
     for (int idx = tid; idx < cnt * nc; idx += kBlock) {
@@ -486,7 +486,7 @@ __global__ __launch_bounds__(kBlock) void k_decide(CrowdView<T> v, int spin)
     if (v.use_j2 && tid >= ndec && tid < nc) {
         double d = 0.0;
         for (int j = 0; j < cnt; ++j) d += S.PC[tid][S.slot[j]];
-        v.jd[(size_t)w * Q + (dec + tid) % Q] = S.jd[tid] + d;
+        v.jd[(size_t)w * v.QR + (dec + tid) % v.QR] = S.jd[tid] + d;
     }
 }
 

@@ -140,7 +140,7 @@ __global__ __launch_bounds__(kBlock) void k_window_dmc(CrowdView<T> v, int e0, i
     const double tau = v.prm->tau, sqrt_tau = sqrt(tau);
     const T* Mspin = v.M + ((size_t)w * 2 + spin) * n * (size_t)n;
     const T* VGLspin = v.VGL + ((size_t)w * 2 + spin) * n * 5 * (size_t)n;
-    T* stage = v.stage + (size_t)w * v.Q * 5 * n;
+    T* stage = v.stage + (size_t)w * v.QR * 5 * n;
     T* Cb = v.Cbuf + (size_t)w * K * n;
 
     int cnt = 0;

@@ -50,8 +50,8 @@ __global__ __launch_bounds__(kFlushThreads) void k_flush_mfma(CrowdView<float> v
     if (tid < cnt) {
         wel[tid] = v.welec[(size_t)w * K + tid];
         const int sl = v.wslot[(size_t)w * K + tid];
-        if (sl < 0 || sl >= v.Q) atomicOr(&v.status[w], 2);
-        wsl[tid] = sl < 0 || sl >= v.Q ? 0 : sl;
+        if (sl < 0 || sl >= v.QR) atomicOr(&v.status[w], 2);
+        wsl[tid] = sl < 0 || sl >= v.QR ? 0 : sl;
     }
     __syncthreads();
 
@@ -62,7 +62,7 @@ __global__ __launch_bounds__(kFlushThreads) void k_flush_mfma(CrowdView<float> v
             if (tid == 0) atomicOr(&v.status[w], 2);
             continue;
         }
-        const float* src = v.stage + ((size_t)w * v.Q + wsl[mm]) * 5 * (size_t)n;
+        const float* src = v.stage + ((size_t)w * v.QR + wsl[mm]) * 5 * (size_t)n;
         float* dst = v.VGL + (((size_t)w * 2 + spin) * n + ea) * 5 * (size_t)n;
         for (int i = tid * 4; i < 5 * n; i += kFlushThreads * 4) {
             float x[4];
@@ -96,7 +96,7 @@ __global__ __launch_bounds__(kFlushThreads) void k_flush_mfma(CrowdView<float> v
     f32x16 xacc;
 #pragma unroll
     for (int q = 0; q < 16; ++q) xacc[q] = 0.0f;
-    const float* urow = v.stage + ((size_t)w * v.Q + wsl[l32 < cnt ? l32 : 0]) * 5 * (size_t)n;
+    const float* urow = v.stage + ((size_t)w * v.QR + wsl[l32 < cnt ? l32 : 0]) * 5 * (size_t)n;
     const bool urow_live = l32 < cnt;
     auto fetch_u = [&](int t, float (&u)[16]) {
 #pragma unroll

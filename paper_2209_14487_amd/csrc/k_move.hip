@@ -414,7 +414,7 @@ __global__ __launch_bounds__(kBlock) void k_move(CrowdView<T> v, int e, int prev
     if (valid) {
         // pending window slot: the proposal's orbital rows and the old inverse column c0_e
         if (wave == 0) store16(v.Cbuf + ((size_t)w * K + cnt) * n + j0, m);
-        for (int k = wave; k < 5; k += 4) store16(v.stage + (((size_t)w * v.Q + cnt) * 5 + k) * n + j0, rv[k]);
+        for (int k = wave; k < 5; k += 4) store16(v.stage + (((size_t)w * v.QR + cnt) * 5 + k) * n + j0, rv[k]);
     }
     // products in T, sums in FP64.  The Metropolis step needs u . c0_e and, per
     // window slot, u . c_m and u_m . c0_e; every wave takes the slots m = wave
@@ -437,7 +437,7 @@ __global__ __launch_bounds__(kBlock) void k_move(CrowdView<T> v, int e, int prev
             for (int i = 0; i < VEC; ++i) { cn[q][i] = (T)0; un[q][i] = (T)0; }
             if (nn < cnt && valid) {
                 load16(v.Cbuf + ((size_t)w * K + nn) * n + j0, cn[q]);
-                load16(v.stage + (((size_t)w * v.Q + nn) * 5 + 0) * n + j0, un[q]);
+                load16(v.stage + (((size_t)w * v.QR + nn) * 5 + 0) * n + j0, un[q]);
             }
         }
 #pragma unroll

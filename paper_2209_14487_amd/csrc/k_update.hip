@@ -52,8 +52,8 @@ __global__ __launch_bounds__(kBlock) void k_flush_vec(CrowdView<T> v, int spin)
         wel[tid] = v.welec[(size_t)w * K + tid];
         grho[tid] = v.wrho[(size_t)w * K + tid];
         const int sl = v.wslot[(size_t)w * K + tid];
-        if (sl < 0 || sl >= v.Q) atomicOr(&v.status[w], 2);
-        wsl[tid] = sl < 0 || sl >= v.Q ? 0 : sl;
+        if (sl < 0 || sl >= v.QR) atomicOr(&v.status[w], 2);
+        wsl[tid] = sl < 0 || sl >= v.QR ? 0 : sl;
     }
 
     // copy the accepted orbital rows of the window into the A, G, L rows
@@ -64,7 +64,7 @@ __global__ __launch_bounds__(kBlock) void k_flush_vec(CrowdView<T> v, int spin)
             if (tid == 0) atomicOr(&v.status[w], 2);
             continue;
         }
-        const T* src = v.stage + ((size_t)w * v.Q + wsl[mm]) * 5 * (size_t)n;
+        const T* src = v.stage + ((size_t)w * v.QR + wsl[mm]) * 5 * (size_t)n;
         T* dst = v.VGL + (((size_t)w * 2 + spin) * n + ea) * 5 * (size_t)n;
         for (int i = tid; i < 5 * n; i += kBlock) dst[i] = src[i];
     }
@@ -88,7 +88,7 @@ __global__ __launch_bounds__(kBlock) void k_flush_vec(CrowdView<T> v, int spin)
     // p[q][m] = M[r] . u_m
     for (int mm = 0; mm < cnt; ++mm) {
         T u[EPL];
-        const T* up = v.stage + (((size_t)w * v.Q + wsl[mm]) * 5 + 0) * n;
+        const T* up = v.stage + (((size_t)w * v.QR + wsl[mm]) * 5 + 0) * n;
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
             const int j = (i * 64 + lane) * VEC;

@@ -85,7 +85,7 @@ __global__ __launch_bounds__(512) void k_window(CrowdView<T> v, int e0, int nmov
     const int rs = v.prm->rec_sweep;
     const double sigma = v.prm->sigma;
     const T* Mspin = v.M + ((size_t)w * 2 + spin) * n * (size_t)n;
-    T* stage = v.stage + (size_t)w * v.Q * 5 * n;
+    T* stage = v.stage + (size_t)w * v.QR * 5 * n;
     T* Cb = v.Cbuf + (size_t)w * K * n;
     const int prop_wave = nw > 1 ? 1 : 0;  // the wave that prepares the next move's stencil
 
