@@ -759,7 +759,7 @@ cq_status cq_crowd_create(const cq_system* const* systems, const int* walkers_pe
         {(void**)&c->sidx, sizeof(size_t) * Wc * c->QR * 64},
         {&c->swt, es * Wc * c->QR * 64 * 5},
         {(void**)&c->pmat, sizeof(double) * Wc * c->Q * c->Q},
-        {(void**)&c->tmat, sizeof(double) * Wc * K * c->Q},
+        {(void**)&c->tmat, sizeof(double) * Wc * K * K},
         {(void**)&c->cur, sizeof(int) * Wc * 3},
         {&c->stage, es * Wc * c->QR * 5 * n},
         {&c->Cbuf, es * Wc * K * n},

@@ -30,7 +30,7 @@
 namespace cq {
 
 constexpr int kMaxDelay = 32;
-constexpr int kMaxCand = 64;   // candidates per round of the batched path
+constexpr int kMaxCand = 88;   // candidates per round of the batched path
 constexpr int kBlock = 256;
 
 // Partial-sum slots of one move workgroup: 4 determinant dots, 5 per window
@@ -89,7 +89,7 @@ struct CrowdView {
     size_t* sidx;        // [W][Q][64] table offsets of its stencil points
     void* swt;           // [W][Q][64][5] T: their value, gradient and Laplacian weights
     double* pmat;        // [W][Q][Q] P of the current round's candidates
-    double* tmat;        // [W][K][Q] T: accepted columns in the basis of the round's c0 columns
+    double* tmat;        // [W][K][K] T: accepted columns in the basis of their own start columns
     int* cur;            // [W][2] next electron to decide, end of the evaluated candidates;
                          // then [W] first candidate of the last round
     const uint32_t* uid;

@@ -334,16 +334,19 @@ __device__ __forceinline__ double pair_change(const CrowdView<T>& v, const doubl
 }
 
 // Decision kernel.  Everything the sequential loop reads sits in LDS (dynamic,
-// about 113 KB at Q = 64): P, the Jastrow pair changes of every candidate pair,
+// about 139 KB at Q = 88): P, the Jastrow pair changes of every candidate pair,
 // T, X[a][i] = u_i . c_a (the accepted columns against every candidate), and
 // L^-1 of the window's triangle (G below the diagonal, rho on it), so that
 //     beta = L^-1 y,  y_a = P[s_a][m]        (a product, not a substitution)
-// and every per-candidate quantity is a lookup or an independent sum.
+// and every per-candidate quantity is a lookup or an independent sum.  T is kept
+// in the basis of the accepted moves' own start columns: c_a = sum_{j<=a}
+// T[a][j] c0_{s_j} (lower triangular, T[a][a] = 1), so an acceptance costs
+// O(accepted), not O(candidates).
 struct DecideLds {
     static constexpr int QM = kMaxCand, D = kMaxDelay;
     double P[QM][QM + 1];
-    double PC[QM][QM + 1];   // PC[m][s]: Jastrow change of candidate m when s (< m) moves
-    double T[D][QM + 1];
+    double PC[QM * (QM - 1) / 2];  // Jastrow change of candidate m when s (< m) moves, at m(m-1)/2 + s
+    double T[D][D + 1];
     double X[D][QM + 1];
     double Li[D][D + 1];
     double u[QM], jd[QM];
@@ -371,7 +374,19 @@ __global__ __launch_bounds__(kBlock) void k_decide(CrowdView<T> v, int spin)
     }
     // candidates: P, uniforms, Jastrow sums, positions
     const double* Pw = v.pmat + (size_t)w * Q * Q;
-    for (int idx = tid; idx < nc * nc; idx += kBlock) S.P[idx / nc][idx % nc] = Pw[(size_t)(idx / nc) * Q + idx % nc];
+    for (int i0 = 0; i0 < nc * nc; i0 += 8 * kBlock) {  // 8 independent loads in flight per thread
+        double x[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int idx = i0 + q * kBlock + tid, ic = idx < nc * nc ? idx : 0;
+            x[q] = Pw[(size_t)(ic / nc) * Q + ic % nc];
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int idx = i0 + q * kBlock + tid;
+            if (idx < nc * nc) S.P[idx / nc][idx % nc] = x[q];
+        }
+    }
     if (tid < nc) {
         const int slot = (dec + tid) % v.QR;
         S.u[tid] = accept_uniform(v.seed, v.uid[w], step, (uint32_t)(e0 + tid));
@@ -386,7 +401,8 @@ __global__ __launch_bounds__(kBlock) void k_decide(CrowdView<T> v, int spin)
     // Jastrow pair changes of all candidate pairs (s < m)
     for (int idx = tid; idx < nc * nc; idx += kBlock) {
         const int m = idx / nc, sx = idx % nc;
-        if (sx < m) S.PC[m][sx] = v.use_j2 ? pair_change(v, S.rnew[m], S.rold[m], S.rnew[sx], S.rold[sx]) : 0.0;
+        if (sx < m)
+            S.PC[m * (m - 1) / 2 + sx] = v.use_j2 ? pair_change(v, S.rnew[m], S.rold[m], S.rnew[sx], S.rold[sx]) : 0.0;
     }
     __syncthreads();
 
@@ -401,7 +417,7 @@ __global__ __launch_bounds__(kBlock) void k_decide(CrowdView<T> v, int spin)
             const int sa = mine ? S.slot[lane] : 0;
             const double y = mine ? S.P[sa][m] : 0.0;
             const double x = mine ? S.X[lane][m] : 0.0;
-            const double pc = mine ? S.PC[m][sa] : 0.0;
+            const double pc = mine ? S.PC[m * (m - 1) / 2 + sa] : 0.0;
             // beta_a = sum_{j<=a} Li[a][j] y_j  (Li is zero above the diagonal)
             const int arow = mine ? lane : 0;
             double beta = 0.0;
@@ -430,18 +446,27 @@ __global__ __launch_bounds__(kBlock) void k_decide(CrowdView<T> v, int spin)
                 for (int t = 0; t < cnt; ++t) li += dpp::lane(x, t) * S.Li[t][lcol];
                 if (mine) S.Li[cnt][lane] = -li * rinv;
                 if (lane == cnt) S.Li[cnt][cnt] = rinv;
-                // new row of T: T[cnt][i] = delta(i, m) - sum_a beta_a T[a][i]   (lane i)
-                double tc = lane == m ? 1.0 : 0.0;
+                // new row of T (accepted basis): T[cnt][j] = -sum_{a>=j} beta_a T[a][j] for
+                // j < cnt, T[cnt][cnt] = 1   (lane j; T is zero above the diagonal)
+                {
+                    const int jc = lane < kMaxDelay ? lane : 0;
+                    double tc = 0.0;
 #pragma unroll 8
-                for (int aa = 0; aa < cnt; ++aa) tc -= dpp::lane(beta, aa) * S.T[aa][lane];
-                S.T[cnt][lane] = lane < nc ? tc : 0.0;
-                // new row of X: X[cnt][i] = sum_{q<=m} T[cnt][q] P[i][q]   (lane i)
-                double xc = 0.0;
+                    for (int aa = 0; aa < cnt; ++aa) tc -= dpp::lane(beta, aa) * S.T[aa][jc];
+                    if (mine) S.T[cnt][lane] = tc;
+                    if (lane == cnt) S.T[cnt][cnt] = 1.0;
+                    if (lane > cnt && lane < kMaxDelay) S.T[cnt][lane] = 0.0;
+                    if (lane == 0) S.slot[cnt] = m;
+                }
+                // new row of X for the later candidates: X[cnt][i] = sum_{j<=cnt} T[cnt][j] P[i][s_j]
+                for (int base = 0; base < DecideLds::QM; base += 64) {
+                    const int i = base + lane, ic = i < DecideLds::QM ? i : DecideLds::QM - 1;
+                    double xc = 0.0;
 #pragma unroll 8
-                for (int q = 0; q <= m; ++q) xc += S.T[cnt][q] * S.P[lane][q];
-                S.X[cnt][lane] = xc;
+                    for (int j = 0; j <= cnt; ++j) xc += S.T[cnt][j] * S.P[ic][S.slot[j]];
+                    if (i < DecideLds::QM) S.X[cnt][i] = xc;
+                }
                 if (lane == 0) {
-                    S.slot[cnt] = m;
                     v.wrho[(size_t)w * K + cnt] = rho;
                 }
                 ld += log(fabs(rho));
@@ -468,9 +493,9 @@ __global__ __launch_bounds__(kBlock) void k_decide(CrowdView<T> v, int spin)
         v.wslot[(size_t)w * K + tid] = a % v.QR;
         for (int k = 0; k < 3; ++k) v.R[((size_t)w * v.ne + spin * n + a) * 3 + k] = S.rnew[S.slot[tid]][k];
     }
-    for (int idx = tid; idx < cnt * nc; idx += kBlock) {
-        const int i = idx / nc, j = idx % nc;
-        v.tmat[((size_t)w * K + i) * Q + j] = S.T[i][j];
+    for (int idx = tid; idx < cnt * cnt; idx += kBlock) {
+        const int i = idx / cnt, j = idx % cnt;
+        v.tmat[((size_t)w * K + i) * K + j] = S.T[i][j];
     }
     for (int idx = tid; idx < cnt * cnt; idx += kBlock) {
         const int i = idx / cnt, j = idx % cnt;
@@ -485,45 +510,49 @@ __global__ __launch_bounds__(kBlock) void k_decide(CrowdView<T> v, int spin)
     // Jastrow sums of the candidates left for later rounds: add this round's moves
     if (v.use_j2 && tid >= ndec && tid < nc) {
         double d = 0.0;
-        for (int j = 0; j < cnt; ++j) d += S.PC[tid][S.slot[j]];
+        for (int j = 0; j < cnt; ++j) d += S.PC[tid * (tid - 1) / 2 + S.slot[j]];
         v.jd[(size_t)w * v.QR + (dec + tid) % v.QR] = S.jd[tid] + d;
     }
 }
 
-// Columns of the accepted moves: c_a = sum_i T[a][i] c0_i for a < cnt (FP64 sums
-// of exact products, rounded to T).  One thread per orbital; the loads of 8
-// candidate columns are issued together.
+// Columns of the accepted moves: c_a = sum_{j<=a} T[a][j] c0_{s_j} for a < cnt,
+// c0_{s_j} the start column of the j-th accepted move's electron (FP64 sums of
+// exact products, rounded to T).  One thread per orbital; the loads of 8
+// columns are issued together.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_cols(CrowdView<T> v, int spin)
 {
-    constexpr int D = kMaxDelay, QM = kMaxCand;
-    __shared__ double s_T[D][QM + 8];
-    const int n = v.n, K = v.K, Q = v.Q;
+    constexpr int D = kMaxDelay;
+    __shared__ double s_T[D][D + 1];
+    __shared__ int s_row[D];
+    const int n = v.n, K = v.K;
     const int nlb = (n + kBlock - 1) / kBlock;
     const int w = blockIdx.x / nlb, l = (blockIdx.x % nlb) * kBlock + threadIdx.x;
     const int cnt = v.cnt[(size_t)2 * v.W + w];
     if (cnt <= 0 || cnt > K) return;
-    const int dec = v.cur[2 * v.W + w];
-    const int nc = (dec + Q < n ? dec + Q : n) - dec;
-    // T padded with zeros (rows a >= cnt, columns i >= nc): no branches in the sums
-    for (int idx = threadIdx.x; idx < D * QM; idx += kBlock) {
-        const int a = idx / QM, i = idx % QM;
-        s_T[a][i] = (a < cnt && i < nc) ? v.tmat[((size_t)w * K + a) * Q + i] : 0.0;
+    // T padded with zeros (rows and columns >= cnt): no branches in the sums
+    for (int idx = threadIdx.x; idx < D * D; idx += kBlock) {
+        const int a = idx / D, j = idx % D;
+        s_T[a][j] = (a < cnt && j < cnt) ? v.tmat[((size_t)w * K + a) * K + j] : 0.0;
+    }
+    if (threadIdx.x < D) {
+        const int e = threadIdx.x < cnt ? v.welec[(size_t)w * K + threadIdx.x] : 0;
+        s_row[threadIdx.x] = e >= 0 && e < n ? e : 0;
     }
     __syncthreads();
     if (l >= n) return;
-    const T* Mw = v.M + (((size_t)w * 2 + spin) * n + dec) * (size_t)n + l;
+    const T* Mw = v.M + ((size_t)w * 2 + spin) * n * (size_t)n + l;
     double acc[D];
 #pragma unroll
     for (int a = 0; a < D; ++a) acc[a] = 0.0;
-    for (int i0 = 0; i0 < nc; i0 += 8) {
+    for (int j0 = 0; j0 < cnt; j0 += 8) {
         double c[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) c[q] = (double)Mw[(size_t)(i0 + q < nc ? i0 + q : 0) * n];
+        for (int q = 0; q < 8; ++q) c[q] = (double)Mw[(size_t)s_row[(j0 + q) & (D - 1)] * n];
 #pragma unroll
         for (int q = 0; q < 8; ++q)
 #pragma unroll
-            for (int a = 0; a < D; ++a) acc[a] = fma(s_T[a][i0 + q], c[q], acc[a]);
+            for (int a = 0; a < D; ++a) acc[a] = fma(s_T[a][(j0 + q) & (D - 1)], c[q], acc[a]);
     }
     if constexpr (sizeof(T) == 4) {
         if (v.ct) {  // transposed for the matrix-core update: 32 per row, zeros past cnt
@@ -552,10 +581,13 @@ __global__ void k_cursor_reset(int* cur, int W)
 
 int batch_rounds(int n, int K) { return (n + K - 1) / K; }
 
+// Candidates per round: about k / acceptance for acceptance near 0.35, so that
+// a round usually closes on k accepted moves rather than on running out.
 int batch_candidates(int n, int K)
 {
-    int q = 2 * K + 8;
+    int q = 3 * K;
     if (q > kMaxCand) q = kMaxCand;
+    if (q < 2) q = 2;
     return q < n ? q : n;
 }
 
