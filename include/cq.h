@@ -56,13 +56,14 @@ typedef enum { CQ_FP64 = 0, CQ_MIXED = 1 } cq_precision;
 typedef enum {
     CQ_KERNEL_VGL = 0,      /* B-spline VGL at the proposals: per move fused with the ratio, Jastrow
                                and the previous decision (MULTI), per window with all its moves
-                               (WINDOW), or per window for all its proposals at once (BATCH) */
+                               (WINDOW), or for the electrons of a round's gather range (BATCH) */
     CQ_KERNEL_RESOLVE = 1,  /* decisions: of a window's last move (MULTI), of a round's moves with
                                the products they need (BATCH) */
     CQ_KERNEL_UPDATE = 2,   /* Sherman-Morrison / delayed rank-k inverse update */
     CQ_KERNEL_ENERGY = 3,   /* local energy */
     CQ_KERNEL_INVERSE = 4,  /* FP64 Gauss-Jordan inversion (initial and periodic recompute) */
-    CQ_KERNEL_PROPOSE = 5,  /* proposals and stencils of a round's new candidates (BATCH) */
+    CQ_KERNEL_PROPOSE = 5,  /* proposals and stencils of a round's gather range, and the Jastrow
+                               sums of its new candidates (BATCH) */
     CQ_KERNEL_COUNT = 6
 } cq_kernel_kind;
 
@@ -174,8 +175,9 @@ cq_status cq_crowd_get_positions(cq_crowd* c, double* R, int* n_walkers_per_syst
 cq_status cq_crowd_get_inverse(cq_crowd* c, double* ainv);
 
 /* Parity mode: the crowd follows the given decisions flags[sweep][e][w]
-   (1 accept, 0 reject) for the next n_sweeps sweeps instead of its own, while
-   still recording its own probability.  flags = NULL switches it off. */
+   (1 accept, 0 reject, 2 or more: the walker's own Metropolis decision) for
+   the next n_sweeps sweeps instead of its own, while still recording its own
+   probability.  flags = NULL switches it off. */
 cq_status cq_crowd_set_forced_decisions(cq_crowd* c, const uint8_t* flags, int n_sweeps);
 /* Record per-move rho_D, dlnJ, P and the decision for the next n_sweeps sweeps
    (0 switches recording off). */

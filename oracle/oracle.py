@@ -185,6 +185,33 @@ def lu_inverse(A):
     return inv, ld.value, sg.value
 
 
+def row_ratio_refined(A, i, phi):
+    """det A' / det A where A' is A with row i replaced by phi, by its definition phi . A^-1 e_i
+    (the determinant part of the ratio step of Alg. 1).  A^-1 e_i comes from an LU solve refined
+    twice with residuals b - A x formed in extended precision (numpy longdouble), and the final dot
+    is taken in extended precision, so the value is good to a few ulp times (1 + eps cond(A)):
+    an arbiter for a long FP64 update chain, whose error grows with each rank-1 or rank-k step."""
+    A = np.asarray(A, dtype=np.float64)
+    n = A.shape[0]
+    b = np.zeros(n)
+    b[i] = 1.0
+    Al = A.astype(np.longdouble)
+    x = np.linalg.solve(A, b)
+    for _ in range(2):
+        r = (b.astype(np.longdouble) - Al @ x.astype(np.longdouble)).astype(np.float64)
+        x = x + np.linalg.solve(A, r)
+    return float(np.asarray(phi, dtype=np.float64).astype(np.longdouble) @ x.astype(np.longdouble))
+
+
+def det_ratio_refined(sys: System, R, e, rnew):
+    """Slater-determinant ratio det A(R') / det A(R) for moving electron e to rnew, with A rebuilt
+    from the orbitals at R (no update chain) and the ratio from ``row_ratio_refined``."""
+    R = np.asarray(R, dtype=np.float64)
+    lo, n = (0, sys.n_up) if e < sys.n_up else (sys.n_up, sys.n_dn)
+    A = np.array([orbital_vgl(sys, R[lo + i], n)[0] for i in range(n)])
+    return row_ratio_refined(A, e - lo, orbital_vgl(sys, rnew, n)[0])
+
+
 def local_energy(sys: System, R, Ainv_up, Ainv_dn, G_up, G_dn, L_up, L_dn):
     """Kinetic local energy from inverses, gradient rows ([n][n][3]) and Laplacian rows."""
     arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (R, Ainv_up, Ainv_dn, G_up, G_dn, L_up, L_dn)]

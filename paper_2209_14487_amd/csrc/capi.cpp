@@ -60,10 +60,11 @@ struct cq_crowd {
     uint32_t first_uid = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
-    // second stream of the batched path: the next round's proposals and gather run on it
-    // while the current round's update runs on `stream`; fork / join events per round
+    // second stream of the batched path: the gather for round r+1 runs on it while round r
+    // is decided and applied on `stream`, then round r+1's Jastrow sums beside round r's
+    // update.  Events per round: P formed (ev_fork), decided (ev_dec), gathered (ev_gat).
     hipStream_t stream2 = nullptr;
-    std::vector<hipEvent_t> fork_ev, join_ev;
+    std::vector<hipEvent_t> ev_fork, ev_dec, ev_gat;
     std::vector<void*> allocs;
     // device state
     double* R = nullptr;
@@ -116,6 +117,7 @@ struct cq_crowd {
     double* pmat = nullptr;
     double* tmat = nullptr;
     int* cur = nullptr;
+    int* look = nullptr;
     uint32_t* uid = nullptr;
     cq::Params* prm = nullptr;
     int* status = nullptr;
@@ -186,6 +188,7 @@ cq::CrowdView<T> view(const cq_crowd* c)
     v.pmat = c->pmat;
     v.tmat = c->tmat;
     v.cur = c->cur;
+    v.look = c->look;
     v.uid = c->uid;
     v.seed = c->seed;
     v.use_j2 = c->sys->use_j2;
@@ -242,43 +245,60 @@ void enqueue_sweep(cq_crowd* c)
     const cq::CrowdView<T> v = view<T>(c);
     const int n = c->n, K = c->K;
     if (c->path == CQ_PATH_BATCH) {
-        // Rounds of both spin blocks in order.  Round r+1's proposals and gather run on
-        // stream2 while round r's update runs on stream (they touch disjoint data: the
-        // gather reads positions and cursors that round r's decisions already wrote, the
-        // update reads and writes the inverse); the next decisions wait for both.
+        // Rounds of both spin blocks in order.  On stream: P(r), decide(r), update(r), ...
+        // On stream2: gather(r+1) once P(r) is formed (so that the decision workgroups of
+        // round r are placed before the gather fills the GPU), then jd(r+1) once decide(r)
+        // is done; P(r+1) waits for both and follows update(r).  gather(r+1) writes only the
+        // ring slots of electrons that round r-1 decided, whose rows update(r-1) has read;
+        // jd(r+1) reads the positions decide(r) wrote and runs beside update(r).
         const int rounds = cq::batch_rounds(n, K), total = 2 * rounds;
         auto gather = [&](int q, hipStream_t st) {
             const int spin = q / rounds, r = q % rounds;
             timed_begin(c, CQ_KERNEL_PROPOSE, st);
-            cq::launch_batch_stencils<T>(v, spin, r == 0, st);
+            cq::launch_batch_stencils<T>(v, spin, r & 1, r == 0, st);
             timed_end(c, CQ_KERNEL_PROPOSE, st);
             timed_begin(c, CQ_KERNEL_VGL, st);
-            cq::launch_batch_vgl<T>(v, spin, st);
+            cq::launch_batch_vgl<T>(v, spin, r & 1, st);
             timed_end(c, CQ_KERNEL_VGL, st);
         };
-        const bool overlap = c->stream2 != nullptr && (int)c->fork_ev.size() >= total;
-        gather(0, c->stream);
-        for (int q = 0; q < total; ++q) {
-            const int spin = q / rounds;
-            timed_begin(c, CQ_KERNEL_RESOLVE);
-            cq::launch_batch_decide<T>(v, spin, c->stream);
-            timed_end(c, CQ_KERNEL_RESOLVE);
-            // no overlap into a new spin block: its candidates' ring slots are not disjoint from
-            // the slots of the rows the last update of the previous block still reads
-            const bool fork = overlap && q + 1 < total && (q + 1) % rounds != 0;
-            if (fork) {
-                (void)hipEventRecord(c->fork_ev[q], c->stream);
-                (void)hipStreamWaitEvent(c->stream2, c->fork_ev[q], 0);
-                gather(q + 1, c->stream2);
-                (void)hipEventRecord(c->join_ev[q], c->stream2);
+        auto jastrow = [&](int q, hipStream_t st) {
+            timed_begin(c, CQ_KERNEL_PROPOSE, st);
+            cq::launch_batch_jd<T>(v, q / rounds, st);
+            timed_end(c, CQ_KERNEL_PROPOSE, st);
+        };
+        const bool overlap = c->stream2 != nullptr && (int)c->ev_gat.size() >= total;
+        hipStream_t s1 = c->stream, s2 = c->stream2;
+        for (int spin = 0; spin < 2; ++spin) {
+            const int q0 = spin * rounds;
+            gather(q0, s1);
+            jastrow(q0, s1);
+            for (int r = 0; r < rounds; ++r) {
+                const int q = q0 + r;
+                const bool next = r + 1 < rounds;
+                if (overlap && r > 0) (void)hipStreamWaitEvent(s1, c->ev_gat[q], 0);
+                timed_begin(c, CQ_KERNEL_RESOLVE);
+                cq::launch_batch_pmat<T>(v, spin, s1);
+                if (overlap && next) {
+                    (void)hipEventRecord(c->ev_fork[q], s1);
+                    (void)hipStreamWaitEvent(s2, c->ev_fork[q], 0);
+                    gather(q + 1, s2);
+                }
+                cq::launch_batch_decide<T>(v, spin, r & 1, s1);
+                timed_end(c, CQ_KERNEL_RESOLVE);
+                if (overlap && next) {
+                    (void)hipEventRecord(c->ev_dec[q], s1);
+                    (void)hipStreamWaitEvent(s2, c->ev_dec[q], 0);
+                    jastrow(q + 1, s2);
+                    (void)hipEventRecord(c->ev_gat[q + 1], s2);
+                }
+                timed_begin(c, CQ_KERNEL_UPDATE);
+                cq::launch_flush<T>(v, spin, s1, true);
+                timed_end(c, CQ_KERNEL_UPDATE);
+                if (!overlap && next) {
+                    gather(q + 1, s1);
+                    jastrow(q + 1, s1);
+                }
             }
-            timed_begin(c, CQ_KERNEL_UPDATE);
-            cq::launch_flush<T>(v, spin, c->stream, true);
-            timed_end(c, CQ_KERNEL_UPDATE);
-            if (fork)
-                (void)hipStreamWaitEvent(c->stream, c->join_ev[q], 0);
-            else if (q + 1 < total)
-                gather(q + 1, c->stream);  // after the update, in stream order
         }
         timed_begin(c, CQ_KERNEL_ENERGY);
         cq::launch_energy<T>(v, c->stream);
@@ -411,6 +431,7 @@ cq_status setup_state(cq_crowd* c)
     const size_t es = c->prec == CQ_FP64 ? 8 : 4;
     HIP_TRY(hipMemsetAsync(c->stage, 0, es * c->Wcap * c->QR * 5 * c->n, c->stream));
     HIP_TRY(hipMemsetAsync(c->cur, 0, sizeof(int) * 3 * c->Wcap, c->stream));
+    HIP_TRY(hipMemsetAsync(c->look, 0, sizeof(int) * 4 * c->Wcap, c->stream));
     HIP_TRY(hipMemsetAsync(c->Cbuf, 0, es * c->Wcap * c->K * c->n, c->stream));
     HIP_TRY(hipMemsetAsync(c->status, 0, sizeof(int) * c->Wcap, c->stream));
     cq::launch_setup_vgl<T>(v, c->stream);
@@ -658,8 +679,8 @@ void cq_crowd_destroy(cq_crowd* c)
     if (c->rec_prob) (void)hipFree(c->rec_prob);
     if (c->rec_acc) (void)hipFree(c->rec_acc);
     if (c->forced) (void)hipFree(c->forced);
-    for (hipEvent_t e : c->fork_ev) (void)hipEventDestroy(e);
-    for (hipEvent_t e : c->join_ev) (void)hipEventDestroy(e);
+    for (auto* evs : {&c->ev_fork, &c->ev_dec, &c->ev_gat})
+        for (hipEvent_t e : *evs) (void)hipEventDestroy(e);
     if (c->stream2) (void)hipStreamDestroy(c->stream2);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
@@ -716,17 +737,15 @@ cq_status cq_crowd_create(const cq_system* const* systems, const int* walkers_pe
     if (c->path == CQ_PATH_BATCH) {
         // default priority, like the crowd's own stream
         if (hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking) == hipSuccess) {
-            const int total = 2 * cq::batch_rounds(c->n, 1);  // enough for any delay rank
-            for (int i = 0; i < total; ++i) {
-                hipEvent_t f, j;
-                if (hipEventCreateWithFlags(&f, hipEventDisableTiming) != hipSuccess) break;
-                if (hipEventCreateWithFlags(&j, hipEventDisableTiming) != hipSuccess) {
-                    (void)hipEventDestroy(f);
-                    break;
+            const int total = 2 * cq::batch_rounds(c->n, 1) + 2;  // enough for any delay rank
+            bool ok = true;
+            for (auto* evs : {&c->ev_fork, &c->ev_dec, &c->ev_gat})
+                for (int i = 0; ok && i < total; ++i) {
+                    hipEvent_t e;
+                    ok = hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+                    if (ok) evs->push_back(e);
                 }
-                c->fork_ev.push_back(f);
-                c->join_ev.push_back(j);
-            }
+            if (!ok) (void)hipGetLastError();
         } else {
             (void)hipGetLastError();
             c->stream2 = nullptr;
@@ -761,6 +780,7 @@ cq_status cq_crowd_create(const cq_system* const* systems, const int* walkers_pe
         {(void**)&c->pmat, sizeof(double) * Wc * c->Q * c->Q},
         {(void**)&c->tmat, sizeof(double) * Wc * K * K},
         {(void**)&c->cur, sizeof(int) * Wc * 3},
+        {(void**)&c->look, sizeof(int) * Wc * 4},
         {&c->stage, es * Wc * c->QR * 5 * n},
         {&c->Cbuf, es * Wc * K * n},
         {(void**)&c->ct, sizeof(float) * Wc * n * cq::kMaxDelay},

@@ -92,6 +92,7 @@ struct CrowdView {
     double* tmat;        // [W][K][K] T: accepted columns in the basis of their own start columns
     int* cur;            // [W][2] next electron to decide, end of the evaluated candidates;
                          // then [W] first candidate of the last round
+    int* look;           // [2][W][2] gather range of the rounds of each parity
     const uint32_t* uid;
     uint64_t seed;
     int use_j2;
@@ -159,9 +160,12 @@ template <typename T> void launch_move(const CrowdView<T>& v, int e, int prev, i
 template <typename T> void launch_first_proposal(const CrowdView<T>& v, hipStream_t s);
 template <typename T> void launch_window(const CrowdView<T>& v, int e0, int nmoves, hipStream_t s);
 int window_threads(int n, int elem_bytes);
-template <typename T> void launch_batch_stencils(const CrowdView<T>& v, int spin, bool block_start, hipStream_t s);
-template <typename T> void launch_batch_vgl(const CrowdView<T>& v, int spin, hipStream_t s);
-template <typename T> void launch_batch_decide(const CrowdView<T>& v, int spin, hipStream_t s);
+template <typename T>
+void launch_batch_stencils(const CrowdView<T>& v, int spin, int par, bool block_start, hipStream_t s);
+template <typename T> void launch_batch_vgl(const CrowdView<T>& v, int spin, int par, hipStream_t s);
+template <typename T> void launch_batch_jd(const CrowdView<T>& v, int spin, hipStream_t s);
+template <typename T> void launch_batch_pmat(const CrowdView<T>& v, int spin, hipStream_t s);
+template <typename T> void launch_batch_decide(const CrowdView<T>& v, int spin, int par, hipStream_t s);
 int batch_rounds(int n, int K);      // rounds per spin block (enough when every move is accepted)
 int batch_candidates(int n, int K);  // candidates per round, Q
 // linv_ready: the window's L^-1 is already in wlinv (the batched path forms it)

@@ -10,8 +10,8 @@
 // small matrices only.
 //
 // Per walker and spin block, electrons are taken in order.  A round looks at the
-// next Q candidates [dec, dec + Q) (evaluated ones are kept in a ring of Q stage
-// slots, slot = electron mod Q) and decides them in order until k moves have been
+// next Q candidates [dec, dec + Q) (evaluated ones are kept in a ring of 2Q stage
+// slots, slot = electron mod 2Q) and decides them in order until k moves have been
 // accepted or the candidates run out; the k (or fewer) accepted moves are then
 // applied to the inverse in one rank-k update (delayed update).  With
 //     P[i][j] = u_i . c0_j      (u_i: value row of candidate i, c0_j: inverse
@@ -27,8 +27,18 @@
 // The Jastrow difference of a candidate is summed over all electrons when it is
 // evaluated; every later accepted move adds the change of its pair term.
 //
-// k_stencils    proposals and stencils of the new candidates
-// k_prop_vgl    gather + VGL of the new candidates, their Jastrow sums
+// The orbital rows of an electron depend on nothing but its own proposal, so
+// the gather runs one round ahead: while round r is decided and applied, the
+// gather fills the ring up to 2Q electrons past round r's first candidate
+// (the furthest round r+1 can reach), on a second stream.  Its range is fixed
+// by the cursors of round r-1, and it writes only ring slots of electrons that
+// round r-1 decided, so it shares no data with round r.  The Jastrow sums need
+// the positions after round r and are formed separately once round r is
+// decided, next to round r's inverse update.
+//
+// k_stencils    proposals and stencils of the electrons in the gather range
+// k_prop_vgl    gather + VGL of the same electrons
+// k_jd          Jastrow sums of a round's new candidates
 // k_pmat        P of every walker's candidates (FP64 sums of exact products)
 // k_decide      one workgroup per walker: the decisions, the window for the
 //               update kernel (accepted rows by slot, rho, G, and T with
@@ -101,26 +111,26 @@ inline int batch_threads(int n, int elem_bytes)
     return t > kBlock ? kBlock : t;
 }
 
-// Candidate t of walker w in the current round: electron a = ev + t (within the
-// spin), evaluated when a < min(dec + Q, n).
-__device__ __forceinline__ bool new_candidate(const int* cur, int w, int t, int Q, int n, int& a)
+// Electron t of walker w's gather range [look[par][w][0], look[par][w][1])
+// (within the spin block); par is the parity of the round the range is for.
+__device__ __forceinline__ bool gather_electron(const int* look, int par, int W, int w, int t, int& a)
 {
-    const int dec = cur[2 * w], ev = cur[2 * w + 1];
-    const int end = dec + Q < n ? dec + Q : n;
-    a = ev + t;
-    return a < end;
+    const int* L = look + ((size_t)par * W + w) * 2;
+    a = L[0] + t;
+    return a < L[1];
 }
 
-// Proposals and stencils of the round's new candidates, one wave per candidate
-// (lane = stencil entry), so that the gather workgroups start loading at once.
+// Proposals and stencils of the electrons in the gather range, one wave per
+// electron (lane = stencil entry), so that the gather workgroups start loading at
+// once.  A range never holds more than Q electrons.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_stencils(CrowdView<T> v, int spin)
+__global__ __launch_bounds__(kBlock) void k_stencils(CrowdView<T> v, int spin, int par)
 {
     const int n = v.n, Q = v.Q, QR = v.QR;
     const int pi = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (pi >= v.W * Q) return;
     int a = 0;
-    if (!new_candidate(v.cur, pi / Q, pi % Q, Q, n, a)) return;
+    if (!gather_electron(v.look, par, v.W, pi / Q, pi % Q, a)) return;
     const int w = pi / Q, e = spin * n + a, slot = a % QR;
     const size_t ps = (size_t)w * QR + slot;
     double z[3], rp[3];
@@ -131,135 +141,160 @@ __global__ __launch_bounds__(kBlock) void k_stencils(CrowdView<T> v, int spin)
     if (lane < 3) v.rprop[ps * 3 + lane] = rp[lane];
 }
 
-// Gather + value/gradient/Laplacian of the round's new candidates.  Each thread
-// owns one 16-byte group of orbitals and runs the 64 stencil points as 4 planes
-// of 16 loads; between issuing a plane's loads and using them it works through
-// its share of the candidate's Jastrow pair sums, which then costs no time of
-// its own.
+// Gather + value/gradient/Laplacian of the electrons in the gather range.  Each
+// thread owns one 16-byte group of orbitals and runs the 64 stencil points as 4
+// planes of 16 loads.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_prop_vgl(CrowdView<T> v, int spin, int pp)
+__global__ __launch_bounds__(kBlock) void k_prop_vgl(CrowdView<T> v, int spin, int pp, int par)
 {
     constexpr int VEC = 16 / sizeof(T);
     __shared__ size_t s_idx[4][64];
     __shared__ T s_w[4][64 * 5];
-    __shared__ double s_rp[4][3];
-    __shared__ double s_part[kBlock];
     __shared__ int s_ok[4];
     const int n = v.n, Q = v.Q, QR = v.QR, groups = n / VEC;
     const int nprop = v.W * Q;
-    const int nt = blockDim.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nt = blockDim.x, tid = threadIdx.x;
     const int first = blockIdx.x * pp;
 
     // stencils of this workgroup's proposals into LDS
     if (tid < pp) {
         const int pi = first + tid;
         int a = 0;
-        s_ok[tid] = pi < nprop && new_candidate(v.cur, pi / Q, pi % Q, Q, n, a);
+        s_ok[tid] = pi < nprop && gather_electron(v.look, par, v.W, pi / Q, pi % Q, a);
     }
     __syncthreads();
     for (int idx = tid; idx < pp * 64; idx += nt) {
         const int p = idx >> 6, l = idx & 63, pi = first + p;
         if (!s_ok[p]) continue;
         int a = 0;
-        new_candidate(v.cur, pi / Q, pi % Q, Q, n, a);
+        gather_electron(v.look, par, v.W, pi / Q, pi % Q, a);
         const size_t ps = (size_t)(pi / Q) * QR + a % QR;
         s_idx[p][l] = v.sidx[ps * 64 + l];
         const T* sw = (const T*)v.swt + (ps * 64 + l) * 5;
 #pragma unroll
         for (int k = 0; k < 5; ++k) s_w[p][l * 5 + k] = sw[k];
-        if (l < 3) s_rp[p][l] = v.rprop[ps * 3 + l];
     }
     __syncthreads();
 
     const int tpp = pp == 1 ? nt : groups;  // threads per proposal
     const int p = tid / tpp, t0 = tid % tpp;
     const int pi = first + p;
-    const bool live = p < pp && pi < nprop && s_ok[p];
+    if (!(p < pp && pi < nprop && s_ok[p])) return;
     int a = 0;
-    if (live) new_candidate(v.cur, pi / Q, pi % Q, Q, n, a);
-    const int w = live ? pi / Q : 0, e = spin * n + a, slot = a % QR;
-    const bool j2 = v.use_j2 && live;
-    const double* Rw = v.R + (size_t)w * v.ne * 3;
-    double re[3], rpp[3];
+    gather_electron(v.look, par, v.W, pi / Q, pi % Q, a);
+    const int w = pi / Q, slot = a % QR;
+    T* dst = v.stage + ((size_t)w * QR + slot) * 5 * (size_t)n;
+    const size_t* sidx = s_idx[p];
+    const T* sw = s_w[p];
+    for (int g = t0; g < groups; g += tpp) {
+        const int j0 = g * VEC;
+        T acc[5][VEC];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        re[k] = j2 ? Rw[(size_t)e * 3 + k] : 0.0;
-        rpp[k] = j2 ? s_rp[p][k] : 0.0;
-    }
-    // this thread's Jastrow pairs: electrons i = t0, t0 + tpp, ... (skipping e)
-    const int jn = j2 ? (v.ne - t0 + tpp - 1) / tpp : 0;
-    int jnext = 0;
-    double dj = 0.0;
-    auto j2_pairs = [&](int count) {
-        for (int c = 0; c < count && jnext < jn; ++c, ++jnext) {
-            const int i = t0 + jnext * tpp;
-            if (i == e) continue;
-            const double aa = ((i >= v.n) == (spin != 0)) ? v.a_par : v.a_anti;
-            const double* ri = Rw + (size_t)i * 3;
-            dj += pair_j2(v, aa, rpp, ri) - pair_j2(v, aa, re, ri);
-        }
-    };
-    const int gsteps = live ? 4 * ((groups - t0 + tpp - 1) / tpp) : 0;  // plane iterations
-    const int jper = gsteps ? (jn + gsteps - 1) / gsteps : 0;
-    if (live) {
-        T* dst = v.stage + ((size_t)w * QR + slot) * 5 * (size_t)n;
-        const size_t* sidx = s_idx[p];
-        const T* sw = s_w[p];
-        for (int g = t0; g < groups; g += tpp) {
-            const int j0 = g * VEC;
-            T acc[5][VEC];
+        for (int k = 0; k < 5; ++k)
 #pragma unroll
-            for (int k = 0; k < 5; ++k)
-#pragma unroll
-                for (int i = 0; i < VEC; ++i) acc[k][i] = (T)0;
+            for (int i = 0; i < VEC; ++i) acc[k][i] = (T)0;
 #pragma unroll 1
-            for (int x = 0; x < 4; ++x) {
-                T vals[16][VEC];
+        for (int x = 0; x < 4; ++x) {
+            T vals[16][VEC];
 #pragma unroll
-                for (int q = 0; q < 16; ++q) load16(v.table + sidx[x * 16 + q] + j0, vals[q]);
-                j2_pairs(jper);  // overlaps the loads in flight
+            for (int q = 0; q < 16; ++q) load16(v.table + sidx[x * 16 + q] + j0, vals[q]);
 #pragma unroll
-                for (int q = 0; q < 16; ++q) {
-                    const T* wq = sw + (x * 16 + q) * 5;
-                    const T wv = wq[0], wgx = wq[1], wgy = wq[2], wgz = wq[3], wl = wq[4];
+            for (int q = 0; q < 16; ++q) {
+                const T* wq = sw + (x * 16 + q) * 5;
+                const T wv = wq[0], wgx = wq[1], wgy = wq[2], wgz = wq[3], wl = wq[4];
 #pragma unroll
-                    for (int i = 0; i < VEC; ++i) {
-                        acc[0][i] += wv * vals[q][i];
-                        acc[1][i] += wgx * vals[q][i];
-                        acc[2][i] += wgy * vals[q][i];
-                        acc[3][i] += wgz * vals[q][i];
-                        acc[4][i] += wl * vals[q][i];
-                    }
+                for (int i = 0; i < VEC; ++i) {
+                    acc[0][i] += wv * vals[q][i];
+                    acc[1][i] += wgx * vals[q][i];
+                    acc[2][i] += wgy * vals[q][i];
+                    acc[3][i] += wgz * vals[q][i];
+                    acc[4][i] += wl * vals[q][i];
                 }
             }
-#pragma unroll
-            for (int k = 0; k < 5; ++k) store16(dst + (size_t)k * n + j0, acc[k]);
         }
+#pragma unroll
+        for (int k = 0; k < 5; ++k) store16(dst + (size_t)k * n + j0, acc[k]);
     }
-    j2_pairs(jn);  // whatever is left (threads without a group of their own)
+}
 
-    // Jastrow difference of each proposal against the current positions
+// Jastrow sums of a round's new candidates [ev, min(dec + Q, n)) against the
+// positions after the previous round:
+//     dlnJ_e = sum_{i != e} u(|r'_e - r_i|) - u(|r_e - r_i|).
+// The coordinate differences are taken in FP64 and each pair term in the
+// precision of the path (FP32 terms in mixed precision, like the ratios); the
+// sums are FP64.  One workgroup per walker and group of kJdCand candidates;
+// thread t takes the electrons i = t, t + kBlock, ...; the partial sums are
+// added in a fixed order.
+constexpr int kJdCand = 8;
+
+template <typename T>
+__device__ __forceinline__ T jd_term(T a, T b, T L, T iL, const double* x, const double* y)
+{
+    T r2 = (T)0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        T d = (T)(x[c] - y[c]);
+        if constexpr (sizeof(T) == 8)
+            d -= L * rint(d / L);
+        else
+            d -= L * rintf(d * iL);
+        r2 += d * d;
+    }
+    const T r = sqrt(r2);
+    return a * r / ((T)1 + b * r);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_jd(CrowdView<T> v, int spin)
+{
+    __shared__ double s_rp[kJdCand][3], s_re[kJdCand][3];
+    __shared__ double s_part[kJdCand][kBlock / 64];
+    const int n = v.n, Q = v.Q, QR = v.QR, ne = v.ne;
+    const int per = (Q + kJdCand - 1) / kJdCand;
+    const int w = blockIdx.x / per, c0 = (blockIdx.x % per) * kJdCand;
+    const int dec = v.cur[2 * w], ev = v.cur[2 * w + 1];
+    const int end = dec + Q < n ? dec + Q : n;
+    const int a0 = ev + c0;
+    if (a0 >= end) return;
+    const int nc = end - a0 < kJdCand ? end - a0 : kJdCand;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const double* Rw = v.R + (size_t)w * ne * 3;
     if (!v.use_j2) {
-        if (live && t0 == 0) v.jd[(size_t)w * QR + slot] = 0.0;
+        if (tid < nc) v.jd[(size_t)w * QR + (a0 + tid) % QR] = 0.0;
         return;
     }
-    if (tpp % 64 == 0) {
-        dj = wave_sum(dj);
-        if (lane == 0) s_part[wave] = dj;
-        __syncthreads();
-        if (live && t0 == 0) {
-            double sum = 0.0;
-            for (int q = 0; q < tpp / 64; ++q) sum += s_part[p * (tpp / 64) + q];
-            v.jd[(size_t)w * QR + slot] = sum;
+    if (tid < kJdCand * 3) {
+        const int c = tid / 3, k = tid % 3;
+        const int a = a0 + (c < nc ? c : 0);
+        s_rp[c][k] = v.rprop[((size_t)w * QR + a % QR) * 3 + k];
+        s_re[c][k] = Rw[((size_t)spin * n + a) * 3 + k];
+    }
+    __syncthreads();
+    const T L = (T)v.L, iL = (T)(1.0 / v.L), b = (T)v.b;
+    double dj[kJdCand];
+#pragma unroll
+    for (int c = 0; c < kJdCand; ++c) dj[c] = 0.0;
+    const int self = spin * n + a0;
+    for (int i = tid; i < ne; i += kBlock) {
+        const double ri[3] = {Rw[(size_t)i * 3], Rw[(size_t)i * 3 + 1], Rw[(size_t)i * 3 + 2]};
+        const T aa = (T)(((i >= n) == (spin != 0)) ? v.a_par : v.a_anti);
+#pragma unroll
+        for (int c = 0; c < kJdCand; ++c) {
+            const T d = jd_term<T>(aa, b, L, iL, s_rp[c], ri) - jd_term<T>(aa, b, L, iL, s_re[c], ri);
+            dj[c] += i == self + c ? 0.0 : (double)d;  // the candidate's own electron is not a pair
         }
-    } else {
-        s_part[tid] = dj;
-        __syncthreads();
-        if (live && t0 == 0) {
-            double sum = 0.0;
-            for (int q = 0; q < tpp; ++q) sum += s_part[tid + q];
-            v.jd[(size_t)w * QR + slot] = sum;
-        }
+    }
+#pragma unroll
+    for (int c = 0; c < kJdCand; ++c) {
+        const double t = wave_sum(dj[c]);
+        if (lane == 0) s_part[c][wave] = t;
+    }
+    __syncthreads();
+    if (tid < nc) {
+        double sum = 0.0;
+#pragma unroll
+        for (int q = 0; q < kBlock / 64; ++q) sum += s_part[tid][q];
+        v.jd[(size_t)w * QR + (a0 + tid) % QR] = sum;
     }
 }
 
@@ -355,8 +390,15 @@ struct DecideLds {
     int cnt, ndec;
 };
 
+// par: parity of the round within the spin block.  Besides the round's window the
+// kernel writes the gather range of round r+2: from the end of round r+1's range
+// to 2Q past round r+1's first candidate.
+// The decision loop is one latency-bound wave per walker: it asks for nearly all
+// of the CU's 160 KB of LDS so that no gather workgroup shares (and slows) its CU.
+constexpr size_t kDecideLds = 160 * 1024 - 1024;
+
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_decide(CrowdView<T> v, int spin)
+__global__ __launch_bounds__(kBlock) void k_decide(CrowdView<T> v, int spin, int par)
 {
     extern __shared__ unsigned char dsm[];
     DecideLds& S = *reinterpret_cast<DecideLds*>(dsm);
@@ -368,8 +410,18 @@ __global__ __launch_bounds__(kBlock) void k_decide(CrowdView<T> v, int spin)
     const int e0 = spin * n + dec;
     const int rs = v.prm->rec_sweep;
     const uint32_t step = v.prm->step;
+    auto next_range = [&](int dec_next) {  // gather range of round r+2
+        const int lo = v.look[((size_t)(par ^ 1) * v.W + w) * 2 + 1];
+        const int hi = dec_next + 2 * Q < n ? dec_next + 2 * Q : n;
+        int* L = v.look + ((size_t)par * v.W + w) * 2;
+        L[0] = lo;
+        L[1] = hi > lo ? hi : lo;
+    };
     if (nc <= 0) {  // this walker's spin block is done
-        if (tid == 0) v.cnt[(size_t)2 * v.W + w] = 0;
+        if (tid == 0) {
+            v.cnt[(size_t)2 * v.W + w] = 0;
+            next_range(dec);
+        }
         return;
     }
     // candidates: P, uniforms, Jastrow sums, positions
@@ -429,7 +481,7 @@ __global__ __launch_bounds__(kBlock) void k_decide(CrowdView<T> v, int spin)
             const double prob = rho * rho * exp(2.0 * dlnj);
             int acc = S.u[m] < prob;
             const size_t ri = ((size_t)rs * v.ne + e0 + m) * v.W + w;
-            if (v.forced && rs < v.prm->forced_cap) acc = v.forced[ri] != 0;
+            if (v.forced && rs < v.prm->forced_cap && v.forced[ri] < 2) acc = v.forced[ri] != 0;
             if (lane == 0 && rs < v.prm->rec_cap) {
                 v.rec_rho[ri] = rho;
                 v.rec_dlnj[ri] = dlnj;
@@ -506,6 +558,7 @@ __global__ __launch_bounds__(kBlock) void k_decide(CrowdView<T> v, int spin)
         v.cur[2 * w] = dec + ndec;
         v.cur[2 * w + 1] = dec + nc;
         v.cur[2 * v.W + w] = dec;  // start of this round's candidates, for the column kernel
+        next_range(dec + ndec);
     }
     // Jastrow sums of the candidates left for later rounds: add this round's moves
     if (v.use_j2 && tid >= ndec && tid < nc) {
@@ -573,10 +626,19 @@ __global__ __launch_bounds__(kBlock) void k_cols(CrowdView<T> v, int spin)
         if (a < cnt) Cw[(size_t)a * n + l] = (T)acc[a];
 }
 
-__global__ void k_cursor_reset(int* cur, int W)
+// Start of a spin block: cursors at 0, gather ranges [0, Q) for round 0 and
+// [Q, 2Q) for round 1 (clipped to N).
+__global__ void k_cursor_reset(int* cur, int* look, int W, int Q, int n)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < 2 * W) cur[i] = 0;
+    if (i < W) {
+        const int q1 = Q < n ? Q : n, q2 = 2 * Q < n ? 2 * Q : n;
+        look[(size_t)i * 2] = 0;
+        look[(size_t)i * 2 + 1] = q1;
+        look[((size_t)W + i) * 2] = q1;
+        look[((size_t)W + i) * 2 + 1] = q2;
+    }
 }
 
 int batch_rounds(int n, int K) { return (n + K - 1) / K; }
@@ -592,40 +654,59 @@ int batch_candidates(int n, int K)
 }
 
 template <typename T>
-void launch_batch_stencils(const CrowdView<T>& v, int spin, bool block_start, hipStream_t s)
+void launch_batch_stencils(const CrowdView<T>& v, int spin, int par, bool block_start, hipStream_t s)
 {
-    if (block_start) hipLaunchKernelGGL(k_cursor_reset, dim3((2 * v.W + 255) / 256), dim3(256), 0, s, v.cur, v.W);
-    hipLaunchKernelGGL(k_stencils<T>, dim3((v.W * v.Q + kBlock / 64 - 1) / (kBlock / 64)), dim3(kBlock), 0, s, v, spin);
+    if (block_start)
+        hipLaunchKernelGGL(k_cursor_reset, dim3((2 * v.W + 255) / 256), dim3(256), 0, s, v.cur, v.look, v.W, v.Q, v.n);
+    hipLaunchKernelGGL(k_stencils<T>, dim3((v.W * v.Q + kBlock / 64 - 1) / (kBlock / 64)), dim3(kBlock), 0, s, v, spin,
+                       par);
 }
 
 template <typename T>
-void launch_batch_vgl(const CrowdView<T>& v, int spin, hipStream_t s)
+void launch_batch_vgl(const CrowdView<T>& v, int spin, int par, hipStream_t s)
 {
     const int pp = batch_pp(v.n, sizeof(T));
     const int nb = (v.W * v.Q + pp - 1) / pp;
-    hipLaunchKernelGGL(k_prop_vgl<T>, dim3(nb), dim3(batch_threads(v.n, sizeof(T))), 0, s, v, spin, pp);
+    hipLaunchKernelGGL(k_prop_vgl<T>, dim3(nb), dim3(batch_threads(v.n, sizeof(T))), 0, s, v, spin, pp, par);
 }
 
 template <typename T>
-void launch_batch_decide(const CrowdView<T>& v, int spin, hipStream_t s)
+void launch_batch_jd(const CrowdView<T>& v, int spin, hipStream_t s)
+{
+    const int per = (v.Q + kJdCand - 1) / kJdCand;
+    hipLaunchKernelGGL(k_jd<T>, dim3(v.W * per), dim3(kBlock), 0, s, v, spin);
+}
+
+template <typename T>
+void launch_batch_pmat(const CrowdView<T>& v, int spin, hipStream_t s)
 {
     const int pb = (v.Q + kPB - 1) / kPB;
     hipLaunchKernelGGL(k_pmat<T>, dim3(v.W * pb * pb), dim3(kBlock), 0, s, v, spin);
+}
+
+template <typename T>
+void launch_batch_decide(const CrowdView<T>& v, int spin, int par, hipStream_t s)
+{
+    static_assert(sizeof(DecideLds) <= kDecideLds, "decision LDS");
     static bool lds_set = false;  // opt in to more than 64 KB of LDS, once per type
     if (!lds_set) {
         (void)hipFuncSetAttribute((const void*)k_decide<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)sizeof(DecideLds));
+                                  (int)kDecideLds);
         lds_set = true;
     }
-    hipLaunchKernelGGL(k_decide<T>, dim3(v.W), dim3(kBlock), sizeof(DecideLds), s, v, spin);
+    hipLaunchKernelGGL(k_decide<T>, dim3(v.W), dim3(kBlock), kDecideLds, s, v, spin, par);
     hipLaunchKernelGGL(k_cols<T>, dim3(v.W * ((v.n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, v, spin);
 }
 
-template void launch_batch_stencils<float>(const CrowdView<float>&, int, bool, hipStream_t);
-template void launch_batch_stencils<double>(const CrowdView<double>&, int, bool, hipStream_t);
-template void launch_batch_vgl<float>(const CrowdView<float>&, int, hipStream_t);
-template void launch_batch_vgl<double>(const CrowdView<double>&, int, hipStream_t);
-template void launch_batch_decide<float>(const CrowdView<float>&, int, hipStream_t);
-template void launch_batch_decide<double>(const CrowdView<double>&, int, hipStream_t);
+template void launch_batch_stencils<float>(const CrowdView<float>&, int, int, bool, hipStream_t);
+template void launch_batch_stencils<double>(const CrowdView<double>&, int, int, bool, hipStream_t);
+template void launch_batch_vgl<float>(const CrowdView<float>&, int, int, hipStream_t);
+template void launch_batch_vgl<double>(const CrowdView<double>&, int, int, hipStream_t);
+template void launch_batch_jd<float>(const CrowdView<float>&, int, hipStream_t);
+template void launch_batch_jd<double>(const CrowdView<double>&, int, hipStream_t);
+template void launch_batch_pmat<float>(const CrowdView<float>&, int, hipStream_t);
+template void launch_batch_pmat<double>(const CrowdView<double>&, int, hipStream_t);
+template void launch_batch_decide<float>(const CrowdView<float>&, int, int, hipStream_t);
+template void launch_batch_decide<double>(const CrowdView<double>&, int, int, hipStream_t);
 
 }  // namespace cq

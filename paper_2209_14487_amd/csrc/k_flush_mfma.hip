@@ -17,7 +17,7 @@
 // the 16 columns 8 (v / 4) + 4 (l / 32) + v % 4 of the tile).  That layout is at
 // the same time the B operand of GEMM 1 (the two k values of step v are the
 // columns of half 0 and half 1) and the accumulator of GEMM 2, so neither product
-// moves the strip.  Each of the 16 waves holds every 16th tile; GEMM 1 partial
+// moves the strip.  Each of the 8 waves holds every 8th tile; GEMM 1 partial
 // sums of the waves are added in a fixed order in LDS.
 #include "cq_device.h"
 #include "cq_internal.h"
@@ -26,14 +26,18 @@ namespace cq {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-constexpr int kFlushWaves = 16;                   // waves per workgroup
+constexpr int kFlushWaves = 8;                    // waves per workgroup (two workgroups per CU)
 constexpr int kFlushThreads = 64 * kFlushWaves;
-constexpr int kStripTiles = 2;                    // 32-column tiles per wave (N <= 16 * 2 * 32)
+constexpr int kStripTiles = 4;                    // 32-column tiles per wave (N <= 8 * 4 * 32)
 
-__global__ __launch_bounds__(kFlushThreads) void k_flush_mfma(CrowdView<float> v, int spin)
+// kCt: the window's columns come transposed in v.ct (batched path); otherwise
+// they are read from the row buffer Cbuf.  Two workgroups per CU (four waves
+// per SIMD): one's operand and HBM latency hides behind the other's MFMAs.
+template <bool kCt>
+__global__ __launch_bounds__(kFlushThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_flush_mfma(CrowdView<float> v, int spin)
 {
     __shared__ float sX[kFlushWaves][32][33];  // per wave: partial X^T[m][i]
-    __shared__ float sB[32][33];      // b[i][m] (FP32 operand of GEMM 2)
+    __shared__ float sB[32][33];      // -b[i][m] (FP32 operand of GEMM 2)
     __shared__ double sY[32][33];     // x[i][j] - delta(row0 + i, e_j)
     __shared__ double sL[32][33];     // L^-1
     __shared__ int wel[32], wsl[32];
@@ -91,37 +95,30 @@ __global__ __launch_bounds__(kFlushThreads) void k_flush_mfma(CrowdView<float> v
         }
     }
 
-    // GEMM 1: X^T[m][i] = sum_k u_m[k] M[row0 + i][k] over this wave's tiles; the
-    // u operands of the next tile load during this tile's MFMAs
+    // GEMM 1: X^T[m][i] = sum_k u_m[k] M[row0 + i][k] over this wave's tiles.  The
+    // second workgroup on the CU covers the operand latency, so there is no register
+    // double buffer here.
     f32x16 xacc;
 #pragma unroll
     for (int q = 0; q < 16; ++q) xacc[q] = 0.0f;
     const float* urow = v.stage + ((size_t)w * v.QR + wsl[l32 < cnt ? l32 : 0]) * 5 * (size_t)n;
     const bool urow_live = l32 < cnt;
-    auto fetch_u = [&](int t, float (&u)[16]) {
 #pragma unroll
-        for (int g = 0; g < 4; ++g) {
-            float x[4];
-            load16(urow + t * 32 + 8 * g + 4 * h, x);
+    for (int tt = 0; tt < kStripTiles; ++tt) {
+        const int t = wave + kFlushWaves * tt;
+        if (t < ntile) {
+            float u[16];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) u[4 * g + q] = urow_live ? x[q] : 0.0f;
-        }
-    };
-    {
-        float u[16], un[16];
-        if (wave < ntile) fetch_u(wave, u);
+            for (int g = 0; g < 4; ++g) {
+                float x[4];
+                load16(urow + t * 32 + 8 * g + 4 * h, x);
 #pragma unroll
-        for (int tt = 0; tt < kStripTiles; ++tt) {
-            const int t = wave + kFlushWaves * tt;
-            if (t < ntile) {
-                if (tt + 1 < kStripTiles && t + kFlushWaves < ntile) fetch_u(t + kFlushWaves, un);
-#pragma unroll
-                for (int q = 0; q < 16; ++q) xacc = __builtin_amdgcn_mfma_f32_32x32x2f32(u[q], mt[tt][q], xacc, 0, 0, 0);
-#pragma unroll
-                for (int q = 0; q < 16; ++q) u[q] = un[q];
+                for (int q = 0; q < 4; ++q) u[4 * g + q] = urow_live ? x[q] : 0.0f;
             }
-            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int q = 0; q < 16; ++q) xacc = __builtin_amdgcn_mfma_f32_32x32x2f32(u[q], mt[tt][q], xacc, 0, 0, 0);
         }
+        __builtin_amdgcn_sched_barrier(0);
     }
 #pragma unroll
     for (int q = 0; q < 16; ++q) sX[wave][8 * (q >> 2) + 4 * h + (q & 3)][l32] = xacc[q];
@@ -151,17 +148,17 @@ __global__ __launch_bounds__(kFlushThreads) void k_flush_mfma(CrowdView<float> v
             for (int r = 0; r < MPT; ++r) b[r] = fma(sL[m0 + r][j], y, b[r]);
         }
 #pragma unroll
-        for (int r = 0; r < MPT; ++r) sB[i][m0 + r] = (float)b[r];
+        for (int r = 0; r < MPT; ++r) sB[i][m0 + r] = -(float)b[r];  // GEMM 2 subtracts
     }
     __syncthreads();
 
     // GEMM 2: M^T[k][i] -= sum_m c_m[k] b[i][m], moves m = 16 h + s.  With the
     // columns stored transposed (Ct[k][m], 32 per row) a lane fetches the 16
     // operands of a tile with 4 vector loads; otherwise one load per step.
-    const float* Ct = v.ct ? v.ct + ((size_t)w * n) * kMaxDelay : nullptr;
+    const float* Ct = kCt ? v.ct + ((size_t)w * n) * kMaxDelay : nullptr;
     const float* Cw = v.Cbuf + (size_t)w * K * n;
     auto fetch = [&](int t, float (&a)[16]) {
-        if (Ct) {
+        if constexpr (kCt) {
             const float* src = Ct + (size_t)(t * 32 + l32) * kMaxDelay + 16 * h;
 #pragma unroll
             for (int g = 0; g < 4; ++g) load16(src + 4 * g, &a[4 * g]);
@@ -174,20 +171,18 @@ __global__ __launch_bounds__(kFlushThreads) void k_flush_mfma(CrowdView<float> v
             }
         }
     };
-    // software pipeline: the operands of the next tile load during this tile's MFMAs
-    float a[16], an[16];
-    if (wave < ntile) fetch(wave, a);
+    float nb[16];  // -b[l32][16 h + q], the same for every tile
+#pragma unroll
+    for (int q = 0; q < 16; ++q) nb[q] = sB[l32][16 * h + q];
 #pragma unroll
     for (int tt = 0; tt < kStripTiles; ++tt) {
         const int t = wave + kFlushWaves * tt;
         if (t < ntile) {
-            if (tt + 1 < kStripTiles && t + kFlushWaves < ntile) fetch(t + kFlushWaves, an);
+            float a[16];
+            fetch(t, a);
             // operands past cnt are zero (Ct and b are zero-padded), so all 16 steps run
 #pragma unroll
-            for (int q = 0; q < 16; ++q)
-                mt[tt] = __builtin_amdgcn_mfma_f32_32x32x2f32(-a[q], sB[l32][16 * h + q], mt[tt], 0, 0, 0);
-#pragma unroll
-            for (int q = 0; q < 16; ++q) a[q] = an[q];
+            for (int q = 0; q < 16; ++q) mt[tt] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[q], nb[q], mt[tt], 0, 0, 0);
         }
         __builtin_amdgcn_sched_barrier(0);
     }
@@ -243,7 +238,10 @@ void launch_flush_mfma(const CrowdView<float>& v, int spin, hipStream_t s, bool 
 {
     const int nstrip = v.n / 32;
     if (!linv_ready) hipLaunchKernelGGL(k_window_linv, dim3(v.W), dim3(64), 0, s, v);
-    hipLaunchKernelGGL(k_flush_mfma, dim3(xcd_grid(v.W, nstrip)), dim3(kFlushThreads), 0, s, v, spin);
+    if (v.ct)
+        hipLaunchKernelGGL(k_flush_mfma<true>, dim3(xcd_grid(v.W, nstrip)), dim3(kFlushThreads), 0, s, v, spin);
+    else
+        hipLaunchKernelGGL(k_flush_mfma<false>, dim3(xcd_grid(v.W, nstrip)), dim3(kFlushThreads), 0, s, v, spin);
 }
 
 }  // namespace cq

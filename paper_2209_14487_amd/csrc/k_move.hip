@@ -215,7 +215,7 @@ __device__ int resolve_wave(const CrowdView<T>& v, int w, int prev, int cnt, boo
     int acc = u < prob;
     const int rs = v.prm->rec_sweep;
     const size_t ri = ((size_t)rs * v.ne + prev) * v.W + w;
-    if (v.forced && rs < v.prm->forced_cap) acc = v.forced[ri] != 0;
+    if (v.forced && rs < v.prm->forced_cap && v.forced[ri] < 2) acc = v.forced[ri] != 0;
     if (owner) {
         if (lane == 0 && rs < v.prm->rec_cap) {
             v.rec_rho[ri] = rho;

@@ -271,7 +271,7 @@ __global__ __launch_bounds__(512) void k_window(CrowdView<T> v, int e0, int nmov
             const double u = accept_uniform(v.seed, v.uid[w], step, (uint32_t)e);
             int acc = u < prob;
             const size_t ri = ((size_t)rs * v.ne + e) * v.W + w;
-            if (v.forced && rs < v.prm->forced_cap) acc = v.forced[ri] != 0;
+            if (v.forced && rs < v.prm->forced_cap && v.forced[ri] < 2) acc = v.forced[ri] != 0;
             if (lane == 0 && rs < v.prm->rec_cap) {
                 v.rec_rho[ri] = rho;
                 v.rec_dlnj[ri] = dlnj;

@@ -65,7 +65,7 @@ def run_gpu(crowd, R0, sweeps, sigma, first_step=0, forced=None):
     return rec
 
 
-def mixed_ratio_check(gpu_rho, ref_rho, label, p99_bound=1e-4):
+def mixed_ratio_check(gpu_rho, ref_rho, label, p99_bound=1e-4, median_bound=1e-5, max_bound=5e-3):
     err = np.abs(gpu_rho - ref_rho)
     rel = err / np.abs(ref_rho)
     big = np.abs(ref_rho) >= 0.1
@@ -73,9 +73,9 @@ def mixed_ratio_check(gpu_rho, ref_rho, label, p99_bound=1e-4):
                  p999=float(np.quantile(rel[big], 0.999)), max_big=float(rel[big].max()),
                  max_all=float(rel.max()))
     print("%s: ratio rel err %s" % (label, " ".join("%s=%.2e" % kv for kv in stats.items())))
-    assert stats["median"] <= 1e-5, stats
+    assert stats["median"] <= median_bound, stats
     assert stats["p99"] <= p99_bound, stats
-    assert stats["max_big"] <= 5e-3, stats
+    assert stats["max_big"] <= max_bound, stats
     return stats
 
 
@@ -348,3 +348,129 @@ def test_autotuned_delay_rank_keeps_the_chain():
     assert np.array_equal(rec["acc"][0], ref.acc[tuned_sweeps])
     assert np.all(np.abs(rec["rho"][0] - ref.rho[tuned_sweeps]) <= 1e-10 * np.maximum(1.0, np.abs(ref.rho[tuned_sweeps])))
     crowd.close()
+
+
+# Full C4 size: 1024 + 1024 electrons, L = 32, 96^3 seeded table, Pade J2, a crowd of 128
+# walkers, delayed rank 32 on the batched path.  The oracle follows three sampled walkers
+# (first, interior, last of the crowd) through the whole up-spin block and the first 256
+# moves of the down-spin block; the other walkers run alongside, as in the timed sweep.
+C4_N, C4_L, C4_G, C4_W = 1024, 32.0, 96, 128
+C4_SAMPLE = [0, 77, 127]
+C4_MOVES = C4_N + 256
+
+
+def c4_reference(o, R0):
+    return orc.vmc(o, R0[C4_SAMPLE], 1, sigma=0.5, uids=np.array(C4_SAMPLE, np.uint32), max_moves=C4_MOVES,
+                   n_threads=len(C4_SAMPLE))
+
+
+def c4_exact_ratios(o, R0w, uid, acc, moves, sigma=0.5):
+    """Determinant ratios at the given moves of sweep 0 of one walker from a fresh, refined solve
+    of the current matrix (oracle.row_ratio_refined), replaying the oracle's decisions and its
+    proposal stream r' = wrap(r_e + sigma z); A is kept by row replacement, with no inverse."""
+    want = set(int(k) for k in moves)
+    out, R, A = {}, np.array(R0w, dtype=np.float64), [None, None]
+    for e in range(max(want) + 1):
+        if e not in want and not acc[e]:
+            continue
+        sp, i = divmod(e, C4_N)
+        rnew = np.mod(R[e] + sigma * orc.gauss3(1004, uid, 0, e), C4_L)
+        phi = orc.orbital_vgl(o, rnew, C4_N)[0]
+        if e in want:
+            if A[sp] is None:
+                A[sp] = np.array([orc.orbital_vgl(o, R[sp * C4_N + j], C4_N)[0] for j in range(C4_N)])
+            out[e] = orc.row_ratio_refined(A[sp], i, phi)
+        if acc[e]:
+            R[e] = rnew
+            if A[sp] is not None:
+                A[sp][i] = phi
+    return out
+
+
+def test_c4_full_size_fp64_sampled_walkers_match_oracle():
+    """At full C4 size the FP64 batched path reproduces the oracle's chain for the sampled walkers:
+    identical decisions (except at near-ties), Jastrow changes within 1e-10, and ratios and
+    acceptance probabilities within 1e-10 relative, across every round and window flush of a spin
+    block and the spin boundary.  At N = 1024 (cond(A) ~ 1e4) the oracle's own chain of a few
+    hundred Sherman-Morrison updates drifts up to a few 1e-10 from the true ratio, so where the two
+    chains differ by more than 1e-10 the arbiter is the ratio from a fresh, refined solve of the
+    current matrix: the GPU value must be within 1e-10 of it there."""
+    g, o = make_pair(C4_N, C4_L, C4_G, 1004, coef_seed=1004)
+    R0 = start_positions(1004, C4_W, 2 * C4_N, C4_L)
+    crowd = cq.Crowd(g, C4_W, precision="fp64", delay_rank=32, seed=1004, path="batch")
+    gpu = run_gpu(crowd, R0, 1, 0.5)
+    crowd.close()
+    g.close()
+    ref = c4_reference(o, R0)
+    tol = 1e-10
+    rel = lambda a, b: np.abs(a - b) / np.maximum(1.0, np.abs(b))
+    for i, w in enumerate(C4_SAMPLE):
+        acc_g, acc_r = gpu["acc"][0, :C4_MOVES, w], ref.acc[0, :C4_MOVES, i]
+        d = np.nonzero(acc_g != acc_r)[0]
+        lim = C4_MOVES if len(d) == 0 else int(d[0])
+        if len(d):
+            assert abs(ref.prob[0, lim, i] - ref.u[0, lim, i]) < NEAR_TIE, "decision differs away from a near-tie"
+        dj_g, dj_r = gpu["dlnj"][0, :lim, w], ref.dlnj[0, :lim, i]
+        assert np.all(rel(dj_g, dj_r) <= tol), (w, "dlnj")
+        rho_g, rho_r = gpu["rho"][0, :lim, w], ref.rho[0, :lim, i]
+        pr_g, pr_r = gpu["prob"][0, :lim, w], ref.prob[0, :lim, i]
+        off = np.nonzero((rel(rho_g, rho_r) > tol) | (rel(pr_g, pr_r) > tol))[0]
+        msg = "   walker %d: %d moves (%d accepted), rho max diff from the oracle %.2e, %d beyond %.0e" % (
+            w, lim, int(acc_r[:lim].sum()), rel(rho_g, rho_r).max(), len(off), tol)
+        if len(off):
+            ex = c4_exact_ratios(o, R0[w], w, acc_r, off)
+            x = np.array([ex[k] for k in off])
+            eg, eo = rel(rho_g[off], x), rel(rho_r[off], x)
+            msg += "; there: GPU - exact max %.2e, oracle - exact max %.2e" % (eg.max(), eo.max())
+            print(msg)
+            assert np.all(eg <= tol), (w, off[eg > tol])
+            assert np.all(rel(pr_g[off], x * x * np.exp(2.0 * dj_r[off])) <= 2 * tol), w
+        else:
+            print(msg)
+
+
+def test_c4_full_size_mixed_bench_configuration_on_oracle_trajectory():
+    """The timed configuration at full C4 size (FP32 table, inverse and update GEMMs; FP64
+    set-up, log|det| and energy sums; delayed rank 32, FP64 recompute every 32 sweeps, batched
+    path, eager launches with HIP-event timing on): set-up log|det|, sign and E_L of the sampled
+    walkers match the oracle, and along the oracle's decisions their ratios stay within the
+    mixed-precision bar.  The other walkers take their own decisions (flag 2)."""
+    g, o = make_pair(C4_N, C4_L, C4_G, 1004, coef_seed=1004, fp64=False, fp32=True)
+    R0 = start_positions(1004, C4_W, 2 * C4_N, C4_L)
+    ld0, sg0, el0, _ = orc.setup(o, R0[C4_SAMPLE], n_threads=len(C4_SAMPLE))
+    ref = c4_reference(o, R0)
+    forced = np.full((1, 2 * C4_N, C4_W), 2, np.uint8)
+    for i, w in enumerate(C4_SAMPLE):
+        forced[0, :C4_MOVES, w] = ref.acc[0, :C4_MOVES, i]
+    crowd = cq.Crowd(g, C4_W, precision="mixed", delay_rank=32, recompute_every=32, seed=1004, path="batch")
+    crowd.set_timing(["propose", "vgl", "resolve", "update", "energy", "inverse"])
+    crowd.set_positions(R0)
+    ld, sg = crowd.logdet()
+    el = crowd.local_energy()
+    lerr = np.abs(ld[C4_SAMPLE] - ld0) / np.maximum(1.0, np.abs(ld0))
+    eerr = np.abs(el[C4_SAMPLE] - el0) / np.maximum(1.0, np.abs(el0))
+    print("   set-up: log|det| max err %.2e, E_L max rel err %.2e" % (lerr.max(), eerr.max()))
+    assert lerr.max() < 1e-4 and np.array_equal(sg[C4_SAMPLE], sg0)
+    assert eerr.max() < 1e-3
+    gpu = run_gpu(crowd, R0, 1, 0.5, forced=forced)
+    crowd.close()
+    g.close()
+    assert np.array_equal(gpu["acc"][0, :C4_MOVES][:, C4_SAMPLE], ref.acc[0, :C4_MOVES])
+    # At N = 1024 (cond(A) ~ 1e4) an FP32 inverse alone costs more than 1e-4: a CPU emulation of
+    # these three walkers' chains with the inverse stored in FP32 and everything else in FP64 gives
+    # median 2.0e-5, p99 4.3e-4, max 1.6e-3 relative; with FP32 dots and FP32 Sherman-Morrison
+    # updates as well, median 3.4e-5, p99 5.8e-4, p99.9 1.3e-3, max 1.9e-3.  The bounds are
+    # about three times the FP32-arithmetic emulation's median, p99 and maximum.
+    mixed_ratio_check(gpu["rho"][0, :C4_MOVES][:, C4_SAMPLE], ref.rho[0, :C4_MOVES], "C4 mixed k=32 batch",
+                      p99_bound=1.5e-3, median_bound=1e-4, max_bound=5e-3)
+    # its own decisions differ from the oracle's only where P and u are within that error
+    own = gpu["prob"][0, :C4_MOVES][:, C4_SAMPLE] > ref.u[0, :C4_MOVES]
+    mism = own != ref.acc[0, :C4_MOVES].astype(bool)
+    gap = np.abs(ref.prob[0, :C4_MOVES][mism] - ref.u[0, :C4_MOVES][mism]) / ref.prob[0, :C4_MOVES][mism]
+    print("   own decisions differing: %d of %d, max |P-u|/P there %.2e"
+          % (mism.sum(), mism.size, gap.max() if mism.any() else 0.0))
+    assert mism.sum() <= 5e-3 * mism.size and np.all(gap <= 1e-2)
+    assert np.all(np.isfinite(gpu["logdet"])) and np.all(np.isfinite(gpu["eloc"]))
+    acc = gpu["acc"].mean()
+    print("   crowd acceptance %.3f" % acc)
+    assert 0.2 < acc < 0.6
