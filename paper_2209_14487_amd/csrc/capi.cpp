@@ -103,6 +103,7 @@ struct cq_crowd {
     void* stage = nullptr;
     void* Cbuf = nullptr;
     float* ct = nullptr;
+    float* ub = nullptr;
     double* wrho = nullptr;
     double* wG = nullptr;
     double* wlinv = nullptr;
@@ -174,6 +175,7 @@ cq::CrowdView<T> view(const cq_crowd* c)
     v.Cbuf = (T*)c->Cbuf;
     // the batched path hands the matrix-core update its columns transposed
     v.ct = (sizeof(T) == 4 && c->path == CQ_PATH_BATCH && cq::flush_mfma_fits(c->n)) ? c->ct : nullptr;
+    v.ub = v.ct ? c->ub : nullptr;
     v.wrho = c->wrho;
     v.wG = c->wG;
     v.wlinv = c->wlinv;
@@ -247,10 +249,11 @@ void enqueue_sweep(cq_crowd* c)
     if (c->path == CQ_PATH_BATCH) {
         // Rounds of both spin blocks in order.  On stream: P(r), decide(r), update(r), ...
         // On stream2: gather(r+1) once P(r) is formed (so that the decision workgroups of
-        // round r are placed before the gather fills the GPU), then jd(r+1) once decide(r)
-        // is done; P(r+1) waits for both and follows update(r).  gather(r+1) writes only the
-        // ring slots of electrons that round r-1 decided, whose rows update(r-1) has read;
-        // jd(r+1) reads the positions decide(r) wrote and runs beside update(r).
+        // round r are placed before the gather starts), then jd(r+1) and the row copy of
+        // round r once decide(r) is done; P(r+1) waits for all of them and follows
+        // update(r).  gather(r+1) writes only the ring slots of electrons that round r-1
+        // decided, whose rows update(r-1) and the row copy of round r-1 have read; jd(r+1)
+        // reads the positions decide(r) wrote and runs beside update(r).
         const int rounds = cq::batch_rounds(n, K), total = 2 * rounds;
         auto gather = [&](int q, hipStream_t st) {
             const int spin = q / rounds, r = q % rounds;
@@ -285,11 +288,16 @@ void enqueue_sweep(cq_crowd* c)
                 }
                 cq::launch_batch_decide<T>(v, spin, r & 1, s1);
                 timed_end(c, CQ_KERNEL_RESOLVE);
+                // the accepted rows go into the walker's matrices beside the update (before
+                // the next decisions overwrite the window, before gather(r+2) reuses the slots)
                 if (overlap && next) {
                     (void)hipEventRecord(c->ev_dec[q], s1);
                     (void)hipStreamWaitEvent(s2, c->ev_dec[q], 0);
                     jastrow(q + 1, s2);
+                    cq::launch_batch_rows<T>(v, spin, s2);
                     (void)hipEventRecord(c->ev_gat[q + 1], s2);
+                } else {
+                    cq::launch_batch_rows<T>(v, spin, s1);
                 }
                 timed_begin(c, CQ_KERNEL_UPDATE);
                 cq::launch_flush<T>(v, spin, s1, true);
@@ -499,6 +507,7 @@ void dmc_generation(cq_crowd* c, int gen, int n_target, double tau)
 {
     cq::CrowdView<T> v = view<T>(c);
     v.ct = nullptr;  // the per-move kernel leaves the window's columns in row layout
+    v.ub = nullptr;
     const int n = c->n, K = c->K;
     for (int spin = 0; spin < 2; ++spin)
         for (int a0 = 0; a0 < n; a0 += K) {
@@ -784,6 +793,7 @@ cq_status cq_crowd_create(const cq_system* const* systems, const int* walkers_pe
         {&c->stage, es * Wc * c->QR * 5 * n},
         {&c->Cbuf, es * Wc * K * n},
         {(void**)&c->ct, sizeof(float) * Wc * n * cq::kMaxDelay},
+        {(void**)&c->ub, sizeof(float) * Wc * n * cq::kMaxDelay},
         {(void**)&c->wrho, sizeof(double) * Wc * K},
         {(void**)&c->wG, sizeof(double) * Wc * K * K},
         {(void**)&c->wlinv, sizeof(double) * Wc * K * K},

@@ -77,6 +77,7 @@ struct CrowdView {
     T* stage;
     T* Cbuf;
     float* ct;           // [W][N][32] columns transposed (Ct[k][m]) for the matrix-core update, or null
+    float* ub;           // [W][32][N] the window's accepted value rows, packed (set with ct), or null
     double* wrho;
     double* wG;
     double* wlinv;       // [W][K][K] inverse of the window's triangle (G below, rho on the diagonal)
@@ -165,6 +166,7 @@ void launch_batch_stencils(const CrowdView<T>& v, int spin, int par, bool block_
 template <typename T> void launch_batch_vgl(const CrowdView<T>& v, int spin, int par, hipStream_t s);
 template <typename T> void launch_batch_jd(const CrowdView<T>& v, int spin, hipStream_t s);
 template <typename T> void launch_batch_pmat(const CrowdView<T>& v, int spin, hipStream_t s);
+template <typename T> void launch_batch_rows(const CrowdView<T>& v, int spin, hipStream_t s);
 template <typename T> void launch_batch_decide(const CrowdView<T>& v, int spin, int par, hipStream_t s);
 int batch_rounds(int n, int K);      // rounds per spin block (enough when every move is accepted)
 int batch_candidates(int n, int K);  // candidates per round, Q

@@ -45,6 +45,8 @@
 //               c_a = sum_i T[a][i] c0_i), the cursors and the Jastrow sums of the
 //               candidates left for later
 // k_cols        the columns c_a of the accepted moves
+#include <algorithm>
+
 #include "cq_device.h"
 #include "cq_internal.h"
 
@@ -143,77 +145,85 @@ __global__ __launch_bounds__(kBlock) void k_stencils(CrowdView<T> v, int spin, i
 
 // Gather + value/gradient/Laplacian of the electrons in the gather range.  Each
 // thread owns one 16-byte group of orbitals and runs the 64 stencil points as 4
-// planes of 16 loads.
+// planes of 16 loads.  The grid is persistent (a few workgroups per CU, each
+// taking groups of pp proposals in turn), so that the decision, column and update
+// kernels of the current round still find room on every CU while it runs.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_prop_vgl(CrowdView<T> v, int spin, int pp, int par)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_prop_vgl(CrowdView<T> v, int spin, int pp, int par)
 {
     constexpr int VEC = 16 / sizeof(T);
-    __shared__ size_t s_idx[4][64];
-    __shared__ T s_w[4][64 * 5];
-    __shared__ int s_ok[4];
+    // dynamic LDS sized for pp proposals: stencil offsets, weights, flags
+    extern __shared__ size_t vgl_lds[];
+    size_t(*s_idx)[64] = reinterpret_cast<size_t(*)[64]>(vgl_lds);
+    T(*s_w)[64 * 5] = reinterpret_cast<T(*)[64 * 5]>(vgl_lds + (size_t)pp * 64);
+    int* s_ok = reinterpret_cast<int*>(&s_w[pp][0]);
     const int n = v.n, Q = v.Q, QR = v.QR, groups = n / VEC;
     const int nprop = v.W * Q;
     const int nt = blockDim.x, tid = threadIdx.x;
-    const int first = blockIdx.x * pp;
-
-    // stencils of this workgroup's proposals into LDS
-    if (tid < pp) {
-        const int pi = first + tid;
-        int a = 0;
-        s_ok[tid] = pi < nprop && gather_electron(v.look, par, v.W, pi / Q, pi % Q, a);
-    }
-    __syncthreads();
-    for (int idx = tid; idx < pp * 64; idx += nt) {
-        const int p = idx >> 6, l = idx & 63, pi = first + p;
-        if (!s_ok[p]) continue;
-        int a = 0;
-        gather_electron(v.look, par, v.W, pi / Q, pi % Q, a);
-        const size_t ps = (size_t)(pi / Q) * QR + a % QR;
-        s_idx[p][l] = v.sidx[ps * 64 + l];
-        const T* sw = (const T*)v.swt + (ps * 64 + l) * 5;
-#pragma unroll
-        for (int k = 0; k < 5; ++k) s_w[p][l * 5 + k] = sw[k];
-    }
-    __syncthreads();
-
     const int tpp = pp == 1 ? nt : groups;  // threads per proposal
     const int p = tid / tpp, t0 = tid % tpp;
-    const int pi = first + p;
-    if (!(p < pp && pi < nprop && s_ok[p])) return;
-    int a = 0;
-    gather_electron(v.look, par, v.W, pi / Q, pi % Q, a);
-    const int w = pi / Q, slot = a % QR;
-    T* dst = v.stage + ((size_t)w * QR + slot) * 5 * (size_t)n;
-    const size_t* sidx = s_idx[p];
-    const T* sw = s_w[p];
-    for (int g = t0; g < groups; g += tpp) {
-        const int j0 = g * VEC;
-        T acc[5][VEC];
+    const int nchunk = (nprop + pp - 1) / pp;
+
+    for (int chunk = blockIdx.x; chunk < nchunk; chunk += gridDim.x) {
+        const int first = chunk * pp;
+        __syncthreads();  // the previous chunk's readers of the stencils are done
+        // stencils of this chunk's proposals into LDS
+        if (tid < pp) {
+            const int pi = first + tid;
+            int a = 0;
+            s_ok[tid] = pi < nprop && gather_electron(v.look, par, v.W, pi / Q, pi % Q, a);
+        }
+        __syncthreads();
+        for (int idx = tid; idx < pp * 64; idx += nt) {
+            const int pq = idx >> 6, l = idx & 63, pi = first + pq;
+            if (!s_ok[pq]) continue;
+            int a = 0;
+            gather_electron(v.look, par, v.W, pi / Q, pi % Q, a);
+            const size_t ps = (size_t)(pi / Q) * QR + a % QR;
+            s_idx[pq][l] = v.sidx[ps * 64 + l];
+            const T* sw = (const T*)v.swt + (ps * 64 + l) * 5;
 #pragma unroll
-        for (int k = 0; k < 5; ++k)
+            for (int k = 0; k < 5; ++k) s_w[pq][l * 5 + k] = sw[k];
+        }
+        __syncthreads();
+
+        const int pi = first + p;
+        if (!(p < pp && pi < nprop && s_ok[p])) continue;
+        int a = 0;
+        gather_electron(v.look, par, v.W, pi / Q, pi % Q, a);
+        const int w = pi / Q, slot = a % QR;
+        T* dst = v.stage + ((size_t)w * QR + slot) * 5 * (size_t)n;
+        const size_t* sidx = s_idx[p];
+        const T* sw = s_w[p];
+        for (int g = t0; g < groups; g += tpp) {
+            const int j0 = g * VEC;
+            T acc[5][VEC];
 #pragma unroll
-            for (int i = 0; i < VEC; ++i) acc[k][i] = (T)0;
+            for (int k = 0; k < 5; ++k)
+#pragma unroll
+                for (int i = 0; i < VEC; ++i) acc[k][i] = (T)0;
 #pragma unroll 1
-        for (int x = 0; x < 4; ++x) {
-            T vals[16][VEC];
+            for (int x = 0; x < 4; ++x) {
+                T vals[16][VEC];
 #pragma unroll
-            for (int q = 0; q < 16; ++q) load16(v.table + sidx[x * 16 + q] + j0, vals[q]);
+                for (int q = 0; q < 16; ++q) load16(v.table + sidx[x * 16 + q] + j0, vals[q]);
 #pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const T* wq = sw + (x * 16 + q) * 5;
-                const T wv = wq[0], wgx = wq[1], wgy = wq[2], wgz = wq[3], wl = wq[4];
+                for (int q = 0; q < 16; ++q) {
+                    const T* wq = sw + (x * 16 + q) * 5;
+                    const T wv = wq[0], wgx = wq[1], wgy = wq[2], wgz = wq[3], wl = wq[4];
 #pragma unroll
-                for (int i = 0; i < VEC; ++i) {
-                    acc[0][i] += wv * vals[q][i];
-                    acc[1][i] += wgx * vals[q][i];
-                    acc[2][i] += wgy * vals[q][i];
-                    acc[3][i] += wgz * vals[q][i];
-                    acc[4][i] += wl * vals[q][i];
+                    for (int i = 0; i < VEC; ++i) {
+                        acc[0][i] += wv * vals[q][i];
+                        acc[1][i] += wgx * vals[q][i];
+                        acc[2][i] += wgy * vals[q][i];
+                        acc[3][i] += wgz * vals[q][i];
+                        acc[4][i] += wl * vals[q][i];
+                    }
                 }
             }
-        }
 #pragma unroll
-        for (int k = 0; k < 5; ++k) store16(dst + (size_t)k * n + j0, acc[k]);
+            for (int k = 0; k < 5; ++k) store16(dst + (size_t)k * n + j0, acc[k]);
+        }
     }
 }
 
@@ -369,11 +379,11 @@ __device__ __forceinline__ double pair_change(const CrowdView<T>& v, const doubl
 }
 
 // Decision kernel.  Everything the sequential loop reads sits in LDS (dynamic,
-// about 139 KB at Q = 88): P, the Jastrow pair changes of every candidate pair,
-// T, X[a][i] = u_i . c_a (the accepted columns against every candidate), and
-// L^-1 of the window's triangle (G below the diagonal, rho on it), so that
-//     beta = L^-1 y,  y_a = P[s_a][m]        (a product, not a substitution)
-// and every per-candidate quantity is a lookup or an independent sum.  T is kept
+// about 140 KB at Q = 88): P, the Jastrow pair changes of every candidate pair,
+// T, X[a][i] = u_i . c_a (the accepted columns against every candidate), L^-1 of
+// the window's triangle (G below the diagonal, rho on it), so that
+//     beta = L^-1 y,  y_a = P[s_a][m]        (a product, not a substitution),
+// and the running ratio and Jastrow sum of every candidate.  T is kept
 // in the basis of the accepted moves' own start columns: c_a = sum_{j<=a}
 // T[a][j] c0_{s_j} (lower triangular, T[a][a] = 1), so an acceptance costs
 // O(accepted), not O(candidates).
@@ -385,6 +395,7 @@ struct DecideLds {
     double X[D][QM + 1];
     double Li[D][D + 1];
     double u[QM], jd[QM];
+    double rho[QM], dj[QM];        // running Schur complement and Jastrow sum of each candidate
     double rold[QM][3], rnew[QM][3];
     int slot[D];
     int cnt, ndec;
@@ -393,9 +404,9 @@ struct DecideLds {
 // par: parity of the round within the spin block.  Besides the round's window the
 // kernel writes the gather range of round r+2: from the end of round r+1's range
 // to 2Q past round r+1's first candidate.
-// The decision loop is one latency-bound wave per walker: it asks for nearly all
-// of the CU's 160 KB of LDS so that no gather workgroup shares (and slows) its CU.
-constexpr size_t kDecideLds = 160 * 1024 - 1024;
+// Gather workgroups per CU: the rest of each CU stays free for the kernels of the
+// round being decided and applied.
+constexpr int kVglBlocksPerCU = 3;
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_decide(CrowdView<T> v, int spin, int par)
@@ -408,8 +419,12 @@ __global__ __launch_bounds__(kBlock) void k_decide(CrowdView<T> v, int spin, int
     const int dec = v.cur[2 * w];
     const int nc = (dec + Q < n ? dec + Q : n) - dec;
     const int e0 = spin * n + dec;
+    // run parameters in registers: the loop below stores to global memory, so loads
+    // through v.prm inside it could not be hoisted and would cost a round trip each
     const int rs = v.prm->rec_sweep;
     const uint32_t step = v.prm->step;
+    const bool recording = rs < v.prm->rec_cap;
+    const bool forcing = v.forced && rs < v.prm->forced_cap;
     auto next_range = [&](int dec_next) {  // gather range of round r+2
         const int lo = v.look[((size_t)(par ^ 1) * v.W + w) * 2 + 1];
         const int hi = dec_next + 2 * Q < n ? dec_next + 2 * Q : n;
@@ -450,6 +465,10 @@ __global__ __launch_bounds__(kBlock) void k_decide(CrowdView<T> v, int spin, int
     }
     __syncthreads();
     for (int idx = tid; idx < kMaxDelay * (kMaxDelay + 1); idx += kBlock) (&S.Li[0][0])[idx] = 0.0;
+    if (tid < nc) {
+        S.rho[tid] = S.P[tid][tid];
+        S.dj[tid] = S.jd[tid];
+    }
     // Jastrow pair changes of all candidate pairs (s < m)
     for (int idx = tid; idx < nc * nc; idx += kBlock) {
         const int m = idx / nc, sx = idx % nc;
@@ -458,37 +477,41 @@ __global__ __launch_bounds__(kBlock) void k_decide(CrowdView<T> v, int spin, int
     }
     __syncthreads();
 
-    // decisions in electron order (wave 0; lane a <-> accepted move a for beta and
-    // x, lane i <-> candidate i for the new rows of T and X)
+    // decisions in electron order (wave 0).  Candidate m's ratio and Jastrow sum are
+    // read from rho[m] and dj[m], which every acceptance brings up to date for all later
+    // candidates at once (lane i <-> candidate i):
+    //     rho_i -= beta_a(i) x_a(i),  dj_i += PC(i, m_a),
+    // with beta(i) = L^-1 y(i), y_j(i) = P[s_j][i], for the new accepted move a; so a
+    // rejection costs O(1) and an acceptance O(accepted) per lane.  On acceptance
+    // (lane a <-> accepted move a): beta(m), the new rows of G, L^-1, T and X.
     if (wave == 0) {
         double ld = v.logdet[w * 2 + spin];
         int sg = v.sign[w * 2 + spin];
         int cnt = 0, m = 0;
         for (; m < nc && cnt < K; ++m) {
-            const bool mine = lane < cnt;
-            const int sa = mine ? S.slot[lane] : 0;
-            const double y = mine ? S.P[sa][m] : 0.0;
-            const double x = mine ? S.X[lane][m] : 0.0;
-            const double pc = mine ? S.PC[m * (m - 1) / 2 + sa] : 0.0;
-            // beta_a = sum_{j<=a} Li[a][j] y_j  (Li is zero above the diagonal)
-            const int arow = mine ? lane : 0;
-            double beta = 0.0;
-#pragma unroll 8
-            for (int j = 0; j < cnt; ++j) beta += S.Li[arow][j] * dpp::lane(y, j);
-            if (!mine) beta = 0.0;
-            const double rho = S.P[m][m] - wave_sum(beta * x);
-            const double dlnj = S.jd[m] + wave_sum(pc);
+            const double rho = S.rho[m];
+            const double dlnj = S.dj[m];
             const double prob = rho * rho * exp(2.0 * dlnj);
             int acc = S.u[m] < prob;
             const size_t ri = ((size_t)rs * v.ne + e0 + m) * v.W + w;
-            if (v.forced && rs < v.prm->forced_cap && v.forced[ri] < 2) acc = v.forced[ri] != 0;
-            if (lane == 0 && rs < v.prm->rec_cap) {
+            if (forcing && v.forced[ri] < 2) acc = v.forced[ri] != 0;
+            if (lane == 0 && recording) {
                 v.rec_rho[ri] = rho;
                 v.rec_dlnj[ri] = dlnj;
                 v.rec_prob[ri] = prob;
                 v.rec_acc[ri] = (uint8_t)acc;
             }
             if (acc) {
+                const bool mine = lane < cnt;
+                const int sa = mine ? S.slot[lane] : 0;
+                const double y = mine ? S.P[sa][m] : 0.0;
+                const double x = mine ? S.X[lane][m] : 0.0;
+                // beta_a = sum_{j<=a} Li[a][j] y_j  (Li is zero above the diagonal)
+                const int arow = mine ? lane : 0;
+                double beta = 0.0;
+#pragma unroll 8
+                for (int j = 0; j < cnt; ++j) beta += S.Li[arow][j] * dpp::lane(y, j);
+                if (!mine) beta = 0.0;
                 const double rinv = 1.0 / rho;
                 if (mine) v.wG[((size_t)w * K + cnt) * K + lane] = x;  // G[cnt][a] = u_m . c_a
                 // new row of L^-1: Li[cnt][j] = -sum_{t=j}^{cnt-1} x_t Li[t][j] / rho  (lane j)
@@ -510,13 +533,25 @@ __global__ __launch_bounds__(kBlock) void k_decide(CrowdView<T> v, int spin, int
                     if (lane > cnt && lane < kMaxDelay) S.T[cnt][lane] = 0.0;
                     if (lane == 0) S.slot[cnt] = m;
                 }
-                // new row of X for the later candidates: X[cnt][i] = sum_{j<=cnt} T[cnt][j] P[i][s_j]
+                // the accepted candidates' slots in a register: lane j holds s_j
+                const int myslot = lane < cnt ? S.slot[lane] : (lane == cnt ? m : 0);
+                // new row of X and of beta for every candidate, and the running updates:
+                //     X[cnt][i]  = sum_{j<=cnt} T[cnt][j]  P[i][s_j]
+                //     beta_cnt(i) = sum_{j<=cnt} Li[cnt][j] P[s_j][i]
                 for (int base = 0; base < DecideLds::QM; base += 64) {
                     const int i = base + lane, ic = i < DecideLds::QM ? i : DecideLds::QM - 1;
-                    double xc = 0.0;
+                    double xc = 0.0, bc = 0.0;
 #pragma unroll 8
-                    for (int j = 0; j <= cnt; ++j) xc += S.T[cnt][j] * S.P[ic][S.slot[j]];
+                    for (int j = 0; j <= cnt; ++j) {
+                        const int sj = __builtin_amdgcn_readlane(myslot, j);
+                        xc += S.T[cnt][j] * S.P[ic][sj];
+                        bc += S.Li[cnt][j] * S.P[sj][ic];
+                    }
                     if (i < DecideLds::QM) S.X[cnt][i] = xc;
+                    if (i > m && i < nc) {
+                        S.rho[i] -= bc * xc;
+                        S.dj[i] += S.PC[i * (i - 1) / 2 + m];
+                    }
                 }
                 if (lane == 0) {
                     v.wrho[(size_t)w * K + cnt] = rho;
@@ -560,24 +595,22 @@ __global__ __launch_bounds__(kBlock) void k_decide(CrowdView<T> v, int spin, int
         v.cur[2 * v.W + w] = dec;  // start of this round's candidates, for the column kernel
         next_range(dec + ndec);
     }
-    // Jastrow sums of the candidates left for later rounds: add this round's moves
-    if (v.use_j2 && tid >= ndec && tid < nc) {
-        double d = 0.0;
-        for (int j = 0; j < cnt; ++j) d += S.PC[tid * (tid - 1) / 2 + S.slot[j]];
-        v.jd[(size_t)w * v.QR + (dec + tid) % v.QR] = S.jd[tid] + d;
-    }
+    // Jastrow sums of the candidates left for later rounds, with this round's moves
+    if (v.use_j2 && tid >= ndec && tid < nc) v.jd[(size_t)w * v.QR + (dec + tid) % v.QR] = S.dj[tid];
 }
 
 // Columns of the accepted moves: c_a = sum_{j<=a} T[a][j] c0_{s_j} for a < cnt,
 // c0_{s_j} the start column of the j-th accepted move's electron (FP64 sums of
 // exact products, rounded to T).  One thread per orbital; the loads of 8
-// columns are issued together.
+// columns are issued together.  For the matrix-core update the kernel also packs
+// the accepted value rows (ub), so that the update kernel's loads need no
+// indirection.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_cols(CrowdView<T> v, int spin)
 {
     constexpr int D = kMaxDelay;
     __shared__ double s_T[D][D + 1];
-    __shared__ int s_row[D];
+    __shared__ int s_row[D], s_slot[D];
     const int n = v.n, K = v.K;
     const int nlb = (n + kBlock - 1) / kBlock;
     const int w = blockIdx.x / nlb, l = (blockIdx.x % nlb) * kBlock + threadIdx.x;
@@ -590,10 +623,18 @@ __global__ __launch_bounds__(kBlock) void k_cols(CrowdView<T> v, int spin)
     }
     if (threadIdx.x < D) {
         const int e = threadIdx.x < cnt ? v.welec[(size_t)w * K + threadIdx.x] : 0;
+        const int sl = threadIdx.x < cnt ? v.wslot[(size_t)w * K + threadIdx.x] : 0;
+        if (e < 0 || e >= n || sl < 0 || sl >= v.QR) atomicOr(&v.status[w], 2);
         s_row[threadIdx.x] = e >= 0 && e < n ? e : 0;
+        s_slot[threadIdx.x] = sl >= 0 && sl < v.QR ? sl : 0;
     }
     __syncthreads();
     if (l >= n) return;
+    if constexpr (sizeof(T) == 4) {
+        if (v.ub)
+            for (int a = 0; a < cnt; ++a)
+                v.ub[((size_t)w * D + a) * n + l] = v.stage[((size_t)w * v.QR + s_slot[a]) * 5 * (size_t)n + l];
+    }
     const T* Mw = v.M + ((size_t)w * 2 + spin) * n * (size_t)n + l;
     double acc[D];
 #pragma unroll
@@ -628,6 +669,31 @@ __global__ __launch_bounds__(kBlock) void k_cols(CrowdView<T> v, int spin)
 
 // Start of a spin block: cursors at 0, gather ranges [0, Q) for round 0 and
 // [Q, 2Q) for round 1 (clipped to N).
+// The accepted orbital rows of the window (value, gradient, Laplacian) go into the
+// walker's matrices: one thread per orbital, for the matrix-core path (the vector
+// update copies them itself).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_rows(CrowdView<T> v, int spin)
+{
+    const int n = v.n, K = v.K;
+    const int nlb = (n + kBlock - 1) / kBlock;
+    const int w = blockIdx.x / nlb, l = (blockIdx.x % nlb) * kBlock + threadIdx.x;
+    int cnt = v.cnt[(size_t)2 * v.W + w];
+    if (cnt > K) cnt = K;
+    if (l >= n) return;
+    for (int a = 0; a < cnt; ++a) {
+        const int e = v.welec[(size_t)w * K + a], sl = v.wslot[(size_t)w * K + a];
+        if (e < 0 || e >= n || sl < 0 || sl >= v.QR) continue;  // reported by the column kernel
+        const T* src = v.stage + ((size_t)w * v.QR + sl) * 5 * (size_t)n + l;
+        T* dst = v.VGL + (((size_t)w * 2 + spin) * n + e) * 5 * (size_t)n + l;
+        T x[5];
+#pragma unroll
+        for (int p = 0; p < 5; ++p) x[p] = src[(size_t)p * n];
+#pragma unroll
+        for (int p = 0; p < 5; ++p) dst[(size_t)p * n] = x[p];
+    }
+}
+
 __global__ void k_cursor_reset(int* cur, int* look, int W, int Q, int n)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -662,12 +728,26 @@ void launch_batch_stencils(const CrowdView<T>& v, int spin, int par, bool block_
                        par);
 }
 
+int device_cu_count()
+{
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+            cus = 256;
+    }
+    return cus;
+}
+
 template <typename T>
 void launch_batch_vgl(const CrowdView<T>& v, int spin, int par, hipStream_t s)
 {
     const int pp = batch_pp(v.n, sizeof(T));
-    const int nb = (v.W * v.Q + pp - 1) / pp;
-    hipLaunchKernelGGL(k_prop_vgl<T>, dim3(nb), dim3(batch_threads(v.n, sizeof(T))), 0, s, v, spin, pp, par);
+    const int nchunk = (v.W * v.Q + pp - 1) / pp;
+    const int nb = std::min(nchunk, kVglBlocksPerCU * device_cu_count());
+    const size_t lds = (size_t)pp * (64 * sizeof(size_t) + 64 * 5 * sizeof(T)) + 4 * sizeof(int);
+    hipLaunchKernelGGL(k_prop_vgl<T>, dim3(nb), dim3(batch_threads(v.n, sizeof(T))), lds, s, v, spin, pp, par);
 }
 
 template <typename T>
@@ -675,6 +755,13 @@ void launch_batch_jd(const CrowdView<T>& v, int spin, hipStream_t s)
 {
     const int per = (v.Q + kJdCand - 1) / kJdCand;
     hipLaunchKernelGGL(k_jd<T>, dim3(v.W * per), dim3(kBlock), 0, s, v, spin);
+}
+
+template <typename T>
+void launch_batch_rows(const CrowdView<T>& v, int spin, hipStream_t s)
+{
+    if (!v.ub) return;
+    hipLaunchKernelGGL(k_rows<T>, dim3(v.W * ((v.n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, v, spin);
 }
 
 template <typename T>
@@ -687,14 +774,13 @@ void launch_batch_pmat(const CrowdView<T>& v, int spin, hipStream_t s)
 template <typename T>
 void launch_batch_decide(const CrowdView<T>& v, int spin, int par, hipStream_t s)
 {
-    static_assert(sizeof(DecideLds) <= kDecideLds, "decision LDS");
     static bool lds_set = false;  // opt in to more than 64 KB of LDS, once per type
     if (!lds_set) {
         (void)hipFuncSetAttribute((const void*)k_decide<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)kDecideLds);
+                                  (int)sizeof(DecideLds));
         lds_set = true;
     }
-    hipLaunchKernelGGL(k_decide<T>, dim3(v.W), dim3(kBlock), kDecideLds, s, v, spin, par);
+    hipLaunchKernelGGL(k_decide<T>, dim3(v.W), dim3(kBlock), sizeof(DecideLds), s, v, spin, par);
     hipLaunchKernelGGL(k_cols<T>, dim3(v.W * ((v.n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, v, spin);
 }
 
@@ -704,6 +790,8 @@ template void launch_batch_vgl<float>(const CrowdView<float>&, int, int, hipStre
 template void launch_batch_vgl<double>(const CrowdView<double>&, int, int, hipStream_t);
 template void launch_batch_jd<float>(const CrowdView<float>&, int, hipStream_t);
 template void launch_batch_jd<double>(const CrowdView<double>&, int, hipStream_t);
+template void launch_batch_rows<float>(const CrowdView<float>&, int, hipStream_t);
+template void launch_batch_rows<double>(const CrowdView<double>&, int, hipStream_t);
 template void launch_batch_pmat<float>(const CrowdView<float>&, int, hipStream_t);
 template void launch_batch_pmat<double>(const CrowdView<double>&, int, hipStream_t);
 template void launch_batch_decide<float>(const CrowdView<float>&, int, int, hipStream_t);

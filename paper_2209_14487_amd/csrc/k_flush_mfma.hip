@@ -30,10 +30,9 @@ constexpr int kFlushWaves = 8;                    // waves per workgroup (two wo
 constexpr int kFlushThreads = 64 * kFlushWaves;
 constexpr int kStripTiles = 4;                    // 32-column tiles per wave (N <= 8 * 4 * 32)
 
-// kCt: the window's columns come transposed in v.ct (batched path); otherwise
-// they are read from the row buffer Cbuf.  Two workgroups per CU (four waves
-// per SIMD): one's operand and HBM latency hides behind the other's MFMAs.
-template <bool kCt>
+// Window and per-move paths: the window's columns are read from the row buffer
+// Cbuf.  Two workgroups per CU (four waves per SIMD): one's operand and HBM
+// latency hides behind the other's MFMAs.
 __global__ __launch_bounds__(kFlushThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_flush_mfma(CrowdView<float> v, int spin)
 {
     __shared__ float sX[kFlushWaves][32][33];  // per wave: partial X^T[m][i]
@@ -152,23 +151,14 @@ __global__ __launch_bounds__(kFlushThreads) __attribute__((amdgpu_waves_per_eu(4
     }
     __syncthreads();
 
-    // GEMM 2: M^T[k][i] -= sum_m c_m[k] b[i][m], moves m = 16 h + s.  With the
-    // columns stored transposed (Ct[k][m], 32 per row) a lane fetches the 16
-    // operands of a tile with 4 vector loads; otherwise one load per step.
-    const float* Ct = kCt ? v.ct + ((size_t)w * n) * kMaxDelay : nullptr;
+    // GEMM 2: M^T[k][i] -= sum_m c_m[k] b[i][m], moves m = 16 h + q, one load per step
     const float* Cw = v.Cbuf + (size_t)w * K * n;
     auto fetch = [&](int t, float (&a)[16]) {
-        if constexpr (kCt) {
-            const float* src = Ct + (size_t)(t * 32 + l32) * kMaxDelay + 16 * h;
 #pragma unroll
-            for (int g = 0; g < 4; ++g) load16(src + 4 * g, &a[4 * g]);
-        } else {
-#pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const int m = 16 * h + q;
-                const float c = Cw[(size_t)(m < cnt ? m : 0) * n + t * 32 + l32];
-                a[q] = m < cnt ? c : 0.0f;
-            }
+        for (int q = 0; q < 16; ++q) {
+            const int m = 16 * h + q;
+            const float c = Cw[(size_t)(m < cnt ? m : 0) * n + t * 32 + l32];
+            a[q] = m < cnt ? c : 0.0f;
         }
     };
     float nb[16];  // -b[l32][16 h + q], the same for every tile
@@ -189,6 +179,152 @@ __global__ __launch_bounds__(kFlushThreads) __attribute__((amdgpu_waves_per_eu(4
 #pragma unroll
     for (int tt = 0; tt < kStripTiles; ++tt) {
         const int t = wave + kFlushWaves * tt;
+        if (t < ntile) {
+            float* dst = Mb + (size_t)l32 * n + t * 32 + 4 * h;
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                float x[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) x[q] = mt[tt][4 * g + q];
+                store16(dst + 8 * g, x);
+            }
+        }
+    }
+}
+
+// Batched path: the window's accepted value rows come packed in v.ub and its
+// columns transposed in v.ct (both written by the column kernel, which has also
+// moved the accepted orbital rows), so a strip's loads need no indirection.  Two
+// workgroups of 8 waves (4 tiles each) per CU: one's loads are in flight while the
+// other runs its MFMAs.
+constexpr int kBatchWaves = 8;
+constexpr int kBatchThreads = 64 * kBatchWaves;
+constexpr int kBatchTiles = 4;
+
+__global__ __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_flush_mfma_batch(
+    CrowdView<float> v, int spin)
+{
+    __shared__ float sX[kBatchWaves][32][33];  // per wave: partial X^T[m][i]
+    __shared__ float sB[32][33];      // -b[i][m] (FP32 operand of GEMM 2)
+    __shared__ double sY[32][33];     // x[i][j] - delta(row0 + i, e_j)
+    __shared__ double sL[32][33];     // L^-1
+    __shared__ int wel[32];
+    const int n = v.n, K = v.K;
+    const int ntile = n / 32, nstrip = n / 32;
+    int w, strip;
+    xcd_map(blockIdx.x, nstrip, w, strip);
+    if (w >= v.W) return;
+    int cnt = v.cnt[(size_t)2 * v.W + w];
+    if (cnt > K) cnt = K;
+    if (cnt <= 0) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int h = lane >> 5, l32 = lane & 31;
+    if (tid < 32) wel[tid] = tid < cnt ? v.welec[(size_t)w * K + tid] : -1;
+    __syncthreads();
+
+    const int row0 = strip * 32;
+    float* Mb = v.M + (((size_t)w * 2 + spin) * n + row0) * (size_t)n;
+    f32x16 mt[kBatchTiles];
+#pragma unroll
+    for (int tt = 0; tt < kBatchTiles; ++tt) {
+        const int t = wave + kBatchWaves * tt;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) mt[tt][q] = 0.0f;
+        if (t < ntile) {
+            const float* src = Mb + (size_t)l32 * n + t * 32 + 4 * h;
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                float x[4];
+                load16(src + 8 * g, x);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) mt[tt][4 * g + q] = x[q];
+            }
+        }
+    }
+
+    // GEMM 1: X^T[m][i] = sum_k u_m[k] M[row0 + i][k] over this wave's tiles.  The
+    // second workgroup on the CU covers the operand latency, so there is no register
+    // double buffer here.
+    f32x16 xacc;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) xacc[q] = 0.0f;
+    const float* urow = v.ub + ((size_t)w * kMaxDelay + l32) * n;
+    const bool urow_live = l32 < cnt;
+#pragma unroll
+    for (int tt = 0; tt < kBatchTiles; ++tt) {
+        const int t = wave + kBatchWaves * tt;
+        if (t < ntile) {
+            float u[16];
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                float x[4];
+                load16(urow + t * 32 + 8 * g + 4 * h, x);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) u[4 * g + q] = urow_live ? x[q] : 0.0f;
+            }
+#pragma unroll
+            for (int q = 0; q < 16; ++q) xacc = __builtin_amdgcn_mfma_f32_32x32x2f32(u[q], mt[tt][q], xacc, 0, 0, 0);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) sX[wave][8 * (q >> 2) + 4 * h + (q & 3)][l32] = xacc[q];
+    __syncthreads();
+
+    // y[i][j] = x[i][j] - delta(row0 + i, e_j) in FP64, then
+    // b[i][m] = sum_j Linv[m][j] y[i][j] (Linv and y zero-padded to 32 x 32)
+    for (int idx = tid; idx < 32 * 32; idx += kBatchThreads) {
+        const int i = idx >> 5, j = idx & 31;
+        double x = 0.0;
+#pragma unroll
+        for (int q = 0; q < kBatchWaves; ++q) x += (double)sX[q][j][i];
+        sY[i][j] = j < cnt ? x - (row0 + i == wel[j] ? 1.0 : 0.0) : 0.0;
+        sL[i][j] = (i < cnt && j <= i) ? v.wlinv[((size_t)w * K + i) * K + j] : 0.0;
+    }
+    __syncthreads();
+    {
+        constexpr int MPT = 32 * 32 / kBatchThreads;  // moves of one row per thread
+        const int i = tid / (32 / MPT), m0 = (tid % (32 / MPT)) * MPT;
+        double b[MPT];
+#pragma unroll
+        for (int r = 0; r < MPT; ++r) b[r] = 0.0;
+#pragma unroll
+        for (int j = 0; j < 32; ++j) {
+            const double y = sY[i][j];
+#pragma unroll
+            for (int r = 0; r < MPT; ++r) b[r] = fma(sL[m0 + r][j], y, b[r]);
+        }
+#pragma unroll
+        for (int r = 0; r < MPT; ++r) sB[i][m0 + r] = -(float)b[r];  // GEMM 2 subtracts
+    }
+    __syncthreads();
+
+    // GEMM 2: M^T[k][i] -= sum_m c_m[k] b[i][m], moves m = 16 h + q, operands Ct[k][m]
+    // (32 per row, zero past cnt), 4 vector loads per tile
+    const float* Ct = v.ct + ((size_t)w * n) * kMaxDelay;
+    auto fetch = [&](int t, float (&a)[16]) {
+        const float* src = Ct + (size_t)(t * 32 + l32) * kMaxDelay + 16 * h;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) load16(src + 4 * g, &a[4 * g]);
+    };
+    float nb[16];  // -b[l32][16 h + q], the same for every tile
+#pragma unroll
+    for (int q = 0; q < 16; ++q) nb[q] = sB[l32][16 * h + q];
+#pragma unroll
+    for (int tt = 0; tt < kBatchTiles; ++tt) {
+        const int t = wave + kBatchWaves * tt;
+        if (t < ntile) {
+            float a[16];
+            fetch(t, a);
+            // operands past cnt are zero (Ct and b are zero-padded), so all 16 steps run
+#pragma unroll
+            for (int q = 0; q < 16; ++q) mt[tt] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[q], nb[q], mt[tt], 0, 0, 0);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int tt = 0; tt < kBatchTiles; ++tt) {
+        const int t = wave + kBatchWaves * tt;
         if (t < ntile) {
             float* dst = Mb + (size_t)l32 * n + t * 32 + 4 * h;
 #pragma unroll
@@ -232,16 +368,19 @@ __global__ __launch_bounds__(64) void k_window_linv(CrowdView<float> v)
     }
 }
 
-bool flush_mfma_fits(int n) { return n % 32 == 0 && n <= kFlushWaves * kStripTiles * 32; }
+bool flush_mfma_fits(int n)
+{
+    return n % 32 == 0 && n <= kFlushWaves * kStripTiles * 32 && n <= kBatchWaves * kBatchTiles * 32;
+}
 
 void launch_flush_mfma(const CrowdView<float>& v, int spin, hipStream_t s, bool linv_ready)
 {
     const int nstrip = v.n / 32;
     if (!linv_ready) hipLaunchKernelGGL(k_window_linv, dim3(v.W), dim3(64), 0, s, v);
-    if (v.ct)
-        hipLaunchKernelGGL(k_flush_mfma<true>, dim3(xcd_grid(v.W, nstrip)), dim3(kFlushThreads), 0, s, v, spin);
+    if (v.ct && v.ub)
+        hipLaunchKernelGGL(k_flush_mfma_batch, dim3(xcd_grid(v.W, nstrip)), dim3(kBatchThreads), 0, s, v, spin);
     else
-        hipLaunchKernelGGL(k_flush_mfma<false>, dim3(xcd_grid(v.W, nstrip)), dim3(kFlushThreads), 0, s, v, spin);
+        hipLaunchKernelGGL(k_flush_mfma, dim3(xcd_grid(v.W, nstrip)), dim3(kFlushThreads), 0, s, v, spin);
 }
 
 }  // namespace cq

@@ -84,6 +84,7 @@ __global__ __launch_bounds__(512) void k_window(CrowdView<T> v, int e0, int nmov
     const uint32_t step = v.prm->step;
     const int rs = v.prm->rec_sweep;
     const double sigma = v.prm->sigma;
+    const bool recording = rs < v.prm->rec_cap, forcing = v.forced && rs < v.prm->forced_cap;
     const T* Mspin = v.M + ((size_t)w * 2 + spin) * n * (size_t)n;
     T* stage = v.stage + (size_t)w * v.QR * 5 * n;
     T* Cb = v.Cbuf + (size_t)w * K * n;
@@ -271,8 +272,8 @@ __global__ __launch_bounds__(512) void k_window(CrowdView<T> v, int e0, int nmov
             const double u = accept_uniform(v.seed, v.uid[w], step, (uint32_t)e);
             int acc = u < prob;
             const size_t ri = ((size_t)rs * v.ne + e) * v.W + w;
-            if (v.forced && rs < v.prm->forced_cap && v.forced[ri] < 2) acc = v.forced[ri] != 0;
-            if (lane == 0 && rs < v.prm->rec_cap) {
+            if (forcing && v.forced[ri] < 2) acc = v.forced[ri] != 0;
+            if (lane == 0 && recording) {
                 v.rec_rho[ri] = rho;
                 v.rec_dlnj[ri] = dlnj;
                 v.rec_prob[ri] = prob;
