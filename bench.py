@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-moves", type=int, default=512, help="moves per walker in the CPU baseline sample")
     ap.add_argument("--delay", type=int, default=None, help="override the delay rank")
+    ap.add_argument("--alone-steps", type=int, default=4,
+                    help="sweeps of a one-stream run that times the gather and the update alone (0: skip)")
     ap.add_argument("--eager", action="store_true", help="skip the extra hipGraph replay run")
     ap.add_argument("--path", default="auto", choices=["auto", "multi", "window", "batch"],
                     help="mapping of the moves to the GPU")
@@ -60,7 +62,7 @@ def make_system(cq, wl, elem_bytes):
 
 
 def run_gpu(cq, wl, precision, delay, recompute, steps, warmup, timing_kinds, use_graph, path="auto",
-            graph_steps=0):
+            graph_steps=0, streams=2):
     """Time `steps` sweeps over `wl.crowds` crowds (one stream each); returns a result dict.
 
     With timing_kinds, HIP events bracket every launch of those kernel kinds on each crowd's
@@ -71,7 +73,7 @@ def run_gpu(cq, wl, precision, delay, recompute, steps, warmup, timing_kinds, us
     crowds = []
     for ci in range(wl.crowds):
         c = cq.Crowd(system, wl.walkers, precision=precision, delay_rank=delay, recompute_every=recompute,
-                     seed=wl.seed, first_uid=ci * wl.walkers, use_graph=use_graph, path=path)
+                     seed=wl.seed, first_uid=ci * wl.walkers, use_graph=use_graph, path=path, streams=streams)
         c.set_positions(start_positions(wl.seed, wl.walkers, wl.n_e, wl.L, first_walker=ci * wl.walkers))
         crowds.append(c)
     log("  %s: %d crowd(s) x %d walkers set up" % (precision, wl.crowds, wl.walkers))
@@ -124,6 +126,34 @@ def run_gpu(cq, wl, precision, delay, recompute, steps, warmup, timing_kinds, us
     if graph_s is not None:
         out["graph_moves_per_s"] = wl.crowds * wl.walkers * wl.n_e * graph_steps / graph_s
     return out
+
+
+def rooflines(res, n, W, steps, traffic, s_c=4, s=4):
+    """(spline roofline, update roofline) from one run's HIP-event kernel times.
+
+    B-spline VGL of the round's proposals (k_prop_vgl): per proposal 64 stencil points x N
+    orbitals read from the table and the 5 rows written; one launch = the round's proposals.
+    Rank-k inverse update (k_flush_mfma_batch): per walker-spin window with r accepted moves it
+    reads and writes the N x N inverse once and does 4 N^2 r useful flops; r summed over the run."""
+    vgl_ms, vgl_n = res["kernels"]["vgl"]
+    props_per_launch = W * n * 2 * steps / max(vgl_n, 1)
+    vgl_bytes = props_per_launch * (64 * n * s_c + 5 * n * s)
+    vgl_t = vgl_ms / max(vgl_n, 1) * 1e-3
+    vgl_gbs = vgl_bytes / vgl_t / 1e9
+    up_ms, up_n = res["kernels"]["update"]
+    up_t = up_ms / max(up_n, 1) * 1e-3
+    r_per_launch = res["accepted_timed"] / max(up_n, 1)
+    up_flops = 4.0 * n * n * r_per_launch
+    up_bytes = W * 2 * n * n * s + 2 * r_per_launch * n * s
+    roof_vgl = dict(bound="hbm", achieved=round(vgl_gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(vgl_gbs / HBM_PEAK_GBS, 4), traffic=traffic, kernel="k_prop_vgl",
+                    us_per_launch=round(vgl_t * 1e6, 3), bytes_per_launch=int(vgl_bytes),
+                    proposals_per_launch=int(props_per_launch))
+    roof_up = dict(bound="mfma", achieved=round(up_flops / up_t / 1e12, 2), peak=FP32_PEAK_TFLOPS,
+                   unit="TFLOP/s", frac=round(up_flops / up_t / 1e12 / FP32_PEAK_TFLOPS, 4),
+                   hbm_gbs=round(up_bytes / up_t / 1e9, 1), kernel="k_flush_mfma_batch",
+                   us_per_launch=round(up_t * 1e6, 3), accepted_per_launch=round(r_per_launch, 2))
+    return roof_vgl, roof_up
 
 
 def kernel_source_hash():
@@ -266,7 +296,7 @@ def main():
     log("  mixed: %.3f s for %d sweeps, %.3e moves/s, acceptance %.3f"
         % (mixed["seconds"], args.steps, mixed["moves_per_s"], mixed["acceptance"]))
 
-    n, W, s_c, s = wl.n, wl.walkers * wl.crowds, 4, 4
+    n, W = wl.n, wl.walkers * wl.crowds
     kinfo = {}
     for k, (ms, cnt) in mixed["kernels"].items():
         kinfo[k] = dict(ms_total=round(ms, 3), launches=cnt, us_per_launch=round(1e3 * ms / max(cnt, 1), 3),
@@ -275,29 +305,9 @@ def main():
         delay = mixed["delay_rank"]
         log("  autotuned delay rank: %d" % delay)
     windows_per_sweep = 2 * ((n + delay - 1) // delay)
-    # B-spline VGL of the window's proposals (k_prop_vgl): per proposal 64 stencil points x N
-    # orbitals read from the table and the 5 rows written; one launch = W x k proposals
-    vgl_ms, vgl_n = mixed["kernels"]["vgl"]
-    props_per_launch = W * n * 2 * args.steps / max(vgl_n, 1)
-    vgl_bytes = props_per_launch * (64 * n * s_c + 5 * n * s)
-    vgl_t = vgl_ms / max(vgl_n, 1) * 1e-3
-    vgl_gbs = vgl_bytes / vgl_t / 1e9
-    # rank-k inverse update (k_flush): per walker-spin window with r accepted moves it reads and
-    # writes the N x N inverse once and does 4 N^2 r flops; r summed over the timed region
-    up_ms, up_n = mixed["kernels"]["update"]
-    up_t = up_ms / max(up_n, 1) * 1e-3
-    r_per_launch = mixed["accepted_timed"] / max(up_n, 1)
-    up_flops = 4.0 * n * n * r_per_launch
-    up_bytes = W * 2 * n * n * s + 2 * r_per_launch * n * s
     traffic = measured_traffic(wl.name)
-    roof_vgl = dict(bound="hbm", achieved=round(vgl_gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(vgl_gbs / HBM_PEAK_GBS, 4), traffic=traffic, kernel="k_prop_vgl",
-                    us_per_launch=round(vgl_t * 1e6, 3), bytes_per_launch=int(vgl_bytes),
-                    proposals_per_launch=int(props_per_launch))
-    roof_up = dict(bound="mfma", achieved=round(up_flops / up_t / 1e12, 2), peak=FP32_PEAK_TFLOPS,
-                   unit="TFLOP/s", frac=round(up_flops / up_t / 1e12 / FP32_PEAK_TFLOPS, 4),
-                   hbm_gbs=round(up_bytes / up_t / 1e9, 1), kernel="k_flush_mfma",
-                   us_per_launch=round(up_t * 1e6, 3), accepted_per_launch=round(r_per_launch, 2))
+    roof_vgl, roof_up = rooflines(mixed, n, W, args.steps, traffic)
+    vgl_ms, up_ms = mixed["kernels"]["vgl"][0], mixed["kernels"]["update"][0]
     dominant = roof_vgl if vgl_ms >= up_ms else roof_up
     out = dict(metric=METRIC, value=round(mixed["moves_per_s"], 1), unit="moves/s", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=round(1e3 * mixed["seconds"] / args.steps, 3),
@@ -314,6 +324,16 @@ def main():
                acceptance=round(mixed["acceptance"], 4), e_mean=mixed["e_mean"])
     if "graph_moves_per_s" in mixed:
         out["graph_moves_per_s"] = round(mixed["graph_moves_per_s"], 1)
+    if args.alone_steps > 0 and args.path in ("auto", "batch"):
+        # the same kernels with the GPU to themselves: one stream, every kernel in order
+        alone = run_gpu(cq, wl, "mixed", delay, wl.recompute_every, args.alone_steps, 1, ["vgl", "update"], False,
+                        path=args.path, streams=1)
+        a_vgl, a_up = rooflines(alone, n, W, args.alone_steps, None)
+        log("  alone: k_prop_vgl %.0f GB/s, update %.1f TFLOP/s" % (a_vgl["achieved"], a_up["achieved"]))
+        out["alone"] = dict(moves_per_s=round(alone["moves_per_s"], 1), steps=args.alone_steps,
+                            roofline_spline=a_vgl, roofline_update=a_up,
+                            note="one stream, no kernel beside another; context for the roofline above, "
+                                 "which is measured in the timed region where gather and update share the GPU")
     if args.fp64_steps > 0:
         f64 = run_gpu(cq, wl, "fp64", delay, 0, args.fp64_steps, 1, [], not args.eager, path=args.path)
         log("  fp64: %.3e moves/s" % f64["moves_per_s"])

@@ -71,7 +71,7 @@ def main():
                fetch_bytes_per_launch=fb, write_bytes_per_launch=wb, traffic_bytes_per_launch=fb + wb,
                source_sha256=kernel_source_hash(),
                command="rocprofv3 --pmc FETCH_SIZE|WRITE_SIZE --output-format csv -d DIR -o run -- "
-                       "python3 bench.py --steps 2 --warmup 1 --fp64-steps 0 --no-cpu --calibrate-copy; "
+                       "python3 bench.py --steps 2 --warmup 1 --fp64-steps 0 --no-cpu --alone-steps 0 --calibrate-copy; "
                        "python3 bench_traffic.py FETCH_DIR WRITE_DIR %s" % workload)
     print(json.dumps(rec, indent=1))
 

@@ -136,6 +136,9 @@ typedef struct {
     int kernel_path;      /* how the moves are mapped to the GPU (cq_kernel_path) */
     int max_walkers;      /* capacity for a DMC population (0: the initial walker count); the
                              per-walker buffers are sized for it */
+    int streams;          /* batched path: 2 (or 0) runs the next round's gather on a second
+                             stream beside the current round's decisions and update; 1 runs
+                             every kernel in order on one stream (each then has the GPU alone) */
 } cq_crowd_desc;
 
 /* Create a crowd of walkers_per_system[s] walkers of each system s.  This

@@ -37,7 +37,8 @@ class CqError(RuntimeError):
 class CrowdDesc(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("delay_rank", ctypes.c_int), ("recompute_every", ctypes.c_int),
                 ("seed", ctypes.c_uint64), ("first_uid", ctypes.c_uint32), ("hip_stream", ctypes.c_void_p),
-                ("use_graph", ctypes.c_int), ("kernel_path", ctypes.c_int), ("max_walkers", ctypes.c_int)]
+                ("use_graph", ctypes.c_int), ("kernel_path", ctypes.c_int), ("max_walkers", ctypes.c_int),
+                ("streams", ctypes.c_int)]
 
 
 _lib = None
@@ -175,14 +176,14 @@ class Crowd:
 
     def __init__(self, system: System, n_walkers: int, precision: str = "mixed", delay_rank: int = 1,
                  recompute_every: int = 0, seed: int = 0, first_uid: int = 0, stream=None,
-                 use_graph: bool = True, path: str = "auto", max_walkers: int = 0):
+                 use_graph: bool = True, path: str = "auto", max_walkers: int = 0, streams: int = 2):
         self.system = system
         self.W = n_walkers
         self._w0 = n_walkers
         self.n = system.n
         self.ne = 2 * system.n
         desc = CrowdDesc(CQ_MIXED if precision == "mixed" else CQ_FP64, delay_rank, recompute_every, seed,
-                         first_uid, _stream_handle(stream), int(use_graph), PATHS[path], max_walkers)
+                         first_uid, _stream_handle(stream), int(use_graph), PATHS[path], max_walkers, streams)
         systems = (ctypes.c_void_p * 1)(system._h.value)
         counts = (ctypes.c_int * 1)(n_walkers)
         h = ctypes.c_void_p()

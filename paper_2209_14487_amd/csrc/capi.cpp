@@ -261,7 +261,7 @@ void enqueue_sweep(cq_crowd* c)
             cq::launch_batch_stencils<T>(v, spin, r & 1, r == 0, st);
             timed_end(c, CQ_KERNEL_PROPOSE, st);
             timed_begin(c, CQ_KERNEL_VGL, st);
-            cq::launch_batch_vgl<T>(v, spin, r & 1, st);
+            cq::launch_batch_vgl<T>(v, spin, r & 1, c->stream2 != nullptr, st);
             timed_end(c, CQ_KERNEL_VGL, st);
         };
         auto jastrow = [&](int q, hipStream_t st) {
@@ -716,6 +716,7 @@ cq_status cq_crowd_create(const cq_system* const* systems, const int* walkers_pe
         return fail(CQ_EINVAL, "unknown kernel_path");
 
     if (desc->max_walkers < 0) return fail(CQ_EINVAL, "max_walkers must be >= 0");
+    if (desc->streams < 0 || desc->streams > 2) return fail(CQ_EINVAL, "streams must be 0, 1 or 2");
     cq_crowd* c = new (std::nothrow) cq_crowd();
     if (!c) return fail(CQ_ENOMEM, "host allocation failed");
     c->sys = s;
@@ -743,7 +744,7 @@ cq_status cq_crowd_create(const cq_system* const* systems, const int* walkers_pe
         }
         c->own_stream = true;
     }
-    if (c->path == CQ_PATH_BATCH) {
+    if (c->path == CQ_PATH_BATCH && desc->streams != 1) {
         // default priority, like the crowd's own stream
         if (hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking) == hipSuccess) {
             const int total = 2 * cq::batch_rounds(c->n, 1) + 2;  // enough for any delay rank

@@ -163,7 +163,7 @@ template <typename T> void launch_window(const CrowdView<T>& v, int e0, int nmov
 int window_threads(int n, int elem_bytes);
 template <typename T>
 void launch_batch_stencils(const CrowdView<T>& v, int spin, int par, bool block_start, hipStream_t s);
-template <typename T> void launch_batch_vgl(const CrowdView<T>& v, int spin, int par, hipStream_t s);
+template <typename T> void launch_batch_vgl(const CrowdView<T>& v, int spin, int par, bool beside, hipStream_t s);
 template <typename T> void launch_batch_jd(const CrowdView<T>& v, int spin, hipStream_t s);
 template <typename T> void launch_batch_pmat(const CrowdView<T>& v, int spin, hipStream_t s);
 template <typename T> void launch_batch_rows(const CrowdView<T>& v, int spin, hipStream_t s);

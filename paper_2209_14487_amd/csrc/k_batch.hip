@@ -404,9 +404,10 @@ struct DecideLds {
 // par: parity of the round within the spin block.  Besides the round's window the
 // kernel writes the gather range of round r+2: from the end of round r+1's range
 // to 2Q past round r+1's first candidate.
-// Gather workgroups per CU: the rest of each CU stays free for the kernels of the
-// round being decided and applied.
+// Gather workgroups per CU when it runs beside the round being decided and applied
+// (the rest of each CU stays free for those kernels), and when it runs alone.
 constexpr int kVglBlocksPerCU = 3;
+constexpr int kVglBlocksPerCUAlone = 8;
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_decide(CrowdView<T> v, int spin, int par)
@@ -741,11 +742,11 @@ int device_cu_count()
 }
 
 template <typename T>
-void launch_batch_vgl(const CrowdView<T>& v, int spin, int par, hipStream_t s)
+void launch_batch_vgl(const CrowdView<T>& v, int spin, int par, bool beside, hipStream_t s)
 {
     const int pp = batch_pp(v.n, sizeof(T));
     const int nchunk = (v.W * v.Q + pp - 1) / pp;
-    const int nb = std::min(nchunk, kVglBlocksPerCU * device_cu_count());
+    const int nb = std::min(nchunk, (beside ? kVglBlocksPerCU : kVglBlocksPerCUAlone) * device_cu_count());
     const size_t lds = (size_t)pp * (64 * sizeof(size_t) + 64 * 5 * sizeof(T)) + 4 * sizeof(int);
     hipLaunchKernelGGL(k_prop_vgl<T>, dim3(nb), dim3(batch_threads(v.n, sizeof(T))), lds, s, v, spin, pp, par);
 }
@@ -786,8 +787,8 @@ void launch_batch_decide(const CrowdView<T>& v, int spin, int par, hipStream_t s
 
 template void launch_batch_stencils<float>(const CrowdView<float>&, int, int, bool, hipStream_t);
 template void launch_batch_stencils<double>(const CrowdView<double>&, int, int, bool, hipStream_t);
-template void launch_batch_vgl<float>(const CrowdView<float>&, int, int, hipStream_t);
-template void launch_batch_vgl<double>(const CrowdView<double>&, int, int, hipStream_t);
+template void launch_batch_vgl<float>(const CrowdView<float>&, int, int, bool, hipStream_t);
+template void launch_batch_vgl<double>(const CrowdView<double>&, int, int, bool, hipStream_t);
 template void launch_batch_jd<float>(const CrowdView<float>&, int, hipStream_t);
 template void launch_batch_jd<double>(const CrowdView<double>&, int, hipStream_t);
 template void launch_batch_rows<float>(const CrowdView<float>&, int, hipStream_t);

@@ -330,6 +330,23 @@ def test_paths_agree():
         assert np.all(np.abs(a["eloc"] - b["eloc"]) <= 1e-10 * np.maximum(1.0, np.abs(b["eloc"])))
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("n,L,G,W,S", [(32, 10.0, 48, 16, 2), (256, 20.0, 64, 4, 1)])
+def test_one_stream_schedule_is_bit_identical(precision, n, L, G, W, S):
+    """The batched path computes the same chain bit for bit whether the next round's gather
+    and Jastrow sums run on a second stream beside the current round (default) or every kernel
+    runs in order on one stream."""
+    g, _ = make_pair(n, L, G, 1003, coef_seed=1003, fp64=precision == "fp64", fp32=precision == "mixed")
+    R0 = start_positions(1003, W, 2 * n, L)
+    res = []
+    for streams in (2, 1):
+        c = cq.Crowd(g, W, precision=precision, delay_rank=16, seed=1003, path="batch", streams=streams)
+        res.append(run_gpu(c, R0, S, 0.5))
+        c.close()
+    for key in ("rho", "dlnj", "prob", "acc", "logdet", "sign", "eloc", "R"):
+        assert np.array_equal(res[0][key], res[1][key]), key
+
+
 def test_autotuned_delay_rank_keeps_the_chain():
     """delay_rank = 0: the first run times sweeps at k = 1, 2, 4, ..., 32 and keeps the fastest;
     the tuning sweeps are ordinary sweeps, so the chain still matches the FP64 oracle."""
