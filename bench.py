@@ -134,7 +134,8 @@ def rooflines(res, n, W, steps, traffic, s_c=4, s=4):
     B-spline VGL of the round's proposals (k_prop_vgl): per proposal 64 stencil points x N
     orbitals read from the table and the 5 rows written; one launch = the round's proposals.
     Rank-k inverse update (k_flush_mfma_batch): per walker-spin window with r accepted moves it
-    reads and writes the N x N inverse once and does 4 N^2 r useful flops; r summed over the run."""
+    reads and writes the N x N inverse once and does 4 N^2 r useful flops; r summed over the run,
+    divided by all of its launches (rounds where no walker has a move left included)."""
     vgl_ms, vgl_n = res["kernels"]["vgl"]
     props_per_launch = W * n * 2 * steps / max(vgl_n, 1)
     vgl_bytes = props_per_launch * (64 * n * s_c + 5 * n * s)
@@ -144,14 +145,13 @@ def rooflines(res, n, W, steps, traffic, s_c=4, s=4):
     up_t = up_ms / max(up_n, 1) * 1e-3
     r_per_launch = res["accepted_timed"] / max(up_n, 1)
     up_flops = 4.0 * n * n * r_per_launch
-    up_bytes = W * 2 * n * n * s + 2 * r_per_launch * n * s
     roof_vgl = dict(bound="hbm", achieved=round(vgl_gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(vgl_gbs / HBM_PEAK_GBS, 4), traffic=traffic, kernel="k_prop_vgl",
                     us_per_launch=round(vgl_t * 1e6, 3), bytes_per_launch=int(vgl_bytes),
                     proposals_per_launch=int(props_per_launch))
     roof_up = dict(bound="mfma", achieved=round(up_flops / up_t / 1e12, 2), peak=FP32_PEAK_TFLOPS,
                    unit="TFLOP/s", frac=round(up_flops / up_t / 1e12 / FP32_PEAK_TFLOPS, 4),
-                   hbm_gbs=round(up_bytes / up_t / 1e9, 1), kernel="k_flush_mfma_batch",
+                   kernel="k_flush_mfma_batch",
                    us_per_launch=round(up_t * 1e6, 3), accepted_per_launch=round(r_per_launch, 2))
     return roof_vgl, roof_up
 
