@@ -820,7 +820,7 @@ cq_status cq_crowd_create(const cq_system* const* systems, const int* walkers_pe
         const int nmat = 2 * c->Wcap, b = cq::panel_width((int)n);
         void *S, *PR, *piv, *la, *ng;
         cq_status st = dev_alloc(c, &S, sizeof(double) * nmat * n * n);
-        if (st == CQ_OK) st = dev_alloc(c, &PR, sizeof(double) * nmat * b * n);
+        if (st == CQ_OK) st = dev_alloc(c, &PR, sizeof(double) * nmat * cq::block_width((int)n) * n);
         if (st == CQ_OK) st = dev_alloc(c, &piv, sizeof(int) * nmat * n * 2);
         if (st == CQ_OK) st = dev_alloc(c, &la, sizeof(double) * nmat * 2);  // log|det| and max|A| per matrix
         if (st == CQ_OK) st = dev_alloc(c, &ng, sizeof(int) * nmat * 2);

@@ -148,7 +148,7 @@ struct WalkerArrays {
 // FP64 Gauss-Jordan workspace for matrices too large for LDS.
 struct InvWork {
     double* S;        // [nmat][N][N]
-    double* PR;       // [nmat][b][N] pivot rows of the current panel (before the update)
+    double* PR;       // [nmat][B][N] pivot rows of the current block of B = 4b columns (before its update)
     int* pivrow;      // [nmat][N] pivot row of column k
     double* logabs;   // [nmat] log|det|, followed by [nmat] max|A_ij| (as 64-bit patterns)
     int* negs;        // [nmat] number of negative pivots
@@ -184,5 +184,6 @@ void launch_dmc_branch(const DmcView& d, const WalkerArrays<T>& src, const Walke
 void launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 size_t inverse_work_bytes(int nmat, int n);
 int panel_width(int n);  // columns per panel of the blocked inversion
+int block_width(int n);  // columns per block (4 panels) of the blocked inversion
 
 }  // namespace cq

@@ -13,11 +13,16 @@
 // not finite) marks the matrix numerically singular.
 //
 // n <= 64: one workgroup per matrix with the matrix in LDS (k_gj_small).
-// n  > 64: blocked.  A panel of b columns is swept by one workgroup per matrix
-// (k_gj_panel, panel in LDS); the same b sweeps act on every other column as the
-// rank-b update  S[i][j] = [i not a pivot of the panel] S[i][j]
-//                          + sum_q P[i][q] S_old[pi(k0+q)][j]
-// with P the swept panel (k_gj_update), 2 n^3 flops in all.
+// n  > 64: blocked on two levels.  A panel of b columns is swept by one workgroup
+// per matrix (k_gj_panel, panel in LDS); the same b sweeps act on every other
+// column as the rank-b update
+//     S[i][j] = [i not a pivot of the panel] S[i][j] + sum_q P[i][q] S_old[pi(k0+q)][j]
+// with P the swept panel.  A block of B = 4b columns is swept panel by panel,
+// each panel's update applied to the block's own columns only; the block's
+// columns then hold the multipliers of all its B sweeps, and one rank-B update
+// with the block's old pivot rows (k_gj_update<64>) brings every other column up
+// to date.  So the whole matrix is read and written n/B times, not n/b times;
+// 2 n^3 flops in all.
 #include "cq_device.h"
 #include "cq_internal.h"
 
@@ -177,12 +182,14 @@ __global__ __launch_bounds__(kBlock) void k_gj_load(CrowdView<T> v, double* __re
 // Sweep the b panel columns k0 .. k0+b-1 of every matrix (one workgroup per
 // matrix, panel and row-use flags in LDS), record the pivots, copy the old
 // pivot rows.
+// The old pivot rows go to rows pr0 .. pr0+b-1 of the matrix's pr_rows-row block
+// of PR.
 __global__ __launch_bounds__(kBlock) void k_gj_panel(double* __restrict__ S, double* __restrict__ PR,
                                                       int* __restrict__ pivrow, int* __restrict__ rowstate,
                                                       double* __restrict__ logabs, int* __restrict__ negs,
                                                       int* __restrict__ status,
                                                       const unsigned long long* __restrict__ scale, int n, int b,
-                                                      int k0, int panel)
+                                                      int k0, int panel, int pr_rows, int pr0)
 {
     extern __shared__ double sh[];
     double* P = sh;                    // [n][b]
@@ -196,9 +203,18 @@ __global__ __launch_bounds__(kBlock) void k_gj_panel(double* __restrict__ S, dou
     const int mat = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     double* Sm = S + (size_t)mat * n * n;
     int* rs = rowstate + (size_t)mat * n;
-    for (int idx = tid; idx < n * b; idx += kBlock) {
-        const int i = idx / b, q = idx % b;
-        P[idx] = Sm[(size_t)i * n + k0 + q];
+    for (int i0 = 0; i0 < n * b; i0 += 8 * kBlock) {  // 8 loads in flight per thread
+        double x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int idx = i0 + u * kBlock + tid;
+            x[u] = idx < n * b ? Sm[(size_t)(idx / b) * n + k0 + idx % b] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int idx = i0 + u * kBlock + tid;
+            if (idx < n * b) P[idx] = x[u];
+        }
     }
     for (int i = tid; i < n; i += kBlock) used[i] = rs[i];
     __syncthreads();
@@ -252,9 +268,18 @@ __global__ __launch_bounds__(kBlock) void k_gj_panel(double* __restrict__ S, dou
         __syncthreads();
     }
     // old pivot rows (all columns; the panel columns of PR are not used)
-    for (int q = 0; q < b; ++q) {
-        const int p = pivs[q];
-        for (int j = tid; j < n; j += kBlock) PR[((size_t)mat * b + q) * n + j] = Sm[(size_t)p * n + j];
+    for (int i0 = 0; i0 < n * b; i0 += 8 * kBlock) {  // 8 loads in flight per thread
+        double x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int idx = i0 + u * kBlock + tid;
+            x[u] = idx < n * b ? Sm[(size_t)pivs[idx / n] * n + idx % n] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int idx = i0 + u * kBlock + tid;
+            if (idx < n * b) PR[((size_t)mat * pr_rows + pr0 + idx / n) * n + idx % n] = x[u];
+        }
     }
     __syncthreads();
     for (int idx = tid; idx < n * b; idx += kBlock) {
@@ -270,59 +295,96 @@ __global__ __launch_bounds__(kBlock) void k_gj_panel(double* __restrict__ S, dou
     }
 }
 
-// Rank-b update of all non-panel columns: 64 x 64 output tile per workgroup.
+// Rank-b update (b <= BMAX) of the columns j in [jlo, jhi) outside [xlo, xhi), for
+// the column tiles jt0 .. jt0+njt-1: 64 x 64 output tile per workgroup (4 waves).  The
+// multipliers are S's columns k0 .. k0+b-1, the old pivot rows are rows pr0 ..
+// pr0+b-1 of PR's pr_rows-row block, and the pivot rows of the update are the
+// rows whose state lies in (plo, phi] (state = panel index + 1).
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <int BMAX>
 __global__ __launch_bounds__(kBlock) void k_gj_update(double* __restrict__ S, const double* __restrict__ PR,
                                                        const int* __restrict__ rowstate, int n, int b, int k0,
-                                                       int panel)
+                                                       int pr_rows, int pr0, int plo, int phi, int jt0, int njt,
+                                                       int jlo, int jhi, int xlo, int xhi)
 {
-    __shared__ double Pt[64][33];   // panel rows i0..i0+63, q < b (b <= 32)
-    __shared__ double Rt[32][65];   // pivot rows q < b, columns j0..j0+63
+    __shared__ double Pt[64][BMAX + 1];   // multiplier rows i0..i0+63, q < b
+    __shared__ double Rt[BMAX][65];       // old pivot rows q < b, columns j0..j0+63
     const int tiles = (n + 63) / 64;
-    const int mat = blockIdx.x / (tiles * tiles), t = blockIdx.x % (tiles * tiles);
-    const int i0 = (t / tiles) * 64, j0 = (t % tiles) * 64;
+    const int mat = blockIdx.x / (tiles * njt), t = blockIdx.x % (tiles * njt);
+    const int i0 = (t / njt) * 64, j0 = (jt0 + t % njt) * 64;
     double* Sm = S + (size_t)mat * n * n;
     const int* rs = rowstate + (size_t)mat * n;
     const int tid = threadIdx.x;
-    for (int idx = tid; idx < 64 * b; idx += kBlock) {
-        const int r = idx / b, q = idx % b;
-        Pt[r][q] = (i0 + r < n) ? Sm[(size_t)(i0 + r) * n + k0 + q] : 0.0;
-    }
-    for (int idx = tid; idx < b * 64; idx += kBlock) {
-        const int q = idx / 64, c = idx % 64;
-        Rt[q][c] = (j0 + c < n) ? PR[((size_t)mat * b + q) * n + j0 + c] : 0.0;
-    }
-    __syncthreads();
-    // thread owns a 4 x 4 block: rows i0 + ty*4 + a, columns j0 + tx + 16 c
-    const int ty = tid / 16, tx = tid % 16;
-    double acc[4][4];
+    {
+        // every load of the two operand tiles in flight before the LDS writes
+        constexpr int U = 64 * BMAX / kBlock;
+        double xp[U], xr[U];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+        for (int u = 0; u < U; ++u) {
+            const int idx = tid + u * kBlock;
+            const int r = idx / b, q = idx % b, qr = idx / 64, c = idx % 64;
+            xp[u] = (idx < 64 * b && i0 + r < n) ? Sm[(size_t)(i0 + r) * n + k0 + q] : 0.0;
+            xr[u] = (idx < 64 * b && j0 + c < n) ? PR[((size_t)mat * pr_rows + pr0 + qr) * n + j0 + c] : 0.0;
+        }
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[a][c] = 0.0;
-    for (int q = 0; q < b; ++q) {
-        double pa[4], rc[4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) pa[a] = Pt[ty * 4 + a][q];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) rc[c] = Rt[q][tx + 16 * c];
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int c = 0; c < 4; ++c) acc[a][c] += pa[a] * rc[c];
-    }
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        const int i = i0 + ty * 4 + a;
-        if (i >= n) continue;
-        const bool pivot_row = rs[i] == panel + 1;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int j = j0 + tx + 16 * c;
-            if (j >= n || (j >= k0 && j < k0 + b)) continue;
-            const size_t o = (size_t)i * n + j;
-            Sm[o] = (pivot_row ? 0.0 : Sm[o]) + acc[a][c];
+        for (int u = 0; u < U; ++u) {
+            const int idx = tid + u * kBlock;
+            if (idx < 64 * b) {
+                Pt[idx / b][idx % b] = xp[u];
+                Rt[idx / 64][idx % 64] = xr[u];
+            }
         }
     }
+    __syncthreads();
+    // FP64 matrix cores (v_mfma_f64_16x16x4f64): wave wv owns the 32 x 32 quarter
+    // (rows 32 (wv / 2), columns 32 (wv % 2)) as 2 x 2 blocks of 16 x 16.  Lane l
+    // supplies A[l % 16][l / 16] and B[l / 16][l % 16] of a step of 4 q values and
+    // holds D[l / 16 + 4 v][l % 16]; b is a multiple of 4.
+    const int lane = tid & 63, wv = tid >> 6;
+    const int r16 = lane & 15, q4 = lane >> 4;
+    const int wi = (wv >> 1) * 32, wj = (wv & 1) * 32;
+    f64x4 acc[2][2];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = f64x4{0.0, 0.0, 0.0, 0.0};
+    // the tile's old values, loaded before the products so that their latency is hidden
+    double old[2][2][4];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = i0 + wi + 16 * bi + q4 + 4 * v;
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj) {
+                const int j = j0 + wj + 16 * bj + r16;
+                const bool live = i < n && j < n && j >= jlo && j < jhi && !(j >= xlo && j < xhi);
+                old[bi][bj][v] = live ? Sm[(size_t)i * n + j] : 0.0;
+            }
+        }
+    for (int q0 = 0; q0 < b; q0 += 4) {
+        const double a0 = Pt[wi + r16][q0 + q4], a1 = Pt[wi + 16 + r16][q0 + q4];
+        const double b0 = Rt[q0 + q4][wj + r16], b1 = Rt[q0 + q4][wj + 16 + r16];
+        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = i0 + wi + 16 * bi + q4 + 4 * v;
+            if (i >= n) continue;
+            const bool pivot_row = rs[i] > plo && rs[i] <= phi;
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj) {
+                const int j = j0 + wj + 16 * bj + r16;
+                if (j >= n || j < jlo || j >= jhi || (j >= xlo && j < xhi)) continue;
+                Sm[(size_t)i * n + j] = (pivot_row ? 0.0 : old[bi][bj][v]) + acc[bi][bj][v];
+            }
+        }
 }
 
 // M[k][c] = S[pi(k)][pi^-1(c)], log|det|, sign, drift, status; one workgroup per matrix.
@@ -382,12 +444,13 @@ __global__ void k_gj_reset(int* rowstate, double* logabs, int* negs, int* mstatu
 }
 
 int panel_width(int n) { return n > 1024 ? 8 : 16; }
+int block_width(int n) { return 4 * panel_width(n); }
 
 size_t inverse_work_bytes(int nmat, int n)
 {
     if (n <= kSmallN) return 0;
-    const int b = panel_width(n);
-    return (size_t)nmat * n * n * sizeof(double) + (size_t)nmat * b * n * sizeof(double)
+    const int B = block_width(n);
+    return (size_t)nmat * n * n * sizeof(double) + (size_t)nmat * B * n * sizeof(double)
            + (size_t)nmat * n * sizeof(int) * 2 + (size_t)nmat * (sizeof(double) + 2 * sizeof(int)) + 4096;
 }
 
@@ -410,12 +473,26 @@ void launch_inverse(const CrowdView<T>& v, const InvWork& wk, hipStream_t s)
     const int bmax = panel_width(n);
     const size_t panel_lds = ((size_t)n * bmax + n) * sizeof(double) + (size_t)n * sizeof(int);
     (void)hipFuncSetAttribute((const void*)k_gj_panel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)panel_lds);
-    for (int k0 = 0, panel = 0; k0 < n; k0 += bmax, ++panel) {
-        const int b = min(bmax, n - k0);  // the last panel may be narrower
-        hipLaunchKernelGGL(k_gj_panel, dim3(nmat), dim3(kBlock), panel_lds, s, wk.S, wk.PR, wk.pivrow, rowstate,
-                           wk.logabs, wk.negs, mstatus, scale, n, b, k0, panel);
-        hipLaunchKernelGGL(k_gj_update, dim3(nmat * tiles * tiles), dim3(kBlock), 0, s, wk.S, wk.PR, rowstate, n, b,
-                           k0, panel);
+    const int B = block_width(n), per_block = B / bmax;
+    static_assert(kBlock == 256, "update tiles");
+    for (int K0 = 0, blk = 0; K0 < n; K0 += B, ++blk) {
+        const int Bw = min(B, n - K0);  // the last block may be narrower
+        const int plo = blk * per_block;
+        int np = 0;
+        for (int k0 = K0; k0 < K0 + Bw; k0 += bmax, ++np) {
+            const int b = min(bmax, K0 + Bw - k0), panel = plo + np;
+            hipLaunchKernelGGL(k_gj_panel, dim3(nmat), dim3(kBlock), panel_lds, s, wk.S, wk.PR, wk.pivrow, rowstate,
+                               wk.logabs, wk.negs, mstatus, scale, n, b, k0, panel, B, np * bmax);
+            if (Bw > b) {  // the panel's sweeps on the rest of the block
+                const int jt0 = K0 / 64, njt = (K0 + Bw - 1) / 64 - jt0 + 1;
+                hipLaunchKernelGGL(k_gj_update<32>, dim3(nmat * tiles * njt), dim3(kBlock), 0, s, wk.S, wk.PR,
+                                   rowstate, n, b, k0, B, np * bmax, panel, panel + 1, jt0, njt, K0, K0 + Bw, k0,
+                                   k0 + b);
+            }
+        }
+        if (n > Bw)  // the block's sweeps on every other column, as one rank-Bw update
+            hipLaunchKernelGGL(k_gj_update<64>, dim3(nmat * tiles * tiles), dim3(kBlock), 0, s, wk.S, wk.PR, rowstate,
+                               n, Bw, K0, B, 0, plo, plo + np, 0, tiles, 0, n, K0, K0 + Bw);
     }
     const size_t fin_lds = (size_t)n * sizeof(double) + (size_t)n * sizeof(int);
     hipLaunchKernelGGL(k_gj_finish<T>, dim3(nmat), dim3(kBlock), fin_lds, s, v, wk.S, wk.pivrow, rowstate, wk.logabs,
