@@ -174,11 +174,41 @@ void launch_flush(const CrowdView<T>& v, int spin, hipStream_t s, bool linv_read
         hipLaunchKernelGGL((k_flush_vec<T, 32>), grid, block, 0, s, v, spin);
 }
 
-// One wave per (walker, electron): this electron's contribution to sum_i [...]
+// One wave per (walker, electron): this electron's contribution to sum_i [...].
+// The determinant part streams the electron's inverse row and its gradient and
+// Laplacian rows (four iterations of loads in flight per lane).  The Jastrow part
+// sums the Pade pair terms over the other electrons: coordinate differences in
+// FP64, each term in the precision of the path (FP32 in mixed precision, like
+// the ratios), the sums in FP64.
+template <typename T>
+__device__ __forceinline__ void j2_energy_terms(T a, T b, T L, T iL, const double* re, const double* rm, T& gx,
+                                                T& gy, T& gz, T& lap)
+{
+    T d[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        T x = (T)(re[c] - rm[c]);
+        if constexpr (sizeof(T) == 8)
+            x -= L * rint(x / L);
+        else
+            x -= L * rintf(x * iL);
+        d[c] = x;
+    }
+    const T r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    const T iq = (T)1 / ((T)1 + b * r);
+    const T du = a * iq * iq, d2u = (T)-2 * a * b * iq * iq * iq;
+    const T f = du / r;
+    gx = f * d[0];
+    gy = f * d[1];
+    gz = f * d[2];
+    lap = d2u + (T)2 * f;
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_energy_rows(CrowdView<T> v)
 {
     constexpr int VEC = 16 / sizeof(T);
+    constexpr int UNR = 4;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const long long gw = (long long)blockIdx.x * 4 + wave;
     if (gw >= (long long)v.W * v.ne) return;
@@ -187,15 +217,30 @@ __global__ __launch_bounds__(kBlock) void k_energy_rows(CrowdView<T> v)
     const T* mrow = v.M + (((size_t)w * 2 + spin) * n + a) * (size_t)n;
     const T* vg = v.VGL + (((size_t)w * 2 + spin) * n + a) * 5 * (size_t)n;
     T s[4] = {(T)0, (T)0, (T)0, (T)0};
-    for (int j = lane * VEC; j < n; j += 64 * VEC) {
-        T m[VEC], x[VEC];
-        load16(mrow + j, m);
+    for (int j0 = lane * VEC; j0 < n; j0 += UNR * 64 * VEC) {
+        T m[UNR][VEC], x[UNR][4][VEC];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            load16(vg + (size_t)(k + 1) * n + j, x);
+        for (int u = 0; u < UNR; ++u) {
+            const int j = j0 + u * 64 * VEC;
+            if (j < n) {
+                load16(mrow + j, m[u]);
 #pragma unroll
-            for (int i = 0; i < VEC; ++i) s[k] += x[i] * m[i];
+                for (int k = 0; k < 4; ++k) load16(vg + (size_t)(k + 1) * n + j, x[u][k]);
+            } else {
+#pragma unroll
+                for (int i = 0; i < VEC; ++i) {
+                    m[u][i] = (T)0;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) x[u][k][i] = (T)0;
+                }
+            }
         }
+#pragma unroll
+        for (int u = 0; u < UNR; ++u)
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+#pragma unroll
+                for (int i = 0; i < VEC; ++i) s[k] += x[u][k][i] * m[u][i];
     }
     double g[3], l;
 #pragma unroll
@@ -203,19 +248,19 @@ __global__ __launch_bounds__(kBlock) void k_energy_rows(CrowdView<T> v)
     l = (double)wave_sum(s[3]);
     double gu[3] = {0.0, 0.0, 0.0}, lu = 0.0;
     if (v.use_j2) {
-        const double* re = v.R + ((size_t)w * v.ne + e) * 3;
+        const double* Rw = v.R + (size_t)w * v.ne * 3;
+        const double re[3] = {Rw[(size_t)e * 3], Rw[(size_t)e * 3 + 1], Rw[(size_t)e * 3 + 2]};
+        const T L = (T)v.L, iL = (T)(1.0 / v.L), b = (T)v.b;
+        const T a_same = (T)v.a_par, a_other = (T)v.a_anti;
         for (int m = lane; m < v.ne; m += 64) {
-            if (m == e) continue;
-            const double aa = ((m >= n) == (spin != 0)) ? v.a_par : v.a_anti;
-            double d[3], u, du, d2u;
-            min_image(re, v.R + ((size_t)w * v.ne + m) * 3, v.L, d);
-            const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-            pade(aa, v.b, r, u, du, d2u);
-            const double f = du / r;
-            gu[0] += f * d[0];
-            gu[1] += f * d[1];
-            gu[2] += f * d[2];
-            lu += d2u + 2.0 * f;
+            const T aa = ((m >= n) == (spin != 0)) ? a_same : a_other;
+            T gx, gy, gz, lp;
+            j2_energy_terms<T>(aa, b, L, iL, re, Rw + (size_t)m * 3, gx, gy, gz, lp);
+            const bool self = m == e;  // the electron's own pair term is not a term
+            gu[0] += self ? 0.0 : (double)gx;
+            gu[1] += self ? 0.0 : (double)gy;
+            gu[2] += self ? 0.0 : (double)gz;
+            lu += self ? 0.0 : (double)lp;
         }
 #pragma unroll
         for (int k = 0; k < 3; ++k) gu[k] = wave_sum(gu[k]);
