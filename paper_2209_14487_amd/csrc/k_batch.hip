@@ -633,8 +633,15 @@ __global__ __launch_bounds__(kBlock) void k_cols(CrowdView<T> v, int spin)
     if (l >= n) return;
     if constexpr (sizeof(T) == 4) {
         if (v.ub)
-            for (int a = 0; a < cnt; ++a)
-                v.ub[((size_t)w * D + a) * n + l] = v.stage[((size_t)w * v.QR + s_slot[a]) * 5 * (size_t)n + l];
+            for (int a0 = 0; a0 < cnt; a0 += 8) {  // 8 loads in flight per thread
+                T x[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    x[q] = a0 + q < cnt ? v.stage[((size_t)w * v.QR + s_slot[a0 + q]) * 5 * (size_t)n + l] : (T)0;
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    if (a0 + q < cnt) v.ub[((size_t)w * D + a0 + q) * n + l] = x[q];
+            }
     }
     const T* Mw = v.M + ((size_t)w * 2 + spin) * n * (size_t)n + l;
     double acc[D];
@@ -682,16 +689,27 @@ __global__ __launch_bounds__(kBlock) void k_rows(CrowdView<T> v, int spin)
     int cnt = v.cnt[(size_t)2 * v.W + w];
     if (cnt > K) cnt = K;
     if (l >= n) return;
-    for (int a = 0; a < cnt; ++a) {
-        const int e = v.welec[(size_t)w * K + a], sl = v.wslot[(size_t)w * K + a];
-        if (e < 0 || e >= n || sl < 0 || sl >= v.QR) continue;  // reported by the column kernel
-        const T* src = v.stage + ((size_t)w * v.QR + sl) * 5 * (size_t)n + l;
-        T* dst = v.VGL + (((size_t)w * 2 + spin) * n + e) * 5 * (size_t)n + l;
-        T x[5];
+    for (int a0 = 0; a0 < cnt; a0 += 4) {  // 4 accepted rows (20 loads) in flight per thread
+        T x[4][5];
+        int e[4];
+        bool ok[4];
 #pragma unroll
-        for (int p = 0; p < 5; ++p) x[p] = src[(size_t)p * n];
+        for (int q = 0; q < 4; ++q) {
+            const int a = a0 + q;
+            e[q] = a < cnt ? v.welec[(size_t)w * K + a] : -1;
+            const int sl = a < cnt ? v.wslot[(size_t)w * K + a] : -1;
+            ok[q] = e[q] >= 0 && e[q] < n && sl >= 0 && sl < v.QR;  // bad entries: reported by the column kernel
+            const T* src = v.stage + ((size_t)w * v.QR + (ok[q] ? sl : 0)) * 5 * (size_t)n + l;
 #pragma unroll
-        for (int p = 0; p < 5; ++p) dst[(size_t)p * n] = x[p];
+            for (int p = 0; p < 5; ++p) x[q][p] = ok[q] ? src[(size_t)p * n] : (T)0;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (!ok[q]) continue;
+            T* dst = v.VGL + (((size_t)w * 2 + spin) * n + e[q]) * 5 * (size_t)n + l;
+#pragma unroll
+            for (int p = 0; p < 5; ++p) dst[(size_t)p * n] = x[q][p];
+        }
     }
 }
 
