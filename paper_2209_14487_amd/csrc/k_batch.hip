@@ -391,11 +391,11 @@ struct DecideLds {
     static constexpr int QM = kMaxCand, D = kMaxDelay;
     double P[QM][QM + 1];
     double PC[QM * (QM - 1) / 2];  // Jastrow change of candidate m when s (< m) moves, at m(m-1)/2 + s
-    double T[D][D + 1];
-    double X[D][QM + 1];
-    double Li[D][D + 1];
+    double X[D][QM + 1];           // X[a][i] = u_i . c_a: candidate i against accepted move a
+    double B[D][QM + 1];           // B[a][i] = beta_a(i), component a of L^-1 y(i)
     double u[QM], jd[QM];
     double rho[QM], dj[QM];        // running Schur complement and Jastrow sum of each candidate
+    double racc[D];                // Schur complements of the accepted moves
     double rold[QM][3], rnew[QM][3];
     int slot[D];
     int cnt, ndec;
@@ -465,7 +465,12 @@ __global__ __launch_bounds__(kBlock) void k_decide(CrowdView<T> v, int spin, int
         }
     }
     __syncthreads();
-    for (int idx = tid; idx < kMaxDelay * (kMaxDelay + 1); idx += kBlock) (&S.Li[0][0])[idx] = 0.0;
+    // rows of X and B start at zero: the sums over accepted moves below run over whole
+    // groups of 8 rows, and the rows past the accepted count must contribute nothing
+    for (int idx = tid; idx < DecideLds::D * (DecideLds::QM + 1); idx += kBlock) {
+        (&S.X[0][0])[idx] = 0.0;
+        (&S.B[0][0])[idx] = 0.0;
+    }
     if (tid < nc) {
         S.rho[tid] = S.P[tid][tid];
         S.dj[tid] = S.jd[tid];
@@ -478,97 +483,97 @@ __global__ __launch_bounds__(kBlock) void k_decide(CrowdView<T> v, int spin, int
     }
     __syncthreads();
 
-    // decisions in electron order (wave 0).  Candidate m's ratio and Jastrow sum are
-    // read from rho[m] and dj[m], which every acceptance brings up to date for all later
-    // candidates at once (lane i <-> candidate i):
-    //     rho_i -= beta_a(i) x_a(i),  dj_i += PC(i, m_a),
-    // with beta(i) = L^-1 y(i), y_j(i) = P[s_j][i], for the new accepted move a; so a
-    // rejection costs O(1) and an acceptance O(accepted) per lane.  On acceptance
-    // (lane a <-> accepted move a): beta(m), the new rows of G, L^-1, T and X.
+    // Decisions in electron order (wave 0, lane <-> candidate).  Candidate i's ratio
+    // and Jastrow sum are rho_i and dj_i, brought up to date by every acceptance of an
+    // earlier candidate m (the a-th accepted move) for all later candidates at once:
+    //     X[a][i] = P[i][m] - sum_{b<a} beta_b(m) X[b][i]
+    //     B[a][i] = (P[m][i] - sum_{t<a} X[t][m] B[t][i]) / rho_m
+    //     rho_i  -= B[a][i] X[a][i],    dj_i += PC(i, m).
+    // Every candidate past the last acceptance is then tested at once (lanes), and a
+    // ballot gives the next acceptance: the candidates before it are rejected with the
+    // ratios they had, since nothing changed them in between.  A rejection costs no
+    // serial step, an acceptance one pass of O(accepted) per lane.
     if (wave == 0) {
-        double ld = v.logdet[w * 2 + spin];
-        int sg = v.sign[w * 2 + spin];
-        int cnt = 0, m = 0;
-        for (; m < nc && cnt < K; ++m) {
-            const double rho = S.rho[m];
-            const double dlnj = S.dj[m];
-            const double prob = rho * rho * exp(2.0 * dlnj);
-            int acc = S.u[m] < prob;
-            const size_t ri = ((size_t)rs * v.ne + e0 + m) * v.W + w;
-            if (forcing && v.forced[ri] < 2) acc = v.forced[ri] != 0;
-            if (lane == 0 && recording) {
-                v.rec_rho[ri] = rho;
-                v.rec_dlnj[ri] = dlnj;
-                v.rec_prob[ri] = prob;
-                v.rec_acc[ri] = (uint8_t)acc;
-            }
-            if (acc) {
-                const bool mine = lane < cnt;
-                const int sa = mine ? S.slot[lane] : 0;
-                const double y = mine ? S.P[sa][m] : 0.0;
-                const double x = mine ? S.X[lane][m] : 0.0;
-                // beta_a = sum_{j<=a} Li[a][j] y_j  (Li is zero above the diagonal)
-                const int arow = mine ? lane : 0;
-                double beta = 0.0;
-#pragma unroll 8
-                for (int j = 0; j < cnt; ++j) beta += S.Li[arow][j] * dpp::lane(y, j);
-                if (!mine) beta = 0.0;
-                const double rinv = 1.0 / rho;
-                if (mine) v.wG[((size_t)w * K + cnt) * K + lane] = x;  // G[cnt][a] = u_m . c_a
-                // new row of L^-1: Li[cnt][j] = -sum_{t=j}^{cnt-1} x_t Li[t][j] / rho  (lane j)
-                const int lcol = lane < kMaxDelay ? lane : 0;
-                double li = 0.0;
-#pragma unroll 8
-                for (int t = 0; t < cnt; ++t) li += dpp::lane(x, t) * S.Li[t][lcol];
-                if (mine) S.Li[cnt][lane] = -li * rinv;
-                if (lane == cnt) S.Li[cnt][cnt] = rinv;
-                // new row of T (accepted basis): T[cnt][j] = -sum_{a>=j} beta_a T[a][j] for
-                // j < cnt, T[cnt][cnt] = 1   (lane j; T is zero above the diagonal)
-                {
-                    const int jc = lane < kMaxDelay ? lane : 0;
-                    double tc = 0.0;
-#pragma unroll 8
-                    for (int aa = 0; aa < cnt; ++aa) tc -= dpp::lane(beta, aa) * S.T[aa][jc];
-                    if (mine) S.T[cnt][lane] = tc;
-                    if (lane == cnt) S.T[cnt][cnt] = 1.0;
-                    if (lane > cnt && lane < kMaxDelay) S.T[cnt][lane] = 0.0;
-                    if (lane == 0) S.slot[cnt] = m;
-                }
-                // the accepted candidates' slots in a register: lane j holds s_j
-                const int myslot = lane < cnt ? S.slot[lane] : (lane == cnt ? m : 0);
-                // new row of X and of beta for every candidate, and the running updates:
-                //     X[cnt][i]  = sum_{j<=cnt} T[cnt][j]  P[i][s_j]
-                //     beta_cnt(i) = sum_{j<=cnt} Li[cnt][j] P[s_j][i]
-                for (int base = 0; base < DecideLds::QM; base += 64) {
-                    const int i = base + lane, ic = i < DecideLds::QM ? i : DecideLds::QM - 1;
-                    double xc = 0.0, bc = 0.0;
-#pragma unroll 8
-                    for (int j = 0; j <= cnt; ++j) {
-                        const int sj = __builtin_amdgcn_readlane(myslot, j);
-                        xc += S.T[cnt][j] * S.P[ic][sj];
-                        bc += S.Li[cnt][j] * S.P[sj][ic];
+        int cnt = 0, first = 0, macc = -1, ndec = 0;
+        double xa = 0.0, ba = 0.0, rinv = 0.0;  // lane a: X[a][m], beta_a(m) of the last acceptance m
+        for (;;) {
+            const bool deciding = cnt < K;
+            bool found = false;
+            int next = nc;
+            double rnext = 0.0;
+            for (int base = first; base < nc; base += 64) {
+                const int i = base + lane;
+                const bool valid = i < nc;
+                const int ic = valid ? i : first;
+                double r = S.rho[ic], d = S.dj[ic];
+                if (macc >= 0) {  // row cnt-1 of X and B, for the acceptance of candidate macc
+                    const int row = cnt - 1;
+                    double xc = S.P[ic][macc], bc = S.P[macc][ic];
+                    for (int a0 = 0; a0 < row; a0 += 8) {
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) {  // rows past row are zero, so are their coefficients
+                            xc -= dpp::lane(ba, a0 + q) * S.X[a0 + q][ic];
+                            bc -= dpp::lane(xa, a0 + q) * S.B[a0 + q][ic];
+                        }
                     }
-                    if (i < DecideLds::QM) S.X[cnt][i] = xc;
-                    if (i > m && i < nc) {
-                        S.rho[i] -= bc * xc;
-                        S.dj[i] += S.PC[i * (i - 1) / 2 + m];
+                    bc *= rinv;
+                    r -= bc * xc;
+                    d += S.PC[ic * (ic - 1) / 2 + macc];
+                    if (valid) {
+                        S.X[row][i] = xc;
+                        S.B[row][i] = bc;
+                        S.rho[i] = r;
+                        S.dj[i] = d;
                     }
                 }
-                if (lane == 0) {
-                    v.wrho[(size_t)w * K + cnt] = rho;
+                if (deciding && !found) {
+                    const double prob = r * r * exp(2.0 * d);
+                    int acc = S.u[ic] < prob;
+                    const size_t ri = ((size_t)rs * v.ne + e0 + ic) * v.W + w;
+                    if (forcing && v.forced[ri] < 2) acc = v.forced[ri] != 0;
+                    const uint64_t hit = __builtin_amdgcn_ballot_w64(valid && acc);
+                    const int lim = hit ? base + __builtin_ctzll(hit) : nc;  // candidates decided here: i <= lim
+                    if (recording && valid && i <= lim) {
+                        v.rec_rho[ri] = r;
+                        v.rec_dlnj[ri] = d;
+                        v.rec_prob[ri] = prob;
+                        v.rec_acc[ri] = (uint8_t)acc;
+                    }
+                    if (hit) {
+                        found = true;
+                        next = lim;
+                        rnext = dpp::lane(r, __builtin_ctzll(hit));
+                    }
                 }
-                ld += log(fabs(rho));
-                if (rho < 0.0) sg = -sg;
-                ++cnt;
             }
+            if (!deciding) {  // the update pass of the last acceptance the window holds
+                ndec = first;
+                break;
+            }
+            if (!found) {  // the rest rejected
+                ndec = nc;
+                break;
+            }
+            // acceptance of candidate next: its coefficients against the earlier accepted
+            // moves, read after this wave's stores of the pass above
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            xa = lane < cnt ? S.X[lane][next] : 0.0;
+            ba = lane < cnt ? S.B[lane][next] : 0.0;
+            if (lane == 0) {
+                S.racc[cnt] = rnext;
+                S.slot[cnt] = next;
+            }
+            rinv = 1.0 / rnext;
+            macc = next;
+            first = next + 1;
+            ++cnt;
         }
         if (lane == 0) {
-            v.logdet[w * 2 + spin] = ld;
-            v.sign[w * 2 + spin] = sg;
             v.nacc[w] += cnt;
-            v.nprop[w] += m;
+            v.nprop[w] += ndec;
             S.cnt = cnt;
-            S.ndec = m;
+            S.ndec = ndec;
         }
     }
     __syncthreads();
@@ -581,13 +586,50 @@ __global__ __launch_bounds__(kBlock) void k_decide(CrowdView<T> v, int spin, int
         v.wslot[(size_t)w * K + tid] = a % v.QR;
         for (int k = 0; k < 3; ++k) v.R[((size_t)w * v.ne + spin * n + a) * 3 + k] = S.rnew[S.slot[tid]][k];
     }
-    for (int idx = tid; idx < cnt * cnt; idx += kBlock) {
-        const int i = idx / cnt, j = idx % cnt;
-        v.tmat[((size_t)w * K + i) * K + j] = S.T[i][j];
-    }
-    for (int idx = tid; idx < cnt * cnt; idx += kBlock) {
-        const int i = idx / cnt, j = idx % cnt;
-        v.wlinv[((size_t)w * K + i) * K + j] = S.Li[i][j];
+    if (wave < 2) {
+        // L^-1 (wave 0) and T (wave 1) of the window by forward substitution, column j
+        // in lane j:  L[c][t] = X[t][s_c] (t < c), L[c][c] = rho_c, so that
+        //     Linv[c][j] = (delta_cj - sum_{t<c} L[c][t] Linv[t][j]) / rho_c;
+        // T inverts the unit lower triangle U[c][a] = beta_a(s_c) = B[a][s_c] (a < c).
+        const bool lower = wave == 0;
+        const double rv = lower && lane < cnt ? 1.0 / S.racc[lane] : 1.0;
+        double col[kMaxDelay];
+#pragma unroll
+        for (int c = 0; c < kMaxDelay; ++c) {
+            col[c] = 0.0;
+            if (c < cnt) {
+                const int sc = S.slot[c];
+                double sum = 0.0;
+#pragma unroll
+                for (int t = 0; t < c; ++t) sum += (lower ? S.X[t][sc] : S.B[t][sc]) * col[t];
+                col[c] = ((c == lane ? 1.0 : 0.0) - sum) * dpp::lane(rv, c);
+            }
+        }
+        double* out = (lower ? v.wlinv : v.tmat) + (size_t)w * K * K;
+        if (lane < cnt)
+#pragma unroll
+            for (int c = 0; c < kMaxDelay; ++c)
+                if (c < cnt) out[(size_t)c * K + lane] = col[c];
+    } else if (wave == 2) {  // G[c][a] = u_{s_c} . c_a (a < c) and the ratios of the window
+        for (int idx = lane; idx < cnt * cnt; idx += 64) {
+            const int c = idx / cnt, a = idx % cnt;
+            if (a < c) v.wG[((size_t)w * K + c) * K + a] = S.X[a][S.slot[c]];
+        }
+        if (lane < cnt) v.wrho[(size_t)w * K + lane] = S.racc[lane];
+    } else {  // log |det| and sign, summed in acceptance order
+        const double rc = lane < cnt ? S.racc[lane] : 1.0;
+        const double lg = log(fabs(rc));
+        const uint64_t neg = __builtin_amdgcn_ballot_w64(rc < 0.0);
+        // the lane reads run in every lane: inside a one-lane branch the compiler may
+        // move the computation of lg there too, and the other lanes would not hold it
+        double ld = v.logdet[w * 2 + spin];
+#pragma unroll
+        for (int c = 0; c < kMaxDelay; ++c)
+            if (c < cnt) ld += dpp::lane(lg, c);
+        if (lane == 0) {
+            v.logdet[w * 2 + spin] = ld;
+            if (__builtin_popcountll(neg) & 1) v.sign[w * 2 + spin] = -v.sign[w * 2 + spin];
+        }
     }
     if (tid == 0) {
         v.cnt[(size_t)2 * v.W + w] = cnt;
