@@ -326,7 +326,9 @@ __global__ __launch_bounds__(kBlock) void k_pmat(CrowdView<T> v, int spin)
     __shared__ double sP[4][kPB][kPB + 1];
     const int Q = v.Q, n = v.n;
     const int nb = (Q + kPB - 1) / kPB;
-    const int w = blockIdx.x / (nb * nb), blk = blockIdx.x % (nb * nb);
+    int w, blk;  // a walker's tiles share one XCD, so its rows are fetched into one L2
+    xcd_map(blockIdx.x, nb * nb, w, blk);
+    if (w >= v.W) return;
     const int bi = blk / nb, bj = blk % nb;
     const int dec = v.cur[2 * w];
     const int nc = (dec + Q < n ? dec + Q : n) - dec;
@@ -441,18 +443,28 @@ __global__ __launch_bounds__(kBlock) void k_decide(CrowdView<T> v, int spin, int
         return;
     }
     // candidates: P, uniforms, Jastrow sums, positions
+    // P (nc x nc, row stride Q): wave v loads rows 22v..22v+21 with the lanes along
+    // the columns, all rows of a column batch in flight together
     const double* Pw = v.pmat + (size_t)w * Q * Q;
-    for (int i0 = 0; i0 < nc * nc; i0 += 8 * kBlock) {  // 8 independent loads in flight per thread
-        double x[8];
+    {
+        constexpr int RPW = DecideLds::QM / 4;
+        static_assert(DecideLds::QM % 4 == 0 && DecideLds::QM <= 128 && kBlock == 256, "P rows per wave");
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int idx = i0 + q * kBlock + tid, ic = idx < nc * nc ? idx : 0;
-            x[q] = Pw[(size_t)(ic / nc) * Q + ic % nc];
-        }
+        for (int half = 0; half < 2; ++half) {
+            const int j = lane + 64 * half;
+            if (j < nc) {
+                double x[RPW];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int idx = i0 + q * kBlock + tid;
-            if (idx < nc * nc) S.P[idx / nc][idx % nc] = x[q];
+                for (int r = 0; r < RPW; ++r) {
+                    const int i = wave * RPW + r;
+                    x[r] = i < nc ? Pw[(size_t)i * Q + j] : 0.0;
+                }
+#pragma unroll
+                for (int r = 0; r < RPW; ++r) {
+                    const int i = wave * RPW + r;
+                    if (i < nc) S.P[i][j] = x[r];
+                }
+            }
         }
     }
     if (tid < nc) {
@@ -644,77 +656,124 @@ __global__ __launch_bounds__(kBlock) void k_decide(CrowdView<T> v, int spin, int
 
 // Columns of the accepted moves: c_a = sum_{j<=a} T[a][j] c0_{s_j} for a < cnt,
 // c0_{s_j} the start column of the j-th accepted move's electron (FP64 sums of
-// exact products, rounded to T).  One thread per orbital; the loads of 8
-// columns are issued together.  For the matrix-core update the kernel also packs
-// the accepted value rows (ub), so that the update kernel's loads need no
-// indirection.
+// exact products, rounded to T).  One thread per orbital.  For the matrix-core
+// update the kernel also packs the accepted value rows (ub), so that the update
+// kernel's loads need no indirection.  The kernel sits between the decisions and
+// the update while the gather of the next round streams beside it, so every
+// global round trip is long: the count, T and the window are loaded in one batch,
+// then all accepted rows at once.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_cols(CrowdView<T> v, int spin)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_cols(CrowdView<T> v, int spin)
 {
-    constexpr int D = kMaxDelay;
-    __shared__ double s_T[D][D + 1];
-    __shared__ int s_row[D], s_slot[D];
+    constexpr int D = kMaxDelay, TL = D * D / kBlock;
+    static_assert(D * D % kBlock == 0, "T tile per thread");
+    __shared__ __align__(16) double s_T[D][D];
+    __shared__ __align__(16) int s_row[D];
+    __shared__ __align__(16) int s_slot[D];
     const int n = v.n, K = v.K;
     const int nlb = (n + kBlock - 1) / kBlock;
-    const int w = blockIdx.x / nlb, l = (blockIdx.x % nlb) * kBlock + threadIdx.x;
+    int w, part;  // a walker's blocks share one XCD
+    xcd_map(blockIdx.x, nlb, w, part);
+    if (w >= v.W) return;
+    const int tid = threadIdx.x, l = part * kBlock + tid;
+    // first batch: the count, T (K x K) and the window's electrons and slots; what
+    // lies past the count is replaced once the loads are back (T by zeros, so the
+    // sums below need no bounds)
     const int cnt = v.cnt[(size_t)2 * v.W + w];
-    if (cnt <= 0 || cnt > K) return;
-    // T padded with zeros (rows and columns >= cnt): no branches in the sums
-    for (int idx = threadIdx.x; idx < D * D; idx += kBlock) {
-        const int a = idx / D, j = idx % D;
-        s_T[a][j] = (a < cnt && j < cnt) ? v.tmat[((size_t)w * K + a) * K + j] : 0.0;
+    double tv[TL];
+#pragma unroll
+    for (int q = 0; q < TL; ++q) {
+        const int idx = q * kBlock + tid, a = idx / D, j = idx % D;
+        tv[q] = a < K && j < K ? v.tmat[((size_t)w * K + a) * K + j] : 0.0;
     }
-    if (threadIdx.x < D) {
-        const int e = threadIdx.x < cnt ? v.welec[(size_t)w * K + threadIdx.x] : 0;
-        const int sl = threadIdx.x < cnt ? v.wslot[(size_t)w * K + threadIdx.x] : 0;
-        if (e < 0 || e >= n || sl < 0 || sl >= v.QR) atomicOr(&v.status[w], 2);
-        s_row[threadIdx.x] = e >= 0 && e < n ? e : 0;
-        s_slot[threadIdx.x] = sl >= 0 && sl < v.QR ? sl : 0;
+    int e = 0, sl = 0;
+    if (tid < K) {
+        e = v.welec[(size_t)w * K + tid];
+        sl = v.wslot[(size_t)w * K + tid];
+    }
+    if (cnt <= 0 || cnt > K) return;
+#pragma unroll
+    for (int q = 0; q < TL; ++q) {
+        const int idx = q * kBlock + tid, a = idx / D, j = idx % D;
+        s_T[j][a] = a < cnt && j < cnt ? tv[q] : 0.0;  // transposed: s_T[j][a] = T[a][j]
+    }
+    if (tid < D) {
+        if (tid < cnt && (e < 0 || e >= n || sl < 0 || sl >= v.QR)) atomicOr(&v.status[w], 2);
+        s_row[tid] = tid < cnt && e >= 0 && e < n ? e : 0;
+        s_slot[tid] = tid < cnt && sl >= 0 && sl < v.QR ? sl : 0;
     }
     __syncthreads();
     if (l >= n) return;
-    if constexpr (sizeof(T) == 4) {
-        if (v.ub)
-            for (int a0 = 0; a0 < cnt; a0 += 8) {  // 8 loads in flight per thread
-                T x[8];
-#pragma unroll
-                for (int q = 0; q < 8; ++q)
-                    x[q] = a0 + q < cnt ? v.stage[((size_t)w * v.QR + s_slot[a0 + q]) * 5 * (size_t)n + l] : (T)0;
-#pragma unroll
-                for (int q = 0; q < 8; ++q)
-                    if (a0 + q < cnt) v.ub[((size_t)w * D + a0 + q) * n + l] = x[q];
-            }
-    }
+    // second batch: the accepted value rows (for ub) and start columns
     const T* Mw = v.M + ((size_t)w * 2 + spin) * n * (size_t)n + l;
-    double acc[D];
+    const bool pack = sizeof(T) == 4 && v.ub != nullptr;
+    // Rows past the count are loaded too (row 0, slot 0: one cached line per thread),
+    // so that no branch splits the batch; their T entries are zero.  Value rows
+    // first: they are stored while the columns are in flight.
+    T c[D], x[D];
+    if (pack) {
 #pragma unroll
-    for (int a = 0; a < D; ++a) acc[a] = 0.0;
-    for (int j0 = 0; j0 < cnt; j0 += 8) {
-        double c[8];
+        for (int j = 0; j < D; ++j) x[j] = v.stage[((size_t)w * v.QR + s_slot[j]) * 5 * (size_t)n + l];
+    } else {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) c[q] = (double)Mw[(size_t)s_row[(j0 + q) & (D - 1)] * n];
-#pragma unroll
-        for (int q = 0; q < 8; ++q)
-#pragma unroll
-            for (int a = 0; a < D; ++a) acc[a] = fma(s_T[a][(j0 + q) & (D - 1)], c[q], acc[a]);
+        for (int j = 0; j < D; ++j) x[j] = (T)0;
     }
+#pragma unroll
+    for (int j = 0; j < D; ++j) c[j] = Mw[(size_t)s_row[j] * n];
+    if constexpr (sizeof(T) == 4) {
+        if (pack)
+#pragma unroll
+            for (int a = 0; a < D; ++a)
+                if (a < cnt) v.ub[((size_t)w * D + a) * n + l] = x[a];
+    }
+    // c_a for 4 accepted moves at a time (one 16-byte store of ct); T is read
+    // transposed, 4 consecutive moves per LDS load
+    auto group = [&](int g, double acc[4]) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] = 0.0;
+#pragma unroll
+        for (int h = 0; h < D / 8; ++h) {
+            if (8 * h < cnt) {
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const int j = 8 * h + q;
+                    const double cj = (double)c[j];
+                    const double2 t01 = *reinterpret_cast<const double2*>(&s_T[j][4 * g]);
+                    const double2 t23 = *reinterpret_cast<const double2*>(&s_T[j][4 * g + 2]);
+                    acc[0] = fma(t01.x, cj, acc[0]);
+                    acc[1] = fma(t01.y, cj, acc[1]);
+                    acc[2] = fma(t23.x, cj, acc[2]);
+                    acc[3] = fma(t23.y, cj, acc[3]);
+                }
+            }
+        }
+    };
     if constexpr (sizeof(T) == 4) {
         if (v.ct) {  // transposed for the matrix-core update: 32 per row, zeros past cnt
             float* dst = v.ct + ((size_t)w * n + l) * D;
-#pragma unroll
+#pragma unroll 1
             for (int g = 0; g < D / 4; ++g) {
-                float x[4];
+                double acc[4] = {0.0, 0.0, 0.0, 0.0};
+                if (4 * g < cnt) group(g, acc);
+                float y[4];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) x[q] = 4 * g + q < cnt ? (float)acc[4 * g + q] : 0.0f;
-                store16(dst + 4 * g, x);
+                for (int q = 0; q < 4; ++q) y[q] = 4 * g + q < cnt ? (float)acc[q] : 0.0f;
+                store16(dst + 4 * g, y);
             }
             return;
         }
     }
     T* Cw = v.Cbuf + (size_t)w * K * n;
+#pragma unroll 1
+    for (int g = 0; g < D / 4; ++g) {
+        if (4 * g < cnt) {
+            double acc[4];
+            group(g, acc);
 #pragma unroll
-    for (int a = 0; a < D; ++a)
-        if (a < cnt) Cw[(size_t)a * n + l] = (T)acc[a];
+            for (int q = 0; q < 4; ++q)
+                if (4 * g + q < cnt) Cw[(size_t)(4 * g + q) * n + l] = (T)acc[q];
+        }
+    }
 }
 
 // Start of a spin block: cursors at 0, gather ranges [0, Q) for round 0 and
@@ -829,7 +888,7 @@ template <typename T>
 void launch_batch_pmat(const CrowdView<T>& v, int spin, hipStream_t s)
 {
     const int pb = (v.Q + kPB - 1) / kPB;
-    hipLaunchKernelGGL(k_pmat<T>, dim3(v.W * pb * pb), dim3(kBlock), 0, s, v, spin);
+    hipLaunchKernelGGL(k_pmat<T>, dim3(xcd_grid(v.W, pb * pb)), dim3(kBlock), 0, s, v, spin);
 }
 
 template <typename T>
@@ -842,7 +901,7 @@ void launch_batch_decide(const CrowdView<T>& v, int spin, int par, hipStream_t s
         lds_set = true;
     }
     hipLaunchKernelGGL(k_decide<T>, dim3(v.W), dim3(kBlock), sizeof(DecideLds), s, v, spin, par);
-    hipLaunchKernelGGL(k_cols<T>, dim3(v.W * ((v.n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, v, spin);
+    hipLaunchKernelGGL(k_cols<T>, dim3(xcd_grid(v.W, (v.n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, v, spin);
 }
 
 template void launch_batch_stencils<float>(const CrowdView<float>&, int, int, bool, hipStream_t);
