@@ -6,10 +6,10 @@
  * and Kent, "A High-Performance Design for Hierarchical Parallelism in the
  * QMCPACK Monte Carlo code" (arXiv 2209.14487): for every walker of a crowd
  * (Sec. III, a subset of the walkers that moves through the algorithm in
- * lock-step, driven by one host thread) and for every particle in turn, lines
- * 5-9 of Alg. 1 -- propose a move, evaluate the wavefunction ratio and the
- * derivatives at the new position, accept or reject -- followed by the local
- * energy (Alg. 1 L11).  The calls are the paper's batched "multi-walker" API
+ * lock-step, driven by one host thread) and for every particle in turn, the
+ * per-particle steps of Alg. 1 -- propose a move, evaluate the wavefunction
+ * ratio and the derivatives at the new position, accept or reject -- followed
+ * by the local energy (Alg. 1).  The calls are the paper's batched "multi-walker" API
  * (Sec. III): one call advances every walker of the crowd.
  *
  * Wavefunction (not specified by the paper; textbook definitions):
@@ -154,7 +154,7 @@ cq_status cq_crowd_create(const cq_system* const* systems, const int* walkers_pe
    counter to first_step. */
 cq_status cq_crowd_set_positions(cq_crowd* c, const double* R, int on_device, uint32_t first_step);
 
-/* Alg. 1 L4-L11 for n_sweeps sweeps: each electron in index order proposes
+/* The VMC sweep of Alg. 1, n_sweeps times: each electron in index order proposes
    r' = wrap(r + sigma z), z ~ N(0, I_3) from Philox counter (uid, step, e, 0/1),
    accepts iff u < rho_D^2 exp(2 dlnJ) with u from counter (uid, step, e, 2), and
    updates the inverse.  The local energy is evaluated after every sweep.
@@ -200,8 +200,8 @@ cq_status cq_crowd_autotune(cq_crowd* c, int sweeps_per_candidate, int* chosen_k
 /* The delay rank in use (after autotuning, the chosen one). */
 cq_status cq_crowd_get_delay_rank(cq_crowd* c, int* k);
 
-/* Diffusion Monte Carlo (paper Alg. 1 with a drift-diffusion move at L5 and
-   reweighting / branching at L12-L13; Sec. II-A).  Runs n_generations
+/* Diffusion Monte Carlo (paper Alg. 1 with a drift-diffusion proposal and
+   reweighting / branching; Sec. II-A).  Runs n_generations
    generations of the crowd's population at time step tau: per generation one
    sweep of drift-diffusion moves (Metropolis-Hastings with the drifted Gaussian
    Green's function; moves that cross a node are rejected), the local energy,

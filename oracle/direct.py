@@ -1,7 +1,7 @@
 """Second, brute-force FP64 reference for tiny systems (N <= 8 per spin).
 
 TEST INFRASTRUCTURE ONLY.  It re-derives the VMC chain of the paper's Alg. 1
-(L5 propose, L7 ratio, L9 accept/reject, L11 local energy) by the most direct
+(propose, ratio, accept/reject, local energy) by the most direct
 route available, so that the C oracle can be pinned against it:
 
 * orbitals: the uniform cubic B-spline in its basis-matrix form

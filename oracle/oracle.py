@@ -1,7 +1,7 @@
 """ctypes wrapper of the FP64 CPU oracle (``qmc_oracle.c``).
 
 TEST INFRASTRUCTURE ONLY.  Nothing in the HIP library or its binding imports
-this module.  Functions follow the paper's Alg. 1 (VMC: lines 4-11; DMC: the
+this module.  Functions follow the paper's Alg. 1 (VMC: the sweep loop; DMC: the
 whole generation loop including reweight/branch and the trial-energy update);
 the wavefunction pieces are textbook definitions named in the C source.
 """
@@ -46,7 +46,7 @@ def lib():
         L.or_local_energy.restype = ctypes.c_double
         L.or_vmc.argtypes = [ctypes.POINTER(OrSystem), ctypes.c_int, dp, dp, ctypes.c_int,
                              ctypes.c_uint32, ctypes.c_double, ctypes.c_int, ctypes.c_int,
-                             dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp]
+                             dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp]
         L.or_vmc.restype = ctypes.c_int
         L.or_setup.argtypes = [ctypes.POINTER(OrSystem), ctypes.c_int, dp, ctypes.c_int, dp, dp, dp, dp]
         L.or_setup.restype = ctypes.c_int
@@ -232,11 +232,12 @@ class VmcResult:
     R: np.ndarray        # [W][Ne][3]
     n_acc: np.ndarray    # [W]
     ainv: Optional[np.ndarray]  # [W][2][n][n] (A^-1 per spin, row j orbital / col i electron)
+    t_moves: Optional[np.ndarray] = None  # [W] wall seconds of each walker's sweeps after set-up
 
 
 def vmc(sys: System, R0, n_sweeps, sigma=0.5, uids=None, first_step=0, max_moves=0,
         n_threads=0, want_ainv=False) -> VmcResult:
-    """Run VMC sweeps (Alg. 1 L4-L11) for every walker of R0 ([W][Ne][3])."""
+    """Run VMC sweeps (the sweep loop of Alg. 1) for every walker of R0 ([W][Ne][3])."""
     R0 = np.ascontiguousarray(R0, dtype=np.float64)
     W, ne = R0.shape[0], R0.shape[1]
     assert ne == sys.n_e
@@ -246,13 +247,15 @@ def vmc(sys: System, R0, n_sweeps, sigma=0.5, uids=None, first_step=0, max_moves
                     np.zeros(shp, np.uint8), np.full((n_sweeps, W, 2), np.nan),
                     np.zeros((n_sweeps, W, 2), np.int32), np.full((n_sweeps, W), np.nan),
                     np.zeros_like(R0), np.zeros(W, np.int64),
-                    np.zeros((W, sys.n_up * sys.n_up + sys.n_dn * sys.n_dn)) if want_ainv else None)
+                    np.zeros((W, sys.n_up * sys.n_up + sys.n_dn * sys.n_dn)) if want_ainv else None,
+                    np.zeros(W))
     cs = sys.c()
     st = lib().or_vmc(ctypes.byref(cs), W, uids.ctypes.data, R0.ctypes.data, n_sweeps, first_step,
                       sigma, max_moves, n_threads,
                       res.rho.ctypes.data, res.dlnj.ctypes.data, res.prob.ctypes.data, res.u.ctypes.data,
                       res.acc.ctypes.data, res.logdet.ctypes.data, res.sign.ctypes.data,
-                      res.eloc.ctypes.data, res.R.ctypes.data, res.n_acc.ctypes.data, _p(res.ainv))
+                      res.eloc.ctypes.data, res.R.ctypes.data, res.n_acc.ctypes.data, _p(res.ainv),
+                      res.t_moves.ctypes.data)
     if st != 0:
         raise ZeroDivisionError("singular starting configuration")
     if want_ainv:
@@ -317,7 +320,7 @@ class DmcResult:
 
 def dmc(sys: System, R0, n_gen, tau, e_trial, n_target=None, max_pop=None, uids=None,
         first_step=0, n_threads=0) -> DmcResult:
-    """Run DMC generations (Alg. 1 including L12-L13) on one system's population."""
+    """Run DMC generations (Alg. 1 including reweighting and branching) on one system's population."""
     R0 = np.ascontiguousarray(R0, dtype=np.float64)
     W, ne = R0.shape[0], R0.shape[1]
     n_target = W if n_target is None else n_target

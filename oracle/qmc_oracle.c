@@ -10,9 +10,8 @@
  *
  * What is computed, and where it is defined:
  *   - the loop structure is the paper's Alg. 1 (walkers -> particles; for each
- *     particle: propose (L5), ratio (L7), derivatives (L8), accept/reject (L9);
- *     then the local energy (L11); reweight/branch and the trial-energy update
- *     (L12-L13) for DMC).  Walkers are spread over OpenMP threads, the pattern
+ *     particle: propose, ratio, derivatives, accept/reject; then the local
+ *     energy; reweight/branch and the trial-energy update for DMC).  Walkers are spread over OpenMP threads, the pattern
  *     of the paper's multi-threaded CPU driver (Alg. 2).
  *   - the paper does not define the wavefunction or the update formulas; those
  *     are textbook mathematics: uniform cubic B-splines (de Boor), a product of
@@ -34,6 +33,7 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <time.h>
 #ifdef _OPENMP
 #include <omp.h>
 #endif
@@ -387,7 +387,7 @@ int or_lu_inverse(int n, const double* A, double* Ainv, double* logdet, int* sig
 }
 
 /* ------------------------------------------------------------------------ */
-/* Kinetic local energy (Alg. 1 L11 with H = kinetic only):                  */
+/* Kinetic local energy (Alg. 1's local-energy step, H = kinetic only):      */
 /*   E_L = -1/2 sum_i [ l_i + lap_i U + |grad_i U|^2 + 2 g_i . grad_i U ]     */
 /*   g_i = sum_j grad phi_j(r_i) Ainv[j][i],  l_i = sum_j lap phi_j(r_i) Ainv[j][i] */
 /* Ainv[s], Gm[s] ([N][N][3]) and Lm[s] ([N][N]) are per spin.               */
@@ -600,18 +600,28 @@ static void drift_current(const or_system* s, const walker* w, int e, double v[3
     for (int c = 0; c < 3; ++c) v[c] = gd[c] + gj[c];
 }
 
+/* Wall-clock seconds (monotonic), for the sweep timing of or_vmc only.      */
+static double wall_seconds(void)
+{
+    struct timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
+}
+
 /* ------------------------------------------------------------------------ */
-/* VMC: Alg. 1 lines 4-11 for a set of walkers, Gaussian proposals           */
+/* VMC: the sweep loop of Alg. 1 for a set of walkers, Gaussian proposals    */
 /* r' = wrap(r_e + sigma z), acceptance min(1, rho_D^2 exp(2 dlnJ)).          */
 /* Records are indexed [(sweep * Ne + e) * W + walker].                      */
 /* max_moves > 0 stops the first sweep after that many electron moves.       */
+/* t_moves_out (optional, [W]): wall seconds each walker spent in its sweeps */
+/* after its set-up.                                                          */
 /* Returns 0, or -1 if a starting configuration is singular.                 */
 /* ------------------------------------------------------------------------ */
 int or_vmc(const or_system* s, int n_walkers, const uint32_t* uids, const double* R0,
            int n_sweeps, uint32_t first_step, double sigma, int max_moves, int n_threads,
            double* rec_rho, double* rec_dlnj, double* rec_prob, double* rec_u, uint8_t* rec_acc,
            double* logdet_out, int* sign_out, double* eloc_out,
-           double* R_out, int64_t* n_acc_out, double* ainv_out)
+           double* R_out, int64_t* n_acc_out, double* ainv_out, double* t_moves_out)
 {
     const int ne = s->n_up + s->n_dn;
     const int nmax = s->n_up > s->n_dn ? s->n_up : s->n_dn;
@@ -631,6 +641,7 @@ int or_vmc(const or_system* s, int n_walkers, const uint32_t* uids, const double
         if (walker_setup(s, &w) != 0) {
             status = -1;
         } else {
+            const double tm0 = wall_seconds();
             int moves_done = 0;
             for (int sw = 0; sw < n_sweeps; ++sw) {
                 uint32_t step = first_step + (uint32_t)sw;
@@ -640,14 +651,14 @@ int or_vmc(const or_system* s, int n_walkers, const uint32_t* uids, const double
                     int sp = spin_of(s, e);
                     int n = sp == 0 ? s->n_up : s->n_dn;
                     double z[3], rnew[3], gd[3];
-                    /* L5: propose */
+                    /* propose */
                     or_gauss3(s->seed, w.uid, step, (uint32_t)e, z);
                     for (int c = 0; c < 3; ++c) rnew[c] = wrap(w.R[3 * e + c] + sigma * z[c], s->L);
-                    /* L7-L8: ratio and derivatives at r' */
+                    /* ratio and derivatives at r' */
                     or_orbital_vgl(s, rnew, n, t.v, t.g, t.l);
                     double rho = det_ratio(s, &w, e, &t, gd);
                     double dlnj = j2_delta(s, w.R, e, rnew);
-                    /* L9: accept / reject */
+                    /* accept / reject */
                     double prob = rho * rho * exp(2.0 * dlnj);
                     double u = or_accept_uniform(s->seed, w.uid, step, (uint32_t)e);
                     int acc = u < prob;
@@ -664,7 +675,7 @@ int or_vmc(const or_system* s, int n_walkers, const uint32_t* uids, const double
                     }
                     moves_done++;
                 }
-                /* L11: local energy */
+                /* local energy */
                 w.eloc = walker_eloc(s, &w);
                 if (logdet_out) {
                     logdet_out[((size_t)sw * n_walkers + iw) * 2 + 0] = w.logdet[0];
@@ -677,6 +688,7 @@ int or_vmc(const or_system* s, int n_walkers, const uint32_t* uids, const double
                 if (eloc_out) eloc_out[(size_t)sw * n_walkers + iw] = w.eloc;
                 if (stop) break;
             }
+            if (t_moves_out) t_moves_out[iw] = wall_seconds() - tm0;
             if (R_out) memcpy(&R_out[(size_t)iw * ne * 3], w.R, sizeof(double) * ne * 3);
             if (n_acc_out) n_acc_out[iw] = w.n_acc;
             if (ainv_out) {
@@ -788,7 +800,7 @@ int or_dmc_move_prob(const or_system* s, const double* R, int e, const double de
 }
 
 /* ------------------------------------------------------------------------ */
-/* DMC: Alg. 1 with drift-diffusion proposals and branching (L12-L13).       */
+/* DMC: Alg. 1 with drift-diffusion proposals, reweighting and branching.    */
 /* Per move (electron e, current drift v = grad ln|Psi| at r_e):             */
 /*   Delta = tau v + sqrt(tau) z,  r' = wrap(r_e + Delta)                    */
 /*   P = rho_D^2 exp(2 dlnJ) * exp(-(|Delta + tau v'|^2 - |Delta - tau v|^2) */
@@ -856,7 +868,7 @@ int or_dmc(const or_system* s, int n_walkers, const uint32_t* uids, const double
             w->eloc = walker_eloc(s, w);
             scratch_free(&t);
         }
-        /* L12: reweight and branch */
+        /* reweight and branch */
         double wsum = 0, wesum = 0;
         int* mult = (int*)malloc(sizeof(int) * (size_t)pop);
         int new_pop = 0;
@@ -895,7 +907,7 @@ int or_dmc(const or_system* s, int n_walkers, const uint32_t* uids, const double
         ws = nws;
         e_old = ne_old;
         free(mult);
-        /* L13: trial energy */
+        /* trial energy */
         double e_est = wesum / wsum;
         e_t = e_est - log((double)new_pop / (double)n_target) / tau;
         pop = new_pop;

@@ -6,7 +6,7 @@ PyTorch is optional plumbing: a torch CUDA tensor may be passed wherever a
 device buffer is accepted and a torch stream as the crowd's stream.
 
 The method is the batched particle-by-particle move of Luo, Doak and Kent,
-arXiv 2209.14487 (Alg. 1 L5-L11 applied to every walker of a crowd in lock-step,
+arXiv 2209.14487 (the move and local-energy steps of Alg. 1 applied to every walker of a crowd in lock-step,
 Sec. III "crowds", Alg. 4).
 """
 import ctypes

@@ -2,7 +2,7 @@
 // (optionally captured once as a hipGraph and replayed), the FP64 recompute
 // schedule, parity-mode buffers and per-kernel event timing.
 //
-// One sweep (paper Alg. 1 L4-L11 over all walkers of the crowd in lock-step,
+// One sweep (the VMC sweep of Alg. 1 over all walkers of the crowd in lock-step,
 // the batched form of Alg. 3/4) is, for e = 0 .. Ne-1:
 //   k_move(e, resolving e-1)  [-> k_move(resolve e only) -> k_flush(spin) at the
 //   end of a window]

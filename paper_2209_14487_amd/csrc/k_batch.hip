@@ -4,9 +4,9 @@
 // Gaussian moves, no drift) depends only on electron e's own position, and e has
 // not moved yet in the sweep when its turn comes.  So the proposals of many
 // upcoming moves are known before any of them is decided, and their orbital rows
-// (paper Alg. 1 L7: B-spline value, gradient, Laplacian) can be evaluated in one
+// (the wavefunction evaluation of Alg. 1: B-spline value, gradient, Laplacian) can be evaluated in one
 // wide, fully parallel gather launch over all walkers.  The sequential part
-// (Alg. 1 L8-L9: ratios, Jastrow, Metropolis, in electron order) then works on
+// (the ratio and accept steps of Alg. 1: ratios, Jastrow, Metropolis, in electron order) then works on
 // small matrices only.
 //
 // Per walker and spin block, electrons are taken in order.  A round looks at the

@@ -1,5 +1,5 @@
 // Diffusion Monte Carlo: drift-diffusion moves and branching (paper Alg. 1 with
-// L5 as a drift-diffusion step and L12-L13 reweighting / branching).
+// its proposal read as a drift-diffusion step, then reweighting / branching).
 //
 // A DMC proposal moves electron e by
 //     delta = tau v(r_e) + sqrt(tau) z,      v = grad ln|Psi| at the current r_e,

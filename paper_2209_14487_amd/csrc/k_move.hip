@@ -1,11 +1,12 @@
-// Per-move kernels of the batched particle-by-particle move (paper Alg. 1
-// L5-L9 applied to every walker of a crowd in lock-step, Alg. 3/4):
+// Per-move kernels of the batched particle-by-particle move (the propose, ratio,
+// derivative and accept steps of Alg. 1 applied to every walker of a crowd in
+// lock-step, Alg. 3/4):
 //
-//   k_move       one launch per move e: L7/L8 B-spline value/gradient/Laplacian
+//   k_move       one launch per move e: B-spline value/gradient/Laplacian
 //                at the proposal r'_e for one orbital chunk, the chunk's partial
 //                dot products with the inverse column and the delayed-update
-//                window, a slice of the Jastrow sums; fused with the L7 ratio and
-//                L9 decision of the previous move and the L5 proposal of the
+//                window, a slice of the Jastrow sums; fused with the ratio and
+//                decision of the previous move and the proposal of the
 //                next one.  Grid: walkers x chunks.
 //
 // Orbital tables are [G][G][G][n_orb] with the orbital index fastest, so the 64

@@ -12,7 +12,7 @@
 //               with the k x k window matrix factorised in move order, which
 //               keeps the rounding of a sequence of Sherman-Morrison steps.
 //               Each wave keeps RPW rows in registers and streams the window rows.
-// k_energy_*    kinetic local energy (Alg. 1 L11):
+// k_energy_*    kinetic local energy (the local-energy step of Alg. 1):
 //                 E_L = -1/2 sum_i [l_i + lap_i U + |grad_i U|^2 + 2 g_i . grad_i U]
 //               g_i = sum_j grad phi_j(r_i) A^-1_ji is the dot of gradient row i
 //               with row i of M (likewise l_i); FP64 sums over electrons.

@@ -1,5 +1,6 @@
 // Walker-resident window kernel: one workgroup per walker performs the k
-// consecutive moves of one update window (paper Alg. 1 L5-L9 for k particles),
+// consecutive moves of one update window (the per-particle steps of Alg. 1 for k
+// particles),
 // keeping the window's bookkeeping in LDS and synchronising only inside the
 // workgroup.  The window's accepted moves are left in global memory for the
 // rank-k update kernel that follows.

@@ -315,7 +315,7 @@ def test_inverse_after_sweeps_matches_direct_inverse():
 
 
 def test_local_energy_matches_finite_differences():
-    """L11: the kinetic local energy formula agrees with -1/2 sum lap Psi / Psi by finite
+    """Local energy: the kinetic local energy formula agrees with -1/2 sum lap Psi / Psi by finite
     differences of the directly evaluated wavefunction (splines + J2)."""
     n = 2
     s, d = _tiny_system(n, G=8, L=4.0, j2=True, seed=13)
