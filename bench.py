@@ -41,6 +41,10 @@ def parse():
     ap.add_argument("--fp64-steps", type=int, default=2, help="sweeps of the FP64 comparison run (0: skip)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-moves", type=int, default=2048, help="moves per walker in the CPU baseline sample")
+    ap.add_argument("--time-kernels", default="vgl,update",
+                    help="kernel kinds bracketed by HIP events in the timed run (comma separated, from "
+                         "propose, vgl, resolve, update, energy, inverse); the events add launches to the "
+                         "timed region, so by default only the two roofline kernels are bracketed")
     ap.add_argument("--delay", type=int, default=None, help="override the delay rank")
     ap.add_argument("--alone-steps", type=int, default=4,
                     help="sweeps of a one-stream run that times the gather and the update alone (0: skip)")
@@ -290,7 +294,10 @@ def main():
         cq.device_copy(dst.data_ptr(), src.data_ptr(), 1 << 30)
         del src, dst
         log("  copied 1 GiB with cq_device_copy (calibration)")
-    kinds = ["propose", "vgl", "resolve", "update", "energy", "inverse"]
+    kinds = [k for k in args.time_kernels.split(",") if k]
+    for k in ("vgl", "update"):  # the rooflines need these two
+        if k not in kinds:
+            kinds.append(k)
     mixed = run_gpu(cq, wl, "mixed", delay, wl.recompute_every, args.steps, args.warmup, kinds, not args.eager,
                     path=args.path, graph_steps=0 if args.eager else max(2, args.steps // 4))
     log("  mixed: %.3f s for %d sweeps, %.3e moves/s, acceptance %.3f"
@@ -318,7 +325,7 @@ def main():
                                     % (wl.name, n, n, wl.L, wl.G, wl.table_bytes(4) / 1e9, wl.crowds, wl.walkers,
                                        delay, wl.recompute_every),
                            precision="mixed", path=args.path,
-                           launch="eager launches with HIP events around every kernel (timed region)"),
+                           launch="eager launches; HIP events around every launch of %s in the timed region" % "/".join(kinds)),
                roofline=dominant, roofline_spline=roof_vgl, roofline_update=roof_up, kernels=kinfo,
                windows_per_sweep=windows_per_sweep,
                acceptance=round(mixed["acceptance"], 4), e_mean=mixed["e_mean"])

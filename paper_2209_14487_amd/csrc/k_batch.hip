@@ -339,24 +339,28 @@ __global__ __launch_bounds__(kBlock) void k_pmat(CrowdView<T> v, int spin)
     const T* urow = v.stage + ((size_t)w * v.QR + (dec + (ci < nc ? ci : 0)) % v.QR) * 5 * (size_t)n;
     const T* crow = v.M + (((size_t)w * 2 + spin) * n + dec + (cj < nc ? cj : 0)) * (size_t)n;
     f64x4 acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-    for (int k0 = wave * KC; k0 < n; k0 += 4 * KC) {
-        T u[VEC], c[VEC];
-        const int kk = k0 + VEC * q;
-        if (kk < n && ci < nc) {
-            load16(urow + kk, u);
-        } else {
+    // 8 chunks of loads in flight per lane.  Addresses past the end (k >= n) or of
+    // rows past the candidates are clamped to valid ones and the values zeroed, so
+    // no branch splits a batch.
+    constexpr int NB = 8;
+    const bool u_live = ci < nc, c_live = cj < nc;
+    for (int k00 = wave * KC; k00 < n; k00 += NB * 4 * KC) {
+        T u[NB][VEC], c[NB][VEC];
 #pragma unroll
-            for (int s = 0; s < VEC; ++s) u[s] = (T)0;
-        }
-        if (kk < n && cj < nc) {
-            load16(crow + kk, c);
-        } else {
-#pragma unroll
-            for (int s = 0; s < VEC; ++s) c[s] = (T)0;
+        for (int it = 0; it < NB; ++it) {
+            const int kk = k00 + it * 4 * KC + VEC * q;
+            const int kc = kk < n ? kk : 0;
+            load16(urow + kc, u[it]);
+            load16(crow + kc, c[it]);
         }
 #pragma unroll
-        for (int s = 0; s < VEC; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64((double)u[s], (double)c[s], acc, 0, 0, 0);
+        for (int it = 0; it < NB; ++it) {
+            const bool in = k00 + it * 4 * KC + VEC * q < n;
+#pragma unroll
+            for (int s = 0; s < VEC; ++s)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(in && u_live ? (double)u[it][s] : 0.0,
+                                                           in && c_live ? (double)c[it][s] : 0.0, acc, 0, 0, 0);
+        }
     }
 #pragma unroll
     for (int t = 0; t < 4; ++t) sP[wave][q + 4 * t][r] = acc[t];
