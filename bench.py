@@ -149,30 +149,32 @@ def rooflines(res, n, W, steps, traffic, s_c=4, s=4):
     up_t = up_ms / max(up_n, 1) * 1e-3
     r_per_launch = res["accepted_timed"] / max(up_n, 1)
     up_flops = 4.0 * n * n * r_per_launch
+    traffic = traffic or {}
     roof_vgl = dict(bound="hbm", achieved=round(vgl_gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(vgl_gbs / HBM_PEAK_GBS, 4), traffic=traffic, kernel="k_prop_vgl",
+                    frac=round(vgl_gbs / HBM_PEAK_GBS, 4), traffic=traffic.get("vgl"), kernel="k_prop_vgl",
                     us_per_launch=round(vgl_t * 1e6, 3), bytes_per_launch=int(vgl_bytes),
                     proposals_per_launch=int(props_per_launch))
     roof_up = dict(bound="mfma", achieved=round(up_flops / up_t / 1e12, 2), peak=FP32_PEAK_TFLOPS,
                    unit="TFLOP/s", frac=round(up_flops / up_t / 1e12 / FP32_PEAK_TFLOPS, 4),
-                   kernel="k_flush_mfma_batch",
+                   traffic=traffic.get("update"), kernel="k_flush_mfma_batch",
                    us_per_launch=round(up_t * 1e6, 3), accepted_per_launch=round(r_per_launch, 2))
     return roof_vgl, roof_up
 
 
 def kernel_source_hash():
-    """SHA-256 of the sources the gather kernel is built from."""
+    """SHA-256 of the sources the gather and update kernels are built from."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("k_batch.hip", "cq_device.h", "cq_internal.h"):
+    for f in ("k_batch.hip", "k_flush_mfma.hip", "cq_device.h", "cq_internal.h"):
         with open(os.path.join(ROOT, "paper_2209_14487_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
 def measured_traffic(workload):
-    """HBM bytes per k_prop_vgl launch from the committed counter summary, or None when the
-    summary is missing or was taken on a different kernel source."""
+    """HBM bytes per launch of k_prop_vgl and of k_flush_mfma_batch ({"vgl": B, "update": B})
+    from the committed counter summary, or None when the summary is missing or was taken on
+    a different kernel source."""
     path = os.path.join(ROOT, "profiles", "k_prop_vgl_%s_traffic.json" % workload)
     if not os.path.exists(path):
         return None
@@ -180,7 +182,7 @@ def measured_traffic(workload):
         rec = json.load(fh)
     if rec.get("source_sha256") != kernel_source_hash():
         return None
-    return rec.get("traffic_bytes_per_launch")
+    return dict(vgl=rec.get("traffic_bytes_per_launch"), update=(rec.get("update") or {}).get("traffic_bytes_per_launch"))
 
 
 def cpu_baseline(wl, moves_per_walker):

@@ -1,5 +1,5 @@
 #!/usr/bin/env python3
-"""HBM traffic of the gather kernel from two rocprofv3 counter runs of bench.py.
+"""HBM traffic of the gather and update kernels from two rocprofv3 counter runs of bench.py.
 
 Usage (on the GPU machine, each run in its own process):
     rocprofv3 --pmc FETCH_SIZE --output-format csv -d OUT/fetch -o run -- \\
@@ -11,9 +11,9 @@ Usage (on the GPU machine, each run in its own process):
 FETCH_SIZE and WRITE_SIZE are read per dispatch in KiB.  The library's plain
 copy kernel (cq::k_copy16, 1 GiB read + 1 GiB written, launched once by
 --calibrate-copy) gives the factor between counter readings and bytes; the
-gather kernel's per-launch average is scaled by it.  The output records the
-source hash of the kernel, so bench.py uses the figure only while the kernel is
-unchanged.
+per-launch averages of the gather (k_prop_vgl) and of the update
+(k_flush_mfma_batch, "update") are scaled by it.  The output records the source
+hash of the kernels, so bench.py uses the figures only while they are unchanged.
 """
 import csv
 import glob
@@ -65,11 +65,17 @@ def main():
     gf, nf = pick(fetch, "k_prop_vgl")
     gw, nw = pick(write, "k_prop_vgl")
     fb, wb = gf * 1024.0 * sf, gw * 1024.0 * sw
+    uf, unf = pick(fetch, "k_flush_mfma_batch")
+    uw, unw = pick(write, "k_flush_mfma_batch")
+    ufb, uwb = uf * 1024.0 * sf, uw * 1024.0 * sw
+    update = dict(kernel="k_flush_mfma_batch", launches=[unf, unw], fetch_kib_per_launch=uf,
+                  write_kib_per_launch=uw, fetch_bytes_per_launch=ufb, write_bytes_per_launch=uwb,
+                  traffic_bytes_per_launch=ufb + uwb)
     rec = dict(kernel="k_prop_vgl", workload=workload, launches=[nf, nw],
                fetch_kib_per_launch=gf, write_kib_per_launch=gw,
                copy_fetch_kib=cf, copy_write_kib=cw, scale_fetch=sf, scale_write=sw,
                fetch_bytes_per_launch=fb, write_bytes_per_launch=wb, traffic_bytes_per_launch=fb + wb,
-               source_sha256=kernel_source_hash(),
+               update=update, source_sha256=kernel_source_hash(),
                command="rocprofv3 --pmc FETCH_SIZE|WRITE_SIZE --output-format csv -d DIR -o run -- "
                        "python3 bench.py --steps 2 --warmup 1 --fp64-steps 0 --no-cpu --alone-steps 0 --calibrate-copy; "
                        "python3 bench_traffic.py FETCH_DIR WRITE_DIR %s" % workload)
