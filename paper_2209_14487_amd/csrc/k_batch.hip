@@ -41,7 +41,7 @@
 // k_jd          Jastrow sums of a round's new candidates
 // k_pmat        P of every walker's candidates (FP64 sums of exact products)
 // k_decide      one workgroup per walker: the decisions, the window for the
-//               update kernel (accepted rows by slot, rho, G, and T with
+//               update kernel (accepted rows by slot, rho, G, L^-1, and T with
 //               c_a = sum_i T[a][i] c0_i), the cursors and the Jastrow sums of the
 //               candidates left for later
 // k_cols        the columns c_a of the accepted moves
@@ -385,14 +385,12 @@ __device__ __forceinline__ double pair_change(const CrowdView<T>& v, const doubl
 }
 
 // Decision kernel.  Everything the sequential loop reads sits in LDS (dynamic,
-// about 140 KB at Q = 88): P, the Jastrow pair changes of every candidate pair,
-// T, X[a][i] = u_i . c_a (the accepted columns against every candidate), L^-1 of
-// the window's triangle (G below the diagonal, rho on it), so that
-//     beta = L^-1 y,  y_a = P[s_a][m]        (a product, not a substitution),
-// and the running ratio and Jastrow sum of every candidate.  T is kept
-// in the basis of the accepted moves' own start columns: c_a = sum_{j<=a}
-// T[a][j] c0_{s_j} (lower triangular, T[a][a] = 1), so an acceptance costs
-// O(accepted), not O(candidates).
+// about 146 KB at Q = 88): P, the Jastrow pair changes of every candidate pair,
+// the rows X[a][i] = u_i . c_a and B[a][i] = beta_a(i) of every accepted move a
+// against every candidate i, and the running ratio and Jastrow sum of every
+// candidate.  An acceptance adds one row of X and of B (O(accepted) per
+// candidate); T and L^-1 of the window follow from these rows once the decisions
+// are made, as the inverses of two triangles, so the loop carries neither.
 struct DecideLds {
     static constexpr int QM = kMaxCand, D = kMaxDelay;
     double P[QM][QM + 1];
