@@ -164,6 +164,79 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
     const int p = tid / tpp, t0 = tid % tpp;
     const int nchunk = (nprop + pp - 1) / pp;
 
+    if (pp == 1) {
+        // One proposal per chunk (large N).  The stencil of the block's next proposal
+        // is loaded while the current one is gathered, and the cursor range of the
+        // proposal after that one chunk earlier still, so that no global round trip
+        // stands between two gathers.
+        auto in_range = [&](int pi, int& a) { return pi < nprop && gather_electron(v.look, par, v.W, pi / Q, pi % Q, a); };
+        size_t nidx = 0;
+        T nw[5] = {(T)0, (T)0, (T)0, (T)0, (T)0};
+        auto fetch = [&](bool ok, int pi, int a) {
+            if (ok && tid < 64) {
+                const size_t ps = (size_t)(pi / Q) * QR + a % QR;
+                nidx = v.sidx[ps * 64 + tid];
+                const T* sw = (const T*)v.swt + (ps * 64 + tid) * 5;
+#pragma unroll
+                for (int k = 0; k < 5; ++k) nw[k] = sw[k];
+            }
+        };
+        int a1 = 0, a2 = 0;
+        bool ok1 = in_range(blockIdx.x, a1);
+        bool ok2 = in_range(blockIdx.x + gridDim.x, a2);
+        fetch(ok1, blockIdx.x, a1);
+        for (int chunk = blockIdx.x; chunk < nchunk; chunk += gridDim.x) {
+            const bool ok = ok1;
+            const int a = a1;
+            __syncthreads();  // the previous proposal's readers of the stencil are done
+            if (ok && tid < 64) {
+                s_idx[0][tid] = nidx;
+#pragma unroll
+                for (int k = 0; k < 5; ++k) s_w[0][tid * 5 + k] = nw[k];
+            }
+            __syncthreads();
+            ok1 = ok2;
+            a1 = a2;
+            fetch(ok1, chunk + gridDim.x, a1);
+            ok2 = in_range(chunk + 2 * gridDim.x, a2);
+            if (!ok) continue;
+            const int w = chunk / Q, slot = a % QR;
+            T* dst = v.stage + ((size_t)w * QR + slot) * 5 * (size_t)n;
+            const size_t* sidx = s_idx[0];
+            const T* sw = s_w[0];
+            for (int g = tid; g < groups; g += nt) {
+                const int j0 = g * VEC;
+                T acc[5][VEC];
+#pragma unroll
+                for (int k = 0; k < 5; ++k)
+#pragma unroll
+                    for (int i = 0; i < VEC; ++i) acc[k][i] = (T)0;
+#pragma unroll 1
+                for (int x = 0; x < 4; ++x) {
+                    T vals[16][VEC];
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) load16(v.table + sidx[x * 16 + q] + j0, vals[q]);
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) {
+                        const T* wq = sw + (x * 16 + q) * 5;
+                        const T wv = wq[0], wgx = wq[1], wgy = wq[2], wgz = wq[3], wl = wq[4];
+#pragma unroll
+                        for (int i = 0; i < VEC; ++i) {
+                            acc[0][i] += wv * vals[q][i];
+                            acc[1][i] += wgx * vals[q][i];
+                            acc[2][i] += wgy * vals[q][i];
+                            acc[3][i] += wgz * vals[q][i];
+                            acc[4][i] += wl * vals[q][i];
+                        }
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < 5; ++k) store16(dst + (size_t)k * n + j0, acc[k]);
+            }
+        }
+        return;
+    }
+
     for (int chunk = blockIdx.x; chunk < nchunk; chunk += gridDim.x) {
         const int first = chunk * pp;
         __syncthreads();  // the previous chunk's readers of the stencils are done
