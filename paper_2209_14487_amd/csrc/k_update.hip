@@ -252,15 +252,31 @@ __global__ __launch_bounds__(kBlock) void k_energy_rows(CrowdView<T> v)
         const double re[3] = {Rw[(size_t)e * 3], Rw[(size_t)e * 3 + 1], Rw[(size_t)e * 3 + 2]};
         const T L = (T)v.L, iL = (T)(1.0 / v.L), b = (T)v.b;
         const T a_same = (T)v.a_par, a_other = (T)v.a_anti;
-        for (int m = lane; m < v.ne; m += 64) {
-            const T aa = ((m >= n) == (spin != 0)) ? a_same : a_other;
-            T gx, gy, gz, lp;
-            j2_energy_terms<T>(aa, b, L, iL, re, Rw + (size_t)m * 3, gx, gy, gz, lp);
-            const bool self = m == e;  // the electron's own pair term is not a term
-            gu[0] += self ? 0.0 : (double)gx;
-            gu[1] += self ? 0.0 : (double)gy;
-            gu[2] += self ? 0.0 : (double)gz;
-            lu += self ? 0.0 : (double)lp;
+        // the positions of 4 partners per lane are loaded together (one round trip per
+        // 256 partners); the terms are summed in the order m = lane, lane + 64, ...
+        constexpr int PU = 4;
+        for (int m0 = lane; m0 < v.ne; m0 += PU * 64) {
+            double rm[PU][3];
+#pragma unroll
+            for (int u = 0; u < PU; ++u) {
+                const int m = m0 + 64 * u, mc = m < v.ne ? m : lane;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) rm[u][c] = Rw[(size_t)mc * 3 + c];
+            }
+#pragma unroll
+            for (int u = 0; u < PU; ++u) {
+                const int m = m0 + 64 * u;
+                if (m < v.ne) {
+                    const T aa = ((m >= n) == (spin != 0)) ? a_same : a_other;
+                    T gx, gy, gz, lp;
+                    j2_energy_terms<T>(aa, b, L, iL, re, rm[u], gx, gy, gz, lp);
+                    const bool self = m == e;  // the electron's own pair term is not a term
+                    gu[0] += self ? 0.0 : (double)gx;
+                    gu[1] += self ? 0.0 : (double)gy;
+                    gu[2] += self ? 0.0 : (double)gz;
+                    lu += self ? 0.0 : (double)lp;
+                }
+            }
         }
 #pragma unroll
         for (int k = 0; k < 3; ++k) gu[k] = wave_sum(gu[k]);
