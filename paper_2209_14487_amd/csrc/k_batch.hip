@@ -387,62 +387,83 @@ __global__ __launch_bounds__(kBlock) void k_jd(CrowdView<T> v, int spin)
 // A[l % 16][l / 16] and B[l / 16][l % 16]; the result is D[l / 16 + 4 v][l % 16].
 // The 4 k values of a step are taken as k0 + VEC q + s (q = l / 16, s = step
 // within a 16-byte load), the same on both operands.  The 4 waves of a
-// workgroup take alternate k chunks; their partial blocks are added in order.
+// workgroup take alternate k chunks; their partial blocks are added in order.  A
+// workgroup covers kPTJ blocks of one block row, which share the row operand: the
+// launch has a third of the workgroups that one block each would need, and each
+// does three times the work between its loads and its stores.
 typedef double f64x4 __attribute__((ext_vector_type(4)));
-constexpr int kPB = 16;  // block edge
+constexpr int kPB = 16;   // block edge
+constexpr int kPTJ = 3;   // column blocks per workgroup
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_pmat(CrowdView<T> v, int spin)
 {
     constexpr int VEC = 16 / sizeof(T);
     constexpr int KC = 4 * VEC;  // k values per chunk
-    __shared__ double sP[4][kPB][kPB + 1];
+    constexpr int TJ = kPTJ;     // column blocks per workgroup, sharing the row operand
+    __shared__ double sP[4][TJ][kPB][kPB + 1];
     const int Q = v.Q, n = v.n;
-    const int nb = (Q + kPB - 1) / kPB;
+    const int nb = (Q + kPB - 1) / kPB, nbg = (nb + TJ - 1) / TJ;
     int w, blk;  // a walker's tiles share one XCD, so its rows are fetched into one L2
-    xcd_map(blockIdx.x, nb * nb, w, blk);
+    xcd_map(blockIdx.x, nb * nbg, w, blk);
     if (w >= v.W) return;
-    const int bi = blk / nb, bj = blk % nb;
+    const int bi = blk / nbg, bj0 = (blk % nbg) * TJ;
     const int dec = v.cur[2 * w];
     const int nc = (dec + Q < n ? dec + Q : n) - dec;
-    if (bi * kPB >= nc || bj * kPB >= nc) return;
+    if (bi * kPB >= nc || bj0 * kPB >= nc) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r = lane & 15, q = lane >> 4;
-    const int ci = bi * kPB + r, cj = bj * kPB + r;
+    const int ci = bi * kPB + r;
     const T* urow = v.stage + ((size_t)w * v.QR + (dec + (ci < nc ? ci : 0)) % v.QR) * 5 * (size_t)n;
-    const T* crow = v.M + (((size_t)w * 2 + spin) * n + dec + (cj < nc ? cj : 0)) * (size_t)n;
-    f64x4 acc = {0.0, 0.0, 0.0, 0.0};
-    // 8 chunks of loads in flight per lane.  Addresses past the end (k >= n) or of
+    const T* crow[TJ];
+    bool c_live[TJ];
+#pragma unroll
+    for (int tj = 0; tj < TJ; ++tj) {
+        const int cj = (bj0 + tj) * kPB + r;
+        c_live[tj] = cj < nc;
+        crow[tj] = v.M + (((size_t)w * 2 + spin) * n + dec + (cj < nc ? cj : 0)) * (size_t)n;
+    }
+    f64x4 acc[TJ];
+#pragma unroll
+    for (int tj = 0; tj < TJ; ++tj) acc[tj] = f64x4{0.0, 0.0, 0.0, 0.0};
+    // 4 chunks of loads in flight per lane.  Addresses past the end (k >= n) or of
     // rows past the candidates are clamped to valid ones and the values zeroed, so
     // no branch splits a batch.
-    constexpr int NB = 8;
-    const bool u_live = ci < nc, c_live = cj < nc;
+    constexpr int NB = 4;
+    const bool u_live = ci < nc;
     for (int k00 = wave * KC; k00 < n; k00 += NB * 4 * KC) {
-        T u[NB][VEC], c[NB][VEC];
+        T u[NB][VEC], c[TJ][NB][VEC];
 #pragma unroll
         for (int it = 0; it < NB; ++it) {
             const int kk = k00 + it * 4 * KC + VEC * q;
             const int kc = kk < n ? kk : 0;
             load16(urow + kc, u[it]);
-            load16(crow + kc, c[it]);
+#pragma unroll
+            for (int tj = 0; tj < TJ; ++tj) load16(crow[tj] + kc, c[tj][it]);
         }
 #pragma unroll
         for (int it = 0; it < NB; ++it) {
             const bool in = k00 + it * 4 * KC + VEC * q < n;
 #pragma unroll
-            for (int s = 0; s < VEC; ++s)
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(in && u_live ? (double)u[it][s] : 0.0,
-                                                           in && c_live ? (double)c[it][s] : 0.0, acc, 0, 0, 0);
+            for (int s2 = 0; s2 < VEC; ++s2) {
+                const double a = in && u_live ? (double)u[it][s2] : 0.0;
+#pragma unroll
+                for (int tj = 0; tj < TJ; ++tj)
+                    acc[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, in && c_live[tj] ? (double)c[tj][it][s2] : 0.0,
+                                                                   acc[tj], 0, 0, 0);
+            }
         }
     }
 #pragma unroll
-    for (int t = 0; t < 4; ++t) sP[wave][q + 4 * t][r] = acc[t];
+    for (int tj = 0; tj < TJ; ++tj)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) sP[wave][tj][q + 4 * t][r] = acc[tj][t];
     __syncthreads();
     double* P = v.pmat + (size_t)w * Q * Q;
-    {
-        const int i = tid >> 4, j = tid & 15;
-        const double sum = ((sP[0][i][j] + sP[1][i][j]) + sP[2][i][j]) + sP[3][i][j];
-        const int gi = bi * kPB + i, gj = bj * kPB + j;
+    for (int idx = tid; idx < TJ * kPB * kPB; idx += kBlock) {
+        const int tj = idx / (kPB * kPB), i = (idx / kPB) % kPB, j = idx % kPB;
+        const double sum = ((sP[0][tj][i][j] + sP[1][tj][i][j]) + sP[2][tj][i][j]) + sP[3][tj][i][j];
+        const int gi = bi * kPB + i, gj = (bj0 + tj) * kPB + j;
         if (gi < nc && gj < nc) P[(size_t)gi * Q + gj] = sum;
     }
 }
@@ -963,7 +984,7 @@ template <typename T>
 void launch_batch_pmat(const CrowdView<T>& v, int spin, hipStream_t s)
 {
     const int pb = (v.Q + kPB - 1) / kPB;
-    hipLaunchKernelGGL(k_pmat<T>, dim3(xcd_grid(v.W, pb * pb)), dim3(kBlock), 0, s, v, spin);
+    hipLaunchKernelGGL(k_pmat<T>, dim3(xcd_grid(v.W, pb * ((pb + kPTJ - 1) / kPTJ))), dim3(kBlock), 0, s, v, spin);
 }
 
 template <typename T>
