@@ -880,30 +880,47 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_rows(CrowdView<T> v, int spin)
 {
+    constexpr int D = kMaxDelay, RB = 8;  // accepted rows per batch of loads
+    __shared__ __align__(16) int s_e[D];
+    __shared__ __align__(16) int s_sl[D];
     const int n = v.n, K = v.K;
     const int nlb = (n + kBlock - 1) / kBlock;
-    const int w = blockIdx.x / nlb, l = (blockIdx.x % nlb) * kBlock + threadIdx.x;
+    int w, part;  // a walker's blocks share one XCD
+    xcd_map(blockIdx.x, nlb, w, part);
+    if (w >= v.W) return;
+    const int tid = threadIdx.x, l = part * kBlock + tid;
+    // the window's electrons and slots in one batch (entries past the count or out of
+    // range are marked; bad entries are reported by the column kernel)
     int cnt = v.cnt[(size_t)2 * v.W + w];
+    int e = -1, sl = -1;
+    if (tid < K) {
+        e = v.welec[(size_t)w * K + tid];
+        sl = v.wslot[(size_t)w * K + tid];
+    }
     if (cnt > K) cnt = K;
+    if (cnt <= 0) return;
+    if (tid < D) {
+        const bool ok = tid < cnt && e >= 0 && e < n && sl >= 0 && sl < v.QR;
+        s_e[tid] = ok ? e : -1;
+        s_sl[tid] = ok ? sl : 0;
+    }
+    __syncthreads();
     if (l >= n) return;
-    for (int a0 = 0; a0 < cnt; a0 += 4) {  // 4 accepted rows (20 loads) in flight per thread
-        T x[4][5];
-        int e[4];
-        bool ok[4];
+    // RB accepted rows (5 RB loads) in flight per thread
+    for (int a0 = 0; a0 < cnt; a0 += RB) {
+        T x[RB][5];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int a = a0 + q;
-            e[q] = a < cnt ? v.welec[(size_t)w * K + a] : -1;
-            const int sl = a < cnt ? v.wslot[(size_t)w * K + a] : -1;
-            ok[q] = e[q] >= 0 && e[q] < n && sl >= 0 && sl < v.QR;  // bad entries: reported by the column kernel
-            const T* src = v.stage + ((size_t)w * v.QR + (ok[q] ? sl : 0)) * 5 * (size_t)n + l;
+        for (int q = 0; q < RB; ++q) {
+            const int a = (a0 + q) & (D - 1);
+            const T* src = v.stage + ((size_t)w * v.QR + s_sl[a]) * 5 * (size_t)n + l;
 #pragma unroll
-            for (int p = 0; p < 5; ++p) x[q][p] = ok[q] ? src[(size_t)p * n] : (T)0;
+            for (int p = 0; p < 5; ++p) x[q][p] = src[(size_t)p * n];
         }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            if (!ok[q]) continue;
-            T* dst = v.VGL + (((size_t)w * 2 + spin) * n + e[q]) * 5 * (size_t)n + l;
+        for (int q = 0; q < RB; ++q) {
+            const int a = a0 + q, ea = s_e[a & (D - 1)];
+            if (a >= cnt || ea < 0) continue;
+            T* dst = v.VGL + (((size_t)w * 2 + spin) * n + ea) * 5 * (size_t)n + l;
 #pragma unroll
             for (int p = 0; p < 5; ++p) dst[(size_t)p * n] = x[q][p];
         }
@@ -977,7 +994,7 @@ template <typename T>
 void launch_batch_rows(const CrowdView<T>& v, int spin, hipStream_t s)
 {
     if (!v.ub) return;
-    hipLaunchKernelGGL(k_rows<T>, dim3(v.W * ((v.n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, v, spin);
+    hipLaunchKernelGGL(k_rows<T>, dim3(xcd_grid(v.W, (v.n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, v, spin);
 }
 
 template <typename T>
