@@ -148,7 +148,7 @@ __global__ __launch_bounds__(kBlock) void k_stencils(CrowdView<T> v, int spin, i
 // planes of 16 loads.  The grid is persistent (a few workgroups per CU, each
 // taking groups of pp proposals in turn), so that the decision, column and update
 // kernels of the current round still find room on every CU while it runs.
-template <typename T>
+template <typename T, bool ONE>  // ONE: one proposal per workgroup at a time (pp == 1)
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_prop_vgl(CrowdView<T> v, int spin, int pp, int par)
 {
     constexpr int VEC = 16 / sizeof(T);
@@ -164,7 +164,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
     const int p = tid / tpp, t0 = tid % tpp;
     const int nchunk = (nprop + pp - 1) / pp;
 
-    if (pp == 1) {
+    if constexpr (ONE) {
         // One proposal per chunk (large N).  The stencil of the block's next proposal
         // is loaded while the current one is gathered, and the cursor range of the
         // proposal after that one chunk earlier still, so that no global round trip
@@ -393,14 +393,13 @@ __global__ __launch_bounds__(kBlock) void k_jd(CrowdView<T> v, int spin)
 // does three times the work between its loads and its stores.
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 constexpr int kPB = 16;   // block edge
-constexpr int kPTJ = 3;   // column blocks per workgroup
+constexpr int kPTJ = 3;   // column blocks per workgroup (when a block row has that many)
 
-template <typename T>
+template <typename T, int TJ>  // TJ column blocks per workgroup, sharing the row operand
 __global__ __launch_bounds__(kBlock) void k_pmat(CrowdView<T> v, int spin)
 {
     constexpr int VEC = 16 / sizeof(T);
     constexpr int KC = 4 * VEC;  // k values per chunk
-    constexpr int TJ = kPTJ;     // column blocks per workgroup, sharing the row operand
     __shared__ double sP[4][TJ][kPB][kPB + 1];
     const int Q = v.Q, n = v.n;
     const int nb = (Q + kPB - 1) / kPB, nbg = (nb + TJ - 1) / TJ;
@@ -980,7 +979,10 @@ void launch_batch_vgl(const CrowdView<T>& v, int spin, int par, bool beside, hip
     const int nchunk = (v.W * v.Q + pp - 1) / pp;
     const int nb = std::min(nchunk, (beside ? kVglBlocksPerCU : kVglBlocksPerCUAlone) * device_cu_count());
     const size_t lds = (size_t)pp * (64 * sizeof(size_t) + 64 * 5 * sizeof(T)) + 4 * sizeof(int);
-    hipLaunchKernelGGL(k_prop_vgl<T>, dim3(nb), dim3(batch_threads(v.n, sizeof(T))), lds, s, v, spin, pp, par);
+    if (pp == 1)
+        hipLaunchKernelGGL((k_prop_vgl<T, true>), dim3(nb), dim3(batch_threads(v.n, sizeof(T))), lds, s, v, spin, pp, par);
+    else
+        hipLaunchKernelGGL((k_prop_vgl<T, false>), dim3(nb), dim3(batch_threads(v.n, sizeof(T))), lds, s, v, spin, pp, par);
 }
 
 template <typename T>
@@ -1001,7 +1003,11 @@ template <typename T>
 void launch_batch_pmat(const CrowdView<T>& v, int spin, hipStream_t s)
 {
     const int pb = (v.Q + kPB - 1) / kPB;
-    hipLaunchKernelGGL(k_pmat<T>, dim3(xcd_grid(v.W, pb * ((pb + kPTJ - 1) / kPTJ))), dim3(kBlock), 0, s, v, spin);
+    if (pb >= kPTJ)  // a block row of at least kPTJ blocks: kPTJ per workgroup
+        hipLaunchKernelGGL((k_pmat<T, kPTJ>), dim3(xcd_grid(v.W, pb * ((pb + kPTJ - 1) / kPTJ))), dim3(kBlock), 0, s, v,
+                           spin);
+    else
+        hipLaunchKernelGGL((k_pmat<T, 1>), dim3(xcd_grid(v.W, pb * pb)), dim3(kBlock), 0, s, v, spin);
 }
 
 template <typename T>
