@@ -163,8 +163,25 @@ cq_status cq_crowd_run_vmc(cq_crowd* c, int n_sweeps, double sigma);
 
 /* Recompute every inverse and log|det| from the current rows in FP64 now.
    If max_drift is non-NULL it receives max |log|det| kept - log|det| recomputed|
-   over walkers and spins.  Synchronous. */
+   over walkers and spins.  Synchronous.  CQ_ESINGULAR if a matrix is singular or
+   not finite (the message names the walker). */
 cq_status cq_crowd_recompute(cq_crowd* c, double* max_drift);
+
+/* Drift record of the FP64 recomputes (the periodic ones inside run_vmc / run_dmc,
+   every recompute_every sweeps or generations, and cq_crowd_recompute):
+   last [W][2] (may be NULL): |log|det| kept - log|det| recomputed| at the last
+   inversion of each walker and spin; max_drift (may be NULL): the largest drift of
+   any recompute since the positions were set (+inf if one was not finite);
+   n_recomputes (may be NULL): how many recomputes ran since then.  Synchronises
+   the crowd's stream. */
+cq_status cq_crowd_get_drift(cq_crowd* c, double* last, double* max_drift, int* n_recomputes);
+
+/* The get calls below synchronise the crowd's stream, copy to caller-owned host
+   memory and then report any error the asynchronous run left on the device:
+   CQ_ESINGULAR when a recompute inside run_vmc / run_dmc met a singular or
+   non-finite matrix, CQ_ESTATE when the update-window bookkeeping went out of range
+   (an internal error); the message names the walker.  The data are copied either
+   way. */
 
 /* log|det A_sigma| [W][2] (FP64) and sign [W][2] (+1/-1). */
 cq_status cq_crowd_get_logdet(cq_crowd* c, double* logdet, int* sign);

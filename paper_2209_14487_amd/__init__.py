@@ -60,6 +60,7 @@ _SIGS = {
     "cq_crowd_get_delay_rank": [_P, _P],
     "cq_crowd_get_uids": [_P, _P],
     "cq_crowd_recompute": [_P, _P],
+    "cq_crowd_get_drift": [_P, _P, _P, _P],
     "cq_crowd_get_logdet": [_P, _P, _P],
     "cq_crowd_get_acceptance": [_P, _P, _P],
     "cq_crowd_get_local_energy": [_P, _P],
@@ -238,6 +239,15 @@ class Crowd:
         d = ctypes.c_double()
         _check(lib().cq_crowd_recompute(self._h, ctypes.byref(d)))
         return d.value
+
+    def drift(self):
+        """(drift [W][2] at the last inversion, largest drift of any recompute since the positions
+        were set, number of recomputes since then); drift = |log|det| kept - log|det| recomputed|."""
+        last = np.zeros((self.W, 2))
+        m = ctypes.c_double()
+        k = ctypes.c_int()
+        _check(lib().cq_crowd_get_drift(self._h, last.ctypes.data, ctypes.byref(m), ctypes.byref(k)))
+        return last, m.value, k.value
 
     def logdet(self):
         ld = np.zeros((self.W, 2))

@@ -123,6 +123,8 @@ struct cq_crowd {
     cq::Params* prm = nullptr;
     int* status = nullptr;
     double* drift = nullptr;
+    unsigned long long* drift_max = nullptr;  // [1]: largest in-run drift since set_positions
+    int n_recomputes = 0;                     // in-run recomputes since set_positions
     cq::InvWork inv{};
     // parity mode
     int rec_cap = 0;
@@ -137,6 +139,9 @@ struct cq_crowd {
     bool ready = false;
     int since_recompute = 0;
     hipGraphExec_t gexec = nullptr;
+    // first failing event / wait call while a sweep is enqueued (the enqueue helpers are
+    // void, so they keep it here and the calling entry point reports it)
+    hipError_t enq_err = hipSuccess;
     // timing
     int timing_mask = 0;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[CQ_KERNEL_COUNT];
@@ -205,6 +210,7 @@ cq::CrowdView<T> view(const cq_crowd* c)
     v.forced = c->forced;
     v.status = c->status;
     v.drift = c->drift;
+    v.drift_max = c->drift_max;
     return v;
 }
 
@@ -230,14 +236,16 @@ void timed_begin(cq_crowd* c, int kind, hipStream_t st = nullptr)
         if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return; }
         pool.push_back({a, b});
     }
-    (void)hipEventRecord(pool[c->ev_used[kind]].first, st ? st : c->stream);
+    const hipError_t e = hipEventRecord(pool[c->ev_used[kind]].first, st ? st : c->stream);
+    if (e != hipSuccess && c->enq_err == hipSuccess) c->enq_err = e;
 }
 
 void timed_end(cq_crowd* c, int kind, hipStream_t st = nullptr)
 {
     if (!(c->timing_mask >> kind & 1) || c->ev_used[kind] >= (size_t)kEventCap || c->ev_used[kind] >= c->ev[kind].size())
         return;
-    (void)hipEventRecord(c->ev[kind][c->ev_used[kind]].second, st ? st : c->stream);
+    const hipError_t e = hipEventRecord(c->ev[kind][c->ev_used[kind]].second, st ? st : c->stream);
+    if (e != hipSuccess && c->enq_err == hipSuccess) c->enq_err = e;
     c->ev_used[kind]++;
 }
 
@@ -271,6 +279,9 @@ void enqueue_sweep(cq_crowd* c)
         };
         const bool overlap = c->stream2 != nullptr && (int)c->ev_gat.size() >= total;
         hipStream_t s1 = c->stream, s2 = c->stream2;
+        auto keep = [&](hipError_t e) {
+            if (e != hipSuccess && c->enq_err == hipSuccess) c->enq_err = e;
+        };
         for (int spin = 0; spin < 2; ++spin) {
             const int q0 = spin * rounds;
             gather(q0, s1);
@@ -278,12 +289,12 @@ void enqueue_sweep(cq_crowd* c)
             for (int r = 0; r < rounds; ++r) {
                 const int q = q0 + r;
                 const bool next = r + 1 < rounds;
-                if (overlap && r > 0) (void)hipStreamWaitEvent(s1, c->ev_gat[q], 0);
+                if (overlap && r > 0) keep(hipStreamWaitEvent(s1, c->ev_gat[q], 0));
                 timed_begin(c, CQ_KERNEL_RESOLVE);
                 cq::launch_batch_pmat<T>(v, spin, s1);
                 if (overlap && next) {
-                    (void)hipEventRecord(c->ev_fork[q], s1);
-                    (void)hipStreamWaitEvent(s2, c->ev_fork[q], 0);
+                    keep(hipEventRecord(c->ev_fork[q], s1));
+                    keep(hipStreamWaitEvent(s2, c->ev_fork[q], 0));
                     gather(q + 1, s2);
                 }
                 cq::launch_batch_decide<T>(v, spin, r & 1, s1);
@@ -291,11 +302,11 @@ void enqueue_sweep(cq_crowd* c)
                 // the accepted rows go into the walker's matrices beside the update (before
                 // the next decisions overwrite the window, before gather(r+2) reuses the slots)
                 if (overlap && next) {
-                    (void)hipEventRecord(c->ev_dec[q], s1);
-                    (void)hipStreamWaitEvent(s2, c->ev_dec[q], 0);
+                    keep(hipEventRecord(c->ev_dec[q], s1));
+                    keep(hipStreamWaitEvent(s2, c->ev_dec[q], 0));
                     jastrow(q + 1, s2);
                     cq::launch_batch_rows<T>(v, spin, s2);
-                    (void)hipEventRecord(c->ev_gat[q + 1], s2);
+                    keep(hipEventRecord(c->ev_gat[q + 1], s2));
                 } else {
                     cq::launch_batch_rows<T>(v, spin, s1);
                 }
@@ -376,6 +387,17 @@ void inverse(cq_crowd* c)
         enqueue_inverse<float>(c);
 }
 
+// The first error of the launches and event calls enqueued since the last check.
+cq_status enqueue_status(cq_crowd* c, const char* where)
+{
+    hipError_t e = c->enq_err;
+    c->enq_err = hipSuccess;
+    const hipError_t l = hipGetLastError();
+    if (e == hipSuccess) e = l;
+    if (e != hipSuccess) return fail(CQ_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
+    return CQ_OK;
+}
+
 cq_status push_params(cq_crowd* c)
 {
     HIP_TRY(hipStreamSynchronize(c->stream));
@@ -396,7 +418,13 @@ cq_status build_graph(cq_crowd* c)
     hipGraph_t g = nullptr;
     HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
     sweep(c);
+    const hipError_t eq = c->enq_err;
+    c->enq_err = hipSuccess;
     hipError_t e = hipStreamEndCapture(c->stream, &g);
+    if (e == hipSuccess && eq != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return fail(CQ_EDEVICE, std::string("sweep capture: ") + hipGetErrorString(eq));
+    }
     if (e != hipSuccess) return fail(CQ_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
     e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
@@ -446,6 +474,9 @@ cq_status setup_state(cq_crowd* c)
     HIP_TRY(hipGetLastError());
     enqueue_inverse<T>(c);
     HIP_TRY(hipGetLastError());
+    // the set-up inversion is no recompute: the drift record starts after it
+    HIP_TRY(hipMemsetAsync(c->drift_max, 0, sizeof(unsigned long long), c->stream));
+    c->n_recomputes = 0;
     cq::launch_energy<T>(v, c->stream);
     HIP_TRY(hipGetLastError());
     return check_singular(c, "set_positions");
@@ -503,7 +534,7 @@ cq_status ensure_dmc(cq_crowd* c, int n_gen)
 }
 
 template <typename T>
-void dmc_generation(cq_crowd* c, int gen, int n_target, double tau)
+void dmc_generation(cq_crowd* c, int gen, int n_target, double tau, bool recompute)
 {
     cq::CrowdView<T> v = view<T>(c);
     v.ct = nullptr;  // the per-move kernel leaves the window's columns in row layout
@@ -518,6 +549,8 @@ void dmc_generation(cq_crowd* c, int gen, int n_target, double tau)
             cq::launch_flush<T>(v, spin, c->stream, false);
             timed_end(c, CQ_KERNEL_UPDATE);
         }
+    // the periodic FP64 recompute, before the energy and the branching read the inverses
+    if (recompute) enqueue_inverse<T>(c);
     timed_begin(c, CQ_KERNEL_ENERGY);
     cq::launch_energy<T>(v, c->stream);
     timed_end(c, CQ_KERNEL_ENERGY);
@@ -806,6 +839,7 @@ cq_status cq_crowd_create(const cq_system* const* systems, const int* walkers_pe
         {(void**)&c->prm, sizeof(cq::Params)},
         {(void**)&c->status, sizeof(int) * Wc},
         {(void**)&c->drift, sizeof(double) * Wc * 2},
+        {(void**)&c->drift_max, sizeof(unsigned long long)},
     };
     for (auto& e : plan) {
         cq_status st = dev_alloc(c, e.p, e.bytes);
@@ -902,14 +936,20 @@ static cq_status autotune_k(cq_crowd* c, int sweeps, int* chosen)
             else
                 cq::launch_first_proposal<float>(view<float>(c), c->stream);
         }
-        (void)hipEventRecord(a, c->stream);
+        hipError_t er = hipEventRecord(a, c->stream);
         for (int s = 0; s < sweeps; ++s) {
             sweep(c);
             c->hp.step += 1;
             c->hp.rec_sweep += 1;
         }
-        (void)hipEventRecord(b, c->stream);
-        HIP_TRY(hipEventSynchronize(b));
+        if (er == hipSuccess) er = hipEventRecord(b, c->stream);
+        if (er == hipSuccess) er = hipEventSynchronize(b);
+        cq_status es = enqueue_status(c, "autotune sweep");
+        if (er != hipSuccess || es != CQ_OK) {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+            return es != CQ_OK ? es : fail(CQ_EDEVICE, std::string("autotune events: ") + hipGetErrorString(er));
+        }
         float ms = 0.0f;
         HIP_TRY(hipEventElapsedTime(&ms, a, b));
         if (best_ms == 0.0f || ms < best_ms) {
@@ -970,12 +1010,14 @@ cq_status cq_crowd_run_vmc(cq_crowd* c, int n_sweeps, double sigma)
         c->hp.step += 1;
         c->hp.rec_sweep += 1;
         if (c->recompute_every > 0 && ++c->since_recompute >= c->recompute_every) {
+            // singular or non-finite pivots set the walker's status bit, which the next
+            // synchronising call reports; the drift goes into the crowd's drift record
             inverse(c);
             c->since_recompute = 0;
+            c->n_recomputes++;
         }
     }
-    HIP_TRY(hipGetLastError());
-    return CQ_OK;
+    return enqueue_status(c, "run_vmc");
 }
 
 cq_status cq_crowd_run_dmc(cq_crowd* c, int n_generations, double tau, double e_trial, int n_target,
@@ -998,11 +1040,17 @@ cq_status cq_crowd_run_dmc(cq_crowd* c, int n_generations, double tau, double e_
     HIP_TRY(hipMemcpy(c->dmc_state, &ds, sizeof(ds), hipMemcpyHostToDevice));
     drop_graph(c);  // walker buffers and the population change from here on
     for (int gen = 0; gen < n_generations; ++gen) {
+        const bool rc = c->recompute_every > 0 && ++c->since_recompute >= c->recompute_every;
+        if (rc) {
+            c->since_recompute = 0;
+            c->n_recomputes++;
+        }
         if (c->prec == CQ_FP64)
-            dmc_generation<double>(c, gen, n_target, tau);
+            dmc_generation<double>(c, gen, n_target, tau, rc);
         else
-            dmc_generation<float>(c, gen, n_target, tau);
-        HIP_TRY(hipGetLastError());
+            dmc_generation<float>(c, gen, n_target, tau, rc);
+        cq_status es = enqueue_status(c, "run_dmc");
+        if (es != CQ_OK) return es;
         HIP_TRY(hipStreamSynchronize(c->stream));
         HIP_TRY(hipMemcpy(&ds, c->dmc_state, sizeof(ds), hipMemcpyDeviceToHost));
         c->hp.step += 1;
@@ -1043,6 +1091,8 @@ cq_status cq_crowd_recompute(cq_crowd* c, double* max_drift)
     if (!c->ready) return fail(CQ_ESTATE, "set positions before recomputing");
     inverse(c);
     HIP_TRY(hipGetLastError());
+    c->since_recompute = 0;
+    c->n_recomputes++;
     cq_status st = check_singular(c, "recompute");
     if (st != CQ_OK) return st;
     if (max_drift) {
@@ -1064,12 +1114,21 @@ static cq_status copy_out(cq_crowd* c, void* dst, const void* src, size_t bytes)
     return CQ_OK;
 }
 
+// Every get call ends here: the walkers' status bits (a singular or non-finite matrix at
+// an in-run recompute, window bookkeeping out of range) become the call's status, so an
+// error inside an asynchronous run surfaces at the first synchronising call after it.
+static cq_status got(cq_crowd* c, cq_status st, const char* where)
+{
+    if (st != CQ_OK) return st;
+    return check_singular(c, where);
+}
+
 cq_status cq_crowd_get_logdet(cq_crowd* c, double* logdet, int* sign)
 {
     if (!c) return fail(CQ_EINVAL, "crowd is NULL");
     cq_status st = copy_out(c, logdet, c->logdet, sizeof(double) * 2 * c->W);
     if (st != CQ_OK) return st;
-    return copy_out(c, sign, c->sign, sizeof(int) * 2 * c->W);
+    return got(c, copy_out(c, sign, c->sign, sizeof(int) * 2 * c->W), "get_logdet");
 }
 
 cq_status cq_crowd_get_acceptance(cq_crowd* c, int64_t* accepted, int64_t* proposed)
@@ -1077,26 +1136,41 @@ cq_status cq_crowd_get_acceptance(cq_crowd* c, int64_t* accepted, int64_t* propo
     if (!c) return fail(CQ_EINVAL, "crowd is NULL");
     cq_status st = copy_out(c, accepted, c->nacc, sizeof(int64_t) * c->W);
     if (st != CQ_OK) return st;
-    return copy_out(c, proposed, c->nprop, sizeof(int64_t) * c->W);
+    return got(c, copy_out(c, proposed, c->nprop, sizeof(int64_t) * c->W), "get_acceptance");
 }
 
 cq_status cq_crowd_get_local_energy(cq_crowd* c, double* e_l)
 {
     if (!c) return fail(CQ_EINVAL, "crowd is NULL");
-    return copy_out(c, e_l, c->eloc, sizeof(double) * c->W);
+    return got(c, copy_out(c, e_l, c->eloc, sizeof(double) * c->W), "get_local_energy");
 }
 
 cq_status cq_crowd_get_positions(cq_crowd* c, double* R, int* n_walkers_per_system)
 {
     if (!c) return fail(CQ_EINVAL, "crowd is NULL");
     if (n_walkers_per_system) n_walkers_per_system[0] = c->W;
-    return copy_out(c, R, c->R, sizeof(double) * c->W * c->ne * 3);
+    return got(c, copy_out(c, R, c->R, sizeof(double) * c->W * c->ne * 3), "get_positions");
+}
+
+cq_status cq_crowd_get_drift(cq_crowd* c, double* last, double* max_drift, int* n_recomputes)
+{
+    if (!c) return fail(CQ_EINVAL, "crowd is NULL");
+    cq_status st = copy_out(c, last, c->drift, sizeof(double) * 2 * c->W);
+    if (st != CQ_OK) return st;
+    unsigned long long bits = 0;
+    st = copy_out(c, &bits, c->drift_max, sizeof(bits));
+    if (st != CQ_OK) return st;
+    double m;
+    std::memcpy(&m, &bits, sizeof(m));
+    if (max_drift) *max_drift = m;
+    if (n_recomputes) *n_recomputes = c->n_recomputes;
+    return got(c, CQ_OK, "get_drift");
 }
 
 cq_status cq_crowd_get_uids(cq_crowd* c, uint32_t* uids)
 {
     if (!c) return fail(CQ_EINVAL, "crowd is NULL");
-    return copy_out(c, uids, c->uid, sizeof(uint32_t) * c->W);
+    return got(c, copy_out(c, uids, c->uid, sizeof(uint32_t) * c->W), "get_uids");
 }
 
 cq_status cq_crowd_get_inverse(cq_crowd* c, double* ainv)
@@ -1106,7 +1180,7 @@ cq_status cq_crowd_get_inverse(cq_crowd* c, double* ainv)
     const size_t n = c->n, cnt = (size_t)c->W * 2 * n * n;
     const size_t es = c->prec == CQ_FP64 ? 8 : 4;
     std::vector<unsigned char> raw(cnt * es);
-    cq_status st = copy_out(c, raw.data(), c->M, cnt * es);
+    cq_status st = got(c, copy_out(c, raw.data(), c->M, cnt * es), "get_inverse");
     if (st != CQ_OK) return st;
     for (size_t m = 0; m < (size_t)c->W * 2; ++m)
         for (size_t i = 0; i < n; ++i)
@@ -1182,7 +1256,7 @@ cq_status cq_crowd_get_move_records(cq_crowd* c, double* rho, double* dlnj, doub
     if (st == CQ_OK) st = copy_out(c, dlnj, c->rec_dlnj, cnt * 8);
     if (st == CQ_OK) st = copy_out(c, prob, c->rec_prob, cnt * 8);
     if (st == CQ_OK) st = copy_out(c, acc, c->rec_acc, cnt);
-    return st;
+    return got(c, st, "get_move_records");
 }
 
 cq_status cq_crowd_set_kernel_timing(cq_crowd* c, int kind_mask)

@@ -107,6 +107,8 @@ struct CrowdView {
     int* status;         // [W] bit 0: singular / not finite at the last inversion; bit 1: window
                          // bookkeeping out of range (internal error)
     double* drift;       // [W][2] |log|det| kept - recomputed| at the last inversion
+    unsigned long long* drift_max;  // largest drift of any inversion since the positions were set (FP64
+                                    // bit pattern: non-negative doubles order like their patterns)
 };
 
 // DMC population state on the device.

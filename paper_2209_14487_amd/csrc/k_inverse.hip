@@ -134,7 +134,9 @@ __global__ __launch_bounds__(kBlock) void k_gj_small(CrowdView<T> v)
         }
         const int sgn = ((negs + parity) & 1) ? -1 : 1;
         const double old = v.logdet[w * 2 + spin];
-        v.drift[w * 2 + spin] = fabs(old - logabs);
+        const double d = fabs(old - logabs);
+        v.drift[w * 2 + spin] = d;
+        if (v.drift_max) atomicMax(v.drift_max, (unsigned long long)__double_as_longlong(isfinite(d) ? d : INFINITY));
         v.logdet[w * 2 + spin] = logabs;
         v.sign[w * 2 + spin] = sgn;
         if (bad) atomicOr(&v.status[w], 1);
@@ -422,7 +424,9 @@ __global__ __launch_bounds__(kBlock) void k_gj_finish(CrowdView<T> v, const doub
         for (int i = 0; i < n; ++i) seen[i] = 0;
         const int sgn = ((negs[mat] + parity) & 1) ? -1 : 1;
         const double old = v.logdet[w * 2 + spin];
-        v.drift[w * 2 + spin] = fabs(old - logabs[mat]);
+        const double d = fabs(old - logabs[mat]);
+        v.drift[w * 2 + spin] = d;
+        if (v.drift_max) atomicMax(v.drift_max, (unsigned long long)__double_as_longlong(isfinite(d) ? d : INFINITY));
         v.logdet[w * 2 + spin] = logabs[mat];
         v.sign[w * 2 + spin] = sgn;
         if (mstatus[mat]) atomicOr(&v.status[w], 1);

@@ -507,3 +507,90 @@ def test_dmc_branching_multiplicity_cap():
     assert np.array_equal(res.uids[::3], np.arange(12))
     assert np.array_equal(res.R[1::3], res.R[::3])
     assert res.uids[1] == orc.child_uid(19, 0, 0, 1)
+
+
+def test_dmc_reweighting_averages_old_and_new_clipped_energies():
+    """The branching weight of a generation is exp(-tau ((E_c(old) + E_c(new)) / 2 - E_T)) with
+    both local energies clipped to E_T +- 0.2 sqrt(Ne / tau).  The generation's moves are replayed
+    here with the per-move functions (drift, Green's-function acceptance), the two local energies
+    of every walker come from finite differences of the directly evaluated wavefunction, and the
+    weights, their sum, the weighted energy, the multiplicities floor(w + u_b) (capped at 3), the
+    children's configurations and the new trial energy are formed by hand from them."""
+    # analytic plane-wave orbitals with the Pade J2: E_L varies smoothly with the positions, so
+    # most energies stay inside the clip window (a random spline table spreads them over tens of Ha)
+    n, W, tau = 4, 12, 0.05
+    s = orc.System(n, n, 5.0, n_orb=n, orb_kind=orc.ORB_PLANEWAVE, use_j2=True, seed=18)
+    d = Direct(n, n, 5.0, planewave=True, use_j2=True, seed=18)
+    R0 = start_positions(84, W, 2 * n, s.L)
+    e_old = np.array([d.eloc_fd(R0[w]) for w in range(W)])
+    e_t = float(np.median(e_old))
+    ecut = 0.2 * np.sqrt(2 * n / tau)
+    res = orc.dmc(s, R0, 1, tau=tau, e_trial=e_t, n_target=W, max_pop=64)
+    R1 = R0.copy()
+    for w in range(W):
+        for e in range(2 * n):
+            v = orc.drift(s, R1[w], e)
+            delta = tau * v + np.sqrt(tau) * orc.gauss3(18, w, 0, e)
+            p, rho = orc.dmc_move_prob(s, R1[w], e, delta, tau)
+            if rho > 0.0 and orc.accept_uniform(18, w, 0, e) < p:
+                R1[w, e] = R1[w, e] + delta
+                R1[w, e] -= s.L * np.floor(R1[w, e] / s.L)
+    e_new = np.array([d.eloc_fd(R1[w]) for w in range(W)])
+    eo = np.clip(e_old, e_t - ecut, e_t + ecut)
+    en = np.clip(e_new, e_t - ecut, e_t + ecut)
+    # the case under test: energies that moved, inside the clip window on both sides
+    free = (np.abs(e_old - e_t) < ecut) & (np.abs(e_new - e_t) < ecut) & (np.abs(e_new - e_old) > 0.05)
+    assert free.sum() >= 3
+    wt = np.exp(-tau * (0.5 * (eo + en) - e_t))
+    mult = np.minimum(3, np.floor(wt + np.array([orc.branch_uniform(18, w, 0) for w in range(W)]))).astype(int)
+    assert res.pop[0] == mult.sum()
+    assert abs(res.wsum[0] - wt.sum()) < 1e-6 * wt.sum()
+    e_est = (wt * e_new).sum() / wt.sum()
+    assert abs(res.e_est[0] - e_est) < 1e-5 * max(1.0, abs(e_est))
+    assert abs(res.e_t[0] - (e_est - np.log(mult.sum() / W) / tau)) < 1e-5 * max(1.0, abs(e_est))
+    assert np.allclose(res.R, np.repeat(R1, mult, axis=0), atol=1e-12)
+    # a weight from the new energy alone would be off by far more than the tolerance above
+    wt_new_only = np.exp(-tau * (en - e_t))
+    assert abs(wt_new_only.sum() - wt.sum()) > 1e-3 * wt.sum()
+
+
+# ---------------------------------------------------- FP32 rounding model
+
+def test_fp32_chain_model_without_rounding_is_the_oracle_chain():
+    """The rounding model of the mixed-precision chain, with nothing rounded, replays the FP64
+    oracle's Sherman-Morrison chain along its decisions: the same ratios to 1e-12, across
+    accepted updates, both spin blocks, several sweeps and a periodic recompute (which changes
+    nothing in exact arithmetic)."""
+    from oracle import fp32_chain
+    n = 3
+    s, _ = _tiny_system(n, j2=True, seed=21)
+    R0 = start_positions(85, 2, 2 * n, s.L)
+    ref = orc.vmc(s, R0, 4, sigma=0.6)
+    assert ref.acc.mean() > 0.2
+    for w in range(2):
+        rho = fp32_chain.replay(s, R0[w], w, ref.acc[:, :, w], sigma=0.6, recompute_every=2, storage="fp64")
+        assert np.allclose(rho, ref.rho[:, :, w], rtol=1e-12, atol=1e-14)
+
+
+def test_fp32_chain_model_rounds_to_single_precision():
+    """With FP32 storage the model's ratios differ from the FP64 chain by FP32 rounding: on a
+    well-conditioned 4 x 4 system every relative error is below 1e-5, and the typical one is of
+    the order of the FP32 unit round-off (2^-24 = 6e-8), neither zero nor larger; the error is
+    the same whether the update is formed in FP32 or in FP64 from the stored values, to that
+    order."""
+    from oracle import fp32_chain
+    n = 4
+    s, _ = _tiny_system(n, j2=True, seed=22)
+    R0 = start_positions(86, 3, 2 * n, s.L)
+    ref = orc.vmc(s, R0, 3, sigma=0.5)
+    for arith in ("fp32", "fp64"):
+        rel = []
+        for w in range(3):
+            rho = fp32_chain.replay(s, R0[w], w, ref.acc[:, :, w], sigma=0.5, storage="fp32", arith=arith)
+            big = np.abs(ref.rho[:, :, w]) > 0.05
+            rel.append((np.abs(rho - ref.rho[:, :, w]) / np.abs(ref.rho[:, :, w]))[big])
+        rel = np.concatenate(rel)
+        assert rel.max() < 1e-5, (arith, rel.max())
+        assert 1e-9 < np.median(rel) < 2e-6, (arith, np.median(rel))
+    st = fp32_chain.ratio_error_stats(rho, ref.rho[:, :, 2])
+    assert st["n"] == 3 * 2 * n and st["median"] <= st["p99"] <= st["p999"]
