@@ -51,6 +51,11 @@ def parse():
     ap.add_argument("--eager", action="store_true", help="skip the extra hipGraph replay run")
     ap.add_argument("--path", default="auto", choices=["auto", "multi", "window", "batch"],
                     help="mapping of the moves to the GPU")
+    ap.add_argument("--sm-steps", type=int, default=1,
+                    help="sweeps of the FP64 Sherman-Morrison (k = 1) run that measures the SM update's "
+                         "HBM GB/s (0: skip)")
+    ap.add_argument("--cpu-one-core-moves", type=int, default=1024,
+                    help="moves of the one-core CPU oracle figure (0: skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 1 GiB with the library's plain copy kernel (counter calibration runs)")
     return ap.parse_args()
@@ -86,6 +91,7 @@ def run_gpu(cq, wl, precision, delay, recompute, steps, warmup, timing_kinds, us
     for c in crowds:
         c.synchronize()
     acc0 = sum(int(c.acceptance()[0].sum()) for c in crowds)
+    rec0 = sum(c.drift()[2] for c in crowds)
     for c in crowds:
         c.set_timing(timing_kinds)
     t0 = time.perf_counter()
@@ -106,6 +112,18 @@ def run_gpu(cq, wl, precision, delay, recompute, steps, warmup, timing_kinds, us
     prop = sum(int(c.acceptance()[1].sum()) for c in crowds)
     k_used = crowds[0].delay_rank()
     el = np.concatenate([c.local_energy() for c in crowds])
+    # FP64 recomputes that fell inside the timed sweeps, and their device time
+    n_rec = sum(c.drift()[2] for c in crowds) - rec0
+    rec_ms_in = kt["inverse"][0] if "inverse" in kt else 0.0
+    rec_ms = None
+    if recompute > 0:
+        # one recompute of every crowd, timed alone (the recomputes of the timed sweeps are too
+        # when there were any): device time per recompute of the whole crowd set
+        for c in crowds:
+            c.set_timing(("inverse",))
+        for c in crowds:
+            c.recompute()
+        rec_ms = sum(c.kernel_timing("inverse")[0] for c in crowds)
     for c in crowds:
         c.set_timing(())
     graph_s = None
@@ -124,9 +142,16 @@ def run_gpu(cq, wl, precision, delay, recompute, steps, warmup, timing_kinds, us
         c.close()
     system.close()
     moves = wl.crowds * wl.walkers * wl.n_e * steps
-    out = dict(seconds=t1 - t0, moves=moves, moves_per_s=moves / (t1 - t0), kernels=kt, delay_rank=k_used,
+    # whole-job time: the timed sweeps with exactly steps / recompute_every recomputes in them
+    # (the recomputes that fell inside are taken out and the amortised share put in)
+    seconds = t1 - t0
+    if recompute > 0 and rec_ms is not None:
+        seconds = seconds - 1e-3 * rec_ms_in + (steps / recompute) * 1e-3 * rec_ms
+    out = dict(seconds=seconds, wall_seconds=t1 - t0, moves=moves, moves_per_s=moves / seconds,
+               wall_moves_per_s=moves / (t1 - t0), kernels=kt, delay_rank=k_used,
                accepted_timed=acc - acc0, acceptance=acc / max(prop, 1), e_mean=float(el.mean()),
-               finite=bool(np.isfinite(el).all()))
+               finite=bool(np.isfinite(el).all()), recomputes_in_timed=n_rec, recompute_ms=rec_ms,
+               recompute_ms_in_timed=rec_ms_in)
     if graph_s is not None:
         out["graph_moves_per_s"] = wl.crowds * wl.walkers * wl.n_e * graph_steps / graph_s
     return out
@@ -161,6 +186,20 @@ def rooflines(res, n, W, steps, traffic, s_c=4, s=4):
     return roof_vgl, roof_up
 
 
+def roofline_sm(res, n, s):
+    """HBM roofline of the Sherman-Morrison update (k = 1, k_flush_vec): per accepted move one read
+    and one write of the N x N inverse (2 N^2 s bytes), plus the move's value row and column read
+    and its 5 orbital rows copied (12 N s); accepted moves of the timed sweeps over the launches."""
+    ms, cnt = res["kernels"]["update"]
+    t = ms / max(cnt, 1) * 1e-3
+    acc_per_launch = res["accepted_timed"] / max(cnt, 1)
+    byts = acc_per_launch * (2.0 * n * n * s + 12.0 * n * s)
+    gbs = byts / t / 1e9
+    return dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s", frac=round(gbs / HBM_PEAK_GBS, 4),
+                traffic=None, kernel="k_flush_vec (FP64, k = 1)", us_per_launch=round(t * 1e6, 3),
+                accepted_per_launch=round(acc_per_launch, 2), bytes_per_launch=int(byts), launches=cnt)
+
+
 def kernel_source_hash():
     """SHA-256 of the sources the gather and update kernels are built from."""
     import hashlib
@@ -185,11 +224,34 @@ def measured_traffic(workload):
     return dict(vgl=rec.get("traffic_bytes_per_launch"), update=(rec.get("update") or {}).get("traffic_bytes_per_launch"))
 
 
-def cpu_baseline(wl, moves_per_walker):
-    """The FP64 oracle (OpenMP over walkers) on a bounded sample of the same workload."""
+def host_cpu():
+    """(threads the oracle may use, logical CPUs of the host, CPU model)."""
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    threads = min(avail, int(env)) if env.isdigit() and int(env) > 0 else avail
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return threads, os.cpu_count() or 1, model
+
+
+def cpu_baseline(wl, moves_per_walker, cq=None, one_core_moves=1024):
+    """The FP64 oracle (OpenMP over walkers, one walker per thread) on a bounded sample of the same
+    workload, on every core this process may use, and on one core.  With the GPU library given, the
+    same walkers also run on the GPU in mixed precision along the oracle's decisions, and the errors
+    of the GPU's ratios, log|det| and local energies against the oracle are reported."""
     import oracle as orc
     from synth import J2_A_ANTI, J2_A_PAR, J2_B, start_positions
-    threads = min(os.cpu_count() or 1, 16)
+    threads, host_cpus, model = host_cpu()
     walkers = threads
     s = orc.System(wl.n, wl.n, wl.L, G=wl.G, n_orb=wl.n, orb_kind=orc.ORB_SEEDED, coef_seed=wl.seed,
                    coef_fp32=True, use_j2=wl.use_j2, j2_a_par=J2_A_PAR, j2_a_anti=J2_A_ANTI, j2_b=J2_B,
@@ -201,10 +263,53 @@ def cpu_baseline(wl, moves_per_walker):
     # the walkers run side by side, one per thread: the slowest one's sweep time (its
     # set-up excluded, timed inside the oracle) is the time of the moves
     move_s = float(np.max(res.t_moves))
-    return dict(value=walkers * moves_per_walker / move_s, unit="moves/s", cores=threads, kind="oracle",
-                sample="%d walkers x first %d electron moves of sweep 0 (%s), FP64 scalar C + OpenMP, "
-                       "timed after each walker's set-up" % (walkers, moves_per_walker, wl.name),
-                seconds=round(t1 - t0, 1), move_seconds=round(move_s, 2))
+    out = dict(value=walkers * min(moves_per_walker, wl.n_e) / move_s, unit="moves/s", cores=threads, kind="oracle",
+               sample="%d walkers x first %d electron moves of sweep 0 (%s), FP64 scalar C + OpenMP, "
+                      "timed after each walker's set-up" % (walkers, min(moves_per_walker, wl.n_e), wl.name),
+               seconds=round(t1 - t0, 1), move_seconds=round(move_s, 2), host_logical_cpus=host_cpus,
+               cpu_model=model)
+    if one_core_moves > 0:
+        r1 = orc.vmc(s, R0[:1], 1, sigma=wl.sigma, max_moves=one_core_moves, n_threads=1)
+        m1 = min(one_core_moves, wl.n_e)
+        out["one_core"] = dict(value=round(m1 / float(r1.t_moves[0]), 1), unit="moves/s",
+                               sample="walker 0, first %d moves of sweep 0, one thread" % m1)
+    if cq is not None:
+        out["errors_vs_oracle"] = gpu_errors(cq, wl, s, R0, res, min(moves_per_walker, wl.n_e))
+    return out
+
+
+def gpu_errors(cq, wl, o, R0, ref, moves):
+    """Mixed-precision GPU chain of the sampled walkers along the oracle's decisions (forced-decision
+    mode, the workload's delay rank and path): relative errors of the ratios against the FP64
+    oracle, and of log|det| and E_L at the end of the sweep when the sample covers it."""
+    from oracle import fp32_chain
+    W = R0.shape[0]
+    system = make_system(cq, wl, 4)
+    c = cq.Crowd(system, W, precision="mixed", delay_rank=wl.delay_rank, recompute_every=wl.recompute_every,
+                 seed=wl.seed, use_graph=False)
+    c.set_positions(R0)
+    forced = np.full((1, wl.n_e, W), 2, np.uint8)
+    forced[0, :moves] = ref.acc[0, :moves]
+    c.record(1)
+    c.set_forced(forced)
+    c.run_vmc(1, wl.sigma)
+    rec = c.records()
+    ld, _ = c.logdet()
+    el = c.local_energy()
+    c.close()
+    system.close()
+    st = fp32_chain.ratio_error_stats(rec["rho"][0, :moves], ref.rho[0, :moves])
+    out = dict(walkers=W, moves_per_walker=moves, ratio_rel=dict((k, float("%.3g" % v)) for k, v in st.items()),
+               note="mixed-precision GPU chain along the FP64 oracle's decisions; relative ratio errors over all "
+                    "moves (max over |rho| >= 1e-3)")
+    if moves == wl.n_e:
+        lrel = np.abs(ld - ref.logdet[0]) / np.maximum(1.0, np.abs(ref.logdet[0]))
+        erel = np.abs(el - ref.eloc[0]) / np.maximum(1.0, np.abs(ref.eloc[0]))
+        out["logdet_rel_max"] = float("%.3g" % lrel.max())
+        out["eloc_rel_median"] = float("%.3g" % np.median(erel))
+        out["eloc_rel_max"] = float("%.3g" % erel.max())
+        out["eloc_bias"] = float("%.3g" % np.mean(el - ref.eloc[0]))
+    return out
 
 
 def run_c5(cq, args):
@@ -297,13 +402,16 @@ def main():
         del src, dst
         log("  copied 1 GiB with cq_device_copy (calibration)")
     kinds = [k for k in args.time_kernels.split(",") if k]
-    for k in ("vgl", "update"):  # the rooflines need these two
+    # the rooflines need the gather and the update; the recompute's device time is taken out
+    # of the timed sweeps and its amortised share put back (events only on recompute launches)
+    for k in ("vgl", "update", "inverse"):
         if k not in kinds:
             kinds.append(k)
     mixed = run_gpu(cq, wl, "mixed", delay, wl.recompute_every, args.steps, args.warmup, kinds, not args.eager,
                     path=args.path, graph_steps=0 if args.eager else max(2, args.steps // 4))
-    log("  mixed: %.3f s for %d sweeps, %.3e moves/s, acceptance %.3f"
-        % (mixed["seconds"], args.steps, mixed["moves_per_s"], mixed["acceptance"]))
+    log("  mixed: %.3f s for %d sweeps (%.3f s wall, %d recompute(s) inside), %.3e moves/s, acceptance %.3f"
+        % (mixed["seconds"], args.steps, mixed["wall_seconds"], mixed["recomputes_in_timed"],
+           mixed["moves_per_s"], mixed["acceptance"]))
 
     n, W = wl.n, wl.walkers * wl.crowds
     kinfo = {}
@@ -330,12 +438,20 @@ def main():
                            launch="eager launches; HIP events around every launch of %s in the timed region" % "/".join(kinds)),
                roofline=dominant, roofline_spline=roof_vgl, roofline_update=roof_up, kernels=kinfo,
                windows_per_sweep=windows_per_sweep,
-               acceptance=round(mixed["acceptance"], 4), e_mean=mixed["e_mean"])
+               acceptance=round(mixed["acceptance"], 4), e_mean=mixed["e_mean"],
+               recompute=dict(every=wl.recompute_every, ms_per_recompute=mixed["recompute_ms"] and round(mixed["recompute_ms"], 3),
+                              in_timed_region=mixed["recomputes_in_timed"],
+                              ms_in_timed_region=round(mixed["recompute_ms_in_timed"], 3),
+                              wall_seconds_timed=round(mixed["wall_seconds"], 4),
+                              wall_moves_per_s=round(mixed["wall_moves_per_s"], 1),
+                              note="value and ms_per_step count steps/every recomputes of the whole crowd: the "
+                                   "device time of the recomputes that fell inside the timed sweeps is replaced "
+                                   "by that share of one timed recompute"))
     if "graph_moves_per_s" in mixed:
         out["graph_moves_per_s"] = round(mixed["graph_moves_per_s"], 1)
     if args.alone_steps > 0 and args.path in ("auto", "batch"):
         # the same kernels with the GPU to themselves: one stream, every kernel in order
-        alone = run_gpu(cq, wl, "mixed", delay, wl.recompute_every, args.alone_steps, 1, ["vgl", "update"], False,
+        alone = run_gpu(cq, wl, "mixed", delay, 0, args.alone_steps, 1, ["vgl", "update"], False,
                         path=args.path, streams=1)
         a_vgl, a_up = rooflines(alone, n, W, args.alone_steps, None)
         log("  alone: k_prop_vgl %.0f GB/s, update %.1f TFLOP/s" % (a_vgl["achieved"], a_up["achieved"]))
@@ -350,9 +466,15 @@ def main():
         # both sides replay the captured sweep graph (no events), so launch overheads match
         ref = mixed.get("graph_moves_per_s", mixed["moves_per_s"])
         out["mixed_over_fp64"] = round(ref / f64["moves_per_s"], 3)
+    if args.sm_steps > 0 and args.path in ("auto", "batch"):
+        # Sherman-Morrison (k = 1) in FP64: the wave-reduced dot products and rank-1 update of
+        # k_flush_vec, judged by HBM GB/s
+        sm = run_gpu(cq, wl, "fp64", 1, 0, args.sm_steps, 0, ["update"], False, path=args.path)
+        out["roofline_sm"] = roofline_sm(sm, n, 8)
+        log("  SM update (FP64, k = 1): %.0f GB/s" % out["roofline_sm"]["achieved"])
     if not args.no_cpu:
         log("  cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_moves)
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_moves, cq, args.cpu_one_core_moves)
     print(json.dumps(out), flush=True)
 
 

@@ -194,16 +194,29 @@ cq_status cq_crowd_get_positions(cq_crowd* c, double* R, int* n_walkers_per_syst
 /* the kept inverses as FP64 [W][2][N][N], element [w][s][j][i] = (A_s^-1)[j][i]. */
 cq_status cq_crowd_get_inverse(cq_crowd* c, double* ainv);
 
-/* Parity mode: the crowd follows the given decisions flags[sweep][e][w]
-   (1 accept, 0 reject, 2 or more: the walker's own Metropolis decision) for
-   the next n_sweeps sweeps instead of its own, while still recording its own
+/* Parity-mode buffers are indexed by walker slot with the walker capacity
+   Wcap = max(initial walkers, max_walkers) as stride: [sweep or generation][e][Wcap]
+   (under DMC the slot is the walker's position in the generation's population).
+
+   The crowd follows the given decisions flags[sweep][e][Wcap] (1 accept, 0
+   reject, 2 or more: the walker's own decision) for the next n_sweeps VMC sweeps
+   or DMC generations instead of its own, while still recording its own
    probability.  flags = NULL switches it off. */
 cq_status cq_crowd_set_forced_decisions(cq_crowd* c, const uint8_t* flags, int n_sweeps);
-/* Record per-move rho_D, dlnJ, P and the decision for the next n_sweeps sweeps
-   (0 switches recording off). */
+/* DMC parity mode: the branching of the next n_generations generations gives
+   walker slot w the multiplicity mult[generation][Wcap] (0..3) instead of
+   floor(w + u_b), so the population follows a reference run; the weights, their
+   sums and E_T are still the crowd's own.  mult = NULL switches it off.
+   CQ_EINVAL for a multiplicity outside 0..3. */
+cq_status cq_crowd_set_forced_branching(cq_crowd* c, const int* mult, int n_generations);
+/* Record per-move rho_D, dlnJ, P and the decision for the next n_sweeps sweeps or
+   generations (0 switches recording off). */
 cq_status cq_crowd_record_moves(cq_crowd* c, int n_sweeps);
-/* Copy the records out: arrays [n_sweeps][Ne][W]; any pointer may be NULL. */
+/* Copy the records out: arrays [n_sweeps][Ne][Wcap]; any pointer may be NULL. */
 cq_status cq_crowd_get_move_records(cq_crowd* c, double* rho, double* dlnj, double* prob, uint8_t* acc);
+/* Drift-diffusion moves accepted and proposed over every DMC generation the crowd
+   has run (the populations that moved, before their branching). */
+cq_status cq_crowd_get_dmc_moves(cq_crowd* c, int64_t* accepted, int64_t* proposed);
 
 /* Delay-rank autotuning for a crowd created with delay_rank = 0: time
    sweeps_per_candidate sweeps (eager launches, HIP events) at every candidate

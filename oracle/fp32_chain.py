@@ -96,3 +96,80 @@ def ratio_error_stats(rho, ref, floor=1e-3):
     big = np.abs(ref[ok]) >= floor
     return dict(n=int(ok.sum()), median=float(np.median(rel)), p99=float(np.quantile(rel, 0.99)),
                 p999=float(np.quantile(rel, 0.999)), max=float(rel[big].max()) if big.any() else 0.0)
+
+
+def replay_dmc(sys, R0, uids, acc, mult, tau, first_step=0, storage="fp32"):
+    """Ratios and acceptance probabilities of a DMC population's chain (drift-diffusion moves with
+    the Green's-function acceptance, then branching; the generation loop of Alg. 1) along the
+    decisions acc [gens][Ne][cap] and multiplicities mult [gens][cap] of a reference run, with the
+    inverse, the value rows and the gradient rows stored in FP32 (``storage="fp32"``) or nothing
+    rounded (``storage="fp64"``).  Drifts are the FP64 sums of the stored gradient rows times the
+    stored inverse column plus the Jastrow gradient; the update is the FP32 Sherman-Morrison step
+    of ``replay``.  Children copy their parent's stored state; copy 0 keeps the uid, copy c >= 1
+    takes the counter-generator uid.  Returns dict(rho, prob) [gens][Ne][cap] (NaN where no
+    walker)."""
+    acc = np.asarray(acc)
+    mult = np.asarray(mult)
+    gens, ne, cap = acc.shape
+    n = sys.n_up
+    lp = storage == "fp32"
+    store = _f32 if lp else (lambda x: np.asarray(x, dtype=np.float64))
+
+    def new_state(R):
+        R = np.array(R, dtype=np.float64)
+        A, Gr = [], []
+        for sp in range(2):
+            rows = [_o.orbital_vgl(sys, R[sp * n + i], n) for i in range(n)]
+            A.append(np.array([store(r[0]) for r in rows]))
+            Gr.append(np.array([store(r[1]) for r in rows]))
+        Ai = [store(np.linalg.inv(A[sp].astype(np.float64))) for sp in range(2)]
+        return dict(R=R, A=A, G=Gr, Ai=Ai)
+
+    pop = [new_state(R0[w]) for w in range(R0.shape[0])]
+    ids = [int(u) for u in uids]
+    rho_out = np.full((gens, ne, cap), np.nan)
+    prob_out = np.full((gens, ne, cap), np.nan)
+    st = np.sqrt(tau)
+    for g in range(gens):
+        step = first_step + g
+        for slot, w in enumerate(pop):
+            R = w["R"]
+            for e in range(ne):
+                sp, i = divmod(e, n)
+                c = w["Ai"][sp][:, i].astype(np.float64)
+                jg, _ = _o.j2_terms(sys, R, e, R[e])
+                v = w["G"][sp][i].astype(np.float64).T @ c + jg
+                delta = tau * v + st * _o.gauss3(sys.seed, ids[slot], step, e)
+                rn = R[e] + delta
+                rn = rn - sys.L * np.floor(rn / sys.L)
+                val, grad, _ = _o.orbital_vgl(sys, rn, n)
+                u, gu = store(val), store(grad)
+                r = float(u.astype(np.float64) @ c)
+                jg2, dlnj = _o.j2_terms(sys, R, e, rn)
+                vn = gu.astype(np.float64).T @ c / r + jg2
+                fwd = np.sum((delta - tau * v) ** 2)
+                bwd = np.sum((delta + tau * vn) ** 2)
+                p = r * r * np.exp(2.0 * dlnj) * np.exp(-(bwd - fwd) / (2.0 * tau))
+                rho_out[g, e, slot] = r
+                prob_out[g, e, slot] = p
+                if acc[g, e, slot]:
+                    Ai = w["Ai"][sp]
+                    if lp:
+                        wrow = u @ Ai
+                        wrow[i] -= np.float32(1.0)
+                        w["Ai"][sp] = Ai - np.outer(Ai[:, i], wrow / np.float32(r))
+                    else:
+                        wrow = u @ Ai
+                        wrow[i] -= 1.0
+                        w["Ai"][sp] = Ai - np.outer(Ai[:, i], wrow) / r
+                    w["A"][sp][i] = u
+                    w["G"][sp][i] = gu
+                    R[e] = rn
+        nxt, nid = [], []
+        for slot, w in enumerate(pop):
+            for k in range(int(mult[g, slot])):
+                nxt.append(dict(R=w["R"].copy(), A=[a.copy() for a in w["A"]], G=[x.copy() for x in w["G"]],
+                                Ai=[a.copy() for a in w["Ai"]]))
+                nid.append(ids[slot] if k == 0 else _o.child_uid(sys.seed, ids[slot], step, k))
+        pop, ids = nxt, nid
+    return dict(rho=rho_out, prob=prob_out)

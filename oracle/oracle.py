@@ -52,8 +52,10 @@ def lib():
         L.or_setup.restype = ctypes.c_int
         L.or_dmc.argtypes = [ctypes.POINTER(OrSystem), ctypes.c_int, dp, dp, ctypes.c_int,
                              ctypes.c_uint32, ctypes.c_double, ctypes.c_double, ctypes.c_int,
-                             ctypes.c_int, ctypes.c_int, dp, dp, dp, dp, dp, dp, dp, dp]
+                             ctypes.c_int, ctypes.c_int, dp, dp, dp, dp, dp, dp, dp, dp,
+                             dp, dp, dp, dp, dp]
         L.or_dmc.restype = ctypes.c_int
+        L.or_j2_terms.argtypes = [ctypes.POINTER(OrSystem), dp, ctypes.c_int, dp, dp, dp]
         L.or_drift.argtypes = [ctypes.POINTER(OrSystem), dp, ctypes.c_int, dp]
         L.or_drift.restype = ctypes.c_int
         L.or_dmc_move_prob.argtypes = [ctypes.POINTER(OrSystem), dp, ctypes.c_int, dp, ctypes.c_double, dp, dp]
@@ -282,6 +284,17 @@ def setup(sys: System, R0, n_threads=0):
     return ld, sg, el, ai
 
 
+def j2_terms(sys: System, R, e, r):
+    """(grad ln J of electron e placed at r, ln J(R') - ln J(R) for the move of e to r)."""
+    R = np.ascontiguousarray(R, dtype=np.float64)
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    g = np.zeros(3)
+    d = ctypes.c_double()
+    cs = sys.c()
+    lib().or_j2_terms(ctypes.byref(cs), R.ctypes.data, e, r.ctypes.data, g.ctypes.data, ctypes.addressof(d))
+    return g, d.value
+
+
 def drift(sys: System, R, e):
     """grad ln|Psi_T| with respect to electron e at configuration R ([Ne][3])."""
     R = np.ascontiguousarray(R, dtype=np.float64)
@@ -316,11 +329,14 @@ class DmcResult:
     uids: np.ndarray      # final population
     R: np.ndarray
     eloc: np.ndarray
+    rec: Optional[dict] = None  # per-move rho, prob, u, acc [gen][Ne][max_pop]; mult [gen][max_pop]
 
 
 def dmc(sys: System, R0, n_gen, tau, e_trial, n_target=None, max_pop=None, uids=None,
-        first_step=0, n_threads=0) -> DmcResult:
-    """Run DMC generations (Alg. 1 including reweighting and branching) on one system's population."""
+        first_step=0, n_threads=0, record=False) -> DmcResult:
+    """Run DMC generations (Alg. 1 including reweighting and branching) on one system's population.
+    record=True also returns every move's rho_D, P, u and decision and every branching
+    multiplicity, indexed by the walker's position in its generation's population."""
     R0 = np.ascontiguousarray(R0, dtype=np.float64)
     W, ne = R0.shape[0], R0.shape[1]
     n_target = W if n_target is None else n_target
@@ -334,12 +350,18 @@ def dmc(sys: System, R0, n_gen, tau, e_trial, n_target=None, max_pop=None, uids=
     uo = np.zeros(max_pop, np.uint32)
     Ro = np.zeros((max_pop, ne, 3))
     eo = np.zeros(max_pop)
+    rec = None
+    if record:
+        shp = (n_gen, ne, max_pop)
+        rec = dict(rho=np.full(shp, np.nan), prob=np.full(shp, np.nan), u=np.full(shp, np.nan),
+                   acc=np.zeros(shp, np.uint8), mult=np.zeros((n_gen, max_pop), np.int32))
     cs = sys.c()
     n = lib().or_dmc(ctypes.byref(cs), W, uids.ctypes.data, R0.ctypes.data, n_gen, first_step, tau,
                      e_trial, n_target, max_pop, n_threads, pop.ctypes.data, wsum.ctypes.data,
                      eest.ctypes.data, et.ctypes.data, counts.ctypes.data, uo.ctypes.data, Ro.ctypes.data,
-                     eo.ctypes.data)
+                     eo.ctypes.data, *([_p(rec[k]) for k in ("rho", "prob", "u", "acc", "mult")] if rec
+                                       else [None] * 5))
     if n < 0:
         raise RuntimeError("oracle DMC failed with status %d" % n)
     return DmcResult(pop, wsum, eest, et, int(counts[0]), int(counts[1]), uo[:n].copy(), Ro[:n].copy(),
-                     eo[:n].copy())
+                     eo[:n].copy(), rec)

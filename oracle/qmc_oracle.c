@@ -324,6 +324,15 @@ static double j2_delta(const or_system* s, const double* R, int e, const double*
     return sum;
 }
 
+/* Test entry point: the Jastrow gradient of electron e placed at r (the other
+   electrons at R), and ln J(R') - ln J(R) for the move of e from R[e] to r. */
+void or_j2_terms(const or_system* s, const double* R, int e, const double r[3], double grad[3], double* dlnj)
+{
+    double lap;
+    j2_grad_lap(s, R, e, r, grad, &lap);
+    *dlnj = j2_delta(s, R, e, r);
+}
+
 /* ------------------------------------------------------------------------ */
 /* LU with partial pivoting (Golub & Van Loan, Alg. 3.4.1; ties -> lowest row */
 /* index), then the inverse by solving A X = I column by column.             */
@@ -813,12 +822,16 @@ int or_dmc_move_prob(const or_system* s, const double* R, int e, const double de
 /* Children follow their parent in population order; copy 0 keeps the       */
 /* parent's uid.  Returns the final population size, -1 on a singular start, */
 /* -2 if the population dies out or exceeds max_pop.                         */
+/* Optional records (any may be NULL): per move rho_D, P, u and the decision */
+/* at [(gen * Ne + e) * max_pop + walker] (walker = position in the          */
+/* generation's population), and the multiplicities at [gen * max_pop + w]. */
 /* ------------------------------------------------------------------------ */
 int or_dmc(const or_system* s, int n_walkers, const uint32_t* uids, const double* R0,
            int n_gen, uint32_t first_step, double tau, double e_trial, int n_target, int max_pop,
            int n_threads,
            int* pop_out, double* wsum_out, double* eest_out, double* et_out,
-           int64_t* counts_out, uint32_t* uids_out, double* R_out, double* eloc_out)
+           int64_t* counts_out, uint32_t* uids_out, double* R_out, double* eloc_out,
+           double* rec_rho, double* rec_prob, double* rec_u, uint8_t* rec_acc, int* mult_out)
 {
     const int ne = s->n_up + s->n_dn;
     const int nmax = s->n_up > s->n_dn ? s->n_up : s->n_dn;
@@ -859,6 +872,11 @@ int or_dmc(const or_system* s, int n_walkers, const uint32_t* uids, const double
                 double prob = dmc_move_prob(s, w, e, delta, tau, &t, rnew, &rho);
                 double u = or_accept_uniform(s->seed, w->uid, step, (uint32_t)e);
                 int acc = (rho > 0.0) && (u < prob);
+                size_t ri = ((size_t)gen * ne + e) * max_pop + iw;
+                if (rec_rho) rec_rho[ri] = rho;
+                if (rec_prob) rec_prob[ri] = prob;
+                if (rec_u) rec_u[ri] = u;
+                if (rec_acc) rec_acc[ri] = (uint8_t)acc;
                 n_prop++;
                 if (acc) {
                     n_acc++;
@@ -882,6 +900,7 @@ int or_dmc(const or_system* s, int n_walkers, const uint32_t* uids, const double
             int m = (int)floor(wt + ub);
             if (m > 3) m = 3;
             mult[iw] = m;
+            if (mult_out) mult_out[(size_t)gen * max_pop + iw] = m;
             new_pop += m;
         }
         if (new_pop == 0 || new_pop > max_pop) {

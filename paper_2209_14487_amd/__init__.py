@@ -67,6 +67,8 @@ _SIGS = {
     "cq_crowd_get_positions": [_P, _P, _P],
     "cq_crowd_get_inverse": [_P, _P],
     "cq_crowd_set_forced_decisions": [_P, _P, _I],
+    "cq_crowd_set_forced_branching": [_P, _P, _I],
+    "cq_crowd_get_dmc_moves": [_P, _P, _P],
     "cq_crowd_record_moves": [_P, _I],
     "cq_crowd_get_move_records": [_P, _P, _P, _P, _P],
     "cq_crowd_set_kernel_timing": [_P, _I],
@@ -181,6 +183,7 @@ class Crowd:
         self.system = system
         self.W = n_walkers
         self._w0 = n_walkers
+        self.Wcap = max(n_walkers, max_walkers)  # walker stride of the parity-mode buffers
         self.n = system.n
         self.ne = 2 * system.n
         desc = CrowdDesc(CQ_MIXED if precision == "mixed" else CQ_FP64, delay_rank, recompute_every, seed,
@@ -282,20 +285,44 @@ class Crowd:
             _check(lib().cq_crowd_set_forced_decisions(self._h, None, 0))
         else:
             f = np.ascontiguousarray(flags, dtype=np.uint8)
-            assert f.shape[1:] == (self.ne, self.W)
+            if f.shape[1:] != (self.ne, self.Wcap):  # [sweeps][Ne][W] padded with own decisions
+                assert f.shape[1] == self.ne and f.shape[2] <= self.Wcap
+                g = np.full((f.shape[0], self.ne, self.Wcap), 2, np.uint8)
+                g[:, :, :f.shape[2]] = f
+                f = g
             _check(lib().cq_crowd_set_forced_decisions(self._h, f.ctypes.data, f.shape[0]))
+
+    def set_forced_branching(self, mult: Optional[np.ndarray]):
+        """DMC parity mode: multiplicities [generations][<= Wcap] to follow (None: off)."""
+        if mult is None:
+            _check(lib().cq_crowd_set_forced_branching(self._h, None, 0))
+        else:
+            m = np.zeros((mult.shape[0], self.Wcap), np.int32)
+            m[:, :mult.shape[1]] = mult
+            _check(lib().cq_crowd_set_forced_branching(self._h, m.ctypes.data, m.shape[0]))
+
+    def dmc_moves(self):
+        """(accepted, proposed) drift-diffusion moves over every DMC generation run so far."""
+        a = ctypes.c_int64()
+        p = ctypes.c_int64()
+        _check(lib().cq_crowd_get_dmc_moves(self._h, ctypes.byref(a), ctypes.byref(p)))
+        return a.value, p.value
 
     def record(self, n_sweeps: int):
         _check(lib().cq_crowd_record_moves(self._h, n_sweeps))
         self._rec = n_sweeps
 
-    def records(self):
-        shp = (self._rec, self.ne, self.W)
+    def records(self, all_slots: bool = False):
+        """Per-move records [sweeps][Ne][W] (all_slots: [sweeps][Ne][Wcap], every walker slot)."""
+        shp = (self._rec, self.ne, self.Wcap)
         rho, dl, pr = np.zeros(shp), np.zeros(shp), np.zeros(shp)
         acc = np.zeros(shp, np.uint8)
         _check(lib().cq_crowd_get_move_records(self._h, rho.ctypes.data, dl.ctypes.data, pr.ctypes.data,
                                                acc.ctypes.data))
-        return dict(rho=rho, dlnj=dl, prob=pr, acc=acc)
+        out = dict(rho=rho, dlnj=dl, prob=pr, acc=acc)
+        if not all_slots:
+            out = {k: v[:, :, :self.W] for k, v in out.items()}
+        return out
 
     def set_timing(self, kinds=()):
         """Time the given kernel kinds (names or ids) with HIP events; () switches timing off."""

@@ -134,6 +134,8 @@ struct cq_crowd {
     uint8_t* rec_acc = nullptr;
     int forced_cap = 0;
     uint8_t* forced = nullptr;
+    int mult_cap = 0;
+    int* forced_mult = nullptr;  // [generations][Wcap] branching multiplicities to follow
     // host state
     cq::Params hp{};
     bool ready = false;
@@ -155,6 +157,7 @@ cq::CrowdView<T> view(const cq_crowd* c)
 {
     cq::CrowdView<T> v{};
     v.W = c->W;
+    v.Wcap = c->Wcap;
     v.n = c->n;
     v.ne = c->ne;
     v.K = c->K;
@@ -560,6 +563,7 @@ void dmc_generation(cq_crowd* c, int gen, int n_target, double tau, bool recompu
     d.mult = c->dmc_mult;
     d.off = c->dmc_off;
     d.history = c->dmc_hist;
+    d.forced_mult = c->mult_cap > 0 ? c->forced_mult : nullptr;
     d.pop = c->W;
     d.cap = c->Wcap;
     d.n_target = n_target;
@@ -721,6 +725,7 @@ void cq_crowd_destroy(cq_crowd* c)
     if (c->rec_prob) (void)hipFree(c->rec_prob);
     if (c->rec_acc) (void)hipFree(c->rec_acc);
     if (c->forced) (void)hipFree(c->forced);
+    if (c->forced_mult) (void)hipFree(c->forced_mult);
     for (auto* evs : {&c->ev_fork, &c->ev_dec, &c->ev_gat})
         for (hipEvent_t e : *evs) (void)hipEventDestroy(e);
     if (c->stream2) (void)hipStreamDestroy(c->stream2);
@@ -1039,6 +1044,10 @@ cq_status cq_crowd_run_dmc(cq_crowd* c, int n_generations, double tau, double e_
     ds.status = 0;
     HIP_TRY(hipMemcpy(c->dmc_state, &ds, sizeof(ds), hipMemcpyHostToDevice));
     drop_graph(c);  // walker buffers and the population change from here on
+    // the generation sums count the moves each walker made since the last branching: clear the
+    // counters the walkers bring from VMC sweeps (children of a branching start at zero)
+    HIP_TRY(hipMemsetAsync(c->nacc, 0, sizeof(long long) * c->W, c->stream));
+    HIP_TRY(hipMemsetAsync(c->nprop, 0, sizeof(long long) * c->W, c->stream));
     for (int gen = 0; gen < n_generations; ++gen) {
         const bool rc = c->recompute_every > 0 && ++c->since_recompute >= c->recompute_every;
         if (rc) {
@@ -1203,7 +1212,7 @@ cq_status cq_crowd_set_forced_decisions(cq_crowd* c, const uint8_t* flags, int n
     }
     c->forced_cap = 0;
     if (flags) {
-        const size_t bytes = (size_t)n_sweeps * c->ne * c->W;
+        const size_t bytes = (size_t)n_sweeps * c->ne * c->Wcap;
         if (hipMalloc((void**)&c->forced, bytes) != hipSuccess) {
             (void)hipGetLastError();
             c->forced = nullptr;
@@ -1218,6 +1227,50 @@ cq_status cq_crowd_set_forced_decisions(cq_crowd* c, const uint8_t* flags, int n
     return push_params(c);
 }
 
+cq_status cq_crowd_set_forced_branching(cq_crowd* c, const int* mult, int n_generations)
+{
+    if (!c) return fail(CQ_EINVAL, "crowd is NULL");
+    if (mult && n_generations < 1) return fail(CQ_EINVAL, "n_generations must be >= 1");
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (c->forced_mult) {
+        HIP_TRY(hipFree(c->forced_mult));
+        c->forced_mult = nullptr;
+    }
+    c->mult_cap = 0;
+    if (mult) {
+        const size_t cnt = (size_t)n_generations * c->Wcap;
+        for (size_t i = 0; i < cnt; ++i)
+            if (mult[i] < 0 || mult[i] > 3) return fail(CQ_EINVAL, "multiplicities must be 0..3");
+        if (hipMalloc((void**)&c->forced_mult, cnt * sizeof(int)) != hipSuccess) {
+            (void)hipGetLastError();
+            c->forced_mult = nullptr;
+            return fail(CQ_ENOMEM, "forced-multiplicity buffer");
+        }
+        HIP_TRY(hipMemcpy(c->forced_mult, mult, cnt * sizeof(int), hipMemcpyHostToDevice));
+        c->mult_cap = n_generations;
+    }
+    c->hp.mult_cap = c->mult_cap;
+    c->hp.rec_sweep = 0;
+    drop_graph(c);
+    return push_params(c);
+}
+
+cq_status cq_crowd_get_dmc_moves(cq_crowd* c, int64_t* accepted, int64_t* proposed)
+{
+    if (!c) return fail(CQ_EINVAL, "crowd is NULL");
+    if (!c->have_alt) {
+        if (accepted) *accepted = 0;
+        if (proposed) *proposed = 0;
+        return CQ_OK;
+    }
+    cq::DmcState ds{};
+    cq_status st = copy_out(c, &ds, c->dmc_state, sizeof(ds));
+    if (st != CQ_OK) return st;
+    if (accepted) *accepted = ds.nacc;
+    if (proposed) *proposed = ds.nprop;
+    return CQ_OK;
+}
+
 cq_status cq_crowd_record_moves(cq_crowd* c, int n_sweeps)
 {
     if (!c) return fail(CQ_EINVAL, "crowd is NULL");
@@ -1230,7 +1283,7 @@ cq_status cq_crowd_record_moves(cq_crowd* c, int n_sweeps)
         }
     c->rec_cap = 0;
     if (n_sweeps > 0) {
-        const size_t cnt = (size_t)n_sweeps * c->ne * c->W;
+        const size_t cnt = (size_t)n_sweeps * c->ne * c->Wcap;
         bool ok = hipMalloc((void**)&c->rec_rho, cnt * 8) == hipSuccess;
         ok = ok && hipMalloc((void**)&c->rec_dlnj, cnt * 8) == hipSuccess;
         ok = ok && hipMalloc((void**)&c->rec_prob, cnt * 8) == hipSuccess;
@@ -1251,7 +1304,7 @@ cq_status cq_crowd_get_move_records(cq_crowd* c, double* rho, double* dlnj, doub
 {
     if (!c) return fail(CQ_EINVAL, "crowd is NULL");
     if (c->rec_cap == 0) return fail(CQ_ESTATE, "recording is off");
-    const size_t cnt = (size_t)c->rec_cap * c->ne * c->W;
+    const size_t cnt = (size_t)c->rec_cap * c->ne * c->Wcap;
     cq_status st = copy_out(c, rho, c->rec_rho, cnt * 8);
     if (st == CQ_OK) st = copy_out(c, dlnj, c->rec_dlnj, cnt * 8);
     if (st == CQ_OK) st = copy_out(c, prob, c->rec_prob, cnt * 8);

@@ -48,6 +48,7 @@ struct Params {
     int32_t rec_sweep;   // index of the current sweep in the record / forced buffers
     int32_t rec_cap;     // record capacity in sweeps (0 = off)
     int32_t forced_cap;  // forced-decision capacity in sweeps (0 = off)
+    int32_t mult_cap;    // forced branching multiplicities, in generations (0 = off)
     double sigma;        // VMC step
     double tau;          // DMC time step
 };
@@ -55,6 +56,7 @@ struct Params {
 template <typename T>
 struct CrowdView {
     int W, n, ne, K;
+    int Wcap;            // walker capacity: the walker stride of the record and forced-decision buffers
     int Q;               // candidates per round (batched path), else K
     int QR;              // stage slots per walker: K, or the candidate ring of the batched path (2 Q,
                          // so a round's new candidates never reuse a slot the previous window's
@@ -127,6 +129,7 @@ struct DmcView {
     int* mult;        // [cap] multiplicities
     int* off;         // [cap] first child index
     double* history;  // [n_gen][4] population, sum of weights, E_est, E_T
+    const int* forced_mult;  // parity mode: [generations][cap] multiplicities to follow, or null
     int pop, cap, n_target, chunks;
     double ecut;
     uint64_t seed;

@@ -138,6 +138,9 @@ __global__ __launch_bounds__(kBlock) void k_window_dmc(CrowdView<T> v, int e0, i
     const int groups = n / VEC, items = 4 * groups;
     const uint32_t step = v.prm->step;
     const double tau = v.prm->tau, sqrt_tau = sqrt(tau);
+    // parity mode: the generation's records and forced decisions (walker stride Wcap)
+    const int rs = v.prm->rec_sweep;
+    const bool recording = rs < v.prm->rec_cap, forcing = v.forced && rs < v.prm->forced_cap;
     const T* Mspin = v.M + ((size_t)w * 2 + spin) * n * (size_t)n;
     const T* VGLspin = v.VGL + ((size_t)w * 2 + spin) * n * 5 * (size_t)n;
     T* stage = v.stage + (size_t)w * v.QR * 5 * n;
@@ -356,7 +359,15 @@ __global__ __launch_bounds__(kBlock) void k_window_dmc(CrowdView<T> v, int e0, i
             }
             const double prob = rho * rho * exp(2.0 * dj) * exp(-(bwd - fwd) / (2.0 * tau));
             const double u = accept_uniform(v.seed, v.uid[w], step, (uint32_t)e);
-            const int acc = rho > 0.0 && u < prob;
+            int acc = rho > 0.0 && u < prob;
+            const size_t ri = ((size_t)rs * v.ne + e) * v.Wcap + w;
+            if (forcing && v.forced[ri] < 2) acc = v.forced[ri] != 0;
+            if (recording && lane == 0) {
+                v.rec_rho[ri] = rho;
+                v.rec_dlnj[ri] = dj;
+                v.rec_prob[ri] = prob;
+                v.rec_acc[ri] = (uint8_t)acc;
+            }
             if (acc) {
                 if (mine) s_G[cnt][lane] = s_x[lane];
                 if (lane == 0) {
@@ -448,6 +459,8 @@ __global__ __launch_bounds__(kBlock) void k_dmc_weights(DmcView d, const double*
     const double ub = branch_uniform(d.seed, uid[w], prm->step);
     int m = (int)floor(wt + ub);
     if (m > 3) m = 3;
+    // parity mode: the given multiplicity (the population then follows the reference's)
+    if (d.forced_mult && prm->rec_sweep < prm->mult_cap) m = d.forced_mult[(size_t)prm->rec_sweep * d.cap + w];
     d.wt[w] = wt;
     d.mult[w] = m;
 }

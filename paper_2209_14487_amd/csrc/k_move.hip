@@ -215,7 +215,7 @@ __device__ int resolve_wave(const CrowdView<T>& v, int w, int prev, int cnt, boo
     const double u = accept_uniform(v.seed, v.uid[w], step, (uint32_t)prev);
     int acc = u < prob;
     const int rs = v.prm->rec_sweep;
-    const size_t ri = ((size_t)rs * v.ne + prev) * v.W + w;
+    const size_t ri = ((size_t)rs * v.ne + prev) * v.Wcap + w;
     if (v.forced && rs < v.prm->forced_cap && v.forced[ri] < 2) acc = v.forced[ri] != 0;
     if (owner) {
         if (lane == 0 && rs < v.prm->rec_cap) {

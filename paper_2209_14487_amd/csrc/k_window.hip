@@ -272,7 +272,7 @@ __global__ __launch_bounds__(512) void k_window(CrowdView<T> v, int e0, int nmov
             const double prob = rho * rho * exp(2.0 * dlnj);
             const double u = accept_uniform(v.seed, v.uid[w], step, (uint32_t)e);
             int acc = u < prob;
-            const size_t ri = ((size_t)rs * v.ne + e) * v.W + w;
+            const size_t ri = ((size_t)rs * v.ne + e) * v.Wcap + w;
             if (forcing && v.forced[ri] < 2) acc = v.forced[ri] != 0;
             if (lane == 0 && recording) {
                 v.rec_rho[ri] = rho;

@@ -594,3 +594,31 @@ def test_fp32_chain_model_rounds_to_single_precision():
         assert 1e-9 < np.median(rel) < 2e-6, (arith, np.median(rel))
     st = fp32_chain.ratio_error_stats(rho, ref.rho[:, :, 2])
     assert st["n"] == 3 * 2 * n and st["median"] <= st["p99"] <= st["p999"]
+
+
+def test_fp32_chain_dmc_model_without_rounding_is_the_oracle_chain():
+    """The DMC variant of the rounding model, with nothing rounded, replays the oracle's DMC
+    population along its decisions and multiplicities: the same ratios and acceptance
+    probabilities (drift, Green's function, Jastrow) for every walker slot of every generation,
+    across branching; the oracle's records are consistent (decisions from rho > 0 and u < P,
+    multiplicities summing to the next population)."""
+    from oracle import fp32_chain
+    n, W, gens, tau = 2, 6, 3, 0.2
+    s, _ = _tiny_system(n, j2=True, seed=23)
+    R0 = start_positions(87, W, 2 * n, s.L)
+    _, _, el0, _ = orc.setup(s, R0)
+    cap = 4 * W + 16
+    ref = orc.dmc(s, R0, gens, tau, float(np.mean(el0)), n_target=W, max_pop=cap, record=True)
+    rec = ref.rec
+    pops = [W] + list(ref.pop[:-1])
+    assert len(set(ref.pop.tolist())) > 1
+    for g in range(gens):
+        live = pops[g]
+        assert rec["mult"][g, :live].sum() == ref.pop[g]
+        own = (rec["rho"][g, :, :live] > 0) & (rec["u"][g, :, :live] < rec["prob"][g, :, :live])
+        assert np.array_equal(own, rec["acc"][g, :, :live].astype(bool))
+    model = fp32_chain.replay_dmc(s, R0, np.arange(W), rec["acc"], rec["mult"], tau, storage="fp64")
+    live = np.isfinite(rec["rho"])
+    assert np.array_equal(live, np.isfinite(model["rho"]))
+    assert np.allclose(model["rho"][live], rec["rho"][live], rtol=1e-10, atol=1e-13)
+    assert np.allclose(model["prob"][live], rec["prob"][live], rtol=1e-9, atol=1e-13)
