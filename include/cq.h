@@ -270,6 +270,26 @@ cq_status cq_crowd_synchronize(cq_crowd* c);
 
 void cq_crowd_destroy(cq_crowd* c);
 
+/* ------------------------------------------------------------ batched inverse */
+
+/* The FP64 recompute of the Slater inverses (Gauss-Jordan with partial pivoting,
+   the same kernels as the periodic recompute of a crowd) for matrices the caller
+   holds, e.g. walkers that arrive from elsewhere with positions only.
+   A     device [nmat][n][n], row-major, A[m][i][j] = phi_j(r_i) (elem_bytes 4: FP32,
+         8: FP64; promoted to FP64 for the elimination);
+   Minv  device [nmat][n][n] of the same element type: Minv[m][a][j] = (A_m^-1)[j][a],
+         so row a is the inverse column of electron a (the crowds' layout);
+   logdet, sign  device [nmat]: log|det A_m| (FP64) and its sign (+1/-1).
+   All pointers are device pointers owned by the caller; A is only read.  The
+   library allocates a workspace of about nmat (n^2 + 64 n) 8 bytes for n > 64 for
+   the duration of the call.  Runs on hip_stream (NULL: the null stream) and
+   returns when the results are written.  Errors: CQ_EINVAL (NULL pointer,
+   elem_bytes not 4 or 8, n outside 1..2048, nmat < 1), CQ_ENOMEM (workspace),
+   CQ_ESINGULAR (a pivot at or below n eps max|A_ij| or not finite; the message
+   names the pair of matrices 2w, 2w+1 holding it). */
+cq_status cq_slater_inverse(const void* A, int elem_bytes, int n, int nmat, void* Minv, double* logdet, int* sign,
+                            void* hip_stream);
+
 /* Plain streaming device-to-device copy of `bytes` bytes (multiple of 16,
    16-byte aligned pointers) with a library kernel on `hip_stream` (NULL: the
    null stream), synchronous.  Its hardware traffic counters give the scale

@@ -75,6 +75,7 @@ _SIGS = {
     "cq_crowd_get_kernel_timing": [_P, _I, _P, _P],
     "cq_crowd_synchronize": [_P],
     "cq_device_copy": [_P, _P, ctypes.c_uint64, _P],
+    "cq_slater_inverse": [_P, _I, _I, _I, _P, _P, _P, _P],
     "cq_crowd_destroy": [_P],
     "cq_last_error": [],
 }
@@ -109,6 +110,14 @@ def _check(st):
 def device_copy(dst, src, nbytes: int, stream=None):
     """Library streaming copy between device buffers (traffic-counter calibration)."""
     _check(lib().cq_device_copy(_ptr(dst), _ptr(src), nbytes, _stream_handle(stream)))
+
+
+def slater_inverse(A, Minv, logdet, sign, stream=None):
+    """FP64 Gauss-Jordan inverses of device matrices A [nmat][n][n] (torch CUDA tensors, float32 or
+    float64): Minv[m][a][j] = (A_m^-1)[j][a], logdet [nmat] float64, sign [nmat] int32."""
+    nmat, n = A.shape[0], A.shape[1]
+    _check(lib().cq_slater_inverse(_ptr(A), A.element_size(), n, nmat, _ptr(Minv), _ptr(logdet), _ptr(sign),
+                                   _stream_handle(stream)))
 
 
 def _ptr(x):

@@ -157,6 +157,7 @@ cq::CrowdView<T> view(const cq_crowd* c)
 {
     cq::CrowdView<T> v{};
     v.W = c->W;
+    v.arow = 5 * c->n;
     v.Wcap = c->Wcap;
     v.n = c->n;
     v.ne = c->ne;
@@ -1336,6 +1337,110 @@ cq_status cq_crowd_get_kernel_timing(cq_crowd* c, int kind, double* total_ms, in
     if (total_ms) *total_ms = tot;
     if (launches) *launches = (int64_t)c->ev_used[kind];
     return CQ_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Workspace of one batched inversion of nmat n x n matrices: the blocked Gauss-Jordan buffers
+// (n > 64 only), then the per-pair status words and per-matrix drift the kernels write.
+size_t slater_work_bytes(int n, int nmat)
+{
+    const size_t pairs = ((size_t)nmat + 1) / 2;
+    size_t b = cq::inverse_work_bytes(nmat, n);
+    return ((b + 255) / 256) * 256 + pairs * sizeof(int) + (size_t)nmat * sizeof(double) + 256;
+}
+
+template <typename T>
+cq_status slater_inverse_impl(const T* A, int n, int nmat, T* Minv, double* logdet, int* sign, hipStream_t st,
+                              unsigned char* work)
+{
+    const int pairs = (nmat + 1) / 2;
+    size_t off = 0;
+    cq::InvWork wk{};
+    if (n > 64) {
+        const int B = cq::block_width(n);
+        wk.S = (double*)(work + off);
+        off += sizeof(double) * (size_t)nmat * n * n;
+        wk.PR = (double*)(work + off);
+        off += sizeof(double) * (size_t)nmat * B * n;
+        wk.pivrow = (int*)(work + off);
+        off += sizeof(int) * (size_t)nmat * n * 2;
+        off = (off + 15) / 16 * 16;
+        wk.logabs = (double*)(work + off);
+        off += sizeof(double) * (size_t)nmat * 2;
+        wk.negs = (int*)(work + off);
+        off += sizeof(int) * (size_t)nmat * 2;
+        wk.b = cq::panel_width(n);
+    }
+    off = (off + 255) / 256 * 256;
+    int* status = (int*)(work + off);
+    off += sizeof(int) * (size_t)pairs;
+    off = (off + 15) / 16 * 16;
+    double* drift = (double*)(work + off);
+    cq::CrowdView<T> v{};
+    v.W = pairs;
+    v.n = n;
+    v.ne = 2 * n;
+    v.arow = n;
+    v.VGL = const_cast<T*>(A);
+    v.M = Minv;
+    v.logdet = logdet;
+    v.sign = sign;
+    v.status = status;
+    v.drift = drift;
+    v.drift_max = nullptr;
+    HIP_TRY(hipMemsetAsync(status, 0, sizeof(int) * (size_t)pairs, st));
+    // the kernels read the previous log|det| for a drift figure that this call does not report
+    HIP_TRY(hipMemsetAsync(logdet, 0, sizeof(double) * (size_t)nmat, st));
+    cq::launch_inverse<T>(v, wk, st, nmat);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(st));
+    std::vector<int> hs(pairs);
+    HIP_TRY(hipMemcpy(hs.data(), status, sizeof(int) * (size_t)pairs, hipMemcpyDeviceToHost));
+    for (int w = 0; w < pairs; ++w)
+        if (hs[w] & 1)
+            return fail(CQ_ESINGULAR, "matrix " + std::to_string(2 * w) +
+                                          (2 * w + 1 < nmat ? " or " + std::to_string(2 * w + 1) : std::string()) +
+                                          " is singular or not finite");
+    return CQ_OK;
+}
+
+cq_status check_slater_args(const void* A, int elem_bytes, int n, int nmat, const void* Minv, const double* logdet,
+                            const int* sign)
+{
+    if (!A || !Minv || !logdet || !sign) return fail(CQ_EINVAL, "NULL argument");
+    if (elem_bytes != 4 && elem_bytes != 8) return fail(CQ_EINVAL, "elem_bytes must be 4 or 8");
+    if (n < 1 || n > 2048) return fail(CQ_EINVAL, "n must be 1..2048");
+    if (nmat < 1) return fail(CQ_EINVAL, "nmat must be >= 1");
+    if ((size_t)nmat * n * n > (size_t)1 << 34) return fail(CQ_EINVAL, "batch too large");
+    return CQ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+cq_status cq_slater_inverse(const void* A, int elem_bytes, int n, int nmat, void* Minv, double* logdet, int* sign,
+                            void* hip_stream)
+{
+    cq_status st = check_slater_args(A, elem_bytes, n, nmat, Minv, logdet, sign);
+    if (st != CQ_OK) return st;
+    void* work = nullptr;
+    const size_t bytes = slater_work_bytes(n, nmat);
+    if (hipMalloc(&work, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(CQ_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes of inversion workspace failed");
+    }
+    hipStream_t s = (hipStream_t)hip_stream;
+    st = elem_bytes == 4 ? slater_inverse_impl<float>((const float*)A, n, nmat, (float*)Minv, logdet, sign, s,
+                                                      (unsigned char*)work)
+                         : slater_inverse_impl<double>((const double*)A, n, nmat, (double*)Minv, logdet, sign, s,
+                                                       (unsigned char*)work);
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(work);
+    return st;
 }
 
 cq_status cq_device_copy(void* dst, const void* src, uint64_t bytes, void* hip_stream)

@@ -56,6 +56,7 @@ struct Params {
 template <typename T>
 struct CrowdView {
     int W, n, ne, K;
+    int arow;            // row stride of the value rows in VGL read by the inversion (5 N in a crowd)
     int Wcap;            // walker capacity: the walker stride of the record and forced-decision buffers
     int Q;               // candidates per round (batched path), else K
     int QR;              // stage slots per walker: K, or the candidate ring of the batched path (2 Q,
@@ -180,7 +181,8 @@ template <typename T> void launch_flush(const CrowdView<T>& v, int spin, hipStre
 bool flush_mfma_fits(int n);  // the FP32 matrix-core update handles this N
 void launch_flush_mfma(const CrowdView<float>& v, int spin, hipStream_t s, bool linv_ready);
 template <typename T> void launch_energy(const CrowdView<T>& v, hipStream_t s);
-template <typename T> void launch_inverse(const CrowdView<T>& v, const InvWork& wk, hipStream_t s);
+// nmat < 0: the 2 W matrices of the view; else matrices 0 .. nmat-1 (matrix m at (m / 2, m % 2))
+template <typename T> void launch_inverse(const CrowdView<T>& v, const InvWork& wk, hipStream_t s, int nmat = -1);
 void launch_sweep_end(Params* prm, hipStream_t s);
 template <typename T> void launch_window_dmc(const CrowdView<T>& v, int e0, int nmoves, hipStream_t s);
 template <typename T>

@@ -54,12 +54,12 @@ __global__ __launch_bounds__(kBlock) void k_gj_small(CrowdView<T> v)
     __shared__ int s_p;
     const int mat = blockIdx.x, w = mat >> 1, spin = mat & 1;
     const int n = v.n, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const T* A = v.VGL + ((size_t)w * 2 + spin) * n * 5 * (size_t)n;
+    const T* A = v.VGL + ((size_t)w * 2 + spin) * n * (size_t)v.arow;
     __shared__ double smax[4];
     double amax = 0.0;
     for (int idx = tid; idx < n * n; idx += kBlock) {
         const int i = idx / n, j = idx % n;  // A[i][j] = phi_j(r_i)
-        const double a = (double)A[(size_t)i * 5 * n + j];
+        const double a = (double)A[(size_t)i * v.arow + j];
         S[j][i] = a;
         amax = fmax(amax, fabs(a));
     }
@@ -157,12 +157,12 @@ __global__ __launch_bounds__(kBlock) void k_gj_load(CrowdView<T> v, double* __re
     const int mat = blockIdx.x / (tiles * tiles), t = blockIdx.x % (tiles * tiles);
     const int ti = t / tiles, tj = t % tiles;
     const int w = mat >> 1, spin = mat & 1;
-    const T* A = v.VGL + ((size_t)w * 2 + spin) * n * 5 * (size_t)n;
+    const T* A = v.VGL + ((size_t)w * 2 + spin) * n * (size_t)v.arow;
     double amax = 0.0;
     for (int idx = threadIdx.x; idx < 64 * 64; idx += kBlock) {
         const int r = idx / 64, c = idx % 64;
         const int i = ti * 64 + r, j = tj * 64 + c;
-        const double a = (i < n && j < n) ? (double)A[(size_t)i * 5 * n + j] : 0.0;
+        const double a = (i < n && j < n) ? (double)A[(size_t)i * v.arow + j] : 0.0;
         tile[r][c] = a;
         amax = fmax(amax, fabs(a));
     }
@@ -459,9 +459,10 @@ size_t inverse_work_bytes(int nmat, int n)
 }
 
 template <typename T>
-void launch_inverse(const CrowdView<T>& v, const InvWork& wk, hipStream_t s)
+void launch_inverse(const CrowdView<T>& v, const InvWork& wk, hipStream_t s, int nmat)
 {
-    const int nmat = v.W * 2, n = v.n;
+    if (nmat < 0) nmat = v.W * 2;
+    const int n = v.n;
     if (n <= kSmallN) {
         hipLaunchKernelGGL(k_gj_small<T>, dim3(nmat), dim3(kBlock), 0, s, v);
         return;
@@ -503,7 +504,7 @@ void launch_inverse(const CrowdView<T>& v, const InvWork& wk, hipStream_t s)
                        wk.negs, mstatus);
 }
 
-template void launch_inverse<float>(const CrowdView<float>&, const InvWork&, hipStream_t);
-template void launch_inverse<double>(const CrowdView<double>&, const InvWork&, hipStream_t);
+template void launch_inverse<float>(const CrowdView<float>&, const InvWork&, hipStream_t, int);
+template void launch_inverse<double>(const CrowdView<double>&, const InvWork&, hipStream_t, int);
 
 }  // namespace cq

@@ -64,3 +64,16 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(cq, "LIB_PATH", str(tmp_path / "absent.so"))
     with pytest.raises(ImportError):
         cq.lib()
+
+
+def test_slater_inverse_arguments_are_checked():
+    L = cq.lib()
+    buf = (ctypes.c_double * 16)()
+    ld = (ctypes.c_double * 1)()
+    sg = (ctypes.c_int * 1)()
+    assert L.cq_slater_inverse(None, 8, 4, 1, buf, ld, sg, None) == cq.CQ_EINVAL
+    assert L.cq_slater_inverse(buf, 2, 4, 1, buf, ld, sg, None) == cq.CQ_EINVAL
+    assert L.cq_slater_inverse(buf, 8, 0, 1, buf, ld, sg, None) == cq.CQ_EINVAL
+    assert L.cq_slater_inverse(buf, 8, 4096, 1, buf, ld, sg, None) == cq.CQ_EINVAL
+    assert L.cq_slater_inverse(buf, 8, 4, 0, buf, ld, sg, None) == cq.CQ_EINVAL
+    assert b"nmat" in L.cq_last_error()
