@@ -1341,7 +1341,7 @@ cq_status cq_crowd_get_kernel_timing(cq_crowd* c, int kind, double* total_ms, in
 
 }  // extern "C"
 
-namespace {
+namespace cq {
 
 // Workspace of one batched inversion of nmat n x n matrices: the blocked Gauss-Jordan buffers
 // (n > 64 only), then the per-pair status words and per-matrix drift the kernels write.
@@ -1352,6 +1352,8 @@ size_t slater_work_bytes(int n, int nmat)
     return ((b + 255) / 256) * 256 + pairs * sizeof(int) + (size_t)nmat * sizeof(double) + 256;
 }
 
+// The inversion proper on a caller-provided workspace of slater_work_bytes(n, nmat) bytes (256-byte
+// aligned); no allocation on any path but the error message of a failure.
 template <typename T>
 cq_status slater_inverse_impl(const T* A, int n, int nmat, T* Minv, double* logdet, int* sign, hipStream_t st,
                               unsigned char* work)
@@ -1397,15 +1399,25 @@ cq_status slater_inverse_impl(const T* A, int n, int nmat, T* Minv, double* logd
     cq::launch_inverse<T>(v, wk, st, nmat);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(st));
-    std::vector<int> hs(pairs);
-    HIP_TRY(hipMemcpy(hs.data(), status, sizeof(int) * (size_t)pairs, hipMemcpyDeviceToHost));
-    for (int w = 0; w < pairs; ++w)
-        if (hs[w] & 1)
-            return fail(CQ_ESINGULAR, "matrix " + std::to_string(2 * w) +
-                                          (2 * w + 1 < nmat ? " or " + std::to_string(2 * w + 1) : std::string()) +
-                                          " is singular or not finite");
+    int hs[256];
+    for (int w0 = 0; w0 < pairs; w0 += 256) {
+        const int cnt = pairs - w0 < 256 ? pairs - w0 : 256;
+        HIP_TRY(hipMemcpy(hs, status + w0, sizeof(int) * (size_t)cnt, hipMemcpyDeviceToHost));
+        for (int q = 0; q < cnt; ++q)
+            if (hs[q] & 1) {
+                const int w = w0 + q;
+                return fail(CQ_ESINGULAR, "matrix " + std::to_string(2 * w) +
+                                              (2 * w + 1 < nmat ? " or " + std::to_string(2 * w + 1) : std::string()) +
+                                              " is singular or not finite");
+            }
+    }
     return CQ_OK;
 }
+
+template cq_status slater_inverse_impl<float>(const float*, int, int, float*, double*, int*, hipStream_t,
+                                              unsigned char*);
+template cq_status slater_inverse_impl<double>(const double*, int, int, double*, double*, int*, hipStream_t,
+                                               unsigned char*);
 
 cq_status check_slater_args(const void* A, int elem_bytes, int n, int nmat, const void* Minv, const double* logdet,
                             const int* sign)
@@ -1418,25 +1430,25 @@ cq_status check_slater_args(const void* A, int elem_bytes, int n, int nmat, cons
     return CQ_OK;
 }
 
-}  // namespace
+}  // namespace cq
 
 extern "C" {
 
 cq_status cq_slater_inverse(const void* A, int elem_bytes, int n, int nmat, void* Minv, double* logdet, int* sign,
                             void* hip_stream)
 {
-    cq_status st = check_slater_args(A, elem_bytes, n, nmat, Minv, logdet, sign);
+    cq_status st = cq::check_slater_args(A, elem_bytes, n, nmat, Minv, logdet, sign);
     if (st != CQ_OK) return st;
     void* work = nullptr;
-    const size_t bytes = slater_work_bytes(n, nmat);
+    const size_t bytes = cq::slater_work_bytes(n, nmat);
     if (hipMalloc(&work, bytes) != hipSuccess) {
         (void)hipGetLastError();
         return fail(CQ_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes of inversion workspace failed");
     }
     hipStream_t s = (hipStream_t)hip_stream;
-    st = elem_bytes == 4 ? slater_inverse_impl<float>((const float*)A, n, nmat, (float*)Minv, logdet, sign, s,
+    st = elem_bytes == 4 ? cq::slater_inverse_impl<float>((const float*)A, n, nmat, (float*)Minv, logdet, sign, s,
                                                       (unsigned char*)work)
-                         : slater_inverse_impl<double>((const double*)A, n, nmat, (double*)Minv, logdet, sign, s,
+                         : cq::slater_inverse_impl<double>((const double*)A, n, nmat, (double*)Minv, logdet, sign, s,
                                                        (unsigned char*)work);
     (void)hipStreamSynchronize(s);
     (void)hipFree(work);

@@ -27,6 +27,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "cq.h"
+
 namespace cq {
 
 constexpr int kMaxDelay = 32;
@@ -190,6 +192,14 @@ void launch_dmc_branch(const DmcView& d, const WalkerArrays<T>& src, const Walke
                        const Params* prm, int gen, hipStream_t s);
 void launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 size_t inverse_work_bytes(int nmat, int n);
+// Batched inversion of caller-held matrices (the C ABI's cq_slater_inverse and its variant on
+// the library's static workspace): bytes of workspace it needs, argument checks, the inversion.
+size_t slater_work_bytes(int n, int nmat);
+cq_status check_slater_args(const void* A, int elem_bytes, int n, int nmat, const void* Minv, const double* logdet,
+                            const int* sign);
+template <typename T>
+cq_status slater_inverse_impl(const T* A, int n, int nmat, T* Minv, double* logdet, int* sign, hipStream_t st,
+                              unsigned char* work);
 int panel_width(int n);  // columns per panel of the blocked inversion
 int block_width(int n);  // columns per block (4 panels) of the blocked inversion
 
