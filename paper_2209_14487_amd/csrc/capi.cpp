@@ -1343,6 +1343,8 @@ cq_status cq_crowd_get_kernel_timing(cq_crowd* c, int kind, double* total_ms, in
 
 namespace cq {
 
+cq_status report_error(cq_status s, const char* msg) { return fail(s, msg); }
+
 // Workspace of one batched inversion of nmat n x n matrices: the blocked Gauss-Jordan buffers
 // (n > 64 only), then the per-pair status words and per-matrix drift the kernels write.
 size_t slater_work_bytes(int n, int nmat)

@@ -195,6 +195,8 @@ size_t inverse_work_bytes(int nmat, int n);
 // Batched inversion of caller-held matrices (the C ABI's cq_slater_inverse and its variant on
 // the library's static workspace): bytes of workspace it needs, argument checks, the inversion.
 size_t slater_work_bytes(int n, int nmat);
+// Sets the thread-local message of cq_last_error and returns s.
+cq_status report_error(cq_status s, const char* msg);
 cq_status check_slater_args(const void* A, int elem_bytes, int n, int nmat, const void* Minv, const double* logdet,
                             const int* sign);
 template <typename T>
