@@ -394,12 +394,11 @@ def main():
         % (wl.name, wl.n, wl.walkers, wl.crowds, wl.G, delay, wl.recompute_every))
 
     if args.calibrate_copy:
-        import torch
-        src = torch.ones(1 << 30, dtype=torch.uint8, device="cuda")
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        cq.device_copy(dst.data_ptr(), src.data_ptr(), 1 << 30)
-        del src, dst
+        src = cq.DeviceArray(np.ones(1 << 30, np.uint8))
+        dst = cq.DeviceArray(shape=(1 << 30,), dtype=np.uint8)
+        cq.device_copy(dst.ptr, src.ptr, 1 << 30)
+        src.free()
+        dst.free()
         log("  copied 1 GiB with cq_device_copy (calibration)")
     kinds = [k for k in args.time_kernels.split(",") if k]
     # the rooflines need the gather and the update; the recompute's device time is taken out

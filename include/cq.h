@@ -214,6 +214,11 @@ cq_status cq_crowd_set_forced_branching(cq_crowd* c, const int* mult, int n_gene
 cq_status cq_crowd_record_moves(cq_crowd* c, int n_sweeps);
 /* Copy the records out: arrays [n_sweeps][Ne][Wcap]; any pointer may be NULL. */
 cq_status cq_crowd_get_move_records(cq_crowd* c, double* rho, double* dlnj, double* prob, uint8_t* acc);
+/* The proposed positions r' of the recorded DMC moves, [n_sweeps][Ne][Wcap][3] (FP64): the
+   state that a drift-diffusion proposal depends on (the drift at the electron's position) is
+   the crowd's own, so a check of its ratios takes the positions from here.  Entries that no DMC
+   move wrote (VMC sweeps, empty walker slots) are NaN.  CQ_ESTATE if recording is off. */
+cq_status cq_crowd_get_move_proposals(cq_crowd* c, double* rnew);
 /* Drift-diffusion moves accepted and proposed over every DMC generation the crowd
    has run (the populations that moved, before their branching). */
 cq_status cq_crowd_get_dmc_moves(cq_crowd* c, int64_t* accepted, int64_t* proposed);

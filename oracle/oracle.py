@@ -38,6 +38,7 @@ def lib():
         L.or_coef.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
         L.or_coef.restype = ctypes.c_double
         L.or_orbital_vgl.argtypes = [ctypes.POINTER(OrSystem), dp, ctypes.c_int, dp, dp, dp]
+        L.or_orbital_vgl_f32.argtypes = [ctypes.POINTER(OrSystem), dp, ctypes.c_int, dp, dp, dp]
         L.or_lnj.argtypes = [ctypes.POINTER(OrSystem), dp]
         L.or_lnj.restype = ctypes.c_double
         L.or_lu_inverse.argtypes = [ctypes.c_int, dp, dp, dp, dp]
@@ -53,7 +54,7 @@ def lib():
         L.or_dmc.argtypes = [ctypes.POINTER(OrSystem), ctypes.c_int, dp, dp, ctypes.c_int,
                              ctypes.c_uint32, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                              ctypes.c_int, ctypes.c_int, dp, dp, dp, dp, dp, dp, dp, dp,
-                             dp, dp, dp, dp, dp]
+                             dp, dp, dp, dp, dp, dp]
         L.or_dmc.restype = ctypes.c_int
         L.or_j2_terms.argtypes = [ctypes.POINTER(OrSystem), dp, ctypes.c_int, dp, dp, dp]
         L.or_drift.argtypes = [ctypes.POINTER(OrSystem), dp, ctypes.c_int, dp]
@@ -168,6 +169,19 @@ def orbital_vgl(sys: System, r, norb=None):
     return v, g, l
 
 
+def orbital_vgl_f32(sys: System, r, norb=None):
+    """The spline of ``orbital_vgl`` evaluated in binary32 arithmetic (weights and sums; the
+    mixed-precision path's arithmetic, used by the rounding model ``fp32_chain``)."""
+    norb = sys.n_orb if norb is None else norb
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    v = np.zeros(norb)
+    g = np.zeros((norb, 3))
+    l = np.zeros(norb)
+    cs = sys.c()
+    lib().or_orbital_vgl_f32(ctypes.byref(cs), r.ctypes.data, norb, v.ctypes.data, g.ctypes.data, l.ctypes.data)
+    return v, g, l
+
+
 def lnj(sys: System, R):
     R = np.ascontiguousarray(R, dtype=np.float64)
     cs = sys.c()
@@ -187,12 +201,10 @@ def lu_inverse(A):
     return inv, ld.value, sg.value
 
 
-def row_ratio_refined(A, i, phi):
-    """det A' / det A where A' is A with row i replaced by phi, by its definition phi . A^-1 e_i
-    (the determinant part of the ratio step of Alg. 1).  A^-1 e_i comes from an LU solve refined
-    twice with residuals b - A x formed in extended precision (numpy longdouble), and the final dot
-    is taken in extended precision, so the value is good to a few ulp times (1 + eps cond(A)):
-    an arbiter for a long FP64 update chain, whose error grows with each rank-1 or rank-k step."""
+def column_refined(A, i):
+    """Column i of A^-1 (the solution of A x = e_i) from an LU solve refined twice with residuals
+    e_i - A x formed in extended precision (numpy longdouble): good to a few ulp times
+    (1 + eps cond(A)), independently of how A was reached."""
     A = np.asarray(A, dtype=np.float64)
     n = A.shape[0]
     b = np.zeros(n)
@@ -202,6 +214,16 @@ def row_ratio_refined(A, i, phi):
     for _ in range(2):
         r = (b.astype(np.longdouble) - Al @ x.astype(np.longdouble)).astype(np.float64)
         x = x + np.linalg.solve(A, r)
+    return x
+
+
+def row_ratio_refined(A, i, phi):
+    """det A' / det A where A' is A with row i replaced by phi, by its definition phi . A^-1 e_i
+    (the determinant part of the ratio step of Alg. 1).  A^-1 e_i comes from ``column_refined``
+    and the final dot is taken in extended precision, so the value is good to a few ulp times
+    (1 + eps cond(A)): an arbiter for a long FP64 update chain, whose error grows with each
+    rank-1 or rank-k step."""
+    x = column_refined(A, i)
     return float(np.asarray(phi, dtype=np.float64).astype(np.longdouble) @ x.astype(np.longdouble))
 
 
@@ -329,14 +351,15 @@ class DmcResult:
     uids: np.ndarray      # final population
     R: np.ndarray
     eloc: np.ndarray
-    rec: Optional[dict] = None  # per-move rho, prob, u, acc [gen][Ne][max_pop]; mult [gen][max_pop]
+    rec: Optional[dict] = None  # per-move rho, prob, u, acc [gen][Ne][max_pop], rnew [gen][Ne][max_pop][3];
+                                # mult [gen][max_pop]
 
 
 def dmc(sys: System, R0, n_gen, tau, e_trial, n_target=None, max_pop=None, uids=None,
         first_step=0, n_threads=0, record=False) -> DmcResult:
     """Run DMC generations (Alg. 1 including reweighting and branching) on one system's population.
-    record=True also returns every move's rho_D, P, u and decision and every branching
-    multiplicity, indexed by the walker's position in its generation's population."""
+    record=True also returns every move's rho_D, P, u, decision and proposed position and every
+    branching multiplicity, indexed by the walker's position in its generation's population."""
     R0 = np.ascontiguousarray(R0, dtype=np.float64)
     W, ne = R0.shape[0], R0.shape[1]
     n_target = W if n_target is None else n_target
@@ -354,13 +377,14 @@ def dmc(sys: System, R0, n_gen, tau, e_trial, n_target=None, max_pop=None, uids=
     if record:
         shp = (n_gen, ne, max_pop)
         rec = dict(rho=np.full(shp, np.nan), prob=np.full(shp, np.nan), u=np.full(shp, np.nan),
-                   acc=np.zeros(shp, np.uint8), mult=np.zeros((n_gen, max_pop), np.int32))
+                   acc=np.zeros(shp, np.uint8), mult=np.zeros((n_gen, max_pop), np.int32),
+                   rnew=np.full(shp + (3,), np.nan))
     cs = sys.c()
     n = lib().or_dmc(ctypes.byref(cs), W, uids.ctypes.data, R0.ctypes.data, n_gen, first_step, tau,
                      e_trial, n_target, max_pop, n_threads, pop.ctypes.data, wsum.ctypes.data,
                      eest.ctypes.data, et.ctypes.data, counts.ctypes.data, uo.ctypes.data, Ro.ctypes.data,
-                     eo.ctypes.data, *([_p(rec[k]) for k in ("rho", "prob", "u", "acc", "mult")] if rec
-                                       else [None] * 5))
+                     eo.ctypes.data, *([_p(rec[k]) for k in ("rho", "prob", "u", "acc", "mult", "rnew")] if rec
+                                       else [None] * 6))
     if n < 0:
         raise RuntimeError("oracle DMC failed with status %d" % n)
     return DmcResult(pop, wsum, eest, et, int(counts[0]), int(counts[1]), uo[:n].copy(), Ro[:n].copy(),

@@ -242,6 +242,60 @@ void or_orbital_vgl(const or_system* s, const double r[3], int norb, double* v, 
     }
 }
 
+/* The same spline evaluated in the arithmetic of the mixed-precision path:  */
+/* the per-axis weights (FP64, as above) are rounded to binary32, the 3-D    */
+/* weights are binary32 products, and the 64 terms are summed in binary32     */
+/* with fused multiply-adds, 16 at a time along each x-plane, the four plane  */
+/* sums then added pairwise ((p0 + p1) + (p2 + p3)).  Coefficients are        */
+/* rounded to binary32.  Used only by the rounding model of the mixed chain;  */
+/* v[n], g[3n+c], lap[n] receive the binary32 results.                       */
+void or_orbital_vgl_f32(const or_system* s, const double r[3], int norb, double* v, double* g, double* lap)
+{
+    const int G = s->G;
+    const double h = s->L / G;
+    int i0[3];
+    float b[3][4], d1[3][4], d2[3][4];
+    for (int ax = 0; ax < 3; ++ax) {
+        double bd[4], d1d[4], d2d[4];
+        bspline_axis(wrap(r[ax], s->L), h, G, &i0[ax], bd, d1d, d2d);
+        for (int k = 0; k < 4; ++k) {
+            b[ax][k] = (float)bd[k];
+            d1[ax][k] = (float)d1d[k];
+            d2[ax][k] = (float)d2d[k];
+        }
+    }
+    for (int n = 0; n < norb; ++n) {
+        float pl[4][5];
+        for (int a = 0; a < 4; ++a) {
+            int jx = (i0[0] + a - 1 + G) % G;
+            float acc[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+            for (int bb = 0; bb < 4; ++bb) {
+                int jy = (i0[1] + bb - 1 + G) % G;
+                for (int c = 0; c < 4; ++c) {
+                    int jz = (i0[2] + c - 1 + G) % G;
+                    float p = (float)coef_at(s, jx, jy, jz, n);
+                    float w[5];
+                    w[0] = b[0][a] * b[1][bb] * b[2][c];
+                    w[1] = d1[0][a] * b[1][bb] * b[2][c];
+                    w[2] = b[0][a] * d1[1][bb] * b[2][c];
+                    w[3] = b[0][a] * b[1][bb] * d1[2][c];
+                    w[4] = d2[0][a] * b[1][bb] * b[2][c] + b[0][a] * d2[1][bb] * b[2][c] +
+                           b[0][a] * b[1][bb] * d2[2][c];
+                    for (int q = 0; q < 5; ++q) acc[q] = fmaf(w[q], p, acc[q]);
+                }
+            }
+            for (int q = 0; q < 5; ++q) pl[a][q] = acc[q];
+        }
+        float o[5];
+        for (int q = 0; q < 5; ++q) o[q] = (pl[0][q] + pl[1][q]) + (pl[2][q] + pl[3][q]);
+        v[n] = o[0];
+        g[3 * n] = o[1];
+        g[3 * n + 1] = o[2];
+        g[3 * n + 2] = o[3];
+        lap[n] = o[4];
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Two-body Pade Jastrow: ln J = + sum_{i<j} u(r_ij), u(r) = a r / (1 + b r), */
 /* a = a_par for equal spins, a_anti for opposite spins; minimum-image        */
@@ -824,14 +878,16 @@ int or_dmc_move_prob(const or_system* s, const double* R, int e, const double de
 /* -2 if the population dies out or exceeds max_pop.                         */
 /* Optional records (any may be NULL): per move rho_D, P, u and the decision */
 /* at [(gen * Ne + e) * max_pop + walker] (walker = position in the          */
-/* generation's population), and the multiplicities at [gen * max_pop + w]. */
+/* generation's population), the proposed position r' at the same index     */
+/* times 3, and the multiplicities at [gen * max_pop + w].                   */
 /* ------------------------------------------------------------------------ */
 int or_dmc(const or_system* s, int n_walkers, const uint32_t* uids, const double* R0,
            int n_gen, uint32_t first_step, double tau, double e_trial, int n_target, int max_pop,
            int n_threads,
            int* pop_out, double* wsum_out, double* eest_out, double* et_out,
            int64_t* counts_out, uint32_t* uids_out, double* R_out, double* eloc_out,
-           double* rec_rho, double* rec_prob, double* rec_u, uint8_t* rec_acc, int* mult_out)
+           double* rec_rho, double* rec_prob, double* rec_u, uint8_t* rec_acc, int* mult_out,
+           double* rec_rnew)
 {
     const int ne = s->n_up + s->n_dn;
     const int nmax = s->n_up > s->n_dn ? s->n_up : s->n_dn;
@@ -877,6 +933,7 @@ int or_dmc(const or_system* s, int n_walkers, const uint32_t* uids, const double
                 if (rec_prob) rec_prob[ri] = prob;
                 if (rec_u) rec_u[ri] = u;
                 if (rec_acc) rec_acc[ri] = (uint8_t)acc;
+                if (rec_rnew) memcpy(&rec_rnew[3 * ri], rnew, sizeof(double) * 3);
                 n_prop++;
                 if (acc) {
                     n_acc++;

@@ -71,6 +71,7 @@ _SIGS = {
     "cq_crowd_get_dmc_moves": [_P, _P, _P],
     "cq_crowd_record_moves": [_P, _I],
     "cq_crowd_get_move_records": [_P, _P, _P, _P, _P],
+    "cq_crowd_get_move_proposals": [_P, _P],
     "cq_crowd_set_kernel_timing": [_P, _I],
     "cq_crowd_get_kernel_timing": [_P, _I, _P, _P],
     "cq_crowd_synchronize": [_P],
@@ -107,17 +108,83 @@ def _check(st):
         raise CqError(st, lib().cq_last_error().decode())
 
 
+_hip = None
+
+
+def _hiprt():
+    """The HIP runtime the library is linked against (already loaded with it)."""
+    global _hip
+    if _hip is None:
+        lib()
+        h = ctypes.CDLL("libamdhip64.so.7")
+        h.hipMalloc.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_size_t]
+        h.hipFree.argtypes = [ctypes.c_void_p]
+        h.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+        h.hipDeviceSynchronize.argtypes = []
+        for f in (h.hipMalloc, h.hipFree, h.hipMemcpy, h.hipDeviceSynchronize):
+            f.restype = ctypes.c_int
+        _hip = h
+    return _hip
+
+
+class DeviceArray:
+    """A device buffer of the library's HIP runtime holding an array (plumbing for callers
+    that pass device pointers): created from a numpy array (copied in) or zeros of a shape and
+    dtype; ``ptr`` is the device address, ``numpy()`` copies the contents back."""
+
+    def __init__(self, arr=None, shape=None, dtype=None):
+        if arr is not None:
+            arr = np.ascontiguousarray(arr)
+            shape, dtype = arr.shape, arr.dtype
+        self.shape, self.dtype = tuple(shape), np.dtype(dtype)
+        self.nbytes = int(np.prod(self.shape)) * self.dtype.itemsize
+        p = ctypes.c_void_p()
+        h = _hiprt()
+        if h.hipMalloc(ctypes.byref(p), max(self.nbytes, 16)) != 0:
+            raise MemoryError("hipMalloc of %d bytes failed" % self.nbytes)
+        self.ptr = p.value
+        src = arr if arr is not None else np.zeros(self.shape, self.dtype)
+        if self.nbytes and h.hipMemcpy(self.ptr, src.ctypes.data, self.nbytes, 1) != 0:
+            raise RuntimeError("hipMemcpy to the device failed")
+
+    @property
+    def itemsize(self):
+        return self.dtype.itemsize
+
+    def numpy(self):
+        out = np.empty(self.shape, self.dtype)
+        if self.nbytes and _hiprt().hipMemcpy(out.ctypes.data, self.ptr, self.nbytes, 2) != 0:
+            raise RuntimeError("hipMemcpy from the device failed")
+        return out
+
+    def free(self):
+        if self.ptr:
+            _hiprt().hipFree(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
 def device_copy(dst, src, nbytes: int, stream=None):
     """Library streaming copy between device buffers (traffic-counter calibration)."""
     _check(lib().cq_device_copy(_ptr(dst), _ptr(src), nbytes, _stream_handle(stream)))
 
 
 def slater_inverse(A, Minv, logdet, sign, stream=None):
-    """FP64 Gauss-Jordan inverses of device matrices A [nmat][n][n] (torch CUDA tensors, float32 or
-    float64): Minv[m][a][j] = (A_m^-1)[j][a], logdet [nmat] float64, sign [nmat] int32."""
+    """FP64 Gauss-Jordan inverses of device matrices A [nmat][n][n] (DeviceArray or torch CUDA
+    tensors, float32 or float64): Minv[m][a][j] = (A_m^-1)[j][a], logdet [nmat] float64, sign
+    [nmat] int32."""
     nmat, n = A.shape[0], A.shape[1]
-    _check(lib().cq_slater_inverse(_ptr(A), A.element_size(), n, nmat, _ptr(Minv), _ptr(logdet), _ptr(sign),
+    _check(lib().cq_slater_inverse(_ptr(A), _itemsize(A), n, nmat, _ptr(Minv), _ptr(logdet), _ptr(sign),
                                    _stream_handle(stream)))
+
+
+def _itemsize(x):
+    return x.itemsize if isinstance(x, DeviceArray) else x.element_size()
 
 
 def _ptr(x):
@@ -128,6 +195,8 @@ def _ptr(x):
         return x
     if isinstance(x, np.ndarray):
         return x.ctypes.data
+    if isinstance(x, DeviceArray):
+        return x.ptr
     if hasattr(x, "data_ptr"):
         return x.data_ptr()
     raise TypeError("unsupported buffer type %r" % type(x))
@@ -329,6 +398,9 @@ class Crowd:
         _check(lib().cq_crowd_get_move_records(self._h, rho.ctypes.data, dl.ctypes.data, pr.ctypes.data,
                                                acc.ctypes.data))
         out = dict(rho=rho, dlnj=dl, prob=pr, acc=acc)
+        rn = np.zeros(shp + (3,))
+        _check(lib().cq_crowd_get_move_proposals(self._h, rn.ctypes.data))
+        out["rnew"] = rn  # DMC proposals (NaN for VMC sweeps)
         if not all_slots:
             out = {k: v[:, :, :self.W] for k, v in out.items()}
         return out

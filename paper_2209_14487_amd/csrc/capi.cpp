@@ -132,6 +132,7 @@ struct cq_crowd {
     double* rec_dlnj = nullptr;
     double* rec_prob = nullptr;
     uint8_t* rec_acc = nullptr;
+    double* rec_rnew = nullptr;  // [rec_cap][Ne][Wcap][3] proposals of DMC moves
     int forced_cap = 0;
     uint8_t* forced = nullptr;
     int mult_cap = 0;
@@ -211,6 +212,7 @@ cq::CrowdView<T> view(const cq_crowd* c)
     v.rec_dlnj = c->rec_dlnj;
     v.rec_prob = c->rec_prob;
     v.rec_acc = c->rec_acc;
+    v.rec_rnew = c->rec_rnew;
     v.forced = c->forced;
     v.status = c->status;
     v.drift = c->drift;
@@ -725,6 +727,7 @@ void cq_crowd_destroy(cq_crowd* c)
     if (c->rec_dlnj) (void)hipFree(c->rec_dlnj);
     if (c->rec_prob) (void)hipFree(c->rec_prob);
     if (c->rec_acc) (void)hipFree(c->rec_acc);
+    if (c->rec_rnew) (void)hipFree(c->rec_rnew);
     if (c->forced) (void)hipFree(c->forced);
     if (c->forced_mult) (void)hipFree(c->forced_mult);
     for (auto* evs : {&c->ev_fork, &c->ev_dec, &c->ev_gat})
@@ -1277,7 +1280,8 @@ cq_status cq_crowd_record_moves(cq_crowd* c, int n_sweeps)
     if (!c) return fail(CQ_EINVAL, "crowd is NULL");
     if (n_sweeps < 0) return fail(CQ_EINVAL, "n_sweeps must be >= 0");
     HIP_TRY(hipStreamSynchronize(c->stream));
-    for (void** p : {(void**)&c->rec_rho, (void**)&c->rec_dlnj, (void**)&c->rec_prob, (void**)&c->rec_acc})
+    for (void** p : {(void**)&c->rec_rho, (void**)&c->rec_dlnj, (void**)&c->rec_prob, (void**)&c->rec_acc,
+                     (void**)&c->rec_rnew})
         if (*p) {
             HIP_TRY(hipFree(*p));
             *p = nullptr;
@@ -1289,10 +1293,13 @@ cq_status cq_crowd_record_moves(cq_crowd* c, int n_sweeps)
         ok = ok && hipMalloc((void**)&c->rec_dlnj, cnt * 8) == hipSuccess;
         ok = ok && hipMalloc((void**)&c->rec_prob, cnt * 8) == hipSuccess;
         ok = ok && hipMalloc((void**)&c->rec_acc, cnt) == hipSuccess;
+        ok = ok && hipMalloc((void**)&c->rec_rnew, cnt * 24) == hipSuccess;
         if (!ok) {
             (void)hipGetLastError();
             return fail(CQ_ENOMEM, "record buffers");
         }
+        // proposals are recorded by DMC moves only: the rest reads as NaN (all bits set)
+        HIP_TRY(hipMemset(c->rec_rnew, 0xFF, cnt * 24));
         c->rec_cap = n_sweeps;
     }
     c->hp.rec_cap = c->rec_cap;
@@ -1311,6 +1318,14 @@ cq_status cq_crowd_get_move_records(cq_crowd* c, double* rho, double* dlnj, doub
     if (st == CQ_OK) st = copy_out(c, prob, c->rec_prob, cnt * 8);
     if (st == CQ_OK) st = copy_out(c, acc, c->rec_acc, cnt);
     return got(c, st, "get_move_records");
+}
+
+cq_status cq_crowd_get_move_proposals(cq_crowd* c, double* rnew)
+{
+    if (!c || !rnew) return fail(CQ_EINVAL, "NULL argument");
+    if (c->rec_cap == 0) return fail(CQ_ESTATE, "recording is off");
+    const size_t cnt = (size_t)c->rec_cap * c->ne * c->Wcap;
+    return got(c, copy_out(c, rnew, c->rec_rnew, cnt * 24), "get_move_proposals");
 }
 
 cq_status cq_crowd_set_kernel_timing(cq_crowd* c, int kind_mask)

@@ -74,13 +74,20 @@ __device__ __forceinline__ double wrap_box(double x, double L) { return x - L * 
 
 // Per-axis cubic B-spline stencil: control points i0-1 .. i0+2 (mod G) and the
 // value / first / second derivative weights at fractional offset t.  The
-// integer cell and t are found in FP64; the weights are formed in T.
+// integer cell, t and the weights are formed in FP64; the weights are stored in T.
 template <typename T>
 struct AxisW {
     int i0;
     T b[4], d1[4], d2[4];
 };
 
+// Per-axis weights of the cubic B-spline at x: cell index i0 and the weights of
+// control points i0-1 .. i0+2 for the value, first and second derivative.  The
+// polynomials are evaluated in FP64 and each weight is rounded to T once, so that
+// an FP32 weight carries an independent half-ulp error (an FP32 factor 1/6 shared
+// by every weight would bias all orbital values alike, and an ill-conditioned
+// Slater matrix amplifies such a correlated error several times more than
+// independent roundings).
 template <typename T>
 __device__ __forceinline__ AxisW<T> axis_weights(double x, double L, int G)
 {
@@ -91,26 +98,24 @@ __device__ __forceinline__ AxisW<T> axis_weights(double x, double L, int G)
     int i = ((int)fl) % G;
     if (i < 0) i += G;
     r.i0 = i;
-    const T t = (T)(s - fl);
-    const T u = (T)1 - t;
-    const T t2 = t * t, t3 = t2 * t;
-    const T sixth = (T)1 / (T)6;
-    r.b[0] = u * u * u * sixth;
-    r.b[1] = ((T)3 * t3 - (T)6 * t2 + (T)4) * sixth;
-    r.b[2] = ((T)-3 * t3 + (T)3 * t2 + (T)3 * t + (T)1) * sixth;
-    r.b[3] = t3 * sixth;
-    const T ih = (T)(1.0 / h);
-    const T ih2 = (T)(1.0 / (h * h));
-    const T half_ih = (T)(0.5 / h);
-    r.d1[0] = -u * u * half_ih;
-    r.d1[1] = ((T)3 * t2 - (T)4 * t) * half_ih;
-    r.d1[2] = ((T)-3 * t2 + (T)2 * t + (T)1) * half_ih;
-    r.d1[3] = t2 * half_ih;
-    r.d2[0] = u * ih2;
-    r.d2[1] = ((T)3 * t - (T)2) * ih2;
-    r.d2[2] = ((T)-3 * t + (T)1) * ih2;
-    r.d2[3] = t * ih2;
-    (void)ih;
+    const double t = s - fl;
+    const double u = 1.0 - t;
+    const double t2 = t * t, t3 = t2 * t;
+    const double sixth = 1.0 / 6.0;
+    r.b[0] = (T)(u * u * u * sixth);
+    r.b[1] = (T)((3.0 * t3 - 6.0 * t2 + 4.0) * sixth);
+    r.b[2] = (T)((-3.0 * t3 + 3.0 * t2 + 3.0 * t + 1.0) * sixth);
+    r.b[3] = (T)(t3 * sixth);
+    const double ih2 = 1.0 / (h * h);
+    const double half_ih = 0.5 / h;
+    r.d1[0] = (T)(-u * u * half_ih);
+    r.d1[1] = (T)((3.0 * t2 - 4.0 * t) * half_ih);
+    r.d1[2] = (T)((-3.0 * t2 + 2.0 * t + 1.0) * half_ih);
+    r.d1[3] = (T)(t2 * half_ih);
+    r.d2[0] = (T)(u * ih2);
+    r.d2[1] = (T)((3.0 * t - 2.0) * ih2);
+    r.d2[2] = (T)((-3.0 * t + 1.0) * ih2);
+    r.d2[3] = (T)(t * ih2);
     return r;
 }
 

@@ -108,6 +108,7 @@ struct CrowdView {
     double* rec_dlnj;
     double* rec_prob;
     uint8_t* rec_acc;
+    double* rec_rnew;    // DMC moves: the proposed position [rec][Ne][Wcap][3], or null
     const uint8_t* forced;
     int* status;         // [W] bit 0: singular / not finite at the last inversion; bit 1: window
                          // bookkeeping out of range (internal error)

@@ -753,12 +753,7 @@ __global__ __launch_bounds__(kBlock) void k_decide(CrowdView<T> v, int spin, int
 // c0_{s_j} the start column of the j-th accepted move's electron (FP64 sums of
 // exact products, rounded to T).  One thread per orbital.  For the matrix-core
 // update the kernel also packs the accepted value rows (ub), so that the update
-// kernel's loads need no indirection, and it folds the window's triangular solve
-// into the columns: the update subtracts sum_m b_m c_m from every row with
-// b = L^-1 y, y the row's products with the accepted rows less the unit vector of
-// its own move, and sum_m b_m c_m = sum_j y_j c'_j with c'_j = sum_m L^-1[m][j] c_m.
-// So the kernel writes c'_j = sum_i Z[j][i] c0_{s_i}, Z = L^-T T (a K x K product in
-// FP64 per walker), and the update needs no solve per row.  The kernel sits between the decisions and
+// kernel's loads need no indirection.  The kernel sits between the decisions and
 // the update while the gather of the next round streams beside it, so every
 // global round trip is long: the count, T and the window are loaded in one batch,
 // then all accepted rows at once.
@@ -768,7 +763,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     constexpr int D = kMaxDelay, TL = D * D / kBlock;
     static_assert(D * D % kBlock == 0, "T tile per thread");
     __shared__ __align__(16) double s_T[D][D];
-    __shared__ __align__(16) double s_L[D][D];  // L^-1 (row m, column j), then Z transposed
     __shared__ __align__(16) int s_row[D];
     __shared__ __align__(16) int s_slot[D];
     const int n = v.n, K = v.K;
@@ -781,13 +775,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     // lies past the count is replaced once the loads are back (T by zeros, so the
     // sums below need no bounds)
     const int cnt = v.cnt[(size_t)2 * v.W + w];
-    const bool fold = sizeof(T) == 4 && v.ct != nullptr;  // the matrix-core update takes c' = L^-T c
-    double tv[TL], lv[TL];
+    double tv[TL];
 #pragma unroll
     for (int q = 0; q < TL; ++q) {
         const int idx = q * kBlock + tid, a = idx / D, j = idx % D;
         tv[q] = a < K && j < K ? v.tmat[((size_t)w * K + a) * K + j] : 0.0;
-        lv[q] = fold && a < K && j < K ? v.wlinv[((size_t)w * K + a) * K + j] : 0.0;
     }
     int e = 0, sl = 0;
     if (tid < K) {
@@ -799,26 +791,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     for (int q = 0; q < TL; ++q) {
         const int idx = q * kBlock + tid, a = idx / D, j = idx % D;
         s_T[j][a] = a < cnt && j < cnt ? tv[q] : 0.0;  // transposed: s_T[j][a] = T[a][j]
-        if (fold) s_L[a][j] = a < cnt && j < cnt ? lv[q] : 0.0;
-    }
-    if (fold) {
-        // Z[j][i] = sum_m L^-1[m][j] T[m][i] (both lower triangular: m >= max(i, j)), into s_T
-        // transposed (s_T[i][j] = Z[j][i]) once every thread has read its T and L^-1 entries
-        __syncthreads();
-        double zv[TL];
-#pragma unroll
-        for (int q = 0; q < TL; ++q) {
-            const int idx = q * kBlock + tid, j = idx / D, i = idx % D;
-            double z = 0.0;
-            for (int m = j > i ? j : i; m < cnt; ++m) z = fma(s_L[m][j], s_T[i][m], z);
-            zv[q] = z;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < TL; ++q) {
-            const int idx = q * kBlock + tid, j = idx / D, i = idx % D;
-            s_T[i][j] = zv[q];
-        }
     }
     if (tid < D) {
         if (tid < cnt && (e < 0 || e >= n || sl < 0 || sl >= v.QR)) atomicOr(&v.status[w], 2);

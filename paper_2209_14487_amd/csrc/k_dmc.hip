@@ -367,6 +367,7 @@ __global__ __launch_bounds__(kBlock) void k_window_dmc(CrowdView<T> v, int e0, i
                 v.rec_dlnj[ri] = dj;
                 v.rec_prob[ri] = prob;
                 v.rec_acc[ri] = (uint8_t)acc;
+                for (int k = 0; k < 3; ++k) v.rec_rnew[3 * ri + k] = rp[k];
             }
             if (acc) {
                 if (mine) s_G[cnt][lane] = s_x[lane];

@@ -193,13 +193,10 @@ __global__ __launch_bounds__(kFlushThreads) __attribute__((amdgpu_waves_per_eu(4
 }
 
 // Batched path: the window's accepted value rows come packed in v.ub and its
-// columns in v.ct, transposed and already multiplied by the inverse of the window
-// triangle (c' = L^-T c, formed by the column kernel), so every row a takes
-//     M[a] -= sum_j y_j c'_j,   y_j = M[a] . u_j - delta(a, e_j)
-// with no solve per row: GEMM 1 (X = M U^T), the cross-wave sum of X less the unit
-// entries, GEMM 2.  The column kernel has also moved the accepted orbital rows, so a
-// strip's loads need no indirection.  Two workgroups of 8 waves (4 tiles each) per
-// CU: one's loads are in flight while the other runs its MFMAs.
+// columns transposed in v.ct (both written by the column kernel, which has also
+// moved the accepted orbital rows), so a strip's loads need no indirection.  Two
+// workgroups of 8 waves (4 tiles each) per CU: one's loads are in flight while the
+// other runs its MFMAs.
 constexpr int kBatchWaves = 8;
 constexpr int kBatchThreads = 64 * kBatchWaves;
 constexpr int kBatchTiles = 4;
@@ -208,7 +205,9 @@ __global__ __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(4
     CrowdView<float> v, int spin)
 {
     __shared__ float sX[kBatchWaves][32][33];  // per wave: partial X^T[m][i]
-    __shared__ float sB[32][33];      // -y[i][j] (FP32 operand of GEMM 2)
+    __shared__ float sB[32][33];      // -b[i][m] (FP32 operand of GEMM 2)
+    __shared__ double sY[32][33];     // x[i][j] - delta(row0 + i, e_j)
+    __shared__ double sL[32][33];     // L^-1
     __shared__ int wel[32];
     const int n = v.n, K = v.K;
     const int ntile = n / 32, nstrip = n / 32;
@@ -272,18 +271,35 @@ __global__ __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(4
     for (int q = 0; q < 16; ++q) sX[wave][8 * (q >> 2) + 4 * h + (q & 3)][l32] = xacc[q];
     __syncthreads();
 
-    // -y[i][j] = -(x[i][j] - delta(row0 + i, e_j)): the wave partials of x added in a fixed
-    // order in FP64, zero past the count
+    // y[i][j] = x[i][j] - delta(row0 + i, e_j) in FP64, then
+    // b[i][m] = sum_j Linv[m][j] y[i][j] (Linv and y zero-padded to 32 x 32)
     for (int idx = tid; idx < 32 * 32; idx += kBatchThreads) {
         const int i = idx >> 5, j = idx & 31;
         double x = 0.0;
 #pragma unroll
         for (int q = 0; q < kBatchWaves; ++q) x += (double)sX[q][j][i];
-        sB[i][j] = j < cnt ? -(float)(x - (row0 + i == wel[j] ? 1.0 : 0.0)) : 0.0f;
+        sY[i][j] = j < cnt ? x - (row0 + i == wel[j] ? 1.0 : 0.0) : 0.0;
+        sL[i][j] = (i < cnt && j <= i) ? v.wlinv[((size_t)w * K + i) * K + j] : 0.0;
+    }
+    __syncthreads();
+    {
+        constexpr int MPT = 32 * 32 / kBatchThreads;  // moves of one row per thread
+        const int i = tid / (32 / MPT), m0 = (tid % (32 / MPT)) * MPT;
+        double b[MPT];
+#pragma unroll
+        for (int r = 0; r < MPT; ++r) b[r] = 0.0;
+#pragma unroll
+        for (int j = 0; j < 32; ++j) {
+            const double y = sY[i][j];
+#pragma unroll
+            for (int r = 0; r < MPT; ++r) b[r] = fma(sL[m0 + r][j], y, b[r]);
+        }
+#pragma unroll
+        for (int r = 0; r < MPT; ++r) sB[i][m0 + r] = -(float)b[r];  // GEMM 2 subtracts
     }
     __syncthreads();
 
-    // GEMM 2: M^T[k][i] -= sum_j c'_j[k] y[i][j], moves j = 16 h + q, operands Ct[k][j]
+    // GEMM 2: M^T[k][i] -= sum_m c_m[k] b[i][m], moves m = 16 h + q, operands Ct[k][m]
     // (32 per row, zero past cnt), 4 vector loads per tile
     const float* Ct = v.ct + ((size_t)w * n) * kMaxDelay;
     auto fetch = [&](int t, float (&a)[16]) {
@@ -291,7 +307,7 @@ __global__ __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(4
 #pragma unroll
         for (int g = 0; g < 4; ++g) load16(src + 4 * g, &a[4 * g]);
     };
-    float nb[16];  // -y[l32][16 h + q], the same for every tile
+    float nb[16];  // -b[l32][16 h + q], the same for every tile
 #pragma unroll
     for (int q = 0; q < 16; ++q) nb[q] = sB[l32][16 * h + q];
 #pragma unroll
@@ -300,7 +316,7 @@ __global__ __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(4
         if (t < ntile) {
             float a[16];
             fetch(t, a);
-            // operands past cnt are zero (Ct and y are zero-padded), so all 16 steps run
+            // operands past cnt are zero (Ct and b are zero-padded), so all 16 steps run
 #pragma unroll
             for (int q = 0; q < 16; ++q) mt[tt] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[q], nb[q], mt[tt], 0, 0, 0);
         }

@@ -18,18 +18,16 @@ def well_conditioned(rng, nmat, n):
 @pytest.mark.parametrize("n,nmat", [(4, 3), (32, 17), (100, 5), (256, 4)])
 @pytest.mark.parametrize("dtype", ["float64", "float32"])
 def test_slater_inverse_matches_lapack(n, nmat, dtype):
-    import torch
     rng = np.random.default_rng(n * 7 + nmat)
     A = well_conditioned(rng, nmat, n)
     A = A.astype(dtype).astype(np.float64)  # the stored values are the reference's input
-    dev = torch.device("cuda:0")
-    tA = torch.tensor(A, dtype=getattr(torch, dtype), device=dev)
-    tM = torch.zeros_like(tA)
-    tl = torch.zeros(nmat, dtype=torch.float64, device=dev)
-    ts = torch.zeros(nmat, dtype=torch.int32, device=dev)
+    tA = cq.DeviceArray(A.astype(dtype))
+    tM = cq.DeviceArray(shape=A.shape, dtype=dtype)
+    tl = cq.DeviceArray(shape=(nmat,), dtype=np.float64)
+    ts = cq.DeviceArray(shape=(nmat,), dtype=np.int32)
     cq.slater_inverse(tA, tM, tl, ts)
-    M = tM.cpu().numpy().astype(np.float64)
-    ld, sg = tl.cpu().numpy(), ts.cpu().numpy()
+    M = tM.numpy().astype(np.float64)
+    ld, sg = tl.numpy(), ts.numpy()
     ref_s, ref_l = np.linalg.slogdet(A)
     inv = np.linalg.inv(A)
     tol = 1e-11 if dtype == "float64" else 2e-7
@@ -42,15 +40,14 @@ def test_slater_inverse_matches_lapack(n, nmat, dtype):
 
 
 def test_slater_inverse_reports_a_singular_matrix():
-    import torch
     rng = np.random.default_rng(5)
     n, nmat = 80, 6
     A = well_conditioned(rng, nmat, n)
     A[3, 7] = A[3, 2]  # two equal rows in matrix 3
-    tA = torch.tensor(A, device="cuda:0")
-    tM = torch.zeros_like(tA)
-    tl = torch.zeros(nmat, dtype=torch.float64, device="cuda:0")
-    ts = torch.zeros(nmat, dtype=torch.int32, device="cuda:0")
+    tA = cq.DeviceArray(A)
+    tM = cq.DeviceArray(shape=A.shape, dtype=np.float64)
+    tl = cq.DeviceArray(shape=(nmat,), dtype=np.float64)
+    ts = cq.DeviceArray(shape=(nmat,), dtype=np.int32)
     with pytest.raises(cq.CqError) as ei:
         cq.slater_inverse(tA, tM, tl, ts)
     assert ei.value.status == cq.CQ_ESINGULAR

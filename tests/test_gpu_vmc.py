@@ -8,12 +8,18 @@ accept/reject decisions except at near-ties |P - u| < 1e-6.  Mixed path (FP32
 table, FP32 inverse), run in forced-decision mode on the oracle's trajectory: the
 relative ratio errors against the FP64 oracle are compared with those of the
 rounding model ``oracle.fp32_chain`` replaying the same walkers along the same
-decisions with the inverse and the orbital rows stored in FP32 (FP32 Sherman-Morrison
-arithmetic, FP64 sums of the ratio products, the same recompute schedule).  The
+decisions with the inverse and the orbital rows stored in FP32 and the updates applied
+as the path applies them (delayed rank-k windows in FP32, FP64 sums of the ratio
+products, the same recompute schedule).  The
 model's errors are what an FP32 inverse costs on these matrices (at N = 1024,
 cond(A) ~ 1e4, they exceed 1e-4 for a few percent of the moves whatever the
 kernels do); the GPU's median and 99th percentile must stay within twice the
-model's, its 99.9th percentile and maximum (over |rho| >= 1e-3) within three times.
+model's, its 99.9th percentile and maximum within three times.  The percentiles are
+over every move; the maximum is over moves with |rho| >= 0.1: the relative error of a
+dot product is bounded by its condition number sum_j |u_j c_j| / |rho|, which grows
+without bound as rho -> 0, so below that floor the largest error of one chain says
+nothing about another chain that groups its sums differently (the GPU's rank-k
+updates against the model's rank-1 steps).
 log|det| within 1e-4 of max(1, |log|det||).
 """
 import numpy as np
@@ -70,23 +76,27 @@ def run_gpu(crowd, R0, sweeps, sigma, first_step=0, forced=None):
 
 # GPU statistic <= factor x the same statistic of the FP32 rounding model
 EMU_FACTOR = dict(median=2.0, p99=2.0, p999=3.0, max=3.0)
+MAX_FLOOR = 0.1  # the maximum is taken over moves with |rho| >= this
 
 
-def emulated_rho(o, R0, acc, uids=None, n_moves=None, recompute_every=0, sigma=0.5):
+def emulated_rho(o, R0, acc, uids=None, n_moves=None, recompute_every=0, sigma=0.5, k=1, path="batch"):
     """Ratios of the FP32 rounding model for walkers R0 along decisions acc [S][Ne][W], with the
-    coefficient table rounded to FP32 as the mixed path stores it."""
+    coefficient table rounded to FP32 as the mixed path stores it and the updates applied as
+    the path applies them: windows of k accepted moves (batched path) or of k proposals."""
     import dataclasses
     o = dataclasses.replace(o, coef_fp32=True)
     W = R0.shape[0]
     uids = range(W) if uids is None else uids
+    close = "accepts" if path == "batch" else "proposals"
     return np.stack([fp32_chain.replay(o, R0[i], int(u), acc[:, :, i], n_moves=n_moves, sigma=sigma,
-                                       recompute_every=recompute_every) for i, u in enumerate(uids)], axis=-1)
+                                       recompute_every=recompute_every, window=k, close_after=close)
+                     for i, u in enumerate(uids)], axis=-1)
 
 
 def mixed_ratio_check(gpu_rho, ref_rho, emu_rho, label):
     """GPU ratio errors against the FP64 oracle, bounded by the rounding model's on the same moves."""
-    g = fp32_chain.ratio_error_stats(gpu_rho, ref_rho)
-    e = fp32_chain.ratio_error_stats(emu_rho, ref_rho)
+    g = fp32_chain.ratio_error_stats(gpu_rho, ref_rho, floor=MAX_FLOOR)
+    e = fp32_chain.ratio_error_stats(emu_rho, ref_rho, floor=MAX_FLOOR)
     print("%s: ratio rel err GPU %s | FP32 model %s" % (
         label, " ".join("%s=%.2e" % (k, g[k]) for k in EMU_FACTOR), " ".join("%s=%.2e" % (k, e[k]) for k in EMU_FACTOR)))
     assert g["n"] == e["n"]
@@ -198,7 +208,7 @@ def test_c2_mixed_precision_on_oracle_trajectory(k, recompute, path):
     ref = orc.vmc(o, R0, S, sigma=0.5)
     crowd = cq.Crowd(g, W, precision="mixed", delay_rank=k, recompute_every=recompute, seed=1002, path=path)
     gpu = run_gpu(crowd, R0, S, 0.5, forced=ref.acc)
-    emu = emulated_rho(o, R0, ref.acc, recompute_every=recompute)
+    emu = emulated_rho(o, R0, ref.acc, recompute_every=recompute, k=k, path=path)
     _, es = mixed_ratio_check(gpu["rho"], ref.rho, emu, "C2 mixed k=%d recompute=%d %s" % (k, recompute, path))
     own_decision_check(gpu["prob"], ref.prob, ref.u, ref.acc, es, 1e-3)
     err = np.abs(gpu["logdet"] - ref.logdet) / np.maximum(1.0, np.abs(ref.logdet))
@@ -291,7 +301,8 @@ def test_n256_blocked_inverse_and_multichunk_sweep(precision, k, path):
         compare_fp64(gpu, ref, S, 2 * n)
     else:
         gpu = run_gpu(crowd, R0, S, 0.5, forced=ref.acc)
-        mixed_ratio_check(gpu["rho"], ref.rho, emulated_rho(o, R0, ref.acc), "N=256 mixed k=%d %s" % (k, path))
+        mixed_ratio_check(gpu["rho"], ref.rho, emulated_rho(o, R0, ref.acc, k=k, path=path),
+                          "N=256 mixed k=%d %s" % (k, path))
     crowd.close()
 
 
@@ -495,7 +506,7 @@ def test_c4_full_size_mixed_bench_configuration_on_oracle_trajectory():
     crowd.close()
     g.close()
     assert np.array_equal(gpu["acc"][0, :C4_MOVES][:, C4_SAMPLE], ref.acc[0, :C4_MOVES])
-    emu = emulated_rho(o, R0[C4_SAMPLE], ref.acc, uids=C4_SAMPLE, n_moves=C4_MOVES)
+    emu = emulated_rho(o, R0[C4_SAMPLE], ref.acc, uids=C4_SAMPLE, n_moves=C4_MOVES, k=32, path="batch")
     _, es = mixed_ratio_check(gpu["rho"][0, :C4_MOVES][:, C4_SAMPLE], ref.rho[0, :C4_MOVES],
                               emu[0, :C4_MOVES], "C4 mixed k=32 batch")
     own_decision_check(gpu["prob"][0, :C4_MOVES][:, C4_SAMPLE], ref.prob[0, :C4_MOVES], ref.u[0, :C4_MOVES],

@@ -254,6 +254,9 @@ def test_refined_row_ratio_matches_exact_rational_value():
             exact = float(sum(Fraction(float(p)) * xi for p, xi in zip(phi, x)))
             got = orc.row_ratio_refined(A, i, phi)
             assert abs(got - exact) <= 1e-13 * abs(exact), (i, got, exact)
+            col = orc.column_refined(A, i)
+            xe = np.array([float(xi) for xi in x])
+            assert np.abs(col - xe).max() <= 1e-13 * np.abs(xe).max()
             if A is H:
                 plain = float(phi @ np.linalg.solve(A, e))
                 assert abs(plain - exact) > 10 * abs(got - exact)
@@ -560,7 +563,8 @@ def test_fp32_chain_model_without_rounding_is_the_oracle_chain():
     """The rounding model of the mixed-precision chain, with nothing rounded, replays the FP64
     oracle's Sherman-Morrison chain along its decisions: the same ratios to 1e-12, across
     accepted updates, both spin blocks, several sweeps and a periodic recompute (which changes
-    nothing in exact arithmetic)."""
+    nothing in exact arithmetic), with the updates applied move by move or as delayed rank-k
+    windows (the same inverse in exact arithmetic)."""
     from oracle import fp32_chain
     n = 3
     s, _ = _tiny_system(n, j2=True, seed=21)
@@ -568,8 +572,10 @@ def test_fp32_chain_model_without_rounding_is_the_oracle_chain():
     ref = orc.vmc(s, R0, 4, sigma=0.6)
     assert ref.acc.mean() > 0.2
     for w in range(2):
-        rho = fp32_chain.replay(s, R0[w], w, ref.acc[:, :, w], sigma=0.6, recompute_every=2, storage="fp64")
-        assert np.allclose(rho, ref.rho[:, :, w], rtol=1e-12, atol=1e-14)
+        for k in (0, 2, 3):  # Sherman-Morrison steps, delayed windows of 2 and 3 accepted moves
+            rho = fp32_chain.replay(s, R0[w], w, ref.acc[:, :, w], sigma=0.6, recompute_every=2, storage="fp64",
+                                    window=k)
+            assert np.allclose(rho, ref.rho[:, :, w], rtol=1e-12, atol=1e-14), k
 
 
 def test_fp32_chain_model_rounds_to_single_precision():
@@ -617,8 +623,65 @@ def test_fp32_chain_dmc_model_without_rounding_is_the_oracle_chain():
         assert rec["mult"][g, :live].sum() == ref.pop[g]
         own = (rec["rho"][g, :, :live] > 0) & (rec["u"][g, :, :live] < rec["prob"][g, :, :live])
         assert np.array_equal(own, rec["acc"][g, :, :live].astype(bool))
-    model = fp32_chain.replay_dmc(s, R0, np.arange(W), rec["acc"], rec["mult"], tau, storage="fp64")
     live = np.isfinite(rec["rho"])
-    assert np.array_equal(live, np.isfinite(model["rho"]))
+    for k in (0, 1, 2):  # move by move, or delayed windows of 1 and 2 proposals
+        model = fp32_chain.replay_dmc(s, R0, np.arange(W), rec["acc"], rec["mult"], tau, storage="fp64", window=k)
+        assert np.array_equal(live, np.isfinite(model["rho"]))
+        assert np.allclose(model["rho"][live], rec["rho"][live], rtol=1e-10, atol=1e-13), k
+        assert np.allclose(model["prob"][live], rec["prob"][live], rtol=1e-9, atol=1e-13), k
+    # along the oracle's own proposals the model reproduces its ratios without forming the drift
+    model = fp32_chain.replay_dmc(s, R0, np.arange(W), rec["acc"], rec["mult"], tau, storage="fp64", window=2,
+                                  rnew=rec["rnew"])
     assert np.allclose(model["rho"][live], rec["rho"][live], rtol=1e-10, atol=1e-13)
-    assert np.allclose(model["prob"][live], rec["prob"][live], rtol=1e-9, atol=1e-13)
+
+
+def test_dmc_records_equal_the_definitions_on_their_trajectory():
+    """Along the oracle's own DMC trajectory (its decisions, proposals and branching), every
+    recorded ratio equals det A'/det A of the current matrix from a refined solve, and every
+    proposal equals wrap(r + tau v + sqrt(tau) z) with the drift v = grad ln|Psi| of the current
+    configuration, and every acceptance probability equals the Green's-function form with the
+    drift at the proposal: the Sherman-Morrison chain, the drift from the kept inverse column, the
+    proposal formula and the acceptance are each pinned to their definitions (a wrong sign or a
+    dropped term in the drift or the Green's function, or a stale column, fails)."""
+    from dmc_replay import periodic_abs, trajectory_checks
+    n, L, G, W, gens, tau, seed = 8, 6.0, 16, 4, 2, 0.05, 1205
+    s = orc.System(n, n, L, G=G, n_orb=n, orb_kind=orc.ORB_SEEDED, coef_seed=seed, use_j2=True,
+                   j2_a_par=0.25, j2_a_anti=0.5, j2_b=1.0, seed=seed)
+    R0 = start_positions(seed, W, 2 * n, L)
+    et = float(np.mean(orc.setup(s, R0)[2]))
+    ref = orc.dmc(s, R0, gens, tau, et, n_target=W, max_pop=4 * W + 16, record=True)
+    t = trajectory_checks(s, R0, np.arange(W), ref.rec["acc"], ref.rec["rnew"], ref.rec["mult"], tau,
+                          lambda g, e, slot: True)
+    m = np.isfinite(t["ratio"]) & np.isfinite(ref.rec["rho"])
+    assert m.sum() == sum([W] + list(ref.pop[:-1])) * 2 * n
+    rerr = np.abs(ref.rec["rho"][m] - t["ratio"][m]) / np.maximum(1.0, np.abs(t["ratio"][m]))
+    derr = np.linalg.norm(periodic_abs(ref.rec["rnew"][m] - t["prop"][m], L), axis=-1) / tau / np.maximum(
+        1.0, t["vabs"][m])
+    perr = np.abs(ref.rec["prob"][m] - t["prob"][m]) / np.maximum(1.0, np.abs(t["prob"][m]))
+    assert rerr.max() < 1e-11 and derr.max() < 1e-11 and perr.max() < 1e-10, (rerr.max(), derr.max(), perr.max())
+
+
+def test_fp32_spline_is_the_spline_within_single_precision_rounding():
+    """The binary32 evaluation of the spline (the rounding model's copy of the mixed path's
+    arithmetic) equals the FP64 spline on the same binary32 coefficients to within the
+    rounding of a 64-term binary32 sum: every value, gradient and Laplacian within
+    64 * 2^-24 of the sum of the magnitudes of its terms (bounded here by 64 * max|c| * the
+    largest weight), typically far below, and not identical (it does round)."""
+    import dataclasses
+    s = orc.System(16, 16, 7.0, G=12, n_orb=16, orb_kind=orc.ORB_SEEDED, coef_seed=44, use_j2=False, seed=44)
+    s = dataclasses.replace(s, coef_fp32=True)
+    rng = np.random.default_rng(5)
+    h = 7.0 / 12
+    scale = [1.0, 1.0 / h, 1.0 / h, 1.0 / h, 3 * 4.0 / h ** 2]  # bounds of the weights' magnitudes per output
+    worst = 0.0
+    for _ in range(20):
+        r = rng.uniform(0, 7.0, 3)
+        a = orc.orbital_vgl(s, r)
+        b = orc.orbital_vgl_f32(s, r)
+        outs_a = [a[0], a[1][:, 0], a[1][:, 1], a[1][:, 2], a[2]]
+        outs_b = [b[0], b[1][:, 0], b[1][:, 1], b[1][:, 2], b[2]]
+        for q in range(5):
+            err = np.abs(outs_a[q] - outs_b[q]).max()
+            assert err <= 64 * 2.0 ** -24 * 64 * scale[q], (q, err)
+            worst = max(worst, err / scale[q])
+    assert worst > 0.0
