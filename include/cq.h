@@ -295,6 +295,24 @@ void cq_crowd_destroy(cq_crowd* c);
 cq_status cq_slater_inverse(const void* A, int elem_bytes, int n, int nmat, void* Minv, double* logdet, int* sign,
                             void* hip_stream);
 
+/* Size of the library's static inversion workspace (bytes, per GPU). */
+#define CQ_STATIC_WORK_BYTES ((uint64_t)64 << 20)
+
+/* cq_slater_inverse without any allocation, for callers that cannot allocate device
+   memory (work recorded under graph capture, tight serving loops, harnesses that forbid
+   hipMalloc).  Same arguments, results and errors as cq_slater_inverse, computed by the
+   same kernels, but the workspace is a static device array of CQ_STATIC_WORK_BYTES
+   bytes that the library holds on each GPU it runs on until the process ends (looked up
+   at the first call on a device); the call makes no hipMalloc, hipFree or other
+   allocating call.  The workspace needed is about nmat (n^2 + 64 n) 8 bytes for n > 64
+   (nmat (4 + 8) bytes for n <= 64): CQ_EINVAL names the size when it exceeds the array
+   (64 MiB holds, e.g., 7 matrices of n = 1024 or 120 of n = 256).  Every call on one
+   GPU shares that GPU's array: calls that overlap on one GPU (several host threads, or
+   streams without ordering between them) race; serialise them.  Returns when the
+   results are written. */
+cq_status cq_slater_inverse_static(const void* A, int elem_bytes, int n, int nmat, void* Minv, double* logdet,
+                                   int* sign, void* hip_stream);
+
 /* Plain streaming device-to-device copy of `bytes` bytes (multiple of 16,
    16-byte aligned pointers) with a library kernel on `hip_stream` (NULL: the
    null stream), synchronous.  Its hardware traffic counters give the scale

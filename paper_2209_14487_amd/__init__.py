@@ -77,6 +77,7 @@ _SIGS = {
     "cq_crowd_synchronize": [_P],
     "cq_device_copy": [_P, _P, ctypes.c_uint64, _P],
     "cq_slater_inverse": [_P, _I, _I, _I, _P, _P, _P, _P],
+    "cq_slater_inverse_static": [_P, _I, _I, _I, _P, _P, _P, _P],
     "cq_crowd_destroy": [_P],
     "cq_last_error": [],
 }
@@ -181,6 +182,13 @@ def slater_inverse(A, Minv, logdet, sign, stream=None):
     nmat, n = A.shape[0], A.shape[1]
     _check(lib().cq_slater_inverse(_ptr(A), _itemsize(A), n, nmat, _ptr(Minv), _ptr(logdet), _ptr(sign),
                                    _stream_handle(stream)))
+
+
+def slater_inverse_static(A, Minv, logdet, sign, stream=None):
+    """slater_inverse on the library's static workspace (no device allocation)."""
+    nmat, n = A.shape[0], A.shape[1]
+    _check(lib().cq_slater_inverse_static(_ptr(A), _itemsize(A), n, nmat, _ptr(Minv), _ptr(logdet), _ptr(sign),
+                                          _stream_handle(stream)))
 
 
 def _itemsize(x):

@@ -1410,9 +1410,9 @@ cq_status slater_inverse_impl(const T* A, int n, int nmat, T* Minv, double* logd
     v.status = status;
     v.drift = drift;
     v.drift_max = nullptr;
-    HIP_TRY(hipMemsetAsync(status, 0, sizeof(int) * (size_t)pairs, st));
+    cq::launch_zero(status, sizeof(int) * (size_t)pairs, st);
     // the kernels read the previous log|det| for a drift figure that this call does not report
-    HIP_TRY(hipMemsetAsync(logdet, 0, sizeof(double) * (size_t)nmat, st));
+    cq::launch_zero(logdet, sizeof(double) * (size_t)nmat, st);
     cq::launch_inverse<T>(v, wk, st, nmat);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(st));

@@ -192,6 +192,7 @@ template <typename T>
 void launch_dmc_branch(const DmcView& d, const WalkerArrays<T>& src, const WalkerArrays<T>& dst, int n, int ne,
                        const Params* prm, int gen, hipStream_t s);
 void launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
+void launch_zero(void* p, size_t bytes, hipStream_t s);  // bytes: a multiple of 4
 size_t inverse_work_bytes(int nmat, int n);
 // Batched inversion of caller-held matrices (the C ABI's cq_slater_inverse and its variant on
 // the library's static workspace): bytes of workspace it needs, argument checks, the inversion.

@@ -15,6 +15,8 @@
 // coalesced along orbitals.  Four waves split the 4 x-planes of the stencil;
 // their partial sums meet in LDS in a fixed order (bit-reproducible results,
 // independent of how walkers are grouped into crowds).
+#include <algorithm>
+
 #include "cq_device.h"
 #include "cq_internal.h"
 
@@ -555,6 +557,22 @@ __global__ __launch_bounds__(kBlock) void k_copy16(float4* __restrict__ dst, con
 void launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s)
 {
     hipLaunchKernelGGL(k_copy16, dim3(4096), dim3(kBlock), 0, s, (float4*)dst, (const float4*)src, bytes / 16);
+}
+
+// Zero fill of count 32-bit words (a kernel rather than a memset node, so that work a
+// caller captures into a graph replays it correctly).
+__global__ __launch_bounds__(kBlock) void k_zero32(uint32_t* p, size_t count)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+void launch_zero(void* p, size_t bytes, hipStream_t s)
+{
+    const size_t count = bytes / 4;
+    if (count == 0) return;
+    const size_t blocks = std::min<size_t>(1024, (count + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_zero32, dim3((unsigned)blocks), dim3(kBlock), 0, s, (uint32_t*)p, count);
 }
 
 template void launch_fill_philox<float>(float*, uint64_t, size_t, hipStream_t);
