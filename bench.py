@@ -58,7 +58,36 @@ def parse():
                     help="moves of the one-core CPU oracle figure (0: skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 1 GiB with the library's plain copy kernel (counter calibration runs)")
+    ap.add_argument("--scan", default="",
+                    help="crowd/walker scan instead of the bench line: comma-separated CROWDSxWALKERS pairs "
+                         "(e.g. 1x512,2x512,4x512); each is timed over --steps sweeps after --warmup, graph replay")
     return ap.parse_args()
+
+
+def run_scan(cq, args):
+    """Moves/s over crowds x walkers per crowd on one GPU (the workload's system, its delay rank and
+    recompute period): crowds are independent streams launched from one host thread, each replaying
+    its captured sweep graph, so they overlap on the GPU (the paper's crowds over threads, Alg. 4)."""
+    import dataclasses
+    from synth import WORKLOADS
+    base = WORKLOADS[args.workload]
+    delay = args.delay if args.delay is not None else base.delay_rank
+    rows = []
+    for pair in args.scan.split(","):
+        nc, nw = (int(x) for x in pair.lower().split("x"))
+        wl = dataclasses.replace(base, crowds=nc, walkers=nw)
+        r = run_gpu(cq, wl, "mixed", delay, wl.recompute_every, args.steps, args.warmup, [], True, path=args.path)
+        rows.append(dict(crowds=nc, walkers_per_crowd=nw, walkers=nc * nw, moves_per_s=round(r["moves_per_s"], 1),
+                         ms_per_sweep=round(1e3 * r["seconds"] / args.steps, 3), acceptance=round(r["acceptance"], 4)))
+        log("  scan %d crowd(s) x %d walkers: %.3e moves/s" % (nc, nw, r["moves_per_s"]))
+    out = dict(metric="electron moves/sec at 1 GPU over crowds x walkers per crowd", unit="moves/s",
+               higher_is_better=True, dtype="f32", n_gpus=1, steps=args.steps, warmup=args.warmup,
+               data="synthetic (seeded Philox B-spline coefficients, uniform starting positions)",
+               config=dict(workload="%s: %d+%d electrons, L=%g bohr, %d^3 FP32 table, Pade J2, delayed rank %d, "
+                                    "FP64 recompute every %d sweeps, mixed precision, graph replay"
+                                    % (base.name, base.n, base.n, base.L, base.G, delay, base.recompute_every)),
+               scan=rows)
+    print(json.dumps(out), flush=True)
 
 
 def make_system(cq, wl, elem_bytes):
@@ -325,8 +354,11 @@ def run_c5(cq, args):
     def one(wl, precision, out):
         s = make_system(cq, wl, 4 if precision == "mixed" else 8)
         cap = 4 * wl.walkers + 64
+        # mixed precision recomputes the inverses in FP64 after every generation: a generation
+        # accepts nearly every move (about N FP32 updates per spin), and without it the FP32
+        # chains of the larger systems drift past the mixed tolerance within two generations
         c = cq.Crowd(s, wl.walkers, precision=precision, delay_rank=wl.delay_rank, seed=wl.seed,
-                     max_walkers=cap, path="window")
+                     max_walkers=cap, path="window", recompute_every=1 if precision == "mixed" else 0)
         c.set_positions(start_positions(wl.seed, wl.walkers, wl.n_e, wl.L))
         c.run_vmc(4, wl.sigma)  # equilibrate in VMC before the first DMC generation
         e0 = float(np.mean(c.local_energy()))
@@ -366,8 +398,8 @@ def run_c5(cq, args):
                ms_per_step=round(1e3 * span / max(gens, 1), 3), higher_is_better=True, scaling="weak",
                vs_baseline=None, dtype="f32", data="synthetic (seeded Philox B-spline coefficients, uniform starts)",
                config=dict(workload="c5: DMC tau=0.01, S1 32+32 e L=10 G=48 target 2000, S2 256+256 e L=20 G=64 "
-                                    "target 500, S3 1024+1024 e L=32 G=96 target 64; mixed; one crowd per "
-                                    "system on its own stream"),
+                                    "target 500, S3 1024+1024 e L=32 G=96 target 64; mixed with an FP64 recompute "
+                                    "after every generation; one crowd per system on its own stream"),
                per_system={k: dict(moves_per_s=round(v["moves"] / v["seconds"], 1), pop=v["pop"], e_t=v["e_t"])
                            for k, v in mixed.items()},
                fp64_per_system_moves_per_s=round(f64_moves / f64_s, 1),
@@ -387,6 +419,9 @@ def main():
     from synth import WORKLOADS
     if args.workload == "c5":
         run_c5(cq, args)
+        return
+    if args.scan:
+        run_scan(cq, args)
         return
     wl = WORKLOADS[args.workload]
     delay = args.delay if args.delay is not None else wl.delay_rank
