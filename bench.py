@@ -58,10 +58,48 @@ def parse():
                     help="moves of the one-core CPU oracle figure (0: skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 1 GiB with the library's plain copy kernel (counter calibration runs)")
+    ap.add_argument("--virtual-points", type=int, default=12,
+                    help="quadrature points per electron of the timed virtual-move launch (0: skip)")
     ap.add_argument("--scan", default="",
                     help="crowd/walker scan instead of the bench line: comma-separated CROWDSxWALKERS pairs "
                          "(e.g. 1x512,2x512,4x512); each is timed over --steps sweeps after --warmup, graph replay")
     return ap.parse_args()
+
+
+def run_virtual(cq, wl, nq, launches=3):
+    """Ratio-only virtual moves of every electron of every walker to nq icosahedral points of
+    radius 0.5 bohr (mixed precision, set-up state), timed with HIP events on the crowd's stream.
+    Algorithmic bytes per point: the 64 stencil rows of the value-only spline, 64 N 4 B."""
+    from synth import icosahedron_offsets, start_positions
+    system = make_system(cq, wl, 4)
+    W = wl.walkers
+    c = cq.Crowd(system, W, precision="mixed", delay_rank=wl.delay_rank, seed=wl.seed)
+    c.set_positions(start_positions(wl.seed, W, wl.n_e, wl.L))
+    off = np.vstack([icosahedron_offsets(0.5), icosahedron_offsets(0.25)])[:nq]
+    out = cq.DeviceArray(shape=(W, wl.n_e, nq), dtype=np.float64)
+    c.virtual_ratios(off, out=(out, None, None))  # warm-up
+    c.synchronize()
+    c.set_timing(("virtual",))
+    for _ in range(launches):
+        c.virtual_ratios(off, out=(out, None, None))
+    c.synchronize()
+    ms, cnt = c.kernel_timing("virtual")
+    c.set_timing(())
+    ratios = out.numpy()
+    c.close()
+    system.close()
+    out.free()
+    t = 1e-3 * ms / cnt
+    points = W * wl.n_e * nq
+    bytes_alg = points * 64 * wl.n * 4
+    gbs = bytes_alg / t / 1e9
+    return dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s", frac=round(gbs / HBM_PEAK_GBS, 4),
+                traffic=None, kernel="k_virtual", us_per_launch=round(t * 1e6, 3), points_per_launch=points,
+                bytes_per_launch=bytes_alg, points_per_s=round(points / t, 1), finite=bool(np.isfinite(ratios).all()),
+                note="value-only spline at %d points around every electron (radius 0.5 and 0.25 bohr) and the "
+                     "dot with its inverse column, plus the Jastrow sums; algorithmic bytes = 64 N 4 B per "
+                     "point (neighbouring points share stencil rows, so cache reuse can take the figure past "
+                     "HBM speed)" % nq)
 
 
 def run_scan(cq, args):
@@ -506,6 +544,10 @@ def main():
         sm = run_gpu(cq, wl, "fp64", 1, 0, args.sm_steps, 0, ["update"], False, path=args.path)
         out["roofline_sm"] = roofline_sm(sm, n, 8)
         log("  SM update (FP64, k = 1): %.0f GB/s" % out["roofline_sm"]["achieved"])
+    if args.virtual_points > 0:
+        out["roofline_virtual"] = run_virtual(cq, wl, args.virtual_points)
+        log("  virtual moves: %.0f GB/s (algorithmic), %.3e points/s" % (out["roofline_virtual"]["achieved"],
+                                                                        out["roofline_virtual"]["points_per_s"]))
     if not args.no_cpu:
         log("  cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_moves, cq, args.cpu_one_core_moves)

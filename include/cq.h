@@ -64,7 +64,8 @@ typedef enum {
     CQ_KERNEL_INVERSE = 4,  /* FP64 Gauss-Jordan inversion (initial and periodic recompute) */
     CQ_KERNEL_PROPOSE = 5,  /* proposals and stencils of a round's gather range, and the Jastrow
                                sums of its new candidates (BATCH) */
-    CQ_KERNEL_COUNT = 6
+    CQ_KERNEL_VIRTUAL = 6,  /* ratio-only virtual moves (cq_crowd_virtual_ratios) */
+    CQ_KERNEL_COUNT = 7
 } cq_kernel_kind;
 
 /* Mapping of the moves to the GPU.  All paths compute the same Markov chain
@@ -255,6 +256,21 @@ cq_status cq_crowd_get_delay_rank(cq_crowd* c, int* k);
    crowd then keeps the last complete generation). */
 cq_status cq_crowd_run_dmc(cq_crowd* c, int n_generations, double tau, double e_trial, int n_target,
                            double* history);
+
+/* Virtual moves: the ratio-only wavefunction evaluations of the local-energy step of Alg. 1
+   (the energy evaluation is the expensive part of a step, Sec. II-A; a non-local energy term
+   needs Psi at quadrature points around an electron without moving it).  For every walker w,
+   electron e (row i of its spin block) and point q of the current state:
+     r_q = wrap(r_e + offsets[q]),  rho_D = sum_j phi_j(r_q) (A^-1)_{j,i},
+     dlnJ = sum_{m != e} [u(|r_q - r_m|) - u(|r_e - r_m|)],  ratio = rho_D exp(dlnJ),
+   with phi in the crowd's precision (FP32 table in mixed precision, the products with the
+   inverse column summed in FP64) and the Jastrow pair terms likewise.  offsets: host array
+   [n_q][3] (bohr), 1 <= n_q <= 64.  ratio, rho, dlnj: [W][Ne][n_q] FP64, any may be NULL;
+   out_on_device = 0: host arrays, the call synchronises; 1: device buffers owned by the
+   caller, the call is asynchronous on the crowd's stream.  Nothing in the crowd changes.
+   Errors: CQ_EINVAL, CQ_ESTATE (positions not set). */
+cq_status cq_crowd_virtual_ratios(cq_crowd* c, const double* offsets, int n_q, double* ratio, double* rho,
+                                  double* dlnj, int out_on_device);
 
 /* Current number of walkers (changes under DMC branching). */
 cq_status cq_crowd_get_population(cq_crowd* c, int* n_walkers);

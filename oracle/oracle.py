@@ -61,6 +61,9 @@ def lib():
         L.or_drift.restype = ctypes.c_int
         L.or_dmc_move_prob.argtypes = [ctypes.POINTER(OrSystem), dp, ctypes.c_int, dp, ctypes.c_double, dp, dp]
         L.or_dmc_move_prob.restype = ctypes.c_int
+        L.or_virtual_ratios.argtypes = [ctypes.POINTER(OrSystem), ctypes.c_int, dp, ctypes.c_int, dp,
+                                        ctypes.c_int, dp, dp, dp]
+        L.or_virtual_ratios.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -389,3 +392,18 @@ def dmc(sys: System, R0, n_gen, tau, e_trial, n_target=None, max_pop=None, uids=
         raise RuntimeError("oracle DMC failed with status %d" % n)
     return DmcResult(pop, wsum, eest, et, int(counts[0]), int(counts[1]), uo[:n].copy(), Ro[:n].copy(),
                      eo[:n].copy(), rec)
+
+
+def virtual_ratios(sys: System, R0, offsets, n_threads=0):
+    """Virtual moves of every electron of every walker to r_e + offsets[q] (the ratio-only
+    evaluations of the local-energy step of Alg. 1): (ratio, rho_D, dlnJ), each [W][Ne][n_q],
+    with ratio = Psi(R with r_e -> r_q) / Psi(R) = rho_D exp(dlnJ) at the set-up state."""
+    R0 = np.ascontiguousarray(R0, dtype=np.float64)
+    off = np.ascontiguousarray(offsets, dtype=np.float64).reshape(-1, 3)
+    W, ne, nq = R0.shape[0], R0.shape[1], off.shape[0]
+    out = [np.zeros((W, ne, nq)) for _ in range(3)]
+    cs = sys.c()
+    if lib().or_virtual_ratios(ctypes.byref(cs), W, R0.ctypes.data, nq, off.ctypes.data, n_threads,
+                               *[o.ctypes.data for o in out]) != 0:
+        raise ZeroDivisionError("singular configuration")
+    return tuple(out)

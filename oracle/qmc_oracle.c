@@ -770,6 +770,63 @@ int or_vmc(const or_system* s, int n_walkers, const uint32_t* uids, const double
     return status;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Virtual moves (the ratio-only evaluations of the local-energy step of     */
+/* Alg. 1, Sec. II-A: a non-local energy term needs Psi at points around an  */
+/* electron, without moving it).  For every walker (configuration R, set up */
+/* from scratch), electron e and point q:                                    */
+/*   r_q = wrap(r_e + offsets[q]),                                          */
+/*   rho_D = sum_j phi_j(r_q) (A^-1)_{j,i}   (i: e's row in its spin block), */
+/*   dlnJ = sum_{m != e} [u(|r_q - r_m|) - u(|r_e - r_m|)],                   */
+/*   ratio = Psi(R with r_e -> r_q) / Psi(R) = rho_D exp(dlnJ).              */
+/* Outputs [W][Ne][n_q] (any may be NULL).  Returns -1 if a configuration is */
+/* singular.                                                                 */
+/* ------------------------------------------------------------------------ */
+int or_virtual_ratios(const or_system* s, int n_walkers, const double* R0, int n_q, const double* offsets,
+                      int n_threads, double* ratio_out, double* rho_out, double* dlnj_out)
+{
+    const int ne = s->n_up + s->n_dn;
+    const int nmax = s->n_up > s->n_dn ? s->n_up : s->n_dn;
+    int status = 0;
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel for schedule(dynamic, 1) reduction(min : status)
+#endif
+    for (int iw = 0; iw < n_walkers; ++iw) {
+        walker w;
+        walker_alloc(s, &w);
+        memcpy(w.R, &R0[(size_t)iw * ne * 3], sizeof(double) * ne * 3);
+        if (walker_setup(s, &w) != 0) {
+            status = -1;
+            walker_free(&w);
+            continue;
+        }
+        double* v = (double*)malloc(sizeof(double) * nmax);
+        double* g = (double*)malloc(sizeof(double) * 3 * nmax);
+        double* l = (double*)malloc(sizeof(double) * nmax);
+        for (int e = 0; e < ne; ++e) {
+            int sp = spin_of(s, e);
+            int n = sp == 0 ? s->n_up : s->n_dn;
+            int i = e - sp * s->n_up;
+            for (int q = 0; q < n_q; ++q) {
+                double rq[3];
+                for (int c = 0; c < 3; ++c) rq[c] = wrap(w.R[3 * e + c] + offsets[3 * q + c], s->L);
+                or_orbital_vgl(s, rq, n, v, g, l);
+                double rho = 0;
+                for (int j = 0; j < n; ++j) rho += v[j] * w.Ainv[sp][(size_t)j * n + i];
+                double dj = j2_delta(s, w.R, e, rq);
+                size_t o = ((size_t)iw * ne + e) * n_q + q;
+                if (ratio_out) ratio_out[o] = rho * exp(dj);
+                if (rho_out) rho_out[o] = rho;
+                if (dlnj_out) dlnj_out[o] = dj;
+            }
+        }
+        free(v); free(g); free(l);
+        walker_free(&w);
+    }
+    return status;
+}
+
 /* Initial state only: A, G, L, Ainv, log|det|, sign and E_L for each walker. */
 int or_setup(const or_system* s, int n_walkers, const double* R0, int n_threads,
              double* logdet_out, int* sign_out, double* eloc_out, double* ainv_out)

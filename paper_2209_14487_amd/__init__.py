@@ -21,9 +21,10 @@ LIB_PATH = os.path.join(_HERE, "libcrowdqmc.so")
 CQ_OK, CQ_EINVAL, CQ_ENOMEM, CQ_EDEVICE, CQ_ESINGULAR, CQ_ESTATE = range(6)
 CQ_FP64, CQ_MIXED = 0, 1
 PATHS = {"auto": 0, "multi": 1, "window": 2, "batch": 3}
-KERNEL_VGL, KERNEL_RESOLVE, KERNEL_UPDATE, KERNEL_ENERGY, KERNEL_INVERSE, KERNEL_PROPOSE = range(6)
+KERNEL_VGL, KERNEL_RESOLVE, KERNEL_UPDATE, KERNEL_ENERGY, KERNEL_INVERSE, KERNEL_PROPOSE, KERNEL_VIRTUAL = range(7)
 KERNEL_NAMES = {"vgl": KERNEL_VGL, "resolve": KERNEL_RESOLVE, "update": KERNEL_UPDATE,
-                "energy": KERNEL_ENERGY, "inverse": KERNEL_INVERSE, "propose": KERNEL_PROPOSE}
+                "energy": KERNEL_ENERGY, "inverse": KERNEL_INVERSE, "propose": KERNEL_PROPOSE,
+                "virtual": KERNEL_VIRTUAL}
 
 _STATUS_NAMES = {1: "CQ_EINVAL", 2: "CQ_ENOMEM", 3: "CQ_EDEVICE", 4: "CQ_ESINGULAR", 5: "CQ_ESTATE"}
 
@@ -56,6 +57,7 @@ _SIGS = {
     "cq_crowd_run_vmc": [_P, _I, ctypes.c_double],
     "cq_crowd_run_dmc": [_P, _I, ctypes.c_double, ctypes.c_double, _I, _P],
     "cq_crowd_get_population": [_P, _P],
+    "cq_crowd_virtual_ratios": [_P, _P, _I, _P, _P, _P, _I],
     "cq_crowd_autotune": [_P, _I, _P],
     "cq_crowd_get_delay_rank": [_P, _P],
     "cq_crowd_get_uids": [_P, _P],
@@ -313,6 +315,19 @@ class Crowd:
         k = ctypes.c_int()
         _check(lib().cq_crowd_get_delay_rank(self._h, ctypes.byref(k)))
         return k.value
+
+    def virtual_ratios(self, offsets, out=None):
+        """Ratio-only virtual moves of every electron to r_e + offsets[q] ([n_q][3]): returns
+        (ratio, rho_D, dlnJ) host arrays [W][Ne][n_q]; with out = (ratio, rho, dlnj) device
+        buffers (DeviceArray or None each) the call only enqueues the kernel."""
+        off = np.ascontiguousarray(offsets, dtype=np.float64).reshape(-1, 3)
+        nq = off.shape[0]
+        if out is not None:
+            _check(lib().cq_crowd_virtual_ratios(self._h, off.ctypes.data, nq, *[_ptr(o) for o in out], 1))
+            return None
+        res = [np.zeros((self.W, self.ne, nq)) for _ in range(3)]
+        _check(lib().cq_crowd_virtual_ratios(self._h, off.ctypes.data, nq, *[r.ctypes.data for r in res], 0))
+        return tuple(res)
 
     def population(self) -> int:
         n = ctypes.c_int()

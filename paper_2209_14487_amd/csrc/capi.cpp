@@ -90,6 +90,11 @@ struct cq_crowd {
         long long* nprop = nullptr;
     } alt;
     bool have_alt = false;
+    // virtual moves: quadrature offsets and (host-output case) result staging
+    double* voff = nullptr;
+    int voff_cap = 0;
+    double* vout = nullptr;
+    size_t vout_cap = 0;
     cq::DmcState* dmc_state = nullptr;
     double* dmc_wt = nullptr;
     int* dmc_mult = nullptr;
@@ -728,6 +733,8 @@ void cq_crowd_destroy(cq_crowd* c)
     if (c->rec_prob) (void)hipFree(c->rec_prob);
     if (c->rec_acc) (void)hipFree(c->rec_acc);
     if (c->rec_rnew) (void)hipFree(c->rec_rnew);
+    if (c->voff) (void)hipFree(c->voff);
+    if (c->vout) (void)hipFree(c->vout);
     if (c->forced) (void)hipFree(c->forced);
     if (c->forced_mult) (void)hipFree(c->forced_mult);
     for (auto* evs : {&c->ev_fork, &c->ev_dec, &c->ev_gat})
@@ -1135,6 +1142,59 @@ static cq_status got(cq_crowd* c, cq_status st, const char* where)
     if (st != CQ_OK) return st;
     return check_singular(c, where);
 }
+
+cq_status cq_crowd_virtual_ratios(cq_crowd* c, const double* offsets, int n_q, double* ratio, double* rho,
+                                  double* dlnj, int out_on_device)
+{
+    if (!c || !offsets) return fail(CQ_EINVAL, "NULL argument");
+    if (n_q < 1 || n_q > 64) return fail(CQ_EINVAL, "n_q must be 1..64");
+    if (!c->ready) return fail(CQ_ESTATE, "positions not set");
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (n_q > c->voff_cap) {
+        if (c->voff) HIP_TRY(hipFree(c->voff));
+        c->voff = nullptr;
+        c->voff_cap = 0;
+        if (hipMalloc((void**)&c->voff, sizeof(double) * 3 * 64) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(CQ_ENOMEM, "virtual-move offsets");
+        }
+        c->voff_cap = 64;
+    }
+    HIP_TRY(hipMemcpy(c->voff, offsets, sizeof(double) * 3 * (size_t)n_q, hipMemcpyHostToDevice));
+    const size_t cnt = (size_t)c->W * c->ne * n_q;
+    double* d[3] = {ratio, rho, dlnj};
+    if (!out_on_device) {
+        // staging for the host outputs, kept for later calls
+        if (3 * cnt > c->vout_cap) {
+            if (c->vout) HIP_TRY(hipFree(c->vout));
+            c->vout = nullptr;
+            c->vout_cap = 0;
+            if (hipMalloc((void**)&c->vout, sizeof(double) * 3 * cnt) != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(CQ_ENOMEM, "virtual-move outputs");
+            }
+            c->vout_cap = 3 * cnt;
+        }
+        for (int k = 0; k < 3; ++k) d[k] = d[k] ? c->vout + k * cnt : nullptr;
+    }
+    timed_begin(c, CQ_KERNEL_VIRTUAL);
+    if (c->prec == CQ_FP64)
+        cq::launch_virtual<double>(view<double>(c), c->voff, n_q, d[0], d[1], d[2], c->stream);
+    else
+        cq::launch_virtual<float>(view<float>(c), c->voff, n_q, d[0], d[1], d[2], c->stream);
+    timed_end(c, CQ_KERNEL_VIRTUAL);
+    HIP_TRY(hipGetLastError());
+    if (!out_on_device) {
+        double* h[3] = {ratio, rho, dlnj};
+        for (int k = 0; k < 3; ++k) {
+            cq_status st = copy_out(c, h[k], d[k], sizeof(double) * cnt);
+            if (st != CQ_OK) return st;
+        }
+        return got(c, CQ_OK, "virtual_ratios");
+    }
+    return CQ_OK;
+}
+
 
 cq_status cq_crowd_get_logdet(cq_crowd* c, double* logdet, int* sign)
 {

@@ -191,6 +191,9 @@ template <typename T> void launch_window_dmc(const CrowdView<T>& v, int e0, int 
 template <typename T>
 void launch_dmc_branch(const DmcView& d, const WalkerArrays<T>& src, const WalkerArrays<T>& dst, int n, int ne,
                        const Params* prm, int gen, hipStream_t s);
+template <typename T>
+void launch_virtual(const CrowdView<T>& v, const double* offsets, int nq, double* ratio, double* rho, double* dlnj,
+                    hipStream_t s);
 void launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 void launch_zero(void* p, size_t bytes, hipStream_t s);  // bytes: a multiple of 4
 size_t inverse_work_bytes(int nmat, int n);

@@ -25,7 +25,7 @@ from typing import Optional
 
 import numpy as np
 
-__all__ = ["Workload", "WORKLOADS", "start_positions", "planewave_table", "workload"]
+__all__ = ["Workload", "WORKLOADS", "start_positions", "planewave_table", "workload", "icosahedron_offsets"]
 
 
 @dataclass(frozen=True)
@@ -104,3 +104,17 @@ def planewave_table(G: int, L: float) -> np.ndarray:
     t[..., 2] = (np.sin(k * x) / beta)[:, None, None]
     t[..., 3] = (np.cos(k * x) / beta)[None, :, None]
     return t
+
+
+def icosahedron_offsets(radius: float) -> np.ndarray:
+    """The 12 vertices of a regular icosahedron on the sphere of the given radius, [12][3]:
+    the points of a 12-point spherical quadrature (equal weights, exact for spherical harmonics
+    of degree up to 5), a synthetic stand-in for the quadrature points of a non-local
+    pseudopotential around an electron."""
+    phi = (1.0 + 5.0 ** 0.5) / 2.0
+    v = []
+    for a in (-1.0, 1.0):
+        for b in (-phi, phi):
+            v += [(0.0, a, b), (a, b, 0.0), (b, 0.0, a)]
+    v = np.array(v)
+    return radius * v / np.linalg.norm(v, axis=1, keepdims=True)

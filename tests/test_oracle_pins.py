@@ -685,3 +685,49 @@ def test_fp32_spline_is_the_spline_within_single_precision_rounding():
             assert err <= 64 * 2.0 ** -24 * 64 * scale[q], (q, err)
             worst = max(worst, err / scale[q])
     assert worst > 0.0
+
+
+# ---------------------------------------------------- virtual moves (ratio only)
+
+def test_virtual_ratios_are_wavefunction_ratios():
+    """Every virtual-move ratio equals Psi(R with r_e -> r_q) / Psi(R) from two direct evaluations
+    of the wavefunction (LU determinants of both spin blocks and the full pair sum of the
+    Jastrow), for electrons of both spins, with a point that crosses the periodic boundary."""
+    from synth import icosahedron_offsets
+    n = 3
+    s, d = _tiny_system(n, j2=True, seed=31)
+    R = start_positions(95, 2, 2 * n, s.L)
+    R[0, 1] = [s.L - 0.05, 0.3, 1.1]  # its points near +x wrap across the box edge
+    off = np.vstack([icosahedron_offsets(0.4), [[0.2, -0.1, 0.05]]])
+    ratio, rho, dlnj = orc.virtual_ratios(s, R, off)
+    assert np.allclose(ratio, rho * np.exp(dlnj), rtol=1e-14)
+    for w in range(2):
+        s0, l0 = d.log_psi(R[w])
+        for e in range(2 * n):
+            for q in range(off.shape[0]):
+                R2 = R[w].copy()
+                R2[e] = np.mod(R2[e] + off[q], s.L)
+                s1, l1 = d.log_psi(R2)
+                ref = s0 * s1 * np.exp(l1 - l0)
+                assert abs(ratio[w, e, q] - ref) <= 1e-11 * max(1.0, abs(ref)), (w, e, q, ratio[w, e, q], ref)
+
+
+def test_virtual_ratios_spherical_mean_of_plane_waves():
+    """For analytic plane-wave orbitals {1, cos kx, sin kx, cos ky} (no Jastrow) the ratio of a
+    virtual move of electron e to r_e + d n is sum_j phi_j(r_e + d n) (A^-1)_{j,e}; its spherical
+    mean over n is sum_j sinc(k_j d) phi_j(r_e) (A^-1)_{j,e}, and summed over the electrons of a
+    spin block the trace identity leaves sum_j sinc(k_j d): with the 12-point icosahedral rule
+    (exact to degree 5) sum_e mean_q(ratio_eq) = sum_j sinc(k_j d) up to O((k d)^6)."""
+    from synth import icosahedron_offsets
+    n, L = 4, 5.0
+    s = orc.System(n, n, L, G=16, n_orb=n, orb_kind=orc.ORB_PLANEWAVE, use_j2=False, seed=1)
+    R = start_positions(96, 3, 2 * n, L)
+    k = 2 * np.pi / L
+    for dd in (0.3, 0.15):
+        ratio, _, _ = orc.virtual_ratios(s, R, icosahedron_offsets(dd))
+        per_spin = ratio.mean(axis=2).reshape(3, 2, n).sum(axis=2)  # [W][spin]
+        exact = 1.0 + 3.0 * np.sin(k * dd) / (k * dd)
+        tol = 2.0 * n * (k * dd) ** 6 / 5040.0
+        assert np.all(np.abs(per_spin - exact) <= tol), (dd, per_spin, exact)
+        # and not trivially: the d^2 term is resolved
+        assert np.all(np.abs(per_spin - 4.0) > 100 * tol)
