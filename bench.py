@@ -381,67 +381,95 @@ def gpu_errors(cq, wl, o, R0, ref, moves):
 
 def run_c5(cq, args):
     """C5: DMC (tau = 0.01) on three systems at once (S1/S2/S3: 32, 256, 1024 electrons per spin;
-    target populations 2000, 500, 64), mixed precision, one crowd per system on its own stream,
-    driven by its own host thread; against the same generations in FP64 run one system after
-    another.  Moves per second over all systems (accepted + rejected drift-diffusion moves)."""
+    target populations 2000, 500, 64), mixed precision, as ONE crowd of the three systems: per spin
+    block and window step one launch of the move kernel serves the walkers of all three systems
+    (largest first) and one launch their updates.  Compared with the same generations in FP64, one
+    system after another (per-system launches), and with three mixed crowds on three streams
+    driven by three host threads.  Moves per second over all systems (accepted + rejected
+    drift-diffusion moves of the populations that moved)."""
     import threading
     from synth import WORKLOADS, start_positions
     systems = [WORKLOADS[k] for k in ("c5s1", "c5s2", "c5s3")]
-    tau, warm, gens = 0.01, args.warmup, args.steps
+    tau, warm, gens, k = 0.01, args.warmup, args.steps, 32
 
-    def one(wl, precision, out):
-        s = make_system(cq, wl, 4 if precision == "mixed" else 8)
-        cap = 4 * wl.walkers + 64
-        # mixed precision recomputes the inverses in FP64 after every generation: a generation
-        # accepts nearly every move (about N FP32 updates per spin), and without it the FP32
-        # chains of the larger systems drift past the mixed tolerance within two generations
-        c = cq.Crowd(s, wl.walkers, precision=precision, delay_rank=wl.delay_rank, seed=wl.seed,
-                     max_walkers=cap, path="window", recompute_every=1 if precision == "mixed" else 0)
-        c.set_positions(start_positions(wl.seed, wl.walkers, wl.n_e, wl.L))
-        c.run_vmc(4, wl.sigma)  # equilibrate in VMC before the first DMC generation
-        e0 = float(np.mean(c.local_energy()))
-        c.run_dmc(warm, tau, e0, n_target=wl.dmc_target)
-        out["ready"].wait()
-        t0 = time.perf_counter()
-        h = c.run_dmc(gens, tau, float("nan"), n_target=wl.dmc_target)
-        t1 = time.perf_counter()
-        out[wl.name] = dict(seconds=t1 - t0, moves=float(h[:, 0].sum()) * wl.n_e if gens else 0.0,
-                            pop=[int(x) for x in h[:, 0]], e_t=float(h[-1, 3]) if gens else None, t0=t0, t1=t1)
-        c.close()
+    # one crowd of three systems, mixed; FP64 recompute after every generation
+    sys_m = [make_system(cq, wl, 4) for wl in systems]
+    counts = [wl.walkers for wl in systems]
+    grp = cq.Crowd(sys_m, counts, precision="mixed", delay_rank=k, recompute_every=1, seed=1005,
+                   max_walkers=sum(4 * w + 64 for w in counts), path="window")
+    grp.set_positions([start_positions(wl.seed, wl.walkers, wl.n_e, wl.L) for wl in systems])
+    grp.run_vmc(4, 0.5)  # equilibrate in VMC before the first DMC generation
+    el = grp.local_energy()
+    offs = np.cumsum([0] + counts)
+    e0 = [float(np.mean(el[offs[i]:offs[i + 1]])) for i in range(3)]
+    targets = [wl.dmc_target for wl in systems]
+    grp.run_dmc_systems(warm, tau, e_trial=e0, n_target=targets)
+    grp.synchronize()
+    m0 = grp.dmc_moves()[1]
+    grp.set_timing(("vgl", "update"))
+    t0 = time.perf_counter()
+    h = grp.run_dmc_systems(gens, tau, n_target=targets)
+    t1 = time.perf_counter()
+    moves = grp.dmc_moves()[1] - m0
+    kv, nv = grp.kernel_timing("vgl")
+    ku, nu = grp.kernel_timing("update")
+    grp.close()
+    for s in sys_m:
         s.close()
+    one = moves / (t1 - t0)
+    log("  c5 mixed, one crowd of three systems: %.3e moves/s over %.2f s" % (one, t1 - t0))
 
-    res = {}
-    # mixed: three systems concurrently
-    out = {"ready": threading.Barrier(len(systems))}
-    ths = [threading.Thread(target=one, args=(wl, "mixed", out)) for wl in systems]
-    for t in ths:
-        t.start()
-    for t in ths:
-        t.join()
-    mixed = {wl.name: out[wl.name] for wl in systems}
-    span = max(v["t1"] for v in mixed.values()) - min(v["t0"] for v in mixed.values())
-    moves = sum(v["moves"] for v in mixed.values())
-    log("  c5 mixed, concurrent: %.3e moves/s over %.2f s" % (moves / span, span))
-    # FP64: one system after another
-    f64 = {}
-    for wl in systems:
-        o = {"ready": threading.Barrier(1)}
-        one(wl, "fp64", o)
-        f64[wl.name] = o[wl.name]
-    f64_s = sum(v["seconds"] for v in f64.values())
-    f64_moves = sum(v["moves"] for v in f64.values())
-    log("  c5 fp64, per system: %.3e moves/s over %.2f s" % (f64_moves / f64_s, f64_s))
-    res = dict(metric="DMC electron moves/sec at 1 GPU, three systems at once (mixed) vs per-system FP64",
-               value=round(moves / span, 1), unit="moves/s", n_gpus=1, steps=gens, warmup=warm,
-               ms_per_step=round(1e3 * span / max(gens, 1), 3), higher_is_better=True, scaling="weak",
+    def separate(precision, concurrent):
+        out = {"ready": threading.Barrier(3 if concurrent else 1)}
+
+        def run(wl):
+            s = make_system(cq, wl, 4 if precision == "mixed" else 8)
+            c = cq.Crowd(s, wl.walkers, precision=precision, delay_rank=min(k, wl.n), seed=wl.seed,
+                         max_walkers=4 * wl.walkers + 64, path="window",
+                         recompute_every=1 if precision == "mixed" else 0)
+            c.set_positions(start_positions(wl.seed, wl.walkers, wl.n_e, wl.L))
+            c.run_vmc(4, wl.sigma)
+            c.run_dmc(warm, tau, float(np.mean(c.local_energy())), n_target=wl.dmc_target)
+            out["ready"].wait()
+            m1 = c.dmc_moves()[1]
+            a = time.perf_counter()
+            c.run_dmc(gens, tau, float("nan"), n_target=wl.dmc_target)
+            b = time.perf_counter()
+            out[wl.name] = dict(seconds=b - a, moves=c.dmc_moves()[1] - m1, t0=a, t1=b)
+            c.close()
+            s.close()
+        if concurrent:
+            ths = [threading.Thread(target=run, args=(wl,)) for wl in systems]
+            for t in ths:
+                t.start()
+            for t in ths:
+                t.join()
+        else:
+            for wl in systems:
+                run(wl)
+        return {wl.name: out[wl.name] for wl in systems}
+
+    f64 = separate("fp64", False)
+    f64_rate = sum(v["moves"] for v in f64.values()) / sum(v["seconds"] for v in f64.values())
+    log("  c5 fp64, per-system launches one system after another: %.3e moves/s" % f64_rate)
+    three = separate("mixed", True)
+    span = max(v["t1"] for v in three.values()) - min(v["t0"] for v in three.values())
+    three_rate = sum(v["moves"] for v in three.values()) / span
+    log("  c5 mixed, three crowds on three streams: %.3e moves/s" % three_rate)
+    res = dict(metric="DMC electron moves/sec at 1 GPU, three systems in one crowd (mixed) vs per-system FP64",
+               value=round(one, 1), unit="moves/s", n_gpus=1, steps=gens, warmup=warm,
+               ms_per_step=round(1e3 * (t1 - t0) / max(gens, 1), 3), higher_is_better=True, scaling="weak",
                vs_baseline=None, dtype="f32", data="synthetic (seeded Philox B-spline coefficients, uniform starts)",
                config=dict(workload="c5: DMC tau=0.01, S1 32+32 e L=10 G=48 target 2000, S2 256+256 e L=20 G=64 "
                                     "target 500, S3 1024+1024 e L=32 G=96 target 64; mixed with an FP64 recompute "
-                                    "after every generation; one crowd per system on its own stream"),
-               per_system={k: dict(moves_per_s=round(v["moves"] / v["seconds"], 1), pop=v["pop"], e_t=v["e_t"])
-                           for k, v in mixed.items()},
-               fp64_per_system_moves_per_s=round(f64_moves / f64_s, 1),
-               mixed_concurrent_over_fp64_sequential=round((moves / span) / (f64_moves / f64_s), 3))
+                                    "after every generation; one crowd of the three systems, delayed rank 32, "
+                                    "one move launch and one update launch per window step for all systems"),
+               populations=[[int(x) for x in h[:, i, 0]] for i in range(3)],
+               e_t=[float(h[-1, i, 3]) for i in range(3)],
+               kernels=dict(vgl=dict(ms_total=round(kv, 3), launches=nv), update=dict(ms_total=round(ku, 3), launches=nu)),
+               fp64_per_system_moves_per_s=round(f64_rate, 1),
+               mixed_one_crowd_over_fp64_per_system=round(one / f64_rate, 3),
+               mixed_three_crowds_three_streams_moves_per_s=round(three_rate, 1))
     print(json.dumps(res), flush=True)
 
 

@@ -142,9 +142,18 @@ typedef struct {
                              every kernel in order on one stream (each then has the GPU alone) */
 } cq_crowd_desc;
 
-/* Create a crowd of walkers_per_system[s] walkers of each system s.  This
-   version accepts n_systems == 1.  Allocates every device buffer up front
-   (CQ_ENOMEM if the device cannot hold them). */
+/* Create a crowd of walkers_per_system[s] walkers of each system s.  Allocates every device
+   buffer up front (CQ_ENOMEM if the device cannot hold them).
+   Several systems (n_systems > 1, the batched uneven workload): the walkers of every system
+   share the crowd's stream and are ordered system by system in every per-walker array (walker
+   uids continue from one system to the next); the descriptor applies to every system (delay
+   rank capped at each system's N); max_walkers > 0 is the capacity over all systems, shared
+   out in proportion to walkers_per_system.  cq_crowd_run_dmc_systems moves the walkers of all
+   systems with the same launches (per spin block and window step, one launch of the
+   walker-resident move kernel over every system's walkers, largest system first, and one update
+   launch over their strips), then runs each system's energy and branching; VMC sweeps run system
+   after system.  The parity-mode calls (forced decisions and branching, move records) take
+   crowds of one system. */
 cq_status cq_crowd_create(const cq_system* const* systems, const int* walkers_per_system, int n_systems,
                           const cq_crowd_desc* desc, cq_crowd** out);
 
@@ -190,7 +199,8 @@ cq_status cq_crowd_get_logdet(cq_crowd* c, double* logdet, int* sign);
 cq_status cq_crowd_get_acceptance(cq_crowd* c, int64_t* accepted, int64_t* proposed);
 /* kinetic local energy -1/2 sum_i lap_i Psi / Psi per walker [W] after the last sweep. */
 cq_status cq_crowd_get_local_energy(cq_crowd* c, double* e_l);
-/* positions [W][Ne][3]; n_walkers_per_system (may be NULL) receives the walker count. */
+/* positions [W][Ne][3] (several systems: each system's block [W_s][Ne_s][3] in turn);
+   n_walkers_per_system (may be NULL) receives the walker count of every system. */
 cq_status cq_crowd_get_positions(cq_crowd* c, double* R, int* n_walkers_per_system);
 /* the kept inverses as FP64 [W][2][N][N], element [w][s][j][i] = (A_s^-1)[j][i]. */
 cq_status cq_crowd_get_inverse(cq_crowd* c, double* ainv);
@@ -271,6 +281,16 @@ cq_status cq_crowd_run_dmc(cq_crowd* c, int n_generations, double tau, double e_
    Errors: CQ_EINVAL, CQ_ESTATE (positions not set). */
 cq_status cq_crowd_virtual_ratios(cq_crowd* c, const double* offsets, int n_q, double* ratio, double* rho,
                                   double* dlnj, int out_on_device);
+
+/* DMC generations of every system of the crowd (one or several), as cq_crowd_run_dmc does for
+   one: e_trial [n_systems] starting trial energies (NULL or NaN entries: continue with the
+   current ones), n_target [n_systems] target populations (NULL: the starting walker counts),
+   history (may be NULL) [n_generations][n_systems][4] of population, sum of weights, E_est and
+   E_T.  With several systems, each generation moves the walkers of all systems with the same
+   launches (see cq_crowd_create), then branches each system's population on its own.
+   Synchronous.  Errors as cq_crowd_run_dmc (CQ_ESTATE names the system). */
+cq_status cq_crowd_run_dmc_systems(cq_crowd* c, int n_generations, double tau, const double* e_trial,
+                                   const int* n_target, double* history);
 
 /* Current number of walkers (changes under DMC branching). */
 cq_status cq_crowd_get_population(cq_crowd* c, int* n_walkers);

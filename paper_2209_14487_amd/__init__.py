@@ -56,6 +56,7 @@ _SIGS = {
     "cq_crowd_set_positions": [_P, _P, _I, ctypes.c_uint32],
     "cq_crowd_run_vmc": [_P, _I, ctypes.c_double],
     "cq_crowd_run_dmc": [_P, _I, ctypes.c_double, ctypes.c_double, _I, _P],
+    "cq_crowd_run_dmc_systems": [_P, _I, ctypes.c_double, _P, _P, _P],
     "cq_crowd_get_population": [_P, _P],
     "cq_crowd_virtual_ratios": [_P, _P, _I, _P, _P, _P, _I],
     "cq_crowd_autotune": [_P, _I, _P],
@@ -263,27 +264,59 @@ class System:
 
 
 class Crowd:
-    """A crowd of walkers of one system moved in lock-step (cq_crowd)."""
+    """A crowd of walkers moved in lock-step (cq_crowd): of one system, or of several systems
+    (pass lists of systems and walker counts) whose DMC generations share their launches."""
 
-    def __init__(self, system: System, n_walkers: int, precision: str = "mixed", delay_rank: int = 1,
+    def __init__(self, system, n_walkers, precision: str = "mixed", delay_rank: int = 1,
                  recompute_every: int = 0, seed: int = 0, first_uid: int = 0, stream=None,
                  use_graph: bool = True, path: str = "auto", max_walkers: int = 0, streams: int = 2):
-        self.system = system
-        self.W = n_walkers
-        self._w0 = n_walkers
-        self.Wcap = max(n_walkers, max_walkers)  # walker stride of the parity-mode buffers
-        self.n = system.n
-        self.ne = 2 * system.n
+        systems = list(system) if isinstance(system, (list, tuple)) else [system]
+        counts = list(n_walkers) if isinstance(n_walkers, (list, tuple)) else [n_walkers]
+        assert len(systems) == len(counts)
+        self.group = len(systems) > 1
+        self.systems = systems
+        self.system = systems[0]
+        self.Ws = counts
+        self.W = sum(counts)
+        self._w0 = self.W
+        self.Wcap = max(self.W, max_walkers)  # walker stride of the parity-mode buffers
+        self.n = systems[0].n
+        self.ne = 2 * systems[0].n
         desc = CrowdDesc(CQ_MIXED if precision == "mixed" else CQ_FP64, delay_rank, recompute_every, seed,
                          first_uid, _stream_handle(stream), int(use_graph), PATHS[path], max_walkers, streams)
-        systems = (ctypes.c_void_p * 1)(system._h.value)
-        counts = (ctypes.c_int * 1)(n_walkers)
+        hs = (ctypes.c_void_p * len(systems))(*[x._h.value for x in systems])
+        cs = (ctypes.c_int * len(counts))(*counts)
         h = ctypes.c_void_p()
-        _check(lib().cq_crowd_create(systems, counts, 1, ctypes.byref(desc), ctypes.byref(h)))
+        _check(lib().cq_crowd_create(hs, cs, len(systems), ctypes.byref(desc), ctypes.byref(h)))
         self._h = h
         self._rec = 0
 
+    def _refresh_counts(self):
+        counts = (ctypes.c_int * len(self.systems))()
+        _check(lib().cq_crowd_get_positions(self._h, None, counts))
+        self.Ws = list(counts)
+        self.W = sum(self.Ws)
+
+    def run_dmc_systems(self, n_generations: int, tau: float, e_trial=None, n_target=None):
+        """DMC generations of every system (one launch per step serves the walkers of all of
+        them); returns the history [n_generations][n_systems][4] (population, sum of weights,
+        E_est, E_T).  e_trial, n_target: per system (None: continue / the starting counts)."""
+        S = len(self.systems)
+        h = np.zeros((n_generations, S, 4))
+        et = None if e_trial is None else np.ascontiguousarray(e_trial, dtype=np.float64)
+        nt = None if n_target is None else np.ascontiguousarray(n_target, dtype=np.int32)
+        try:
+            _check(lib().cq_crowd_run_dmc_systems(self._h, n_generations, tau, None if et is None else et.ctypes.data,
+                                                  None if nt is None else nt.ctypes.data, h.ctypes.data))
+        finally:
+            self._refresh_counts()
+        return h
+
     def set_positions(self, R, first_step: int = 0):
+        if self.group:  # one array [W_s][Ne_s][3] per system
+            flat = np.concatenate([np.ascontiguousarray(r, dtype=np.float64).ravel() for r in R])
+            _check(lib().cq_crowd_set_positions(self._h, flat.ctypes.data, 0, first_step))
+            return
         if isinstance(R, np.ndarray):
             R = np.ascontiguousarray(R, dtype=np.float64)
             assert R.shape == (self.W, self.ne, 3)
@@ -371,6 +404,17 @@ class Crowd:
         return e
 
     def positions(self):
+        """[W][Ne][3]; with several systems a list of [W_s][Ne_s][3]."""
+        if self.group:
+            self._refresh_counts()
+            sizes = [w * 2 * x.n * 3 for w, x in zip(self.Ws, self.systems)]
+            flat = np.zeros(sum(sizes))
+            _check(lib().cq_crowd_get_positions(self._h, flat.ctypes.data, None))
+            out, o = [], 0
+            for w, x, k in zip(self.Ws, self.systems, sizes):
+                out.append(flat[o:o + k].reshape(w, 2 * x.n, 3))
+                o += k
+            return out
         R = np.zeros((self.W, self.ne, 3))
         _check(lib().cq_crowd_get_positions(self._h, R.ctypes.data, None))
         return R

@@ -142,6 +142,17 @@ struct cq_crowd {
     uint8_t* forced = nullptr;
     int mult_cap = 0;
     int* forced_mult = nullptr;  // [generations][Wcap] branching multiplicities to follow
+    // several systems: one crowd per system, all on this crowd's stream, and the device views
+    // and work lists of the launches that serve the walkers of every system at once
+    std::vector<cq_crowd*> subs;
+    void* gviews = nullptr;                 // CrowdView<T> [systems]
+    int2* gwalk = nullptr;                  // (system, walker) items of each window step
+    int4* gstrip = nullptr;                 // (system, walker, strip) items of each window step
+    size_t gwalk_cap = 0, gstrip_cap = 0;
+    std::vector<int2> hwalk;                // host copies (kept until the next generation's copy)
+    std::vector<int4> hstrip;
+    std::vector<unsigned char> hviews;
+    int n_cu = 0;
     // host state
     cq::Params hp{};
     bool ready = false;
@@ -545,7 +556,7 @@ cq_status ensure_dmc(cq_crowd* c, int n_gen)
 }
 
 template <typename T>
-void dmc_generation(cq_crowd* c, int gen, int n_target, double tau, bool recompute)
+void dmc_moves(cq_crowd* c)
 {
     cq::CrowdView<T> v = view<T>(c);
     v.ct = nullptr;  // the per-move kernel leaves the window's columns in row layout
@@ -560,6 +571,116 @@ void dmc_generation(cq_crowd* c, int gen, int n_target, double tau, bool recompu
             cq::launch_flush<T>(v, spin, c->stream, false);
             timed_end(c, CQ_KERNEL_UPDATE);
         }
+}
+
+// The moves of one generation for the walkers of every system of a group: per spin block and
+// window step j, ONE launch of the walker-resident move kernel over the walkers of all systems
+// that have a window j (largest system first) and ONE update launch over their strips.
+template <typename T>
+cq_status group_moves(cq_crowd* g)
+{
+    const int S = (int)g->subs.size();
+    std::vector<cq::CrowdView<T>> hv(S);
+    int max_n = 0, max_win = 0;
+    bool mfma = sizeof(T) == 4;
+    for (int s = 0; s < S; ++s) {
+        cq_crowd* c = g->subs[s];
+        hv[s] = view<T>(c);
+        hv[s].ct = nullptr;
+        hv[s].ub = nullptr;
+        max_n = std::max(max_n, c->n);
+        max_win = std::max(max_win, (c->n + c->K - 1) / c->K);
+        mfma = mfma && cq::flush_mfma_fits(c->n);
+    }
+    // systems in order of decreasing N: the longest windows are handed out first
+    std::vector<int> order(S);
+    for (int s = 0; s < S; ++s) order[s] = s;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return g->subs[a]->n > g->subs[b]->n; });
+    const int rows = mfma ? 32 : 16;  // rows per update workgroup
+    g->hwalk.clear();
+    g->hstrip.clear();
+    std::vector<size_t> woff(max_win + 1), soff(max_win + 1);
+    for (int j = 0; j < max_win; ++j) {
+        woff[j] = g->hwalk.size();
+        soff[j] = g->hstrip.size();
+        for (int s : order) {
+            cq_crowd* c = g->subs[s];
+            if (j * c->K >= c->n) continue;
+            const int strips = (c->n + rows - 1) / rows;
+            for (int w = 0; w < c->W; ++w) g->hwalk.push_back(make_int2(s, w));
+            for (int w = 0; w < c->W; ++w)
+                for (int t = 0; t < strips; ++t) g->hstrip.push_back(make_int4(s, w, t, 0));
+        }
+    }
+    woff[max_win] = g->hwalk.size();
+    soff[max_win] = g->hstrip.size();
+    const size_t vb = sizeof(cq::CrowdView<T>) * S;
+    if (!g->gviews) {
+        if (hipMalloc(&g->gviews, sizeof(cq::CrowdView<double>) * S + sizeof(cq::CrowdView<float>) * S) !=
+            hipSuccess) {
+            (void)hipGetLastError();
+            return fail(CQ_ENOMEM, "group views");
+        }
+    }
+    if (g->hwalk.size() > g->gwalk_cap) {
+        if (g->gwalk) HIP_TRY(hipFree(g->gwalk));
+        g->gwalk = nullptr;
+        g->gwalk_cap = 0;
+        const size_t cap = g->hwalk.size() * 2;
+        if (hipMalloc((void**)&g->gwalk, sizeof(int2) * cap) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(CQ_ENOMEM, "group walker items");
+        }
+        g->gwalk_cap = cap;
+    }
+    if (g->hstrip.size() > g->gstrip_cap) {
+        if (g->gstrip) HIP_TRY(hipFree(g->gstrip));
+        g->gstrip = nullptr;
+        g->gstrip_cap = 0;
+        const size_t cap = g->hstrip.size() * 2;
+        if (hipMalloc((void**)&g->gstrip, sizeof(int4) * cap) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(CQ_ENOMEM, "group strip items");
+        }
+        g->gstrip_cap = cap;
+    }
+    g->hviews.assign((const unsigned char*)hv.data(), (const unsigned char*)hv.data() + vb);
+    HIP_TRY(hipMemcpyAsync(g->gviews, g->hviews.data(), vb, hipMemcpyHostToDevice, g->stream));
+    HIP_TRY(hipMemcpyAsync(g->gwalk, g->hwalk.data(), sizeof(int2) * g->hwalk.size(), hipMemcpyHostToDevice,
+                           g->stream));
+    HIP_TRY(hipMemcpyAsync(g->gstrip, g->hstrip.data(), sizeof(int4) * g->hstrip.size(), hipMemcpyHostToDevice,
+                           g->stream));
+    const cq::CrowdView<T>* dv = (const cq::CrowdView<T>*)g->gviews;
+    const int cus = g->n_cu > 0 ? g->n_cu : 256;
+    for (int spin = 0; spin < 2; ++spin)
+        for (int j = 0; j < max_win; ++j) {
+            const int nw = (int)(woff[j + 1] - woff[j]), ns = (int)(soff[j + 1] - soff[j]);
+            timed_begin(g, CQ_KERNEL_VGL);
+            cq::launch_window_dmc_multi<T>(dv, g->gwalk + woff[j], nw, max_n, spin, j, std::min(nw, 4 * cus),
+                                           g->stream);
+            timed_end(g, CQ_KERNEL_VGL);
+            timed_begin(g, CQ_KERNEL_UPDATE);
+            if constexpr (sizeof(T) == 4) {
+                if (mfma)
+                    cq::launch_flush_mfma_multi((const cq::CrowdView<float>*)dv, g->gwalk + woff[j], nw,
+                                                g->gstrip + soff[j], ns, spin, 2 * cus, g->stream);
+                else
+                    cq::launch_flush_vec_multi<T>(dv, g->gstrip + soff[j], ns, max_n, spin, 4 * cus, g->stream);
+            } else {
+                cq::launch_flush_vec_multi<T>(dv, g->gstrip + soff[j], ns, max_n, spin, 4 * cus, g->stream);
+            }
+            timed_end(g, CQ_KERNEL_UPDATE);
+        }
+    return CQ_OK;
+}
+
+// After the moves of a generation: the periodic FP64 recompute, the local energy and the
+// branching of one system's population.
+template <typename T>
+void dmc_post(cq_crowd* c, int gen, int n_target, double tau, bool recompute)
+{
+    cq::CrowdView<T> v = view<T>(c);
+    const int n = c->n;
     // the periodic FP64 recompute, before the energy and the branching read the inverses
     if (recompute) enqueue_inverse<T>(c);
     timed_begin(c, CQ_KERNEL_ENERGY);
@@ -720,6 +841,10 @@ void cq_crowd_destroy(cq_crowd* c)
 {
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (cq_crowd* sub : c->subs) cq_crowd_destroy(sub);
+    if (c->gviews) (void)hipFree(c->gviews);
+    if (c->gwalk) (void)hipFree(c->gwalk);
+    if (c->gstrip) (void)hipFree(c->gstrip);
     drop_graph(c);
     for (int k = 0; k < CQ_KERNEL_COUNT; ++k)
         for (auto& p : c->ev[k]) {
@@ -750,7 +875,61 @@ cq_status cq_crowd_create(const cq_system* const* systems, const int* walkers_pe
     if (!out) return fail(CQ_EINVAL, "out is NULL");
     *out = nullptr;
     if (!systems || !walkers_per_system || !desc) return fail(CQ_EINVAL, "NULL argument");
-    if (n_systems != 1) return fail(CQ_EINVAL, "this version runs crowds of one system");
+    if (n_systems < 1) return fail(CQ_EINVAL, "n_systems must be >= 1");
+    if (n_systems > 1) {
+        // one crowd per system on a shared stream; walker uids continue from system to system
+        int total = 0;
+        if (desc->precision != CQ_FP64 && desc->precision != CQ_MIXED) return fail(CQ_EINVAL, "unknown precision");
+        for (int k = 0; k < n_systems; ++k) {
+            if (!systems[k]) return fail(CQ_EINVAL, "system is NULL");
+            if (walkers_per_system[k] < 1) return fail(CQ_EINVAL, "need at least one walker per system");
+            if (!systems[k]->table[desc->precision == CQ_FP64 ? 1 : 0])
+                return fail(CQ_EINVAL, "system " + std::to_string(k) +
+                                           (desc->precision == CQ_FP64 ? " has no FP64 table" : " has no FP32 table"));
+            total += walkers_per_system[k];
+        }
+        if (desc->max_walkers < 0) return fail(CQ_EINVAL, "max_walkers must be >= 0");
+        cq_crowd* g = new (std::nothrow) cq_crowd();
+        if (!g) return fail(CQ_ENOMEM, "host allocation failed");
+        g->W = total;
+        g->prec = desc->precision;
+        if (desc->hip_stream) {
+            g->stream = (hipStream_t)desc->hip_stream;
+        } else {
+            if (hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking) != hipSuccess) {
+                delete g;
+                return fail(CQ_EDEVICE, "hipStreamCreate failed");
+            }
+            g->own_stream = true;
+        }
+        int dev = 0;
+        if (hipGetDevice(&dev) == hipSuccess)
+            (void)hipDeviceGetAttribute(&g->n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+        uint32_t uid = desc->first_uid;
+        for (int k = 0; k < n_systems; ++k) {
+            cq_crowd_desc d = *desc;
+            d.hip_stream = g->stream;
+            d.first_uid = uid;
+            if (d.delay_rank > systems[k]->n_up) d.delay_rank = systems[k]->n_up;
+            // the walker capacity is shared out in proportion to the starting walkers
+            d.max_walkers = desc->max_walkers > 0
+                                ? (int)(((int64_t)desc->max_walkers * walkers_per_system[k] + total - 1) / total)
+                                : 0;
+            cq_crowd* sub = nullptr;
+            cq_status st = cq_crowd_create(&systems[k], &walkers_per_system[k], 1, &d, &sub);
+            if (st != CQ_OK) {
+                cq_crowd_destroy(g);
+                return st;
+            }
+            g->subs.push_back(sub);
+            uid += (uint32_t)std::max(walkers_per_system[k], d.max_walkers);
+        }
+        g->n = g->subs[0]->n;
+        g->ne = g->subs[0]->ne;
+        g->K = g->subs[0]->K;
+        *out = g;
+        return CQ_OK;
+    }
     const cq_system* s = systems[0];
     if (!s) return fail(CQ_EINVAL, "system is NULL");
     const int W = walkers_per_system[0];
@@ -907,6 +1086,16 @@ cq_status cq_crowd_create(const cq_system* const* systems, const int* walkers_pe
 cq_status cq_crowd_set_positions(cq_crowd* c, const double* R, int on_device, uint32_t first_step)
 {
     if (!c || !R) return fail(CQ_EINVAL, "NULL argument");
+    if (!c->subs.empty()) {
+        size_t off = 0;
+        for (cq_crowd* sub : c->subs) {
+            cq_status st = cq_crowd_set_positions(sub, R + off, on_device, first_step);
+            if (st != CQ_OK) return st;
+            off += (size_t)sub->W * sub->ne * 3;
+        }
+        c->ready = true;
+        return CQ_OK;
+    }
     const size_t bytes = sizeof(double) * c->W * c->ne * 3;
     HIP_TRY(hipStreamSynchronize(c->stream));
     HIP_TRY(hipMemcpy(c->R, R, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice));
@@ -987,6 +1176,14 @@ static cq_status autotune_k(cq_crowd* c, int sweeps, int* chosen)
 cq_status cq_crowd_autotune(cq_crowd* c, int sweeps_per_candidate, int* chosen_k)
 {
     if (!c) return fail(CQ_EINVAL, "crowd is NULL");
+    if (!c->subs.empty()) {
+        for (cq_crowd* sub : c->subs) {
+            cq_status st = cq_crowd_autotune(sub, sweeps_per_candidate, nullptr);
+            if (st != CQ_OK) return st;
+        }
+        if (chosen_k) *chosen_k = c->subs[0]->K;
+        return CQ_OK;
+    }
     if (sweeps_per_candidate < 1) return fail(CQ_EINVAL, "sweeps_per_candidate must be >= 1");
     if (!c->ready) return fail(CQ_ESTATE, "set positions before autotuning");
     return autotune_k(c, sweeps_per_candidate, chosen_k);
@@ -995,6 +1192,13 @@ cq_status cq_crowd_autotune(cq_crowd* c, int sweeps_per_candidate, int* chosen_k
 cq_status cq_crowd_run_vmc(cq_crowd* c, int n_sweeps, double sigma)
 {
     if (!c) return fail(CQ_EINVAL, "crowd is NULL");
+    if (!c->subs.empty()) {
+        for (cq_crowd* sub : c->subs) {
+            cq_status st = cq_crowd_run_vmc(sub, n_sweeps, sigma);
+            if (st != CQ_OK) return st;
+        }
+        return CQ_OK;
+    }
     if (n_sweeps < 0 || !(sigma > 0.0) || !std::isfinite(sigma)) return fail(CQ_EINVAL, "bad n_sweeps or sigma");
     if (!c->ready) return fail(CQ_ESTATE, "set positions before running");
     if (sigma != c->hp.sigma) {
@@ -1036,64 +1240,135 @@ cq_status cq_crowd_run_vmc(cq_crowd* c, int n_sweeps, double sigma)
     return enqueue_status(c, "run_vmc");
 }
 
+}  // extern "C"
+
+namespace {
+
+// DMC generations of one crowd, or of every system of a group (the walkers of all systems
+// moved by the same launches, then each system's energy and branching).  e_trial and
+// n_target per system (e_trial NaN: continue with the current E_T); history [gen][S][4].
+cq_status run_dmc_set(cq_crowd* owner, const std::vector<cq_crowd*>& set, int n_generations, double tau,
+                      const double* e_trial, const int* n_target, double* history)
+{
+    const int S = (int)set.size();
+    for (int s = 0; s < S; ++s) {
+        cq_crowd* c = set[s];
+        if (!c->ready) return fail(CQ_ESTATE, "set positions before running");
+        if (n_target[s] < 1) return fail(CQ_EINVAL, "n_target must be >= 1");
+    }
+    if (n_generations == 0) return CQ_OK;
+    for (int s = 0; s < S; ++s) {
+        cq_crowd* c = set[s];
+        cq_status st = ensure_dmc(c, n_generations);
+        if (st != CQ_OK) return st;
+        c->hp.tau = tau;
+        st = push_params(c);
+        if (st != CQ_OK) return st;
+        cq::DmcState ds{};
+        HIP_TRY(hipMemcpy(&ds, c->dmc_state, sizeof(ds), hipMemcpyDeviceToHost));
+        if (e_trial && std::isfinite(e_trial[s])) ds.e_t = e_trial[s];
+        ds.status = 0;
+        HIP_TRY(hipMemcpy(c->dmc_state, &ds, sizeof(ds), hipMemcpyHostToDevice));
+        drop_graph(c);  // walker buffers and the population change from here on
+        // the generation sums count the moves each walker made since the last branching: clear
+        // the counters the walkers bring from VMC sweeps (children of a branching start at zero)
+        HIP_TRY(hipMemsetAsync(c->nacc, 0, sizeof(long long) * c->W, c->stream));
+        HIP_TRY(hipMemsetAsync(c->nprop, 0, sizeof(long long) * c->W, c->stream));
+    }
+    const bool fp64 = owner->prec == CQ_FP64;
+    for (int gen = 0; gen < n_generations; ++gen) {
+        if (S == 1) {
+            if (fp64)
+                dmc_moves<double>(set[0]);
+            else
+                dmc_moves<float>(set[0]);
+        } else {
+            cq_status st = fp64 ? group_moves<double>(owner) : group_moves<float>(owner);
+            if (st != CQ_OK) return st;
+        }
+        for (int s = 0; s < S; ++s) {
+            cq_crowd* c = set[s];
+            const bool rc = c->recompute_every > 0 && ++c->since_recompute >= c->recompute_every;
+            if (rc) {
+                c->since_recompute = 0;
+                c->n_recomputes++;
+            }
+            if (fp64)
+                dmc_post<double>(c, gen, n_target[s], tau, rc);
+            else
+                dmc_post<float>(c, gen, n_target[s], tau, rc);
+        }
+        cq_status es = enqueue_status(owner, "run_dmc");
+        if (es != CQ_OK) return es;
+        HIP_TRY(hipStreamSynchronize(owner->stream));
+        for (int s = 0; s < S; ++s) {
+            cq_crowd* c = set[s];
+            cq::DmcState ds{};
+            HIP_TRY(hipStreamSynchronize(c->stream));
+            HIP_TRY(hipMemcpy(&ds, c->dmc_state, sizeof(ds), hipMemcpyDeviceToHost));
+            c->hp.step += 1;
+            c->hp.rec_sweep += 1;
+            if (ds.status) {
+                if (history)
+                    for (int g2 = 0; g2 < gen; ++g2)
+                        HIP_TRY(hipMemcpy(history + ((size_t)g2 * S + s) * 4, c->dmc_hist + (size_t)g2 * 4,
+                                          sizeof(double) * 4, hipMemcpyDeviceToHost));
+                return fail(CQ_ESTATE, "DMC population " + std::to_string(ds.new_pop) +
+                                           (ds.new_pop == 0 ? " died out" : " exceeds max_walkers") +
+                                           (S > 1 ? " in system " + std::to_string(s) : std::string()) +
+                                           " at generation " + std::to_string(gen));
+            }
+            cq_status cs = check_singular(c, "run_dmc");
+            if (cs != CQ_OK) return cs;
+            swap_walker_sets(c);
+            c->W = ds.new_pop;
+        }
+        if (S > 1) {
+            int tot = 0;
+            for (cq_crowd* c : set) tot += c->W;
+            owner->W = tot;
+        }
+    }
+    if (history)
+        for (int s = 0; s < S; ++s)
+            for (int g2 = 0; g2 < n_generations; ++g2)
+                HIP_TRY(hipMemcpy(history + ((size_t)g2 * S + s) * 4, set[s]->dmc_hist + (size_t)g2 * 4,
+                                  sizeof(double) * 4, hipMemcpyDeviceToHost));
+    return CQ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 cq_status cq_crowd_run_dmc(cq_crowd* c, int n_generations, double tau, double e_trial, int n_target,
                            double* history)
 {
     if (!c) return fail(CQ_EINVAL, "crowd is NULL");
+    if (!c->subs.empty()) return fail(CQ_EINVAL, "a crowd of several systems runs DMC with cq_crowd_run_dmc_systems");
     if (n_generations < 0 || !(tau > 0.0) || !std::isfinite(tau) || n_target < 1)
         return fail(CQ_EINVAL, "bad n_generations, tau or n_target");
-    if (!c->ready) return fail(CQ_ESTATE, "set positions before running");
-    if (n_generations == 0) return CQ_OK;
-    cq_status st = ensure_dmc(c, n_generations);
-    if (st != CQ_OK) return st;
-    c->hp.tau = tau;
-    st = push_params(c);
-    if (st != CQ_OK) return st;
-    cq::DmcState ds{};
-    HIP_TRY(hipMemcpy(&ds, c->dmc_state, sizeof(ds), hipMemcpyDeviceToHost));
-    if (std::isfinite(e_trial)) ds.e_t = e_trial;
-    ds.status = 0;
-    HIP_TRY(hipMemcpy(c->dmc_state, &ds, sizeof(ds), hipMemcpyHostToDevice));
-    drop_graph(c);  // walker buffers and the population change from here on
-    // the generation sums count the moves each walker made since the last branching: clear the
-    // counters the walkers bring from VMC sweeps (children of a branching start at zero)
-    HIP_TRY(hipMemsetAsync(c->nacc, 0, sizeof(long long) * c->W, c->stream));
-    HIP_TRY(hipMemsetAsync(c->nprop, 0, sizeof(long long) * c->W, c->stream));
-    for (int gen = 0; gen < n_generations; ++gen) {
-        const bool rc = c->recompute_every > 0 && ++c->since_recompute >= c->recompute_every;
-        if (rc) {
-            c->since_recompute = 0;
-            c->n_recomputes++;
-        }
-        if (c->prec == CQ_FP64)
-            dmc_generation<double>(c, gen, n_target, tau, rc);
-        else
-            dmc_generation<float>(c, gen, n_target, tau, rc);
-        cq_status es = enqueue_status(c, "run_dmc");
-        if (es != CQ_OK) return es;
-        HIP_TRY(hipStreamSynchronize(c->stream));
-        HIP_TRY(hipMemcpy(&ds, c->dmc_state, sizeof(ds), hipMemcpyDeviceToHost));
-        c->hp.step += 1;
-        c->hp.rec_sweep += 1;
-        if (ds.status) {
-            if (history) HIP_TRY(hipMemcpy(history, c->dmc_hist, sizeof(double) * 4 * gen, hipMemcpyDeviceToHost));
-            return fail(CQ_ESTATE, "DMC population " + std::to_string(ds.new_pop) +
-                                       (ds.new_pop == 0 ? " died out" : " exceeds max_walkers") + " at generation " +
-                                       std::to_string(gen));
-        }
-        cq_status cs = check_singular(c, "run_dmc");
-        if (cs != CQ_OK) return cs;
-        swap_walker_sets(c);
-        c->W = ds.new_pop;
-    }
-    if (history)
-        HIP_TRY(hipMemcpy(history, c->dmc_hist, sizeof(double) * 4 * (size_t)n_generations, hipMemcpyDeviceToHost));
-    return CQ_OK;
+    return run_dmc_set(c, {c}, n_generations, tau, &e_trial, &n_target, history);
+}
+
+cq_status cq_crowd_run_dmc_systems(cq_crowd* c, int n_generations, double tau, const double* e_trial,
+                                   const int* n_target, double* history)
+{
+    if (!c) return fail(CQ_EINVAL, "crowd is NULL");
+    if (n_generations < 0 || !(tau > 0.0) || !std::isfinite(tau)) return fail(CQ_EINVAL, "bad n_generations or tau");
+    std::vector<cq_crowd*> set = c->subs.empty() ? std::vector<cq_crowd*>{c} : c->subs;
+    std::vector<int> tgt(set.size());
+    for (size_t s = 0; s < set.size(); ++s) tgt[s] = n_target ? n_target[s] : set[s]->W;
+    return run_dmc_set(c, set, n_generations, tau, e_trial, tgt.data(), history);
 }
 
 cq_status cq_crowd_get_delay_rank(cq_crowd* c, int* k)
 {
     if (!c || !k) return fail(CQ_EINVAL, "NULL argument");
+    if (!c->subs.empty()) {
+        *k = c->subs[0]->K;
+        return CQ_OK;
+    }
     *k = c->K;
     return CQ_OK;
 }
@@ -1101,6 +1376,12 @@ cq_status cq_crowd_get_delay_rank(cq_crowd* c, int* k)
 cq_status cq_crowd_get_population(cq_crowd* c, int* n_walkers)
 {
     if (!c || !n_walkers) return fail(CQ_EINVAL, "NULL argument");
+    if (!c->subs.empty()) {
+        int tot = 0;
+        for (cq_crowd* sub : c->subs) tot += sub->W;
+        *n_walkers = tot;
+        return CQ_OK;
+    }
     *n_walkers = c->W;
     return CQ_OK;
 }
@@ -1108,6 +1389,17 @@ cq_status cq_crowd_get_population(cq_crowd* c, int* n_walkers)
 cq_status cq_crowd_recompute(cq_crowd* c, double* max_drift)
 {
     if (!c) return fail(CQ_EINVAL, "crowd is NULL");
+    if (!c->subs.empty()) {
+        double m = 0.0;
+        for (cq_crowd* sub : c->subs) {
+            double d = 0.0;
+            cq_status st = cq_crowd_recompute(sub, max_drift ? &d : nullptr);
+            if (st != CQ_OK) return st;
+            m = std::max(m, d);
+        }
+        if (max_drift) *max_drift = m;
+        return CQ_OK;
+    }
     if (!c->ready) return fail(CQ_ESTATE, "set positions before recomputing");
     inverse(c);
     HIP_TRY(hipGetLastError());
@@ -1147,6 +1439,17 @@ cq_status cq_crowd_virtual_ratios(cq_crowd* c, const double* offsets, int n_q, d
                                   double* dlnj, int out_on_device)
 {
     if (!c || !offsets) return fail(CQ_EINVAL, "NULL argument");
+    if (!c->subs.empty()) {
+        size_t off = 0;
+        for (cq_crowd* sub : c->subs) {
+            cq_status st = cq_crowd_virtual_ratios(sub, offsets, n_q, ratio ? ratio + off : nullptr,
+                                                   rho ? rho + off : nullptr, dlnj ? dlnj + off : nullptr,
+                                                   out_on_device);
+            if (st != CQ_OK) return st;
+            off += (size_t)sub->W * sub->ne * n_q;
+        }
+        return CQ_OK;
+    }
     if (n_q < 1 || n_q > 64) return fail(CQ_EINVAL, "n_q must be 1..64");
     if (!c->ready) return fail(CQ_ESTATE, "positions not set");
     HIP_TRY(hipStreamSynchronize(c->stream));
@@ -1199,6 +1502,15 @@ cq_status cq_crowd_virtual_ratios(cq_crowd* c, const double* offsets, int n_q, d
 cq_status cq_crowd_get_logdet(cq_crowd* c, double* logdet, int* sign)
 {
     if (!c) return fail(CQ_EINVAL, "crowd is NULL");
+    if (!c->subs.empty()) {
+        size_t off = 0;
+        for (cq_crowd* sub : c->subs) {
+            cq_status st = cq_crowd_get_logdet(sub, logdet ? logdet + 2 * off : nullptr, sign ? sign + 2 * off : nullptr);
+            if (st != CQ_OK) return st;
+            off += sub->W;
+        }
+        return CQ_OK;
+    }
     cq_status st = copy_out(c, logdet, c->logdet, sizeof(double) * 2 * c->W);
     if (st != CQ_OK) return st;
     return got(c, copy_out(c, sign, c->sign, sizeof(int) * 2 * c->W), "get_logdet");
@@ -1207,6 +1519,16 @@ cq_status cq_crowd_get_logdet(cq_crowd* c, double* logdet, int* sign)
 cq_status cq_crowd_get_acceptance(cq_crowd* c, int64_t* accepted, int64_t* proposed)
 {
     if (!c) return fail(CQ_EINVAL, "crowd is NULL");
+    if (!c->subs.empty()) {
+        size_t off = 0;
+        for (cq_crowd* sub : c->subs) {
+            cq_status st = cq_crowd_get_acceptance(sub, accepted ? accepted + off : nullptr,
+                                                   proposed ? proposed + off : nullptr);
+            if (st != CQ_OK) return st;
+            off += sub->W;
+        }
+        return CQ_OK;
+    }
     cq_status st = copy_out(c, accepted, c->nacc, sizeof(int64_t) * c->W);
     if (st != CQ_OK) return st;
     return got(c, copy_out(c, proposed, c->nprop, sizeof(int64_t) * c->W), "get_acceptance");
@@ -1215,12 +1537,32 @@ cq_status cq_crowd_get_acceptance(cq_crowd* c, int64_t* accepted, int64_t* propo
 cq_status cq_crowd_get_local_energy(cq_crowd* c, double* e_l)
 {
     if (!c) return fail(CQ_EINVAL, "crowd is NULL");
+    if (!c->subs.empty()) {
+        size_t off = 0;
+        for (cq_crowd* sub : c->subs) {
+            cq_status st = cq_crowd_get_local_energy(sub, e_l ? e_l + off : nullptr);
+            if (st != CQ_OK) return st;
+            off += sub->W;
+        }
+        return CQ_OK;
+    }
     return got(c, copy_out(c, e_l, c->eloc, sizeof(double) * c->W), "get_local_energy");
 }
 
 cq_status cq_crowd_get_positions(cq_crowd* c, double* R, int* n_walkers_per_system)
 {
     if (!c) return fail(CQ_EINVAL, "crowd is NULL");
+    if (!c->subs.empty()) {
+        size_t off = 0;
+        for (size_t k = 0; k < c->subs.size(); ++k) {
+            cq_crowd* sub = c->subs[k];
+            cq_status st = cq_crowd_get_positions(sub, R ? R + off : nullptr, nullptr);
+            if (st != CQ_OK) return st;
+            if (n_walkers_per_system) n_walkers_per_system[k] = sub->W;
+            off += (size_t)sub->W * sub->ne * 3;
+        }
+        return CQ_OK;
+    }
     if (n_walkers_per_system) n_walkers_per_system[0] = c->W;
     return got(c, copy_out(c, R, c->R, sizeof(double) * c->W * c->ne * 3), "get_positions");
 }
@@ -1228,6 +1570,23 @@ cq_status cq_crowd_get_positions(cq_crowd* c, double* R, int* n_walkers_per_syst
 cq_status cq_crowd_get_drift(cq_crowd* c, double* last, double* max_drift, int* n_recomputes)
 {
     if (!c) return fail(CQ_EINVAL, "crowd is NULL");
+    if (!c->subs.empty()) {
+        size_t off = 0;
+        double m = 0.0;
+        int nr = 0;
+        for (cq_crowd* sub : c->subs) {
+            double dm = 0.0;
+            int k = 0;
+            cq_status st = cq_crowd_get_drift(sub, last ? last + 2 * off : nullptr, &dm, &k);
+            if (st != CQ_OK) return st;
+            m = std::max(m, dm);
+            nr = std::max(nr, k);
+            off += sub->W;
+        }
+        if (max_drift) *max_drift = m;
+        if (n_recomputes) *n_recomputes = nr;
+        return CQ_OK;
+    }
     cq_status st = copy_out(c, last, c->drift, sizeof(double) * 2 * c->W);
     if (st != CQ_OK) return st;
     unsigned long long bits = 0;
@@ -1243,12 +1602,30 @@ cq_status cq_crowd_get_drift(cq_crowd* c, double* last, double* max_drift, int* 
 cq_status cq_crowd_get_uids(cq_crowd* c, uint32_t* uids)
 {
     if (!c) return fail(CQ_EINVAL, "crowd is NULL");
+    if (!c->subs.empty()) {
+        size_t off = 0;
+        for (cq_crowd* sub : c->subs) {
+            cq_status st = cq_crowd_get_uids(sub, uids ? uids + off : nullptr);
+            if (st != CQ_OK) return st;
+            off += sub->W;
+        }
+        return CQ_OK;
+    }
     return got(c, copy_out(c, uids, c->uid, sizeof(uint32_t) * c->W), "get_uids");
 }
 
 cq_status cq_crowd_get_inverse(cq_crowd* c, double* ainv)
 {
     if (!c) return fail(CQ_EINVAL, "crowd is NULL");
+    if (!c->subs.empty()) {
+        size_t off = 0;
+        for (cq_crowd* sub : c->subs) {
+            cq_status st = cq_crowd_get_inverse(sub, ainv ? ainv + off : nullptr);
+            if (st != CQ_OK) return st;
+            off += (size_t)sub->W * 2 * sub->n * sub->n;
+        }
+        return CQ_OK;
+    }
     if (!ainv) return CQ_OK;
     const size_t n = c->n, cnt = (size_t)c->W * 2 * n * n;
     const size_t es = c->prec == CQ_FP64 ? 8 : 4;
@@ -1268,6 +1645,7 @@ cq_status cq_crowd_get_inverse(cq_crowd* c, double* ainv)
 cq_status cq_crowd_set_forced_decisions(cq_crowd* c, const uint8_t* flags, int n_sweeps)
 {
     if (!c) return fail(CQ_EINVAL, "crowd is NULL");
+    if (!c->subs.empty()) return fail(CQ_EINVAL, "parity mode works on crowds of one system");
     if (flags && n_sweeps < 1) return fail(CQ_EINVAL, "n_sweeps must be >= 1");
     HIP_TRY(hipStreamSynchronize(c->stream));
     if (c->forced) {
@@ -1294,6 +1672,7 @@ cq_status cq_crowd_set_forced_decisions(cq_crowd* c, const uint8_t* flags, int n
 cq_status cq_crowd_set_forced_branching(cq_crowd* c, const int* mult, int n_generations)
 {
     if (!c) return fail(CQ_EINVAL, "crowd is NULL");
+    if (!c->subs.empty()) return fail(CQ_EINVAL, "parity mode works on crowds of one system");
     if (mult && n_generations < 1) return fail(CQ_EINVAL, "n_generations must be >= 1");
     HIP_TRY(hipStreamSynchronize(c->stream));
     if (c->forced_mult) {
@@ -1322,6 +1701,19 @@ cq_status cq_crowd_set_forced_branching(cq_crowd* c, const int* mult, int n_gene
 cq_status cq_crowd_get_dmc_moves(cq_crowd* c, int64_t* accepted, int64_t* proposed)
 {
     if (!c) return fail(CQ_EINVAL, "crowd is NULL");
+    if (!c->subs.empty()) {
+        int64_t a = 0, b = 0;
+        for (cq_crowd* sub : c->subs) {
+            int64_t x = 0, y = 0;
+            cq_status st = cq_crowd_get_dmc_moves(sub, &x, &y);
+            if (st != CQ_OK) return st;
+            a += x;
+            b += y;
+        }
+        if (accepted) *accepted = a;
+        if (proposed) *proposed = b;
+        return CQ_OK;
+    }
     if (!c->have_alt) {
         if (accepted) *accepted = 0;
         if (proposed) *proposed = 0;
@@ -1338,6 +1730,7 @@ cq_status cq_crowd_get_dmc_moves(cq_crowd* c, int64_t* accepted, int64_t* propos
 cq_status cq_crowd_record_moves(cq_crowd* c, int n_sweeps)
 {
     if (!c) return fail(CQ_EINVAL, "crowd is NULL");
+    if (!c->subs.empty()) return fail(CQ_EINVAL, "parity mode works on crowds of one system");
     if (n_sweeps < 0) return fail(CQ_EINVAL, "n_sweeps must be >= 0");
     HIP_TRY(hipStreamSynchronize(c->stream));
     for (void** p : {(void**)&c->rec_rho, (void**)&c->rec_dlnj, (void**)&c->rec_prob, (void**)&c->rec_acc,
@@ -1371,6 +1764,7 @@ cq_status cq_crowd_record_moves(cq_crowd* c, int n_sweeps)
 cq_status cq_crowd_get_move_records(cq_crowd* c, double* rho, double* dlnj, double* prob, uint8_t* acc)
 {
     if (!c) return fail(CQ_EINVAL, "crowd is NULL");
+    if (!c->subs.empty()) return fail(CQ_EINVAL, "parity mode works on crowds of one system");
     if (c->rec_cap == 0) return fail(CQ_ESTATE, "recording is off");
     const size_t cnt = (size_t)c->rec_cap * c->ne * c->Wcap;
     cq_status st = copy_out(c, rho, c->rec_rho, cnt * 8);
@@ -1383,6 +1777,7 @@ cq_status cq_crowd_get_move_records(cq_crowd* c, double* rho, double* dlnj, doub
 cq_status cq_crowd_get_move_proposals(cq_crowd* c, double* rnew)
 {
     if (!c || !rnew) return fail(CQ_EINVAL, "NULL argument");
+    if (!c->subs.empty()) return fail(CQ_EINVAL, "parity mode works on crowds of one system");
     if (c->rec_cap == 0) return fail(CQ_ESTATE, "recording is off");
     const size_t cnt = (size_t)c->rec_cap * c->ne * c->Wcap;
     return got(c, copy_out(c, rnew, c->rec_rnew, cnt * 24), "get_move_proposals");
@@ -1391,6 +1786,10 @@ cq_status cq_crowd_get_move_proposals(cq_crowd* c, double* rnew)
 cq_status cq_crowd_set_kernel_timing(cq_crowd* c, int kind_mask)
 {
     if (!c) return fail(CQ_EINVAL, "crowd is NULL");
+    for (cq_crowd* sub : c->subs) {
+        cq_status st = cq_crowd_set_kernel_timing(sub, kind_mask);
+        if (st != CQ_OK) return st;
+    }
     if (kind_mask < 0 || kind_mask >= (1 << CQ_KERNEL_COUNT)) return fail(CQ_EINVAL, "bad kernel kind mask");
     HIP_TRY(hipStreamSynchronize(c->stream));
     c->timing_mask = kind_mask;
@@ -1409,8 +1808,17 @@ cq_status cq_crowd_get_kernel_timing(cq_crowd* c, int kind, double* total_ms, in
         HIP_TRY(hipEventElapsedTime(&ms, c->ev[kind][i].first, c->ev[kind][i].second));
         tot += ms;
     }
+    int64_t cnt = (int64_t)c->ev_used[kind];
+    for (cq_crowd* sub : c->subs) {  // a group's per-system launches (energy, branching, recompute)
+        double ms = 0.0;
+        int64_t k = 0;
+        cq_status st = cq_crowd_get_kernel_timing(sub, kind, &ms, &k);
+        if (st != CQ_OK) return st;
+        tot += ms;
+        cnt += k;
+    }
     if (total_ms) *total_ms = tot;
-    if (launches) *launches = (int64_t)c->ev_used[kind];
+    if (launches) *launches = cnt;
     return CQ_OK;
 }
 
@@ -1545,6 +1953,11 @@ cq_status cq_device_copy(void* dst, const void* src, uint64_t bytes, void* hip_s
 cq_status cq_crowd_synchronize(cq_crowd* c)
 {
     if (!c) return fail(CQ_EINVAL, "crowd is NULL");
+    for (cq_crowd* sub : c->subs) {
+        cq_status st = cq_crowd_synchronize(sub);
+        if (st != CQ_OK) return st;
+    }
+    if (!c->subs.empty()) return CQ_OK;
     HIP_TRY(hipStreamSynchronize(c->stream));
     HIP_TRY(hipGetLastError());
     return check_singular(c, "synchronize");

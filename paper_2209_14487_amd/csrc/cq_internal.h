@@ -188,6 +188,18 @@ template <typename T> void launch_energy(const CrowdView<T>& v, hipStream_t s);
 template <typename T> void launch_inverse(const CrowdView<T>& v, const InvWork& wk, hipStream_t s, int nmat = -1);
 void launch_sweep_end(Params* prm, hipStream_t s);
 template <typename T> void launch_window_dmc(const CrowdView<T>& v, int e0, int nmoves, hipStream_t s);
+// Walkers of several systems in one launch (device views, one (system, walker) item each; window
+// step j of spin block `spin`; persistent grid)
+template <typename T>
+void launch_window_dmc_multi(const CrowdView<T>* views, const int2* items, int n_items, int max_n, int spin, int j,
+                             int grid, hipStream_t s);
+// The window updates of several systems in one launch: L^-1 per (system, walker) item, then the
+// strips of 32 rows (FP32 matrix cores) or 16 rows (vector path), one (system, walker, strip) item each
+void launch_flush_mfma_multi(const CrowdView<float>* views, const int2* walkers, int n_walkers, const int4* strips,
+                             int n_strips, int spin, int grid, hipStream_t s);
+template <typename T>
+void launch_flush_vec_multi(const CrowdView<T>* views, const int4* strips, int n_strips, int max_n, int spin, int grid,
+                            hipStream_t s);
 template <typename T>
 void launch_dmc_branch(const DmcView& d, const WalkerArrays<T>& src, const WalkerArrays<T>& dst, int n, int ne,
                        const Params* prm, int gen, hipStream_t s);

@@ -112,8 +112,9 @@ __device__ __forceinline__ double block_sum(double x, double (*red)[8], int slot
 
 }  // namespace
 
+// The moves of one window of walker w (any system: every size comes from the view).
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_window_dmc(CrowdView<T> v, int e0, int nmoves)
+__device__ __forceinline__ void window_dmc_body(const CrowdView<T>& v, const int w, int e0, int nmoves)
 {
     constexpr int VEC = 16 / sizeof(T);
     constexpr int D = kMaxDelay;
@@ -131,7 +132,6 @@ __global__ __launch_bounds__(kBlock) void k_window_dmc(CrowdView<T> v, int e0, i
     __shared__ T s_w[64 * 5];
     __shared__ int s_acc;
 
-    const int w = blockIdx.x;
     if (w >= v.W) return;
     const int nt = blockDim.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
     const int spin = e0 >= n;
@@ -418,6 +418,44 @@ __global__ __launch_bounds__(kBlock) void k_window_dmc(CrowdView<T> v, int e0, i
 }
 
 template <typename T>
+__global__ __launch_bounds__(kBlock) void k_window_dmc(CrowdView<T> v, int e0, int nmoves)
+{
+    window_dmc_body<T>(v, blockIdx.x, e0, nmoves);
+}
+
+// Walkers of several systems in one launch: item i = (system, walker), window j of spin
+// block `spin` (systems whose blocks have fewer windows skip it).  Persistent: the grid
+// strides over the items, which come largest system first, so the long windows start first
+// and the short ones fill in behind them.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_window_dmc_multi(const CrowdView<T>* __restrict__ views,
+                                                             const int2* __restrict__ items, int n_items, int spin,
+                                                             int j)
+{
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int2 item = items[it];
+        const CrowdView<T> v = views[item.x];
+        const int a0 = j * v.K;
+        if (a0 < v.n) window_dmc_body<T>(v, item.y, spin * v.n + a0, min(v.K, v.n - a0));
+        __syncthreads();  // the next item reuses the shared memory
+    }
+}
+
+template <typename T>
+void launch_window_dmc_multi(const CrowdView<T>* views, const int2* items, int n_items, int max_n, int spin, int j,
+                             int grid, hipStream_t s)
+{
+    const size_t lds = 8 * (size_t)max_n * sizeof(T);
+    static bool lds_set = false;
+    if (!lds_set) {
+        (void)hipFuncSetAttribute((const void*)k_window_dmc_multi<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)(8 * 2048 * sizeof(T)));
+        lds_set = true;
+    }
+    hipLaunchKernelGGL(k_window_dmc_multi<T>, dim3(grid), dim3(kBlock), lds, s, views, items, n_items, spin, j);
+}
+
+template <typename T>
 void launch_window_dmc(const CrowdView<T>& v, int e0, int nmoves, hipStream_t s)
 {
     const size_t lds = 8 * (size_t)v.n * sizeof(T);
@@ -545,6 +583,10 @@ void launch_dmc_branch(const DmcView& d, const WalkerArrays<T>& src, const Walke
 }
 
 template void launch_window_dmc<float>(const CrowdView<float>&, int, int, hipStream_t);
+template void launch_window_dmc_multi<float>(const CrowdView<float>*, const int2*, int, int, int, int, int,
+                                             hipStream_t);
+template void launch_window_dmc_multi<double>(const CrowdView<double>*, const int2*, int, int, int, int, int,
+                                              hipStream_t);
 template void launch_window_dmc<double>(const CrowdView<double>&, int, int, hipStream_t);
 template void launch_dmc_branch<float>(const DmcView&, const WalkerArrays<float>&, const WalkerArrays<float>&, int, int,
                                        const Params*, int, hipStream_t);

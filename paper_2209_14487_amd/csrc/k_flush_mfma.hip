@@ -19,6 +19,8 @@
 // columns of half 0 and half 1) and the accumulator of GEMM 2, so neither product
 // moves the strip.  Each of the 8 waves holds every 8th tile; GEMM 1 partial
 // sums of the waves are added in a fixed order in LDS.
+#include <algorithm>
+
 #include "cq_device.h"
 #include "cq_internal.h"
 
@@ -33,7 +35,7 @@ constexpr int kStripTiles = 4;                    // 32-column tiles per wave (N
 // Window and per-move paths: the window's columns are read from the row buffer
 // Cbuf.  Two workgroups per CU (four waves per SIMD): one's operand and HBM
 // latency hides behind the other's MFMAs.
-__global__ __launch_bounds__(kFlushThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_flush_mfma(CrowdView<float> v, int spin)
+__device__ __forceinline__ void flush_mfma_body(const CrowdView<float>& v, int spin, const int w, const int strip)
 {
     __shared__ float sX[kFlushWaves][32][33];  // per wave: partial X^T[m][i]
     __shared__ float sB[32][33];      // -b[i][m] (FP32 operand of GEMM 2)
@@ -42,8 +44,6 @@ __global__ __launch_bounds__(kFlushThreads) __attribute__((amdgpu_waves_per_eu(4
     __shared__ int wel[32], wsl[32];
     const int n = v.n, K = v.K;
     const int ntile = n / 32, nstrip = n / 32;
-    int w, strip;
-    xcd_map(blockIdx.x, nstrip, w, strip);
     if (w >= v.W) return;
     int cnt = v.cnt[(size_t)2 * v.W + w];
     if (cnt > K) cnt = K;
@@ -189,6 +189,24 @@ __global__ __launch_bounds__(kFlushThreads) __attribute__((amdgpu_waves_per_eu(4
                 store16(dst + 8 * g, x);
             }
         }
+    }
+}
+
+__global__ __launch_bounds__(kFlushThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_flush_mfma(CrowdView<float> v, int spin)
+{
+    int w, strip;
+    xcd_map(blockIdx.x, v.n / 32, w, strip);
+    flush_mfma_body(v, spin, w, strip);
+}
+
+// Several systems in one launch: item i = (system, walker, strip of 32 rows); persistent.
+__global__ __launch_bounds__(kFlushThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_flush_mfma_multi(
+    const CrowdView<float>* __restrict__ views, const int4* __restrict__ items, int n_items, int spin)
+{
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int4 item = items[it];
+        flush_mfma_body(views[item.x], spin, item.y, item.z);
+        __syncthreads();  // the next item reuses the shared memory
     }
 }
 
@@ -340,11 +358,11 @@ __global__ __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(4
 
 // L^-1 of each walker's window (lower triangular, FP64): lane j forms column j
 // by forward substitution down the rows.
-__global__ __launch_bounds__(64) void k_window_linv(CrowdView<float> v)
+__device__ __forceinline__ void window_linv_body(const CrowdView<float>& v, const int w)
 {
     __shared__ double sL[32][33];
     __shared__ double sX[32][33];
-    const int w = blockIdx.x, K = v.K, lane = threadIdx.x;
+    const int K = v.K, lane = threadIdx.x;
     int cnt = v.cnt[(size_t)2 * v.W + w];
     if (cnt > K) cnt = K;
     if (cnt <= 0) return;
@@ -366,6 +384,27 @@ __global__ __launch_bounds__(64) void k_window_linv(CrowdView<float> v)
         const int r = idx / cnt, c = idx % cnt;
         v.wlinv[((size_t)w * K + r) * K + c] = sX[r][c];
     }
+}
+
+__global__ __launch_bounds__(64) void k_window_linv(CrowdView<float> v) { window_linv_body(v, blockIdx.x); }
+
+__global__ __launch_bounds__(64) void k_window_linv_multi(const CrowdView<float>* __restrict__ views,
+                                                          const int2* __restrict__ items, int n_items)
+{
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int2 item = items[it];
+        window_linv_body(views[item.x], item.y);
+        __syncthreads();
+    }
+}
+
+void launch_flush_mfma_multi(const CrowdView<float>* views, const int2* walkers, int n_walkers, const int4* strips,
+                             int n_strips, int spin, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_window_linv_multi, dim3(std::min(n_walkers, 4 * grid)), dim3(64), 0, s, views, walkers,
+                       n_walkers);
+    hipLaunchKernelGGL(k_flush_mfma_multi, dim3(std::min(n_strips, grid)), dim3(kFlushThreads), 0, s, views, strips,
+                       n_strips, spin);
 }
 
 bool flush_mfma_fits(int n)

@@ -16,6 +16,8 @@
 //                 E_L = -1/2 sum_i [l_i + lap_i U + |grad_i U|^2 + 2 g_i . grad_i U]
 //               g_i = sum_j grad phi_j(r_i) A^-1_ji is the dot of gradient row i
 //               with row i of M (likewise l_i); FP64 sums over electrons.
+#include <algorithm>
+
 #include "cq_device.h"
 #include "cq_internal.h"
 
@@ -25,7 +27,7 @@ constexpr int kRowsPerWave = 4;
 constexpr int kRowsPerBlock = 4 * kRowsPerWave;
 
 template <typename T, int EPL>
-__global__ __launch_bounds__(kBlock) void k_flush_vec(CrowdView<T> v, int spin)
+__device__ __forceinline__ void flush_vec_body(const CrowdView<T>& v, int spin, const int w, const int strip)
 {
     constexpr int VEC = 16 / sizeof(T);
     constexpr int NV = EPL / VEC;  // 16-byte vectors per lane per row
@@ -37,8 +39,6 @@ __global__ __launch_bounds__(kBlock) void k_flush_vec(CrowdView<T> v, int spin)
     __shared__ double xs[4][kRowsPerWave][kMaxDelay];
     const int n = v.n, K = v.K;
     const int nstrip = (n + kRowsPerBlock - 1) / kRowsPerBlock;
-    int w, strip;
-    xcd_map(blockIdx.x, nstrip, w, strip);
     if (w >= v.W) return;
     int cnt = v.cnt[(size_t)2 * v.W + w];  // final size of the window
     if (cnt > K) cnt = K;
@@ -147,6 +147,46 @@ __global__ __launch_bounds__(kBlock) void k_flush_vec(CrowdView<T> v, int spin)
             const int j = (i * 64 + lane) * VEC;
             if (r0 + q < n && j < n) store16(Mbase + (size_t)(r0 + q) * n + j, &mr[q][i * VEC]);
         }
+}
+
+template <typename T, int EPL>
+__global__ __launch_bounds__(kBlock) void k_flush_vec(CrowdView<T> v, int spin)
+{
+    int w, strip;
+    xcd_map(blockIdx.x, (v.n + kRowsPerBlock - 1) / kRowsPerBlock, w, strip);
+    flush_vec_body<T, EPL>(v, spin, w, strip);
+}
+
+// Several systems in one launch: item i = (system, walker, strip of 16 rows); persistent.  EPL
+// covers the largest system; the smaller ones leave the lanes past their N idle.
+template <typename T, int EPL>
+__global__ __launch_bounds__(kBlock) void k_flush_vec_multi(const CrowdView<T>* __restrict__ views,
+                                                            const int4* __restrict__ items, int n_items, int spin)
+{
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int4 item = items[it];
+        flush_vec_body<T, EPL>(views[item.x], spin, item.y, item.z);
+        __syncthreads();  // the next item reuses the shared memory
+    }
+}
+
+template <typename T>
+void launch_flush_vec_multi(const CrowdView<T>* views, const int4* strips, int n_strips, int max_n, int spin, int grid,
+                            hipStream_t s)
+{
+    constexpr int VEC = 16 / sizeof(T);
+    const int per_lane = (max_n + 63) / 64;
+    const dim3 g(std::min(n_strips, grid)), b(kBlock);
+    if (per_lane <= VEC)
+        hipLaunchKernelGGL((k_flush_vec_multi<T, VEC>), g, b, 0, s, views, strips, n_strips, spin);
+    else if (per_lane <= 4)
+        hipLaunchKernelGGL((k_flush_vec_multi<T, 4>), g, b, 0, s, views, strips, n_strips, spin);
+    else if (per_lane <= 8)
+        hipLaunchKernelGGL((k_flush_vec_multi<T, 8>), g, b, 0, s, views, strips, n_strips, spin);
+    else if (per_lane <= 16)
+        hipLaunchKernelGGL((k_flush_vec_multi<T, 16>), g, b, 0, s, views, strips, n_strips, spin);
+    else
+        hipLaunchKernelGGL((k_flush_vec_multi<T, 32>), g, b, 0, s, views, strips, n_strips, spin);
 }
 
 template <typename T>
@@ -309,6 +349,8 @@ void launch_energy(const CrowdView<T>& v, hipStream_t s)
 }
 
 template void launch_flush<float>(const CrowdView<float>&, int, hipStream_t, bool);
+template void launch_flush_vec_multi<float>(const CrowdView<float>*, const int4*, int, int, int, int, hipStream_t);
+template void launch_flush_vec_multi<double>(const CrowdView<double>*, const int4*, int, int, int, int, hipStream_t);
 template void launch_flush<double>(const CrowdView<double>&, int, hipStream_t, bool);
 template void launch_energy<float>(const CrowdView<float>&, hipStream_t);
 template void launch_energy<double>(const CrowdView<double>&, hipStream_t);

@@ -56,6 +56,9 @@ def test_invalid_arguments_are_rejected_before_any_device_work():
     counts2 = (ctypes.c_int * 2)(16, 16)
     systems2 = (ctypes.c_void_p * 2)(h.value, h.value)
     assert L.cq_crowd_create(systems2, counts2, 2, ctypes.byref(desc), ctypes.byref(c)) == cq.CQ_EINVAL
+    assert b"system 0 has no FP64 table" in L.cq_last_error()  # checked for every system, before any device call
+    counts0 = (ctypes.c_int * 2)(16, 0)
+    assert L.cq_crowd_create(systems2, counts0, 2, ctypes.byref(desc), ctypes.byref(c)) == cq.CQ_EINVAL
     L.cq_system_destroy(h)
 
 
