@@ -117,6 +117,17 @@ cq_status cq_system_fill_bspline_philox(cq_system* sys, uint64_t seed, int elem_
    a_anti for opposite spins.  Without this call the Jastrow factor is 1. */
 cq_status cq_system_load_pade_j2(cq_system* sys, double a_par, double a_anti, double b);
 
+/* Add the electron-electron Coulomb energy to the local energy (enable = 1; 0 removes it):
+   the electrons (charge -1) in the periodic box with a uniform neutralising background, by
+   Ewald summation,
+     V = sum_{i<j} erfc(alpha r_ij) / r_ij + (2 pi / L^3) sum_{k != 0} exp(-k^2/4alpha^2) / k^2
+         |sum_i exp(i k.r_i)|^2 - alpha Ne / sqrt(pi) - pi Ne^2 / (2 alpha^2 L^3),
+   minimum-image pairs, alpha L = 10.1 and k = 2 pi n / L with n^2 <= 18^2 (each left-out term
+   below about 1e-12 of its kind), in FP64 for every precision; one electron per cell gives the
+   Madelung energy -2.8372975 / (2 L).  Crowds created afterwards include it in E_L (and so in
+   the DMC weights and energies); the kinetic part is unchanged.  Errors: CQ_EINVAL, CQ_ENOMEM. */
+cq_status cq_system_set_coulomb(cq_system* sys, int enable);
+
 void cq_system_destroy(cq_system* sys);
 
 /* ----------------------------------------------------------------- crowds */

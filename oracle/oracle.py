@@ -64,6 +64,8 @@ def lib():
         L.or_virtual_ratios.argtypes = [ctypes.POINTER(OrSystem), ctypes.c_int, dp, ctypes.c_int, dp,
                                         ctypes.c_int, dp, dp, dp]
         L.or_virtual_ratios.restype = ctypes.c_int
+        L.or_ewald_energy.argtypes = [ctypes.POINTER(OrSystem), dp, ctypes.c_double]
+        L.or_ewald_energy.restype = ctypes.c_double
         _lib = L
     return _lib
 
@@ -80,6 +82,7 @@ class OrSystem(ctypes.Structure):
         ("use_j2", ctypes.c_int),
         ("j2_a_par", ctypes.c_double), ("j2_a_anti", ctypes.c_double), ("j2_b", ctypes.c_double),
         ("seed", ctypes.c_uint64),
+        ("use_coulomb", ctypes.c_int),
     ]
 
 
@@ -103,6 +106,7 @@ class System:
     j2_a_anti: float = 0.5
     j2_b: float = 1.0
     seed: int = 0
+    use_coulomb: bool = False
     _c: OrSystem = field(default=None, repr=False)
 
     @property
@@ -117,7 +121,7 @@ class System:
                            self.table.ctypes.data if self.table is not None else None,
                            int(self.coef_seed), int(self.coef_fp32), int(self.use_j2),
                            float(self.j2_a_par), float(self.j2_a_anti), float(self.j2_b),
-                           int(self.seed))
+                           int(self.seed), int(self.use_coulomb))
         return self._c
 
 
@@ -407,3 +411,12 @@ def virtual_ratios(sys: System, R0, offsets, n_threads=0):
                                *[o.ctypes.data for o in out]) != 0:
         raise ZeroDivisionError("singular configuration")
     return tuple(out)
+
+
+def ewald_energy(sys: System, R, alpha=None):
+    """Electron-electron Coulomb energy of one configuration R [Ne][3] in the periodic box with a
+    uniform neutralising background (Ewald summation with splitting parameter alpha, default
+    6 / L; the value does not depend on alpha)."""
+    R = np.ascontiguousarray(R, dtype=np.float64)
+    cs = sys.c()
+    return lib().or_ewald_energy(ctypes.byref(cs), R.ctypes.data, 6.0 / sys.L if alpha is None else alpha)

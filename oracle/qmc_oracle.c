@@ -147,6 +147,7 @@ typedef struct {
     int use_j2;
     double j2_a_par, j2_a_anti, j2_b;
     uint64_t seed;        /* key of the move generator */
+    int use_coulomb;      /* add the Ewald electron-electron energy to E_L */
 } or_system;
 
 static double coef_at(const or_system* s, int ix, int iy, int iz, int n)
@@ -455,6 +456,54 @@ int or_lu_inverse(int n, const double* A, double* Ainv, double* logdet, int* sig
 /*   g_i = sum_j grad phi_j(r_i) Ainv[j][i],  l_i = sum_j lap phi_j(r_i) Ainv[j][i] */
 /* Ainv[s], Gm[s] ([N][N][3]) and Lm[s] ([N][N]) are per spin.               */
 /* ------------------------------------------------------------------------ */
+/* ------------------------------------------------------------------------ */
+/* Electron-electron Coulomb energy of one configuration in the periodic box */
+/* with a uniform neutralising background (Ewald summation; charges -1,     */
+/* Omega = L^3, N = Ne):                                                      */
+/*   V = 1/2 sum_{i,j} sum'_n erfc(alpha |r_ij + n L|) / |r_ij + n L|         */
+/*     + (2 pi / Omega) sum_{k != 0} exp(-k^2 / (4 alpha^2)) / k^2 |rho_k|^2   */
+/*     - alpha N / sqrt(pi) - pi N^2 / (2 alpha^2 Omega),                     */
+/* rho_k = sum_i exp(i k . r_i), k = 2 pi n / L; the prime drops n = 0 when  */
+/* i = j.  The value does not depend on alpha; the image and k shells are   */
+/* taken until the terms fall below 1e-18 of the leading ones.              */
+/* ------------------------------------------------------------------------ */
+double or_ewald_energy(const or_system* s, const double* R, double alpha)
+{
+    const int N = s->n_up + s->n_dn;
+    const double L = s->L, omega = L * L * L;
+    const int nr = (int)ceil(6.5 / (alpha * L)) + 1;        /* image shells: alpha r >= 6.5 beyond */
+    const int nk = (int)ceil(13.0 * alpha * L / (2.0 * OR_PI)) + 1;  /* k shells: k / (2 alpha) >= 6.5 */
+    double real = 0.0;
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j)
+            for (int a = -nr; a <= nr; ++a)
+                for (int b = -nr; b <= nr; ++b)
+                    for (int c = -nr; c <= nr; ++c) {
+                        if (i == j && a == 0 && b == 0 && c == 0) continue;
+                        double d[3] = {R[3 * i] - R[3 * j] + a * L, R[3 * i + 1] - R[3 * j + 1] + b * L,
+                                       R[3 * i + 2] - R[3 * j + 2] + c * L};
+                        double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+                        real += 0.5 * erfc(alpha * r) / r;
+                    }
+    double recip = 0.0;
+    for (int a = -nk; a <= nk; ++a)
+        for (int b = -nk; b <= nk; ++b)
+            for (int c = -nk; c <= nk; ++c) {
+                if (a == 0 && b == 0 && c == 0) continue;
+                double k[3] = {2.0 * OR_PI * a / L, 2.0 * OR_PI * b / L, 2.0 * OR_PI * c / L};
+                double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+                double re = 0.0, im = 0.0;
+                for (int i = 0; i < N; ++i) {
+                    double ph = k[0] * R[3 * i] + k[1] * R[3 * i + 1] + k[2] * R[3 * i + 2];
+                    re += cos(ph);
+                    im += sin(ph);
+                }
+                recip += exp(-k2 / (4.0 * alpha * alpha)) / k2 * (re * re + im * im);
+            }
+    recip *= 2.0 * OR_PI / omega;
+    return real + recip - alpha * N / sqrt(OR_PI) - OR_PI * (double)N * N / (2.0 * alpha * alpha * omega);
+}
+
 double or_local_energy(const or_system* s, const double* R,
                        const double* Ainv_up, const double* Ainv_dn,
                        const double* G_up, const double* G_dn,
@@ -481,7 +530,9 @@ double or_local_energy(const or_system* s, const double* R,
                  + 2.0 * (g[0] * gu[0] + g[1] * gu[1] + g[2] * gu[2]);
         }
     }
-    return -0.5 * sum;
+    double e = -0.5 * sum;
+    if (s->use_coulomb) e += or_ewald_energy(s, R, 6.0 / s->L);
+    return e;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -51,6 +51,7 @@ _SIGS = {
     "cq_system_load_bspline": [_P, _P, _I, _I, _I, _I, _I, _I],
     "cq_system_fill_bspline_philox": [_P, ctypes.c_uint64, _I, _I, _I],
     "cq_system_load_pade_j2": [_P, ctypes.c_double, ctypes.c_double, ctypes.c_double],
+    "cq_system_set_coulomb": [_P, _I],
     "cq_system_destroy": [_P],
     "cq_crowd_create": [_P, _P, _I, _P, _P],
     "cq_crowd_set_positions": [_P, _P, _I, ctypes.c_uint32],
@@ -250,6 +251,10 @@ class System:
 
     def load_j2(self, a_par=0.25, a_anti=0.5, b=1.0):
         _check(lib().cq_system_load_pade_j2(self._h, a_par, a_anti, b))
+
+    def set_coulomb(self, enable: bool = True):
+        """Include the Ewald electron-electron energy in E_L of crowds created afterwards."""
+        _check(lib().cq_system_set_coulomb(self._h, int(enable)))
 
     def close(self):
         if self._h:

@@ -47,6 +47,11 @@ struct cq_system {
     bool owned[2] = {false, false};
     int use_j2 = 0;
     double a_par = 0.0, a_anti = 0.0, b = 1.0;
+    // Ewald electron-electron energy in E_L (cq_system_set_coulomb)
+    int coulomb = 0, nmax = 0, nk = 0;
+    double alpha = 0.0;
+    int4* kvec = nullptr;
+    double* kfac = nullptr;
 };
 
 struct cq_crowd {
@@ -153,6 +158,9 @@ struct cq_crowd {
     std::vector<int4> hstrip;
     std::vector<unsigned char> hviews;
     int n_cu = 0;
+    // Ewald buffers (systems with the Coulomb energy)
+    double2* ew_phase = nullptr;
+    double* ew_part = nullptr;
     // host state
     cq::Params hp{};
     bool ready = false;
@@ -234,6 +242,32 @@ cq::CrowdView<T> view(const cq_crowd* c)
     v.drift = c->drift;
     v.drift_max = c->drift_max;
     return v;
+}
+
+// The local energy of every walker: the kinetic part, plus the Ewald electron-electron energy
+// when the system has it.
+template <typename T>
+void local_energy(cq_crowd* c, const cq::CrowdView<T>& v, hipStream_t st)
+{
+    cq::launch_energy<T>(v, st);
+    const cq_system* s = c->sys;
+    if (s && s->coulomb && c->ew_phase) {
+        cq::EwaldView e{};
+        e.W = c->W;
+        e.ne = c->ne;
+        e.nmax = s->nmax;
+        e.nk = s->nk;
+        e.pk = (s->nk + cq::ewald_wavevectors_per_block() - 1) / cq::ewald_wavevectors_per_block();
+        e.pr = 8;
+        e.L = s->L;
+        e.alpha = s->alpha;
+        e.R = c->R;
+        e.kvec = s->kvec;
+        e.kfac = s->kfac;
+        e.phase = c->ew_phase;
+        e.part = c->ew_part;
+        cq::launch_ewald(e, c->eloc, st);
+    }
 }
 
 cq_status dev_alloc(cq_crowd* c, void** p, size_t bytes)
@@ -342,7 +376,7 @@ void enqueue_sweep(cq_crowd* c)
             }
         }
         timed_begin(c, CQ_KERNEL_ENERGY);
-        cq::launch_energy<T>(v, c->stream);
+        local_energy<T>(c, v, c->stream);
         timed_end(c, CQ_KERNEL_ENERGY);
         cq::launch_sweep_end(c->prm, c->stream);
         return;
@@ -358,7 +392,7 @@ void enqueue_sweep(cq_crowd* c)
                 timed_end(c, CQ_KERNEL_UPDATE);
             }
         timed_begin(c, CQ_KERNEL_ENERGY);
-        cq::launch_energy<T>(v, c->stream);
+        local_energy<T>(c, v, c->stream);
         timed_end(c, CQ_KERNEL_ENERGY);
         cq::launch_sweep_end(c->prm, c->stream);
         return;
@@ -380,7 +414,7 @@ void enqueue_sweep(cq_crowd* c)
         }
     }
     timed_begin(c, CQ_KERNEL_ENERGY);
-    cq::launch_energy<T>(v, c->stream);
+    local_energy<T>(c, v, c->stream);
     timed_end(c, CQ_KERNEL_ENERGY);
     cq::launch_sweep_end(c->prm, c->stream);
 }
@@ -499,7 +533,7 @@ cq_status setup_state(cq_crowd* c)
     // the set-up inversion is no recompute: the drift record starts after it
     HIP_TRY(hipMemsetAsync(c->drift_max, 0, sizeof(unsigned long long), c->stream));
     c->n_recomputes = 0;
-    cq::launch_energy<T>(v, c->stream);
+    local_energy<T>(c, v, c->stream);
     HIP_TRY(hipGetLastError());
     return check_singular(c, "set_positions");
 }
@@ -684,7 +718,7 @@ void dmc_post(cq_crowd* c, int gen, int n_target, double tau, bool recompute)
     // the periodic FP64 recompute, before the energy and the branching read the inverses
     if (recompute) enqueue_inverse<T>(c);
     timed_begin(c, CQ_KERNEL_ENERGY);
-    cq::launch_energy<T>(v, c->stream);
+    local_energy<T>(c, v, c->stream);
     timed_end(c, CQ_KERNEL_ENERGY);
     cq::DmcView d{};
     d.state = c->dmc_state;
@@ -829,9 +863,49 @@ cq_status cq_system_load_pade_j2(cq_system* s, double a_par, double a_anti, doub
     return CQ_OK;
 }
 
+cq_status cq_system_set_coulomb(cq_system* s, int enable)
+{
+    if (!s) return fail(CQ_EINVAL, "system is NULL");
+    if (!enable) {
+        s->coulomb = 0;
+        return CQ_OK;
+    }
+    if (!s->kvec) {
+        // alpha L = 10.1: beyond the nearest image every pair term is below erfc(5.05) = 8e-13 of it;
+        // wavevectors with n^2 <= 18^2, where exp(-k^2 / 4 alpha^2) has fallen to 1e-13
+        const int nmax = 18;
+        const double L = s->L, alpha = 10.1 / L;
+        std::vector<int4> kv;
+        std::vector<double> kf;
+        for (int a = 0; a <= nmax; ++a)
+            for (int b = -nmax; b <= nmax; ++b)
+                for (int c = -nmax; c <= nmax; ++c) {
+                    const bool half = a > 0 || (a == 0 && (b > 0 || (b == 0 && c > 0)));
+                    if (!half || a * a + b * b + c * c > nmax * nmax) continue;
+                    const double k2 = (4.0 * M_PI * M_PI / (L * L)) * (double)(a * a + b * b + c * c);
+                    kv.push_back(make_int4(a, b, c, 0));
+                    kf.push_back(std::exp(-k2 / (4.0 * alpha * alpha)) / k2);
+                }
+        if (hipMalloc((void**)&s->kvec, sizeof(int4) * kv.size()) != hipSuccess ||
+            hipMalloc((void**)&s->kfac, sizeof(double) * kf.size()) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(CQ_ENOMEM, "Ewald wavevectors");
+        }
+        HIP_TRY(hipMemcpy(s->kvec, kv.data(), sizeof(int4) * kv.size(), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(s->kfac, kf.data(), sizeof(double) * kf.size(), hipMemcpyHostToDevice));
+        s->nmax = nmax;
+        s->nk = (int)kv.size();
+        s->alpha = alpha;
+    }
+    s->coulomb = 1;
+    return CQ_OK;
+}
+
 void cq_system_destroy(cq_system* s)
 {
     if (!s) return;
+    if (s->kvec) (void)hipFree(s->kvec);
+    if (s->kfac) (void)hipFree(s->kfac);
     for (int i = 0; i < 2; ++i)
         if (s->owned[i]) (void)hipFree(s->table[i]);
     delete s;
@@ -1064,6 +1138,16 @@ cq_status cq_crowd_create(const cq_system* const* systems, const int* walkers_pe
         c->inv.logabs = (double*)la;
         c->inv.negs = (int*)ng;
         c->inv.b = b;
+    }
+    if (s->coulomb) {
+        const int pk = (s->nk + cq::ewald_wavevectors_per_block() - 1) / cq::ewald_wavevectors_per_block();
+        cq_status st = dev_alloc(c, (void**)&c->ew_phase, sizeof(double2) * Wc * ne * 3 * (s->nmax + 1));
+        if (st == CQ_OK) st = dev_alloc(c, (void**)&c->ew_part, sizeof(double) * Wc * (pk + 8));
+        if (st != CQ_OK) {
+            std::string msg = g_err;
+            cq_crowd_destroy(c);
+            return fail(st, msg);
+        }
     }
     std::vector<uint32_t> uids(W);
     for (int w = 0; w < W; ++w) uids[w] = desc->first_uid + (uint32_t)w;

@@ -154,6 +154,18 @@ struct WalkerArrays {
     long long* nprop;
 };
 
+// Ewald electron-electron energy of a crowd's walkers (FP64).
+struct EwaldView {
+    int W, ne, nmax, nk, pk, pr;  // walkers, electrons, largest |n| component, half-space
+                                  // wavevectors, blocks per walker for the k sum and the pairs
+    double L, alpha;
+    const double* R;              // [W][Ne][3]
+    const int4* kvec;             // [nk] (nx, ny, nz, 0), the half space of 0 < n^2 <= nmax^2
+    const double* kfac;           // [nk] exp(-k^2 / 4 alpha^2) / k^2
+    double2* phase;               // [W][Ne][3][nmax + 1] exp(i 2 pi m x / L)
+    double* part;                 // [W][pk + pr] block sums
+};
+
 // FP64 Gauss-Jordan workspace for matrices too large for LDS.
 struct InvWork {
     double* S;        // [nmat][N][N]
@@ -206,6 +218,8 @@ void launch_dmc_branch(const DmcView& d, const WalkerArrays<T>& src, const Walke
 template <typename T>
 void launch_virtual(const CrowdView<T>& v, const double* offsets, int nq, double* ratio, double* rho, double* dlnj,
                     hipStream_t s);
+void launch_ewald(const EwaldView& e, double* eloc, hipStream_t s);  // adds V_ee to eloc
+int ewald_wavevectors_per_block();
 void launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 void launch_zero(void* p, size_t bytes, hipStream_t s);  // bytes: a multiple of 4
 size_t inverse_work_bytes(int nmat, int n);

@@ -731,3 +731,41 @@ def test_virtual_ratios_spherical_mean_of_plane_waves():
         assert np.all(np.abs(per_spin - exact) <= tol), (dd, per_spin, exact)
         # and not trivially: the d^2 term is resolved
         assert np.all(np.abs(per_spin - 4.0) > 100 * tol)
+
+
+# ---------------------------------------------------- Ewald electron-electron energy
+
+# Madelung constant of a simple cubic lattice of unit charges in a uniform neutralising background
+# (the Wigner-crystal value of Nijboer and de Wette, Physica 23 (1957) 309): one charge per cubic cell
+# of edge L has the Coulomb energy -XI_SC / (2 L).
+XI_SC = 2.837297479480620
+
+
+def test_ewald_one_electron_is_the_madelung_energy():
+    """One electron per periodic cell: V = -xi_sc / (2 L) wherever it sits and whatever the splitting
+    parameter (a missing self or background term, or a wrong 2 pi / Omega, changes the value)."""
+    for L in (5.0, 7.0):
+        s = orc.System(1, 0, L)
+        for r in ([0.0, 0.0, 0.0], [1.0, 2.0, 3.0], [L - 1e-9, 0.5 * L, 0.1]):
+            for a in (3.0 / L, 6.0 / L, 9.0 / L):
+                v = orc.ewald_energy(s, np.array([r]), a)
+                assert abs(v * L + XI_SC / 2) < 1e-12, (L, r, a, v)
+
+
+def test_ewald_energy_is_independent_of_the_splitting_and_homogeneous():
+    """For 8 electrons anywhere in the box the Ewald sum does not depend on alpha (the real-space
+    and reciprocal parts trade terms exactly), does not change under a common translation, and
+    scales as 1/lambda when the box and the positions are scaled by lambda."""
+    L = 7.0
+    s = orc.System(4, 4, L)
+    R = np.random.default_rng(1).uniform(0, L, (8, 3))
+    vals = [orc.ewald_energy(s, R, a / L) for a in (2.5, 4.0, 6.0, 9.0)]
+    assert max(vals) - min(vals) < 1e-12 * abs(vals[0])
+    shifted = np.mod(R + np.array([1.3, -2.2, 0.4]), L)
+    assert abs(orc.ewald_energy(s, shifted) - vals[0]) < 1e-12 * abs(vals[0])
+    s2 = orc.System(4, 4, 2.0 * L)
+    assert abs(2.0 * orc.ewald_energy(s2, 2.0 * R) - vals[0]) < 1e-12 * abs(vals[0])
+    # two electrons far closer than the box: the Coulomb 1/r dominates and sets the sign and size
+    R2 = R.copy()
+    R2[1] = R2[0] + [1e-3, 0.0, 0.0]
+    assert orc.ewald_energy(s, R2) - vals[0] > 900.0
