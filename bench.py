@@ -271,7 +271,7 @@ def kernel_source_hash():
     """SHA-256 of the sources the gather and update kernels are built from."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("k_batch.hip", "k_flush_mfma.hip", "cq_device.h", "cq_internal.h"):
+    for f in ("k_batch.hip", "k_flush_mfma.hip", "k_update.hip", "k_virtual.hip", "cq_device.h", "cq_internal.h"):
         with open(os.path.join(ROOT, "paper_2209_14487_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -288,7 +288,9 @@ def measured_traffic(workload):
         rec = json.load(fh)
     if rec.get("source_sha256") != kernel_source_hash():
         return None
-    return dict(vgl=rec.get("traffic_bytes_per_launch"), update=(rec.get("update") or {}).get("traffic_bytes_per_launch"))
+    return dict(vgl=rec.get("traffic_bytes_per_launch"), update=(rec.get("update") or {}).get("traffic_bytes_per_launch"),
+                sm=(rec.get("sm") or {}).get("traffic_bytes_per_launch"),
+                virtual=(rec.get("virtual") or {}).get("traffic_bytes_per_launch"))
 
 
 def host_cpu():
@@ -571,9 +573,11 @@ def main():
         # k_flush_vec, judged by HBM GB/s
         sm = run_gpu(cq, wl, "fp64", 1, 0, args.sm_steps, 0, ["update"], False, path=args.path)
         out["roofline_sm"] = roofline_sm(sm, n, 8)
+        out["roofline_sm"]["traffic"] = (traffic or {}).get("sm")
         log("  SM update (FP64, k = 1): %.0f GB/s" % out["roofline_sm"]["achieved"])
     if args.virtual_points > 0:
         out["roofline_virtual"] = run_virtual(cq, wl, args.virtual_points)
+        out["roofline_virtual"]["traffic"] = (traffic or {}).get("virtual")
         log("  virtual moves: %.0f GB/s (algorithmic), %.3e points/s" % (out["roofline_virtual"]["achieved"],
                                                                         out["roofline_virtual"]["points_per_s"]))
     if not args.no_cpu:

@@ -11,8 +11,10 @@ Usage (on the GPU machine, each run in its own process):
 FETCH_SIZE and WRITE_SIZE are read per dispatch in KiB.  The library's plain
 copy kernel (cq::k_copy16, 1 GiB read + 1 GiB written, launched once by
 --calibrate-copy) gives the factor between counter readings and bytes; the
-per-launch averages of the gather (k_prop_vgl) and of the update
-(k_flush_mfma_batch, "update") are scaled by it.  The output records the source
+per-launch averages of the gather (k_prop_vgl), of the update
+(k_flush_mfma_batch, "update"), of the FP64 Sherman-Morrison update
+(k_flush_vec<double>, "sm") and of the virtual-move kernel (k_virtual,
+"virtual") are scaled by it.  The output records the source
 hash of the kernels, so bench.py uses the figures only while they are unchanged.
 """
 import csv
@@ -71,11 +73,19 @@ def main():
     update = dict(kernel="k_flush_mfma_batch", launches=[unf, unw], fetch_kib_per_launch=uf,
                   write_kib_per_launch=uw, fetch_bytes_per_launch=ufb, write_bytes_per_launch=uwb,
                   traffic_bytes_per_launch=ufb + uwb)
+    extra = {}
+    for key, needle in (("sm", "k_flush_vec<double"), ("virtual", "k_virtual")):
+        if any(needle in k for k in fetch) and any(needle in k for k in write):
+            xf, xnf = pick(fetch, needle)
+            xw, xnw = pick(write, needle)
+            extra[key] = dict(kernel=needle, launches=[xnf, xnw], fetch_kib_per_launch=xf, write_kib_per_launch=xw,
+                              fetch_bytes_per_launch=xf * 1024.0 * sf, write_bytes_per_launch=xw * 1024.0 * sw,
+                              traffic_bytes_per_launch=xf * 1024.0 * sf + xw * 1024.0 * sw)
     rec = dict(kernel="k_prop_vgl", workload=workload, launches=[nf, nw],
                fetch_kib_per_launch=gf, write_kib_per_launch=gw,
                copy_fetch_kib=cf, copy_write_kib=cw, scale_fetch=sf, scale_write=sw,
                fetch_bytes_per_launch=fb, write_bytes_per_launch=wb, traffic_bytes_per_launch=fb + wb,
-               update=update, source_sha256=kernel_source_hash(),
+               update=update, source_sha256=kernel_source_hash(), **extra,
                command="rocprofv3 --pmc FETCH_SIZE|WRITE_SIZE --output-format csv -d DIR -o run -- "
                        "python3 bench.py --steps 2 --warmup 1 --fp64-steps 0 --no-cpu --alone-steps 0 --calibrate-copy; "
                        "python3 bench_traffic.py FETCH_DIR WRITE_DIR %s" % workload)
