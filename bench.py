@@ -227,7 +227,8 @@ def run_gpu(cq, wl, precision, delay, recompute, steps, warmup, timing_kinds, us
 def rooflines(res, n, W, steps, traffic, s_c=4, s=4):
     """(spline roofline, update roofline) from one run's HIP-event kernel times.
 
-    B-spline VGL of the round's proposals (k_prop_vgl): per proposal 64 stencil points x N
+    B-spline VGL of the round's proposals (k_prop_vgl_wave, or k_prop_vgl when N has fewer than
+    64 orbital groups of 16 bytes): per proposal 64 stencil points x N
     orbitals read from the table and the 5 rows written; one launch = the round's proposals.
     Rank-k inverse update (k_flush_mfma_batch): per walker-spin window with r accepted moves it
     reads and writes the N x N inverse once and does 4 N^2 r useful flops; r summed over the run,
@@ -243,7 +244,8 @@ def rooflines(res, n, W, steps, traffic, s_c=4, s=4):
     up_flops = 4.0 * n * n * r_per_launch
     traffic = traffic or {}
     roof_vgl = dict(bound="hbm", achieved=round(vgl_gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(vgl_gbs / HBM_PEAK_GBS, 4), traffic=traffic.get("vgl"), kernel="k_prop_vgl",
+                    frac=round(vgl_gbs / HBM_PEAK_GBS, 4), traffic=traffic.get("vgl"),
+                    kernel="k_prop_vgl_wave" if n * s_c // 16 >= 64 else "k_prop_vgl",
                     us_per_launch=round(vgl_t * 1e6, 3), bytes_per_launch=int(vgl_bytes),
                     proposals_per_launch=int(props_per_launch))
     roof_up = dict(bound="mfma", achieved=round(up_flops / up_t / 1e12, 2), peak=FP32_PEAK_TFLOPS,

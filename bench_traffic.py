@@ -11,7 +11,7 @@ Usage (on the GPU machine, each run in its own process):
 FETCH_SIZE and WRITE_SIZE are read per dispatch in KiB.  The library's plain
 copy kernel (cq::k_copy16, 1 GiB read + 1 GiB written, launched once by
 --calibrate-copy) gives the factor between counter readings and bytes; the
-per-launch averages of the gather (k_prop_vgl), of the update
+per-launch averages of the gather (k_prop_vgl_wave), of the update
 (k_flush_mfma_batch, "update"), of the FP64 Sherman-Morrison update
 (k_flush_vec<double>, "sm") and of the virtual-move kernel (k_virtual,
 "virtual") are scaled by it.  The output records the source
@@ -64,8 +64,8 @@ def main():
     cf, _ = pick(fetch, "k_copy16")
     cw, _ = pick(write, "k_copy16")
     sf, sw = copy_bytes / (cf * 1024.0), copy_bytes / (cw * 1024.0)
-    gf, nf = pick(fetch, "k_prop_vgl")
-    gw, nw = pick(write, "k_prop_vgl")
+    gf, nf = pick(fetch, "k_prop_vgl_wave<float")
+    gw, nw = pick(write, "k_prop_vgl_wave<float")
     fb, wb = gf * 1024.0 * sf, gw * 1024.0 * sw
     uf, unf = pick(fetch, "k_flush_mfma_batch")
     uw, unw = pick(write, "k_flush_mfma_batch")
@@ -81,7 +81,7 @@ def main():
             extra[key] = dict(kernel=needle, launches=[xnf, xnw], fetch_kib_per_launch=xf, write_kib_per_launch=xw,
                               fetch_bytes_per_launch=xf * 1024.0 * sf, write_bytes_per_launch=xw * 1024.0 * sw,
                               traffic_bytes_per_launch=xf * 1024.0 * sf + xw * 1024.0 * sw)
-    rec = dict(kernel="k_prop_vgl", workload=workload, launches=[nf, nw],
+    rec = dict(kernel="k_prop_vgl_wave", workload=workload, launches=[nf, nw],
                fetch_kib_per_launch=gf, write_kib_per_launch=gw,
                copy_fetch_kib=cf, copy_write_kib=cw, scale_fetch=sf, scale_write=sw,
                fetch_bytes_per_launch=fb, write_bytes_per_launch=wb, traffic_bytes_per_launch=fb + wb,

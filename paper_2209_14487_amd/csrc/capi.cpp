@@ -65,11 +65,12 @@ struct cq_crowd {
     uint32_t first_uid = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
-    // second stream of the batched path: the gather for round r+1 runs on it while round r
-    // is decided and applied on `stream`, then round r+1's Jastrow sums beside round r's
-    // update.  Events per round: P formed (ev_fork), decided (ev_dec), gathered (ev_gat).
+    // second stream of the batched path: the gather for round r+2 runs on it while round
+    // r+1 is decided and applied on `stream`, then round r+2's Jastrow sums.  Events per
+    // round: first gather done (ev_fork, at a spin block's start), decided (ev_dec),
+    // columns (or update) done (ev_cols), gathered (ev_gat).
     hipStream_t stream2 = nullptr;
-    std::vector<hipEvent_t> ev_fork, ev_dec, ev_gat;
+    std::vector<hipEvent_t> ev_fork, ev_dec, ev_cols, ev_gat;
     std::vector<void*> allocs;
     // device state
     double* R = nullptr;
@@ -311,21 +312,31 @@ void enqueue_sweep(cq_crowd* c)
     const cq::CrowdView<T> v = view<T>(c);
     const int n = c->n, K = c->K;
     if (c->path == CQ_PATH_BATCH) {
-        // Rounds of both spin blocks in order.  On stream: P(r), decide(r), update(r), ...
-        // On stream2: gather(r+1) once P(r) is formed (so that the decision workgroups of
-        // round r are placed before the gather starts), then jd(r+1) and the row copy of
-        // round r once decide(r) is done; P(r+1) waits for all of them and follows
-        // update(r).  gather(r+1) writes only the ring slots of electrons that round r-1
-        // decided, whose rows update(r-1) and the row copy of round r-1 have read; jd(r+1)
-        // reads the positions decide(r) wrote and runs beside update(r).
+        // Rounds of both spin blocks in order.  On stream: P(r), decide(r), cols(r),
+        // update(r), P(r+1), ...  On stream2, two rounds ahead: gather(r+2) as soon as
+        // cols(r) is done (update(r) too when the update reads the stage ring), then
+        // jd(r+2) and the row copy of round r+1 once decide(r+1) is done; P(r+2) waits
+        // for them.  So the gather runs beside the whole of round r+1: P, decisions,
+        // columns and update.
+        //   gather(r+2)'s range, fixed by decide(r), lies in [d + Q, d + 2Q) with d the
+        //   first candidate of round r+1; its ring slots (electron mod 2Q) are those of
+        //   electrons decided in round r or before, whose readers (P, decide, cols, the
+        //   row copy and a stage-reading update of those rounds) have finished, and are
+        //   disjoint from round r+1's candidates [d, d + Q).
+        //   jd(r+2) reads the positions decide(r+1) wrote and the proposals of gather(r+2).
+        //   The row copy of round r+1 reads the window decide(r+2) overwrites; P(r+2)
+        //   orders them.
+        // A spin block starts with gather(0) and jd(0) on stream, then gather(1) on
+        // stream2 (its range is set by the cursor reset).
         const int rounds = cq::batch_rounds(n, K), total = 2 * rounds;
+        const bool overlap = c->stream2 != nullptr && (int)c->ev_gat.size() >= total;
         auto gather = [&](int q, hipStream_t st) {
             const int spin = q / rounds, r = q % rounds;
             timed_begin(c, CQ_KERNEL_PROPOSE, st);
             cq::launch_batch_stencils<T>(v, spin, r & 1, r == 0, st);
             timed_end(c, CQ_KERNEL_PROPOSE, st);
             timed_begin(c, CQ_KERNEL_VGL, st);
-            cq::launch_batch_vgl<T>(v, spin, r & 1, c->stream2 != nullptr, st);
+            cq::launch_batch_vgl<T>(v, spin, r & 1, overlap, st);
             timed_end(c, CQ_KERNEL_VGL, st);
         };
         auto jastrow = [&](int q, hipStream_t st) {
@@ -333,32 +344,34 @@ void enqueue_sweep(cq_crowd* c)
             cq::launch_batch_jd<T>(v, q / rounds, st);
             timed_end(c, CQ_KERNEL_PROPOSE, st);
         };
-        const bool overlap = c->stream2 != nullptr && (int)c->ev_gat.size() >= total;
         hipStream_t s1 = c->stream, s2 = c->stream2;
         auto keep = [&](hipError_t e) {
             if (e != hipSuccess && c->enq_err == hipSuccess) c->enq_err = e;
         };
+        // the vector update reads the accepted rows from the stage ring; the matrix-core
+        // update reads them packed by the column kernel
+        const bool update_reads_stage = v.ub == nullptr;
         for (int spin = 0; spin < 2; ++spin) {
             const int q0 = spin * rounds;
             gather(q0, s1);
             jastrow(q0, s1);
+            if (overlap && rounds > 1) {
+                keep(hipEventRecord(c->ev_fork[q0], s1));
+                keep(hipStreamWaitEvent(s2, c->ev_fork[q0], 0));
+                gather(q0 + 1, s2);
+            }
             for (int r = 0; r < rounds; ++r) {
                 const int q = q0 + r;
-                const bool next = r + 1 < rounds;
+                const bool next = r + 1 < rounds, ahead = overlap && r + 2 < rounds;
                 if (overlap && r > 0) keep(hipStreamWaitEvent(s1, c->ev_gat[q], 0));
                 timed_begin(c, CQ_KERNEL_RESOLVE);
                 cq::launch_batch_pmat<T>(v, spin, s1);
-                if (overlap && next) {
-                    keep(hipEventRecord(c->ev_fork[q], s1));
-                    keep(hipStreamWaitEvent(s2, c->ev_fork[q], 0));
-                    gather(q + 1, s2);
-                }
                 cq::launch_batch_decide<T>(v, spin, r & 1, s1);
+                if (overlap && next) keep(hipEventRecord(c->ev_dec[q], s1));
+                cq::launch_batch_cols<T>(v, spin, s1);
                 timed_end(c, CQ_KERNEL_RESOLVE);
-                // the accepted rows go into the walker's matrices beside the update (before
-                // the next decisions overwrite the window, before gather(r+2) reuses the slots)
+                if (ahead && !update_reads_stage) keep(hipEventRecord(c->ev_cols[q], s1));
                 if (overlap && next) {
-                    keep(hipEventRecord(c->ev_dec[q], s1));
                     keep(hipStreamWaitEvent(s2, c->ev_dec[q], 0));
                     jastrow(q + 1, s2);
                     cq::launch_batch_rows<T>(v, spin, s2);
@@ -369,6 +382,11 @@ void enqueue_sweep(cq_crowd* c)
                 timed_begin(c, CQ_KERNEL_UPDATE);
                 cq::launch_flush<T>(v, spin, s1, true);
                 timed_end(c, CQ_KERNEL_UPDATE);
+                if (ahead) {
+                    if (update_reads_stage) keep(hipEventRecord(c->ev_cols[q], s1));
+                    keep(hipStreamWaitEvent(s2, c->ev_cols[q], 0));
+                    gather(q + 2, s2);
+                }
                 if (!overlap && next) {
                     gather(q + 1, s1);
                     jastrow(q + 1, s1);
@@ -936,7 +954,7 @@ void cq_crowd_destroy(cq_crowd* c)
     if (c->vout) (void)hipFree(c->vout);
     if (c->forced) (void)hipFree(c->forced);
     if (c->forced_mult) (void)hipFree(c->forced_mult);
-    for (auto* evs : {&c->ev_fork, &c->ev_dec, &c->ev_gat})
+    for (auto* evs : {&c->ev_fork, &c->ev_dec, &c->ev_cols, &c->ev_gat})
         for (hipEvent_t e : *evs) (void)hipEventDestroy(e);
     if (c->stream2) (void)hipStreamDestroy(c->stream2);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -1051,7 +1069,7 @@ cq_status cq_crowd_create(const cq_system* const* systems, const int* walkers_pe
         if (hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking) == hipSuccess) {
             const int total = 2 * cq::batch_rounds(c->n, 1) + 2;  // enough for any delay rank
             bool ok = true;
-            for (auto* evs : {&c->ev_fork, &c->ev_dec, &c->ev_gat})
+            for (auto* evs : {&c->ev_fork, &c->ev_dec, &c->ev_cols, &c->ev_gat})
                 for (int i = 0; ok && i < total; ++i) {
                     hipEvent_t e;
                     ok = hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;

@@ -189,6 +189,7 @@ template <typename T> void launch_batch_jd(const CrowdView<T>& v, int spin, hipS
 template <typename T> void launch_batch_pmat(const CrowdView<T>& v, int spin, hipStream_t s);
 template <typename T> void launch_batch_rows(const CrowdView<T>& v, int spin, hipStream_t s);
 template <typename T> void launch_batch_decide(const CrowdView<T>& v, int spin, int par, hipStream_t s);
+template <typename T> void launch_batch_cols(const CrowdView<T>& v, int spin, hipStream_t s);
 int batch_rounds(int n, int K);      // rounds per spin block (enough when every move is accepted)
 int batch_candidates(int n, int K);  // candidates per round, Q
 // linv_ready: the window's L^-1 is already in wlinv (the batched path forms it)

@@ -28,16 +28,18 @@
 // evaluated; every later accepted move adds the change of its pair term.
 //
 // The orbital rows of an electron depend on nothing but its own proposal, so
-// the gather runs one round ahead: while round r is decided and applied, the
-// gather fills the ring up to 2Q electrons past round r's first candidate
-// (the furthest round r+1 can reach), on a second stream.  Its range is fixed
-// by the cursors of round r-1, and it writes only ring slots of electrons that
-// round r-1 decided, so it shares no data with round r.  The Jastrow sums need
+// the gather runs ahead: from the end of round r-1's column kernel, through
+// round r's P, decisions, columns and update, the gather fills the ring up to
+// 2Q electrons past round r's first candidate (the furthest round r+1 can
+// reach), on a second stream.  Its range is fixed by the cursors of round r-1,
+// and it writes only ring slots of electrons that round r-1 (or an earlier
+// round) decided, so it shares no data with round r.  The Jastrow sums need
 // the positions after round r and are formed separately once round r is
 // decided, next to round r's inverse update.
 //
 // k_stencils    proposals and stencils of the electrons in the gather range
-// k_prop_vgl    gather + VGL of the same electrons
+// k_prop_vgl_wave / k_prop_vgl   gather + VGL of the same electrons (N >= 64 orbital
+//               groups of 16 bytes / smaller N)
 // k_jd          Jastrow sums of a round's new candidates
 // k_pmat        P of every walker's candidates (FP64 sums of exact products)
 // k_decide      one workgroup per walker: the decisions, the window for the
@@ -94,23 +96,15 @@ __device__ __forceinline__ double pair_j2(const CrowdView<T>& v, double a, const
     return u;
 }
 
-// Proposals per workgroup: one when a proposal's orbital groups fill the
-// workgroup, else up to 4 (a proposal then takes `groups` consecutive threads).
-inline int batch_pp(int n, int elem_bytes)
-{
-    const int groups = n / (16 / elem_bytes);
-    if (groups >= kBlock) return 1;
-    const int pp = kBlock / groups;
-    return pp > 4 ? 4 : pp;
-}
+// Gather layout for small N (fewer than 64 orbital groups of 16 bytes): 4
+// proposals per workgroup, `groups` consecutive threads each.
+constexpr int kVglSmallPP = 4;
 
-inline int batch_threads(int n, int elem_bytes)
+inline int vgl_groups(int n, int elem_bytes) { return n / (16 / elem_bytes); }
+
+inline int vgl_small_threads(int n, int elem_bytes)
 {
-    const int groups = n / (16 / elem_bytes);
-    const int pp = batch_pp(n, elem_bytes);
-    if (pp == 1) return kBlock;
-    const int t = ((pp * groups + 63) / 64) * 64;
-    return t > kBlock ? kBlock : t;
+    return ((kVglSmallPP * vgl_groups(n, elem_bytes) + 63) / 64) * 64;
 }
 
 // Electron t of walker w's gather range [look[par][w][0], look[par][w][1])
@@ -143,13 +137,96 @@ __global__ __launch_bounds__(kBlock) void k_stencils(CrowdView<T> v, int spin, i
     if (lane < 3) v.rprop[ps * 3 + lane] = rp[lane];
 }
 
-// Gather + value/gradient/Laplacian of the electrons in the gather range.  Each
-// thread owns one 16-byte group of orbitals and runs the 64 stencil points as 4
-// planes of 16 loads.  The grid is persistent (a few workgroups per CU, each
-// taking groups of pp proposals in turn), so that the decision, column and update
-// kernels of the current round still find room on every CU while it runs.
-template <typename T, bool ONE>  // ONE: one proposal per workgroup at a time (pp == 1)
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_prop_vgl(CrowdView<T> v, int spin, int pp, int par)
+// Gather + value/gradient/Laplacian of the electrons in the gather range, for
+// N whose orbital groups (16 bytes each) fill whole waves (groups >= 64).  Every
+// wave takes one slice of 64 groups of one proposal at a time, so the stencil
+// (64 table offsets and 320 weights) is the same for all its lanes and is read with
+// scalar loads: no LDS and no barrier.  Lane l of the slice owns one group, and
+// each x-plane's 16 table loads (16 bytes per lane) are issued together before any
+// of its sums, so that a wave keeps 16 KB in flight.  Work items (proposal,
+// slice) go round-robin over the waves of a persistent grid (a few workgroups per
+// CU), so that the decision, column and update kernels of the current round still
+// find room on every CU while it runs.
+//
+// A pointer into the constant address space marks the stencil and the gather
+// ranges as read-only for the kernel's duration; loads through it at a
+// wave-uniform address become scalar loads.
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T*;
+
+template <typename T>
+__device__ __forceinline__ cptr<T> as_const(const T* p)
+{
+    return (cptr<T>)p;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_prop_vgl_wave(CrowdView<T> v,
+                                                                                                  int spin, int par)
+{
+    constexpr int VEC = 16 / sizeof(T);
+    const int n = v.n, Q = v.Q, QR = v.QR, groups = n / VEC;
+    const int slices = (groups + 63) >> 6;
+    const int nitem = v.W * Q * slices;
+    const int lane = threadIdx.x & 63;
+    const int wave0 = __builtin_amdgcn_readfirstlane(blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6));
+    const int nwave = gridDim.x * (kBlock / 64);
+    const cptr<int> look = as_const(v.look);
+    const cptr<size_t> sidx_all = as_const(v.sidx);
+    const cptr<T> swt_all = as_const((const T*)v.swt);
+    for (int item = wave0; item < nitem; item += nwave) {
+        const int pi = item / slices, sl = item - pi * slices;
+        const int w = pi / Q, t = pi - w * Q;
+        const cptr<int> lk = look + ((size_t)par * v.W + w) * 2;  // gather range of this round
+        const int a = lk[0] + t;
+        if (a >= lk[1]) continue;
+        const int g = sl * 64 + lane;
+        const size_t ps = (size_t)w * QR + a % QR;
+        const cptr<size_t> sidx = sidx_all + ps * 64;
+        const cptr<T> sw = swt_all + ps * 64 * 5;
+        const uint32_t lane_off = (uint32_t)(g < groups ? g : 0) * (uint32_t)(VEC * sizeof(T));
+        T acc[5][VEC];
+#pragma unroll
+        for (int k = 0; k < 5; ++k)
+#pragma unroll
+            for (int i = 0; i < VEC; ++i) acc[k][i] = (T)0;
+#pragma unroll 1
+        for (int x = 0; x < 4; ++x) {
+            T vals[16][VEC];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const char* base = reinterpret_cast<const char*>(v.table + sidx[x * 16 + q]);
+                load16(reinterpret_cast<const T*>(base + lane_off), vals[q]);
+            }
+            // keeps the sums (and the scheduler's interleaving of them) behind the loads
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const cptr<T> wq = sw + (x * 16 + q) * 5;
+                const T wv = wq[0], wgx = wq[1], wgy = wq[2], wgz = wq[3], wl = wq[4];
+#pragma unroll
+                for (int i = 0; i < VEC; ++i) {
+                    acc[0][i] += wv * vals[q][i];
+                    acc[1][i] += wgx * vals[q][i];
+                    acc[2][i] += wgy * vals[q][i];
+                    acc[3][i] += wgz * vals[q][i];
+                    acc[4][i] += wl * vals[q][i];
+                }
+            }
+        }
+        if (g < groups) {
+            T* dst = v.stage + ps * 5 * (size_t)n + (size_t)g * VEC;
+#pragma unroll
+            for (int k = 0; k < 5; ++k) store16(dst + (size_t)k * n, acc[k]);
+        }
+    }
+}
+
+// The same for small N (groups < 64): up to 4 proposals per workgroup, `groups`
+// consecutive threads per proposal, stencils staged in LDS.
+template <typename T>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_prop_vgl(CrowdView<T> v, int spin,
+                                                                                           int pp, int par)
 {
     constexpr int VEC = 16 / sizeof(T);
     // dynamic LDS sized for pp proposals: stencil offsets, weights, flags
@@ -160,82 +237,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
     const int n = v.n, Q = v.Q, QR = v.QR, groups = n / VEC;
     const int nprop = v.W * Q;
     const int nt = blockDim.x, tid = threadIdx.x;
-    const int tpp = pp == 1 ? nt : groups;  // threads per proposal
-    const int p = tid / tpp, t0 = tid % tpp;
+    const int p = tid / groups, t0 = tid % groups;  // proposal of the chunk, group
     const int nchunk = (nprop + pp - 1) / pp;
-
-    if constexpr (ONE) {
-        // One proposal per chunk (large N).  The stencil of the block's next proposal
-        // is loaded while the current one is gathered, and the cursor range of the
-        // proposal after that one chunk earlier still, so that no global round trip
-        // stands between two gathers.
-        auto in_range = [&](int pi, int& a) { return pi < nprop && gather_electron(v.look, par, v.W, pi / Q, pi % Q, a); };
-        size_t nidx = 0;
-        T nw[5] = {(T)0, (T)0, (T)0, (T)0, (T)0};
-        auto fetch = [&](bool ok, int pi, int a) {
-            if (ok && tid < 64) {
-                const size_t ps = (size_t)(pi / Q) * QR + a % QR;
-                nidx = v.sidx[ps * 64 + tid];
-                const T* sw = (const T*)v.swt + (ps * 64 + tid) * 5;
-#pragma unroll
-                for (int k = 0; k < 5; ++k) nw[k] = sw[k];
-            }
-        };
-        int a1 = 0, a2 = 0;
-        bool ok1 = in_range(blockIdx.x, a1);
-        bool ok2 = in_range(blockIdx.x + gridDim.x, a2);
-        fetch(ok1, blockIdx.x, a1);
-        for (int chunk = blockIdx.x; chunk < nchunk; chunk += gridDim.x) {
-            const bool ok = ok1;
-            const int a = a1;
-            __syncthreads();  // the previous proposal's readers of the stencil are done
-            if (ok && tid < 64) {
-                s_idx[0][tid] = nidx;
-#pragma unroll
-                for (int k = 0; k < 5; ++k) s_w[0][tid * 5 + k] = nw[k];
-            }
-            __syncthreads();
-            ok1 = ok2;
-            a1 = a2;
-            fetch(ok1, chunk + gridDim.x, a1);
-            ok2 = in_range(chunk + 2 * gridDim.x, a2);
-            if (!ok) continue;
-            const int w = chunk / Q, slot = a % QR;
-            T* dst = v.stage + ((size_t)w * QR + slot) * 5 * (size_t)n;
-            const size_t* sidx = s_idx[0];
-            const T* sw = s_w[0];
-            for (int g = tid; g < groups; g += nt) {
-                const int j0 = g * VEC;
-                T acc[5][VEC];
-#pragma unroll
-                for (int k = 0; k < 5; ++k)
-#pragma unroll
-                    for (int i = 0; i < VEC; ++i) acc[k][i] = (T)0;
-#pragma unroll 1
-                for (int x = 0; x < 4; ++x) {
-                    T vals[16][VEC];
-#pragma unroll
-                    for (int q = 0; q < 16; ++q) load16(v.table + sidx[x * 16 + q] + j0, vals[q]);
-#pragma unroll
-                    for (int q = 0; q < 16; ++q) {
-                        const T* wq = sw + (x * 16 + q) * 5;
-                        const T wv = wq[0], wgx = wq[1], wgy = wq[2], wgz = wq[3], wl = wq[4];
-#pragma unroll
-                        for (int i = 0; i < VEC; ++i) {
-                            acc[0][i] += wv * vals[q][i];
-                            acc[1][i] += wgx * vals[q][i];
-                            acc[2][i] += wgy * vals[q][i];
-                            acc[3][i] += wgz * vals[q][i];
-                            acc[4][i] += wl * vals[q][i];
-                        }
-                    }
-                }
-#pragma unroll
-                for (int k = 0; k < 5; ++k) store16(dst + (size_t)k * n + j0, acc[k]);
-            }
-        }
-        return;
-    }
 
     for (int chunk = blockIdx.x; chunk < nchunk; chunk += gridDim.x) {
         const int first = chunk * pp;
@@ -268,8 +271,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
         T* dst = v.stage + ((size_t)w * QR + slot) * 5 * (size_t)n;
         const size_t* sidx = s_idx[p];
         const T* sw = s_w[p];
-        for (int g = t0; g < groups; g += tpp) {
-            const int j0 = g * VEC;
+        {
+            const int j0 = t0 * VEC;
             T acc[5][VEC];
 #pragma unroll
             for (int k = 0; k < 5; ++k)
@@ -502,8 +505,11 @@ struct DecideLds {
 // kernel writes the gather range of round r+2: from the end of round r+1's range
 // to 2Q past round r+1's first candidate.
 // Gather workgroups per CU when it runs beside the round being decided and applied
-// (the rest of each CU stays free for those kernels), and when it runs alone.
+// (the rest of each CU stays free for those kernels: one workgroup of the wave-sliced
+// gather, 4 waves of 92 registers, leaves room for an update workgroup of 8 waves of
+// 124 registers and for the decision and column kernels), and when it runs alone.
 constexpr int kVglBlocksPerCU = 3;
+constexpr int kVglWaveBlocksPerCU = 1;
 constexpr int kVglBlocksPerCUAlone = 8;
 
 template <typename T>
@@ -975,14 +981,19 @@ int device_cu_count()
 template <typename T>
 void launch_batch_vgl(const CrowdView<T>& v, int spin, int par, bool beside, hipStream_t s)
 {
-    const int pp = batch_pp(v.n, sizeof(T));
+    const int groups = vgl_groups(v.n, sizeof(T));
+    if (groups >= 64) {
+        const int items = v.W * v.Q * ((groups + 63) / 64);
+        const int nb = std::min((items + kBlock / 64 - 1) / (kBlock / 64),
+                                (beside ? kVglWaveBlocksPerCU : kVglBlocksPerCUAlone) * device_cu_count());
+        hipLaunchKernelGGL(k_prop_vgl_wave<T>, dim3(nb), dim3(kBlock), 0, s, v, spin, par);
+        return;
+    }
+    const int pp = kVglSmallPP;
     const int nchunk = (v.W * v.Q + pp - 1) / pp;
     const int nb = std::min(nchunk, (beside ? kVglBlocksPerCU : kVglBlocksPerCUAlone) * device_cu_count());
     const size_t lds = (size_t)pp * (64 * sizeof(size_t) + 64 * 5 * sizeof(T)) + 4 * sizeof(int);
-    if (pp == 1)
-        hipLaunchKernelGGL((k_prop_vgl<T, true>), dim3(nb), dim3(batch_threads(v.n, sizeof(T))), lds, s, v, spin, pp, par);
-    else
-        hipLaunchKernelGGL((k_prop_vgl<T, false>), dim3(nb), dim3(batch_threads(v.n, sizeof(T))), lds, s, v, spin, pp, par);
+    hipLaunchKernelGGL(k_prop_vgl<T>, dim3(nb), dim3(vgl_small_threads(v.n, sizeof(T))), lds, s, v, spin, pp, par);
 }
 
 template <typename T>
@@ -1020,6 +1031,11 @@ void launch_batch_decide(const CrowdView<T>& v, int spin, int par, hipStream_t s
         lds_set = true;
     }
     hipLaunchKernelGGL(k_decide<T>, dim3(v.W), dim3(kBlock), sizeof(DecideLds), s, v, spin, par);
+}
+
+template <typename T>
+void launch_batch_cols(const CrowdView<T>& v, int spin, hipStream_t s)
+{
     hipLaunchKernelGGL(k_cols<T>, dim3(xcd_grid(v.W, (v.n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, v, spin);
 }
 
@@ -1033,6 +1049,8 @@ template void launch_batch_rows<float>(const CrowdView<float>&, int, hipStream_t
 template void launch_batch_rows<double>(const CrowdView<double>&, int, hipStream_t);
 template void launch_batch_pmat<float>(const CrowdView<float>&, int, hipStream_t);
 template void launch_batch_pmat<double>(const CrowdView<double>&, int, hipStream_t);
+template void launch_batch_cols<float>(const CrowdView<float>&, int, hipStream_t);
+template void launch_batch_cols<double>(const CrowdView<double>&, int, hipStream_t);
 template void launch_batch_decide<float>(const CrowdView<float>&, int, int, hipStream_t);
 template void launch_batch_decide<double>(const CrowdView<double>&, int, int, hipStream_t);
 
