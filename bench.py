@@ -178,6 +178,7 @@ def run_gpu(cq, wl, precision, delay, recompute, steps, warmup, timing_kinds, us
     acc = sum(int(c.acceptance()[0].sum()) for c in crowds)
     prop = sum(int(c.acceptance()[1].sum()) for c in crowds)
     k_used = crowds[0].delay_rank()
+    path_used = crowds[0].path()
     el = np.concatenate([c.local_energy() for c in crowds])
     # FP64 recomputes that fell inside the timed sweeps, and their device time
     n_rec = sum(c.drift()[2] for c in crowds) - rec0
@@ -215,7 +216,7 @@ def run_gpu(cq, wl, precision, delay, recompute, steps, warmup, timing_kinds, us
     if recompute > 0 and rec_ms is not None:
         seconds = seconds - 1e-3 * rec_ms_in + (steps / recompute) * 1e-3 * rec_ms
     out = dict(seconds=seconds, wall_seconds=t1 - t0, moves=moves, moves_per_s=moves / seconds,
-               wall_moves_per_s=moves / (t1 - t0), kernels=kt, delay_rank=k_used,
+               wall_moves_per_s=moves / (t1 - t0), kernels=kt, delay_rank=k_used, path=path_used,
                accepted_timed=acc - acc0, acceptance=acc / max(prop, 1), e_mean=float(el.mean()),
                finite=bool(np.isfinite(el).all()), recomputes_in_timed=n_rec, recompute_ms=rec_ms,
                recompute_ms_in_timed=rec_ms_in)
@@ -234,6 +235,7 @@ def rooflines(res, n, W, steps, traffic, s_c=4, s=4):
     reads and writes the N x N inverse once and does 4 N^2 r useful flops; r summed over the run,
     divided by all of its launches (rounds where no walker has a move left included)."""
     vgl_ms, vgl_n = res["kernels"]["vgl"]
+    sweep_path = res.get("path") == "sweep"  # one launch per sweep does the gather of every move
     props_per_launch = W * n * 2 * steps / max(vgl_n, 1)
     vgl_bytes = props_per_launch * (64 * n * s_c + 5 * n * s)
     vgl_t = vgl_ms / max(vgl_n, 1) * 1e-3
@@ -245,9 +247,12 @@ def rooflines(res, n, W, steps, traffic, s_c=4, s=4):
     traffic = traffic or {}
     roof_vgl = dict(bound="hbm", achieved=round(vgl_gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(vgl_gbs / HBM_PEAK_GBS, 4), traffic=traffic.get("vgl"),
-                    kernel="k_prop_vgl_wave" if n * s_c // 16 >= 64 else "k_prop_vgl",
+                    kernel="k_sweep" if sweep_path else ("k_prop_vgl_wave" if n * s_c // 16 >= 64 else "k_prop_vgl"),
                     us_per_launch=round(vgl_t * 1e6, 3), bytes_per_launch=int(vgl_bytes),
                     proposals_per_launch=int(props_per_launch))
+    if up_n == 0:  # the whole-sweep path applies its updates inside k_sweep
+        return roof_vgl, dict(bound="mfma", achieved=0.0, peak=FP32_PEAK_TFLOPS, unit="TFLOP/s", frac=0.0,
+                              traffic=None, kernel="k_sweep", note="Sherman-Morrison updates inside k_sweep")
     roof_up = dict(bound="mfma", achieved=round(up_flops / up_t / 1e12, 2), peak=FP32_PEAK_TFLOPS,
                    unit="TFLOP/s", frac=round(up_flops / up_t / 1e12 / FP32_PEAK_TFLOPS, 4),
                    traffic=traffic.get("update"), kernel="k_flush_mfma_batch",
@@ -538,7 +543,7 @@ def main():
                                     "%d crowd(s) x %d walkers, delayed rank %d, FP64 recompute every %d sweeps"
                                     % (wl.name, n, n, wl.L, wl.G, wl.table_bytes(4) / 1e9, wl.crowds, wl.walkers,
                                        delay, wl.recompute_every),
-                           precision="mixed", path=args.path,
+                           precision="mixed", path=mixed["path"],
                            launch="eager launches; HIP events around every launch of %s in the timed region" % "/".join(kinds)),
                roofline=dominant, roofline_spline=roof_vgl, roofline_update=roof_up, kernels=kinfo,
                windows_per_sweep=windows_per_sweep,
@@ -553,7 +558,7 @@ def main():
                                    "by that share of one timed recompute"))
     if "graph_moves_per_s" in mixed:
         out["graph_moves_per_s"] = round(mixed["graph_moves_per_s"], 1)
-    if args.alone_steps > 0 and args.path in ("auto", "batch"):
+    if args.alone_steps > 0 and mixed["path"] == "batch":
         # the same kernels with the GPU to themselves: one stream, every kernel in order
         alone = run_gpu(cq, wl, "mixed", delay, 0, args.alone_steps, 1, ["vgl", "update"], False,
                         path=args.path, streams=1)
@@ -570,7 +575,7 @@ def main():
         # both sides replay the captured sweep graph (no events), so launch overheads match
         ref = mixed.get("graph_moves_per_s", mixed["moves_per_s"])
         out["mixed_over_fp64"] = round(ref / f64["moves_per_s"], 3)
-    if args.sm_steps > 0 and args.path in ("auto", "batch"):
+    if args.sm_steps > 0 and mixed["path"] == "batch":
         # Sherman-Morrison (k = 1) in FP64: the wave-reduced dot products and rank-1 update of
         # k_flush_vec, judged by HBM GB/s
         sm = run_gpu(cq, wl, "fp64", 1, 0, args.sm_steps, 0, ["update"], False, path=args.path)

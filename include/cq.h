@@ -83,8 +83,19 @@ typedef enum {
                     which has not moved yet), then one workgroup per walker
                     decides the window's moves in order from the k x k products of
                     proposal rows and inverse columns.
-   CQ_PATH_AUTO:    CQ_PATH_BATCH. */
-typedef enum { CQ_PATH_AUTO = 0, CQ_PATH_MULTI = 1, CQ_PATH_WINDOW = 2, CQ_PATH_BATCH = 3 } cq_kernel_path;
+   CQ_PATH_SWEEP:   one workgroup per walker runs every move of a sweep in one
+                    launch, the walker's inverses in LDS, a Sherman-Morrison update
+                    after each accepted move (delay rank 1).  For small systems,
+                    where launches would dominate: N <= 64 and N a multiple of 4.
+   CQ_PATH_AUTO:    CQ_PATH_SWEEP when it applies and the delay rank is 0 or 1,
+                    else CQ_PATH_BATCH. */
+typedef enum {
+    CQ_PATH_AUTO = 0,
+    CQ_PATH_MULTI = 1,
+    CQ_PATH_WINDOW = 2,
+    CQ_PATH_BATCH = 3,
+    CQ_PATH_SWEEP = 4
+} cq_kernel_path;
 
 typedef struct cq_system cq_system;  /* orbitals + Jastrow + box + electron counts (opaque) */
 typedef struct cq_crowd cq_crowd;    /* walkers moved in lock-step (opaque) */
@@ -139,7 +150,8 @@ typedef struct {
                              rank-k update (the batched path closes a window after k accepted
                              moves, the per-move paths after k proposals); 0 = autotune: the
                              first run_vmc (or cq_crowd_autotune) times sweeps at k = 1, 2, 4,
-                             ..., min(32, n_up) and keeps the fastest */
+                             ..., min(32, n_up) and keeps the fastest (the whole-sweep path
+                             always uses k = 1) */
     int recompute_every;  /* sweeps between FP64 recomputes of the inverses (0 = never) */
     uint64_t seed;        /* Philox key of the move random numbers */
     uint32_t first_uid;   /* walker w of this crowd has uid first_uid + w (random streams) */
@@ -250,12 +262,17 @@ cq_status cq_crowd_get_dmc_moves(cq_crowd* c, int64_t* accepted, int64_t* propos
    k = 1, 2, 4, ..., min(32, n_up) and keep the fastest; *chosen_k (may be NULL)
    receives it.  The timed sweeps are ordinary sweeps of the chain (they advance
    the positions and the random-number step).  run_vmc calls it with one sweep
-   per candidate when the crowd has not been tuned.  Errors: CQ_EINVAL,
+   per candidate when the crowd has not been tuned.  On the whole-sweep path
+   (CQ_PATH_SWEEP) nothing is timed and k stays 1.  Errors: CQ_EINVAL,
    CQ_ESTATE (positions not set). */
 cq_status cq_crowd_autotune(cq_crowd* c, int sweeps_per_candidate, int* chosen_k);
 
 /* The delay rank in use (after autotuning, the chosen one). */
 cq_status cq_crowd_get_delay_rank(cq_crowd* c, int* k);
+
+/* The kernel path in use (cq_kernel_path; CQ_PATH_AUTO resolved at creation; for a
+   crowd of several systems, the first system's). */
+cq_status cq_crowd_get_path(cq_crowd* c, int* path);
 
 /* Diffusion Monte Carlo (paper Alg. 1 with a drift-diffusion proposal and
    reweighting / branching; Sec. II-A).  Runs n_generations

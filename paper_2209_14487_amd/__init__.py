@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libcrowdqmc.so")
 
 CQ_OK, CQ_EINVAL, CQ_ENOMEM, CQ_EDEVICE, CQ_ESINGULAR, CQ_ESTATE = range(6)
 CQ_FP64, CQ_MIXED = 0, 1
-PATHS = {"auto": 0, "multi": 1, "window": 2, "batch": 3}
+PATHS = {"auto": 0, "multi": 1, "window": 2, "batch": 3, "sweep": 4}
 KERNEL_VGL, KERNEL_RESOLVE, KERNEL_UPDATE, KERNEL_ENERGY, KERNEL_INVERSE, KERNEL_PROPOSE, KERNEL_VIRTUAL = range(7)
 KERNEL_NAMES = {"vgl": KERNEL_VGL, "resolve": KERNEL_RESOLVE, "update": KERNEL_UPDATE,
                 "energy": KERNEL_ENERGY, "inverse": KERNEL_INVERSE, "propose": KERNEL_PROPOSE,
@@ -62,6 +62,7 @@ _SIGS = {
     "cq_crowd_virtual_ratios": [_P, _P, _I, _P, _P, _P, _I],
     "cq_crowd_autotune": [_P, _I, _P],
     "cq_crowd_get_delay_rank": [_P, _P],
+    "cq_crowd_get_path": [_P, _P],
     "cq_crowd_get_uids": [_P, _P],
     "cq_crowd_recompute": [_P, _P],
     "cq_crowd_get_drift": [_P, _P, _P, _P],
@@ -353,6 +354,12 @@ class Crowd:
         k = ctypes.c_int()
         _check(lib().cq_crowd_get_delay_rank(self._h, ctypes.byref(k)))
         return k.value
+
+    def path(self) -> str:
+        """The kernel path in use ("multi", "window", "batch" or "sweep")."""
+        p = ctypes.c_int()
+        _check(lib().cq_crowd_get_path(self._h, ctypes.byref(p)))
+        return {v: k for k, v in PATHS.items()}[p.value]
 
     def virtual_ratios(self, offsets, out=None):
         """Ratio-only virtual moves of every electron to r_e + offsets[q] ([n_q][3]): returns

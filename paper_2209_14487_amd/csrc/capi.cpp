@@ -399,6 +399,16 @@ void enqueue_sweep(cq_crowd* c)
         cq::launch_sweep_end(c->prm, c->stream);
         return;
     }
+    if (c->path == CQ_PATH_SWEEP) {
+        timed_begin(c, CQ_KERNEL_VGL);
+        cq::launch_sweep<T>(v, c->stream);
+        timed_end(c, CQ_KERNEL_VGL);
+        timed_begin(c, CQ_KERNEL_ENERGY);
+        local_energy<T>(c, v, c->stream);
+        timed_end(c, CQ_KERNEL_ENERGY);
+        cq::launch_sweep_end(c->prm, c->stream);
+        return;
+    }
     if (c->path == CQ_PATH_WINDOW) {
         for (int spin = 0; spin < 2; ++spin)
             for (int a0 = 0; a0 < n; a0 += K) {
@@ -1032,8 +1042,17 @@ cq_status cq_crowd_create(const cq_system* const* systems, const int* walkers_pe
     int K = desc->delay_rank == 0 ? std::min(32, s->n_up) : desc->delay_rank;
     if (K < 1 || K > cq::kMaxDelay) return fail(CQ_EINVAL, "delay_rank must be 0..32");
     if (desc->recompute_every < 0) return fail(CQ_EINVAL, "recompute_every must be >= 0");
-    if (desc->kernel_path < CQ_PATH_AUTO || desc->kernel_path > CQ_PATH_BATCH)
+    if (desc->kernel_path < CQ_PATH_AUTO || desc->kernel_path > CQ_PATH_SWEEP)
         return fail(CQ_EINVAL, "unknown kernel_path");
+    // the whole-sweep path: N <= 64 (both inverses in LDS), N % 4 == 0, delay rank 1;
+    // the automatic choice for such systems unless a delay rank above 1 is asked for
+    const bool sweep_fits = s->n_up <= cq::kSweepMaxN && s->n_up % 4 == 0;
+    const bool sweep_k = desc->delay_rank == 0 || desc->delay_rank == 1;
+    if (desc->kernel_path == CQ_PATH_SWEEP && !(sweep_fits && sweep_k))
+        return fail(CQ_EINVAL, "the whole-sweep path needs N <= 64, N a multiple of 4 and delay rank 0 or 1");
+    const int path = desc->kernel_path != CQ_PATH_AUTO ? desc->kernel_path
+                                                        : (sweep_fits && sweep_k ? CQ_PATH_SWEEP : CQ_PATH_BATCH);
+    if (path == CQ_PATH_SWEEP) K = 1;
 
     if (desc->max_walkers < 0) return fail(CQ_EINVAL, "max_walkers must be >= 0");
     if (desc->streams < 0 || desc->streams > 2) return fail(CQ_EINVAL, "streams must be 0, 1 or 2");
@@ -1046,11 +1065,11 @@ cq_status cq_crowd_create(const cq_system* const* systems, const int* walkers_pe
     c->ne = 2 * s->n_up;
     c->K = K;
     c->Kcap = K;
-    c->autotune = desc->delay_rank == 0;
+    c->autotune = desc->delay_rank == 0 && path != CQ_PATH_SWEEP;
     c->prec = desc->precision;
     c->recompute_every = desc->recompute_every;
     c->use_graph = desc->use_graph;
-    c->path = desc->kernel_path != CQ_PATH_AUTO ? desc->kernel_path : CQ_PATH_BATCH;
+    c->path = path;
     c->Q = c->path == CQ_PATH_BATCH ? cq::batch_candidates(c->n, K) : K;
     c->QR = c->path == CQ_PATH_BATCH ? 2 * c->Q : c->Q;
     c->seed = desc->seed;
@@ -1221,6 +1240,11 @@ cq_status cq_crowd_set_positions(cq_crowd* c, const double* R, int on_device, ui
 // ordinary sweeps of the chain.
 static cq_status autotune_k(cq_crowd* c, int sweeps, int* chosen)
 {
+    if (c->path == CQ_PATH_SWEEP) {  // delay rank 1 by construction
+        c->tuned = true;
+        if (chosen) *chosen = c->K;
+        return CQ_OK;
+    }
     hipEvent_t a, b;
     HIP_TRY(hipEventCreate(&a));
     if (hipEventCreate(&b) != hipSuccess) {
@@ -1462,6 +1486,13 @@ cq_status cq_crowd_run_dmc_systems(cq_crowd* c, int n_generations, double tau, c
     std::vector<int> tgt(set.size());
     for (size_t s = 0; s < set.size(); ++s) tgt[s] = n_target ? n_target[s] : set[s]->W;
     return run_dmc_set(c, set, n_generations, tau, e_trial, tgt.data(), history);
+}
+
+cq_status cq_crowd_get_path(cq_crowd* c, int* path)
+{
+    if (!c || !path) return fail(CQ_EINVAL, "NULL argument");
+    *path = c->subs.empty() ? c->path : c->subs[0]->path;
+    return CQ_OK;
 }
 
 cq_status cq_crowd_get_delay_rank(cq_crowd* c, int* k)

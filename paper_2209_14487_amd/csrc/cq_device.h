@@ -193,6 +193,18 @@ __device__ __forceinline__ void xcd_map(int bid, int per_walker, int& w, int& pa
 
 inline int xcd_grid(int W, int per_walker) { return ((W + 7) / 8) * 8 * per_walker; }
 
+// Pointer into the constant address space: it marks memory as read-only for the
+// kernel's duration, and loads through it at a wave-uniform address become scalar
+// loads.
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T*;
+
+template <typename T>
+__device__ __forceinline__ cptr<T> as_const(const T* p)
+{
+    return (cptr<T>)p;
+}
+
 template <typename T>
 struct Vec16;  // 16-byte vector of T
 template <>

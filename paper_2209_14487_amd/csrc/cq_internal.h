@@ -34,6 +34,7 @@ namespace cq {
 constexpr int kMaxDelay = 32;
 constexpr int kMaxCand = 88;   // candidates per round of the batched path
 constexpr int kBlock = 256;
+constexpr int kSweepMaxN = 64;  // largest N of the whole-sweep path (both inverses in LDS)
 
 // Partial-sum slots of one move workgroup: 4 determinant dots, 5 per window
 // slot, then the Jastrow difference and gradient.
@@ -188,6 +189,8 @@ template <typename T> void launch_batch_vgl(const CrowdView<T>& v, int spin, int
 template <typename T> void launch_batch_jd(const CrowdView<T>& v, int spin, hipStream_t s);
 template <typename T> void launch_batch_pmat(const CrowdView<T>& v, int spin, hipStream_t s);
 template <typename T> void launch_batch_rows(const CrowdView<T>& v, int spin, hipStream_t s);
+int device_cu_count();
+template <typename T> void launch_sweep(const CrowdView<T>& v, hipStream_t s);
 template <typename T> void launch_batch_decide(const CrowdView<T>& v, int spin, int par, hipStream_t s);
 template <typename T> void launch_batch_cols(const CrowdView<T>& v, int spin, hipStream_t s);
 int batch_rounds(int n, int K);      // rounds per spin block (enough when every move is accepted)

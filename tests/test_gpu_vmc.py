@@ -88,8 +88,12 @@ def emulated_rho(o, R0, acc, uids=None, n_moves=None, recompute_every=0, sigma=0
     W = R0.shape[0]
     uids = range(W) if uids is None else uids
     close = "accepts" if path == "batch" else "proposals"
+    # the whole-sweep path applies each accepted move at once (Sherman-Morrison in FP64 from
+    # the FP32-stored values, stored back in FP32)
+    window, arith = (0, "fp64") if path == "sweep" else (k, "fp32")
     return np.stack([fp32_chain.replay(o, R0[i], int(u), acc[:, :, i], n_moves=n_moves, sigma=sigma,
-                                       recompute_every=recompute_every, window=k, close_after=close)
+                                       recompute_every=recompute_every, window=window, close_after=close,
+                                       arith=arith)
                      for i, u in enumerate(uids)], axis=-1)
 
 
@@ -154,9 +158,14 @@ def compare_fp64(gpu, ref, sweeps, ne, tol=1e-10):
 
 
 PATHS = ["multi", "window", "batch"]
+ALL_PATHS = PATHS + ["sweep"]  # the whole-sweep path runs delay rank 1 only
 
 
-@pytest.mark.parametrize("path", PATHS)
+def rank_for(path, k):
+    return 1 if path == "sweep" else k
+
+
+@pytest.mark.parametrize("path", ALL_PATHS)
 def test_c1_fp64_sherman_morrison_matches_oracle(path):
     """C1: 4+4 electrons, L=5, 16^3 plane-wave spline, 16 walkers, 200 sweeps, FP64, SM."""
     n, L, G, W, S = 4, 5.0, 16, 16, 200
@@ -175,8 +184,7 @@ def test_c1_fp64_sherman_morrison_matches_oracle(path):
     crowd.close()
 
 
-@pytest.mark.parametrize("path", PATHS)
-@pytest.mark.parametrize("k", [1, 4, 8, 32])
+@pytest.mark.parametrize("k,path", [(k, p) for p in PATHS for k in (1, 4, 8, 32)] + [(1, "sweep")])
 def test_c2_shape_fp64_delayed_ranks_match_oracle(k, path):
     """C2 shapes (32+32, L=10, 48^3 seeded table, Pade J2) on 61 walkers (ragged against the
     8-XCD mapping): Sherman-Morrison and rank-k delayed updates reproduce the oracle chain."""
@@ -196,7 +204,7 @@ def test_c2_shape_fp64_delayed_ranks_match_oracle(k, path):
 
 @pytest.mark.parametrize("k,recompute,path", [(1, 2, "window"), (8, 2, "window"), (32, 0, "window"),
                                               (8, 2, "multi"), (1, 2, "batch"), (8, 2, "batch"),
-                                              (32, 0, "batch")])
+                                              (32, 0, "batch"), (1, 2, "sweep"), (1, 0, "sweep")])
 def test_c2_mixed_precision_on_oracle_trajectory(k, recompute, path):
     """C2 mixed precision (FP32 table, FP32 inverse and dots, FP64 log|det| and sums) follows
     the oracle's decisions; its own ratios stay within 1e-4 relative of the FP64 oracle, its
@@ -221,7 +229,7 @@ def test_c2_mixed_precision_on_oracle_trajectory(k, recompute, path):
     crowd.close()
 
 
-@pytest.mark.parametrize("path", PATHS)
+@pytest.mark.parametrize("path", ALL_PATHS)
 def test_crowd_partition_is_bit_identical(path):
     """Splitting the walkers into crowds changes nothing (paper Sec. III: crowd size 1 is the
     per-walker driver, one crowd is the whole-population batch): FP64 results per walker are
@@ -234,7 +242,7 @@ def test_crowd_partition_is_bit_identical(path):
         out_R, out_ld, out_el = [], [], []
         lo = 0
         for p in parts:
-            c = cq.Crowd(g, p, precision="fp64", delay_rank=4, seed=7, first_uid=lo, path=path)
+            c = cq.Crowd(g, p, precision="fp64", delay_rank=rank_for(path, 4), seed=7, first_uid=lo, path=path)
             c.set_positions(R0[lo:lo + p])
             c.run_vmc(S, 0.5)
             out_R.append(c.positions())
@@ -253,7 +261,7 @@ def test_crowd_partition_is_bit_identical(path):
         assert np.array_equal(x, y)
 
 
-@pytest.mark.parametrize("path", PATHS)
+@pytest.mark.parametrize("path", ALL_PATHS)
 def test_graph_replay_equals_eager_launches(path):
     """The sweep captured once as a hipGraph and replayed gives the eager result bit for bit."""
     n, L, G, W, S = 32, 10.0, 48, 16, 3
@@ -261,8 +269,8 @@ def test_graph_replay_equals_eager_launches(path):
     R0 = start_positions(1002, W, 2 * n, L)
     res = []
     for use_graph in (False, True):
-        c = cq.Crowd(g, W, precision="mixed", delay_rank=8, recompute_every=2, seed=9, use_graph=use_graph,
-                     path=path)
+        c = cq.Crowd(g, W, precision="mixed", delay_rank=rank_for(path, 8), recompute_every=2, seed=9,
+                     use_graph=use_graph, path=path)
         c.set_positions(R0)
         for _ in range(S):
             c.run_vmc(1, 0.5)
@@ -342,17 +350,109 @@ def test_singular_start_is_reported():
     crowd.close()
 
 
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_recompute_reports_the_drift_of_the_kept_log_det(precision):
+    """cq_crowd_recompute's max_drift and cq_crowd_get_drift's per-walker record are
+    |log|det| kept by the update chain - log|det| of the fresh inversion| (the drift the
+    periodic FP64 recompute removes).  The fresh value is pinned to the oracle's LU of the
+    orbital rows at the crowd's final positions (FP32-evaluated rows in mixed precision, as
+    the path stores them), and the kept value is the chain's: so the drift is that of the
+    chain, about 1e-6..1e-4 in mixed precision and at rounding level in FP64."""
+    n, L, G, W, S, seed = 32, 10.0, 48, 16, 6, 1002
+    fp32 = precision == "mixed"
+    g, o = make_pair(n, L, G, seed, coef_seed=seed, fp64=not fp32, fp32=fp32)
+    crowd = cq.Crowd(g, W, precision=precision, delay_rank=8, recompute_every=0, seed=seed, path="batch")
+    crowd.set_positions(start_positions(seed, W, 2 * n, L))
+    crowd.run_vmc(S, 0.5)
+    kept, _ = crowd.logdet()
+    R = crowd.positions()
+    max_drift = crowd.recompute()
+    fresh, _ = crowd.logdet()
+    last, m, k = crowd.drift()
+    crowd.close()
+    g.close()
+    vgl = orc.orbital_vgl_f32 if fp32 else orc.orbital_vgl
+    ref = np.zeros((W, 2))
+    for w in range(W):
+        for s in range(2):
+            A = np.array([vgl(o, R[w, s * n + i], n)[0] for i in range(n)])
+            ref[w, s] = orc.lu_inverse(A)[1]
+    # the fresh log|det| is the oracle's: FP64 inversion of the same rows (in mixed precision the
+    # GPU's FP32 rows sum the 64 stencil terms in another order than the oracle's FP32 model, and
+    # those last-bit differences move log|det| by up to a few 1e-6: the mixed log|det| bar)
+    tol = 1e-4 if fp32 else 1e-10
+    assert np.all(np.abs(fresh - ref) <= tol * np.maximum(1.0, np.abs(ref)))
+    drift = np.abs(kept - fresh)
+    assert np.allclose(last, drift, rtol=0, atol=1e-15)
+    assert max_drift == pytest.approx(drift.max(), rel=0, abs=1e-15)
+    assert m == pytest.approx(drift.max(), rel=0, abs=1e-15) and k == 1
+    if fp32:
+        assert 1e-8 < drift.max() < 1e-3
+    else:
+        assert drift.max() < 1e-10
+
+
+@pytest.mark.parametrize("precision,n,L,G,W,S", [("fp64", 4, 5.0, 16, 9, 3), ("mixed", 8, 6.0, 24, 9, 3),
+                                                  ("fp64", 64, 12.0, 48, 5, 2), ("mixed", 64, 12.0, 48, 5, 2)])
+def test_sweep_path_sizes(precision, n, L, G, W, S):
+    """Whole-sweep path at its edges: one orbital group (N = 4 FP64, N = 8 FP32: a quad of
+    lanes per group), and the largest N = 64 (both inverses fill 64 KB of LDS in FP64).  FP64
+    matches the oracle's chain; mixed precision follows the oracle's decisions within the FP32
+    rounding model (Sherman-Morrison steps in FP64 from FP32-stored values), with the FP64
+    recompute after every sweep (without it the FP32 ratio errors of a sweep's ~100 accepted
+    moves at N = 64 add up in log|det| past the 1e-4 bar)."""
+    fp32 = precision == "mixed"
+    g, o = make_pair(n, L, G, 1005, coef_seed=1005, fp64=not fp32, fp32=fp32)
+    R0 = start_positions(1005, W, 2 * n, L)
+    ref = orc.vmc(o, R0, S, sigma=0.5)
+    crowd = cq.Crowd(g, W, precision=precision, delay_rank=1, recompute_every=1 if fp32 else 0, seed=1005,
+                     path="sweep")
+    if fp32:
+        gpu = run_gpu(crowd, R0, S, 0.5, forced=ref.acc)
+        emu = emulated_rho(o, R0, ref.acc, recompute_every=1, path="sweep")
+        mixed_ratio_check(gpu["rho"], ref.rho, emu, "sweep N=%d mixed" % n)
+        err = np.abs(gpu["logdet"] - ref.logdet) / np.maximum(1.0, np.abs(ref.logdet))
+        assert err.max() < 1e-4, err.max()
+    else:
+        gpu = run_gpu(crowd, R0, S, 0.5)
+        compare_fp64(gpu, ref, S, 2 * n)
+    crowd.close()
+
+
+def test_sweep_path_limits():
+    """The whole-sweep path refuses what it cannot hold (N > 64, a delay rank above 1) with
+    CQ_EINVAL; the automatic choice takes it for small N at delay rank 0 or 1 and the batched
+    path otherwise."""
+    for n, k in ((68, 1), (32, 4)):
+        g = cq.System(n, 10.0)
+        g.fill_philox(1, 8, 16)
+        with pytest.raises(cq.CqError) as ei:
+            cq.Crowd(g, 2, precision="fp64", delay_rank=k, seed=1, path="sweep")
+        assert ei.value.status == cq.CQ_EINVAL
+        g.close()
+    g = cq.System(32, 10.0)
+    g.fill_philox(1, 8, 16)
+    for k, path in ((1, "sweep"), (0, "sweep"), (8, "batch")):
+        c = cq.Crowd(g, 2, precision="fp64", delay_rank=k, seed=1)
+        assert c.path() == path
+        if path == "sweep":  # nothing to tune: the delay rank is 1 and no sweep runs
+            c.set_positions(start_positions(1, 2, 64, 10.0))
+            assert c.autotune(1) == 1 and c.acceptance()[1].sum() == 0
+        c.close()
+    g.close()
+
+
 def test_paths_agree():
-    """The per-move multi-workgroup path, the walker-resident window path and the batched-window
-    path compute the same chain: identical decisions, and ratios, log|det| and energies within
-    the FP64 parity bar (their sums are grouped differently, so they agree to rounding, not bit
-    for bit)."""
+    """The per-move multi-workgroup path, the walker-resident window path, the batched-window
+    path and the whole-sweep path compute the same chain: identical decisions, and ratios,
+    log|det| and energies within the FP64 parity bar (their sums are grouped differently, so
+    they agree to rounding, not bit for bit)."""
     n, L, G, W, S = 32, 10.0, 48, 20, 3
     g, _ = make_pair(n, L, G, 1002, coef_seed=1002)
     R0 = start_positions(1002, W, 2 * n, L)
     out = []
-    for path in PATHS:
-        c = cq.Crowd(g, W, precision="fp64", delay_rank=8, seed=1002, path=path)
+    for path in ALL_PATHS:
+        c = cq.Crowd(g, W, precision="fp64", delay_rank=rank_for(path, 8), seed=1002, path=path)
         out.append(run_gpu(c, R0, S, 0.5))
         c.close()
     b = out[0]
@@ -386,7 +486,7 @@ def test_autotuned_delay_rank_keeps_the_chain():
     n, L, G, W, S = 32, 10.0, 48, 16, 1
     g, o = make_pair(n, L, G, 1002, coef_seed=1002)
     R0 = start_positions(1002, W, 2 * n, L)
-    crowd = cq.Crowd(g, W, precision="fp64", delay_rank=0, seed=1002)
+    crowd = cq.Crowd(g, W, precision="fp64", delay_rank=0, seed=1002, path="batch")
     crowd.set_positions(R0)
     k = crowd.autotune(1)
     assert k in (1, 2, 4, 8, 16, 32) and crowd.delay_rank() == k
