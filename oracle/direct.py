@@ -72,13 +72,15 @@ class Direct:
     """Psi_T(R) = det A_up det A_dn exp(sum_{i<j} u(r_ij)), evaluated directly."""
 
     def __init__(self, n_up, n_dn, L, table=None, planewave=False, use_j2=False,
-                 a_par=0.25, a_anti=0.5, b=1.0, seed=0):
+                 a_par=0.25, a_anti=0.5, b=1.0, seed=0, ions=None, j1_a=-1.0, j1_b=1.0):
         self.n_up, self.n_dn, self.L = n_up, n_dn, L
         self.table = table
         self.planewave = planewave
         self.use_j2 = use_j2
         self.a_par, self.a_anti, self.b = a_par, a_anti, b
         self.seed = seed
+        self.ions = None if ions is None else np.asarray(ions, dtype=np.float64).reshape(-1, 3)
+        self.j1_a, self.j1_b = j1_a, j1_b
 
     @property
     def n_e(self):
@@ -97,16 +99,23 @@ class Direct:
         return out
 
     def lnj(self, R):
-        if not self.use_j2:
-            return 0.0
+        """ln J: the Pade pairs (if any) plus the one-body terms a1 r / (1 + b1 r) of every
+        electron with every centre (minimum image)."""
         s = 0.0
-        for i in range(self.n_e):
-            for j in range(i + 1, self.n_e):
-                d = R[i] - R[j]
+        if self.use_j2:
+            for i in range(self.n_e):
+                for j in range(i + 1, self.n_e):
+                    d = R[i] - R[j]
+                    d = d - self.L * np.rint(d / self.L)
+                    r = np.sqrt(d @ d)
+                    a = self.a_par if (i < self.n_up) == (j < self.n_up) else self.a_anti
+                    s += a * r / (1 + self.b * r)
+        if self.ions is not None:
+            for i in range(self.n_e):
+                d = R[i][None, :] - self.ions
                 d = d - self.L * np.rint(d / self.L)
-                r = np.sqrt(d @ d)
-                a = self.a_par if (i < self.n_up) == (j < self.n_up) else self.a_anti
-                s += a * r / (1 + self.b * r)
+                r = np.sqrt((d * d).sum(axis=1))
+                s += float(np.sum(self.j1_a * r / (1 + self.j1_b * r)))
         return s
 
     def log_psi(self, R):

@@ -83,6 +83,9 @@ class OrSystem(ctypes.Structure):
         ("j2_a_par", ctypes.c_double), ("j2_a_anti", ctypes.c_double), ("j2_b", ctypes.c_double),
         ("seed", ctypes.c_uint64),
         ("use_coulomb", ctypes.c_int),
+        ("n_ions", ctypes.c_int),
+        ("ions", ctypes.c_void_p),
+        ("j1_a", ctypes.c_double), ("j1_b", ctypes.c_double),
     ]
 
 
@@ -107,6 +110,9 @@ class System:
     j2_b: float = 1.0
     seed: int = 0
     use_coulomb: bool = False
+    ions: Optional[np.ndarray] = None   # [n_ions][3] one-body Jastrow centres, or None
+    j1_a: float = -1.0
+    j1_b: float = 1.0
     _c: OrSystem = field(default=None, repr=False)
 
     @property
@@ -116,12 +122,17 @@ class System:
     def c(self) -> OrSystem:
         if self.table is not None:
             self.table = np.ascontiguousarray(self.table, dtype=np.float64)
+        if self.ions is not None:
+            self.ions = np.ascontiguousarray(self.ions, dtype=np.float64).reshape(-1, 3)
         self._c = OrSystem(self.n_up, self.n_dn, float(self.L), int(self.G), int(self.n_orb),
                            int(self.orb_kind),
                            self.table.ctypes.data if self.table is not None else None,
                            int(self.coef_seed), int(self.coef_fp32), int(self.use_j2),
                            float(self.j2_a_par), float(self.j2_a_anti), float(self.j2_b),
-                           int(self.seed), int(self.use_coulomb))
+                           int(self.seed), int(self.use_coulomb),
+                           0 if self.ions is None else int(self.ions.shape[0]),
+                           self.ions.ctypes.data if self.ions is not None else None,
+                           float(self.j1_a), float(self.j1_b))
         return self._c
 
 

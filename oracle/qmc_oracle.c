@@ -15,7 +15,8 @@
  *     of the paper's multi-threaded CPU driver (Alg. 2).
  *   - the paper does not define the wavefunction or the update formulas; those
  *     are textbook mathematics: uniform cubic B-splines (de Boor), a product of
- *     one Slater determinant per spin and a two-body Pade Jastrow factor, the
+ *     one Slater determinant per spin, a two-body Pade Jastrow factor and a
+ *     one-body Pade factor around fixed centres, the
  *     Sherman-Morrison rank-1 update of the inverse, LU with partial pivoting,
  *     importance-sampled DMC (Reynolds, Ceperley, Alder, Lester 1982) and the
  *     Philox4x32-10 counter-based generator (Salmon, Moraes, Dror, Shaw, SC'11).
@@ -148,6 +149,9 @@ typedef struct {
     double j2_a_par, j2_a_anti, j2_b;
     uint64_t seed;        /* key of the move generator */
     int use_coulomb;      /* add the Ewald electron-electron energy to E_L */
+    int n_ions;           /* one-body Jastrow centres (0: no one-body Jastrow) */
+    const double* ions;   /* [n_ions][3] */
+    double j1_a, j1_b;    /* u1(r) = a r / (1 + b r) */
 } or_system;
 
 static double coef_at(const or_system* s, int ix, int iy, int iz, int n)
@@ -326,29 +330,53 @@ static void pade(double a, double b, double r, double* u, double* du, double* d2
     *d2u = -2.0 * a * b / (q * q * q);
 }
 
-/* Full ln J of a configuration (used by the tests as brute force). */
+/* One-body Pade Jastrow: ln J1 = + sum_i sum_I u1(|r_i - R_I|), u1(r) = a r / (1 + b r)
+   with the same Pade form as the pairs and its own a, b; minimum-image distance to each
+   centre R_I.  u1 of one electron at r summed over the centres, with its gradient
+   sum u1'(d) d/|d| and Laplacian sum u1'' + 2 u1'/d. */
+static double j1_at(const or_system* s, const double* r, double grad[3], double* lap)
+{
+    double sum = 0.0;
+    for (int I = 0; I < s->n_ions; ++I) {
+        double d[3], u, du, d2u;
+        min_image(r, &s->ions[3 * I], s->L, d);
+        double rr = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        pade(s->j1_a, s->j1_b, rr, &u, &du, &d2u);
+        sum += u;
+        if (grad)
+            for (int c = 0; c < 3; ++c) grad[c] += du * d[c] / rr;
+        if (lap) *lap += d2u + 2.0 * du / rr;
+    }
+    return sum;
+}
+
+/* Full ln J of a configuration (used by the tests as brute force): the pairs, then
+   the one-body terms. */
 double or_lnj(const or_system* s, const double* R)
 {
     int ne = s->n_up + s->n_dn;
     double sum = 0;
-    if (!s->use_j2) return 0.0;
-    for (int i = 0; i < ne; ++i)
-        for (int j = i + 1; j < ne; ++j) {
-            double d[3], u, du, d2u;
-            min_image(&R[3 * i], &R[3 * j], s->L, d);
-            pade(pade_a(s, i, j), s->j2_b, sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]), &u, &du, &d2u);
-            sum += u;
-        }
+    if (s->use_j2)
+        for (int i = 0; i < ne; ++i)
+            for (int j = i + 1; j < ne; ++j) {
+                double d[3], u, du, d2u;
+                min_image(&R[3 * i], &R[3 * j], s->L, d);
+                pade(pade_a(s, i, j), s->j2_b, sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]), &u, &du, &d2u);
+                sum += u;
+            }
+    for (int i = 0; i < ne; ++i) sum += j1_at(s, &R[3 * i], NULL, NULL);
     return sum;
 }
 
 /* Gradient and Laplacian of ln J with respect to electron e at position re,
-   all other electrons at R.  grad = sum_m u'(d) d/|d|, lap = sum_m u'' + 2u'/d. */
+   all other electrons at R.  grad = sum_m u'(d) d/|d|, lap = sum_m u'' + 2u'/d,
+   then the one-body terms of e at re. */
 static void j2_grad_lap(const or_system* s, const double* R, int e, const double* re,
                         double grad[3], double* lap)
 {
     int ne = s->n_up + s->n_dn;
     grad[0] = grad[1] = grad[2] = 0; *lap = 0;
+    j1_at(s, re, grad, lap);
     if (!s->use_j2) return;
     for (int m = 0; m < ne; ++m) {
         if (m == e) continue;
@@ -361,12 +389,13 @@ static void j2_grad_lap(const or_system* s, const double* R, int e, const double
     }
 }
 
-/* ln J(R') - ln J(R) when electron e moves from R[e] to rnew. */
+/* ln J(R') - ln J(R) when electron e moves from R[e] to rnew: the one-body change,
+   then the pairs. */
 static double j2_delta(const or_system* s, const double* R, int e, const double* rnew)
 {
     int ne = s->n_up + s->n_dn;
-    double sum = 0;
-    if (!s->use_j2) return 0.0;
+    double sum = j1_at(s, rnew, NULL, NULL) - j1_at(s, &R[3 * e], NULL, NULL);
+    if (!s->use_j2) return sum;
     for (int m = 0; m < ne; ++m) {
         if (m == e) continue;
         double d[3], u1, u0, du, d2u;

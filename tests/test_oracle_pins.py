@@ -216,10 +216,17 @@ def test_lu_inverse_logdet_sign():
 
 # ------------------------------------------------------- chain vs brute force
 
-def _tiny_system(n, G=8, L=4.0, j2=True, seed=11):
+# one-body Jastrow centres for the pins (a1 < 0: the electrons are drawn to them)
+J1_IONS = np.array([[0.7, 1.1, 2.9], [3.1, 2.6, 0.4], [1.9, 3.7, 1.6]])
+J1_A, J1_B = -0.8, 1.3
+
+
+def _tiny_system(n, G=8, L=4.0, j2=True, seed=11, j1=False):
     tab = np.random.default_rng(seed).uniform(-1, 1, (G, G, G, n))
-    s = orc.System(n, n, L, G=G, n_orb=n, orb_kind=orc.ORB_TABLE, table=tab, use_j2=j2, seed=seed)
-    d = Direct(n, n, L, table=tab, use_j2=j2, seed=seed)
+    ions = J1_IONS if j1 else None
+    s = orc.System(n, n, L, G=G, n_orb=n, orb_kind=orc.ORB_TABLE, table=tab, use_j2=j2, seed=seed, ions=ions,
+                   j1_a=J1_A, j1_b=J1_B)
+    d = Direct(n, n, L, table=tab, use_j2=j2, seed=seed, ions=ions, j1_a=J1_A, j1_b=J1_B)
     return s, d
 
 
@@ -279,12 +286,13 @@ def test_det_ratio_refined_matches_direct_determinants():
         assert abs(orc.det_ratio_refined(s, R, e, rnew) - ref) <= 1e-12 * max(1.0, abs(ref))
 
 
-@pytest.mark.parametrize("n,j2", [(1, True), (2, False), (3, True)])
-def test_vmc_chain_matches_direct_determinants(n, j2):
+@pytest.mark.parametrize("n,j2,j1", [(1, True, False), (2, False, False), (3, True, False), (2, False, True),
+                                     (3, True, True)])
+def test_vmc_chain_matches_direct_determinants(n, j2, j1):
     """P4 / P7 / P10: Sherman-Morrison ratios equal det(A')/det(A) from two LUs, the Jastrow
-    ratio equals the brute-force difference of full pair sums, the accept sequence is the same,
-    and the accumulated log|det| equals slogdet of the final matrices."""
-    s, d = _tiny_system(n, j2=j2)
+    ratio equals the brute-force difference of full pair (and one-body) sums, the accept
+    sequence is the same, and the accumulated log|det| equals slogdet of the final matrices."""
+    s, d = _tiny_system(n, j2=j2, j1=j1)
     R0 = start_positions(77, 3, 2 * n, s.L)
     sweeps = 6
     res = orc.vmc(s, R0, sweeps, sigma=0.6)
@@ -317,11 +325,12 @@ def test_inverse_after_sweeps_matches_direct_inverse():
             assert err < 1e-11
 
 
-def test_local_energy_matches_finite_differences():
+@pytest.mark.parametrize("j1", [False, True])
+def test_local_energy_matches_finite_differences(j1):
     """Local energy: the kinetic local energy formula agrees with -1/2 sum lap Psi / Psi by finite
-    differences of the directly evaluated wavefunction (splines + J2)."""
+    differences of the directly evaluated wavefunction (splines + J2, and the one-body Jastrow)."""
     n = 2
-    s, d = _tiny_system(n, G=8, L=4.0, j2=True, seed=13)
+    s, d = _tiny_system(n, G=8, L=4.0, j2=True, seed=13, j1=j1)
     R0 = start_positions(79, 3, 2 * n, s.L)
     res = orc.vmc(s, R0, 2, sigma=0.5)
     for w in range(3):
@@ -377,6 +386,34 @@ def test_two_electron_jastrow_closed_form():
     # minimum image: a separation of L - r is the same pair at distance r
     R1 = np.array([[0.5, 0.5, 0.5], [0.5 + L - 1.5, 0.5, 0.5]])
     assert abs(orc.lnj(s, R1) - a * 1.5 / 2.5) < 1e-14
+
+
+def test_one_body_jastrow_closed_form():
+    """One-body Jastrow, one centre, one up and one down electron, constant orbital, no pair term:
+    ln J = sum_i u1(r_i) with u1 = a r / (1 + b r), and E_L = sum_i -1/2 (u1'' + 2 u1'/r_i + u1'^2)
+    with u1' = a/(1+br)^2, u1'' = -2ab/(1+br)^3, for distances below L/2; a centre seen through the
+    box boundary counts at its minimum-image distance."""
+    G, L = 4, 10.0
+    tab = np.ones((G, G, G, 1))
+    a, b = -1.2, 0.7
+    ion = np.array([[2.0, 5.0, 5.0]])
+    s = orc.System(1, 1, L, G=G, n_orb=1, orb_kind=orc.ORB_TABLE, table=tab, use_j2=False, seed=5, ions=ion,
+                   j1_a=a, j1_b=b)
+
+    def parts(r):
+        up = a / (1 + b * r) ** 2
+        upp = -2 * a * b / (1 + b * r) ** 3
+        return a * r / (1 + b * r), -0.5 * (upp + 2 * up / r + up * up)
+
+    for r1, r2 in ((0.4, 3.0), (1.5, 4.6), (2.7, 0.9)):
+        R = np.array([[[2.0 + r1, 5.0, 5.0], [2.0, 5.0 - r2, 5.0]]])
+        _, _, el, _ = orc.setup(s, R)
+        (l1, e1), (l2, e2) = parts(r1), parts(r2)
+        assert abs(el[0] - (e1 + e2)) < 1e-13
+        assert abs(orc.lnj(s, R[0]) - (l1 + l2)) < 1e-15
+    # through the boundary: x = 2 - 1.5 + L sits 1.5 from the centre
+    R = np.array([[2.0 - 1.5 + L, 5.0, 5.0], [2.0, 5.0, 5.0 + 0.8]])
+    assert abs(orc.lnj(s, R) - (parts(1.5)[0] + parts(0.8)[0])) < 1e-14
 
 
 def test_metropolis_always_accepts_when_ratio_is_one():
@@ -461,11 +498,13 @@ def test_dmc_branching_bookkeeping():
     assert np.allclose(res.e_t, res.e_est - np.log(res.pop / 20.0) / 0.05, atol=1e-12)
 
 
-def test_dmc_drift_matches_finite_differences():
+@pytest.mark.parametrize("j1", [False, True])
+def test_dmc_drift_matches_finite_differences(j1):
     """The DMC drift grad ln|Psi_T| (determinant part from the inverse column and gradient row,
-    plus the Jastrow gradient) agrees with central differences of the direct ln|Psi|."""
+    plus the Jastrow gradient, one-body terms included) agrees with central differences of the
+    direct ln|Psi|."""
     n = 3
-    s, d = _tiny_system(n, G=8, L=4.0, j2=True, seed=16)
+    s, d = _tiny_system(n, G=8, L=4.0, j2=True, seed=16, j1=j1)
     R = start_positions(82, 1, 2 * n, s.L)[0]
     for e in range(2 * n):
         v = orc.drift(s, R, e)
