@@ -128,6 +128,16 @@ cq_status cq_system_fill_bspline_philox(cq_system* sys, uint64_t seed, int elem_
    a_anti for opposite spins.  Without this call the Jastrow factor is 1. */
 cq_status cq_system_load_pade_j2(cq_system* sys, double a_par, double a_anti, double b);
 
+/* One-body Pade Jastrow around fixed centres (the electron-ion factor of a Slater-Jastrow
+   wavefunction, part of the local-energy step of Alg. 1):
+     ln J1 = + sum_i sum_I u1(|r_i - R_I|),  u1(r) = a r / (1 + b r),
+   minimum-image distances.  centres: host array [n_centres][3] (bohr), copied;
+   0 <= n_centres <= 64 (0 removes the factor); a finite, b >= 0.  It enters every
+   move's ratio, the DMC drift and the local energy, in FP64 in both precisions.  Call it
+   before creating crowds of the system.  Errors: CQ_EINVAL (bad arguments, nothing
+   changed), CQ_EDEVICE. */
+cq_status cq_system_load_pade_j1(cq_system* sys, const double* centres, int n_centres, double a, double b);
+
 /* Add the electron-electron Coulomb energy to the local energy (enable = 1; 0 removes it):
    the electrons (charge -1) in the periodic box with a uniform neutralising background, by
    Ewald summation,

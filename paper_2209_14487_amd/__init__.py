@@ -51,6 +51,7 @@ _SIGS = {
     "cq_system_load_bspline": [_P, _P, _I, _I, _I, _I, _I, _I],
     "cq_system_fill_bspline_philox": [_P, ctypes.c_uint64, _I, _I, _I],
     "cq_system_load_pade_j2": [_P, ctypes.c_double, ctypes.c_double, ctypes.c_double],
+    "cq_system_load_pade_j1": [_P, _P, ctypes.c_int, ctypes.c_double, ctypes.c_double],
     "cq_system_set_coulomb": [_P, _I],
     "cq_system_destroy": [_P],
     "cq_crowd_create": [_P, _P, _I, _P, _P],
@@ -252,6 +253,11 @@ class System:
 
     def load_j2(self, a_par=0.25, a_anti=0.5, b=1.0):
         _check(lib().cq_system_load_pade_j2(self._h, a_par, a_anti, b))
+
+    def load_j1(self, centres, a, b):
+        """One-body Pade Jastrow a r / (1 + b r) around the centres [n][3] (n = 0 removes it)."""
+        c = np.ascontiguousarray(np.asarray(centres, dtype=np.float64).reshape(-1, 3))
+        _check(lib().cq_system_load_pade_j1(self._h, c.ctypes.data if c.size else None, c.shape[0], a, b))
 
     def set_coulomb(self, enable: bool = True):
         """Include the Ewald electron-electron energy in E_L of crowds created afterwards."""

@@ -47,6 +47,10 @@ struct cq_system {
     bool owned[2] = {false, false};
     int use_j2 = 0;
     double a_par = 0.0, a_anti = 0.0, b = 1.0;
+    // one-body Jastrow (cq_system_load_pade_j1): centres on the device
+    double* ions = nullptr;
+    int n_ions = 0;
+    double j1_a = 0.0, j1_b = 1.0;
     // Ewald electron-electron energy in E_L (cq_system_set_coulomb)
     int coulomb = 0, nmax = 0, nk = 0;
     double alpha = 0.0;
@@ -232,6 +236,10 @@ cq::CrowdView<T> view(const cq_crowd* c)
     v.a_par = c->sys->a_par;
     v.a_anti = c->sys->a_anti;
     v.b = c->sys->b;
+    v.ions = c->sys->ions;
+    v.n_ions = c->sys->n_ions;
+    v.j1_a = c->sys->j1_a;
+    v.j1_b = c->sys->j1_b;
     v.prm = c->prm;
     v.rec_rho = c->rec_rho;
     v.rec_dlnj = c->rec_dlnj;
@@ -891,6 +899,35 @@ cq_status cq_system_load_pade_j2(cq_system* s, double a_par, double a_anti, doub
     return CQ_OK;
 }
 
+cq_status cq_system_load_pade_j1(cq_system* s, const double* centres, int n_centres, double a, double b)
+{
+    if (!s) return fail(CQ_EINVAL, "system is NULL");
+    if (n_centres < 0 || n_centres > cq::kMaxIons)
+        return fail(CQ_EINVAL, "n_centres must be 0.." + std::to_string(cq::kMaxIons));
+    if (n_centres > 0 && !centres) return fail(CQ_EINVAL, "centres is NULL");
+    if (!std::isfinite(a) || !(b >= 0.0) || !std::isfinite(b))
+        return fail(CQ_EINVAL, "Jastrow parameters must be finite, b >= 0");
+    for (int i = 0; i < 3 * n_centres; ++i)
+        if (!std::isfinite(centres[i])) return fail(CQ_EINVAL, "centre coordinates must be finite");
+    if (n_centres == 0) {
+        s->n_ions = 0;
+        return CQ_OK;
+    }
+    double* d = nullptr;
+    HIP_TRY(hipMalloc(&d, sizeof(double) * 3 * n_centres));
+    const hipError_t e = hipMemcpy(d, centres, sizeof(double) * 3 * n_centres, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(d);
+        return fail(CQ_EDEVICE, std::string("hipMemcpy: ") + hipGetErrorString(e));
+    }
+    if (s->ions) (void)hipFree(s->ions);
+    s->ions = d;
+    s->n_ions = n_centres;
+    s->j1_a = a;
+    s->j1_b = b;
+    return CQ_OK;
+}
+
 cq_status cq_system_set_coulomb(cq_system* s, int enable)
 {
     if (!s) return fail(CQ_EINVAL, "system is NULL");
@@ -934,6 +971,7 @@ void cq_system_destroy(cq_system* s)
     if (!s) return;
     if (s->kvec) (void)hipFree(s->kvec);
     if (s->kfac) (void)hipFree(s->kfac);
+    if (s->ions) (void)hipFree(s->ions);
     for (int i = 0; i < 2; ++i)
         if (s->owned[i]) (void)hipFree(s->table[i]);
     delete s;

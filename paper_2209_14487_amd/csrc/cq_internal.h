@@ -34,7 +34,8 @@ namespace cq {
 constexpr int kMaxDelay = 32;
 constexpr int kMaxCand = 88;   // candidates per round of the batched path
 constexpr int kBlock = 256;
-constexpr int kSweepMaxN = 64;  // largest N of the whole-sweep path (both inverses in LDS)
+constexpr int kSweepMaxN = 64;
+constexpr int kMaxIons = 64;    // centres of the one-body Jastrow  // largest N of the whole-sweep path (both inverses in LDS)
 
 // Partial-sum slots of one move workgroup: 4 determinant dots, 5 per window
 // slot, then the Jastrow difference and gradient.
@@ -104,6 +105,9 @@ struct CrowdView {
     uint64_t seed;
     int use_j2;
     double a_par, a_anti, b;
+    const double* ions;  // [n_ions][3] centres of the one-body Jastrow (n_ions = 0: none)
+    int n_ions;
+    double j1_a, j1_b;
     Params* prm;
     double* rec_rho;
     double* rec_dlnj;

@@ -51,6 +51,7 @@
 
 #include "cq_device.h"
 #include "cq_internal.h"
+#include "cq_jastrow.h"
 #include "cq_stencil.h"
 
 namespace cq {
@@ -264,7 +265,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
 
 // Jastrow sums of a round's new candidates [ev, min(dec + Q, n)) against the
 // positions after the previous round:
-//     dlnJ_e = sum_{i != e} u(|r'_e - r_i|) - u(|r_e - r_i|).
+//     dlnJ_e = sum_{i != e} u(|r'_e - r_i|) - u(|r_e - r_i|)
+//              + sum_I u1(|r'_e - R_I|) - u1(|r_e - R_I|)     (one-body terms, FP64).
 // The coordinate differences are taken in FP64 and each pair term in the
 // precision of the path (FP32 terms in mixed precision, like the ratios); the
 // sums are FP64.  One workgroup per walker and group of kJdCand candidates;
@@ -304,7 +306,7 @@ __global__ __launch_bounds__(kBlock) void k_jd(CrowdView<T> v, int spin)
     const int nc = end - a0 < kJdCand ? end - a0 : kJdCand;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const double* Rw = v.R + (size_t)w * ne * 3;
-    if (!v.use_j2) {
+    if (!v.use_j2 && !v.n_ions) {
         if (tid < nc) v.jd[(size_t)w * QR + (a0 + tid) % QR] = 0.0;
         return;
     }
@@ -320,7 +322,7 @@ __global__ __launch_bounds__(kBlock) void k_jd(CrowdView<T> v, int spin)
 #pragma unroll
     for (int c = 0; c < kJdCand; ++c) dj[c] = 0.0;
     const int self = spin * n + a0;
-    for (int i = tid; i < ne; i += kBlock) {
+    for (int i = tid; v.use_j2 && i < ne; i += kBlock) {
         const double ri[3] = {Rw[(size_t)i * 3], Rw[(size_t)i * 3 + 1], Rw[(size_t)i * 3 + 2]};
         const T aa = (T)(((i >= n) == (spin != 0)) ? v.a_par : v.a_anti);
 #pragma unroll
@@ -329,6 +331,10 @@ __global__ __launch_bounds__(kBlock) void k_jd(CrowdView<T> v, int spin)
             dj[c] += i == self + c ? 0.0 : (double)d;  // the candidate's own electron is not a pair
         }
     }
+    // one-body terms (FP64), the centres shared out over the threads
+#pragma unroll
+    for (int c = 0; c < kJdCand; ++c)
+        if (v.n_ions) dj[c] += j1_delta(v, s_rp[c], s_re[c], tid, kBlock);
 #pragma unroll
     for (int c = 0; c < kJdCand; ++c) {
         const double t = wave_sum(dj[c]);

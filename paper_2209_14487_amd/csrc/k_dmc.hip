@@ -29,6 +29,7 @@
 // prefix sum run in population order (one thread), as the definition reads.
 #include "cq_device.h"
 #include "cq_internal.h"
+#include "cq_jastrow.h"
 
 namespace cq {
 
@@ -72,14 +73,19 @@ __device__ __forceinline__ void dmc_stencil(const CrowdView<T>& v, const double 
 }
 
 // Jastrow gradient of electron e at position r against the current positions of
-// the other electrons, and (with r0) the difference ln J(r) - ln J(r0); this
-// thread's share of the electrons (tid, tid + nt, ...).
+// the other electrons and the one-body centres, and (with r0) the difference
+// ln J(r) - ln J(r0); this thread's share of the electrons and centres (tid, tid + nt, ...).
 template <typename T>
 __device__ __forceinline__ void j2_part(const CrowdView<T>& v, int w, int e, const double r[3], const double* r0,
                                         int tid, int nt, double g[3], double& dj)
 {
     const int spin = e >= v.n;
-    for (int m = tid; m < v.ne; m += nt) {
+    if (v.n_ions) {
+        double lap = 0.0;
+        (void)j1_at(v, r, tid, nt, g, lap);
+        if (r0) dj += j1_delta(v, r, r0, tid, nt);
+    }
+    for (int m = tid; v.use_j2 && m < v.ne; m += nt) {
         if (m == e) continue;
         const double* rm = v.R + ((size_t)w * v.ne + m) * 3;
         const double aa = ((m >= v.n) == (spin != 0)) ? v.a_par : v.a_anti;
@@ -166,7 +172,7 @@ __device__ __forceinline__ void window_dmc_body(const CrowdView<T>& v, const int
             }
         }
         double jg[3] = {0.0, 0.0, 0.0}, dummy = 0.0;
-        if (v.use_j2) j2_part(v, w, e, re, nullptr, tid, nt, jg, dummy);
+        if (v.use_j2 || v.n_ions) j2_part(v, w, e, re, nullptr, tid, nt, jg, dummy);
         __syncthreads();
         // window dots, one wave per slot: y_m = u_m . c0, gm_k = g_k . c_m
         for (int m = wave; m < cnt; m += nw) {
@@ -292,7 +298,7 @@ __device__ __forceinline__ void window_dmc_body(const CrowdView<T>& v, const int
             }
         }
         double jg2[3] = {0.0, 0.0, 0.0}, dj = 0.0;
-        if (v.use_j2) j2_part(v, w, e, rp, re, tid, nt, jg2, dj);
+        if (v.use_j2 || v.n_ions) j2_part(v, w, e, rp, re, tid, nt, jg2, dj);
         __syncthreads();
         // window dots, one wave per slot: x_m = u . c_m, xg_k = grad_k u . c_m
         for (int m = wave; m < cnt; m += nw) {

@@ -19,6 +19,7 @@
 
 #include "cq_device.h"
 #include "cq_internal.h"
+#include "cq_jastrow.h"
 
 namespace cq {
 
@@ -489,6 +490,15 @@ __global__ __launch_bounds__(kBlock) void k_move(CrowdView<T> v, int e, int prev
             jv[2] += f * d1[1];
             jv[3] += f * d1[2];
         }
+    }
+    if (v.n_ions && c == 0) {  // one-body terms in the first chunk, centres over the threads
+        double re[3], g[3] = {0.0, 0.0, 0.0}, lap = 0.0;
+        for (int k = 0; k < 3; ++k) re[k] = v.R[((size_t)w * v.ne + e) * 3 + k];
+        jv[0] += j1_delta(v, rp, re, tid, kBlock);
+        (void)j1_at(v, rp, tid, kBlock, g, lap);
+        jv[1] += g[0];
+        jv[2] += g[1];
+        jv[3] += g[2];
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) jv[k] = wave_sum(jv[k]);

@@ -11,6 +11,7 @@
 //   u       = phi(r'), grad, Laplacian            (tricubic B-spline, 64 points)
 //   rho     = u . M[a]                            (exact products, FP64 sum)
 //   dlnJ    = sum_{m != e} u(|r' - r_m|) - u(|r_e - r_m|)   (FP64)
+//             + sum_I u1(|r' - R_I|) - u1(|r_e - R_I|)   (one-body terms)
 //   accept  if u_e < rho^2 exp(2 dlnJ)
 //   update  M[b] <- M[b] - ((u . M[b]) - delta_ab) / rho * M_old[a]   for every b
 //           (FP64 from the stored values, then stored in T)
@@ -26,6 +27,7 @@
 // them); the inverses and positions go back at the end of the sweep.
 #include "cq_device.h"
 #include "cq_internal.h"
+#include "cq_jastrow.h"
 #include "cq_stencil.h"
 
 namespace cq {
@@ -174,8 +176,9 @@ __global__ __launch_bounds__(kBlock) void k_sweep(CrowdView<T> v, int B)
                     pade(aa, v.b, sqrt(d0[0] * d0[0] + d0[1] * d0[1] + d0[2] * d0[2]), u0j, du, d2u);
                     dj += u1 - u0j;
                 }
-                dj = wave_sum(dj);
             }
+            if (v.n_ions) dj += j1_delta(v, rp, s_R[e], lane, 64);
+            if (v.use_j2 || v.n_ions) dj = wave_sum(dj);
             const double prob = rho * rho * exp(2.0 * dj);
             int acc = s_u[m] < prob;
             const size_t ri = ((size_t)rs * ne + e) * v.Wcap + w;

@@ -20,6 +20,7 @@
 
 #include "cq_device.h"
 #include "cq_internal.h"
+#include "cq_jastrow.h"
 
 namespace cq {
 
@@ -318,6 +319,13 @@ __global__ __launch_bounds__(kBlock) void k_energy_rows(CrowdView<T> v)
                 }
             }
         }
+    }
+    if (v.n_ions) {  // one-body terms of the electron, the centres over the lanes
+        const double* re = v.R + ((size_t)w * v.ne + e) * 3;
+        const double r3[3] = {re[0], re[1], re[2]};
+        (void)j1_at(v, r3, lane, 64, gu, lu);
+    }
+    if (v.use_j2 || v.n_ions) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) gu[k] = wave_sum(gu[k]);
         lu = wave_sum(lu);

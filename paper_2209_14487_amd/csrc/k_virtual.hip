@@ -16,6 +16,7 @@
 // summed once.  Sums over threads: wave sums, then waves in a fixed order.
 #include "cq_device.h"
 #include "cq_internal.h"
+#include "cq_jastrow.h"
 
 namespace cq {
 
@@ -87,12 +88,15 @@ __global__ __launch_bounds__(kBlock) void k_virtual(CrowdView<T> v, const double
     const T L_T = (T)v.L;
     (void)L_T;
     double j_old = 0.0;
-    if (v.use_j2) {
-        for (int m = tid; m < ne; m += kBlock) {
+    const bool jas = v.use_j2 || v.n_ions;
+    if (jas) {
+        for (int m = tid; v.use_j2 && m < ne; m += kBlock) {
             if (m == e) continue;
             const T a = (T)(((m >= n) == (spin != 0)) ? v.a_par : v.a_anti);
             j_old += (double)pade_u<T>(a, (T)v.b, pair_dist<T>(re, Rw + 3 * m, v.L));
         }
+        double g[3] = {0.0, 0.0, 0.0}, lap = 0.0;  // one-body terms (FP64), centres over the threads
+        if (v.n_ions) j_old += j1_at(v, re, tid, kBlock, g, lap);
         j_old = vblock_sum(j_old, s_red, lane, wave, nw);
     }
     for (int q = 0; q < nq; ++q) {
@@ -136,14 +140,16 @@ __global__ __launch_bounds__(kBlock) void k_virtual(CrowdView<T> v, const double
         }
         const double rho = vblock_sum(part, s_red, lane, wave, nw);
         double dj = 0.0;
-        if (v.use_j2) {
+        if (jas) {
             const double rq[3] = {s_rq[0], s_rq[1], s_rq[2]};
             double jn = 0.0;
-            for (int m = tid; m < ne; m += kBlock) {
+            for (int m = tid; v.use_j2 && m < ne; m += kBlock) {
                 if (m == e) continue;
                 const T a = (T)(((m >= n) == (spin != 0)) ? v.a_par : v.a_anti);
                 jn += (double)pade_u<T>(a, (T)v.b, pair_dist<T>(rq, Rw + 3 * m, v.L));
             }
+            double g[3] = {0.0, 0.0, 0.0}, lap = 0.0;
+            if (v.n_ions) jn += j1_at(v, rq, tid, kBlock, g, lap);
             dj = vblock_sum(jn, s_red, lane, wave, nw) - j_old;
         }
         if (tid == 0) {

@@ -11,6 +11,7 @@
 // lane p takes the window slots m = p (mod 4).
 #include "cq_device.h"
 #include "cq_internal.h"
+#include "cq_jastrow.h"
 
 namespace cq {
 
@@ -216,6 +217,11 @@ __global__ __launch_bounds__(512) void k_window(CrowdView<T> v, int e0, int nmov
                     }
                 }
             }
+        }
+        if (v.n_ions) {  // one-body terms, the centres shared out over the threads
+            double re[3];
+            for (int k = 0; k < 3; ++k) re[k] = v.R[((size_t)w * v.ne + e) * 3 + k];
+            dj += j1_delta(v, rp, re, tid, nt);
         }
         // the next move's proposal and stencil (electron e+1 has not moved in this window)
         if (wave == prop_wave && mv + 1 < nmoves) {
