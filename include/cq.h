@@ -280,6 +280,18 @@ cq_status cq_crowd_autotune(cq_crowd* c, int sweeps_per_candidate, int* chosen_k
 /* The delay rank in use (after autotuning, the chosen one). */
 cq_status cq_crowd_get_delay_rank(cq_crowd* c, int* k);
 
+/* Rounds per spin block of the batched path.  A spin block of N electrons needs at most
+   N / k rounds (delay rank k), but at ordinary acceptance far fewer; by default each sweep
+   runs as many as recent sweeps needed plus a margin (learned from a report the device
+   writes after each block, without synchronising), and a tail kernel then finishes, one
+   move at a time, any walker with electrons left.  rounds = 0: that default; rounds >= 1:
+   exactly that many (at most N / k) before the tail kernel, for callers that know their
+   acceptance and for tests of the tail.  The chain is the same either way (decisions to
+   rounding); only the speed changes.  Errors: CQ_EINVAL. */
+cq_status cq_crowd_set_round_plan(cq_crowd* c, int rounds);
+/* The planned rounds of each spin block [2] (0 on the other paths). */
+cq_status cq_crowd_get_round_plan(cq_crowd* c, int* rounds);
+
 /* The kernel path in use (cq_kernel_path; CQ_PATH_AUTO resolved at creation; for a
    crowd of several systems, the first system's). */
 cq_status cq_crowd_get_path(cq_crowd* c, int* path);

@@ -64,6 +64,8 @@ _SIGS = {
     "cq_crowd_autotune": [_P, _I, _P],
     "cq_crowd_get_delay_rank": [_P, _P],
     "cq_crowd_get_path": [_P, _P],
+    "cq_crowd_set_round_plan": [_P, ctypes.c_int],
+    "cq_crowd_get_round_plan": [_P, _P],
     "cq_crowd_get_uids": [_P, _P],
     "cq_crowd_recompute": [_P, _P],
     "cq_crowd_get_drift": [_P, _P, _P, _P],
@@ -360,6 +362,15 @@ class Crowd:
         k = ctypes.c_int()
         _check(lib().cq_crowd_get_delay_rank(self._h, ctypes.byref(k)))
         return k.value
+
+    def set_round_plan(self, rounds: int):
+        """Rounds per spin block of the batched path before the tail kernel (0: learned)."""
+        _check(lib().cq_crowd_set_round_plan(self._h, int(rounds)))
+
+    def round_plan(self):
+        r = np.zeros(2, np.int32)
+        _check(lib().cq_crowd_get_round_plan(self._h, r.ctypes.data))
+        return r
 
     def path(self) -> str:
         """The kernel path in use ("multi", "window", "batch" or "sweep")."""

@@ -134,6 +134,13 @@ struct cq_crowd {
     double* tmat = nullptr;
     int* cur = nullptr;
     int* look = nullptr;
+    // planned rounds per spin block of the batched path: learned from the rounds recent
+    // sweeps needed (pinned report written by the device), or fixed by the caller
+    int* used = nullptr;
+    int* left = nullptr;
+    int* hplan = nullptr;  // pinned host [5]: valid, used/left of spin 0, used/left of spin 1
+    int plan[2] = {-1, -1};
+    int plan_fixed = 0;
     uint32_t* uid = nullptr;
     cq::Params* prm = nullptr;
     int* status = nullptr;
@@ -230,6 +237,8 @@ cq::CrowdView<T> view(const cq_crowd* c)
     v.tmat = c->tmat;
     v.cur = c->cur;
     v.look = c->look;
+    v.used = c->used;
+    v.left = c->left;
     v.uid = c->uid;
     v.seed = c->seed;
     v.use_j2 = c->sys->use_j2;
@@ -314,6 +323,47 @@ void timed_end(cq_crowd* c, int kind, hipStream_t st = nullptr)
     c->ev_used[kind]++;
 }
 
+// Rounds a margin above the most any recent sweep needed absorb the sweep-to-sweep
+// spread; when the tail kernel still had work, the plan grows by more.
+constexpr int kPlanMargin = 2;
+
+int planned_rounds(const cq_crowd* c, int spin, int rounds)
+{
+    const int p = c->plan_fixed > 0 ? c->plan_fixed : c->plan[spin];
+    return p > 0 && p < rounds ? p : rounds;
+}
+
+void reset_plan(cq_crowd* c)
+{
+    c->plan[0] = c->plan[1] = -1;
+    if (c->hplan) c->hplan[0] = 0;
+}
+
+// Take the latest report of the rounds each spin block needed (written by the device into
+// pinned memory after the block; no synchronisation, a report a sweep or two old does as
+// well).  The first report sets the plan; later ones only grow it, so that a captured sweep
+// graph is rebuilt rarely.  Returns whether the plan changed.
+bool update_plan(cq_crowd* c)
+{
+    if (!c->hplan || c->path != CQ_PATH_BATCH || c->plan_fixed > 0) return false;
+    const volatile int* h = c->hplan;
+    if (!h[0]) return false;
+    const int rounds = cq::batch_rounds(c->n, c->K);
+    bool changed = false;
+    for (int s = 0; s < 2; ++s) {
+        const int used = h[1 + 2 * s], left = h[2 + 2 * s];
+        int want = used + kPlanMargin;
+        if (left) want = std::max(want, (c->plan[s] > 0 ? c->plan[s] : used) + 2 * kPlanMargin);
+        want = std::max(1, std::min(want, rounds));
+        const int p = c->plan[s] < 0 ? want : std::max(c->plan[s], want);
+        if (p != c->plan[s]) {
+            c->plan[s] = p;
+            changed = true;
+        }
+    }
+    return changed;
+}
+
 template <typename T>
 void enqueue_sweep(cq_crowd* c)
 {
@@ -360,21 +410,24 @@ void enqueue_sweep(cq_crowd* c)
         // update reads them packed by the column kernel
         const bool update_reads_stage = v.ub == nullptr;
         for (int spin = 0; spin < 2; ++spin) {
+            // R planned rounds (the rest of the block's N / k would find every walker done,
+            // at the usual acceptance); the tail kernel finishes any walker left over
+            const int R = planned_rounds(c, spin, rounds);
             const int q0 = spin * rounds;
             gather(q0, s1);
             jastrow(q0, s1);
-            if (overlap && rounds > 1) {
+            if (overlap && R > 1) {
                 keep(hipEventRecord(c->ev_fork[q0], s1));
                 keep(hipStreamWaitEvent(s2, c->ev_fork[q0], 0));
                 gather(q0 + 1, s2);
             }
-            for (int r = 0; r < rounds; ++r) {
+            for (int r = 0; r < R; ++r) {
                 const int q = q0 + r;
-                const bool next = r + 1 < rounds, ahead = overlap && r + 2 < rounds;
+                const bool next = r + 1 < R, ahead = overlap && r + 2 < R;
                 if (overlap && r > 0) keep(hipStreamWaitEvent(s1, c->ev_gat[q], 0));
                 timed_begin(c, CQ_KERNEL_RESOLVE);
                 cq::launch_batch_pmat<T>(v, spin, s1);
-                cq::launch_batch_decide<T>(v, spin, r & 1, s1);
+                cq::launch_batch_decide<T>(v, spin, r & 1, r, s1);
                 if (overlap && next) keep(hipEventRecord(c->ev_dec[q], s1));
                 cq::launch_batch_cols<T>(v, spin, s1);
                 timed_end(c, CQ_KERNEL_RESOLVE);
@@ -400,6 +453,9 @@ void enqueue_sweep(cq_crowd* c)
                     jastrow(q + 1, s1);
                 }
             }
+            timed_begin(c, CQ_KERNEL_RESOLVE);
+            cq::launch_leftover<T>(v, spin, c->hplan, R < rounds, s1);
+            timed_end(c, CQ_KERNEL_RESOLVE);
         }
         timed_begin(c, CQ_KERNEL_ENERGY);
         local_energy<T>(c, v, c->stream);
@@ -1002,6 +1058,7 @@ void cq_crowd_destroy(cq_crowd* c)
     if (c->vout) (void)hipFree(c->vout);
     if (c->forced) (void)hipFree(c->forced);
     if (c->forced_mult) (void)hipFree(c->forced_mult);
+    if (c->hplan) (void)hipHostFree(c->hplan);
     for (auto* evs : {&c->ev_fork, &c->ev_dec, &c->ev_cols, &c->ev_gat})
         for (hipEvent_t e : *evs) (void)hipEventDestroy(e);
     if (c->stream2) (void)hipStreamDestroy(c->stream2);
@@ -1138,6 +1195,14 @@ cq_status cq_crowd_create(const cq_system* const* systems, const int* walkers_pe
             c->stream2 = nullptr;
         }
     }
+    if (c->path == CQ_PATH_BATCH) {  // the device's report of the rounds each spin block needed
+        if (hipHostMalloc((void**)&c->hplan, 5 * sizeof(int), hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess) {
+            (void)hipGetLastError();
+            c->hplan = nullptr;  // no report: every sweep runs all N / k rounds
+        } else {
+            for (int i = 0; i < 5; ++i) c->hplan[i] = 0;
+        }
+    }
     const size_t es = c->prec == CQ_FP64 ? 8 : 4;
     const size_t n = c->n, ne = c->ne;
     constexpr int CHf = cq::chunk_orbitals<float>(), CHd = cq::chunk_orbitals<double>();
@@ -1168,6 +1233,8 @@ cq_status cq_crowd_create(const cq_system* const* systems, const int* walkers_pe
         {(void**)&c->tmat, sizeof(double) * Wc * K * K},
         {(void**)&c->cur, sizeof(int) * Wc * 3},
         {(void**)&c->look, sizeof(int) * Wc * 4},
+        {(void**)&c->used, sizeof(int) * 2},
+        {(void**)&c->left, sizeof(int) * 2},
         {&c->stage, es * Wc * c->QR * 5 * n},
         {&c->Cbuf, es * Wc * K * n},
         {(void**)&c->ct, sizeof(float) * Wc * n * cq::kMaxDelay},
@@ -1299,6 +1366,7 @@ static cq_status autotune_k(cq_crowd* c, int sweeps, int* chosen)
         c->Q = c->path == CQ_PATH_BATCH ? cq::batch_candidates(c->n, k) : k;
         c->QR = c->path == CQ_PATH_BATCH ? 2 * c->Q : c->Q;
         drop_graph(c);
+        reset_plan(c);  // the previous candidate's sweeps have completed (event synchronised)
         if (c->path == CQ_PATH_MULTI) {
             if (c->prec == CQ_FP64)
                 cq::launch_first_proposal<double>(view<double>(c), c->stream);
@@ -1332,6 +1400,7 @@ static cq_status autotune_k(cq_crowd* c, int sweeps, int* chosen)
     c->Q = c->path == CQ_PATH_BATCH ? cq::batch_candidates(c->n, best_k) : best_k;
     c->QR = c->path == CQ_PATH_BATCH ? 2 * c->Q : c->Q;
     drop_graph(c);
+    reset_plan(c);
     c->tuned = true;
     if (chosen) *chosen = best_k;
     return check_singular(c, "autotune");
@@ -1382,6 +1451,7 @@ cq_status cq_crowd_run_vmc(cq_crowd* c, int n_sweeps, double sigma)
             cq::launch_first_proposal<float>(view<float>(c), c->stream);
     }
     for (int s = 0; s < n_sweeps; ++s) {
+        if (update_plan(c)) drop_graph(c);
         if (c->use_graph && !c->timing_mask) {
             if (!c->gexec) {
                 cq_status st = build_graph(c);
@@ -1524,6 +1594,36 @@ cq_status cq_crowd_run_dmc_systems(cq_crowd* c, int n_generations, double tau, c
     std::vector<int> tgt(set.size());
     for (size_t s = 0; s < set.size(); ++s) tgt[s] = n_target ? n_target[s] : set[s]->W;
     return run_dmc_set(c, set, n_generations, tau, e_trial, tgt.data(), history);
+}
+
+cq_status cq_crowd_set_round_plan(cq_crowd* c, int rounds)
+{
+    if (!c) return fail(CQ_EINVAL, "crowd is NULL");
+    if (rounds < 0) return fail(CQ_EINVAL, "rounds must be >= 0");
+    if (!c->subs.empty()) {
+        for (cq_crowd* sub : c->subs) {
+            cq_status st = cq_crowd_set_round_plan(sub, rounds);
+            if (st != CQ_OK) return st;
+        }
+        return CQ_OK;
+    }
+    c->plan_fixed = rounds;
+    drop_graph(c);
+    return CQ_OK;
+}
+
+cq_status cq_crowd_get_round_plan(cq_crowd* c, int* rounds)
+{
+    if (!c || !rounds) return fail(CQ_EINVAL, "NULL argument");
+    cq_crowd* x = c->subs.empty() ? c : c->subs[0];
+    if (x->path != CQ_PATH_BATCH) {
+        rounds[0] = rounds[1] = 0;
+        return CQ_OK;
+    }
+    (void)update_plan(x);
+    const int all = cq::batch_rounds(x->n, x->K);
+    for (int s = 0; s < 2; ++s) rounds[s] = planned_rounds(x, s, all);
+    return CQ_OK;
 }
 
 cq_status cq_crowd_get_path(cq_crowd* c, int* path)

@@ -101,6 +101,8 @@ struct CrowdView {
     int* cur;            // [W][2] next electron to decide, end of the evaluated candidates;
                          // then [W] first candidate of the last round
     int* look;           // [2][W][2] gather range of the rounds of each parity
+    int* used;           // [2] rounds of the current spin block in which some walker had candidates
+    int* left;           // [2] whether the block's tail kernel had electrons to move
     const uint32_t* uid;
     uint64_t seed;
     int use_j2;
@@ -195,8 +197,11 @@ template <typename T> void launch_batch_pmat(const CrowdView<T>& v, int spin, hi
 template <typename T> void launch_batch_rows(const CrowdView<T>& v, int spin, hipStream_t s);
 int device_cu_count();
 template <typename T> void launch_sweep(const CrowdView<T>& v, hipStream_t s);
-template <typename T> void launch_batch_decide(const CrowdView<T>& v, int spin, int par, hipStream_t s);
+template <typename T> void launch_batch_decide(const CrowdView<T>& v, int spin, int par, int round, hipStream_t s);
 template <typename T> void launch_batch_cols(const CrowdView<T>& v, int spin, hipStream_t s);
+// tail of a spin block after the planned rounds (run), and the plan record for the host
+template <typename T> void launch_leftover(const CrowdView<T>& v, int spin, int* host_report, bool run,
+                                           hipStream_t s);
 int batch_rounds(int n, int K);      // rounds per spin block (enough when every move is accepted)
 int batch_candidates(int n, int K);  // candidates per round, Q
 // linv_ready: the window's L^-1 is already in wlinv (the batched path forms it)

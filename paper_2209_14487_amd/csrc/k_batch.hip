@@ -478,7 +478,7 @@ constexpr int kVglWaveBlocksPerCU = 1;
 constexpr int kVglBlocksPerCUAlone = 8;
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_decide(CrowdView<T> v, int spin, int par)
+__global__ __launch_bounds__(kBlock) void k_decide(CrowdView<T> v, int spin, int par, int round)
 {
     extern __shared__ unsigned char dsm[];
     DecideLds& S = *reinterpret_cast<DecideLds*>(dsm);
@@ -508,6 +508,7 @@ __global__ __launch_bounds__(kBlock) void k_decide(CrowdView<T> v, int spin, int
         }
         return;
     }
+    if (tid == 0) atomicMax(&v.used[spin], round + 1);  // rounds the block has needed so far
     // candidates: P, uniforms, Jastrow sums, positions
     // P (nc x nc, row stride Q): wave v loads rows 22v..22v+21 with the lanes along
     // the columns, all rows of a column batch in flight together
@@ -897,10 +898,14 @@ __global__ __launch_bounds__(kBlock) void k_rows(CrowdView<T> v, int spin)
     }
 }
 
-__global__ void k_cursor_reset(int* cur, int* look, int W, int Q, int n)
+__global__ void k_cursor_reset(int* cur, int* look, int* used, int* left, int spin, int W, int Q, int n)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < 2 * W) cur[i] = 0;
+    if (i == 0) {
+        used[spin] = 0;
+        left[spin] = 0;
+    }
     if (i < W) {
         const int q1 = Q < n ? Q : n, q2 = 2 * Q < n ? 2 * Q : n;
         look[(size_t)i * 2] = 0;
@@ -926,7 +931,8 @@ template <typename T>
 void launch_batch_stencils(const CrowdView<T>& v, int spin, int par, bool block_start, hipStream_t s)
 {
     if (block_start)
-        hipLaunchKernelGGL(k_cursor_reset, dim3((2 * v.W + 255) / 256), dim3(256), 0, s, v.cur, v.look, v.W, v.Q, v.n);
+        hipLaunchKernelGGL(k_cursor_reset, dim3((2 * v.W + 255) / 256), dim3(256), 0, s, v.cur, v.look, v.used, v.left,
+                           spin, v.W, v.Q, v.n);
     hipLaunchKernelGGL(k_stencils<T>, dim3((v.W * v.Q + kBlock / 64 - 1) / (kBlock / 64)), dim3(kBlock), 0, s, v, spin,
                        par);
 }
@@ -987,7 +993,7 @@ void launch_batch_pmat(const CrowdView<T>& v, int spin, hipStream_t s)
 }
 
 template <typename T>
-void launch_batch_decide(const CrowdView<T>& v, int spin, int par, hipStream_t s)
+void launch_batch_decide(const CrowdView<T>& v, int spin, int par, int round, hipStream_t s)
 {
     static bool lds_set = false;  // opt in to more than 64 KB of LDS, once per type
     if (!lds_set) {
@@ -995,7 +1001,7 @@ void launch_batch_decide(const CrowdView<T>& v, int spin, int par, hipStream_t s
                                   (int)sizeof(DecideLds));
         lds_set = true;
     }
-    hipLaunchKernelGGL(k_decide<T>, dim3(v.W), dim3(kBlock), sizeof(DecideLds), s, v, spin, par);
+    hipLaunchKernelGGL(k_decide<T>, dim3(v.W), dim3(kBlock), sizeof(DecideLds), s, v, spin, par, round);
 }
 
 template <typename T>
@@ -1016,7 +1022,7 @@ template void launch_batch_pmat<float>(const CrowdView<float>&, int, hipStream_t
 template void launch_batch_pmat<double>(const CrowdView<double>&, int, hipStream_t);
 template void launch_batch_cols<float>(const CrowdView<float>&, int, hipStream_t);
 template void launch_batch_cols<double>(const CrowdView<double>&, int, hipStream_t);
-template void launch_batch_decide<float>(const CrowdView<float>&, int, int, hipStream_t);
-template void launch_batch_decide<double>(const CrowdView<double>&, int, int, hipStream_t);
+template void launch_batch_decide<float>(const CrowdView<float>&, int, int, int, hipStream_t);
+template void launch_batch_decide<double>(const CrowdView<double>&, int, int, int, hipStream_t);
 
 }  // namespace cq

@@ -333,6 +333,58 @@ def test_batch_rounds_at_extreme_acceptance(sigma, k):
     crowd.close()
 
 
+@pytest.mark.parametrize("precision,n,L,G,W,S,k,plan", [("fp64", 32, 10.0, 48, 24, 3, 8, 1),
+                                                         ("fp64", 32, 10.0, 48, 24, 3, 4, 3),
+                                                         ("mixed", 32, 10.0, 48, 24, 3, 8, 1),
+                                                         ("fp64", 256, 20.0, 64, 3, 1, 32, 1)])
+def test_round_plan_tail_kernel_keeps_the_chain(precision, n, L, G, W, S, k, plan):
+    """Batched path with fewer rounds per spin block than the walkers need (a fixed plan):
+    the tail kernel moves every electron left, one move at a time, and the chain is the
+    oracle's (FP64: ratios, log|det|, E_L within the parity bar, decisions except near-ties;
+    mixed: on the oracle's trajectory within the FP32 rounding model)."""
+    fp32 = precision == "mixed"
+    g, o = make_pair(n, L, G, 1006, coef_seed=1006, fp64=not fp32, fp32=fp32)
+    R0 = start_positions(1006, W, 2 * n, L)
+    ref = orc.vmc(o, R0, S, sigma=0.5)
+    crowd = cq.Crowd(g, W, precision=precision, delay_rank=k, recompute_every=2 if fp32 else 0, seed=1006,
+                     path="batch")
+    crowd.set_round_plan(plan)
+    assert list(crowd.round_plan()) == [plan, plan]
+    if fp32:
+        gpu = run_gpu(crowd, R0, S, 0.5, forced=ref.acc)
+        emu = emulated_rho(o, R0, ref.acc, recompute_every=2, k=k, path="batch")
+        mixed_ratio_check(gpu["rho"], ref.rho, emu, "tail kernel mixed k=%d plan=%d" % (k, plan))
+    elif S == 1 and n >= 256:
+        # about a hundred Sherman-Morrison steps per spin block on each side (the oracle's and
+        # the tail kernel's): the arbiter decides where the two chains have drifted apart
+        gpu = run_gpu(crowd, R0, S, 0.5)
+        arbitrated_fp64_check(gpu, ref, o, R0, range(W), range(W), 2 * n)
+    else:
+        gpu = run_gpu(crowd, R0, S, 0.5)
+        compare_fp64(gpu, ref, S, 2 * n)
+    crowd.close()
+
+
+def test_round_plan_is_learned_and_keeps_the_chain():
+    """The default plan: the first sweep runs all N / k rounds of each spin block, later ones
+    as many as were needed plus a margin (fewer than N / k at this acceptance: 64 electrons per
+    spin at k = 4 take about 8 of the 16 rounds); the chain over those sweeps is the oracle's."""
+    n, L, G, W, S, k = 64, 12.0, 48, 16, 5, 4
+    g, o = make_pair(n, L, G, 1007, coef_seed=1007)
+    R0 = start_positions(1007, W, 2 * n, L)
+    crowd = cq.Crowd(g, W, precision="fp64", delay_rank=k, seed=1007, path="batch")
+    assert list(crowd.round_plan()) == [n // k, n // k]
+    gpu = run_gpu(crowd, R0, S, 0.5)
+    plan = crowd.round_plan()
+    print("   learned plan", plan.tolist(), "of", n // k)
+    assert np.all(plan < n // k) and np.all(plan >= 1)
+    ref = orc.vmc(o, R0, S, sigma=0.5)
+    # five sweeps of rank-4 and Sherman-Morrison steps on both sides: the arbiter decides where the
+    # two FP64 chains have drifted apart by more than the parity bar
+    arbitrated_fp64_check(gpu, ref, o, R0, range(W), range(W), S * 2 * n)
+    crowd.close()
+
+
 def test_singular_start_is_reported():
     """Two same-spin electrons at one position make A singular: CQ_ESINGULAR names the walker."""
     n, L, G, W = 4, 5.0, 16, 3
@@ -514,27 +566,64 @@ def c4_reference(o, R0):
                    n_threads=len(C4_SAMPLE))
 
 
-def c4_exact_ratios(o, R0w, uid, acc, moves, sigma=0.5):
-    """Determinant ratios at the given moves of sweep 0 of one walker from a fresh, refined solve
-    of the current matrix (oracle.row_ratio_refined), replaying the oracle's decisions and its
-    proposal stream r' = wrap(r_e + sigma z); A is kept by row replacement, with no inverse."""
+def exact_ratios(o, R0w, uid, acc, moves, sigma=0.5):
+    """Determinant ratios at the given moves (flat index sweep * Ne + electron, from sweep 0) of
+    one walker from a fresh, refined solve of the current matrix (oracle.row_ratio_refined),
+    replaying the oracle's decisions acc (flat) and its proposal stream r' = wrap(r_e + sigma z);
+    A is kept by row replacement, with no inverse."""
+    n, L = o.n_up, o.L
+    ne = 2 * n
     want = set(int(k) for k in moves)
     out, R, A = {}, np.array(R0w, dtype=np.float64), [None, None]
-    for e in range(max(want) + 1):
-        if e not in want and not acc[e]:
+    for m in range(max(want) + 1):
+        if m not in want and not acc[m]:
             continue
-        sp, i = divmod(e, C4_N)
-        rnew = np.mod(R[e] + sigma * orc.gauss3(1004, uid, 0, e), C4_L)
-        phi = orc.orbital_vgl(o, rnew, C4_N)[0]
-        if e in want:
+        sweep, e = divmod(m, ne)
+        sp, i = divmod(e, n)
+        rnew = np.mod(R[e] + sigma * orc.gauss3(o.seed, uid, sweep, e), L)
+        phi = orc.orbital_vgl(o, rnew, n)[0]
+        if m in want:
             if A[sp] is None:
-                A[sp] = np.array([orc.orbital_vgl(o, R[sp * C4_N + j], C4_N)[0] for j in range(C4_N)])
-            out[e] = orc.row_ratio_refined(A[sp], i, phi)
-        if acc[e]:
+                A[sp] = np.array([orc.orbital_vgl(o, R[sp * n + j], n)[0] for j in range(n)])
+            out[m] = orc.row_ratio_refined(A[sp], i, phi)
+        if acc[m]:
             R[e] = rnew
             if A[sp] is not None:
                 A[sp][i] = phi
     return out
+
+
+def arbitrated_fp64_check(gpu, ref, o, R0, walkers, uids, moves, tol=1e-10, label=""):
+    """The first `moves` moves (flat over sweeps) of the given walkers (columns of ref): identical
+    decisions except at near-ties, Jastrow changes within tol, and ratios within tol relative of
+    the oracle's; where a long FP64 update chain (the oracle's Sherman-Morrison steps, or the
+    GPU's) has drifted more than tol, the arbiter is the ratio from a fresh, refined solve of the
+    current matrix, and the GPU value must be within tol of it there."""
+    rel = lambda a, b: np.abs(a - b) / np.maximum(1.0, np.abs(b))
+    flat = lambda x, col: x[:, :, col].ravel()[:moves]
+    for i, w in enumerate(walkers):
+        acc_g, acc_r = flat(gpu["acc"], w), flat(ref.acc, i)
+        d = np.nonzero(acc_g != acc_r)[0]
+        lim = moves if len(d) == 0 else int(d[0])
+        if len(d):
+            assert abs(flat(ref.prob, i)[lim] - flat(ref.u, i)[lim]) < NEAR_TIE, "decision differs away from a near-tie"
+        dj_g, dj_r = flat(gpu["dlnj"], w)[:lim], flat(ref.dlnj, i)[:lim]
+        assert np.all(rel(dj_g, dj_r) <= tol), (w, "dlnj")
+        rho_g, rho_r = flat(gpu["rho"], w)[:lim], flat(ref.rho, i)[:lim]
+        pr_g, pr_r = flat(gpu["prob"], w)[:lim], flat(ref.prob, i)[:lim]
+        off = np.nonzero((rel(rho_g, rho_r) > tol) | (rel(pr_g, pr_r) > tol))[0]
+        msg = "   %swalker %d: %d moves (%d accepted), rho max diff from the oracle %.2e, %d beyond %.0e" % (
+            label, w, lim, int(acc_r[:lim].sum()), rel(rho_g, rho_r).max(), len(off), tol)
+        if len(off):
+            ex = exact_ratios(o, R0[w], int(uids[i]), acc_r, off)
+            x = np.array([ex[k] for k in off])
+            eg, eo = rel(rho_g[off], x), rel(rho_r[off], x)
+            msg += "; there: GPU - exact max %.2e, oracle - exact max %.2e" % (eg.max(), eo.max())
+            print(msg)
+            assert np.all(eg <= tol), (w, off[eg > tol])
+            assert np.all(rel(pr_g[off], x * x * np.exp(2.0 * dj_r[off])) <= 2 * tol), w
+        else:
+            print(msg)
 
 
 def test_c4_full_size_fp64_sampled_walkers_match_oracle():
@@ -552,31 +641,7 @@ def test_c4_full_size_fp64_sampled_walkers_match_oracle():
     crowd.close()
     g.close()
     ref = c4_reference(o, R0)
-    tol = 1e-10
-    rel = lambda a, b: np.abs(a - b) / np.maximum(1.0, np.abs(b))
-    for i, w in enumerate(C4_SAMPLE):
-        acc_g, acc_r = gpu["acc"][0, :C4_MOVES, w], ref.acc[0, :C4_MOVES, i]
-        d = np.nonzero(acc_g != acc_r)[0]
-        lim = C4_MOVES if len(d) == 0 else int(d[0])
-        if len(d):
-            assert abs(ref.prob[0, lim, i] - ref.u[0, lim, i]) < NEAR_TIE, "decision differs away from a near-tie"
-        dj_g, dj_r = gpu["dlnj"][0, :lim, w], ref.dlnj[0, :lim, i]
-        assert np.all(rel(dj_g, dj_r) <= tol), (w, "dlnj")
-        rho_g, rho_r = gpu["rho"][0, :lim, w], ref.rho[0, :lim, i]
-        pr_g, pr_r = gpu["prob"][0, :lim, w], ref.prob[0, :lim, i]
-        off = np.nonzero((rel(rho_g, rho_r) > tol) | (rel(pr_g, pr_r) > tol))[0]
-        msg = "   walker %d: %d moves (%d accepted), rho max diff from the oracle %.2e, %d beyond %.0e" % (
-            w, lim, int(acc_r[:lim].sum()), rel(rho_g, rho_r).max(), len(off), tol)
-        if len(off):
-            ex = c4_exact_ratios(o, R0[w], w, acc_r, off)
-            x = np.array([ex[k] for k in off])
-            eg, eo = rel(rho_g[off], x), rel(rho_r[off], x)
-            msg += "; there: GPU - exact max %.2e, oracle - exact max %.2e" % (eg.max(), eo.max())
-            print(msg)
-            assert np.all(eg <= tol), (w, off[eg > tol])
-            assert np.all(rel(pr_g[off], x * x * np.exp(2.0 * dj_r[off])) <= 2 * tol), w
-        else:
-            print(msg)
+    arbitrated_fp64_check(gpu, ref, o, R0, C4_SAMPLE, C4_SAMPLE, C4_MOVES)
 
 
 def test_c4_full_size_mixed_bench_configuration_on_oracle_trajectory():
