@@ -278,7 +278,8 @@ def kernel_source_hash():
     """SHA-256 of the sources the gather and update kernels are built from."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("k_batch.hip", "k_flush_mfma.hip", "k_update.hip", "k_virtual.hip", "cq_device.h", "cq_internal.h"):
+    for f in ("k_batch.hip", "k_flush_mfma.hip", "k_update.hip", "k_virtual.hip", "cq_device.h", "cq_internal.h",
+              "cq_stencil.h", "cq_jastrow.h"):
         with open(os.path.join(ROOT, "paper_2209_14487_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
