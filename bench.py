@@ -60,6 +60,12 @@ def parse():
                     help="first copy 1 GiB with the library's plain copy kernel (counter calibration runs)")
     ap.add_argument("--virtual-points", type=int, default=12,
                     help="quadrature points per electron of the timed virtual-move launch (0: skip)")
+    ap.add_argument("--tiles", default="",
+                    help="launch shapes of the batched path, Q,G (candidates per round, gather workgroups per CU "
+                         "beside the update); default: the built-in rules")
+    ap.add_argument("--tile-cache", default="",
+                    help="JSON tile cache: take the shapes from it, or tune them (2 sweeps per candidate, before "
+                         "the warm-up) and add them to it")
     ap.add_argument("--scan", default="",
                     help="crowd/walker scan instead of the bench line: comma-separated CROWDSxWALKERS pairs "
                          "(e.g. 1x512,2x512,4x512); each is timed over --steps sweeps after --warmup, graph replay")
@@ -138,7 +144,7 @@ def make_system(cq, wl, elem_bytes):
 
 
 def run_gpu(cq, wl, precision, delay, recompute, steps, warmup, timing_kinds, use_graph, path="auto",
-            graph_steps=0, streams=2):
+            graph_steps=0, streams=2, tiles=None, tile_cache=None):
     """Time `steps` sweeps over `wl.crowds` crowds (one stream each); returns a result dict.
 
     With timing_kinds, HIP events bracket every launch of those kernel kinds on each crowd's
@@ -151,8 +157,13 @@ def run_gpu(cq, wl, precision, delay, recompute, steps, warmup, timing_kinds, us
         c = cq.Crowd(system, wl.walkers, precision=precision, delay_rank=delay, recompute_every=recompute,
                      seed=wl.seed, first_uid=ci * wl.walkers, use_graph=use_graph, path=path, streams=streams)
         c.set_positions(start_positions(wl.seed, wl.walkers, wl.n_e, wl.L, first_walker=ci * wl.walkers))
+        if tiles:
+            c.set_tiles(*tiles)
+        elif tile_cache:
+            t, hit = c.autotune_tiles(2, tile_cache)
+            log("  tiles %s (%s)" % (t, "from the cache" if hit else "tuned"))
         crowds.append(c)
-    log("  %s: %d crowd(s) x %d walkers set up" % (precision, wl.crowds, wl.walkers))
+    log("  %s: %d crowd(s) x %d walkers set up, tiles %s" % (precision, wl.crowds, wl.walkers, crowds[0].tiles()))
     for c in crowds:
         c.run_vmc(warmup, wl.sigma)
     for c in crowds:
@@ -179,6 +190,7 @@ def run_gpu(cq, wl, precision, delay, recompute, steps, warmup, timing_kinds, us
     prop = sum(int(c.acceptance()[1].sum()) for c in crowds)
     k_used = crowds[0].delay_rank()
     path_used = crowds[0].path()
+    tiles_used = crowds[0].tiles()
     el = np.concatenate([c.local_energy() for c in crowds])
     # FP64 recomputes that fell inside the timed sweeps, and their device time
     n_rec = sum(c.drift()[2] for c in crowds) - rec0
@@ -216,7 +228,7 @@ def run_gpu(cq, wl, precision, delay, recompute, steps, warmup, timing_kinds, us
     if recompute > 0 and rec_ms is not None:
         seconds = seconds - 1e-3 * rec_ms_in + (steps / recompute) * 1e-3 * rec_ms
     out = dict(seconds=seconds, wall_seconds=t1 - t0, moves=moves, moves_per_s=moves / seconds,
-               wall_moves_per_s=moves / (t1 - t0), kernels=kt, delay_rank=k_used, path=path_used,
+               wall_moves_per_s=moves / (t1 - t0), kernels=kt, delay_rank=k_used, path=path_used, tiles=tiles_used,
                accepted_timed=acc - acc0, acceptance=acc / max(prop, 1), e_mean=float(el.mean()),
                finite=bool(np.isfinite(el).all()), recomputes_in_timed=n_rec, recompute_ms=rec_ms,
                recompute_ms_in_timed=rec_ms_in)
@@ -517,8 +529,10 @@ def main():
     for k in ("vgl", "update", "inverse"):
         if k not in kinds:
             kinds.append(k)
+    tiles = tuple(int(x) for x in args.tiles.split(",")) if args.tiles else None
     mixed = run_gpu(cq, wl, "mixed", delay, wl.recompute_every, args.steps, args.warmup, kinds, not args.eager,
-                    path=args.path, graph_steps=0 if args.eager else max(2, args.steps // 4))
+                    path=args.path, graph_steps=0 if args.eager else max(2, args.steps // 4), tiles=tiles,
+                    tile_cache=args.tile_cache or None)
     log("  mixed: %.3f s for %d sweeps (%.3f s wall, %d recompute(s) inside), %.3e moves/s, acceptance %.3f"
         % (mixed["seconds"], args.steps, mixed["wall_seconds"], mixed["recomputes_in_timed"],
            mixed["moves_per_s"], mixed["acceptance"]))
@@ -544,7 +558,7 @@ def main():
                                     "%d crowd(s) x %d walkers, delayed rank %d, FP64 recompute every %d sweeps"
                                     % (wl.name, n, n, wl.L, wl.G, wl.table_bytes(4) / 1e9, wl.crowds, wl.walkers,
                                        delay, wl.recompute_every),
-                           precision="mixed", path=mixed["path"],
+                           precision="mixed", path=mixed["path"], tiles=mixed["tiles"],
                            launch="eager launches; HIP events around every launch of %s in the timed region" % "/".join(kinds)),
                roofline=dominant, roofline_spline=roof_vgl, roofline_update=roof_up, kernels=kinfo,
                windows_per_sweep=windows_per_sweep,
@@ -562,7 +576,7 @@ def main():
     if args.alone_steps > 0 and mixed["path"] == "batch":
         # the same kernels with the GPU to themselves: one stream, every kernel in order
         alone = run_gpu(cq, wl, "mixed", delay, 0, args.alone_steps, 1, ["vgl", "update"], False,
-                        path=args.path, streams=1)
+                        path=args.path, streams=1, tiles=(mixed["tiles"]["candidates"], 0))
         a_vgl, a_up = rooflines(alone, n, W, args.alone_steps, None)
         log("  alone: k_prop_vgl %.0f GB/s, update %.1f TFLOP/s" % (a_vgl["achieved"], a_up["achieved"]))
         out["alone"] = dict(moves_per_s=round(alone["moves_per_s"], 1), steps=args.alone_steps,

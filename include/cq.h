@@ -47,7 +47,8 @@ typedef enum {
     CQ_ENOMEM = 2,     /* device or host allocation failed */
     CQ_EDEVICE = 3,    /* HIP runtime error (message says which call) */
     CQ_ESINGULAR = 4,  /* a Slater matrix was singular or not finite (message names the walker) */
-    CQ_ESTATE = 5      /* call made in the wrong state (e.g. run before positions are set) */
+    CQ_ESTATE = 5,     /* call made in the wrong state (e.g. run before positions are set) */
+    CQ_EIO = 6         /* a file could not be read or written (the tile cache) */
 } cq_status;
 
 typedef enum { CQ_FP64 = 0, CQ_MIXED = 1 } cq_precision;
@@ -291,6 +292,56 @@ cq_status cq_crowd_get_delay_rank(cq_crowd* c, int* k);
 cq_status cq_crowd_set_round_plan(cq_crowd* c, int rounds);
 /* The planned rounds of each spin block [2] (0 on the other paths). */
 cq_status cq_crowd_get_round_plan(cq_crowd* c, int* rounds);
+
+/* Launch shapes of the batched path (the crowd batching of Sec. III; the paper's drivers
+   fix theirs per kernel, Sec. II-D).  Neither changes the chain (same proposals and
+   uniforms, decisions to rounding), only the speed:
+     candidates            Q, the upcoming proposals whose orbital rows one round evaluates
+                           per walker; from the delay rank k (or 2, if larger) up to the
+                           value the crowd was created with, min(88, 3 k_max, N); 0 = that
+                           default.  A round examines at most Q candidates and closes after
+                           k acceptances, so Q >= k keeps N / k rounds enough for a block.
+     gather_blocks_per_cu  workgroups per compute unit of the persistent orbital gather
+                           while it runs beside the decisions and the update (two-stream
+                           schedule), 1..8; 0 = the built-in rule (1 for the wave-sliced
+                           gather at N >= 256 in FP32 / 128 in FP64, else 3). */
+typedef struct cq_tiles {
+    int candidates;
+    int gather_blocks_per_cu;
+} cq_tiles;
+
+/* Set the launch shapes (values as above; 0 keeps a field's default).  Takes effect from
+   the next sweep (a captured sweep graph is rebuilt).  Other paths accept and ignore them.
+   Errors: CQ_EINVAL (out of range; nothing changes). */
+cq_status cq_crowd_set_tiles(cq_crowd* c, const cq_tiles* t);
+/* The launch shapes in use, defaults resolved (candidates = Q; gather_blocks_per_cu as
+   launched). */
+cq_status cq_crowd_get_tiles(cq_crowd* c, cq_tiles* t);
+
+/* Tile autotuning for the batched path.  With cache_path non-NULL and an entry in it for
+   this device (architecture name and compute-unit count), N, walkers, precision and delay
+   rank, apply that entry and time nothing (*from_cache = 1).  Otherwise time
+   sweeps_per_candidate sweeps (eager launches, HIP events, after one untimed sweep that
+   learns the round plan) for every candidate pair: Q in {1.5 k, 2 k, default} within the
+   limits above, gather workgroups per CU in {1, 2, 3}; keep the fastest and, with
+   cache_path, append it to the cache (*from_cache = 0).  Every timed sweep is an ordinary
+   sweep of the chain.  On other paths nothing is timed and the defaults stay.  chosen and
+   from_cache may be NULL.  Errors: CQ_EINVAL, CQ_ESTATE (positions not set), CQ_EIO (the
+   cache cannot be written). */
+cq_status cq_crowd_autotune_tiles(cq_crowd* c, int sweeps_per_candidate, const char* cache_path, cq_tiles* chosen,
+                                  int* from_cache);
+
+/* The tile cache (host only, no GPU call).  A JSON file: an array with one object per line,
+   {"device": "...", "n": N, "walkers": W, "precision": "mixed"|"fp64", "delay_rank": k,
+   "candidates": Q, "gather_blocks_per_cu": g, "ms_per_sweep": t}.  Lookup returns the last
+   entry that matches every key (*found = 0 and *out untouched if none, or if the file does
+   not exist); lines that do not parse are skipped.  Store appends an entry (creating the
+   file), keeping the file a valid JSON array.  device: at most 127 bytes, no '"' or '\'.
+   Errors: CQ_EINVAL, CQ_EIO. */
+cq_status cq_tile_cache_find(const char* path, const char* device, int n, int walkers, int precision, int delay_rank,
+                             cq_tiles* out, int* found);
+cq_status cq_tile_cache_store(const char* path, const char* device, int n, int walkers, int precision, int delay_rank,
+                              const cq_tiles* t, double ms_per_sweep);
 
 /* The kernel path in use (cq_kernel_path; CQ_PATH_AUTO resolved at creation; for a
    crowd of several systems, the first system's). */

@@ -18,7 +18,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcrowdqmc.so")
 
-CQ_OK, CQ_EINVAL, CQ_ENOMEM, CQ_EDEVICE, CQ_ESINGULAR, CQ_ESTATE = range(6)
+CQ_OK, CQ_EINVAL, CQ_ENOMEM, CQ_EDEVICE, CQ_ESINGULAR, CQ_ESTATE, CQ_EIO = range(7)
 CQ_FP64, CQ_MIXED = 0, 1
 PATHS = {"auto": 0, "multi": 1, "window": 2, "batch": 3, "sweep": 4}
 KERNEL_VGL, KERNEL_RESOLVE, KERNEL_UPDATE, KERNEL_ENERGY, KERNEL_INVERSE, KERNEL_PROPOSE, KERNEL_VIRTUAL = range(7)
@@ -26,7 +26,7 @@ KERNEL_NAMES = {"vgl": KERNEL_VGL, "resolve": KERNEL_RESOLVE, "update": KERNEL_U
                 "energy": KERNEL_ENERGY, "inverse": KERNEL_INVERSE, "propose": KERNEL_PROPOSE,
                 "virtual": KERNEL_VIRTUAL}
 
-_STATUS_NAMES = {1: "CQ_EINVAL", 2: "CQ_ENOMEM", 3: "CQ_EDEVICE", 4: "CQ_ESINGULAR", 5: "CQ_ESTATE"}
+_STATUS_NAMES = {1: "CQ_EINVAL", 2: "CQ_ENOMEM", 3: "CQ_EDEVICE", 4: "CQ_ESINGULAR", 5: "CQ_ESTATE", 6: "CQ_EIO"}
 
 
 class CqError(RuntimeError):
@@ -40,6 +40,11 @@ class CrowdDesc(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("first_uid", ctypes.c_uint32), ("hip_stream", ctypes.c_void_p),
                 ("use_graph", ctypes.c_int), ("kernel_path", ctypes.c_int), ("max_walkers", ctypes.c_int),
                 ("streams", ctypes.c_int)]
+
+
+class Tiles(ctypes.Structure):
+    """cq_tiles: candidates per round (Q) and gather workgroups per CU beside the update."""
+    _fields_ = [("candidates", ctypes.c_int), ("gather_blocks_per_cu", ctypes.c_int)]
 
 
 _lib = None
@@ -65,6 +70,11 @@ _SIGS = {
     "cq_crowd_get_delay_rank": [_P, _P],
     "cq_crowd_get_path": [_P, _P],
     "cq_crowd_set_round_plan": [_P, ctypes.c_int],
+    "cq_crowd_set_tiles": [_P, _P],
+    "cq_crowd_get_tiles": [_P, _P],
+    "cq_crowd_autotune_tiles": [_P, _I, ctypes.c_char_p, _P, _P],
+    "cq_tile_cache_find": [ctypes.c_char_p, ctypes.c_char_p, _I, _I, _I, _I, _P, _P],
+    "cq_tile_cache_store": [ctypes.c_char_p, ctypes.c_char_p, _I, _I, _I, _I, _P, ctypes.c_double],
     "cq_crowd_get_round_plan": [_P, _P],
     "cq_crowd_get_uids": [_P, _P],
     "cq_crowd_recompute": [_P, _P],
@@ -115,6 +125,26 @@ def exported_names():
 def _check(st):
     if st != CQ_OK:
         raise CqError(st, lib().cq_last_error().decode())
+
+
+def _prec(precision) -> int:
+    return CQ_FP64 if precision in ("fp64", CQ_FP64) else CQ_MIXED
+
+
+def tile_cache_find(path, device: str, n: int, walkers: int, precision, delay_rank: int):
+    """The tile cache's last entry for the key (cq_tile_cache_find; host only), or None."""
+    t, found = Tiles(), ctypes.c_int()
+    _check(lib().cq_tile_cache_find(os.fsencode(path), device.encode(), int(n), int(walkers), _prec(precision),
+                                    int(delay_rank), ctypes.byref(t), ctypes.byref(found)))
+    return dict(candidates=t.candidates, gather_blocks_per_cu=t.gather_blocks_per_cu) if found.value else None
+
+
+def tile_cache_store(path, device: str, n: int, walkers: int, precision, delay_rank: int, candidates: int,
+                     gather_blocks_per_cu: int, ms_per_sweep: float):
+    """Append an entry to the tile cache (cq_tile_cache_store; host only)."""
+    t = Tiles(int(candidates), int(gather_blocks_per_cu))
+    _check(lib().cq_tile_cache_store(os.fsencode(path), device.encode(), int(n), int(walkers), _prec(precision),
+                                     int(delay_rank), ctypes.byref(t), float(ms_per_sweep)))
 
 
 _hip = None
@@ -371,6 +401,25 @@ class Crowd:
         r = np.zeros(2, np.int32)
         _check(lib().cq_crowd_get_round_plan(self._h, r.ctypes.data))
         return r
+
+    def set_tiles(self, candidates: int = 0, gather_blocks_per_cu: int = 0):
+        """Launch shapes of the batched path (0: default); see cq_crowd_set_tiles."""
+        t = Tiles(int(candidates), int(gather_blocks_per_cu))
+        _check(lib().cq_crowd_set_tiles(self._h, ctypes.byref(t)))
+
+    def tiles(self) -> dict:
+        t = Tiles()
+        _check(lib().cq_crowd_get_tiles(self._h, ctypes.byref(t)))
+        return dict(candidates=t.candidates, gather_blocks_per_cu=t.gather_blocks_per_cu)
+
+    def autotune_tiles(self, sweeps_per_candidate: int = 1, cache_path=None):
+        """Time the candidate launch shapes (or take them from the JSON cache); returns
+        (tiles dict, from_cache)."""
+        t, hit = Tiles(), ctypes.c_int()
+        path = None if cache_path is None else os.fsencode(cache_path)
+        _check(lib().cq_crowd_autotune_tiles(self._h, int(sweeps_per_candidate), path, ctypes.byref(t),
+                                             ctypes.byref(hit)))
+        return dict(candidates=t.candidates, gather_blocks_per_cu=t.gather_blocks_per_cu), bool(hit.value)
 
     def path(self) -> str:
         """The kernel path in use ("multi", "window", "batch" or "sweep")."""

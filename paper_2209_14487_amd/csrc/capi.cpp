@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "cq.h"
+#include "cq_host.h"
 #include "cq_internal.h"
 
 namespace {
@@ -38,6 +39,8 @@ cq_status fail(cq_status s, const std::string& msg)
 constexpr int kEventCap = 1 << 16;  // timed launches kept per kernel kind between reads
 
 }  // namespace
+
+cq_status cq::host_fail(cq_status s, const std::string& msg) { return fail(s, msg); }
 
 struct cq_system {
     int n_up = 0, n_dn = 0;
@@ -63,6 +66,9 @@ struct cq_crowd {
     int W = 0, n = 0, ne = 0, K = 1, Q = 1, QR = 1, prec = CQ_MIXED, recompute_every = 0, use_graph = 0;
     int Wcap = 0;  // capacity of the per-walker buffers (DMC populations)
     int Kcap = 1;  // largest delay rank the window buffers hold
+    // batched path: candidate buffers hold Qcap per walker; q_req (0: the default rule) and
+    // vgl_wg (gather workgroups per CU beside the update, 0: built-in) are cq_crowd_set_tiles'
+    int Qcap = 1, q_req = 0, vgl_wg = 0;
     bool autotune = false, tuned = false;
     int path = CQ_PATH_WINDOW;
     uint64_t seed = 0;
@@ -201,6 +207,7 @@ cq::CrowdView<T> view(const cq_crowd* c)
     v.K = c->K;
     v.Q = c->Q;
     v.QR = c->QR;
+    v.vgl_wg = c->vgl_wg;
     v.G = c->sys->G;
     v.n_orb = c->sys->n_orb;
     v.L = c->sys->L;
@@ -333,6 +340,23 @@ int planned_rounds(const cq_crowd* c, int spin, int rounds)
     return p > 0 && p < rounds ? p : rounds;
 }
 
+// Candidates per round for the current delay rank: the requested Q (cq_crowd_set_tiles) or
+// the default rule, at least min(k, N) (so N / k rounds finish a block) and at most the
+// buffers' Qcap.
+int min_candidates(const cq_crowd* c) { return std::min(std::max(c->K, 2), c->n); }
+
+void apply_q(cq_crowd* c)
+{
+    if (c->path != CQ_PATH_BATCH) {
+        c->Q = c->QR = c->K;
+        return;
+    }
+    int q = c->q_req > 0 ? c->q_req : cq::batch_candidates(c->n, c->K);
+    q = std::min(std::max(q, min_candidates(c)), c->Qcap);
+    c->Q = q;
+    c->QR = 2 * q;
+}
+
 void reset_plan(cq_crowd* c)
 {
     c->plan[0] = c->plan[1] = -1;
@@ -347,10 +371,12 @@ bool update_plan(cq_crowd* c)
 {
     if (!c->hplan || c->path != CQ_PATH_BATCH || c->plan_fixed > 0) return false;
     const volatile int* h = c->hplan;
-    if (!h[0]) return false;
+    const int have = h[0];  // bit s: spin s has reported since the plan restarted
+    if (!have) return false;
     const int rounds = cq::batch_rounds(c->n, c->K);
     bool changed = false;
     for (int s = 0; s < 2; ++s) {
+        if (!((have >> s) & 1)) continue;
         const int used = h[1 + 2 * s], left = h[2 + 2 * s];
         int want = used + kPlanMargin;
         if (left) want = std::max(want, (c->plan[s] > 0 ? c->plan[s] : used) + 2 * kPlanMargin);
@@ -1167,6 +1193,7 @@ cq_status cq_crowd_create(const cq_system* const* systems, const int* walkers_pe
     c->path = path;
     c->Q = c->path == CQ_PATH_BATCH ? cq::batch_candidates(c->n, K) : K;
     c->QR = c->path == CQ_PATH_BATCH ? 2 * c->Q : c->Q;
+    c->Qcap = c->Q;  // the candidate buffers below are sized for it
     c->seed = desc->seed;
     c->first_uid = desc->first_uid;
     if (desc->hip_stream) {
@@ -1363,8 +1390,7 @@ static cq_status autotune_k(cq_crowd* c, int sweeps, int* chosen)
     cands.push_back(c->Kcap);
     for (int k : cands) {
         c->K = k;
-        c->Q = c->path == CQ_PATH_BATCH ? cq::batch_candidates(c->n, k) : k;
-        c->QR = c->path == CQ_PATH_BATCH ? 2 * c->Q : c->Q;
+        apply_q(c);
         drop_graph(c);
         reset_plan(c);  // the previous candidate's sweeps have completed (event synchronised)
         if (c->path == CQ_PATH_MULTI) {
@@ -1397,8 +1423,7 @@ static cq_status autotune_k(cq_crowd* c, int sweeps, int* chosen)
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     c->K = best_k;
-    c->Q = c->path == CQ_PATH_BATCH ? cq::batch_candidates(c->n, best_k) : best_k;
-    c->QR = c->path == CQ_PATH_BATCH ? 2 * c->Q : c->Q;
+    apply_q(c);
     drop_graph(c);
     reset_plan(c);
     c->tuned = true;
@@ -1631,6 +1656,176 @@ cq_status cq_crowd_get_path(cq_crowd* c, int* path)
     if (!c || !path) return fail(CQ_EINVAL, "NULL argument");
     *path = c->subs.empty() ? c->path : c->subs[0]->path;
     return CQ_OK;
+}
+
+cq_status cq_crowd_set_tiles(cq_crowd* c, const cq_tiles* t)
+{
+    if (!c || !t) return fail(CQ_EINVAL, "NULL argument");
+    if (!c->subs.empty()) {
+        for (cq_crowd* sub : c->subs) {
+            cq_status st = cq_crowd_set_tiles(sub, t);
+            if (st != CQ_OK) return st;
+        }
+        return CQ_OK;
+    }
+    if (t->gather_blocks_per_cu < 0 || t->gather_blocks_per_cu > 8)
+        return fail(CQ_EINVAL, "gather_blocks_per_cu must be 0..8");
+    if (t->candidates < 0) return fail(CQ_EINVAL, "candidates must be >= 0");
+    if (c->path != CQ_PATH_BATCH) return CQ_OK;
+    if (t->candidates > 0 && (t->candidates < min_candidates(c) || t->candidates > c->Qcap))
+        return fail(CQ_EINVAL, "candidates must lie in [" + std::to_string(min_candidates(c)) + ", " +
+                                   std::to_string(c->Qcap) + "] at this delay rank");
+    // rounds per block depend on Q: restart the plan once no report of the old shapes is due
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->q_req = t->candidates;
+    c->vgl_wg = t->gather_blocks_per_cu;
+    apply_q(c);
+    drop_graph(c);
+    reset_plan(c);
+    return CQ_OK;
+}
+
+cq_status cq_crowd_get_tiles(cq_crowd* c, cq_tiles* t)
+{
+    if (!c || !t) return fail(CQ_EINVAL, "NULL argument");
+    cq_crowd* x = c->subs.empty() ? c : c->subs[0];
+    if (x->path != CQ_PATH_BATCH) {
+        t->candidates = 0;
+        t->gather_blocks_per_cu = 0;
+        return CQ_OK;
+    }
+    t->candidates = x->Q;
+    t->gather_blocks_per_cu = cq::batch_vgl_blocks_per_cu(x->n, x->prec == CQ_FP64 ? 8 : 4, x->vgl_wg);
+    return CQ_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// "<architecture>/<compute units>cu" of the current device, the tile cache's device key
+cq_status device_key(std::string* key)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, dev));
+    std::string arch;
+    for (const char* p = prop.gcnArchName; *p && arch.size() < 100; ++p)
+        if (*p != '"' && *p != '\\' && (unsigned char)*p >= 0x20) arch.push_back(*p);
+    *key = (arch.empty() ? std::string("unknown") : arch) + "/" + std::to_string(prop.multiProcessorCount) + "cu";
+    return CQ_OK;
+}
+
+// Time `sweeps` eager sweeps of the chain (after one untimed sweep that learns the round
+// plan for the current shapes); *ms per sweep.
+cq_status time_sweeps(cq_crowd* c, int sweeps, hipEvent_t a, hipEvent_t b, float* ms)
+{
+    auto one = [&]() {
+        if (update_plan(c)) drop_graph(c);
+        sweep(c);
+        c->hp.step += 1;
+        c->hp.rec_sweep += 1;
+    };
+    one();
+    HIP_TRY(hipStreamSynchronize(c->stream));  // the plan report of that sweep is in
+    cq_status es = enqueue_status(c, "tile autotune sweep");
+    if (es != CQ_OK) return es;
+    (void)update_plan(c);
+    HIP_TRY(hipEventRecord(a, c->stream));
+    for (int s = 0; s < sweeps; ++s) {
+        sweep(c);
+        c->hp.step += 1;
+        c->hp.rec_sweep += 1;
+    }
+    HIP_TRY(hipEventRecord(b, c->stream));
+    HIP_TRY(hipEventSynchronize(b));
+    es = enqueue_status(c, "tile autotune sweep");
+    if (es != CQ_OK) return es;
+    float t = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&t, a, b));
+    *ms = t / sweeps;
+    return CQ_OK;
+}
+
+cq_status autotune_tiles(cq_crowd* c, int sweeps, const char* cache, cq_tiles* chosen, int* from_cache)
+{
+    if (from_cache) *from_cache = 0;
+    if (c->path != CQ_PATH_BATCH) return chosen ? cq_crowd_get_tiles(c, chosen) : CQ_OK;
+    if (c->autotune && !c->tuned) {  // the delay rank is part of the key: choose it first
+        cq_status st = autotune_k(c, 1, nullptr);
+        if (st != CQ_OK) return st;
+    }
+    std::string dev;
+    cq_status st = device_key(&dev);
+    if (st != CQ_OK) return st;
+    if (cache) {
+        cq_tiles t{};
+        int found = 0;
+        st = cq_tile_cache_find(cache, dev.c_str(), c->n, c->W, c->prec, c->K, &t, &found);
+        if (st != CQ_OK) return st;
+        if (found && cq_crowd_set_tiles(c, &t) == CQ_OK) {
+            if (from_cache) *from_cache = 1;
+            return chosen ? cq_crowd_get_tiles(c, chosen) : CQ_OK;
+        }
+    }
+    // candidates: Q in {1.5 k, 2 k, default}, gather workgroups per CU in {1, 2, 3}
+    std::vector<int> qs;
+    const int qdef = std::min(std::max(cq::batch_candidates(c->n, c->K), min_candidates(c)), c->Qcap);
+    for (int q : {(3 * c->K + 1) / 2, 2 * c->K, qdef}) {
+        q = std::min(std::max(q, min_candidates(c)), c->Qcap);
+        if (std::find(qs.begin(), qs.end(), q) == qs.end()) qs.push_back(q);
+    }
+    hipEvent_t a, b;
+    HIP_TRY(hipEventCreate(&a));
+    if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return fail(CQ_EDEVICE, "hipEventCreate failed");
+    }
+    cq_tiles best{0, 0};
+    float best_ms = 0.0f;
+    for (int q : qs)
+        for (int g = 1; g <= 3 && st == CQ_OK; ++g) {
+            const cq_tiles t{q, g};
+            st = cq_crowd_set_tiles(c, &t);
+            float ms = 0.0f;
+            if (st == CQ_OK) st = time_sweeps(c, sweeps, a, b, &ms);
+            if (st == CQ_OK && (best_ms == 0.0f || ms < best_ms)) {
+                best_ms = ms;
+                best = t;
+            }
+        }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (st != CQ_OK) return st;
+    st = cq_crowd_set_tiles(c, &best);
+    if (st != CQ_OK) return st;
+    if (cache) {
+        st = cq_tile_cache_store(cache, dev.c_str(), c->n, c->W, c->prec, c->K, &best, best_ms);
+        if (st != CQ_OK) return st;
+    }
+    if (chosen) *chosen = best;
+    return check_singular(c, "tile autotune");
+}
+
+}  // namespace
+
+extern "C" {
+
+cq_status cq_crowd_autotune_tiles(cq_crowd* c, int sweeps_per_candidate, const char* cache_path, cq_tiles* chosen,
+                                  int* from_cache)
+{
+    if (!c) return fail(CQ_EINVAL, "crowd is NULL");
+    if (sweeps_per_candidate < 1) return fail(CQ_EINVAL, "sweeps_per_candidate must be >= 1");
+    if (!c->subs.empty()) {
+        for (cq_crowd* sub : c->subs) {
+            cq_status st = cq_crowd_autotune_tiles(sub, sweeps_per_candidate, cache_path, nullptr, from_cache);
+            if (st != CQ_OK) return st;
+        }
+        return chosen ? cq_crowd_get_tiles(c, chosen) : CQ_OK;
+    }
+    if (!c->ready) return fail(CQ_ESTATE, "set positions before autotuning");
+    return autotune_tiles(c, sweeps_per_candidate, cache_path, chosen, from_cache);
 }
 
 cq_status cq_crowd_get_delay_rank(cq_crowd* c, int* k)

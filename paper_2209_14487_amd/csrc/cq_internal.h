@@ -63,6 +63,7 @@ struct CrowdView {
     int arow;            // row stride of the value rows in VGL read by the inversion (5 N in a crowd)
     int Wcap;            // walker capacity: the walker stride of the record and forced-decision buffers
     int Q;               // candidates per round (batched path), else K
+    int vgl_wg;          // gather workgroups per CU beside the update (batched path; 0: built-in rule)
     int QR;              // stage slots per walker: K, or the candidate ring of the batched path (2 Q,
                          // so a round's new candidates never reuse a slot the previous window's
                          // update still reads)
@@ -192,6 +193,8 @@ int window_threads(int n, int elem_bytes);
 template <typename T>
 void launch_batch_stencils(const CrowdView<T>& v, int spin, int par, bool block_start, hipStream_t s);
 template <typename T> void launch_batch_vgl(const CrowdView<T>& v, int spin, int par, bool beside, hipStream_t s);
+// workgroups per CU of the gather launched beside the update: the request, else the built-in rule
+int batch_vgl_blocks_per_cu(int n, int elem_bytes, int request);
 template <typename T> void launch_batch_jd(const CrowdView<T>& v, int spin, hipStream_t s);
 template <typename T> void launch_batch_pmat(const CrowdView<T>& v, int spin, hipStream_t s);
 template <typename T> void launch_batch_rows(const CrowdView<T>& v, int spin, hipStream_t s);

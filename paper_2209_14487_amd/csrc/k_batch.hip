@@ -949,20 +949,26 @@ int device_cu_count()
     return cus;
 }
 
+int batch_vgl_blocks_per_cu(int n, int elem_bytes, int request)
+{
+    if (request > 0) return request;
+    return vgl_groups(n, elem_bytes) >= 64 ? kVglWaveBlocksPerCU : kVglBlocksPerCU;
+}
+
 template <typename T>
 void launch_batch_vgl(const CrowdView<T>& v, int spin, int par, bool beside, hipStream_t s)
 {
     const int groups = vgl_groups(v.n, sizeof(T));
+    const int per_cu = beside ? batch_vgl_blocks_per_cu(v.n, sizeof(T), v.vgl_wg) : kVglBlocksPerCUAlone;
     if (groups >= 64) {
         const int items = v.W * v.Q * ((groups + 63) / 64);
-        const int nb = std::min((items + kBlock / 64 - 1) / (kBlock / 64),
-                                (beside ? kVglWaveBlocksPerCU : kVglBlocksPerCUAlone) * device_cu_count());
+        const int nb = std::min((items + kBlock / 64 - 1) / (kBlock / 64), per_cu * device_cu_count());
         hipLaunchKernelGGL(k_prop_vgl_wave<T>, dim3(nb), dim3(kBlock), 0, s, v, spin, par);
         return;
     }
     const int pp = kVglSmallPP;
     const int nchunk = (v.W * v.Q + pp - 1) / pp;
-    const int nb = std::min(nchunk, (beside ? kVglBlocksPerCU : kVglBlocksPerCUAlone) * device_cu_count());
+    const int nb = std::min(nchunk, per_cu * device_cu_count());
     const size_t lds = (size_t)pp * (64 * sizeof(size_t) + 64 * 5 * sizeof(T)) + 4 * sizeof(int);
     hipLaunchKernelGGL(k_prop_vgl<T>, dim3(nb), dim3(vgl_small_threads(v.n, sizeof(T))), lds, s, v, spin, pp, par);
 }

@@ -159,15 +159,16 @@ __global__ __launch_bounds__(kBlock) void k_leftover(CrowdView<T> v, int spin)
 }
 
 // The block's plan record for the host (pinned memory): out[1 + 2 spin] = rounds in which
-// some walker had candidates, out[2 + 2 spin] = whether k_leftover had work; out[0] = 1
-// once a record has been written.
+// some walker had candidates, out[2 + 2 spin] = whether k_leftover had work; bit `spin` of
+// out[0] is set once that spin's record has been written (the host clears out[0] when the
+// plan restarts, so a spin's fields are read only after a record of its own).
 __global__ void k_plan_report(const int* used, const int* left, int spin, int* out)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         out[1 + 2 * spin] = used[spin];
         out[2 + 2 * spin] = left[spin];
         __threadfence_system();
-        out[0] = 1;
+        out[0] = out[0] | (1 << spin);
     }
 }
 

@@ -22,6 +22,8 @@ nothing about another chain that groups its sums differently (the GPU's rank-k
 updates against the model's rank-1 steps).
 log|det| within 1e-4 of max(1, |log|det||).
 """
+import json
+
 import numpy as np
 import pytest
 
@@ -551,6 +553,59 @@ def test_autotuned_delay_rank_keeps_the_chain():
     assert np.all(np.abs(rec["rho"][0] - ref.rho[tuned_sweeps]) <= 1e-10 * np.maximum(1.0, np.abs(ref.rho[tuned_sweeps])))
     crowd.close()
 
+
+
+def test_tile_autotune_keeps_the_chain_and_uses_its_cache(tmp_path):
+    """cq_crowd_autotune_tiles times every pair (Q, gather workgroups per CU) with one untimed
+    and one timed sweep each; those are ordinary sweeps of the chain, so the chain after tuning
+    is still the FP64 oracle's.  The choice goes into the JSON cache, and a second crowd with
+    the same key takes it from there without running a sweep."""
+    n, L, G, W, S, k, seed = 32, 10.0, 48, 8, 1, 4, 1011
+    g, o = make_pair(n, L, G, seed, coef_seed=seed)
+    R0 = start_positions(seed, W, 2 * n, L)
+    cache = str(tmp_path / "tiles.json")
+    crowd = cq.Crowd(g, W, precision="fp64", delay_rank=k, seed=seed, path="batch")
+    assert crowd.tiles()["candidates"] == 12  # min(88, 3 k, N)
+    crowd.set_positions(R0)
+    t, hit = crowd.autotune_tiles(1, cache)
+    assert not hit and t["candidates"] in (6, 8, 12) and t["gather_blocks_per_cu"] in (1, 2, 3)
+    assert crowd.tiles() == t
+    tuned_sweeps = 3 * 3 * 2  # Q in {6, 8, 12} x {1, 2, 3} workgroups per CU, 1 + 1 sweeps each
+    crowd.record(S)
+    crowd.run_vmc(S, 0.5)
+    ref = orc.vmc(o, R0, tuned_sweeps + S, sigma=0.5)
+    rec = crowd.records()
+    assert np.array_equal(rec["acc"][0], ref.acc[tuned_sweeps])
+    for key in ("rho", "dlnj", "prob"):
+        b = getattr(ref, key)[tuned_sweeps]
+        assert np.all(np.abs(rec[key][0] - b) <= 1e-10 * np.maximum(1.0, np.abs(b))), key
+    entry = json.load(open(cache))[-1]
+    assert (entry["n"], entry["walkers"], entry["precision"], entry["delay_rank"]) == (n, W, "fp64", k)
+    assert (entry["candidates"], entry["gather_blocks_per_cu"]) == (t["candidates"], t["gather_blocks_per_cu"])
+    crowd.close()
+    # the same key again: from the cache, no sweep run (the chain starts at sweep 0)
+    crowd = cq.Crowd(g, W, precision="fp64", delay_rank=k, seed=seed, path="batch")
+    crowd.set_positions(R0)
+    t2, hit = crowd.autotune_tiles(1, cache)
+    assert hit and t2 == t and crowd.tiles() == t
+    crowd.record(S)
+    crowd.run_vmc(S, 0.5)
+    rec = crowd.records()
+    assert np.array_equal(rec["acc"][0], ref.acc[0])
+    assert np.all(np.abs(rec["rho"][0] - ref.rho[0]) <= 1e-10 * np.maximum(1.0, np.abs(ref.rho[0])))
+    # shapes out of range are refused and change nothing; other paths report none
+    for bad in (dict(candidates=3), dict(candidates=13), dict(gather_blocks_per_cu=9)):
+        with pytest.raises(cq.CqError) as ei:
+            crowd.set_tiles(**bad)
+        assert ei.value.status == cq.CQ_EINVAL
+    assert crowd.tiles() == t
+    crowd.close()
+    sweep = cq.Crowd(g, W, precision="fp64", seed=seed, path="sweep")
+    sweep.set_positions(R0)
+    assert sweep.tiles() == dict(candidates=0, gather_blocks_per_cu=0)
+    assert sweep.autotune_tiles(1, cache) == (dict(candidates=0, gather_blocks_per_cu=0), False)
+    sweep.close()
+    g.close()
 
 # Full C4 size: 1024 + 1024 electrons, L = 32, 96^3 seeded table, Pade J2, a crowd of 128
 # walkers, delayed rank 32 on the batched path.  The oracle follows three sampled walkers
