@@ -25,7 +25,8 @@ from typing import Optional
 
 import numpy as np
 
-__all__ = ["Workload", "WORKLOADS", "start_positions", "planewave_table", "workload", "icosahedron_offsets"]
+__all__ = ["Workload", "WORKLOADS", "start_positions", "planewave_table", "workload", "icosahedron_offsets",
+           "TRICLINIC", "cell_positions", "complex_table"]
 
 
 @dataclass(frozen=True)
@@ -118,3 +119,33 @@ def icosahedron_offsets(radius: float) -> np.ndarray:
             v += [(0.0, a, b), (a, b, 0.0), (b, 0.0, a)]
     v = np.array(v)
     return radius * v / np.linalg.norm(v, axis=1, keepdims=True)
+
+
+# A general (triclinic) cell for the complex-orbital tests and workload: lattice vectors as rows,
+# bohr (edges 10.0, 9.0 and 11.0; angles of about 100 degrees between a1 and a2, 70 between a1
+# and a3, 86 between a2 and a3; volume 907 bohr^3).
+TRICLINIC = np.array([[10.0, 0.0, 0.0],
+                      [-1.5, 8.874119674649425, 0.0],
+                      [3.7622215, 1.5, 10.221357245]])
+
+
+def cell_positions(seed: int, n_walkers: int, n_e: int, lattice, first_walker: int = 0) -> np.ndarray:
+    """Uniform starting positions in the cell spanned by the rows of `lattice`: uniform fractional
+    coordinates f in [0, 1)^3, r = f @ lattice.  Shape [W][Ne][3], FP64; walker w depends only on
+    (seed, first_walker + w)."""
+    lat = np.asarray(lattice, dtype=np.float64)
+    out = np.empty((n_walkers, n_e, 3))
+    for w in range(n_walkers):
+        rng = np.random.default_rng([seed, first_walker + w, 7])
+        out[w] = rng.uniform(0.0, 1.0, size=(n_e, 3)) @ lat
+    return out
+
+
+def complex_table(seed: int, G: int, n: int) -> np.ndarray:
+    """Seeded complex B-spline coefficients, real and imaginary parts U[-1, 1], shape [G][G][G][n]
+    complex128 (orbital index fastest)."""
+    rng = np.random.default_rng([seed, G, n, 11])
+    t = np.empty((G, G, G, n), np.complex128)
+    t.real = rng.uniform(-1.0, 1.0, size=t.shape)
+    t.imag = rng.uniform(-1.0, 1.0, size=t.shape)
+    return t
