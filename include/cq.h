@@ -412,6 +412,69 @@ cq_status cq_crowd_synchronize(cq_crowd* c);
 
 void cq_crowd_destroy(cq_crowd* c);
 
+/* ------------------------------------------- complex orbitals, general cells */
+
+/* Bloch orbitals with a twist in a general (triclinic) periodic cell: the same move of
+   Alg. 1 with complex orbitals and determinants.  FP64 throughout.
+     phi_j(r) = exp(i k.r) s_j(f),  f = r L^-1 (fractional coordinates; L [3][3] holds the
+     lattice vectors as rows, r = f L), s_j a periodic uniform cubic B-spline over a G^3 grid
+     in f with complex coefficients (control point q of an axis at f = q / G).
+   Cartesian derivatives come through L^-1 (gradient) and the metric L^-T L^-1 with the full
+   Hessian in f (Laplacian); the twist adds i k s to the gradient and 2 i k.grad s - k^2 s to
+   the Laplacian.  Positions are kept wrapped into the cell, f - floor(f), and phi is taken at
+   the wrapped position (|Psi| and every ratio of derivatives are unaffected; the phase of Psi
+   follows the wrapped coordinates).  The pair Jastrow takes the minimum image in fractional
+   coordinates, d - rint(d L^-1) L.  A move is accepted when u < |rho_D|^2 exp(2 dlnJ), the
+   Slater inverses follow each acceptance by a Sherman-Morrison update (delay rank 1), and the
+   kinetic local energy -1/2 sum_i lap_i Psi / Psi is complex (its real part is the estimator).
+   Random numbers as for cq_crowd_run_vmc: Philox counters (uid, step, e, 0..2).  VMC only. */
+typedef struct cq_csystem cq_csystem;  /* complex orbitals + cell + twist + Jastrow (opaque) */
+typedef struct cq_ccrowd cq_ccrowd;    /* walkers of a complex system (opaque) */
+
+/* n electrons per spin (1..512), lattice [3][3] (rows, bohr; non-degenerate), twist [3]
+   (Cartesian, 1/bohr; NULL = 0).  Errors: CQ_EINVAL. */
+cq_status cq_csystem_create(int n, const double* lattice, const double* twist, cq_csystem** out);
+/* Complex coefficients [G][G][G][n_orb] (interleaved real, imaginary FP64; orbital index
+   fastest), grid G >= 4, n_orb == n.  coefs_on_device = 0: host array, copied; 1: a device
+   buffer the system borrows (it must outlive the system).  Errors: CQ_EINVAL, CQ_ENOMEM. */
+cq_status cq_csystem_load_bspline(cq_csystem* sys, const void* coefs, int grid, int n_orb, int coefs_on_device);
+/* Pade pair Jastrow u(r) = a r / (1 + b r) (a_par equal spins, a_anti opposite). */
+cq_status cq_csystem_load_pade_j2(cq_csystem* sys, double a_par, double a_anti, double b);
+void cq_csystem_destroy(cq_csystem* sys);
+
+/* A crowd of `walkers` walkers (uids first_uid + w) on a borrowed hipStream_t or its own
+   (hip_stream NULL).  Device buffers: inverses and orbital rows, 16 (2 n^2 + 10 n^2) bytes per
+   walker, plus a Gauss-Jordan workspace of 64 n^2 bytes.  Errors: CQ_EINVAL (no table),
+   CQ_ENOMEM, CQ_EDEVICE. */
+cq_status cq_ccrowd_create(const cq_csystem* sys, int walkers, uint64_t seed, uint32_t first_uid, void* hip_stream,
+                           cq_ccrowd** out);
+/* Positions R [W][2n][3] (host), then the orbital rows of every electron, both inverses
+   (Gauss-Jordan with partial pivoting by modulus), log|det|, phase and E_L.  Resets the
+   counters; the next sweep uses step first_step.  Errors: CQ_EINVAL, CQ_ESINGULAR (names the
+   walker). */
+cq_status cq_ccrowd_set_positions(cq_ccrowd* c, const double* R, uint32_t first_step);
+/* n_sweeps sweeps (one kernel launch each, every walker at once, each electron in index order)
+   and the local energy after each; asynchronous.  Errors: CQ_EINVAL, CQ_ESTATE. */
+cq_status cq_ccrowd_run_vmc(cq_ccrowd* c, int n_sweeps, double sigma);
+/* Fresh inverses, log|det| and phase from the current orbital rows (FP64 recompute);
+   *max_drift (may be NULL) = max |log|det| kept - log|det| fresh| over walkers and spins. */
+cq_status cq_ccrowd_recompute(cq_ccrowd* c, double* max_drift);
+/* log|det| [W][2] and phase [W][2] (radians in [-pi, pi]). */
+cq_status cq_ccrowd_get_logdet(cq_ccrowd* c, double* logdet, double* phase);
+/* E_L [W][2] (real, imaginary). */
+cq_status cq_ccrowd_get_local_energy(cq_ccrowd* c, double* el);
+cq_status cq_ccrowd_get_positions(cq_ccrowd* c, double* R);
+cq_status cq_ccrowd_get_acceptance(cq_ccrowd* c, int64_t* accepted, int64_t* proposed);
+/* A^-1 of one walker and spin, [n][n][2] (row j orbital, column i electron; real, imaginary). */
+cq_status cq_ccrowd_get_inverse(cq_ccrowd* c, int walker, int spin, double* out);
+/* Keep the ratio rho [S][2n][W][2], ln J change, acceptance probability and decision of
+   every move of the next n_sweeps sweeps (0: stop recording).  get_move_records copies them
+   out (CQ_ESTATE when recording is off). */
+cq_status cq_ccrowd_record_moves(cq_ccrowd* c, int n_sweeps);
+cq_status cq_ccrowd_get_move_records(cq_ccrowd* c, double* rho, double* dlnj, double* prob, uint8_t* acc);
+cq_status cq_ccrowd_synchronize(cq_ccrowd* c);
+void cq_ccrowd_destroy(cq_ccrowd* c);
+
 /* ------------------------------------------------------------ batched inverse */
 
 /* The FP64 recompute of the Slater inverses (Gauss-Jordan with partial pivoting,

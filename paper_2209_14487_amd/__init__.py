@@ -97,9 +97,26 @@ _SIGS = {
     "cq_slater_inverse": [_P, _I, _I, _I, _P, _P, _P, _P],
     "cq_slater_inverse_static": [_P, _I, _I, _I, _P, _P, _P, _P],
     "cq_crowd_destroy": [_P],
+    "cq_csystem_create": [_I, _P, _P, _P],
+    "cq_csystem_load_bspline": [_P, _P, _I, _I, _I],
+    "cq_csystem_load_pade_j2": [_P, ctypes.c_double, ctypes.c_double, ctypes.c_double],
+    "cq_csystem_destroy": [_P],
+    "cq_ccrowd_create": [_P, _I, ctypes.c_uint64, ctypes.c_uint32, _P, _P],
+    "cq_ccrowd_set_positions": [_P, _P, ctypes.c_uint32],
+    "cq_ccrowd_run_vmc": [_P, _I, ctypes.c_double],
+    "cq_ccrowd_recompute": [_P, _P],
+    "cq_ccrowd_get_logdet": [_P, _P, _P],
+    "cq_ccrowd_get_local_energy": [_P, _P],
+    "cq_ccrowd_get_positions": [_P, _P],
+    "cq_ccrowd_get_acceptance": [_P, _P, _P],
+    "cq_ccrowd_get_inverse": [_P, _I, _I, _P],
+    "cq_ccrowd_record_moves": [_P, _I],
+    "cq_ccrowd_get_move_records": [_P, _P, _P, _P, _P],
+    "cq_ccrowd_synchronize": [_P],
+    "cq_ccrowd_destroy": [_P],
     "cq_last_error": [],
 }
-_VOID = {"cq_system_destroy", "cq_crowd_destroy"}
+_VOID = {"cq_system_destroy", "cq_crowd_destroy", "cq_csystem_destroy", "cq_ccrowd_destroy"}
 
 
 def lib():
@@ -570,6 +587,128 @@ class Crowd:
     def close(self):
         if self._h:
             lib().cq_crowd_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class ComplexSystem:
+    """Complex (Bloch) orbitals with a twist in a general cell (cq_csystem); FP64."""
+
+    def __init__(self, n_per_spin: int, lattice, twist=(0.0, 0.0, 0.0)):
+        lat = np.ascontiguousarray(np.asarray(lattice, dtype=np.float64).reshape(3, 3))
+        k = np.ascontiguousarray(np.asarray(twist, dtype=np.float64).reshape(3))
+        h = ctypes.c_void_p()
+        _check(lib().cq_csystem_create(n_per_spin, lat.ctypes.data, k.ctypes.data, ctypes.byref(h)))
+        self._h = h
+        self.n = n_per_spin
+        self._keep = []
+
+    def load_table(self, table):
+        """table [G][G][G][N] complex128: numpy (copied) or a complex128 torch CUDA tensor (borrowed)."""
+        G = table.shape[0]
+        if isinstance(table, np.ndarray):
+            arr = np.ascontiguousarray(table, dtype=np.complex128)
+            _check(lib().cq_csystem_load_bspline(self._h, arr.ctypes.data, G, table.shape[3], 0))
+        else:
+            assert table.is_contiguous() and table.element_size() == 16
+            self._keep.append(table)
+            _check(lib().cq_csystem_load_bspline(self._h, table.data_ptr(), G, table.shape[3], 1))
+
+    def load_j2(self, a_par=0.25, a_anti=0.5, b=1.0):
+        _check(lib().cq_csystem_load_pade_j2(self._h, a_par, a_anti, b))
+
+    def close(self):
+        if self._h:
+            lib().cq_csystem_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class ComplexCrowd:
+    """Walkers of a ComplexSystem moved by one sweep kernel per sweep (cq_ccrowd)."""
+
+    def __init__(self, system: ComplexSystem, walkers: int, seed: int = 0, first_uid: int = 0, stream=None):
+        h = ctypes.c_void_p()
+        _check(lib().cq_ccrowd_create(system._h, walkers, seed, first_uid, stream, ctypes.byref(h)))
+        self._h = h
+        self.sys = system
+        self.W = walkers
+        self.n = system.n
+        self._rec = 0
+
+    def set_positions(self, R, first_step: int = 0):
+        R = np.ascontiguousarray(R, dtype=np.float64)
+        assert R.shape == (self.W, 2 * self.n, 3)
+        _check(lib().cq_ccrowd_set_positions(self._h, R.ctypes.data, first_step))
+
+    def run_vmc(self, n_sweeps: int, sigma: float = 0.5):
+        _check(lib().cq_ccrowd_run_vmc(self._h, n_sweeps, sigma))
+
+    def recompute(self) -> float:
+        d = ctypes.c_double()
+        _check(lib().cq_ccrowd_recompute(self._h, ctypes.byref(d)))
+        return d.value
+
+    def logdet(self):
+        """(log|det| [W][2], phase [W][2])."""
+        ld = np.zeros((self.W, 2))
+        ph = np.zeros((self.W, 2))
+        _check(lib().cq_ccrowd_get_logdet(self._h, ld.ctypes.data, ph.ctypes.data))
+        return ld, ph
+
+    def local_energy(self):
+        el = np.zeros((self.W, 2))
+        _check(lib().cq_ccrowd_get_local_energy(self._h, el.ctypes.data))
+        return el[:, 0] + 1j * el[:, 1]
+
+    def positions(self):
+        R = np.zeros((self.W, 2 * self.n, 3))
+        _check(lib().cq_ccrowd_get_positions(self._h, R.ctypes.data))
+        return R
+
+    def acceptance(self):
+        a = np.zeros(self.W, np.int64)
+        p = np.zeros(self.W, np.int64)
+        _check(lib().cq_ccrowd_get_acceptance(self._h, a.ctypes.data, p.ctypes.data))
+        return a, p
+
+    def inverse(self, walker: int, spin: int):
+        """A^-1 [n][n] complex (row j orbital, column i electron)."""
+        out = np.zeros((self.n, self.n, 2))
+        _check(lib().cq_ccrowd_get_inverse(self._h, walker, spin, out.ctypes.data))
+        return out[..., 0] + 1j * out[..., 1]
+
+    def record(self, n_sweeps: int):
+        _check(lib().cq_ccrowd_record_moves(self._h, n_sweeps))
+        self._rec = n_sweeps
+
+    def records(self):
+        """rho [S][Ne][W] complex, dlnj, prob [S][Ne][W], acc [S][Ne][W] uint8."""
+        shp = (self._rec, 2 * self.n, self.W)
+        rho = np.zeros(shp + (2,))
+        dj = np.zeros(shp)
+        pr = np.zeros(shp)
+        acc = np.zeros(shp, np.uint8)
+        _check(lib().cq_ccrowd_get_move_records(self._h, rho.ctypes.data, dj.ctypes.data, pr.ctypes.data,
+                                                acc.ctypes.data))
+        return dict(rho=rho[..., 0] + 1j * rho[..., 1], dlnj=dj, prob=pr, acc=acc)
+
+    def synchronize(self):
+        _check(lib().cq_ccrowd_synchronize(self._h))
+
+    def close(self):
+        if self._h:
+            lib().cq_ccrowd_destroy(self._h)
             self._h = None
 
     def __del__(self):
