@@ -472,6 +472,10 @@ cq_status cq_ccrowd_get_inverse(cq_ccrowd* c, int walker, int spin, double* out)
    out (CQ_ESTATE when recording is off). */
 cq_status cq_ccrowd_record_moves(cq_ccrowd* c, int n_sweeps);
 cq_status cq_ccrowd_get_move_records(cq_ccrowd* c, double* rho, double* dlnj, double* prob, uint8_t* acc);
+/* HIP events around every launch of the sweep kernel while on (set_timing also clears the
+   record); get_timing returns their total device time (ms) and count, then clears them. */
+cq_status cq_ccrowd_set_timing(cq_ccrowd* c, int on);
+cq_status cq_ccrowd_get_timing(cq_ccrowd* c, double* ms, int64_t* launches);
 cq_status cq_ccrowd_synchronize(cq_ccrowd* c);
 void cq_ccrowd_destroy(cq_ccrowd* c);
 

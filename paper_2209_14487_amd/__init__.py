@@ -112,6 +112,8 @@ _SIGS = {
     "cq_ccrowd_get_inverse": [_P, _I, _I, _P],
     "cq_ccrowd_record_moves": [_P, _I],
     "cq_ccrowd_get_move_records": [_P, _P, _P, _P, _P],
+    "cq_ccrowd_set_timing": [_P, _I],
+    "cq_ccrowd_get_timing": [_P, _P, _P],
     "cq_ccrowd_synchronize": [_P],
     "cq_ccrowd_destroy": [_P],
     "cq_last_error": [],
@@ -702,6 +704,16 @@ class ComplexCrowd:
         _check(lib().cq_ccrowd_get_move_records(self._h, rho.ctypes.data, dj.ctypes.data, pr.ctypes.data,
                                                 acc.ctypes.data))
         return dict(rho=rho[..., 0] + 1j * rho[..., 1], dlnj=dj, prob=pr, acc=acc)
+
+    def set_timing(self, on: bool = True):
+        _check(lib().cq_ccrowd_set_timing(self._h, int(on)))
+
+    def timing(self):
+        """(device ms, launches) of the sweep kernel since timing was switched on or last read."""
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        _check(lib().cq_ccrowd_get_timing(self._h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
 
     def synchronize(self):
         _check(lib().cq_ccrowd_synchronize(self._h))

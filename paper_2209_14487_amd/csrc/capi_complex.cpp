@@ -45,6 +45,10 @@ struct cq_ccrowd {
     double* rec_dlnj = nullptr;
     double* rec_prob = nullptr;
     uint8_t* rec_acc = nullptr;
+    // HIP events around every sweep-kernel launch while timing is on
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    size_t ev_used = 0;
 };
 
 namespace {
@@ -225,6 +229,10 @@ void cq_ccrowd_destroy(cq_ccrowd* c)
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     free_records(c);
+    for (auto& p : c->ev) {
+        (void)hipEventDestroy(p.first);
+        (void)hipEventDestroy(p.second);
+    }
     for (void* p : {(void*)c->R, (void*)c->M, (void*)c->VGL, (void*)c->logdet, (void*)c->phase, (void*)c->eloc,
                     (void*)c->nacc, (void*)c->nprop, (void*)c->uid, (void*)c->status, (void*)c->work})
         if (p) (void)hipFree(p);
@@ -324,7 +332,22 @@ cq_status cq_ccrowd_run_vmc(cq_ccrowd* c, int n_sweeps, double sigma)
     for (int s = 0; s < n_sweeps; ++s) {
         cq::CView v = cview(c);
         v.sigma = sigma;
+        std::pair<hipEvent_t, hipEvent_t>* e = nullptr;
+        if (c->timing) {
+            if (c->ev_used == c->ev.size()) {
+                std::pair<hipEvent_t, hipEvent_t> p{};
+                CHIP_TRY(hipEventCreate(&p.first));
+                if (hipEventCreate(&p.second) != hipSuccess) {
+                    (void)hipEventDestroy(p.first);
+                    return host_fail(CQ_EDEVICE, "hipEventCreate failed");
+                }
+                c->ev.push_back(p);
+            }
+            e = &c->ev[c->ev_used++];
+            CHIP_TRY(hipEventRecord(e->first, c->stream));
+        }
         cq::launch_csweep(v, c->stream);
+        if (e) CHIP_TRY(hipEventRecord(e->second, c->stream));
         cq::launch_cenergy(v, c->stream);
         c->step += 1;
         c->rec_sweep += 1;
@@ -436,6 +459,30 @@ cq_status cq_ccrowd_get_move_records(cq_ccrowd* c, double* rho, double* dlnj, do
     CHIP_TRY(hipMemcpy(dlnj, c->rec_dlnj, cnt * 8, hipMemcpyDeviceToHost));
     CHIP_TRY(hipMemcpy(prob, c->rec_prob, cnt * 8, hipMemcpyDeviceToHost));
     CHIP_TRY(hipMemcpy(acc, c->rec_acc, cnt, hipMemcpyDeviceToHost));
+    return CQ_OK;
+}
+
+cq_status cq_ccrowd_set_timing(cq_ccrowd* c, int on)
+{
+    if (!c) return host_fail(CQ_EINVAL, "crowd is NULL");
+    c->timing = on != 0;
+    c->ev_used = 0;
+    return CQ_OK;
+}
+
+cq_status cq_ccrowd_get_timing(cq_ccrowd* c, double* ms, int64_t* launches)
+{
+    if (!c || !ms || !launches) return host_fail(CQ_EINVAL, "NULL argument");
+    CHIP_TRY(hipStreamSynchronize(c->stream));
+    double t = 0.0;
+    for (size_t i = 0; i < c->ev_used; ++i) {
+        float x = 0.0f;
+        CHIP_TRY(hipEventElapsedTime(&x, c->ev[i].first, c->ev[i].second));
+        t += x;
+    }
+    *ms = t;
+    *launches = (int64_t)c->ev_used;
+    c->ev_used = 0;
     return CQ_OK;
 }
 
