@@ -5,8 +5,9 @@
 // after each acceptance), and the complex local energy.  Everything is FP64.
 //
 // A spline evaluation takes 64 stencil points of the complex table (16 bytes per
-// orbital, one thread per orbital, coalesced along the orbital index) with five real
-// weights per point: the value weight, the three Cartesian gradient weights
+// orbital, coalesced along the orbital index; in the sweep kernel one thread per orbital
+// and x-plane of the stencil when 4 N fits the workgroup, the four planes' sums then added
+// in order, else one thread per orbital) with five real weights per point: the value weight, the three Cartesian gradient weights
 // L^-1 (d/df_a) and the Laplacian weight sum_ab (L^-T L^-1)_ab d2/df_a df_b, so that the
 // cell's metric (including its off-diagonal Hessian terms) costs nothing per orbital.  The
 // twist multiplies the periodic part by exp(i k.r) and shifts the derivatives.
@@ -118,6 +119,22 @@ __device__ __forceinline__ void cstencil(const CView& v, const double r[3], int 
     sw[l * 5 + 4] = lap;
 }
 
+// The twisted rows from the periodic part's sums acc[5] (value, gradient, Laplacian):
+// phi = ph s, grad phi = ph (grad s + i k s), lap phi = ph (lap s + 2 i k.grad s - k^2 s).
+__device__ __forceinline__ void twist_rows(const CView& v, double2 ph, const double2 acc[5], double2 out[5])
+{
+    const double2 s = acc[0];
+    out[0] = cmul(ph, s);
+    double2 kg = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        out[1 + c] = cmul(ph, make_double2(acc[1 + c].x - v.k[c] * s.y, acc[1 + c].y + v.k[c] * s.x));
+        kg.x += v.k[c] * acc[1 + c].x;
+        kg.y += v.k[c] * acc[1 + c].y;
+    }
+    out[4] = cmul(ph, make_double2(acc[4].x - 2.0 * kg.y - v.k2 * s.x, acc[4].y + 2.0 * kg.x - v.k2 * s.y));
+}
+
 // Value, gradient and Laplacian of orbital j at the stencil's position (twist phase ph =
 // exp(i k.r)), into out[5].
 __device__ __forceinline__ void corbital(const CView& v, const size_t* sidx, const double* sw, double2 ph, int j,
@@ -135,16 +152,7 @@ __device__ __forceinline__ void corbital(const CView& v, const size_t* sidx, con
             acc[k].y += sw[q * 5 + k] * c.y;
         }
     }
-    const double2 s = acc[0];
-    out[0] = cmul(ph, s);
-    double2 kg = make_double2(0.0, 0.0);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        out[1 + c] = cmul(ph, make_double2(acc[1 + c].x - v.k[c] * s.y, acc[1 + c].y + v.k[c] * s.x));
-        kg.x += v.k[c] * acc[1 + c].x;
-        kg.y += v.k[c] * acc[1 + c].y;
-    }
-    out[4] = cmul(ph, make_double2(acc[4].x - 2.0 * kg.y - v.k2 * s.x, acc[4].y + 2.0 * kg.x - v.k2 * s.y));
+    twist_rows(v, ph, acc, out);
 }
 
 __device__ __forceinline__ double2 twist_phase(const CView& v, const double r[3])
@@ -153,17 +161,30 @@ __device__ __forceinline__ double2 twist_phase(const CView& v, const double r[3]
     return make_double2(cos(th), sin(th));
 }
 
-// Sum over the workgroup in a fixed order (waves, then wave index); every thread gets it.
-__device__ __forceinline__ double cblock_sum(double x, double* red, int lane, int wave, int nw)
+// Three sums over the workgroup in a fixed order (each wave's, then the waves in index
+// order); every thread gets them.
+__device__ __forceinline__ void cblock_sum3(double& a, double& b, double& c, double (*red)[kBlock / 64], int lane,
+                                            int wave, int nw)
 {
-    x = wave_sum(x);
+    a = wave_sum(a);
+    b = wave_sum(b);
+    c = wave_sum(c);
     __syncthreads();
-    if (lane == 0) red[wave] = x;
+    if (lane == 0) {
+        red[0][wave] = a;
+        red[1][wave] = b;
+        red[2][wave] = c;
+    }
     __syncthreads();
-    double s = 0.0;
-    for (int q = 0; q < nw; ++q) s += red[q];
-    return s;
+    a = b = c = 0.0;
+    for (int q = 0; q < nw; ++q) {
+        a += red[0][q];
+        b += red[1][q];
+        c += red[2][q];
+    }
 }
+
+constexpr int kRowBatch = 4;  // rows of the inverse one wave updates with their loads in flight together
 
 }  // namespace
 
@@ -320,10 +341,10 @@ __global__ __launch_bounds__(kBlock) void k_cinverse(CView v)
 // the electron and adds log|rho| and arg rho to log|det| and the phase.
 __global__ __launch_bounds__(kBlock) void k_csweep(CView v)
 {
-    extern __shared__ double2 cs_lds[];  // u [5][n], then c0 [n]
+    extern __shared__ double2 cs_lds[];  // u [5][n], c0 [n], then (4 n <= threads) the planes' sums [4][5][n]
     __shared__ size_t s_idx[64];
     __shared__ double s_w[64 * 5];
-    __shared__ double s_red[kBlock / 64];
+    __shared__ double s_red[3][kBlock / 64];
     __shared__ double s_rp[3];
     const int w = blockIdx.x;
     if (w >= v.W) return;
@@ -351,11 +372,50 @@ __global__ __launch_bounds__(kBlock) void k_csweep(CView v)
         const double rp[3] = {s_rp[0], s_rp[1], s_rp[2]};
         const double re[3] = {Rw[(size_t)e * 3], Rw[(size_t)e * 3 + 1], Rw[(size_t)e * 3 + 2]};
         const double2 ph = twist_phase(v, rp);
-        for (int j = tid; j < n; j += nt) {
-            double2 o[5];
-            corbital(v, s_idx, s_w, ph, j, o);
+        if (4 * n <= nt) {
+            // one x-plane of the stencil (16 points) per item, the planes' sums added in order
+            double2* part = c0 + n;  // [4][5][n]
+            if (tid < 4 * n) {
+                const int p = tid / n, j = tid % n;
+                double2 acc[5];
 #pragma unroll
-            for (int k = 0; k < 5; ++k) u[(size_t)k * n + j] = o[k];
+                for (int k = 0; k < 5; ++k) acc[k] = make_double2(0.0, 0.0);
+                double2 cq[16];
+#pragma unroll
+                for (int q = 0; q < 16; ++q) cq[q] = v.table[s_idx[p * 16 + q] + j];
+#pragma unroll
+                for (int q = 0; q < 16; ++q)
+#pragma unroll
+                    for (int k = 0; k < 5; ++k) {
+                        acc[k].x += s_w[(p * 16 + q) * 5 + k] * cq[q].x;
+                        acc[k].y += s_w[(p * 16 + q) * 5 + k] * cq[q].y;
+                    }
+#pragma unroll
+                for (int k = 0; k < 5; ++k) part[((size_t)p * 5 + k) * n + j] = acc[k];
+            }
+            __syncthreads();
+            for (int j = tid; j < n; j += nt) {
+                double2 acc[5];
+#pragma unroll
+                for (int k = 0; k < 5; ++k) {
+                    acc[k] = part[(size_t)k * n + j];
+                    for (int p = 1; p < 4; ++p) {
+                        acc[k].x += part[((size_t)p * 5 + k) * n + j].x;
+                        acc[k].y += part[((size_t)p * 5 + k) * n + j].y;
+                    }
+                }
+                double2 o[5];
+                twist_rows(v, ph, acc, o);
+#pragma unroll
+                for (int k = 0; k < 5; ++k) u[(size_t)k * n + j] = o[k];
+            }
+        } else {
+            for (int j = tid; j < n; j += nt) {
+                double2 o[5];
+                corbital(v, s_idx, s_w, ph, j, o);
+#pragma unroll
+                for (int k = 0; k < 5; ++k) u[(size_t)k * n + j] = o[k];
+            }
         }
         __syncthreads();
         double rx = 0.0, ry = 0.0, dj = 0.0;
@@ -373,9 +433,7 @@ __global__ __launch_bounds__(kBlock) void k_csweep(CView v)
                 pade(aa, v.b, cell_distance(v, re, Rw + (size_t)m * 3, d), u0, du, d2u);
                 dj += u1 - u0;
             }
-        rx = cblock_sum(rx, s_red, lane, wave, nw);
-        ry = cblock_sum(ry, s_red, lane, wave, nw);
-        dj = cblock_sum(dj, s_red, lane, wave, nw);
+        cblock_sum3(rx, ry, dj, s_red, lane, wave, nw);
         const double2 rho = make_double2(rx, ry);
         const double prob = (rx * rx + ry * ry) * exp(2.0 * dj);
         const bool acc = accept_uniform(v.seed, uid, v.step, (uint32_t)e) < prob;
@@ -393,21 +451,43 @@ __global__ __launch_bounds__(kBlock) void k_csweep(CView v)
         for (int j = tid; j < n; j += nt) c0[j] = M[(size_t)a * n + j];
         __syncthreads();  // the old column is in LDS before any row changes
         const double2 irho = cdiv(make_double2(1.0, 0.0), rho);
-        for (int b = wave; b < n; b += nw) {
-            double2* Mb = M + (size_t)b * n;
-            double xr = 0.0, xi = 0.0;
+        // rows b0 .. b0 + kRowBatch - 1 per wave and pass: every row's loads are issued
+        // before any of them is used, and its dot and update are those of a row alone
+        constexpr int RB = kRowBatch;
+        for (int b0 = wave * RB; b0 < n; b0 += nw * RB) {
+            double xr[RB], xi[RB];
+#pragma unroll
+            for (int r = 0; r < RB; ++r) xr[r] = xi[r] = 0.0;
             for (int j = lane; j < n; j += 64) {
-                const double2 p = cmul(u[j], Mb[j]);
-                xr += p.x;
-                xi += p.y;
+                const double2 uj = u[j];
+                double2 m[RB];
+#pragma unroll
+                for (int r = 0; r < RB; ++r)
+                    m[r] = b0 + r < n ? M[(size_t)(b0 + r) * n + j] : make_double2(0.0, 0.0);
+#pragma unroll
+                for (int r = 0; r < RB; ++r) {
+                    const double2 p = cmul(uj, m[r]);
+                    xr[r] += p.x;
+                    xi[r] += p.y;
+                }
             }
-            xr = wave_sum(xr);
-            xi = wave_sum(xi);
-            const double2 beta = cmul(make_double2(xr - (b == a ? 1.0 : 0.0), xi), irho);
+            double2 beta[RB];
+#pragma unroll
+            for (int r = 0; r < RB; ++r)
+                beta[r] = cmul(make_double2(wave_sum(xr[r]) - (b0 + r == a ? 1.0 : 0.0), wave_sum(xi[r])), irho);
             for (int j = lane; j < n; j += 64) {
-                const double2 q = cmul(beta, c0[j]);
-                Mb[j].x -= q.x;
-                Mb[j].y -= q.y;
+                const double2 c = c0[j];
+                double2 m[RB];
+#pragma unroll
+                for (int r = 0; r < RB; ++r)
+                    m[r] = b0 + r < n ? M[(size_t)(b0 + r) * n + j] : make_double2(0.0, 0.0);
+#pragma unroll
+                for (int r = 0; r < RB; ++r) {
+                    if (b0 + r < n) {
+                        const double2 q = cmul(beta[r], c);
+                        M[(size_t)(b0 + r) * n + j] = make_double2(m[r].x - q.x, m[r].y - q.y);
+                    }
+                }
             }
         }
         double2* dst = v.VGL + (((size_t)w * 2 + spin) * n + a) * 5 * (size_t)n;
@@ -493,7 +573,7 @@ void launch_cinverse(const CView& v, hipStream_t s)
 
 void launch_csweep(const CView& v, hipStream_t s)
 {
-    const size_t lds = sizeof(double2) * 6 * (size_t)v.n;
+    const size_t lds = sizeof(double2) * (4 * v.n <= kBlock ? 26 : 6) * (size_t)v.n;
     static bool opted = false;  // more than 64 KB of dynamic LDS at the largest N
     if (!opted) {
         (void)hipFuncSetAttribute((const void*)k_csweep, hipFuncAttributeMaxDynamicSharedMemorySize,
