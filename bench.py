@@ -570,8 +570,9 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: every box here has one MI355X, and the walker-parallel path "
-              "is not sharded across GPUs in this build (see DESIGN.md for how it would shard).",
+        print("bench.py measures one GPU only: the walker-parallel path is not sharded across GPUs "
+              "(walkers are independent; each GPU would run its own crowds on its own copy of the "
+              "orbital table, with a few FP64 sums all-reduced per generation).",
               file=sys.stderr)
         sys.exit(2)
     import paper_2209_14487_amd as cq
