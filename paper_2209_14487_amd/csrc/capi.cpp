@@ -1645,7 +1645,7 @@ cq_status cq_crowd_get_round_plan(cq_crowd* c, int* rounds)
         rounds[0] = rounds[1] = 0;
         return CQ_OK;
     }
-    (void)update_plan(x);
+    if (update_plan(x)) drop_graph(x);  // a captured sweep holds the old plan's rounds
     const int all = cq::batch_rounds(x->n, x->K);
     for (int s = 0; s < 2; ++s) rounds[s] = planned_rounds(x, s, all);
     return CQ_OK;
