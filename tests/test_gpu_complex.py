@@ -38,7 +38,7 @@ def phase_diff(a, b):
     return np.abs(np.exp(1j * np.asarray(a)) - np.exp(1j * np.asarray(b)))
 
 
-@pytest.mark.parametrize("n,G,W", [(4, 8, 6), (32, 16, 8), (64, 12, 4)])
+@pytest.mark.parametrize("n,G,W", [(4, 8, 6), (32, 16, 8), (33, 10, 3), (64, 12, 4), (96, 10, 2)])
 def test_setup_matches_oracle(n, G, W):
     seed = 1500 + n
     g, o = pair(n, G, seed)
@@ -60,7 +60,8 @@ def test_setup_matches_oracle(n, G, W):
 
 
 @pytest.mark.parametrize("n,G,W,S,sigma,twisted", [(4, 8, 8, 4, 1.0, True), (32, 16, 6, 2, 0.5, True),
-                                                   (32, 16, 4, 2, 0.5, False), (64, 12, 3, 1, 0.4, True)])
+                                                   (32, 16, 4, 2, 0.5, False), (33, 10, 3, 1, 0.5, True),
+                                                   (64, 12, 3, 1, 0.4, True), (96, 10, 2, 1, 0.4, True)])
 def test_vmc_chain_matches_oracle(n, G, W, S, sigma, twisted):
     seed = 1600 + n
     g, o = pair(n, G, seed, twist=TWIST if twisted else np.zeros(3))

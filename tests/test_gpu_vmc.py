@@ -387,6 +387,33 @@ def test_round_plan_is_learned_and_keeps_the_chain():
     crowd.close()
 
 
+
+def test_round_plan_of_each_spin_comes_from_its_own_report():
+    """Each spin block's plan is learned from that block's own report: a report of the up block
+    alone never sets the down block's plan (which once read the down block's empty fields and
+    planned 2 rounds, leaving most of that block to the tail kernel).  After a few sweeps both
+    plans cover the rounds the blocks need (about half of N / k at this acceptance), and new
+    launch shapes restart the plan."""
+    n, L, G, W, k = 64, 12.0, 48, 16, 4
+    g, _ = make_pair(n, L, G, 1012, coef_seed=1012)
+    R0 = start_positions(1012, W, 2 * n, L)
+    crowd = cq.Crowd(g, W, precision="fp64", delay_rank=k, seed=1012, path="batch")
+    crowd.set_positions(R0)
+    for _ in range(4):
+        crowd.run_vmc(1, 0.5)
+    crowd.synchronize()
+    plan = crowd.round_plan()
+    print("   plan", plan.tolist(), "of", n // k)
+    assert np.all(plan >= 6) and np.all(plan <= n // k)
+    crowd.set_tiles(candidates=8)
+    assert list(crowd.round_plan()) == [n // k, n // k]
+    crowd.run_vmc(3, 0.5)
+    crowd.synchronize()
+    plan = crowd.round_plan()
+    assert np.all(plan >= 6) and np.all(plan <= n // k)
+    crowd.close()
+    g.close()
+
 def test_singular_start_is_reported():
     """Two same-spin electrons at one position make A singular: CQ_ESINGULAR names the walker."""
     n, L, G, W = 4, 5.0, 16, 3
