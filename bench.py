@@ -113,20 +113,20 @@ def run_virtual(cq, wl, nq, launches=3):
 C6 = dict(n=64, G=24, walkers=512, sigma=0.5, seed=1006, twist=(0.11, -0.07, 0.05))
 
 
-def run_complex(cq, args):
-    """The complex-orbital path: moves/s over timed sweeps (one sweep-kernel launch each, HIP events
-    around every launch) and the kernel's algorithmic bytes per launch: per move 64 stencil rows of
-    N complex FP64 coefficients and the inverse row of the ratio, per accepted move one read and one
-    write of the N x N complex inverse and the five new orbital rows."""
+def complex_leg(cq, args, precision):
+    """Timed sweeps of the C6 system with one table precision: (moves/s, roofline dict, acceptance,
+    E_L [W], R0)."""
     from synth import J2_A_ANTI, J2_A_PAR, J2_B, TRICLINIC, cell_positions, complex_table
     c6 = C6
     n, W, G = c6["n"], c6["walkers"], c6["G"]
     ne = 2 * n
+    table = complex_table(c6["seed"], G, n)
+    cb = 16 if precision == "fp64" else 8  # bytes per coefficient
     g = cq.ComplexSystem(n, TRICLINIC, c6["twist"])
-    g.load_table(complex_table(c6["seed"], G, n))
+    g.load_table(table if cb == 16 else table.astype(np.complex64))
     g.load_j2(J2_A_PAR, J2_A_ANTI, J2_B)
     R0 = cell_positions(c6["seed"], W, ne, TRICLINIC)
-    crowd = cq.ComplexCrowd(g, W, seed=c6["seed"])
+    crowd = cq.ComplexCrowd(g, W, seed=c6["seed"], precision=precision)
     crowd.set_positions(R0)
     crowd.run_vmc(args.warmup, c6["sigma"])
     crowd.synchronize()
@@ -144,26 +144,42 @@ def run_complex(cq, args):
     moves = int(prop1 - prop0)
     accepted = int(acc1 - acc0)
     t_launch = 1e-3 * ms / max(launches, 1)
-    bytes_launch = (moves * (64 * n * 16 + n * 16) + accepted * (2 * n * n * 16 + 5 * n * 16)) / max(launches, 1)
+    bytes_launch = (moves * (64 * n * cb + n * 16) + accepted * (2 * n * n * 16 + 5 * n * 16)) / max(launches, 1)
     gbs = bytes_launch / t_launch / 1e9
+    roof = dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(gbs / HBM_PEAK_GBS, 4), traffic=None, kernel="k_csweep",
+                us_per_launch=round(t_launch * 1e6, 3), bytes_per_launch=int(bytes_launch),
+                moves_per_launch=moves // max(launches, 1),
+                note="one launch = one sweep of every walker (one workgroup each); the table and most "
+                     "inverses stay in the caches, so the chain of dependent moves, not HBM, bounds the kernel")
+    return moves / (t1 - t0), t1 - t0, roof, accepted / max(moves, 1), el, R0
+
+
+def run_complex(cq, args):
+    """The complex-orbital path: moves/s over timed sweeps (one sweep-kernel launch each, HIP events
+    around every launch) and the kernel's algorithmic bytes per launch: per move 64 stencil rows of
+    N complex coefficients and the inverse row of the ratio, per accepted move one read and one
+    write of the N x N complex inverse and the five new orbital rows.  The headline reads the
+    complex128 table; `coef32` reads the complex64 table with the same FP64 arithmetic."""
+    from synth import J2_A_ANTI, J2_A_PAR, J2_B, TRICLINIC, complex_table
+    c6 = C6
+    n, W, G = c6["n"], c6["walkers"], c6["G"]
+    ne = 2 * n
+    rate, secs, roof, acc, el, R0 = complex_leg(cq, args, "fp64")
+    rate32, _, roof32, _, el32, _ = complex_leg(cq, args, "mixed")
     out = dict(metric="electron moves/sec at 1 GPU, complex orbitals with a twist in a triclinic cell (FP64)",
-               value=round(moves / (t1 - t0), 1), unit="moves/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
-               ms_per_step=round(1e3 * (t1 - t0) / args.steps, 3), higher_is_better=True, scaling="weak",
+               value=round(rate, 1), unit="moves/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+               ms_per_step=round(1e3 * secs / args.steps, 3), higher_is_better=True, scaling="weak",
                vs_baseline=None, dtype="f64",
                data="synthetic (seeded complex B-spline coefficients, uniform fractional starting positions)",
                config=dict(workload="c6: %d+%d electrons, triclinic cell (volume %.0f bohr^3), %d^3 complex FP64 "
                                     "table (%.3f GB), twist %s, Pade J2, %d walkers, Sherman-Morrison"
                                     % (n, n, abs(np.linalg.det(TRICLINIC)), G, G ** 3 * n * 16 / 1e9,
                                        list(c6["twist"]), W)),
-               roofline=dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                             frac=round(gbs / HBM_PEAK_GBS, 4), traffic=None, kernel="k_csweep",
-                             us_per_launch=round(t_launch * 1e6, 3), bytes_per_launch=int(bytes_launch),
-                             moves_per_launch=moves // max(launches, 1),
-                             note="one launch = one sweep of every walker (one workgroup each); the 14 MB table "
-                                  "and most inverses stay in the caches, so the chain of dependent moves, not "
-                                  "HBM, bounds the kernel"),
-               acceptance=round(accepted / max(moves, 1), 4), e_mean=float(np.mean(el.real)),
-               e_imag_mean=float(np.mean(el.imag)))
+               roofline=roof, acceptance=round(acc, 4), e_mean=float(np.mean(el.real)),
+               e_imag_mean=float(np.mean(el.imag)),
+               coef32=dict(moves_per_s=round(rate32, 1), roofline=roof32, e_mean=float(np.mean(el32.real)),
+                           note="complex64 coefficients (half the spline bytes), every sum and the inverses FP64"))
     if not args.no_cpu:
         from oracle import complex_oracle as co
         o = co.CSystem(n, TRICLINIC, np.array(c6["twist"]), table=complex_table(c6["seed"], G, n), use_j2=True,
@@ -174,8 +190,9 @@ def run_complex(cq, args):
         out["cpu_baseline"] = dict(value=round(2 * ne / dt, 2), unit="moves/s", cores=1, kind="oracle",
                                    sample="walkers 0 and 1, one sweep each (%d moves each, set-up and local energy included), "
                                           "numpy FP64 complex oracle, one thread" % ne, seconds=round(dt, 2))
-    log("  complex: %.3e moves/s, k_csweep %.1f us per launch, %.0f GB/s algorithmic, acceptance %.3f"
-        % (out["value"], t_launch * 1e6, gbs, out["acceptance"]))
+    log("  complex: %.3e moves/s, k_csweep %.1f us per launch, %.0f GB/s algorithmic, acceptance %.3f; "
+        "complex64 table %.3e moves/s, %.1f us per launch"
+        % (out["value"], roof["us_per_launch"], roof["achieved"], out["acceptance"], rate32, roof32["us_per_launch"]))
     print(json.dumps(out), flush=True)
 
 

@@ -434,20 +434,25 @@ typedef struct cq_ccrowd cq_ccrowd;    /* walkers of a complex system (opaque) *
 /* n electrons per spin (1..512), lattice [3][3] (rows, bohr; non-degenerate), twist [3]
    (Cartesian, 1/bohr; NULL = 0).  Errors: CQ_EINVAL. */
 cq_status cq_csystem_create(int n, const double* lattice, const double* twist, cq_csystem** out);
-/* Complex coefficients [G][G][G][n_orb] (interleaved real, imaginary FP64; orbital index
-   fastest), grid G >= 4, n_orb == n.  coefs_on_device = 0: host array, copied; 1: a device
-   buffer the system borrows (it must outlive the system).  Errors: CQ_EINVAL, CQ_ENOMEM. */
-cq_status cq_csystem_load_bspline(cq_csystem* sys, const void* coefs, int grid, int n_orb, int coefs_on_device);
+/* Complex coefficients [G][G][G][n_orb] (interleaved real, imaginary; orbital index
+   fastest): elem_bytes 16 (complex128, for CQ_FP64 crowds) or 8 (complex64, for CQ_MIXED
+   crowds); a system may hold both, on one grid.  Grid G >= 4, n_orb == n.
+   coefs_on_device = 0: host array, copied; 1: a device buffer the system borrows (it must
+   outlive the system).  Errors: CQ_EINVAL, CQ_ENOMEM. */
+cq_status cq_csystem_load_bspline(cq_csystem* sys, const void* coefs, int elem_bytes, int grid, int n_orb,
+                                  int coefs_on_device);
 /* Pade pair Jastrow u(r) = a r / (1 + b r) (a_par equal spins, a_anti opposite). */
 cq_status cq_csystem_load_pade_j2(cq_csystem* sys, double a_par, double a_anti, double b);
 void cq_csystem_destroy(cq_csystem* sys);
 
 /* A crowd of `walkers` walkers (uids first_uid + w) on a borrowed hipStream_t or its own
-   (hip_stream NULL).  Device buffers: inverses and orbital rows, 16 (2 n^2 + 10 n^2) bytes per
-   walker, plus a Gauss-Jordan workspace of 64 n^2 bytes.  Errors: CQ_EINVAL (no table),
+   (hip_stream NULL).  precision CQ_FP64 reads the complex128 table; CQ_MIXED reads the
+   complex64 table (half the spline bytes), every sum, row, inverse and energy staying FP64.
+   Device buffers: inverses and orbital rows, 16 (2 n^2 + 10 n^2) bytes per walker, plus a
+   Gauss-Jordan workspace of 64 n^2 bytes.  Errors: CQ_EINVAL (no table of that precision),
    CQ_ENOMEM, CQ_EDEVICE. */
-cq_status cq_ccrowd_create(const cq_csystem* sys, int walkers, uint64_t seed, uint32_t first_uid, void* hip_stream,
-                           cq_ccrowd** out);
+cq_status cq_ccrowd_create(const cq_csystem* sys, int walkers, int precision, uint64_t seed, uint32_t first_uid,
+                           void* hip_stream, cq_ccrowd** out);
 /* Positions R [W][2n][3] (host), then the orbital rows of every electron, both inverses
    (Gauss-Jordan with partial pivoting by modulus), log|det|, phase and E_L.  Resets the
    counters; the next sweep uses step first_step.  Errors: CQ_EINVAL, CQ_ESINGULAR (names the

@@ -98,10 +98,10 @@ _SIGS = {
     "cq_slater_inverse_static": [_P, _I, _I, _I, _P, _P, _P, _P],
     "cq_crowd_destroy": [_P],
     "cq_csystem_create": [_I, _P, _P, _P],
-    "cq_csystem_load_bspline": [_P, _P, _I, _I, _I],
+    "cq_csystem_load_bspline": [_P, _P, _I, _I, _I, _I],
     "cq_csystem_load_pade_j2": [_P, ctypes.c_double, ctypes.c_double, ctypes.c_double],
     "cq_csystem_destroy": [_P],
-    "cq_ccrowd_create": [_P, _I, ctypes.c_uint64, ctypes.c_uint32, _P, _P],
+    "cq_ccrowd_create": [_P, _I, _I, ctypes.c_uint64, ctypes.c_uint32, _P, _P],
     "cq_ccrowd_set_positions": [_P, _P, ctypes.c_uint32],
     "cq_ccrowd_run_vmc": [_P, _I, ctypes.c_double],
     "cq_ccrowd_recompute": [_P, _P],
@@ -611,15 +611,18 @@ class ComplexSystem:
         self._keep = []
 
     def load_table(self, table):
-        """table [G][G][G][N] complex128: numpy (copied) or a complex128 torch CUDA tensor (borrowed)."""
+        """table [G][G][G][N] complex128 (FP64 crowds) or complex64 (mixed crowds): numpy (copied)
+        or a torch CUDA tensor of that type (borrowed, kept alive here)."""
         G = table.shape[0]
         if isinstance(table, np.ndarray):
-            arr = np.ascontiguousarray(table, dtype=np.complex128)
-            _check(lib().cq_csystem_load_bspline(self._h, arr.ctypes.data, G, table.shape[3], 0))
+            eb = 8 if table.dtype == np.complex64 else 16
+            arr = np.ascontiguousarray(table, dtype=np.complex64 if eb == 8 else np.complex128)
+            _check(lib().cq_csystem_load_bspline(self._h, arr.ctypes.data, eb, G, table.shape[3], 0))
         else:
-            assert table.is_contiguous() and table.element_size() == 16
+            assert table.is_contiguous() and table.element_size() in (8, 16)
             self._keep.append(table)
-            _check(lib().cq_csystem_load_bspline(self._h, table.data_ptr(), G, table.shape[3], 1))
+            _check(lib().cq_csystem_load_bspline(self._h, table.data_ptr(), table.element_size(), G,
+                                                 table.shape[3], 1))
 
     def load_j2(self, a_par=0.25, a_anti=0.5, b=1.0):
         _check(lib().cq_csystem_load_pade_j2(self._h, a_par, a_anti, b))
@@ -639,9 +642,12 @@ class ComplexSystem:
 class ComplexCrowd:
     """Walkers of a ComplexSystem moved by one sweep kernel per sweep (cq_ccrowd)."""
 
-    def __init__(self, system: ComplexSystem, walkers: int, seed: int = 0, first_uid: int = 0, stream=None):
+    def __init__(self, system: ComplexSystem, walkers: int, seed: int = 0, first_uid: int = 0, stream=None,
+                 precision: str = "fp64"):
+        """precision "fp64": complex128 table; "mixed": complex64 table, FP64 arithmetic."""
         h = ctypes.c_void_p()
-        _check(lib().cq_ccrowd_create(system._h, walkers, seed, first_uid, stream, ctypes.byref(h)))
+        _check(lib().cq_ccrowd_create(system._h, walkers, _prec(precision), seed, first_uid, stream,
+                                      ctypes.byref(h)))
         self._h = h
         self.sys = system
         self.W = walkers

@@ -16,15 +16,16 @@ struct cq_csystem {
     int n = 0;
     double lat[9] = {}, linv[9] = {}, metric[6] = {}, k[3] = {};
     int G = 0, n_orb = 0;
-    double2* table = nullptr;
-    bool owned = false;
+    double2* table = nullptr;  // complex128 coefficients
+    float2* table32 = nullptr;  // complex64 coefficients (a system may hold both, of one grid)
+    bool owned = false, owned32 = false;
     int use_j2 = 0;
     double a_par = 0.0, a_anti = 0.0, b = 1.0;
 };
 
 struct cq_ccrowd {
     const cq_csystem* sys = nullptr;
-    int W = 0, n = 0, ne = 0;
+    int W = 0, n = 0, ne = 0, prec = CQ_FP64;
     uint64_t seed = 0;
     uint32_t first_uid = 0, step = 0;
     hipStream_t stream = nullptr;
@@ -75,7 +76,8 @@ cq::CView cview(const cq_ccrowd* c)
     std::memcpy(v.metric, s->metric, sizeof v.metric);
     std::memcpy(v.k, s->k, sizeof v.k);
     v.k2 = s->k[0] * s->k[0] + s->k[1] * s->k[1] + s->k[2] * s->k[2];
-    v.table = s->table;
+    v.table = c->prec == CQ_FP64 ? s->table : nullptr;
+    v.table32 = c->prec == CQ_FP64 ? nullptr : s->table32;
     v.R = c->R;
     v.M = c->M;
     v.VGL = c->VGL;
@@ -180,25 +182,30 @@ cq_status cq_csystem_create(int n, const double* lattice, const double* twist, c
     return CQ_OK;
 }
 
-cq_status cq_csystem_load_bspline(cq_csystem* s, const void* coefs, int grid, int n_orb, int coefs_on_device)
+cq_status cq_csystem_load_bspline(cq_csystem* s, const void* coefs, int elem_bytes, int grid, int n_orb,
+                                  int coefs_on_device)
 {
     if (!s || !coefs) return host_fail(CQ_EINVAL, "NULL argument");
+    if (elem_bytes != 8 && elem_bytes != 16) return host_fail(CQ_EINVAL, "elem_bytes must be 8 or 16");
     if (grid < 4 || grid > 1024) return host_fail(CQ_EINVAL, "grid must be 4..1024");
     if (n_orb != s->n) return host_fail(CQ_EINVAL, "n_orb must equal n");
-    if (s->owned && s->table) (void)hipFree(s->table);
-    s->table = nullptr;
-    s->owned = false;
-    const size_t bytes = sizeof(double2) * (size_t)grid * grid * grid * n_orb;
+    if ((s->table || s->table32) && grid != s->G) return host_fail(CQ_EINVAL, "both tables must share one grid");
+    void** slot = elem_bytes == 16 ? (void**)&s->table : (void**)&s->table32;
+    bool& owned = elem_bytes == 16 ? s->owned : s->owned32;
+    if (owned && *slot) (void)hipFree(*slot);
+    *slot = nullptr;
+    owned = false;
+    const size_t bytes = (size_t)elem_bytes * grid * grid * grid * n_orb;
     if (coefs_on_device) {
-        s->table = (double2*)coefs;
+        *slot = const_cast<void*>(coefs);
     } else {
-        if (hipMalloc((void**)&s->table, bytes) != hipSuccess) {
+        if (hipMalloc(slot, bytes) != hipSuccess) {
             (void)hipGetLastError();
-            s->table = nullptr;
+            *slot = nullptr;
             return host_fail(CQ_ENOMEM, "complex table");
         }
-        s->owned = true;
-        CHIP_TRY(hipMemcpy(s->table, coefs, bytes, hipMemcpyHostToDevice));
+        owned = true;
+        CHIP_TRY(hipMemcpy(*slot, coefs, bytes, hipMemcpyHostToDevice));
     }
     s->G = grid;
     s->n_orb = n_orb;
@@ -221,6 +228,7 @@ void cq_csystem_destroy(cq_csystem* s)
 {
     if (!s) return;
     if (s->owned && s->table) (void)hipFree(s->table);
+    if (s->owned32 && s->table32) (void)hipFree(s->table32);
     delete s;
 }
 
@@ -240,15 +248,18 @@ void cq_ccrowd_destroy(cq_ccrowd* c)
     delete c;
 }
 
-cq_status cq_ccrowd_create(const cq_csystem* s, int walkers, uint64_t seed, uint32_t first_uid, void* hip_stream,
-                           cq_ccrowd** out)
+cq_status cq_ccrowd_create(const cq_csystem* s, int walkers, int precision, uint64_t seed, uint32_t first_uid,
+                           void* hip_stream, cq_ccrowd** out)
 {
     if (!s || !out) return host_fail(CQ_EINVAL, "NULL argument");
     *out = nullptr;
     if (walkers < 1) return host_fail(CQ_EINVAL, "walkers must be >= 1");
-    if (!s->table) return host_fail(CQ_EINVAL, "the system has no table");
+    if (precision != CQ_FP64 && precision != CQ_MIXED) return host_fail(CQ_EINVAL, "bad precision");
+    if (precision == CQ_FP64 && !s->table) return host_fail(CQ_EINVAL, "the system has no complex128 table");
+    if (precision == CQ_MIXED && !s->table32) return host_fail(CQ_EINVAL, "the system has no complex64 table");
     auto* c = new cq_ccrowd;
     c->sys = s;
+    c->prec = precision;
     c->W = walkers;
     c->n = s->n;
     c->ne = 2 * s->n;

@@ -23,7 +23,8 @@ struct CView {
     double linv[9];    // L^-1: f = r L^-1
     double metric[6];  // (L^-T L^-1): xx, yy, zz, xy, xz, yz
     double k[3], k2;   // twist and |k|^2
-    const double2* table;  // [G][G][G][n_orb]
+    const double2* table;    // [G][G][G][n_orb] complex128 coefficients, or
+    const float2* table32;   // complex64 coefficients (the other pointer is null); the sums are FP64
     double* R;             // [W][ne][3]
     double2* M;            // [W][2][n][n]: M[a][j] = (A^-1)[j][a]
     double2* VGL;          // [W][2][n][5][n]: value, gradient x y z, Laplacian rows of phi

@@ -135,8 +135,21 @@ __device__ __forceinline__ void twist_rows(const CView& v, double2 ph, const dou
     out[4] = cmul(ph, make_double2(acc[4].x - 2.0 * kg.y - v.k2 * s.x, acc[4].y + 2.0 * kg.x - v.k2 * s.y));
 }
 
+// Coefficient i of the table (complex64 tables are widened to FP64).
+template <bool F32>
+__device__ __forceinline__ double2 coef(const CView& v, size_t i)
+{
+    if constexpr (F32) {
+        const float2 c = v.table32[i];
+        return make_double2((double)c.x, (double)c.y);
+    } else {
+        return v.table[i];
+    }
+}
+
 // Value, gradient and Laplacian of orbital j at the stencil's position (twist phase ph =
 // exp(i k.r)), into out[5].
+template <bool F32>
 __device__ __forceinline__ void corbital(const CView& v, const size_t* sidx, const double* sw, double2 ph, int j,
                                          double2 out[5])
 {
@@ -145,7 +158,7 @@ __device__ __forceinline__ void corbital(const CView& v, const size_t* sidx, con
     for (int k = 0; k < 5; ++k) acc[k] = make_double2(0.0, 0.0);
 #pragma unroll 16
     for (int q = 0; q < 64; ++q) {
-        const double2 c = v.table[sidx[q] + j];
+        const double2 c = coef<F32>(v, sidx[q] + j);
 #pragma unroll
         for (int k = 0; k < 5; ++k) {
             acc[k].x += sw[q * 5 + k] * c.x;
@@ -189,6 +202,7 @@ constexpr int kRowBatch = 4;  // rows of the inverse one wave updates with their
 }  // namespace
 
 // Orbital rows of electron e of walker w at its (wrapped) position: one workgroup each.
+template <bool F32>
 __global__ __launch_bounds__(kBlock) void k_csetup_rows(CView v)
 {
     __shared__ size_t s_idx[64];
@@ -210,7 +224,7 @@ __global__ __launch_bounds__(kBlock) void k_csetup_rows(CView v)
     double2* dst = v.VGL + (((size_t)w * 2 + spin) * n + a) * 5 * (size_t)n;
     for (int j = tid; j < n; j += blockDim.x) {
         double2 o[5];
-        corbital(v, s_idx, s_w, ph, j, o);
+        corbital<F32>(v, s_idx, s_w, ph, j, o);
 #pragma unroll
         for (int k = 0; k < 5; ++k) dst[(size_t)k * n + j] = o[k];
     }
@@ -339,6 +353,7 @@ __global__ __launch_bounds__(kBlock) void k_cinverse(CView v)
 // change, accepts when u < |rho|^2 exp(2 dlnJ), and on acceptance updates the inverse by
 // Sherman-Morrison, M[b] -= ((u . M[b]) - delta_ab) / rho M_old[a], copies the rows, moves
 // the electron and adds log|rho| and arg rho to log|det| and the phase.
+template <bool F32>
 __global__ __launch_bounds__(kBlock) void k_csweep(CView v)
 {
     extern __shared__ double2 cs_lds[];  // u [5][n], c0 [n], then (4 n <= threads) the planes' sums [4][5][n]
@@ -382,7 +397,7 @@ __global__ __launch_bounds__(kBlock) void k_csweep(CView v)
                 for (int k = 0; k < 5; ++k) acc[k] = make_double2(0.0, 0.0);
                 double2 cq[16];
 #pragma unroll
-                for (int q = 0; q < 16; ++q) cq[q] = v.table[s_idx[p * 16 + q] + j];
+                for (int q = 0; q < 16; ++q) cq[q] = coef<F32>(v, s_idx[p * 16 + q] + j);
 #pragma unroll
                 for (int q = 0; q < 16; ++q)
 #pragma unroll
@@ -412,7 +427,7 @@ __global__ __launch_bounds__(kBlock) void k_csweep(CView v)
         } else {
             for (int j = tid; j < n; j += nt) {
                 double2 o[5];
-                corbital(v, s_idx, s_w, ph, j, o);
+                corbital<F32>(v, s_idx, s_w, ph, j, o);
 #pragma unroll
                 for (int k = 0; k < 5; ++k) u[(size_t)k * n + j] = o[k];
             }
@@ -563,7 +578,10 @@ __global__ __launch_bounds__(kBlock) void k_cenergy(CView v)
 
 void launch_csetup_rows(const CView& v, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_csetup_rows, dim3(v.W * v.ne), dim3(kBlock), 0, s, v);
+    if (v.table32)
+        hipLaunchKernelGGL(k_csetup_rows<true>, dim3(v.W * v.ne), dim3(kBlock), 0, s, v);
+    else
+        hipLaunchKernelGGL(k_csetup_rows<false>, dim3(v.W * v.ne), dim3(kBlock), 0, s, v);
 }
 
 void launch_cinverse(const CView& v, hipStream_t s)
@@ -574,13 +592,16 @@ void launch_cinverse(const CView& v, hipStream_t s)
 void launch_csweep(const CView& v, hipStream_t s)
 {
     const size_t lds = sizeof(double2) * (4 * v.n <= kBlock ? 26 : 6) * (size_t)v.n;
-    static bool opted = false;  // more than 64 KB of dynamic LDS at the largest N
+    static bool opted = false;  // the dynamic LDS of the largest N, for both kernels
     if (!opted) {
-        (void)hipFuncSetAttribute((const void*)k_csweep, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)(sizeof(double2) * 6 * kCMaxN));
+        for (const void* f : {(const void*)k_csweep<true>, (const void*)k_csweep<false>})
+            (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(sizeof(double2) * 6 * kCMaxN));
         opted = true;
     }
-    hipLaunchKernelGGL(k_csweep, dim3(v.W), dim3(kBlock), lds, s, v);
+    if (v.table32)
+        hipLaunchKernelGGL(k_csweep<true>, dim3(v.W), dim3(kBlock), lds, s, v);
+    else
+        hipLaunchKernelGGL(k_csweep<false>, dim3(v.W), dim3(kBlock), lds, s, v);
 }
 
 void launch_cenergy(const CView& v, hipStream_t s)

@@ -6,6 +6,8 @@ of the Cartesian derivatives and of Psi, determinant ratios, slogdet).
 FP64 on both sides: set-up log|det|, phase, inverses and the complex E_L within 1e-10
 (relative to max(1, |value|)); over VMC sweeps identical decisions except at near-ties, and
 complex ratios, ln J changes, acceptance probabilities, log|det|, phase and E_L within 1e-10.
+The mixed crowds read complex64 coefficients and do every sum in FP64; the oracle takes the
+same coefficients (the complex64 table widened to complex128), so the same 1e-10 bar holds.
 """
 import numpy as np
 import pytest
@@ -24,11 +26,13 @@ def rel(a, b):
     return np.abs(np.asarray(a) - np.asarray(b)) / np.maximum(1.0, np.abs(np.asarray(b)))
 
 
-def pair(n, G, seed, lattice=TRICLINIC, twist=TWIST, j2=True):
+def pair(n, G, seed, lattice=TRICLINIC, twist=TWIST, j2=True, precision="fp64"):
     table = complex_table(seed, G, n)
+    if precision == "mixed":
+        table = table.astype(np.complex64)
     g = cq.ComplexSystem(n, lattice, twist)
     g.load_table(table)
-    o = co.CSystem(n, lattice, twist, table=table, use_j2=j2, seed=seed)
+    o = co.CSystem(n, lattice, twist, table=table.astype(np.complex128), use_j2=j2, seed=seed)
     if j2:
         g.load_j2(o.j2_a_par, o.j2_a_anti, o.j2_b)
     return g, o
@@ -38,12 +42,14 @@ def phase_diff(a, b):
     return np.abs(np.exp(1j * np.asarray(a)) - np.exp(1j * np.asarray(b)))
 
 
-@pytest.mark.parametrize("n,G,W", [(4, 8, 6), (32, 16, 8), (33, 10, 3), (64, 12, 4), (96, 10, 2)])
-def test_setup_matches_oracle(n, G, W):
+@pytest.mark.parametrize("n,G,W,precision", [(4, 8, 6, "fp64"), (32, 16, 8, "fp64"), (33, 10, 3, "fp64"),
+                                             (64, 12, 4, "fp64"), (96, 10, 2, "fp64"), (32, 16, 8, "mixed"),
+                                             (96, 10, 2, "mixed")])
+def test_setup_matches_oracle(n, G, W, precision):
     seed = 1500 + n
-    g, o = pair(n, G, seed)
+    g, o = pair(n, G, seed, precision=precision)
     R0 = cell_positions(seed, W, 2 * n, TRICLINIC)
-    crowd = cq.ComplexCrowd(g, W, seed=seed)
+    crowd = cq.ComplexCrowd(g, W, seed=seed, precision=precision)
     crowd.set_positions(R0)
     ld, ph = crowd.logdet()
     el = crowd.local_energy()
@@ -59,14 +65,15 @@ def test_setup_matches_oracle(n, G, W):
     g.close()
 
 
-@pytest.mark.parametrize("n,G,W,S,sigma,twisted", [(4, 8, 8, 4, 1.0, True), (32, 16, 6, 2, 0.5, True),
-                                                   (32, 16, 4, 2, 0.5, False), (33, 10, 3, 1, 0.5, True),
-                                                   (64, 12, 3, 1, 0.4, True), (96, 10, 2, 1, 0.4, True)])
-def test_vmc_chain_matches_oracle(n, G, W, S, sigma, twisted):
+@pytest.mark.parametrize("n,G,W,S,sigma,twisted,precision", [
+    (4, 8, 8, 4, 1.0, True, "fp64"), (32, 16, 6, 2, 0.5, True, "fp64"), (32, 16, 4, 2, 0.5, False, "fp64"),
+    (33, 10, 3, 1, 0.5, True, "fp64"), (64, 12, 3, 1, 0.4, True, "fp64"), (96, 10, 2, 1, 0.4, True, "fp64"),
+    (32, 16, 6, 2, 0.5, True, "mixed"), (64, 12, 3, 1, 0.4, True, "mixed")])
+def test_vmc_chain_matches_oracle(n, G, W, S, sigma, twisted, precision):
     seed = 1600 + n
-    g, o = pair(n, G, seed, twist=TWIST if twisted else np.zeros(3))
+    g, o = pair(n, G, seed, twist=TWIST if twisted else np.zeros(3), precision=precision)
     R0 = cell_positions(seed, W, 2 * n, TRICLINIC)
-    crowd = cq.ComplexCrowd(g, W, seed=seed)
+    crowd = cq.ComplexCrowd(g, W, seed=seed, precision=precision)
     crowd.set_positions(R0)
     crowd.record(S)
     ld = np.zeros((S, W, 2))
@@ -123,6 +130,13 @@ def test_complex_path_arguments():
     g = cq.ComplexSystem(4, TRICLINIC, TWIST)
     with pytest.raises(cq.CqError) as ei:
         cq.ComplexCrowd(g, 2)  # no table yet
+    assert ei.value.status == cq.CQ_EINVAL
+    g.load_table(complex_table(1, 8, 4).astype(np.complex64))
+    with pytest.raises(cq.CqError) as ei:
+        cq.ComplexCrowd(g, 2, precision="fp64")  # only the complex64 table
+    assert ei.value.status == cq.CQ_EINVAL
+    with pytest.raises(cq.CqError) as ei:
+        g.load_table(complex_table(1, 10, 4))  # a second table on another grid
     assert ei.value.status == cq.CQ_EINVAL
     with pytest.raises(cq.CqError) as ei:
         g.load_table(complex_table(1, 8, 5))
