@@ -61,8 +61,8 @@ def parse():
     ap.add_argument("--virtual-points", type=int, default=12,
                     help="quadrature points per electron of the timed virtual-move launch (0: skip)")
     ap.add_argument("--tiles", default="",
-                    help="launch shapes of the batched path, Q,G (candidates per round, gather workgroups per CU "
-                         "beside the update); default: the built-in rules")
+                    help="launch shapes of the batched path, Q,G[,U] (candidates per round, gather workgroups per CU "
+                         "beside the update, FP64 update kernel 1 vector / 2 matrix cores); default: the built-in rules")
     ap.add_argument("--tile-cache", default="",
                     help="JSON tile cache: take the shapes from it, or tune them (2 sweeps per candidate, before "
                          "the warm-up) and add them to it")
@@ -676,9 +676,10 @@ def main():
                             note="one stream, no kernel beside another; context for the roofline above, "
                                  "which is measured in the timed region where gather and update share the GPU")
     if args.fp64_steps > 0:
-        f64 = run_gpu(cq, wl, "fp64", delay, 0, args.fp64_steps, 1, [], not args.eager, path=args.path)
+        f64 = run_gpu(cq, wl, "fp64", delay, 0, args.fp64_steps, 1, [], not args.eager, path=args.path, tiles=tiles)
         log("  fp64: %.3e moves/s" % f64["moves_per_s"])
         out["fp64_moves_per_s"] = round(f64["moves_per_s"], 1)
+        out["fp64_tiles"] = f64["tiles"]
         # both sides replay the captured sweep graph (no events), so launch overheads match
         ref = mixed.get("graph_moves_per_s", mixed["moves_per_s"])
         out["mixed_over_fp64"] = round(ref / f64["moves_per_s"], 3)

@@ -304,26 +304,33 @@ cq_status cq_crowd_get_round_plan(cq_crowd* c, int* rounds);
      gather_blocks_per_cu  workgroups per compute unit of the persistent orbital gather
                            while it runs beside the decisions and the update (two-stream
                            schedule), 1..8; 0 = the built-in rule (1 for the wave-sliced
-                           gather at N >= 256 in FP32 / 128 in FP64, else 3). */
+                           gather at N >= 256 in FP32 / 128 in FP64, else 3).
+     update_kernel         the rank-k update of an FP64 crowd: 1 = vector units (k_flush_vec),
+                           2 = FP64 matrix cores (strips of 16 rows, N % 16 == 0 and N <= 1024;
+                           otherwise the vector units); 0 = the default, vector units.  FP32
+                           crowds always take the FP32 matrix-core update when N % 32 == 0 (the
+                           field is ignored). */
 typedef struct cq_tiles {
     int candidates;
     int gather_blocks_per_cu;
+    int update_kernel;
 } cq_tiles;
 
 /* Set the launch shapes (values as above; 0 keeps a field's default).  Takes effect from
    the next sweep (a captured sweep graph is rebuilt).  Other paths accept and ignore them.
    Errors: CQ_EINVAL (out of range; nothing changes). */
 cq_status cq_crowd_set_tiles(cq_crowd* c, const cq_tiles* t);
-/* The launch shapes in use, defaults resolved (candidates = Q; gather_blocks_per_cu as
-   launched). */
+/* The launch shapes in use, defaults resolved (candidates = Q; gather_blocks_per_cu and
+   update_kernel (1 vector units, 2 matrix cores) as launched). */
 cq_status cq_crowd_get_tiles(cq_crowd* c, cq_tiles* t);
 
 /* Tile autotuning for the batched path.  With cache_path non-NULL and an entry in it for
    this device (architecture name and compute-unit count), N, walkers, precision and delay
    rank, apply that entry and time nothing (*from_cache = 1).  Otherwise time
    sweeps_per_candidate sweeps (eager launches, HIP events, after one untimed sweep that
-   learns the round plan) for every candidate pair: Q in {1.5 k, 2 k, default} within the
-   limits above, gather workgroups per CU in {1, 2, 3}; keep the fastest and, with
+   learns the round plan) for every candidate: Q in {1.5 k, 2 k, default} within the
+   limits above, gather workgroups per CU in {1, 2, 3} and, for an FP64 crowd whose N the
+   matrix-core update takes, both update kernels; keep the fastest and, with
    cache_path, append it to the cache (*from_cache = 0).  Every timed sweep is an ordinary
    sweep of the chain.  On other paths nothing is timed and the defaults stay.  chosen and
    from_cache may be NULL.  Errors: CQ_EINVAL, CQ_ESTATE (positions not set), CQ_EIO (the
@@ -333,7 +340,8 @@ cq_status cq_crowd_autotune_tiles(cq_crowd* c, int sweeps_per_candidate, const c
 
 /* The tile cache (host only, no GPU call).  A JSON file: an array with one object per line,
    {"device": "...", "n": N, "walkers": W, "precision": "mixed"|"fp64", "delay_rank": k,
-   "candidates": Q, "gather_blocks_per_cu": g, "ms_per_sweep": t}.  Lookup returns the last
+   "candidates": Q, "gather_blocks_per_cu": g, "update_kernel": u, "ms_per_sweep": t}
+   (an entry without update_kernel reads as 0).  Lookup returns the last
    entry that matches every key (*found = 0 and *out untouched if none, or if the file does
    not exist); lines that do not parse are skipped.  Store appends an entry (creating the
    file), keeping the file a valid JSON array.  device: at most 127 bytes, no '"' or '\'.

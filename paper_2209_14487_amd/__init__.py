@@ -43,8 +43,13 @@ class CrowdDesc(ctypes.Structure):
 
 
 class Tiles(ctypes.Structure):
-    """cq_tiles: candidates per round (Q) and gather workgroups per CU beside the update."""
-    _fields_ = [("candidates", ctypes.c_int), ("gather_blocks_per_cu", ctypes.c_int)]
+    """cq_tiles: candidates per round (Q), gather workgroups per CU beside the update, and the
+    FP64 update kernel (1 vector units, 2 matrix cores; 0 default)."""
+    _fields_ = [("candidates", ctypes.c_int), ("gather_blocks_per_cu", ctypes.c_int), ("update_kernel", ctypes.c_int)]
+
+
+def _tiles_dict(t):
+    return dict(candidates=t.candidates, gather_blocks_per_cu=t.gather_blocks_per_cu, update_kernel=t.update_kernel)
 
 
 _lib = None
@@ -155,13 +160,13 @@ def tile_cache_find(path, device: str, n: int, walkers: int, precision, delay_ra
     t, found = Tiles(), ctypes.c_int()
     _check(lib().cq_tile_cache_find(os.fsencode(path), device.encode(), int(n), int(walkers), _prec(precision),
                                     int(delay_rank), ctypes.byref(t), ctypes.byref(found)))
-    return dict(candidates=t.candidates, gather_blocks_per_cu=t.gather_blocks_per_cu) if found.value else None
+    return _tiles_dict(t) if found.value else None
 
 
 def tile_cache_store(path, device: str, n: int, walkers: int, precision, delay_rank: int, candidates: int,
-                     gather_blocks_per_cu: int, ms_per_sweep: float):
+                     gather_blocks_per_cu: int, ms_per_sweep: float, update_kernel: int = 0):
     """Append an entry to the tile cache (cq_tile_cache_store; host only)."""
-    t = Tiles(int(candidates), int(gather_blocks_per_cu))
+    t = Tiles(int(candidates), int(gather_blocks_per_cu), int(update_kernel))
     _check(lib().cq_tile_cache_store(os.fsencode(path), device.encode(), int(n), int(walkers), _prec(precision),
                                      int(delay_rank), ctypes.byref(t), float(ms_per_sweep)))
 
@@ -421,15 +426,15 @@ class Crowd:
         _check(lib().cq_crowd_get_round_plan(self._h, r.ctypes.data))
         return r
 
-    def set_tiles(self, candidates: int = 0, gather_blocks_per_cu: int = 0):
+    def set_tiles(self, candidates: int = 0, gather_blocks_per_cu: int = 0, update_kernel: int = 0):
         """Launch shapes of the batched path (0: default); see cq_crowd_set_tiles."""
-        t = Tiles(int(candidates), int(gather_blocks_per_cu))
+        t = Tiles(int(candidates), int(gather_blocks_per_cu), int(update_kernel))
         _check(lib().cq_crowd_set_tiles(self._h, ctypes.byref(t)))
 
     def tiles(self) -> dict:
         t = Tiles()
         _check(lib().cq_crowd_get_tiles(self._h, ctypes.byref(t)))
-        return dict(candidates=t.candidates, gather_blocks_per_cu=t.gather_blocks_per_cu)
+        return _tiles_dict(t)
 
     def autotune_tiles(self, sweeps_per_candidate: int = 1, cache_path=None):
         """Time the candidate launch shapes (or take them from the JSON cache); returns
@@ -438,7 +443,7 @@ class Crowd:
         path = None if cache_path is None else os.fsencode(cache_path)
         _check(lib().cq_crowd_autotune_tiles(self._h, int(sweeps_per_candidate), path, ctypes.byref(t),
                                              ctypes.byref(hit)))
-        return dict(candidates=t.candidates, gather_blocks_per_cu=t.gather_blocks_per_cu), bool(hit.value)
+        return _tiles_dict(t), bool(hit.value)
 
     def path(self) -> str:
         """The kernel path in use ("multi", "window", "batch" or "sweep")."""

@@ -68,7 +68,7 @@ struct cq_crowd {
     int Kcap = 1;  // largest delay rank the window buffers hold
     // batched path: candidate buffers hold Qcap per walker; q_req (0: the default rule) and
     // vgl_wg (gather workgroups per CU beside the update, 0: built-in) are cq_crowd_set_tiles'
-    int Qcap = 1, q_req = 0, vgl_wg = 0;
+    int Qcap = 1, q_req = 0, vgl_wg = 0, upd_kernel = 0;
     bool autotune = false, tuned = false;
     int path = CQ_PATH_WINDOW;
     uint64_t seed = 0;
@@ -208,6 +208,7 @@ cq::CrowdView<T> view(const cq_crowd* c)
     v.Q = c->Q;
     v.QR = c->QR;
     v.vgl_wg = c->vgl_wg;
+    v.upd_mfma = c->upd_kernel == 2;
     v.G = c->sys->G;
     v.n_orb = c->sys->n_orb;
     v.L = c->sys->L;
@@ -1670,6 +1671,7 @@ cq_status cq_crowd_set_tiles(cq_crowd* c, const cq_tiles* t)
     }
     if (t->gather_blocks_per_cu < 0 || t->gather_blocks_per_cu > 8)
         return fail(CQ_EINVAL, "gather_blocks_per_cu must be 0..8");
+    if (t->update_kernel < 0 || t->update_kernel > 2) return fail(CQ_EINVAL, "update_kernel must be 0..2");
     if (t->candidates < 0) return fail(CQ_EINVAL, "candidates must be >= 0");
     if (c->path != CQ_PATH_BATCH) return CQ_OK;
     if (t->candidates > 0 && (t->candidates < min_candidates(c) || t->candidates > c->Qcap))
@@ -1679,6 +1681,7 @@ cq_status cq_crowd_set_tiles(cq_crowd* c, const cq_tiles* t)
     HIP_TRY(hipStreamSynchronize(c->stream));
     c->q_req = t->candidates;
     c->vgl_wg = t->gather_blocks_per_cu;
+    c->upd_kernel = t->update_kernel;
     apply_q(c);
     drop_graph(c);
     reset_plan(c);
@@ -1692,10 +1695,13 @@ cq_status cq_crowd_get_tiles(cq_crowd* c, cq_tiles* t)
     if (x->path != CQ_PATH_BATCH) {
         t->candidates = 0;
         t->gather_blocks_per_cu = 0;
+        t->update_kernel = 0;
         return CQ_OK;
     }
     t->candidates = x->Q;
     t->gather_blocks_per_cu = cq::batch_vgl_blocks_per_cu(x->n, x->prec == CQ_FP64 ? 8 : 4, x->vgl_wg);
+    t->update_kernel = (x->prec == CQ_FP64 ? x->upd_kernel == 2 && cq::flush_f64_mfma_fits(x->n)
+                                            : cq::flush_mfma_fits(x->n)) ? 2 : 1;
     return CQ_OK;
 }
 
@@ -1782,19 +1788,24 @@ cq_status autotune_tiles(cq_crowd* c, int sweeps, const char* cache, cq_tiles* c
         (void)hipEventDestroy(a);
         return fail(CQ_EDEVICE, "hipEventCreate failed");
     }
-    cq_tiles best{0, 0};
+    // the FP64 update kernels: vector units, and the matrix cores when they take this N
+    std::vector<int> uks{1};
+    if (c->prec == CQ_FP64 && cq::flush_f64_mfma_fits(c->n)) uks.push_back(2);
+    cq_tiles best{0, 0, 0};
     float best_ms = 0.0f;
     for (int q : qs)
-        for (int g = 1; g <= 3 && st == CQ_OK; ++g) {
-            const cq_tiles t{q, g};
-            st = cq_crowd_set_tiles(c, &t);
-            float ms = 0.0f;
-            if (st == CQ_OK) st = time_sweeps(c, sweeps, a, b, &ms);
-            if (st == CQ_OK && (best_ms == 0.0f || ms < best_ms)) {
-                best_ms = ms;
-                best = t;
+        for (int g = 1; g <= 3 && st == CQ_OK; ++g)
+            for (int uk : uks) {
+                if (st != CQ_OK) break;
+                const cq_tiles t{q, g, c->prec == CQ_FP64 ? uk : 0};
+                st = cq_crowd_set_tiles(c, &t);
+                float ms = 0.0f;
+                if (st == CQ_OK) st = time_sweeps(c, sweeps, a, b, &ms);
+                if (st == CQ_OK && (best_ms == 0.0f || ms < best_ms)) {
+                    best_ms = ms;
+                    best = t;
+                }
             }
-        }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     if (st != CQ_OK) return st;

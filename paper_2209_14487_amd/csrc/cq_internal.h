@@ -64,6 +64,7 @@ struct CrowdView {
     int Wcap;            // walker capacity: the walker stride of the record and forced-decision buffers
     int Q;               // candidates per round (batched path), else K
     int vgl_wg;          // gather workgroups per CU beside the update (batched path; 0: built-in rule)
+    int upd_mfma;        // FP64 batched path: the rank-k update on the FP64 matrix cores
     int QR;              // stage slots per walker: K, or the candidate ring of the batched path (2 Q,
                          // so a round's new candidates never reuse a slot the previous window's
                          // update still reads)
@@ -210,6 +211,8 @@ int batch_candidates(int n, int K);  // candidates per round, Q
 // linv_ready: the window's L^-1 is already in wlinv (the batched path forms it)
 template <typename T> void launch_flush(const CrowdView<T>& v, int spin, hipStream_t s, bool linv_ready = false);
 bool flush_mfma_fits(int n);  // the FP32 matrix-core update handles this N
+bool flush_f64_mfma_fits(int n);  // the FP64 matrix-core update of the batched path handles this N
+void launch_flush_f64_mfma(const CrowdView<double>& v, int spin, hipStream_t s);
 void launch_flush_mfma(const CrowdView<float>& v, int spin, hipStream_t s, bool linv_ready);
 template <typename T> void launch_energy(const CrowdView<T>& v, hipStream_t s);
 // nmat < 0: the 2 W matrices of the view; else matrices 0 .. nmat-1 (matrix m at (m / 2, m % 2))

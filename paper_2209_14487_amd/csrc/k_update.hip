@@ -198,6 +198,13 @@ void launch_flush(const CrowdView<T>& v, int spin, hipStream_t s, bool linv_read
             launch_flush_mfma(v, spin, s, linv_ready);
             return;
         }
+    } else {
+        // the batched path (its windows come with linv_ready), when its shapes ask for the
+        // FP64 matrix cores
+        if (linv_ready && v.upd_mfma && flush_f64_mfma_fits(v.n)) {
+            launch_flush_f64_mfma(v, spin, s);
+            return;
+        }
     }
     constexpr int VEC = 16 / sizeof(T);
     const int nstrip = (v.n + kRowsPerBlock - 1) / kRowsPerBlock;

@@ -131,9 +131,12 @@ extern "C" cq_status cq_tile_cache_find(const char* path, const char* device, in
         long q, g;
         if (!parse_line(line, m) || !matches(m, device, n, walkers, precision, delay_rank)) continue;
         if (!get_int(m, "candidates", &q) || !get_int(m, "gather_blocks_per_cu", &g)) continue;
-        if (q < 0 || q > 1 << 20 || g < 0 || g > 64) continue;
+        long u = 0;
+        if (m.count("update_kernel") && !get_int(m, "update_kernel", &u)) continue;
+        if (q < 0 || q > 1 << 20 || g < 0 || g > 64 || u < 0 || u > 2) continue;
         out->candidates = (int)q;
         out->gather_blocks_per_cu = (int)g;
+        out->update_kernel = (int)u;
         *found = 1;  // keep scanning: the last matching entry wins
     }
     return CQ_OK;
@@ -145,7 +148,8 @@ extern "C" cq_status cq_tile_cache_store(const char* path, const char* device, i
     if (!path || !t) return cq::host_fail(CQ_EINVAL, "tile cache: NULL argument");
     if (!valid_device(device)) return cq::host_fail(CQ_EINVAL, "tile cache: bad device name");
     if (n < 1 || walkers < 1 || delay_rank < 1 || (precision != CQ_FP64 && precision != CQ_MIXED) ||
-        t->candidates < 0 || t->gather_blocks_per_cu < 0 || t->gather_blocks_per_cu > 64 || !(ms_per_sweep >= 0.0))
+        t->candidates < 0 || t->gather_blocks_per_cu < 0 || t->gather_blocks_per_cu > 64 || t->update_kernel < 0 ||
+        t->update_kernel > 2 || !(ms_per_sweep >= 0.0))
         return cq::host_fail(CQ_EINVAL, "tile cache: bad entry");
     std::vector<std::string> lines;
     bool exists = false;
@@ -160,9 +164,9 @@ extern "C" cq_status cq_tile_cache_store(const char* path, const char* device, i
     char buf[512];
     std::snprintf(buf, sizeof buf,
                   "{\"device\": \"%s\", \"n\": %d, \"walkers\": %d, \"precision\": \"%s\", \"delay_rank\": %d, "
-                  "\"candidates\": %d, \"gather_blocks_per_cu\": %d, \"ms_per_sweep\": %.6g}",
+                  "\"candidates\": %d, \"gather_blocks_per_cu\": %d, \"update_kernel\": %d, \"ms_per_sweep\": %.6g}",
                   device, n, walkers, prec_name(precision), delay_rank, t->candidates, t->gather_blocks_per_cu,
-                  ms_per_sweep);
+                  t->update_kernel, ms_per_sweep);
     keep.push_back(buf);
     // write a sibling file, then rename it over the cache
     const std::string tmp = std::string(path) + ".tmp";

@@ -596,8 +596,10 @@ def test_tile_autotune_keeps_the_chain_and_uses_its_cache(tmp_path):
     crowd.set_positions(R0)
     t, hit = crowd.autotune_tiles(1, cache)
     assert not hit and t["candidates"] in (6, 8, 12) and t["gather_blocks_per_cu"] in (1, 2, 3)
+    assert t["update_kernel"] in (1, 2)
     assert crowd.tiles() == t
-    tuned_sweeps = 3 * 3 * 2  # Q in {6, 8, 12} x {1, 2, 3} workgroups per CU, 1 + 1 sweeps each
+    # Q in {6, 8, 12} x {1, 2, 3} workgroups per CU x {vector, matrix-core} FP64 update, 1 + 1 sweeps each
+    tuned_sweeps = 3 * 3 * 2 * 2
     crowd.record(S)
     crowd.run_vmc(S, 0.5)
     ref = orc.vmc(o, R0, tuned_sweeps + S, sigma=0.5)
@@ -608,7 +610,8 @@ def test_tile_autotune_keeps_the_chain_and_uses_its_cache(tmp_path):
         assert np.all(np.abs(rec[key][0] - b) <= 1e-10 * np.maximum(1.0, np.abs(b))), key
     entry = json.load(open(cache))[-1]
     assert (entry["n"], entry["walkers"], entry["precision"], entry["delay_rank"]) == (n, W, "fp64", k)
-    assert (entry["candidates"], entry["gather_blocks_per_cu"]) == (t["candidates"], t["gather_blocks_per_cu"])
+    assert (entry["candidates"], entry["gather_blocks_per_cu"], entry["update_kernel"]) == (
+        t["candidates"], t["gather_blocks_per_cu"], t["update_kernel"])
     crowd.close()
     # the same key again: from the cache, no sweep run (the chain starts at sweep 0)
     crowd = cq.Crowd(g, W, precision="fp64", delay_rank=k, seed=seed, path="batch")
@@ -621,7 +624,7 @@ def test_tile_autotune_keeps_the_chain_and_uses_its_cache(tmp_path):
     assert np.array_equal(rec["acc"][0], ref.acc[0])
     assert np.all(np.abs(rec["rho"][0] - ref.rho[0]) <= 1e-10 * np.maximum(1.0, np.abs(ref.rho[0])))
     # shapes out of range are refused and change nothing; other paths report none
-    for bad in (dict(candidates=3), dict(candidates=13), dict(gather_blocks_per_cu=9)):
+    for bad in (dict(candidates=3), dict(candidates=13), dict(gather_blocks_per_cu=9), dict(update_kernel=3)):
         with pytest.raises(cq.CqError) as ei:
             crowd.set_tiles(**bad)
         assert ei.value.status == cq.CQ_EINVAL
@@ -629,9 +632,32 @@ def test_tile_autotune_keeps_the_chain_and_uses_its_cache(tmp_path):
     crowd.close()
     sweep = cq.Crowd(g, W, precision="fp64", seed=seed, path="sweep")
     sweep.set_positions(R0)
-    assert sweep.tiles() == dict(candidates=0, gather_blocks_per_cu=0)
-    assert sweep.autotune_tiles(1, cache) == (dict(candidates=0, gather_blocks_per_cu=0), False)
+    none = dict(candidates=0, gather_blocks_per_cu=0, update_kernel=0)
+    assert sweep.tiles() == none
+    assert sweep.autotune_tiles(1, cache) == (none, False)
     sweep.close()
+    g.close()
+
+
+@pytest.mark.parametrize("n,L,G,W,S,k", [(32, 10.0, 48, 16, 2, 8), (64, 12.0, 48, 8, 2, 4), (256, 20.0, 64, 3, 1, 32)])
+def test_fp64_matrix_core_update_keeps_the_chain(n, L, G, W, S, k):
+    """The FP64 rank-k update on the matrix cores (update_kernel = 2: strips of 16 rows of the
+    inverse, both products on v_mfma_f64_16x16x4f64, forward substitution in move order) follows
+    the oracle's chain like the vector one: decisions, ratios and ln J changes within 1e-10 (or,
+    where the two FP64 update chains have parted by more, of the refined ratio)."""
+    seed = 1013
+    g, o = make_pair(n, L, G, seed, coef_seed=seed)
+    R0 = start_positions(seed, W, 2 * n, L)
+    crowd = cq.Crowd(g, W, precision="fp64", delay_rank=k, seed=seed, path="batch")
+    crowd.set_tiles(update_kernel=2)
+    assert crowd.tiles()["update_kernel"] == 2
+    gpu = run_gpu(crowd, R0, S, 0.5)
+    ref = orc.vmc(o, R0, S, sigma=0.5)
+    arbitrated_fp64_check(gpu, ref, o, R0, range(W), range(W), S * 2 * n)
+    if np.array_equal(gpu["acc"], ref.acc):  # the same chain throughout: log|det| and E_L of its end
+        assert np.all(np.abs(gpu["logdet"][-1] - ref.logdet[-1]) <= 1e-9 * np.maximum(1.0, np.abs(ref.logdet[-1])))
+        assert np.all(np.abs(gpu["eloc"][-1] - ref.eloc[-1]) <= 1e-8 * np.maximum(1.0, np.abs(ref.eloc[-1])))
+    crowd.close()
     g.close()
 
 # Full C4 size: 1024 + 1024 electrons, L = 32, 96^3 seeded table, Pade J2, a crowd of 128
