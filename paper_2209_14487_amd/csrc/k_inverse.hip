@@ -181,114 +181,133 @@ __global__ __launch_bounds__(kBlock) void k_gj_load(CrowdView<T> v, double* __re
     }
 }
 
-// Sweep the b panel columns k0 .. k0+b-1 of every matrix (one workgroup per
-// matrix, panel and row-use flags in LDS), record the pivots, copy the old
-// pivot rows.
-// The old pivot rows go to rows pr0 .. pr0+b-1 of the matrix's pr_rows-row block
-// of PR.
-__global__ __launch_bounds__(kBlock) void k_gj_panel(double* __restrict__ S, double* __restrict__ PR,
-                                                      int* __restrict__ pivrow, int* __restrict__ rowstate,
-                                                      double* __restrict__ logabs, int* __restrict__ negs,
-                                                      int* __restrict__ status,
-                                                      const unsigned long long* __restrict__ scale, int n, int b,
-                                                      int k0, int panel, int pr_rows, int pr0)
+// Sweep the b panel columns k0 .. k0+b-1 of every matrix (b <= BP; one workgroup per
+// matrix), record the pivots, copy the old pivot rows.  The panel lives in registers:
+// thread t of TH holds rows t, t + TH, ... (R of them) with their b panel columns, so a sweep
+// is a wave argmax, one barrier and a rank-1 update of the thread's own rows.  Each
+// wave hands its candidate pivot row to the others through LDS with its argmax, and
+// the LDS slots alternate with the parity of the sweep, so one barrier per sweep is
+// enough.  Pivot choice: the largest |B[i][k]| among the unused rows, the lowest index
+// on ties; rows whose entry is NaN rank below every number, so a column of NaNs still
+// takes the first unused row (and is flagged).
+// The old pivot rows go to rows pr0 .. pr0+b-1 of the matrix's pr_rows-row block of PR.
+template <int TH, int R, int BP>
+__global__ __launch_bounds__(TH) void k_gj_panel(double* __restrict__ S, double* __restrict__ PR,
+                                                             int* __restrict__ pivrow, int* __restrict__ rowstate,
+                                                             double* __restrict__ logabs, int* __restrict__ negs,
+                                                             int* __restrict__ status,
+                                                             const unsigned long long* __restrict__ scale, int n,
+                                                             int b, int k0, int panel, int pr_rows, int pr0)
 {
-    extern __shared__ double sh[];
-    double* P = sh;                    // [n][b]
-    double* colk = P + (size_t)n * b;  // [n]
-    int* used = (int*)(colk + n);      // [n]
-    __shared__ double rowp[64];
-    __shared__ double wbest[4];
-    __shared__ int wbi[4];
-    __shared__ int pivs[64];
-    __shared__ double s_piv;
+    constexpr int kPanelThreads = TH, kPanelWaves = TH / 64;
+    __shared__ double wrow[2][kPanelWaves][BP];  // each wave's candidate pivot row
+    __shared__ double wval[2][kPanelWaves];
+    __shared__ int widx[2][kPanelWaves];
+    __shared__ int pivs[BP];
     const int mat = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     double* Sm = S + (size_t)mat * n * n;
     int* rs = rowstate + (size_t)mat * n;
-    for (int i0 = 0; i0 < n * b; i0 += 8 * kBlock) {  // 8 loads in flight per thread
-        double x[8];
+    double x[R][BP];
+    int used[R];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int idx = i0 + u * kBlock + tid;
-            x[u] = idx < n * b ? Sm[(size_t)(idx / b) * n + k0 + idx % b] : 0.0;
-        }
+    for (int r = 0; r < R; ++r) {
+        const int i = tid + r * kPanelThreads;
+        const bool live = i < n;
+        used[r] = live ? rs[i] : 1;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int idx = i0 + u * kBlock + tid;
-            if (idx < n * b) P[idx] = x[u];
-        }
+        for (int j = 0; j < BP; ++j) x[r][j] = (live && j < b) ? Sm[(size_t)i * n + k0 + j] : 0.0;
     }
-    for (int i = tid; i < n; i += kBlock) used[i] = rs[i];
-    __syncthreads();
     const double tiny = n * 2.220446049250313e-16 * __longlong_as_double((long long)scale[mat]);
     double la = 0.0;
     int ng = 0, bad = 0;
-    for (int q = 0; q < b; ++q) {
+#pragma unroll
+    for (int q = 0; q < BP; ++q) {
+        if (q >= b) break;
+        const int par = q & 1;
         double best = -1.0;
         int bi = n;
-        for (int i = tid; i < n; i += kBlock)
-            if (used[i] == 0) {
-                const double val = fabs(P[i * b + q]);
-                if (val > best) { best = val; bi = i; }
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (used[r] == 0) {
+                const double a = fabs(x[r][q]);
+                const double key = a == a ? a : -0.5;
+                if (key > best) {
+                    best = key;
+                    bi = tid + r * kPanelThreads;
+                }
             }
         wave_argmax(best, bi);
-        if (lane == 0) { wbest[wave] = best; wbi[wave] = bi; }
-        __syncthreads();
-        if (tid == 0) {
-            double bb = wbest[0];
-            int ii = wbi[0];
-            for (int x = 1; x < 4; ++x)
-                if (wbest[x] > bb || (wbest[x] == bb && wbi[x] < ii)) { bb = wbest[x]; ii = wbi[x]; }
-            if (ii >= n)  // every candidate is NaN: take the first unused row, flagged below
-                for (int i = n - 1; i >= 0; --i)
-                    if (used[i] == 0) ii = i;
-            pivs[q] = ii;
-            s_piv = P[ii * b + q];
-            used[ii] = panel + 1;
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (tid + r * kPanelThreads == bi)
+#pragma unroll
+                for (int j = 0; j < BP; ++j) wrow[par][wave][j] = x[r][j];
+        if (lane == 0) {
+            wval[par][wave] = best;
+            widx[par][wave] = bi;
         }
         __syncthreads();
-        const int p = pivs[q];
-        const double piv = s_piv;
+        // every thread combines the waves' candidates in wave order (same result everywhere);
+        // some row is always unused, since a matrix has n rows and n sweeps
+        int ww = 0, p = widx[par][0];
+        double bb = wval[par][0];
+#pragma unroll
+        for (int o = 1; o < kPanelWaves; ++o) {
+            const double ov = wval[par][o];
+            const int oi = widx[par][o];
+            if (ov > bb || (ov == bb && oi < p)) {
+                bb = ov;
+                p = oi;
+                ww = o;
+            }
+        }
+        double rowp[BP];
+#pragma unroll
+        for (int j = 0; j < BP; ++j) rowp[j] = wrow[par][ww][j];
+        const double piv = rowp[q];
         if (!(fabs(piv) > tiny) || !isfinite(piv)) bad = 1;
         la += log(fabs(piv));
         ng += piv < 0.0;
-        for (int i = tid; i < n; i += kBlock) colk[i] = P[i * b + q];
-        if (tid < b) rowp[tid] = P[p * b + tid];
-        __syncthreads();
         const double ipiv = 1.0 / piv;
-        for (int idx = tid; idx < n * b; idx += kBlock) {
-            const int i = idx / b, j = idx % b;
-            double val;
-            if (i == p)
-                val = (j == q) ? ipiv : rowp[j] * ipiv;
-            else if (j == q)
-                val = -colk[i] * ipiv;
-            else
-                val = P[idx] - colk[i] * rowp[j] * ipiv;
-            P[idx] = val;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (tid + r * kPanelThreads == p) {
+#pragma unroll
+                for (int j = 0; j < BP; ++j) x[r][j] = (j == q) ? ipiv : rowp[j] * ipiv;
+                used[r] = panel + 1;
+            } else {
+                const double c = x[r][q];
+#pragma unroll
+                for (int j = 0; j < BP; ++j) x[r][j] = (j == q) ? -c * ipiv : x[r][j] - c * rowp[j] * ipiv;
+            }
         }
-        __syncthreads();
+        if (tid == 0) pivs[q] = p;
     }
+    __syncthreads();
     // old pivot rows (all columns; the panel columns of PR are not used)
-    for (int i0 = 0; i0 < n * b; i0 += 8 * kBlock) {  // 8 loads in flight per thread
-        double x[8];
+    for (int i0 = 0; i0 < n * b; i0 += 8 * kPanelThreads) {  // 8 loads in flight per thread
+        double y[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            const int idx = i0 + u * kBlock + tid;
-            x[u] = idx < n * b ? Sm[(size_t)pivs[idx / n] * n + idx % n] : 0.0;
+            const int idx = i0 + u * kPanelThreads + tid;
+            y[u] = idx < n * b ? Sm[(size_t)pivs[idx / n] * n + idx % n] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            const int idx = i0 + u * kBlock + tid;
-            if (idx < n * b) PR[((size_t)mat * pr_rows + pr0 + idx / n) * n + idx % n] = x[u];
+            const int idx = i0 + u * kPanelThreads + tid;
+            if (idx < n * b) PR[((size_t)mat * pr_rows + pr0 + idx / n) * n + idx % n] = y[u];
         }
     }
     __syncthreads();
-    for (int idx = tid; idx < n * b; idx += kBlock) {
-        const int i = idx / b, q = idx % b;
-        Sm[(size_t)i * n + k0 + q] = P[idx];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = tid + r * kPanelThreads;
+        if (i >= n) continue;
+#pragma unroll
+        for (int j = 0; j < BP; ++j)
+            if (j < b) Sm[(size_t)i * n + k0 + j] = x[r][j];
+        rs[i] = used[r];
     }
-    for (int i = tid; i < n; i += kBlock) rs[i] = used[i];
     if (tid < b) pivrow[(size_t)mat * n + k0 + tid] = pivs[tid];
     if (tid == 0) {
         logabs[mat] += la;
@@ -297,61 +316,87 @@ __global__ __launch_bounds__(kBlock) void k_gj_panel(double* __restrict__ S, dou
     }
 }
 
-// Rank-b update (b <= BMAX) of the columns j in [jlo, jhi) outside [xlo, xhi), for
-// the column tiles jt0 .. jt0+njt-1: 64 x 64 output tile per workgroup (4 waves).  The
-// multipliers are S's columns k0 .. k0+b-1, the old pivot rows are rows pr0 ..
-// pr0+b-1 of PR's pr_rows-row block, and the pivot rows of the update are the
-// rows whose state lies in (plo, phi] (state = panel index + 1).
+// Rank-b update of the columns j in [jlo, jhi) outside [xlo, xhi), for the column tiles
+// jt0 .. jt0+njt-1: 64 x 64 output tile per workgroup (4 waves), the b multipliers and
+// old pivot rows staged through LDS KC at a time (the next chunk's loads in flight during
+// the current chunk's products; small chunks leave room for 4 workgroups per CU).  The
+// multipliers are S's columns k0 .. k0+b-1, the old pivot rows are rows pr0 .. pr0+b-1 of
+// PR's pr_rows-row block, and the pivot rows of the update are the rows whose state lies
+// in (plo, phi] (state = panel index + 1).  The tiles of one matrix run on one XCD, so
+// the operands they share stay in that XCD's L2.
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-template <int BMAX>
+template <int KC>
 __global__ __launch_bounds__(kBlock) void k_gj_update(double* __restrict__ S, const double* __restrict__ PR,
-                                                       const int* __restrict__ rowstate, int n, int b, int k0,
-                                                       int pr_rows, int pr0, int plo, int phi, int jt0, int njt,
-                                                       int jlo, int jhi, int xlo, int xhi)
+                                                       const int* __restrict__ rowstate, int nmat, int n, int b,
+                                                       int k0, int pr_rows, int pr0, int plo, int phi, int jt0,
+                                                       int njt, int jlo, int jhi, int xlo, int xhi)
 {
-    __shared__ double Pt[64][BMAX + 1];   // multiplier rows i0..i0+63, q < b
-    __shared__ double Rt[BMAX][65];       // old pivot rows q < b, columns j0..j0+63
+    __shared__ double Pt[64][KC + 1];  // multiplier rows i0..i0+63, one chunk of q
+    __shared__ double Rt[KC][65];      // one chunk of old pivot rows, columns j0..j0+63
     const int tiles = (n + 63) / 64;
-    const int mat = blockIdx.x / (tiles * njt), t = blockIdx.x % (tiles * njt);
+    int mat, t;
+    xcd_map(blockIdx.x, tiles * njt, mat, t);
+    if (mat >= nmat) return;
     const int i0 = (t / njt) * 64, j0 = (jt0 + t % njt) * 64;
     double* Sm = S + (size_t)mat * n * n;
     const int* rs = rowstate + (size_t)mat * n;
     const int tid = threadIdx.x;
-    {
-        // every load of the two operand tiles in flight before the LDS writes
-        constexpr int U = 64 * BMAX / kBlock;
-        double xp[U], xr[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int idx = tid + u * kBlock;
-            const int r = idx / b, q = idx % b, qr = idx / 64, c = idx % 64;
-            xp[u] = (idx < 64 * b && i0 + r < n) ? Sm[(size_t)(i0 + r) * n + k0 + q] : 0.0;
-            xr[u] = (idx < 64 * b && j0 + c < n) ? PR[((size_t)mat * pr_rows + pr0 + qr) * n + j0 + c] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int idx = tid + u * kBlock;
-            if (idx < 64 * b) {
-                Pt[idx / b][idx % b] = xp[u];
-                Rt[idx / 64][idx % 64] = xr[u];
-            }
-        }
-    }
-    __syncthreads();
     // FP64 matrix cores (v_mfma_f64_16x16x4f64): wave wv owns the 32 x 32 quarter
     // (rows 32 (wv / 2), columns 32 (wv % 2)) as 2 x 2 blocks of 16 x 16.  Lane l
     // supplies A[l % 16][l / 16] and B[l / 16][l % 16] of a step of 4 q values and
-    // holds D[l / 16 + 4 v][l % 16]; b is a multiple of 4.
+    // holds D[l / 16 + 4 v][l % 16]; operands past b are zero.
     const int lane = tid & 63, wv = tid >> 6;
     const int r16 = lane & 15, q4 = lane >> 4;
     const int wi = (wv >> 1) * 32, wj = (wv & 1) * 32;
+    constexpr int U = 64 * KC / kBlock;
+    static_assert(U * kBlock == 64 * KC, "chunk loads");
+    double xp[U], xr[U];
+    auto load_chunk = [&](int kc) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int idx = tid + u * kBlock;
+            const int r = idx / KC, q = idx % KC, qr = idx / 64, c = idx % 64;
+            xp[u] = (kc + q < b && i0 + r < n) ? Sm[(size_t)(i0 + r) * n + k0 + kc + q] : 0.0;
+            xr[u] = (kc + qr < b && j0 + c < n) ? PR[((size_t)mat * pr_rows + pr0 + kc + qr) * n + j0 + c] : 0.0;
+        }
+    };
     f64x4 acc[2][2];
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = f64x4{0.0, 0.0, 0.0, 0.0};
-    // the tile's old values, loaded before the products so that their latency is hidden
+    auto stage = [&](bool first) {
+        if (!first) __syncthreads();  // the previous chunk's products are done with the LDS
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int idx = tid + u * kBlock;
+            Pt[idx / KC][idx % KC] = xp[u];
+            Rt[idx / 64][idx % 64] = xr[u];
+        }
+        __syncthreads();
+    };
+    auto products = [&]() {
+#pragma unroll
+        for (int q0 = 0; q0 < KC; q0 += 4) {
+            const double a0 = Pt[wi + r16][q0 + q4], a1 = Pt[wi + 16 + r16][q0 + q4];
+            const double b0 = Rt[q0 + q4][wj + r16], b1 = Rt[q0 + q4][wj + 16 + r16];
+            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+        }
+    };
+    // every chunk but the last: the next chunk's loads in flight during the products
+    const int nch = (b + KC - 1) / KC;
+    load_chunk(0);
+    for (int c = 0; c + 1 < nch; ++c) {
+        stage(c == 0);
+        load_chunk((c + 1) * KC);
+        products();
+    }
+    stage(nch == 1);
+    // the tile's old values, in flight during the last chunk's products
     double old[2][2][4];
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
@@ -365,14 +410,7 @@ __global__ __launch_bounds__(kBlock) void k_gj_update(double* __restrict__ S, co
                 old[bi][bj][v] = live ? Sm[(size_t)i * n + j] : 0.0;
             }
         }
-    for (int q0 = 0; q0 < b; q0 += 4) {
-        const double a0 = Pt[wi + r16][q0 + q4], a1 = Pt[wi + 16 + r16][q0 + q4];
-        const double b0 = Rt[q0 + q4][wj + r16], b1 = Rt[q0 + q4][wj + 16 + r16];
-        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
-    }
+    products();
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
@@ -474,30 +512,35 @@ void launch_inverse(const CrowdView<T>& v, const InvWork& wk, hipStream_t s, int
     hipLaunchKernelGGL(k_gj_reset, dim3(256), dim3(kBlock), 0, s, rowstate, wk.logabs, wk.negs, mstatus, scale,
                        nmat, n);
     hipLaunchKernelGGL(k_gj_load<T>, dim3(nmat * tiles * tiles), dim3(kBlock), 0, s, v, wk.S, scale);
-    // panel width: the n x b panel plus a column and the row flags must fit in LDS
     const int bmax = panel_width(n);
-    const size_t panel_lds = ((size_t)n * bmax + n) * sizeof(double) + (size_t)n * sizeof(int);
-    (void)hipFuncSetAttribute((const void*)k_gj_panel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)panel_lds);
     const int B = block_width(n), per_block = B / bmax;
     static_assert(kBlock == 256, "update tiles");
+    const int mat_groups = ((nmat + 7) / 8) * 8;  // update grids: the tiles of a matrix on one XCD
     for (int K0 = 0, blk = 0; K0 < n; K0 += B, ++blk) {
         const int Bw = min(B, n - K0);  // the last block may be narrower
         const int plo = blk * per_block;
         int np = 0;
         for (int k0 = K0; k0 < K0 + Bw; k0 += bmax, ++np) {
             const int b = min(bmax, K0 + Bw - k0), panel = plo + np;
-            hipLaunchKernelGGL(k_gj_panel, dim3(nmat), dim3(kBlock), panel_lds, s, wk.S, wk.PR, wk.pivrow, rowstate,
-                               wk.logabs, wk.negs, mstatus, scale, n, b, k0, panel, B, np * bmax);
+            if (n <= 512)
+                hipLaunchKernelGGL((k_gj_panel<512, 1, 16>), dim3(nmat), dim3(512), 0, s, wk.S, wk.PR, wk.pivrow,
+                                   rowstate, wk.logabs, wk.negs, mstatus, scale, n, b, k0, panel, B, np * bmax);
+            else if (n <= 1024)
+                hipLaunchKernelGGL((k_gj_panel<1024, 1, 16>), dim3(nmat), dim3(1024), 0, s, wk.S, wk.PR, wk.pivrow,
+                                   rowstate, wk.logabs, wk.negs, mstatus, scale, n, b, k0, panel, B, np * bmax);
+            else
+                hipLaunchKernelGGL((k_gj_panel<1024, 2, 8>), dim3(nmat), dim3(1024), 0, s, wk.S, wk.PR, wk.pivrow,
+                                   rowstate, wk.logabs, wk.negs, mstatus, scale, n, b, k0, panel, B, np * bmax);
             if (Bw > b) {  // the panel's sweeps on the rest of the block
                 const int jt0 = K0 / 64, njt = (K0 + Bw - 1) / 64 - jt0 + 1;
-                hipLaunchKernelGGL(k_gj_update<32>, dim3(nmat * tiles * njt), dim3(kBlock), 0, s, wk.S, wk.PR,
-                                   rowstate, n, b, k0, B, np * bmax, panel, panel + 1, jt0, njt, K0, K0 + Bw, k0,
-                                   k0 + b);
+                hipLaunchKernelGGL(k_gj_update<16>, dim3(mat_groups * tiles * njt), dim3(kBlock), 0, s, wk.S, wk.PR,
+                                   rowstate, nmat, n, b, k0, B, np * bmax, panel, panel + 1, jt0, njt, K0, K0 + Bw,
+                                   k0, k0 + b);
             }
         }
         if (n > Bw)  // the block's sweeps on every other column, as one rank-Bw update
-            hipLaunchKernelGGL(k_gj_update<64>, dim3(nmat * tiles * tiles), dim3(kBlock), 0, s, wk.S, wk.PR, rowstate,
-                               n, Bw, K0, B, 0, plo, plo + np, 0, tiles, 0, n, K0, K0 + Bw);
+            hipLaunchKernelGGL(k_gj_update<32>, dim3(mat_groups * tiles * tiles), dim3(kBlock), 0, s, wk.S, wk.PR,
+                               rowstate, nmat, n, Bw, K0, B, 0, plo, plo + np, 0, tiles, 0, n, K0, K0 + Bw);
     }
     const size_t fin_lds = (size_t)n * sizeof(double) + (size_t)n * sizeof(int);
     hipLaunchKernelGGL(k_gj_finish<T>, dim3(nmat), dim3(kBlock), fin_lds, s, v, wk.S, wk.pivrow, rowstate, wk.logabs,

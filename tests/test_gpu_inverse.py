@@ -1,7 +1,9 @@
 """GPU parity of the batched FP64 Slater inverse (cq_slater_inverse: the periodic-recompute
 kernels applied to caller-held matrices) against LAPACK through numpy: inverse, log|det| and
 sign, for the one-workgroup LDS path (n <= 64) and the blocked path (n > 64, with a ragged last
-block), FP64 and FP32 storage, an odd number of matrices, and a singular matrix reported."""
+block and a panel narrower than 4 columns at n = 101; one and two panel rows per thread of the
+register panel at n = 600 and 1040, 8-column panels above n = 1024), FP64 and FP32 storage, an odd
+number of matrices, and a singular matrix reported."""
 import numpy as np
 import pytest
 
@@ -15,7 +17,7 @@ def well_conditioned(rng, nmat, n):
     return A + n ** 0.5 * np.eye(n)[None] * rng.choice([-1.0, 1.0], (nmat, 1, 1))
 
 
-@pytest.mark.parametrize("n,nmat", [(4, 3), (32, 17), (100, 5), (256, 4)])
+@pytest.mark.parametrize("n,nmat", [(4, 3), (32, 17), (100, 5), (101, 3), (256, 4), (600, 3), (1040, 2)])
 @pytest.mark.parametrize("dtype", ["float64", "float32"])
 def test_slater_inverse_matches_lapack(n, nmat, dtype):
     rng = np.random.default_rng(n * 7 + nmat)
