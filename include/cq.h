@@ -503,8 +503,8 @@ void cq_ccrowd_destroy(cq_ccrowd* c);
          so row a is the inverse column of electron a (the crowds' layout);
    logdet, sign  device [nmat]: log|det A_m| (FP64) and its sign (+1/-1).
    All pointers are device pointers owned by the caller; A is only read.  The
-   library allocates a workspace of about nmat (n^2 + 64 n) 8 bytes for n > 64 for
-   the duration of the call.  Runs on hip_stream (NULL: the null stream) and
+   library allocates a workspace of about nmat n (n + 144) 8 bytes for 64 < n <= 1024
+   (nmat n (n + 80) 8 bytes above) for the duration of the call.  Runs on hip_stream (NULL: the null stream) and
    returns when the results are written.  Errors: CQ_EINVAL (NULL pointer,
    elem_bytes not 4 or 8, n outside 1..2048, nmat < 1), CQ_ENOMEM (workspace),
    CQ_ESINGULAR (a pivot at or below n eps max|A_ij| or not finite; the message
@@ -521,9 +521,10 @@ cq_status cq_slater_inverse(const void* A, int elem_bytes, int n, int nmat, void
    same kernels, but the workspace is a static device array of CQ_STATIC_WORK_BYTES
    bytes that the library holds on each GPU it runs on until the process ends (looked up
    at the first call on a device); the call makes no hipMalloc, hipFree or other
-   allocating call.  The workspace needed is about nmat (n^2 + 64 n) 8 bytes for n > 64
-   (nmat (4 + 8) bytes for n <= 64): CQ_EINVAL names the size when it exceeds the array
-   (64 MiB holds, e.g., 7 matrices of n = 1024 or 120 of n = 256).  Every call on one
+   allocating call.  The workspace needed is about nmat n (n + 144) 8 bytes for
+   64 < n <= 1024, nmat n (n + 80) 8 bytes above (nmat (4 + 8) bytes for n <= 64):
+   CQ_EINVAL names the size when it exceeds the array (64 MiB holds, e.g., 7 matrices of
+   n = 1024 or 81 of n = 256).  Every call on one
    GPU shares that GPU's array: calls that overlap on one GPU (several host threads, or
    streams without ordering between them) race; serialise them.  Returns when the
    results are written. */

@@ -1292,7 +1292,7 @@ cq_status cq_crowd_create(const cq_system* const* systems, const int* walkers_pe
     if (invb) {
         const int nmat = 2 * c->Wcap, b = cq::panel_width((int)n);
         void *S, *PR, *piv, *la, *ng;
-        cq_status st = dev_alloc(c, &S, sizeof(double) * nmat * n * n);
+        cq_status st = dev_alloc(c, &S, sizeof(double) * nmat * n * cq::s_ld((int)n));
         if (st == CQ_OK) st = dev_alloc(c, &PR, sizeof(double) * nmat * cq::block_width((int)n) * n);
         if (st == CQ_OK) st = dev_alloc(c, &piv, sizeof(int) * nmat * n * 2);
         if (st == CQ_OK) st = dev_alloc(c, &la, sizeof(double) * nmat * 2);  // log|det| and max|A| per matrix
@@ -2326,7 +2326,7 @@ cq_status slater_inverse_impl(const T* A, int n, int nmat, T* Minv, double* logd
     if (n > 64) {
         const int B = cq::block_width(n);
         wk.S = (double*)(work + off);
-        off += sizeof(double) * (size_t)nmat * n * n;
+        off += sizeof(double) * (size_t)nmat * n * cq::s_ld(n);
         wk.PR = (double*)(work + off);
         off += sizeof(double) * (size_t)nmat * B * n;
         wk.pivrow = (int*)(work + off);

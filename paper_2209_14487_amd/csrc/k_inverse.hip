@@ -14,15 +14,15 @@
 //
 // n <= 64: one workgroup per matrix with the matrix in LDS (k_gj_small).
 // n  > 64: blocked on two levels.  A panel of b columns is swept by one workgroup
-// per matrix (k_gj_panel, panel in LDS); the same b sweeps act on every other
+// per matrix (k_gj_panel, panel in registers); the same b sweeps act on every other
 // column as the rank-b update
 //     S[i][j] = [i not a pivot of the panel] S[i][j] + sum_q P[i][q] S_old[pi(k0+q)][j]
-// with P the swept panel.  A block of B = 4b columns is swept panel by panel,
+// with P the swept panel.  A block of B = 8b columns is swept panel by panel,
 // each panel's update applied to the block's own columns only; the block's
 // columns then hold the multipliers of all its B sweeps, and one rank-B update
-// with the block's old pivot rows (k_gj_update<64>) brings every other column up
+// with the block's old pivot rows (k_gj_update) brings every other column up
 // to date.  So the whole matrix is read and written n/B times, not n/b times;
-// 2 n^3 flops in all.
+// 2 n^3 flops in all.  S has a row stride of n + 16 doubles (s_ld).
 #include "cq_device.h"
 #include "cq_internal.h"
 
@@ -173,11 +173,11 @@ __global__ __launch_bounds__(kBlock) void k_gj_load(CrowdView<T> v, double* __re
         const double m = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
         atomicMax(&scale[mat], (unsigned long long)__double_as_longlong(m));
     }
-    double* Sm = S + (size_t)mat * n * n;
+    double* Sm = S + (size_t)mat * n * s_ld(n);
     for (int idx = threadIdx.x; idx < 64 * 64; idx += kBlock) {
         const int r = idx / 64, c = idx % 64;  // output row j = tj*64 + r, column i = ti*64 + c
         const int j = tj * 64 + r, i = ti * 64 + c;
-        if (i < n && j < n) Sm[(size_t)j * n + i] = tile[c][r];
+        if (i < n && j < n) Sm[(size_t)j * s_ld(n) + i] = tile[c][r];
     }
 }
 
@@ -205,7 +205,7 @@ __global__ __launch_bounds__(TH) void k_gj_panel(double* __restrict__ S, double*
     __shared__ int widx[2][kPanelWaves];
     __shared__ int pivs[BP];
     const int mat = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    double* Sm = S + (size_t)mat * n * n;
+    double* Sm = S + (size_t)mat * n * s_ld(n);
     int* rs = rowstate + (size_t)mat * n;
     double x[R][BP];
     int used[R];
@@ -215,7 +215,7 @@ __global__ __launch_bounds__(TH) void k_gj_panel(double* __restrict__ S, double*
         const bool live = i < n;
         used[r] = live ? rs[i] : 1;
 #pragma unroll
-        for (int j = 0; j < BP; ++j) x[r][j] = (live && j < b) ? Sm[(size_t)i * n + k0 + j] : 0.0;
+        for (int j = 0; j < BP; ++j) x[r][j] = (live && j < b) ? Sm[(size_t)i * s_ld(n) + k0 + j] : 0.0;
     }
     const double tiny = n * 2.220446049250313e-16 * __longlong_as_double((long long)scale[mat]);
     double la = 0.0;
@@ -265,9 +265,11 @@ __global__ __launch_bounds__(TH) void k_gj_panel(double* __restrict__ S, double*
 #pragma unroll
         for (int j = 0; j < BP; ++j) rowp[j] = wrow[par][ww][j];
         const double piv = rowp[q];
-        if (!(fabs(piv) > tiny) || !isfinite(piv)) bad = 1;
-        la += log(fabs(piv));
-        ng += piv < 0.0;
+        if (tid == 0) {
+            if (!(fabs(piv) > tiny) || !isfinite(piv)) bad = 1;
+            la += log(fabs(piv));
+            ng += piv < 0.0;
+        }
         const double ipiv = 1.0 / piv;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -290,7 +292,7 @@ __global__ __launch_bounds__(TH) void k_gj_panel(double* __restrict__ S, double*
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int idx = i0 + u * kPanelThreads + tid;
-            y[u] = idx < n * b ? Sm[(size_t)pivs[idx / n] * n + idx % n] : 0.0;
+            y[u] = idx < n * b ? Sm[(size_t)pivs[idx / n] * s_ld(n) + idx % n] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
@@ -305,7 +307,7 @@ __global__ __launch_bounds__(TH) void k_gj_panel(double* __restrict__ S, double*
         if (i >= n) continue;
 #pragma unroll
         for (int j = 0; j < BP; ++j)
-            if (j < b) Sm[(size_t)i * n + k0 + j] = x[r][j];
+            if (j < b) Sm[(size_t)i * s_ld(n) + k0 + j] = x[r][j];
         rs[i] = used[r];
     }
     if (tid < b) pivrow[(size_t)mat * n + k0 + tid] = pivs[tid];
@@ -339,7 +341,7 @@ __global__ __launch_bounds__(kBlock) void k_gj_update(double* __restrict__ S, co
     xcd_map(blockIdx.x, tiles * njt, mat, t);
     if (mat >= nmat) return;
     const int i0 = (t / njt) * 64, j0 = (jt0 + t % njt) * 64;
-    double* Sm = S + (size_t)mat * n * n;
+    double* Sm = S + (size_t)mat * n * s_ld(n);
     const int* rs = rowstate + (size_t)mat * n;
     const int tid = threadIdx.x;
     // FP64 matrix cores (v_mfma_f64_16x16x4f64): wave wv owns the 32 x 32 quarter
@@ -357,7 +359,7 @@ __global__ __launch_bounds__(kBlock) void k_gj_update(double* __restrict__ S, co
         for (int u = 0; u < U; ++u) {
             const int idx = tid + u * kBlock;
             const int r = idx / KC, q = idx % KC, qr = idx / 64, c = idx % 64;
-            xp[u] = (kc + q < b && i0 + r < n) ? Sm[(size_t)(i0 + r) * n + k0 + kc + q] : 0.0;
+            xp[u] = (kc + q < b && i0 + r < n) ? Sm[(size_t)(i0 + r) * s_ld(n) + k0 + kc + q] : 0.0;
             xr[u] = (kc + qr < b && j0 + c < n) ? PR[((size_t)mat * pr_rows + pr0 + kc + qr) * n + j0 + c] : 0.0;
         }
     };
@@ -407,7 +409,7 @@ __global__ __launch_bounds__(kBlock) void k_gj_update(double* __restrict__ S, co
             for (int bj = 0; bj < 2; ++bj) {
                 const int j = j0 + wj + 16 * bj + r16;
                 const bool live = i < n && j < n && j >= jlo && j < jhi && !(j >= xlo && j < xhi);
-                old[bi][bj][v] = live ? Sm[(size_t)i * n + j] : 0.0;
+                old[bi][bj][v] = live ? Sm[(size_t)i * s_ld(n) + j] : 0.0;
             }
         }
     products();
@@ -422,44 +424,74 @@ __global__ __launch_bounds__(kBlock) void k_gj_update(double* __restrict__ S, co
             for (int bj = 0; bj < 2; ++bj) {
                 const int j = j0 + wj + 16 * bj + r16;
                 if (j >= n || j < jlo || j >= jhi || (j >= xlo && j < xhi)) continue;
-                Sm[(size_t)i * n + j] = (pivot_row ? 0.0 : old[bi][bj][v]) + acc[bi][bj][v];
+                Sm[(size_t)i * s_ld(n) + j] = (pivot_row ? 0.0 : old[bi][bj][v]) + acc[bi][bj][v];
             }
         }
 }
 
-// M[k][c] = S[pi(k)][pi^-1(c)], log|det|, sign, drift, status; one workgroup per matrix.
+// M[k][c] = S[pi(k)][pi^-1(c)] for kFinRows rows k per workgroup (reads gathered within a row of
+// S, writes coalesced); the first workgroup of each matrix also forms log|det|, the sign (the
+// parity of pi counted as the parity of its inversions, in parallel from LDS), the drift and the
+// status.
+constexpr int kFinRows = 16;
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_gj_finish(CrowdView<T> v, const double* __restrict__ S,
-                                                       const int* __restrict__ pivrow, int* __restrict__ rowstate,
+                                                       const int* __restrict__ pivrow,
                                                        const double* __restrict__ logabs,
                                                        const int* __restrict__ negs, const int* __restrict__ mstatus)
 {
-    extern __shared__ double rowbuf[];   // [n]
-    int* inv_perm = (int*)(rowbuf + v.n);  // [n]
-    const int mat = blockIdx.x, w = mat >> 1, spin = mat & 1, n = v.n, tid = threadIdx.x;
+    extern __shared__ int fin_sh[];
+    int* inv_perm = fin_sh;     // [n]
+    int* prl = fin_sh + v.n;    // [n]
+    __shared__ int wpar[kBlock / 64];
+    const int n = v.n, tid = threadIdx.x, parts = (n + kFinRows - 1) / kFinRows;
+    const int mat = blockIdx.x / parts, part = blockIdx.x % parts, w = mat >> 1, spin = mat & 1;
     const int* pr = pivrow + (size_t)mat * n;
-    for (int k = tid; k < n; k += kBlock) inv_perm[pr[k]] = k;
-    __syncthreads();
-    const double* Sm = S + (size_t)mat * n * n;
-    T* M = v.M + ((size_t)w * 2 + spin) * n * (size_t)n;
-    for (int k = 0; k < n; ++k) {
-        const double* src = Sm + (size_t)pr[k] * n;
-        for (int j = tid; j < n; j += kBlock) rowbuf[j] = src[j];
-        __syncthreads();
-        for (int c = tid; c < n; c += kBlock) M[(size_t)k * n + c] = (T)rowbuf[inv_perm[c]];
-        __syncthreads();
+    for (int k = tid; k < n; k += kBlock) {
+        const int p = pr[k];
+        prl[k] = p;
+        inv_perm[p] = k;
     }
-    if (tid == 0) {
-        int* seen = rowstate + (size_t)mat * n;  // reused as scratch: zero it
-        for (int i = 0; i < n; ++i) seen[i] = 0;
-        int parity = 0;
-        for (int i = 0; i < n; ++i) {
-            if (seen[i]) continue;
-            int len = 0;
-            for (int j = i; !seen[j]; j = pr[j]) { seen[j] = 1; ++len; }
-            parity ^= (len - 1) & 1;
+    __syncthreads();
+    const double* Sm = S + (size_t)mat * n * s_ld(n);
+    T* M = v.M + ((size_t)w * 2 + spin) * n * (size_t)n;
+    // two rows at a time, every load of both in flight before the stores (n <= 8 kBlock)
+    for (int kk = 0; kk < kFinRows; kk += 2) {
+        double x[2][8];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int k = part * kFinRows + kk + h;
+            const double* src = Sm + (size_t)prl[k < n ? k : 0] * s_ld(n);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int c = tid + u * kBlock;
+                x[h][u] = (k < n && c < n) ? src[inv_perm[c]] : 0.0;
+            }
         }
-        for (int i = 0; i < n; ++i) seen[i] = 0;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int k = part * kFinRows + kk + h;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int c = tid + u * kBlock;
+                if (k < n && c < n) M[(size_t)k * n + c] = (T)x[h][u];
+            }
+        }
+    }
+    if (part != 0) return;
+    int par = 0;
+    for (int i = tid; i < n; i += kBlock) {
+        const int pi = prl[i];
+        for (int j = i + 1; j < n; ++j) par ^= prl[j] < pi;
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) par ^= __shfl_xor(par, off, 64);
+    if ((tid & 63) == 0) wpar[tid >> 6] = par;
+    __syncthreads();
+    if (tid == 0) {
+        int parity = 0;
+        for (int x = 0; x < kBlock / 64; ++x) parity ^= wpar[x];
         const int sgn = ((negs[mat] + parity) & 1) ? -1 : 1;
         const double old = v.logdet[w * 2 + spin];
         const double d = fabs(old - logabs[mat]);
@@ -486,13 +518,13 @@ __global__ void k_gj_reset(int* rowstate, double* logabs, int* negs, int* mstatu
 }
 
 int panel_width(int n) { return n > 1024 ? 8 : 16; }
-int block_width(int n) { return 4 * panel_width(n); }
+int block_width(int n) { return 8 * panel_width(n); }
 
 size_t inverse_work_bytes(int nmat, int n)
 {
     if (n <= kSmallN) return 0;
     const int B = block_width(n);
-    return (size_t)nmat * n * n * sizeof(double) + (size_t)nmat * B * n * sizeof(double)
+    return (size_t)nmat * n * s_ld(n) * sizeof(double) + (size_t)nmat * B * n * sizeof(double)
            + (size_t)nmat * n * sizeof(int) * 2 + (size_t)nmat * (sizeof(double) + 2 * sizeof(int)) + 4096;
 }
 
@@ -539,12 +571,12 @@ void launch_inverse(const CrowdView<T>& v, const InvWork& wk, hipStream_t s, int
             }
         }
         if (n > Bw)  // the block's sweeps on every other column, as one rank-Bw update
-            hipLaunchKernelGGL(k_gj_update<32>, dim3(mat_groups * tiles * tiles), dim3(kBlock), 0, s, wk.S, wk.PR,
+            hipLaunchKernelGGL(k_gj_update<16>, dim3(mat_groups * tiles * tiles), dim3(kBlock), 0, s, wk.S, wk.PR,
                                rowstate, nmat, n, Bw, K0, B, 0, plo, plo + np, 0, tiles, 0, n, K0, K0 + Bw);
     }
-    const size_t fin_lds = (size_t)n * sizeof(double) + (size_t)n * sizeof(int);
-    hipLaunchKernelGGL(k_gj_finish<T>, dim3(nmat), dim3(kBlock), fin_lds, s, v, wk.S, wk.pivrow, rowstate, wk.logabs,
-                       wk.negs, mstatus);
+    const size_t fin_lds = (size_t)2 * n * sizeof(int);
+    hipLaunchKernelGGL(k_gj_finish<T>, dim3(nmat * ((n + kFinRows - 1) / kFinRows)), dim3(kBlock), fin_lds, s, v, wk.S,
+                       wk.pivrow, wk.logabs, wk.negs, mstatus);
 }
 
 template void launch_inverse<float>(const CrowdView<float>&, const InvWork&, hipStream_t, int);
