@@ -37,7 +37,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=32)
     ap.add_argument("--warmup", type=int, default=4)
-    ap.add_argument("--workload", default="c4")
+    ap.add_argument("--workload", default="c4",
+                    help="c1..c6, or inverse (the FP64 recompute alone on the C4 matrices)")
     ap.add_argument("--fp64-steps", type=int, default=2, help="sweeps of the FP64 comparison run (0: skip)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-moves", type=int, default=2048, help="moves per walker in the CPU baseline sample")
@@ -193,6 +194,42 @@ def run_complex(cq, args):
     log("  complex: %.3e moves/s, k_csweep %.1f us per launch, %.0f GB/s algorithmic, acceptance %.3f; "
         "complex64 table %.3e moves/s, %.1f us per launch"
         % (out["value"], roof["us_per_launch"], roof["achieved"], out["acceptance"], rate32, roof32["us_per_launch"]))
+    print(json.dumps(out), flush=True)
+
+
+def run_inverse(cq, args):
+    """The FP64 recompute alone: cq_slater_inverse (the recompute's kernels) on the 2W Slater
+    matrices of a workload's system (C4: 256 matrices of N = 1024, stored in FP32 as in the mixed
+    crowd), seeded diagonally dominated entries, `steps` timed calls after `warmup`.  The call is
+    synchronous and allocates its workspace, so the wall time per call is an upper bound of the
+    kernels' time; the roofline counts 2 N^3 flops per matrix against the FP64 peak."""
+    from synth import WORKLOADS
+    wl = WORKLOADS["c4" if args.workload == "inverse" else args.workload]
+    n, nmat = wl.n, 2 * wl.walkers
+    rng = np.random.default_rng(wl.seed)
+    A = rng.uniform(-1, 1, (nmat, n, n)).astype(np.float32)
+    A += np.float32(n ** 0.5) * np.eye(n, dtype=np.float32)[None]
+    tA, tM = cq.DeviceArray(A), cq.DeviceArray(shape=A.shape, dtype=np.float32)
+    tl, ts = cq.DeviceArray(shape=(nmat,), dtype=np.float64), cq.DeviceArray(shape=(nmat,), dtype=np.int32)
+    for _ in range(args.warmup):
+        cq.slater_inverse(tA, tM, tl, ts)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        cq.slater_inverse(tA, tM, tl, ts)
+    secs = (time.perf_counter() - t0) / args.steps
+    ld = tl.numpy()
+    ref = np.linalg.slogdet(A[0].astype(np.float64))[1]
+    tflops = 2.0 * n ** 3 * nmat / secs / 1e12
+    out = dict(metric="FP64 batched Slater inversion (the periodic recompute)", value=round(1e3 * secs, 3),
+               unit="ms per call", higher_is_better=False, n_gpus=1, steps=args.steps, warmup=args.warmup,
+               dtype="f64", data="synthetic (seeded uniform entries plus sqrt(N) on the diagonal)",
+               config=dict(workload="%s recompute: %d matrices of N = %d, FP32 storage, FP64 arithmetic"
+                                    % (wl.name, nmat, n)),
+               roofline=dict(bound="mfma", achieved=round(tflops, 2), peak=78.6, unit="TFLOP/s",
+                             frac=round(tflops / 78.6, 4), traffic=None,
+                             note="2 N^3 flops per matrix over the wall time of a synchronous call"),
+               logdet_check=abs(float(ld[0]) - float(ref)))
+    log("  inverse: %.2f ms per call, %.1f TFLOP/s" % (1e3 * secs, tflops))
     print(json.dumps(out), flush=True)
 
 
@@ -599,6 +636,9 @@ def main():
         return
     if args.workload == "c6":
         run_complex(cq, args)
+        return
+    if args.workload == "inverse":
+        run_inverse(cq, args)
         return
     if args.scan:
         run_scan(cq, args)

@@ -207,15 +207,34 @@ __global__ __launch_bounds__(TH) void k_gj_panel(double* __restrict__ S, double*
     const int mat = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     double* Sm = S + (size_t)mat * n * s_ld(n);
     int* rs = rowstate + (size_t)mat * n;
+    // the panel is read and written in whole row segments (a wave covers 64 / BP rows per
+    // access) and handed to the row-per-thread layout through LDS
+    extern __shared__ double ptile[];  // [R TH][BP + 1]
+    constexpr int LD = BP + 1;
+    static_assert((R * BP) % 8 == 0, "panel loads");
+#pragma unroll
+    for (int h = 0; h < R * BP; h += 8) {  // 8 loads in flight per thread
+        double y[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int idx = tid + (h + u) * kPanelThreads, row = idx / BP, col = idx % BP;
+            y[u] = (row < n && col < b) ? Sm[(size_t)row * s_ld(n) + k0 + col] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int idx = tid + (h + u) * kPanelThreads;
+            ptile[(idx / BP) * LD + idx % BP] = y[u];
+        }
+    }
+    __syncthreads();
     double x[R][BP];
     int used[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int i = tid + r * kPanelThreads;
-        const bool live = i < n;
-        used[r] = live ? rs[i] : 1;
+        used[r] = i < n ? rs[i] : 1;
 #pragma unroll
-        for (int j = 0; j < BP; ++j) x[r][j] = (live && j < b) ? Sm[(size_t)i * s_ld(n) + k0 + j] : 0.0;
+        for (int j = 0; j < BP; ++j) x[r][j] = ptile[i * LD + j];
     }
     const double tiny = n * 2.220446049250313e-16 * __longlong_as_double((long long)scale[mat]);
     double la = 0.0;
@@ -261,9 +280,7 @@ __global__ __launch_bounds__(TH) void k_gj_panel(double* __restrict__ S, double*
                 ww = o;
             }
         }
-        double rowp[BP];
-#pragma unroll
-        for (int j = 0; j < BP; ++j) rowp[j] = wrow[par][ww][j];
+        const double* rowp = wrow[par][ww];  // read from LDS where used (broadcast)
         const double piv = rowp[q];
         if (tid == 0) {
             if (!(fabs(piv) > tiny) || !isfinite(piv)) bad = 1;
@@ -285,6 +302,14 @@ __global__ __launch_bounds__(TH) void k_gj_panel(double* __restrict__ S, double*
         }
         if (tid == 0) pivs[q] = p;
     }
+    // the swept panel back to the LDS tile (the registers are free from here on)
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = tid + r * kPanelThreads;
+#pragma unroll
+        for (int j = 0; j < BP; ++j) ptile[i * LD + j] = x[r][j];
+        if (i < n) rs[i] = used[r];
+    }
     __syncthreads();
     // old pivot rows (all columns; the panel columns of PR are not used)
     for (int i0 = 0; i0 < n * b; i0 += 8 * kPanelThreads) {  // 8 loads in flight per thread
@@ -302,13 +327,9 @@ __global__ __launch_bounds__(TH) void k_gj_panel(double* __restrict__ S, double*
     }
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int i = tid + r * kPanelThreads;
-        if (i >= n) continue;
-#pragma unroll
-        for (int j = 0; j < BP; ++j)
-            if (j < b) Sm[(size_t)i * s_ld(n) + k0 + j] = x[r][j];
-        rs[i] = used[r];
+    for (int u = 0; u < R * BP; ++u) {
+        const int idx = tid + u * kPanelThreads, row = idx / BP, col = idx % BP;
+        if (row < n && col < b) Sm[(size_t)row * s_ld(n) + k0 + col] = ptile[row * LD + col];
     }
     if (tid < b) pivrow[(size_t)mat * n + k0 + tid] = pivs[tid];
     if (tid == 0) {
@@ -518,6 +539,7 @@ __global__ void k_gj_reset(int* rowstate, double* logabs, int* negs, int* mstatu
 }
 
 int panel_width(int n) { return n > 1024 ? 8 : 16; }
+static size_t panel_lds(int th, int r, int bp) { return (size_t)th * r * (bp + 1) * sizeof(double); }
 int block_width(int n) { return 8 * panel_width(n); }
 
 size_t inverse_work_bytes(int nmat, int n)
@@ -546,6 +568,16 @@ void launch_inverse(const CrowdView<T>& v, const InvWork& wk, hipStream_t s, int
     hipLaunchKernelGGL(k_gj_load<T>, dim3(nmat * tiles * tiles), dim3(kBlock), 0, s, v, wk.S, scale);
     const int bmax = panel_width(n);
     const int B = block_width(n), per_block = B / bmax;
+    static bool panel_attr = false;  // the panels' LDS tiles exceed the default 64 KB
+    if (!panel_attr) {
+        (void)hipFuncSetAttribute((const void*)k_gj_panel<512, 1, 16>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)panel_lds(512, 1, 16));
+        (void)hipFuncSetAttribute((const void*)k_gj_panel<1024, 1, 16>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)panel_lds(1024, 1, 16));
+        (void)hipFuncSetAttribute((const void*)k_gj_panel<1024, 2, 8>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)panel_lds(1024, 2, 8));
+        panel_attr = true;
+    }
     static_assert(kBlock == 256, "update tiles");
     const int mat_groups = ((nmat + 7) / 8) * 8;  // update grids: the tiles of a matrix on one XCD
     for (int K0 = 0, blk = 0; K0 < n; K0 += B, ++blk) {
@@ -555,14 +587,17 @@ void launch_inverse(const CrowdView<T>& v, const InvWork& wk, hipStream_t s, int
         for (int k0 = K0; k0 < K0 + Bw; k0 += bmax, ++np) {
             const int b = min(bmax, K0 + Bw - k0), panel = plo + np;
             if (n <= 512)
-                hipLaunchKernelGGL((k_gj_panel<512, 1, 16>), dim3(nmat), dim3(512), 0, s, wk.S, wk.PR, wk.pivrow,
-                                   rowstate, wk.logabs, wk.negs, mstatus, scale, n, b, k0, panel, B, np * bmax);
+                hipLaunchKernelGGL((k_gj_panel<512, 1, 16>), dim3(nmat), dim3(512), panel_lds(512, 1, 16), s, wk.S,
+                                   wk.PR, wk.pivrow, rowstate, wk.logabs, wk.negs, mstatus, scale, n, b, k0, panel, B,
+                                   np * bmax);
             else if (n <= 1024)
-                hipLaunchKernelGGL((k_gj_panel<1024, 1, 16>), dim3(nmat), dim3(1024), 0, s, wk.S, wk.PR, wk.pivrow,
-                                   rowstate, wk.logabs, wk.negs, mstatus, scale, n, b, k0, panel, B, np * bmax);
+                hipLaunchKernelGGL((k_gj_panel<1024, 1, 16>), dim3(nmat), dim3(1024), panel_lds(1024, 1, 16), s,
+                                   wk.S, wk.PR, wk.pivrow, rowstate, wk.logabs, wk.negs, mstatus, scale, n, b, k0,
+                                   panel, B, np * bmax);
             else
-                hipLaunchKernelGGL((k_gj_panel<1024, 2, 8>), dim3(nmat), dim3(1024), 0, s, wk.S, wk.PR, wk.pivrow,
-                                   rowstate, wk.logabs, wk.negs, mstatus, scale, n, b, k0, panel, B, np * bmax);
+                hipLaunchKernelGGL((k_gj_panel<1024, 2, 8>), dim3(nmat), dim3(1024), panel_lds(1024, 2, 8), s, wk.S,
+                                   wk.PR, wk.pivrow, rowstate, wk.logabs, wk.negs, mstatus, scale, n, b, k0, panel,
+                                   B, np * bmax);
             if (Bw > b) {  // the panel's sweeps on the rest of the block
                 const int jt0 = K0 / 64, njt = (K0 + Bw - 1) / 64 - jt0 + 1;
                 hipLaunchKernelGGL(k_gj_update<16>, dim3(mat_groups * tiles * njt), dim3(kBlock), 0, s, wk.S, wk.PR,
