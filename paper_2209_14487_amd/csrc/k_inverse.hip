@@ -356,7 +356,9 @@ __global__ __launch_bounds__(kBlock) void k_gj_update(double* __restrict__ S, co
                                                        int njt, int jlo, int jhi, int xlo, int xhi)
 {
     __shared__ double Pt[64][KC + 1];  // multiplier rows i0..i0+63, one chunk of q
-    __shared__ double Rt[KC][65];      // one chunk of old pivot rows, columns j0..j0+63
+    // one chunk of old pivot rows, columns j0..j0+63; a row stride of 80 doubles puts the
+    // four q rows of an operand read in two halves of the LDS banks (65 gave 4-way conflicts)
+    __shared__ double Rt[KC][80];
     const int tiles = (n + 63) / 64;
     int mat, t;
     xcd_map(blockIdx.x, tiles * njt, mat, t);
