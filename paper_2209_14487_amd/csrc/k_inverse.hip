@@ -31,6 +31,55 @@ namespace cq {
 constexpr int kSmallN = 64;
 
 // argmax of |value| over the block (ties -> lowest index); returns in *best_i.
+// One step of an argmax over lanes through a DPP lane pattern (no LDS): the larger value,
+// the lower index on ties; every lane of the pattern has a source lane.
+template <int CTRL>
+__device__ __forceinline__ void argmax_dpp(double& val, int& idx)
+{
+    const long long bits = __double_as_longlong(val);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)bits, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(bits >> 32), CTRL, 0xF, 0xF, false);
+    const int oi = __builtin_amdgcn_update_dpp(0, idx, CTRL, 0xF, 0xF, false);
+    const double ov = __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+    if (ov > val || (ov == val && oi < idx)) {
+        val = ov;
+        idx = oi;
+    }
+}
+
+// argmax over each row of 16 lanes, the result in all 16: quad_perm [1,0,3,2] and [2,3,0,1]
+// combine the lanes of a quad, row_half_mirror the quads of a half row, row_mirror the halves
+__device__ __forceinline__ void row_argmax(double& val, int& idx)
+{
+    argmax_dpp<0xB1>(val, idx);
+    argmax_dpp<0x4E>(val, idx);
+    argmax_dpp<0x141>(val, idx);
+    argmax_dpp<0x140>(val, idx);
+}
+
+// argmax over the wave, the same result in every lane: rows by DPP, then the four rows'
+// results read as wave-uniform values and combined in row order
+__device__ __forceinline__ void wave_argmax_dpp(double& val, int& idx)
+{
+    row_argmax(val, idx);
+    const long long bits = __double_as_longlong(val);
+    double bv = 0.0;
+    int bi = 0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int lo = __builtin_amdgcn_readlane((int)bits, 16 * r);
+        const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), 16 * r);
+        const int oi = __builtin_amdgcn_readlane(idx, 16 * r);
+        const double ov = __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+        if (r == 0 || ov > bv || (ov == bv && oi < bi)) {
+            bv = ov;
+            bi = oi;
+        }
+    }
+    val = bv;
+    idx = bi;
+}
+
 __device__ __forceinline__ void wave_argmax(double& val, int& idx)
 {
 #pragma unroll
@@ -204,6 +253,7 @@ __global__ __launch_bounds__(TH) void k_gj_panel(double* __restrict__ S, double*
     __shared__ double wval[2][kPanelWaves];
     __shared__ int widx[2][kPanelWaves];
     __shared__ int pivs[BP];
+    __shared__ double spiv[BP], slog[BP];
     const int mat = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     double* Sm = S + (size_t)mat * n * s_ld(n);
     int* rs = rowstate + (size_t)mat * n;
@@ -237,11 +287,10 @@ __global__ __launch_bounds__(TH) void k_gj_panel(double* __restrict__ S, double*
         for (int j = 0; j < BP; ++j) x[r][j] = ptile[i * LD + j];
     }
     const double tiny = n * 2.220446049250313e-16 * __longlong_as_double((long long)scale[mat]);
-    double la = 0.0;
     int ng = 0, bad = 0;
 #pragma unroll
     for (int q = 0; q < BP; ++q) {
-        if (q >= b) break;
+        if (q >= b) continue;  // b is uniform; a constant trip count keeps the loop fully unrolled
         const int par = q & 1;
         double best = -1.0;
         int bi = n;
@@ -255,7 +304,7 @@ __global__ __launch_bounds__(TH) void k_gj_panel(double* __restrict__ S, double*
                     bi = tid + r * kPanelThreads;
                 }
             }
-        wave_argmax(best, bi);
+        wave_argmax_dpp(best, bi);
 #pragma unroll
         for (int r = 0; r < R; ++r)
             if (tid + r * kPanelThreads == bi)
@@ -266,25 +315,19 @@ __global__ __launch_bounds__(TH) void k_gj_panel(double* __restrict__ S, double*
             widx[par][wave] = bi;
         }
         __syncthreads();
-        // every thread combines the waves' candidates in wave order (same result everywhere);
+        // every lane takes one wave's candidate (a row of lanes repeats them when there are
+        // fewer than 16 waves) and the row argmax combines them, the same result in every lane;
         // some row is always unused, since a matrix has n rows and n sweeps
-        int ww = 0, p = widx[par][0];
-        double bb = wval[par][0];
-#pragma unroll
-        for (int o = 1; o < kPanelWaves; ++o) {
-            const double ov = wval[par][o];
-            const int oi = widx[par][o];
-            if (ov > bb || (ov == bb && oi < p)) {
-                bb = ov;
-                p = oi;
-                ww = o;
-            }
-        }
+        static_assert(kPanelWaves <= 16 && (kPanelWaves & (kPanelWaves - 1)) == 0, "candidate rows");
+        double bb = wval[par][lane & (kPanelWaves - 1)];
+        int p = widx[par][lane & (kPanelWaves - 1)];
+        row_argmax(bb, p);
+        const int ww = (p % kPanelThreads) >> 6;  // the wave holding row p sent it
         const double* rowp = wrow[par][ww];  // read from LDS where used (broadcast)
         const double piv = rowp[q];
-        if (tid == 0) {
+        if (tid == 0) {  // the logarithms are taken after the sweeps, off their chain
             if (!(fabs(piv) > tiny) || !isfinite(piv)) bad = 1;
-            la += log(fabs(piv));
+            spiv[q] = piv;
             ng += piv < 0.0;
         }
         const double ipiv = 1.0 / piv;
@@ -311,6 +354,7 @@ __global__ __launch_bounds__(TH) void k_gj_panel(double* __restrict__ S, double*
         if (i < n) rs[i] = used[r];
     }
     __syncthreads();
+    if (tid < b) slog[tid] = log(fabs(spiv[tid]));
     // old pivot rows (all columns; the panel columns of PR are not used)
     for (int i0 = 0; i0 < n * b; i0 += 8 * kPanelThreads) {  // 8 loads in flight per thread
         double y[8];
@@ -333,6 +377,8 @@ __global__ __launch_bounds__(TH) void k_gj_panel(double* __restrict__ S, double*
     }
     if (tid < b) pivrow[(size_t)mat * n + k0 + tid] = pivs[tid];
     if (tid == 0) {
+        double la = 0.0;
+        for (int q = 0; q < b; ++q) la += slog[q];  // in sweep order
         logabs[mat] += la;
         negs[mat] += ng;
         if (bad) status[mat] = 1;
