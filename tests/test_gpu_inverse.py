@@ -54,3 +54,40 @@ def test_slater_inverse_reports_a_singular_matrix():
         cq.slater_inverse(tA, tM, tl, ts)
     assert ei.value.status == cq.CQ_ESINGULAR
     assert "matrix 2 or 3" in str(ei.value)
+
+
+def paired_blocks(n, delta, dtype):
+    """2 x 2 blocks on rows and columns (t, t + h), h = n // 2: [[delta, 1], [1, 1]] for even t,
+    [[1, 1], [1, delta]] for odd t (a last odd row is 1 on the diagonal).  Column t of A^T then
+    holds delta in row t and 1 in row t + h for even t, so only the largest-magnitude pivot is
+    usable; rows t and t + h lie in different waves of the panel kernel and of the small kernel."""
+    h = n // 2
+    A = np.zeros((n, n))
+    for t in range(h):
+        a, b = (delta, 1.0) if t % 2 == 0 else (1.0, delta)
+        A[t, t], A[t, t + h], A[t + h, t], A[t + h, t + h] = a, 1.0, 1.0, b
+    if n % 2:
+        A[n - 1, n - 1] = 1.0
+    return A.astype(dtype).astype(np.float64)
+
+
+@pytest.mark.parametrize("n", [40, 300, 602, 1024, 1041])
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+def test_slater_inverse_takes_the_largest_pivot_across_waves(n, dtype):
+    """A pivot of 1e-20 sits below the n eps max|A| threshold: picking it instead of the 1 in the
+    other row of its block would report the matrix singular (and lose the inverse)."""
+    A = np.stack([paired_blocks(n, 1e-20, dtype), paired_blocks(n, 1e-20, dtype).T])
+    nmat = A.shape[0]
+    tA = cq.DeviceArray(A.astype(dtype))
+    tM = cq.DeviceArray(shape=A.shape, dtype=dtype)
+    tl = cq.DeviceArray(shape=(nmat,), dtype=np.float64)
+    ts = cq.DeviceArray(shape=(nmat,), dtype=np.int32)
+    cq.slater_inverse(tA, tM, tl, ts)
+    M = tM.numpy().astype(np.float64)
+    ref_s, ref_l = np.linalg.slogdet(A)
+    inv = np.linalg.inv(A)
+    tol = 1e-14 if dtype == "float64" else 1e-7
+    for m in range(nmat):
+        assert np.abs(M[m] - inv[m].T).max() <= tol * np.abs(inv[m]).max(), m
+    assert np.all(np.abs(tl.numpy() - ref_l) <= 1e-12)
+    assert np.array_equal(ts.numpy(), ref_s.astype(np.int32))
